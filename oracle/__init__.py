@@ -1,0 +1,287 @@
+"""CPU oracle for the parallel-tempering EA spin-glass path -- TEST INFRASTRUCTURE.
+
+A plain, slow, single-threaded C implementation (``ea_oracle.c``) of what the
+GPU path computes, plus an independent exact-enumeration helper (``enum.c``).
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package; the product library never does.
+
+The arithmetic lives in C; this module only marshals numpy arrays through
+ctypes.  Build with :func:`build` (gcc -O2, no fast-math, no intrinsics).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["ea_oracle.c", "enum.c"]
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle shared library (always recompiles)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fvisibility=hidden",
+           "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+P = C.c_void_p
+
+
+def _declare(L):
+    L.or_philox4x32_10.argtypes = [P, P, P]
+    L.or_philox4x32_10.restype = None
+    L.or_philox_stream.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, P,
+                                   C.c_int64, P]
+    L.or_philox_stream.restype = None
+    L.or_energy.argtypes = [C.c_int, C.c_int, P, P]
+    L.or_energy.restype = C.c_int64
+    L.or_local_x.argtypes = [C.c_int, C.c_int, P, P, C.c_int]
+    L.or_local_x.restype = C.c_int
+    L.or_metro_thresholds.argtypes = [P, C.c_int, C.c_int, P]
+    L.or_metro_thresholds.restype = None
+    L.or_pt_thresholds.argtypes = [P, C.c_int, C.c_int, C.c_int, P, C.c_int]
+    L.or_pt_thresholds.restype = C.c_int
+    L.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_uint64, P]
+    L.or_create.restype = P
+    L.or_destroy.argtypes = [P]
+    L.or_destroy.restype = None
+    for name in ("or_exchange", "or_houdayer", "or_measure", "or_recompute_energies"):
+        getattr(L, name).argtypes = [P]
+        getattr(L, name).restype = None
+    L.or_sweep.argtypes = [P, C.c_int]
+    L.or_sweep.restype = None
+    L.or_mcs.argtypes = [P, C.c_int, C.c_int, C.c_int]
+    L.or_mcs.restype = None
+    L.or_houdayer_move.argtypes = [C.c_int, C.c_int, P, P, P, C.c_uint64, P, P]
+    L.or_houdayer_move.restype = C.c_int64
+    L.or_observables.argtypes = [P, P, P, P]
+    L.or_observables.restype = None
+    L.or_get_spins.argtypes = [P, P]
+    L.or_set_spins.argtypes = [P, P]
+    L.or_get_energies.argtypes = [P, P]
+    L.or_get_maps.argtypes = [P, P, P]
+    L.or_get_counters.argtypes = [P, P]
+    L.or_get_moments.argtypes = [P, P, P, P, P, P, P]
+    L.or_pt_table_len.argtypes = [P]
+    L.or_pt_table_len.restype = C.c_int
+    L.or_get_pt_table.argtypes = [P, P]
+    L.or_sweep_order.argtypes = [C.c_int, C.c_int, P]
+    L.or_metro_rule.argtypes = [C.c_int, C.c_uint32, P]
+    L.or_metro_rule.restype = C.c_int
+    L.en_density_of_states.argtypes = [C.c_int, C.c_int, P, P]
+    L.en_density_of_states.restype = C.c_int
+    L.en_state_energies.argtypes = [C.c_int, C.c_int, P, P]
+    L.en_state_energies.restype = C.c_int
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def nsites(L: int, d: int) -> int:
+    return L ** d
+
+
+# --------------------------------------------------------------------------
+# Stateless helpers
+# --------------------------------------------------------------------------
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def philox_stream(c0, c1, c2, c3, key, n) -> np.ndarray:
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros((n, 4), np.uint32)
+    lib().or_philox_stream(c0, c1, c2, c3, _p(k), n, _p(out))
+    return out
+
+
+def energy(L: int, d: int, J: np.ndarray, spins: np.ndarray) -> int:
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    return int(lib().or_energy(L, d, _p(J), _p(s)))
+
+
+def local_x(L: int, d: int, J: np.ndarray, spins: np.ndarray, i: int) -> int:
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    return int(lib().or_local_x(L, d, _p(J), _p(s), i))
+
+
+def metro_thresholds(betas, d: int) -> np.ndarray:
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    out = np.zeros((len(b), d), np.uint32)
+    lib().or_metro_thresholds(_p(b), len(b), d, _p(out))
+    return out
+
+
+def pt_thresholds(betas, d: int, N: int) -> np.ndarray:
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    M = lib().or_pt_thresholds(_p(b), len(b), d, N, None, 0)
+    out = np.zeros((len(b) - 1, M), np.uint32)
+    lib().or_pt_thresholds(_p(b), len(b), d, N, _p(out), M)
+    return out
+
+
+def metro_rule(x: int, r: int, thr_row: np.ndarray) -> int:
+    t = np.ascontiguousarray(thr_row, dtype=np.uint32)
+    return int(lib().or_metro_rule(int(x), int(r), _p(t)))
+
+
+def sweep_order(L: int, d: int) -> np.ndarray:
+    out = np.zeros(nsites(L, d), np.int32)
+    lib().or_sweep_order(L, d, _p(out))
+    return out
+
+
+def houdayer_move(L, d, J, sa, sb, r64):
+    """Applies one Houdayer move in place on int8 arrays sa, sb.
+
+    Returns (delta, cluster_mask, cluster_size)."""
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    assert sa.dtype == np.int8 and sb.dtype == np.int8
+    assert sa.flags.c_contiguous and sb.flags.c_contiguous
+    N = nsites(L, d)
+    cl = np.zeros(N, np.int8)
+    size = np.zeros(1, np.int32)
+    delta = lib().or_houdayer_move(L, d, _p(J), _p(sa), _p(sb), C.c_uint64(r64),
+                                   _p(cl), _p(size))
+    return int(delta), cl.astype(bool), int(size[0])
+
+
+def density_of_states(L: int, d: int, J: np.ndarray) -> np.ndarray:
+    N = nsites(L, d)
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    out = np.zeros(2 * d * N + 1, np.uint64)
+    rc = lib().en_density_of_states(L, d, _p(J), _p(out))
+    assert rc == 0
+    return out
+
+
+def state_energies(L: int, d: int, J: np.ndarray) -> np.ndarray:
+    N = nsites(L, d)
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    out = np.zeros(1 << N, np.int32)
+    rc = lib().en_state_energies(L, d, _p(J), _p(out))
+    assert rc == 0
+    return out
+
+
+# --------------------------------------------------------------------------
+# Job wrapper
+# --------------------------------------------------------------------------
+class OracleJob:
+    """S samples x 2 replica sets x NT temperatures, as in the GPU library."""
+
+    def __init__(self, samples, replicas, L, dim, couplings, betas, seed,
+                 sample_keys=None):
+        self.S, self.NT, self.L, self.d = int(samples), int(replicas), int(L), int(dim)
+        self.N = nsites(self.L, self.d)
+        self._J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(
+            self.S, self.d, self.N)
+        self._b = np.ascontiguousarray(betas, dtype=np.float64)
+        keys = None
+        if sample_keys is not None:
+            self._keys = np.ascontiguousarray(sample_keys, dtype=np.uint32)
+            keys = _p(self._keys)
+        self._h = lib().or_create(self.S, self.NT, self.L, self.d, _p(self._J),
+                                  _p(self._b), C.c_uint64(seed), keys)
+        if not self._h:
+            raise ValueError("oracle rejected the job arguments")
+
+    def close(self):
+        if self._h:
+            lib().or_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n=1):
+        lib().or_sweep(self._h, int(n))
+
+    def exchange(self):
+        lib().or_exchange(self._h)
+
+    def houdayer(self):
+        lib().or_houdayer(self._h)
+
+    def measure(self):
+        lib().or_measure(self._h)
+
+    def mcs(self, n, houdayer=False, measure=False):
+        lib().or_mcs(self._h, int(n), int(bool(houdayer)), int(bool(measure)))
+
+    def spins(self) -> np.ndarray:
+        out = np.zeros((self.S, 2 * self.NT, self.N), np.int8)
+        lib().or_get_spins(self._h, _p(out))
+        return out
+
+    def set_spins(self, spins):
+        s = np.ascontiguousarray(spins, dtype=np.int8).reshape(self.S, 2 * self.NT, self.N)
+        lib().or_set_spins(self._h, _p(s))
+
+    def energies(self) -> np.ndarray:
+        out = np.zeros((self.S, 2 * self.NT), np.int64)
+        lib().or_get_energies(self._h, _p(out))
+        return out
+
+    def maps(self):
+        sot = np.zeros((self.S, 2, self.NT), np.int32)
+        tos = np.zeros((self.S, 2, self.NT), np.int32)
+        lib().or_get_maps(self._h, _p(sot), _p(tos))
+        return sot, tos
+
+    def counters(self):
+        out = np.zeros(4, np.uint64)
+        lib().or_get_counters(self._h, _p(out))
+        return dict(t=int(out[0]), u=int(out[1]), v=int(out[2]), n_meas=int(out[3]))
+
+    def moments(self):
+        ST = (self.S, self.NT)
+        arrs = [np.zeros(ST, np.int64) for _ in range(5)]
+        q4 = np.zeros(ST + (2,), np.uint64)
+        lib().or_get_moments(self._h, *[_p(a) for a in arrs], _p(q4))
+        names = ["E", "E2", "Q", "AQ", "Q2"]
+        out = dict(zip(names, arrs))
+        out["Q4"] = q4
+        return out
+
+    def pt_table(self) -> np.ndarray:
+        M = lib().or_pt_table_len(self._h)
+        out = np.zeros((self.NT - 1, M), np.uint32)
+        lib().or_get_pt_table(self._h, _p(out))
+        return out
+
+    def observables(self):
+        ps = np.zeros((self.S, self.NT, 5), np.float64)
+        dis = np.zeros((self.NT, 6), np.float64)
+        n = np.zeros(1, np.int64)
+        lib().or_observables(self._h, _p(ps), _p(dis), _p(n))
+        return ps, dis, int(n[0])

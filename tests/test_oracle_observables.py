@@ -1,0 +1,53 @@
+"""Pins for the oracle's measurement and readout (Sec. 2.1, Eqs. (3)-(4))."""
+from fractions import Fraction
+
+import numpy as np
+
+from paper_2003_04621_amd import workloads as W
+
+
+def test_q4_accumulates_beyond_64_bits(orc):
+    L, d, S, NT = 48, 3, 1, 2
+    N = L ** d
+    J = W.couplings_pm_j(S, L, d, 5)
+    job = orc.OracleJob(S, NT, L, d, J, np.array([1.0, 0.5]), 1)
+    job.set_spins(np.ones((S, 2 * NT, N), np.int8))
+    job.measure()
+    job.measure()
+    m = job.moments()
+    q4 = 2 * N ** 4
+    assert q4 >= 2 ** 64
+    assert int(m["Q4"][0, 0, 0]) == q4 % 2 ** 64 and int(m["Q4"][0, 0, 1]) == q4 >> 64
+    assert int(m["Q"][0, 0]) == 2 * N and int(m["Q2"][0, 0]) == 2 * N * N
+    E_all_up = -int(J[0].astype(np.int64).sum())
+    assert int(m["E"][0, 1]) == 2 * 2 * E_all_up
+    ps, dis, n = job.observables()
+    assert n == 2
+    assert ps[0, 0, 1] == 1.0 and ps[0, 0, 3] == 1.0 and ps[0, 0, 4] == 1.0
+    assert dis[0, 5] == 1.0                      # g = (3 - 1/1) / 2
+
+
+def test_readout_is_exact_ratio_of_integer_moments(orc):
+    L, d, S, NT = 4, 3, 5, 3
+    N = L ** d
+    job = orc.OracleJob(S, NT, L, d, W.couplings_pm_j(S, L, d, 9),
+                        W.geometric_betas(0.9, 2.0, NT), 3)
+    job.mcs(7, houdayer=True, measure=True)
+    ps, dis, n = job.observables()
+    m = job.moments()
+    q4 = m["Q4"][..., 0].astype(object) + m["Q4"][..., 1].astype(object) * 2 ** 64
+    for s in range(S):
+        for k in range(NT):
+            want = [Fraction(int(m["E"][s, k]), 2 * n * N),
+                    Fraction(int(m["Q"][s, k]), n * N),
+                    Fraction(int(m["AQ"][s, k]), n * N),
+                    Fraction(int(m["Q2"][s, k]), n * N ** 2),
+                    Fraction(int(q4[s, k]), n * N ** 4)]
+            for c in range(5):
+                assert abs(ps[s, k, c] - float(want[c])) <= 1e-15 * max(1.0, abs(float(want[c])))
+    for k in range(NT):
+        q2 = Fraction(int(m["Q2"][:, k].sum()), S * n * N ** 2)
+        q4k = Fraction(int(q4[:, k].sum()), S * n * N ** 4)
+        g = 0.5 * (3 - float(q4k / q2 ** 2))
+        assert abs(dis[k, 5] - g) < 1e-13
+        assert abs(dis[k, 0] - float(Fraction(int(m["E"][:, k].sum()), S * 2 * n * N))) < 1e-15
