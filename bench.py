@@ -1,0 +1,157 @@
+"""Throughput benchmark: parallel-tempering Monte Carlo of the 3D +-J
+Edwards-Anderson spin glass on one MI355X.
+
+Workload (default "3d_l16"): L = 16 periodic, 1000 disorder samples x 2
+replica sets x 32 temperatures (geometric T in [0.9, 2.0]), int8 spins and
+couplings.  One step = one Monte Carlo step of the whole path: a checkerboard
+Metropolis sweep of all 64,000 lattices, one replica-exchange pass and one
+measurement (E, overlap moments).  All inputs are resident on the GPU before
+the timed region.
+
+Prints one JSON line: spin flips/ns over the timed steps, the sweep kernel's
+roofline position (VALU-bound: integer issue slots), and the CPU oracle's
+rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes, one 32-bit VALU op per lane per clock
+# at 2.4 GHz (a wave64 instruction occupies a SIMD for 4 clocks).
+PEAK_VALU_OPS = 256 * 64 * 2.4e9
+# Algorithmic integer work per attempted flip: the site's share of one
+# Philox4x32-10 call (10 rounds x (2 32x32->64 multiplies + 2 three-input
+# xors) per 4 words = 10 ops) plus the threshold compare (1 op).  The local
+# field and the classification are bit-sliced over a row word and not counted.
+OPS_PER_FLIP = 11
+
+
+def cpu_baseline(wl, budget_s: float):
+    import oracle
+    from paper_2003_04621_amd import workloads as W
+    keys = [0, 1]
+    J = wl.couplings()[keys]
+    ref = oracle.OracleJob(len(keys), wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed,
+                           sample_keys=keys)
+    per_mcs = len(keys) * 2 * wl.replicas * wl.N
+    # calibrate on a few steps, then run about `budget_s` seconds
+    t = time.perf_counter()
+    ref.mcs(2, houdayer=wl.houdayer, measure=True)
+    dt = time.perf_counter() - t
+    n = max(1, int(budget_s / max(dt / 2, 1e-6)))
+    t = time.perf_counter()
+    ref.mcs(n, houdayer=wl.houdayer, measure=True)
+    dt = time.perf_counter() - t
+    return {"value": round(per_mcs * n / dt / 1e9, 6), "unit": "flips/ns", "cores": 1,
+            "kind": "oracle",
+            "sample": f"samples {keys} of {wl.samples} (all {2 * wl.replicas} replicas), "
+                      f"{n} Monte Carlo steps, {dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="3d_l16")
+    ap.add_argument("--layout", choices=["int8", "packed"], default="int8")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-bytes", type=float, default=None,
+                    help="HBM bytes per sweep launch measured with rocprofv3 counters")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 5 times (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 5}), flush=True)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path shards by disorder sample and "
+              "has no multi-GPU run; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2003_04621_amd import pt, workloads as W
+
+    wl = W.workload(args.workload)
+    layout = pt.PT_LAYOUT_PACKED if args.layout == "packed" else pt.PT_LAYOUT_INT8
+    torch.cuda.set_device(0)
+    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed,
+                     layout=layout)
+    flips_per_step = wl.flips_per_sweep
+    print(f"# workload {wl.name}: S={wl.samples} NT={wl.replicas} L={wl.L} d={wl.dim} "
+          f"layout={args.layout}; warmup {args.warmup}", file=sys.stderr, flush=True)
+    pt.pt_mcs(job, args.warmup, houdayer=wl.houdayer, measure=True)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        a, b = ev[i]
+        a.record(stream)
+        pt.pt_sweep(job, 1)
+        b.record(stream)
+        if wl.houdayer:
+            pt.pt_houdayer(job)
+        pt.pt_exchange(job)
+        pt.pt_measure(job)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    value = flips_per_step * K / elapsed / 1e9
+    achieved = OPS_PER_FLIP * flips_per_step / (sweep_ms * 1e-3) / 1e12
+    peak = PEAK_VALU_OPS / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "TOP/s", "frac": round(achieved / peak, 4),
+                "traffic": args.traffic_bytes, "kernel": "k_sweep<3>",
+                "sweep_ms": round(sweep_ms, 5),
+                "sweep_flips_per_ns": round(flips_per_step / (sweep_ms * 1e6), 1)}
+    counters = pt.pt_get_counters(job)
+    assert counters["t"] == args.warmup + K and counters["n_meas"] == args.warmup + K
+    _, dis, n_meas = pt.pt_observables(job)
+    pt.pt_destroy(job)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+    out = {
+        "metric": "spin flips/ns (1 GPU)", "value": round(value, 2), "unit": "flips/ns",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / K * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": wl.name, "dim": wl.dim, "L": wl.L, "samples": wl.samples,
+                   "replica_sets": 2, "temperatures": wl.replicas,
+                   "T_range": [round(1 / wl.betas[0], 6), round(1 / wl.betas[-1], 6)],
+                   "spin_layout": args.layout,
+                   "step": "sweep+houdayer+exchange+measure" if wl.houdayer
+                   else "sweep+exchange+measure"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "e_coldest": round(float(dis[0, 0]), 6), "binder_coldest": round(float(dis[0, 5]), 6),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

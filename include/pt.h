@@ -1,0 +1,178 @@
+/*
+ * pt.h -- C ABI of the MI355X (gfx950) parallel-tempering EA spin-glass library.
+ *
+ * The library simulates the +-J Edwards-Anderson Ising spin glass, Eq. (1) of
+ * Kumar, Gross, Janke, Weigel (arXiv:2003.04621) at zero field, for many
+ * disorder samples at once.  Every sample carries two replica sets (N_C = 2,
+ * Sec. 3) of N_T temperatures each, i.e. 2*N_T configurations ("slots").
+ * One Monte Carlo step (Sec. 2.4) is: pt_sweep(job, 1), then optionally
+ * pt_houdayer(job), then pt_exchange(job), then optionally pt_measure(job).
+ *
+ * Conventions used by every entry point:
+ *   - Lattice: L^dim sites, square (dim 2) or simple cubic (dim 3), periodic.
+ *     Site i = x0 + L*x1 (+ L^2*x2).  L must be even, 4 <= L <= 64.
+ *   - Couplings: int8 [samples][dim][L^dim], each +1 or -1; entry [s][mu][i]
+ *     is the bond between site i and i + e_mu (Eq. (2) draws them).
+ *   - Spins: int8 +1/-1 [samples][2*replicas][L^dim], indexed by slot
+ *     r = c*replicas + j (replica set c in {0,1}, j < replicas).
+ *   - Temperatures: betas[k] = 1/T_k, k = 0 the coldest; strictly decreasing.
+ *   - Temperature maps (Sec. 3, two index arrays): slot_of_temp[s][c][k] = j
+ *     means slot c*replicas + j currently runs at beta_k; temp_of_slot is its
+ *     inverse.  Replica exchange swaps map entries, never spins.
+ *   - Energies: int32 [samples][2*replicas], E = -sum_<ij> J_ij s_i s_j.
+ *   - Randomness: Philox4x32-10 (Sec. 3, Salmon et al. 2011) keyed by the
+ *     64-bit seed; the counter of every draw is a pure function of (sample,
+ *     slot, site, sweep/pass), so results do not depend on launch shape.
+ *
+ * Ownership: input arrays are host memory owned by the caller and are copied
+ * before the call returns.  Output arrays are host memory allocated by the
+ * caller.  Device state belongs to the job until pt_destroy and is allocated
+ * through the hooks of pt_set_allocator (hipMalloc/hipFree if none are set).
+ *
+ * Synchronisation: pt_sweep, pt_exchange, pt_houdayer, pt_measure and pt_mcs
+ * only enqueue work on the job's stream.  pt_observables, pt_get_*, pt_set_*,
+ * pt_get_state, pt_set_state and pt_destroy synchronise that stream.  A job
+ * handle is not thread-safe; distinct handles may be used concurrently.
+ *
+ * Errors: every function returns PT_OK (0) or a negative code and never
+ * throws.  pt_last_error() gives a thread-local message for the last failure.
+ * Invalid arguments (PT_EINVAL) leave the job unchanged.  A HIP failure
+ * (PT_EDEVICE) poisons the job; every later call on it returns PT_ESTATE
+ * except pt_destroy.
+ */
+#ifndef PT_SPINGLASS_H
+#define PT_SPINGLASS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PT_OK 0
+#define PT_EINVAL (-1)
+#define PT_ENOMEM (-2)
+#define PT_EDEVICE (-3)
+#define PT_ESTATE (-4)
+
+/* Device spin layouts (pt_init_ex flags). */
+#define PT_LAYOUT_INT8 0u   /* one int8 per spin, lattice-contiguous */
+#define PT_LAYOUT_PACKED 1u /* one bit per spin, split by checkerboard colour */
+
+/* pt_mcs flags */
+#define PT_MCS_HOUDAYER 1u
+#define PT_MCS_MEASURE 2u
+
+typedef struct pt_job pt_job;
+
+/* Creates a job: copies the couplings in, draws the initial spins (one
+ * Philox word per site), sets the maps to the identity, computes every
+ * energy and zeroes the sweep/exchange/Houdayer counters and the moments.
+ * Sec. 2.1 (model, Eqs. (1)-(2)), Sec. 3 (replica layout).
+ *   out       receives the handle (unchanged on failure)
+ *   samples   >= 1 and < 2^28
+ *   replicas  N_T >= 2
+ *   L, dim    even L in [4, 64]; dim 2 or 3
+ *   couplings host int8 [samples][dim][L^dim], every entry +1 or -1
+ *   betas     host double [replicas], finite, > 0, strictly decreasing
+ *   seed      Philox key
+ * Returns PT_EINVAL for any violated condition, PT_ENOMEM if allocation
+ * fails, PT_EDEVICE on a HIP error. */
+int pt_init(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
+            int32_t dim, const int8_t *couplings, const double *betas,
+            uint64_t seed);
+
+/* pt_init with a device spin layout: flags = PT_LAYOUT_INT8 or
+ * PT_LAYOUT_PACKED.  Results are bit-identical for both layouts. */
+int pt_init_ex(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
+               int32_t dim, const int8_t *couplings, const double *betas,
+               uint64_t seed, uint32_t flags);
+
+/* n >= 0 Metropolis sweeps (Sec. 2.2) of every configuration: colour 0 of
+ * the checkerboard, then colour 1.  A site with x = s_i * sum_j J_ij s_j <= 0
+ * always flips; otherwise it flips iff its 32-bit Philox word r satisfies
+ * r < floor(2^32 exp(-2 x beta_k)) (clamped to 2^32-1), beta_k being the
+ * slot's current temperature.  Energies are updated by 2x per flip.  The word
+ * of a site comes from counter (R*ceil(L/8) + (b>>2), 2t + colour, slot,
+ * 3<<28 | sample), word b & 3, where R = i / L, b = (i % L) >> 1 and t the
+ * job's sweep counter, which advances by n.  PT_EINVAL if n < 0. */
+int pt_sweep(pt_job *job, int32_t n);
+
+/* One replica-exchange pass (Sec. 2.2, Eq. (5)).  For each sample and each
+ * replica set separately, k = 0 .. N_T-2 ascending: with a, b the slots at
+ * beta_k, beta_{k+1} and D = E_b - E_a, the temperatures are swapped iff
+ * D <= 0 or r < floor(2^32 exp(-(beta_k - beta_{k+1}) D)), r being word 0 of
+ * the Philox counter (k, u, set, 4<<28 | sample), u the exchange counter. */
+int pt_exchange(pt_job *job);
+
+/* One Houdayer cluster move (Sec. 2.4, Eq. (10)) per sample and temperature
+ * k, on the pair (set 0, set 1) currently at beta_k.  With q_i = s_i^a s_i^b
+ * and n the number of q = -1 sites, nothing happens if n = 0; otherwise the
+ * seed is the m-th q = -1 site in increasing i, m = floor(r64 n / 2^64) with
+ * r64 = w0 | w1 << 32 from Philox counter (k, v, 0, 5<<28 | sample); the
+ * cluster is its nearest-neighbour connected component of q = -1 sites, and
+ * both replicas are negated on it (equivalently: exchanged there).  E_a
+ * changes by delta and E_b by -delta. */
+int pt_houdayer(pt_job *job);
+
+/* Accumulates one measurement (Eqs. (3), (4)): per sample and temperature,
+ * exact integer sums of E (both replicas), E^2, Q, |Q|, Q^2 and Q^4 (128-bit)
+ * with Q = sum_i s_i^a s_i^b over the pair at that temperature. */
+int pt_measure(pt_job *job);
+
+/* n Monte Carlo steps (Sec. 2.4): sweep, Houdayer if flags has
+ * PT_MCS_HOUDAYER, exchange, measure if flags has PT_MCS_MEASURE. */
+int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
+
+/* Observables from the accumulated moments, in double precision.
+ *   per_sample [samples][replicas][5]: <e>, <q>, <|q|>, <q^2>, <q^4>
+ *   disorder   [replicas][6]: the same averaged over samples (integer
+ *              numerators summed first) and the Binder parameter
+ *              g = (3 - [<q^4>]/[<q^2>]^2) / 2
+ *   n_meas     number of measurements
+ * Any output pointer may be NULL.  With no measurement the averages are NaN. */
+int pt_observables(pt_job *job, double *per_sample, double *disorder,
+                   int64_t *n_meas);
+
+/* Releases the job and its device memory (synchronises its stream). */
+int pt_destroy(pt_job *job);
+
+/* ---- state access (synchronous) ---------------------------------------- */
+/* int8 [samples][2*replicas][L^dim] */
+int pt_get_spins(pt_job *job, int8_t *out);
+/* Replaces every spin (entries must be +1/-1) and recomputes every energy. */
+int pt_set_spins(pt_job *job, const int8_t *in);
+/* int32 [samples][2*replicas] */
+int pt_get_energies(pt_job *job, int32_t *out);
+/* int32 [samples][2][replicas] each; either may be NULL */
+int pt_get_maps(pt_job *job, int32_t *slot_of_temp, int32_t *temp_of_slot);
+/* uint64 [4]: sweeps t, exchange passes u, Houdayer passes v, measurements */
+int pt_get_counters(pt_job *job, uint64_t *out);
+/* int64 [samples][replicas][7]: sum E, sum E^2, sum Q, sum |Q|, sum Q^2,
+ * sum Q^4 low 64 bits, sum Q^4 high 64 bits */
+int pt_get_moments(pt_job *job, int64_t *out);
+/* Checkpoint: the whole dynamic state (spins, energies, maps, counters,
+ * moments).  With buf == NULL, *len receives the size.  Otherwise *len must
+ * hold at least that size.  pt_set_state restores a state taken from a job of
+ * identical shape and layout; continuing is bit-identical to never stopping. */
+int pt_get_state(pt_job *job, void *buf, size_t *len);
+int pt_set_state(pt_job *job, const void *buf, size_t len);
+
+/* ---- plumbing ------------------------------------------------------------ */
+/* Makes the job enqueue on a HIP stream (hipStream_t; NULL = null stream). */
+int pt_set_stream(pt_job *job, void *hip_stream);
+/* Process-wide device allocator hooks used by later pt_init calls; pass NULLs
+ * to restore hipMalloc/hipFree.  alloc(bytes, ctx) returns device memory or
+ * NULL; free_(ptr, ctx) releases it. */
+int pt_set_allocator(void *(*alloc)(size_t, void *),
+                     void (*free_)(void *, void *), void *ctx);
+/* Thread-local message for the last failure on this thread ("" if none). */
+const char *pt_last_error(void);
+/* Library version string. */
+const char *pt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PT_SPINGLASS_H */

@@ -1,0 +1,48 @@
+// kernels.h -- host-side launchers of the gfx950 kernels (one per step of
+// the path).  All launchers enqueue on `st` and return hipGetLastError().
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace ptsg {
+
+// Initial spins: site i of slot r, sample s takes word i&3 of Philox counter
+// (i>>2, 0, r, 2<<28 | s); s_i = -1 iff the word's top bit is set.
+hipError_t launch_init_spins(const Geo& g, void* spins, hipStream_t st);
+
+// int8 couplings [S][d][N] -> direction words jw [S][2][2d][NR]: bit b of
+// jw[s][c][dir][R] is set iff the bond between the colour-c site b of row R and
+// its neighbour in direction dir (+x0, -x0, +x1, -x1, +x2, -x2) is -1.
+hipError_t launch_pack_couplings(const Geo& g, const int8_t* J8, uint32_t* jw, hipStream_t st);
+
+// Energy of every slot from scratch: E = 2 * #unsatisfied bonds - d*N.
+hipError_t launch_energy(const Geo& g, const void* spins, const uint32_t* jw, int32_t* E,
+                         hipStream_t st);
+
+// n checkerboard Metropolis sweeps starting at sweep number ctr->t.
+hipError_t launch_sweep(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
+                        const int32_t* tos, const uint32_t* thr, DevCounters* ctr, int n,
+                        hipStream_t st);
+
+// One replica-exchange pass numbered ctr->u.
+hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t* tos,
+                           const uint32_t* thrpt, int M, DevCounters* ctr, hipStream_t st);
+
+// One Houdayer pass numbered ctr->v.
+hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
+                           const int32_t* sot, DevCounters* ctr, hipStream_t st);
+
+// One measurement; mom is int64 [S][NT][8].
+hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E,
+                          const int32_t* sot, int64_t* mom, DevCounters* ctr, hipStream_t st);
+
+// Advances the device counters by `step` (one thread; enqueued after the
+// kernels that read them).
+hipError_t launch_advance(DevCounters* ctr, CounterStep step, hipStream_t st);
+
+// Launch shape of the sweep kernel (threads per lattice T, lattices per block).
+void sweep_shape(const Geo& g, int& T, int& LPB, int& threads, size_t& lds);
+
+}  // namespace ptsg

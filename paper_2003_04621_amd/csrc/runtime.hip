@@ -1,0 +1,573 @@
+// runtime.hip -- the C ABI declared in include/pt.h: job state, argument
+// validation, host-built acceptance tables, device memory and the
+// sequencing of the kernels on the job's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "pt.h"
+
+#define PT_API extern "C" __attribute__((visibility("default")))
+
+using namespace ptsg;
+
+namespace {
+
+thread_local std::string g_err;
+
+void* (*g_alloc)(size_t, void*) = nullptr;
+void (*g_free)(void*, void*) = nullptr;
+void* g_ctx = nullptr;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// Acceptance probability p -> 32-bit threshold floor(2^32 p), clamped to
+// [0, 2^32 - 1]; a uniform 32-bit word r accepts iff r < threshold.
+uint32_t threshold_u32(double p) {
+  const double v = std::floor(std::ldexp(p, 32));
+  if (v >= 4294967295.0) return 0xFFFFFFFFu;
+  if (v <= 0.0) return 0u;
+  return (uint32_t)v;
+}
+
+}  // namespace
+
+struct pt_job {
+  Geo g{};
+  hipStream_t stream = nullptr;
+  void* spins = nullptr;     // int8 [S][2NT][N] or u32 [S][2NT][2][NR]
+  uint32_t* jw = nullptr;    // [S][2][2d][NR]
+  int32_t* E = nullptr;      // [S][2NT]
+  int32_t* sot = nullptr;    // [S][2][NT]
+  int32_t* tos = nullptr;    // [S][2][NT]
+  uint32_t* thr = nullptr;   // [NT][4]
+  uint32_t* thrpt = nullptr; // [NT-1][M]
+  int M = 0;
+  DevCounters* ctr = nullptr;
+  int64_t* mom = nullptr;    // [S][NT][8]
+  bool poisoned = false;
+  std::vector<void*> allocs;
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_ctx = nullptr;
+
+  size_t spin_bytes() const {
+    const size_t lat = (size_t)g.S * g.nslot;
+    return g.layout == kLayoutPacked ? lat * 2 * g.NR * sizeof(uint32_t) : lat * g.N;
+  }
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 4;
+    if (alloc_fn) {
+      p = alloc_fn(bytes, alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) allocs.push_back(p);
+    return p;
+  }
+  void release() {
+    for (void* p : allocs) {
+      if (free_fn)
+        free_fn(p, alloc_ctx);
+      else
+        (void)hipFree(p);
+    }
+    allocs.clear();
+  }
+};
+
+namespace {
+
+int device_error(pt_job* job, hipError_t e, const char* where) {
+  if (job) job->poisoned = true;
+  return fail(PT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define PT_HIP(job, expr)                                      \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return device_error(job, e_, #expr); \
+  } while (0)
+
+int check_job(pt_job* job) {
+  if (!job) return fail(PT_EINVAL, "null job handle");
+  if (job->poisoned) return fail(PT_ESTATE, "job is poisoned by an earlier device error");
+  return PT_OK;
+}
+
+void pack_host(const Geo& g, const int8_t* in, uint32_t* out) {
+  // int8 lattices -> colour-split row words (used by pt_set_spins, packed layout)
+  const size_t nlat = (size_t)g.S * g.nslot;
+  for (size_t lat = 0; lat < nlat; ++lat) {
+    const int8_t* s = in + lat * g.N;
+    uint32_t* w = out + lat * 2 * g.NR;
+    for (int R = 0; R < g.NR; ++R) {
+      const int x1 = R % g.L, x2 = R / g.L;
+      uint32_t W[2] = {0, 0};
+      for (int x0 = 0; x0 < g.L; ++x0) {
+        const int c = (x0 + x1 + x2) & 1;
+        if (s[(size_t)R * g.L + x0] < 0) W[c] |= 1u << (x0 >> 1);
+      }
+      w[R] = W[0];
+      w[g.NR + R] = W[1];
+    }
+  }
+}
+
+void unpack_host(const Geo& g, const uint32_t* in, int8_t* out) {
+  const size_t nlat = (size_t)g.S * g.nslot;
+  for (size_t lat = 0; lat < nlat; ++lat) {
+    int8_t* s = out + lat * g.N;
+    const uint32_t* w = in + lat * 2 * g.NR;
+    for (int R = 0; R < g.NR; ++R) {
+      const int x1 = R % g.L, x2 = R / g.L;
+      for (int x0 = 0; x0 < g.L; ++x0) {
+        const int c = (x0 + x1 + x2) & 1;
+        s[(size_t)R * g.L + x0] = ((w[c * g.NR + R] >> (x0 >> 1)) & 1u) ? (int8_t)-1 : (int8_t)1;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+PT_API const char* pt_last_error(void) { return g_err.c_str(); }
+PT_API const char* pt_version(void) { return "ptsg-gfx950 0.1"; }
+
+PT_API int pt_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return fail(PT_EINVAL, "allocator and free hooks must both be set or both be NULL");
+  g_alloc = alloc;
+  g_free = free_;
+  g_ctx = ctx;
+  return PT_OK;
+}
+
+PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
+                      const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags) {
+  g_err.clear();
+  if (!out || !couplings || !betas) return fail(PT_EINVAL, "null pointer argument");
+  if (dim != 2 && dim != 3) return fail(PT_EINVAL, "dim must be 2 or 3");
+  if (L < 4 || L > 64 || (L & 1)) return fail(PT_EINVAL, "L must be even and in [4, 64]");
+  if (samples < 1 || samples >= (1 << 28)) return fail(PT_EINVAL, "samples must be in [1, 2^28)");
+  if (replicas < 2 || replicas > 4096) return fail(PT_EINVAL, "replicas must be in [2, 4096]");
+  if (flags != PT_LAYOUT_INT8 && flags != PT_LAYOUT_PACKED) return fail(PT_EINVAL, "unknown flags");
+  for (int k = 0; k < replicas; ++k) {
+    if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
+      return fail(PT_EINVAL, "betas must be finite and > 0");
+    if (k > 0 && !(betas[k] < betas[k - 1]))
+      return fail(PT_EINVAL, "betas must be strictly decreasing (index 0 = coldest)");
+  }
+  const long N = (dim == 3) ? (long)L * L * L : (long)L * L;
+  const long ncoup = (long)samples * dim * N;
+  for (long i = 0; i < ncoup; ++i)
+    if (couplings[i] != 1 && couplings[i] != -1) return fail(PT_EINVAL, "couplings must be +1 or -1");
+  const long nlat = (long)samples * 2 * replicas;
+  if (nlat > 0x7FFFFFFFL || (long)samples * replicas > 0x7FFFFFFFL)
+    return fail(PT_EINVAL, "too many lattices for one job");
+
+  pt_job* job = new (std::nothrow) pt_job();
+  if (!job) return fail(PT_ENOMEM, "host allocation failed");
+  job->alloc_fn = g_alloc;
+  job->free_fn = g_free;
+  job->alloc_ctx = g_ctx;
+  Geo& g = job->g;
+  g.L = L;
+  g.d = dim;
+  g.N = (int)N;
+  g.NR = (int)(N / L);
+  g.H = L / 2;
+  g.G = (L + 7) / 8;
+  g.magicL = (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L);
+  g.maskH = (g.H == 32) ? 0xFFFFFFFFu : ((1u << g.H) - 1u);
+  g.S = samples;
+  g.NT = replicas;
+  g.nslot = 2 * replicas;
+  g.layout = (int)flags;
+  g.key0 = (uint32_t)seed;
+  g.key1 = (uint32_t)(seed >> 32);
+
+  // Metropolis thresholds: x = 2m (m = 1..d), energy change 4m.
+  std::vector<uint32_t> thr((size_t)replicas * 4, 0u);
+  for (int k = 0; k < replicas; ++k)
+    for (int m = 1; m <= dim; ++m) {
+      const double dE = (double)(4 * m);
+      thr[(size_t)k * 4 + (m - 1)] = threshold_u32(std::exp(-(betas[k] * dE)));
+    }
+  // Exchange thresholds: D = 2m, row length M = first m where every row is 0.
+  int M = 1;
+  const long mmax = (long)dim * N;
+  for (int k = 0; k + 1 < replicas; ++k) {
+    const double db = betas[k] - betas[k + 1];
+    long m = 1;
+    while (m <= mmax && threshold_u32(std::exp(-(db * (double)(2 * m)))) != 0u) ++m;
+    if (m > M) M = (int)m;
+  }
+  std::vector<uint32_t> thrpt((size_t)(replicas - 1) * M, 0u);
+  for (int k = 0; k + 1 < replicas; ++k) {
+    const double db = betas[k] - betas[k + 1];
+    thrpt[(size_t)k * M] = 0xFFFFFFFFu;
+    for (int m = 1; m < M; ++m)
+      thrpt[(size_t)k * M + m] = threshold_u32(std::exp(-(db * (double)(2 * m))));
+  }
+  job->M = M;
+
+  const size_t maps = sizeof(int32_t) * (size_t)samples * 2 * replicas;
+  job->spins = job->dalloc(job->spin_bytes());
+  job->jw = (uint32_t*)job->dalloc(sizeof(uint32_t) * (size_t)samples * 2 * 2 * dim * g.NR);
+  job->E = (int32_t*)job->dalloc(sizeof(int32_t) * (size_t)nlat);
+  job->sot = (int32_t*)job->dalloc(maps);
+  job->tos = (int32_t*)job->dalloc(maps);
+  job->thr = (uint32_t*)job->dalloc(sizeof(uint32_t) * thr.size());
+  job->thrpt = (uint32_t*)job->dalloc(sizeof(uint32_t) * thrpt.size());
+  job->ctr = (DevCounters*)job->dalloc(sizeof(DevCounters));
+  job->mom = (int64_t*)job->dalloc(sizeof(int64_t) * 8 * (size_t)samples * replicas);
+  int8_t* J8 = (int8_t*)job->dalloc((size_t)ncoup);
+  if (!job->spins || !job->jw || !job->E || !job->sot || !job->tos || !job->thr || !job->thrpt ||
+      !job->ctr || !job->mom || !J8) {
+    job->release();
+    delete job;
+    return fail(PT_ENOMEM, "device allocation failed");
+  }
+  std::vector<int32_t> ident((size_t)samples * 2 * replicas);
+  for (size_t i = 0; i < ident.size(); ++i) ident[i] = (int32_t)(i % replicas);
+
+  hipStream_t st = job->stream;
+  hipError_t e = hipSuccess;
+  auto step = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+  step(hipMemcpyAsync(J8, couplings, (size_t)ncoup, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->thr, thr.data(), sizeof(uint32_t) * thr.size(), hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->thrpt, thrpt.data(), sizeof(uint32_t) * thrpt.size(), hipMemcpyHostToDevice,
+                      st));
+  step(hipMemcpyAsync(job->sot, ident.data(), maps, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->tos, ident.data(), maps, hipMemcpyHostToDevice, st));
+  step(hipMemsetAsync(job->ctr, 0, sizeof(DevCounters), st));
+  step(hipMemsetAsync(job->mom, 0, sizeof(int64_t) * 8 * (size_t)samples * replicas, st));
+  step(launch_pack_couplings(g, J8, job->jw, st));
+  step(launch_init_spins(g, job->spins, st));
+  step(launch_energy(g, job->spins, job->jw, job->E, st));
+  step(hipStreamSynchronize(st));
+  if (e != hipSuccess) {
+    std::string msg = std::string("pt_init: ") + hipGetErrorString(e);
+    job->release();
+    delete job;
+    return fail(PT_EDEVICE, msg);
+  }
+  *out = job;
+  return PT_OK;
+}
+
+PT_API int pt_init(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
+                   const int8_t* couplings, const double* betas, uint64_t seed) {
+  return pt_init_ex(out, samples, replicas, L, dim, couplings, betas, seed, PT_LAYOUT_INT8);
+}
+
+PT_API int pt_destroy(pt_job* job) {
+  if (!job) return fail(PT_EINVAL, "null job handle");
+  (void)hipStreamSynchronize(job->stream);
+  (void)hipGetLastError();
+  job->release();
+  delete job;
+  return PT_OK;
+}
+
+PT_API int pt_set_stream(pt_job* job, void* hip_stream) {
+  if (int rc = check_job(job)) return rc;
+  job->stream = (hipStream_t)hip_stream;
+  return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// asynchronous steps
+// ---------------------------------------------------------------------------
+PT_API int pt_sweep(pt_job* job, int32_t n) {
+  if (int rc = check_job(job)) return rc;
+  if (n < 0) return fail(PT_EINVAL, "n must be >= 0");
+  const int chunk = 1000;
+  for (int done = 0; done < n; done += chunk) {
+    const int m = (n - done) < chunk ? (n - done) : chunk;
+    PT_HIP(job, launch_sweep(job->g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, m,
+                             job->stream));
+    PT_HIP(job, launch_advance(job->ctr, CounterStep{(uint32_t)m, 0, 0, 0}, job->stream));
+  }
+  return PT_OK;
+}
+
+PT_API int pt_exchange(pt_job* job) {
+  if (int rc = check_job(job)) return rc;
+  PT_HIP(job, launch_exchange(job->g, job->E, job->sot, job->tos, job->thrpt, job->M, job->ctr,
+                              job->stream));
+  PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 1, 0, 0}, job->stream));
+  return PT_OK;
+}
+
+PT_API int pt_houdayer(pt_job* job) {
+  if (int rc = check_job(job)) return rc;
+  PT_HIP(job, launch_houdayer(job->g, job->spins, job->jw, job->E, job->sot, job->ctr, job->stream));
+  PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 1, 0}, job->stream));
+  return PT_OK;
+}
+
+PT_API int pt_measure(pt_job* job) {
+  if (int rc = check_job(job)) return rc;
+  PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->ctr, job->stream));
+  PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 0, 1}, job->stream));
+  return PT_OK;
+}
+
+PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
+  if (int rc = check_job(job)) return rc;
+  if (n < 0) return fail(PT_EINVAL, "n must be >= 0");
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE)) return fail(PT_EINVAL, "unknown flags");
+  // Within one step every counter is read by exactly one kernel, so a single
+  // advance per step keeps the numbering of the separate entry points.
+  const Geo& g = job->g;
+  hipStream_t st = job->stream;
+  const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  for (int i = 0; i < n; ++i) {
+    PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, st));
+    if (hou) PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
+    PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->ctr, st));
+    if (meas) PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->ctr, st));
+    PT_HIP(job, launch_advance(job->ctr, CounterStep{1, 1, hou ? 1u : 0u, meas ? 1u : 0u}, st));
+  }
+  return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// synchronous state access
+// ---------------------------------------------------------------------------
+PT_API int pt_get_counters(pt_job* job, uint64_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (!out) return fail(PT_EINVAL, "null output");
+  DevCounters c;
+  PT_HIP(job, hipMemcpyAsync(&c, job->ctr, sizeof(c), hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  out[0] = c.t;
+  out[1] = c.u;
+  out[2] = c.v;
+  out[3] = c.n_meas;
+  return PT_OK;
+}
+
+PT_API int pt_get_spins(pt_job* job, int8_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (!out) return fail(PT_EINVAL, "null output");
+  const Geo& g = job->g;
+  if (g.layout == kLayoutPacked) {
+    std::vector<uint32_t> tmp(job->spin_bytes() / sizeof(uint32_t));
+    PT_HIP(job, hipMemcpyAsync(tmp.data(), job->spins, job->spin_bytes(), hipMemcpyDeviceToHost,
+                               job->stream));
+    PT_HIP(job, hipStreamSynchronize(job->stream));
+    unpack_host(g, tmp.data(), out);
+  } else {
+    PT_HIP(job, hipMemcpyAsync(out, job->spins, job->spin_bytes(), hipMemcpyDeviceToHost, job->stream));
+    PT_HIP(job, hipStreamSynchronize(job->stream));
+  }
+  return PT_OK;
+}
+
+PT_API int pt_set_spins(pt_job* job, const int8_t* in) {
+  if (int rc = check_job(job)) return rc;
+  if (!in) return fail(PT_EINVAL, "null input");
+  const Geo& g = job->g;
+  const size_t n = (size_t)g.S * g.nslot * g.N;
+  for (size_t i = 0; i < n; ++i)
+    if (in[i] != 1 && in[i] != -1) return fail(PT_EINVAL, "spins must be +1 or -1");
+  if (g.layout == kLayoutPacked) {
+    std::vector<uint32_t> tmp(job->spin_bytes() / sizeof(uint32_t));
+    pack_host(g, in, tmp.data());
+    PT_HIP(job, hipMemcpyAsync(job->spins, tmp.data(), job->spin_bytes(), hipMemcpyHostToDevice,
+                               job->stream));
+    PT_HIP(job, launch_energy(g, job->spins, job->jw, job->E, job->stream));
+    PT_HIP(job, hipStreamSynchronize(job->stream));
+  } else {
+    PT_HIP(job, hipMemcpyAsync(job->spins, in, n, hipMemcpyHostToDevice, job->stream));
+    PT_HIP(job, launch_energy(g, job->spins, job->jw, job->E, job->stream));
+    PT_HIP(job, hipStreamSynchronize(job->stream));
+  }
+  return PT_OK;
+}
+
+PT_API int pt_get_energies(pt_job* job, int32_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (!out) return fail(PT_EINVAL, "null output");
+  const size_t n = (size_t)job->g.S * job->g.nslot;
+  PT_HIP(job, hipMemcpyAsync(out, job->E, sizeof(int32_t) * n, hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  return PT_OK;
+}
+
+PT_API int pt_get_maps(pt_job* job, int32_t* slot_of_temp, int32_t* temp_of_slot) {
+  if (int rc = check_job(job)) return rc;
+  const size_t n = sizeof(int32_t) * (size_t)job->g.S * 2 * job->g.NT;
+  if (slot_of_temp)
+    PT_HIP(job, hipMemcpyAsync(slot_of_temp, job->sot, n, hipMemcpyDeviceToHost, job->stream));
+  if (temp_of_slot)
+    PT_HIP(job, hipMemcpyAsync(temp_of_slot, job->tos, n, hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  return PT_OK;
+}
+
+PT_API int pt_get_moments(pt_job* job, int64_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (!out) return fail(PT_EINVAL, "null output");
+  const size_t n = (size_t)job->g.S * job->g.NT;
+  std::vector<int64_t> m(8 * n);
+  PT_HIP(job, hipMemcpyAsync(m.data(), job->mom, sizeof(int64_t) * m.size(), hipMemcpyDeviceToHost,
+                             job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  for (size_t i = 0; i < n; ++i)
+    for (int c = 0; c < 7; ++c) out[i * 7 + c] = m[i * 8 + c];
+  return PT_OK;
+}
+
+PT_API int pt_observables(pt_job* job, double* per_sample, double* disorder, int64_t* n_meas) {
+  if (int rc = check_job(job)) return rc;
+  const Geo& g = job->g;
+  const size_t n = (size_t)g.S * g.NT;
+  std::vector<int64_t> m(8 * n);
+  DevCounters c;
+  PT_HIP(job, hipMemcpyAsync(m.data(), job->mom, sizeof(int64_t) * m.size(), hipMemcpyDeviceToHost,
+                             job->stream));
+  PT_HIP(job, hipMemcpyAsync(&c, job->ctr, sizeof(c), hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  if (n_meas) *n_meas = (int64_t)c.n_meas;
+  const double nm = (double)c.n_meas, Nd = (double)g.N;
+  const double N2 = Nd * Nd, N4 = N2 * N2;
+  auto q4_of = [&](size_t i) {
+    const unsigned __int128 v =
+        ((unsigned __int128)(uint64_t)m[i * 8 + 6] << 64) | (unsigned __int128)(uint64_t)m[i * 8 + 5];
+    return v;
+  };
+  if (per_sample) {
+    for (size_t i = 0; i < n; ++i) {
+      double* o = per_sample + i * 5;
+      o[0] = (double)m[i * 8 + 0] / (2.0 * nm * Nd);
+      o[1] = (double)m[i * 8 + 2] / (nm * Nd);
+      o[2] = (double)m[i * 8 + 3] / (nm * Nd);
+      o[3] = (double)m[i * 8 + 4] / (nm * N2);
+      o[4] = (double)q4_of(i) / (nm * N4);
+    }
+  }
+  if (disorder) {
+    const double S = (double)g.S;
+    for (int k = 0; k < g.NT; ++k) {
+      int64_t sE = 0, sQ = 0, sAQ = 0, sQ2 = 0;
+      unsigned __int128 sQ4 = 0;
+      for (int s = 0; s < g.S; ++s) {
+        const size_t i = (size_t)s * g.NT + k;
+        sE += m[i * 8 + 0];
+        sQ += m[i * 8 + 2];
+        sAQ += m[i * 8 + 3];
+        sQ2 += m[i * 8 + 4];
+        sQ4 += q4_of(i);
+      }
+      double* o = disorder + (size_t)k * 6;
+      o[0] = (double)sE / (S * 2.0 * nm * Nd);
+      o[1] = (double)sQ / (S * nm * Nd);
+      o[2] = (double)sAQ / (S * nm * Nd);
+      o[3] = (double)sQ2 / (S * nm * N2);
+      o[4] = (double)sQ4 / (S * nm * N4);
+      o[5] = 0.5 * (3.0 - o[4] / (o[3] * o[3]));
+    }
+  }
+  return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoint / restore
+// ---------------------------------------------------------------------------
+namespace {
+struct StateHeader {
+  uint64_t magic;
+  int32_t S, NT, L, d, layout, pad;
+  uint64_t spin_bytes;
+};
+constexpr uint64_t kStateMagic = 0x50545347'53544154ull;  // "PTSGSTAT"
+
+size_t state_size(const pt_job* job) {
+  const Geo& g = job->g;
+  const size_t lat = (size_t)g.S * g.nslot;
+  return sizeof(StateHeader) + job->spin_bytes() + sizeof(int32_t) * lat +
+         2 * sizeof(int32_t) * (size_t)g.S * 2 * g.NT + sizeof(DevCounters) +
+         sizeof(int64_t) * 8 * (size_t)g.S * g.NT;
+}
+}  // namespace
+
+PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
+  if (int rc = check_job(job)) return rc;
+  if (!len) return fail(PT_EINVAL, "null length");
+  const size_t need = state_size(job);
+  if (!buf) {
+    *len = need;
+    return PT_OK;
+  }
+  if (*len < need) return fail(PT_EINVAL, "state buffer too small");
+  const Geo& g = job->g;
+  char* p = static_cast<char*>(buf);
+  StateHeader h{kStateMagic, g.S, g.NT, g.L, g.d, g.layout, 0, (uint64_t)job->spin_bytes()};
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  const size_t lat = (size_t)g.S * g.nslot, maps = sizeof(int32_t) * (size_t)g.S * 2 * g.NT;
+  hipStream_t st = job->stream;
+  PT_HIP(job, hipMemcpyAsync(p, job->spins, job->spin_bytes(), hipMemcpyDeviceToHost, st));
+  p += job->spin_bytes();
+  PT_HIP(job, hipMemcpyAsync(p, job->E, sizeof(int32_t) * lat, hipMemcpyDeviceToHost, st));
+  p += sizeof(int32_t) * lat;
+  PT_HIP(job, hipMemcpyAsync(p, job->sot, maps, hipMemcpyDeviceToHost, st));
+  p += maps;
+  PT_HIP(job, hipMemcpyAsync(p, job->tos, maps, hipMemcpyDeviceToHost, st));
+  p += maps;
+  PT_HIP(job, hipMemcpyAsync(p, job->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, st));
+  p += sizeof(DevCounters);
+  PT_HIP(job, hipMemcpyAsync(p, job->mom, sizeof(int64_t) * 8 * (size_t)g.S * g.NT,
+                             hipMemcpyDeviceToHost, st));
+  PT_HIP(job, hipStreamSynchronize(st));
+  *len = need;
+  return PT_OK;
+}
+
+PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
+  if (int rc = check_job(job)) return rc;
+  if (!buf) return fail(PT_EINVAL, "null state buffer");
+  if (len != state_size(job)) return fail(PT_EINVAL, "state size does not match this job");
+  const Geo& g = job->g;
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kStateMagic || h.S != g.S || h.NT != g.NT || h.L != g.L || h.d != g.d ||
+      h.layout != g.layout || h.spin_bytes != job->spin_bytes())
+    return fail(PT_EINVAL, "state was taken from a job of another shape or layout");
+  const char* p = static_cast<const char*>(buf) + sizeof(h);
+  const size_t lat = (size_t)g.S * g.nslot, maps = sizeof(int32_t) * (size_t)g.S * 2 * g.NT;
+  hipStream_t st = job->stream;
+  PT_HIP(job, hipMemcpyAsync(job->spins, p, job->spin_bytes(), hipMemcpyHostToDevice, st));
+  p += job->spin_bytes();
+  PT_HIP(job, hipMemcpyAsync(job->E, p, sizeof(int32_t) * lat, hipMemcpyHostToDevice, st));
+  p += sizeof(int32_t) * lat;
+  PT_HIP(job, hipMemcpyAsync(job->sot, p, maps, hipMemcpyHostToDevice, st));
+  p += maps;
+  PT_HIP(job, hipMemcpyAsync(job->tos, p, maps, hipMemcpyHostToDevice, st));
+  p += maps;
+  PT_HIP(job, hipMemcpyAsync(job->ctr, p, sizeof(DevCounters), hipMemcpyHostToDevice, st));
+  p += sizeof(DevCounters);
+  PT_HIP(job, hipMemcpyAsync(job->mom, p, sizeof(int64_t) * 8 * (size_t)g.S * g.NT,
+                             hipMemcpyHostToDevice, st));
+  PT_HIP(job, hipStreamSynchronize(st));
+  return PT_OK;
+}

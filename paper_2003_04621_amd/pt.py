@@ -1,0 +1,274 @@
+"""Python binding of the C ABI in include/pt.h (argument marshalling only).
+
+Every function has the name of its C entry point and forwards to it through
+ctypes; all simulation work runs in the gfx950 kernels of ``libptsg.so``.
+PyTorch supplies device memory (its caching allocator, through
+``pt_set_allocator``) and the stream (its current stream, through
+``pt_set_stream``).  Loading fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptsg.so")
+
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
+PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
+PT_MCS_HOUDAYER, PT_MCS_MEASURE = 1, 2
+_CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
+          PT_ESTATE: "PT_ESTATE"}
+
+EXPORTS = [
+    "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_measure", "pt_mcs",
+    "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
+    "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_state", "pt_set_state",
+    "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
+]
+
+
+class PTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_hooks = None
+
+
+def lib():
+    """Loads libptsg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_2003_04621_amd.build.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, U32, U64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64
+        sig = {
+            "pt_init": [C.POINTER(P), I32, I32, I32, I32, P, P, U64],
+            "pt_init_ex": [C.POINTER(P), I32, I32, I32, I32, P, P, U64, U32],
+            "pt_sweep": [P, I32], "pt_exchange": [P], "pt_houdayer": [P], "pt_measure": [P],
+            "pt_mcs": [P, I32, U32], "pt_observables": [P, P, P, P], "pt_destroy": [P],
+            "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
+            "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
+            "pt_get_state": [P, P, C.POINTER(C.c_size_t)], "pt_set_state": [P, P, C.c_size_t],
+            "pt_set_stream": [P, P], "pt_set_allocator": [_ALLOC, _FREE, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.pt_last_error.argtypes = []
+        L.pt_last_error.restype = C.c_char_p
+        L.pt_version.argtypes = []
+        L.pt_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PT_OK:
+        raise PTError(rc, lib().pt_last_error().decode())
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def pt_last_error() -> str:
+    return lib().pt_last_error().decode()
+
+
+def pt_version() -> str:
+    return lib().pt_version().decode()
+
+
+def use_torch_memory() -> None:
+    """Routes the library's device allocations through torch's caching
+    allocator (on torch's current stream)."""
+    global _hooks
+    import torch
+
+    def _alloc(size, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(size))
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+    hooks = (_ALLOC(_alloc), _FREE(_free))
+    _check(lib().pt_set_allocator(hooks[0], hooks[1], None))
+    _hooks = hooks
+
+
+def pt_set_allocator(alloc=None, free=None):
+    """pt_set_allocator(None, None) restores hipMalloc/hipFree."""
+    global _hooks
+    if alloc is None and free is None:
+        _check(lib().pt_set_allocator(_ALLOC(), _FREE(), None))
+        _hooks = None
+        return
+    hooks = (_ALLOC(alloc), _FREE(free))
+    _check(lib().pt_set_allocator(hooks[0], hooks[1], None))
+    _hooks = hooks
+
+
+_live_jobs = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live_jobs():
+    # runs before torch's own exit handlers (registered earlier), so the
+    # device memory goes back to the caching allocator while it still exists
+    for job in list(_live_jobs):
+        try:
+            pt_destroy(job)
+        except Exception:
+            pass
+
+
+class Job:
+    """Owning handle of a pt_job plus its shape."""
+
+    def __init__(self, handle, samples, replicas, L, dim, layout):
+        self.h = handle
+        self.S, self.NT, self.L, self.d, self.layout = samples, replicas, L, dim, layout
+        self.N = L ** dim
+        _live_jobs.add(self)
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().pt_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_INT8,
+            stream=None) -> Job:
+    """Creates a job; `stream` is a torch.cuda.Stream, a raw hipStream_t int,
+    or None for torch's current stream (torch memory hooks are installed)."""
+    import torch
+    if _hooks is None:
+        use_torch_memory()
+    J = np.ascontiguousarray(couplings, dtype=np.int8)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    if b.shape != (int(replicas),):
+        raise PTError(PT_EINVAL, "betas must have shape (replicas,)")
+    if J.size != int(samples) * int(dim) * int(L) ** int(dim):
+        raise PTError(PT_EINVAL, "couplings must have samples*dim*L^dim entries")
+    h = C.c_void_p()
+    _check(lib().pt_init_ex(C.byref(h), int(samples), int(replicas), int(L), int(dim), _p(J),
+                            _p(b), C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(layout)))
+    job = Job(h, int(samples), int(replicas), int(L), int(dim), int(layout))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    pt_set_stream(job, stream)
+    return job
+
+
+def pt_set_stream(job: Job, stream) -> None:
+    raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+    _check(lib().pt_set_stream(job.h, C.c_void_p(raw)))
+
+
+def pt_sweep(job: Job, n: int = 1) -> None:
+    _check(lib().pt_sweep(job.h, int(n)))
+
+
+def pt_exchange(job: Job) -> None:
+    _check(lib().pt_exchange(job.h))
+
+
+def pt_houdayer(job: Job) -> None:
+    _check(lib().pt_houdayer(job.h))
+
+
+def pt_measure(job: Job) -> None:
+    _check(lib().pt_measure(job.h))
+
+
+def pt_mcs(job: Job, n: int, houdayer: bool = False, measure: bool = False) -> None:
+    flags = (PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
+    _check(lib().pt_mcs(job.h, int(n), flags))
+
+
+def pt_observables(job: Job):
+    ps = np.zeros((job.S, job.NT, 5), np.float64)
+    dis = np.zeros((job.NT, 6), np.float64)
+    n = np.zeros(1, np.int64)
+    _check(lib().pt_observables(job.h, _p(ps), _p(dis), _p(n)))
+    return ps, dis, int(n[0])
+
+
+def pt_destroy(job: Job) -> None:
+    if job.h:
+        _check(lib().pt_destroy(job.h))
+        job.h = None
+
+
+def pt_get_spins(job: Job) -> np.ndarray:
+    out = np.zeros((job.S, 2 * job.NT, job.N), np.int8)
+    _check(lib().pt_get_spins(job.h, _p(out)))
+    return out
+
+
+def pt_set_spins(job: Job, spins) -> None:
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    if s.size != job.S * 2 * job.NT * job.N:
+        raise PTError(PT_EINVAL, "spins must have samples*2*replicas*L^dim entries")
+    _check(lib().pt_set_spins(job.h, _p(s)))
+
+
+def pt_get_energies(job: Job) -> np.ndarray:
+    out = np.zeros((job.S, 2 * job.NT), np.int32)
+    _check(lib().pt_get_energies(job.h, _p(out)))
+    return out
+
+
+def pt_get_maps(job: Job):
+    sot = np.zeros((job.S, 2, job.NT), np.int32)
+    tos = np.zeros((job.S, 2, job.NT), np.int32)
+    _check(lib().pt_get_maps(job.h, _p(sot), _p(tos)))
+    return sot, tos
+
+
+def pt_get_counters(job: Job) -> dict:
+    out = np.zeros(4, np.uint64)
+    _check(lib().pt_get_counters(job.h, _p(out)))
+    return dict(t=int(out[0]), u=int(out[1]), v=int(out[2]), n_meas=int(out[3]))
+
+
+def pt_get_moments(job: Job) -> dict:
+    out = np.zeros((job.S, job.NT, 7), np.int64)
+    _check(lib().pt_get_moments(job.h, _p(out)))
+    names = ["E", "E2", "Q", "AQ", "Q2"]
+    d = {n: out[:, :, i].copy() for i, n in enumerate(names)}
+    d["Q4"] = out[:, :, 5:7].view(np.uint64).copy()
+    return d
+
+
+def pt_get_state(job: Job) -> bytes:
+    n = C.c_size_t(0)
+    _check(lib().pt_get_state(job.h, None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib().pt_get_state(job.h, C.cast(buf, C.c_void_p), C.byref(n)))
+    return buf.raw[: n.value]
+
+
+def pt_set_state(job: Job, state: bytes) -> None:
+    buf = C.create_string_buffer(state, len(state))
+    _check(lib().pt_set_state(job.h, C.cast(buf, C.c_void_p), len(state)))
