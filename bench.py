@@ -6,7 +6,9 @@ replica sets x 32 temperatures (geometric T in [0.9, 2.0]), int8 spins and
 couplings.  One step = one Monte Carlo step of the whole path: a checkerboard
 Metropolis sweep of all 64,000 lattices, one replica-exchange pass and one
 measurement (E, overlap moments).  All inputs are resident on the GPU before
-the timed region.
+the timed region.  Steps run fused (one workgroup per sample, the sample
+resident in LDS, `--chunk` steps per launch); the same steps with one launch
+per kernel are timed afterwards for comparison.
 
 Prints one JSON line: spin flips/ns over the timed steps, the sweep kernel's
 roofline position (VALU-bound: integer issue slots), and the CPU oracle's
@@ -64,6 +66,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="3d_l16")
     ap.add_argument("--layout", choices=["int8", "packed"], default="int8")
+    ap.add_argument("--chunk", type=int, default=500, help="steps per fused launch")
+    ap.add_argument("--plain-steps", type=int, default=300,
+                    help="steps re-timed with one launch per kernel (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic-bytes", type=float, default=None,
@@ -102,33 +107,46 @@ def main():
 
     K = args.steps
     stream = torch.cuda.current_stream()
+    chunk = max(1, min(args.chunk, K))
+    starts = list(range(0, K, chunk))
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(K)]
+          for _ in starts]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(K):
-        a, b = ev[i]
+    for (a, b), st in zip(ev, starts):
+        n = min(chunk, K - st)
         a.record(stream)
-        pt.pt_sweep(job, 1)
+        pt.pt_mcs(job, n, houdayer=wl.houdayer, measure=True)
         b.record(stream)
-        if wl.houdayer:
-            pt.pt_houdayer(job)
-        pt.pt_exchange(job)
-        pt.pt_measure(job)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    # one fused launch per chunk: average launch duration over full chunks
+    full = [a.elapsed_time(b) for (a, b), st in zip(ev, starts) if K - st >= chunk]
+    launch_ms = float(np.mean(full))
     value = flips_per_step * K / elapsed / 1e9
-    achieved = OPS_PER_FLIP * flips_per_step / (sweep_ms * 1e-3) / 1e12
+    achieved = OPS_PER_FLIP * flips_per_step * chunk / (launch_ms * 1e-3) / 1e12
     peak = PEAK_VALU_OPS / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TOP/s", "frac": round(achieved / peak, 4),
-                "traffic": args.traffic_bytes, "kernel": "k_sweep<3>",
-                "sweep_ms": round(sweep_ms, 5),
-                "sweep_flips_per_ns": round(flips_per_step / (sweep_ms * 1e6), 1)}
+                "traffic": args.traffic_bytes,
+                "kernel": f"k_mcs<{wl.dim}> ({chunk} steps per launch)",
+                "launch_ms": round(launch_ms, 4)}
+
+    # the same steps as separate per-step launches, for the fused/plain ratio
+    plain = None
+    if args.plain_steps > 0:
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        pt.pt_mcs(job, args.plain_steps, houdayer=wl.houdayer, measure=True, plain=True)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - tp
+        plain = {"value": round(flips_per_step * args.plain_steps / dtp / 1e9, 2),
+                 "unit": "flips/ns", "steps": args.plain_steps,
+                 "form": "one launch per kernel per step"}
     counters = pt.pt_get_counters(job)
-    assert counters["t"] == args.warmup + K and counters["n_meas"] == args.warmup + K
+    total = args.warmup + K + max(args.plain_steps, 0)
+    assert counters["t"] == total and counters["n_meas"] == total, counters
     _, dis, n_meas = pt.pt_observables(job)
     pt.pt_destroy(job)
 
@@ -148,6 +166,7 @@ def main():
                    else "sweep+exchange+measure"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "plain_form": plain,
         "e_coldest": round(float(dis[0, 0]), 6), "binder_coldest": round(float(dis[0, 5]), 6),
     }
     print(json.dumps(out), flush=True)

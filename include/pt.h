@@ -63,6 +63,7 @@ extern "C" {
 /* pt_mcs flags */
 #define PT_MCS_HOUDAYER 1u
 #define PT_MCS_MEASURE 2u
+#define PT_MCS_PLAIN 4u /* force the separate per-step kernels */
 
 typedef struct pt_job pt_job;
 
@@ -122,7 +123,11 @@ int pt_houdayer(pt_job *job);
 int pt_measure(pt_job *job);
 
 /* n Monte Carlo steps (Sec. 2.4): sweep, Houdayer if flags has
- * PT_MCS_HOUDAYER, exchange, measure if flags has PT_MCS_MEASURE. */
+ * PT_MCS_HOUDAYER, exchange, measure if flags has PT_MCS_MEASURE.  When all
+ * 2*replicas configurations of one sample fit in a workgroup's LDS the steps
+ * run fused (one workgroup per sample, the sample resident on chip for the
+ * whole launch); PT_MCS_PLAIN forces one launch per step and kernel.  Both
+ * forms give bit-identical results. */
 int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
 
 /* Observables from the accumulated moments, in double precision.

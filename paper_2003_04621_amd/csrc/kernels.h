@@ -42,6 +42,22 @@ hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E,
 // kernels that read them).
 hipError_t launch_advance(DevCounters* ctr, CounterStep step, hipStream_t st);
 
+// LDS word offsets of the fused Monte Carlo step kernel (one sample per
+// workgroup).  PC = Houdayer pairs processed together.
+struct FusedLayout {
+  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, Qs, Cs, hcnt, hdelta, PC, words;
+};
+
+// Plans the LDS of the fused kernel; false if one sample does not fit.
+bool fused_plan(const Geo& g, bool houdayer, FusedLayout& lay);
+
+// nmcs whole Monte Carlo steps with every sample resident in LDS; the
+// counters are read, not advanced (enqueue launch_advance afterwards).
+hipError_t launch_mcs_fused(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
+                            int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
+                            const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
+                            int nmcs, bool houdayer, bool measure, hipStream_t st);
+
 // Launch shape of the sweep kernel (threads per lattice T, lattices per block).
 void sweep_shape(const Geo& g, int& T, int& LPB, int& threads, size_t& lds);
 

@@ -54,6 +54,8 @@ struct pt_job {
   int M = 0;
   DevCounters* ctr = nullptr;
   int64_t* mom = nullptr;    // [S][NT][8]
+  FusedLayout plan[2];       // fused-step LDS plans without / with Houdayer
+  bool fused_ok[2] = {false, false};
   bool poisoned = false;
   std::vector<void*> allocs;
   void* (*alloc_fn)(size_t, void*) = nullptr;
@@ -224,6 +226,8 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
       thrpt[(size_t)k * M + m] = threshold_u32(std::exp(-(db * (double)(2 * m))));
   }
   job->M = M;
+  job->fused_ok[0] = fused_plan(g, false, job->plan[0]);
+  job->fused_ok[1] = fused_plan(g, true, job->plan[1]);
 
   const size_t maps = sizeof(int32_t) * (size_t)samples * 2 * replicas;
   job->spins = job->dalloc(job->spin_bytes());
@@ -333,12 +337,27 @@ PT_API int pt_measure(pt_job* job) {
 PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   if (int rc = check_job(job)) return rc;
   if (n < 0) return fail(PT_EINVAL, "n must be >= 0");
-  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE)) return fail(PT_EINVAL, "unknown flags");
-  // Within one step every counter is read by exactly one kernel, so a single
-  // advance per step keeps the numbering of the separate entry points.
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
+    return fail(PT_EINVAL, "unknown flags");
   const Geo& g = job->g;
   hipStream_t st = job->stream;
   const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  if (!(flags & PT_MCS_PLAIN) && job->fused_ok[hou ? 1 : 0]) {
+    const int chunk = 500;
+    for (int done = 0; done < n; done += chunk) {
+      const int m = (n - done) < chunk ? (n - done) : chunk;
+      PT_HIP(job, launch_mcs_fused(g, job->plan[hou ? 1 : 0], job->spins, job->jw, job->E, job->sot,
+                                   job->tos, job->thr, job->thrpt, job->M, job->mom, job->ctr, m,
+                                   hou, meas, st));
+      PT_HIP(job, launch_advance(job->ctr,
+                                 CounterStep{(uint32_t)m, (uint32_t)m, hou ? (uint32_t)m : 0u,
+                                             meas ? (uint32_t)m : 0u},
+                                 st));
+    }
+    return PT_OK;
+  }
+  // Within one step every counter is read by exactly one kernel, so a single
+  // advance per step keeps the numbering of the separate entry points.
   for (int i = 0; i < n; ++i) {
     PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, st));
     if (hou) PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));

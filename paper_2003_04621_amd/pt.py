@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libptsg.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
 PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
-PT_MCS_HOUDAYER, PT_MCS_MEASURE = 1, 2
+PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN = 1, 2, 4
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE"}
 
@@ -201,8 +201,10 @@ def pt_measure(job: Job) -> None:
     _check(lib().pt_measure(job.h))
 
 
-def pt_mcs(job: Job, n: int, houdayer: bool = False, measure: bool = False) -> None:
-    flags = (PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
+def pt_mcs(job: Job, n: int, houdayer: bool = False, measure: bool = False,
+           plain: bool = False) -> None:
+    flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
+             | (PT_MCS_PLAIN if plain else 0))
     _check(lib().pt_mcs(job.h, int(n), flags))
 
 

@@ -212,3 +212,22 @@ def test_full_size_2d_l64_houdayer_sampled(pt):
     assert (pt.pt_get_energies(job)[picks] == ref.energies()).all()
     for a, b in zip(pt.pt_get_maps(job), ref.maps()):
         assert (a[picks] == b).all()
+
+
+@pytest.mark.parametrize("d,L,S,NT,layout,hou,meas", [
+    (3, 8, 3, 5, 0, False, True), (3, 16, 2, 6, 1, True, True), (2, 64, 2, 5, 0, True, True),
+    (2, 6, 3, 3, 1, True, False), (3, 12, 2, 4, 0, False, False), (2, 16, 4, 7, 0, True, True),
+])
+def test_fused_steps_equal_plain_and_oracle(pt, d, L, S, NT, layout, hou, meas):
+    say(f"fused case d={d} L={L} S={S} NT={NT} layout={layout} hou={hou} meas={meas}")
+    J = W.couplings_pm_j(S, L, d, 300 + L)
+    betas = W.geometric_betas(0.3, 2.0, NT)
+    fused = pt.pt_init(S, NT, L, d, J, betas, 77, layout=layout)
+    plain = pt.pt_init(S, NT, L, d, J, betas, 77, layout=layout)
+    ref = oracle.OracleJob(S, NT, L, d, J, betas, 77)
+    for n in (1, 4, 7):
+        pt.pt_mcs(fused, n, houdayer=hou, measure=meas)
+        pt.pt_mcs(plain, n, houdayer=hou, measure=meas, plain=True)
+        ref.mcs(n, houdayer=hou, measure=meas)
+        compare(pt, fused, ref, f"fused after {n}")
+        compare(pt, plain, ref, f"plain after {n}")
