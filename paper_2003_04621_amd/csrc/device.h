@@ -2,16 +2,25 @@
 // Philox4x32-10, lattice geometry, the colour-split bit layout held in LDS,
 // and the job's device counters.
 //
-// Bit layout ("row words").  A row is the set of L sites with fixed (x1, x2);
-// R = x1 + L*x2 is its index, NR = L^(dim-1) rows per lattice.  For colour
-// c in {0,1} of the checkerboard, the row word W[c][R] holds in bit b the spin
-// of the site x0 = 2b + p(c,R), p(c,R) = (c + x1 + x2) & 1; bit set <=> s = -1.
-// H = L/2 bits are used.  Because the checkerboard is bipartite for even L,
-// every neighbour of a colour-c site is a colour-(1-c) site, and the six
-// neighbour words of W[c][R] are:
-//   +x0: rotr(W[1-c][R], p)        -x0: rotr(W[1-c][R], H-1+p)
-//   +-x1: W[1-c][R +- e_x1]        +-x2: W[1-c][R +- e_x2]
-// (rotations within H bits), so one word operation serves H sites.
+// Bit layout.  A row is the set of L sites with fixed (x1, x2); R = x1 + L*x2
+// is its index, NR = L^(dim-1) rows per lattice.  For colour c of the
+// checkerboard, the H = L/2 sites of colour c in row R (x0 = 2b + p(c,R),
+// b < H, p(c,R) = (c + x1 + x2) & 1) form an H-bit "row field"; bit set <=>
+// s = -1.  P row fields of the same lattice and colour share one 32-bit word:
+// the slowest coordinate xs (x2 in 3D, x1 in 2D) is cut into P blocks of
+// B = L/P values, xs = f*B + xs', and field f (bits f*H .. f*H+H-1) of word
+// w = x1 + L*xs' (3D) or w = xs' (2D) holds the row with that xs.  B is even,
+// so p(c,R) is the same for every field of a word.  NW = NR/P words per
+// lattice and colour.
+//
+// Because the checkerboard is bipartite for even L, every neighbour of a
+// colour-c site is a colour-(1-c) site, and the 2d neighbour words of a
+// colour-c word w, with O = W[1-c]:
+//   +x0: per field rotr(O[w], p)       -x0: per field rotr(O[w], H-1+p)
+//   +-x1 (3D): O[w +- e_x1]
+//   +-xs: O[w +- e_xs'] inside a block; across a block boundary the word at
+//         the other end of the block with its fields rotated by one field.
+// One word operation therefore serves P*H sites.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,21 +41,52 @@ struct Ctr4 {
   uint32_t x, y, z, w;
 };
 
+// Three-input bitwise function with truth table TT (gfx950 v_bitop3_b32):
+// result bit = TT bit number (a_bit * 4 + b_bit * 2 + c_bit).
+template <unsigned TT>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:%4" : "=v"(r) : "v"(a), "v"(b), "v"(c), "i"(TT));
+  return r;
+}
+// The same with a wave-uniform third operand.
+template <unsigned TT>
+__device__ __forceinline__ uint32_t bop3s(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:%4" : "=v"(r) : "v"(a), "v"(b), "s"(c), "i"(TT));
+  return r;
+}
+constexpr unsigned kXor3 = 0x96;   // a ^ b ^ c
+constexpr unsigned kMaj3 = 0xE8;   // majority(a, b, c)
+constexpr unsigned kAndOr = 0xEA;  // (a & b) | c
+
 __device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
     Ctr4 n;
-    n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    n.x = bop3s<kXor3>((uint32_t)(p1 >> 32), c.y, k0);
     n.y = (uint32_t)p1;
-    n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    n.z = bop3s<kXor3>((uint32_t)(p0 >> 32), c.w, k1);
     n.w = (uint32_t)p0;
     c = n;
     k0 += kWeyl0;
     k1 += kWeyl1;
   }
   return c;
+}
+
+// (mask << 1) | (r < t): the borrow of r - t shifted into the mask, two VALU
+// instructions (t wave-uniform).
+__device__ __forceinline__ uint32_t shift_in_less(uint32_t mask, uint32_t r, uint32_t t) {
+  uint32_t out, tmp;
+  asm("v_subrev_co_u32_e32 %1, vcc, %3, %2\n\t"
+      "v_addc_co_u32_e32 %0, vcc, %4, %4, vcc"
+      : "=v"(out), "=&v"(tmp)
+      : "v"(r), "s"(t), "v"(mask)
+      : "vcc");
+  return out;
 }
 
 // Counter tags (top four bits of the fourth counter word).
@@ -58,9 +98,12 @@ constexpr uint32_t kTagInit = 2u, kTagMetro = 3u, kTagPT = 4u, kTagHou = 5u;
 enum : int { kLayoutInt8 = 0, kLayoutPacked = 1 };
 
 struct Geo {
-  int L, d, N, NR, H, G;  // G = ceil(L/8): Philox calls per row word
+  int L, d, N, NR, H, G;  // G = ceil(L/8): Philox calls per row field
+  int P, B, NW;           // fields per word, block length, words per colour
   uint32_t magicL;        // ceil(2^32 / L): x / L == umulhi(x, magicL) for x < 2^20
   uint32_t maskH;         // low H bits
+  uint32_t maskW;         // low P*H bits
+  uint32_t LB, HB;        // lowest / highest bit of every field
   int S, NT, nslot;
   int layout;
   uint32_t key0, key1;
@@ -75,6 +118,13 @@ struct DevCounters {
   uint32_t pad[4];
 };
 
+// Counters are read by the kernels at their start and advanced afterwards by
+// k_advance, a one-thread kernel enqueued behind them on the same stream (a
+// per-block atomic on one address serialises tens of thousands of blocks).
+struct CounterStep {
+  uint32_t dt, du, dv, dm;
+};
+
 __device__ __forceinline__ uint32_t divL(const Geo& g, uint32_t x) {
   return __umulhi(x, g.magicL);
 }
@@ -83,52 +133,137 @@ __device__ __forceinline__ uint32_t load_counter(const uint32_t* p) {
   return __atomic_load_n(p, __ATOMIC_RELAXED);
 }
 
-// Counters are read by the kernels at their start and advanced afterwards by
-// k_advance, a one-thread kernel enqueued behind them on the same stream (a
-// per-block atomic on one address serialises tens of thousands of blocks).
-struct CounterStep {
-  uint32_t dt, du, dv, dm;
+// ---------------------------------------------------------------------------
+// Word geometry.
+// ---------------------------------------------------------------------------
+struct WordNb {
+  int x1, xs;     // 3D: x1 and x2' (block-local x2); 2D: xs = x1' (x1 unused)
+  int par;        // p(c, word) = (c + par) & 1
+  int w1p, w1m;   // 3D: words at x1 +- 1
+  int wsp, wsm;   // words at xs +- 1 (other end of the block when crossing)
+  bool crp, crm;  // the xs neighbour crosses a block boundary (rotate fields)
 };
 
-// Row geometry: coordinates and the four neighbour rows.
-struct RowNb {
-  int x1, x2, p0;        // p0 = (x1 + x2) & 1: colour of even x0
-  int r1p, r1m, r2p, r2m;
-};
-
-__device__ __forceinline__ RowNb row_nb(const Geo& g, int R) {
-  RowNb q;
+__device__ __forceinline__ WordNb word_nb(const Geo& g, int w) {
+  WordNb q;
   if (g.d == 3) {
-    q.x2 = (int)divL(g, (uint32_t)R);
-    q.x1 = R - q.x2 * g.L;
+    q.xs = (int)divL(g, (uint32_t)w);
+    q.x1 = w - q.xs * g.L;
+    q.par = (q.x1 + q.xs) & 1;
+    q.w1p = (q.x1 == g.L - 1) ? w - (g.L - 1) : w + 1;
+    q.w1m = (q.x1 == 0) ? w + (g.L - 1) : w - 1;
+    q.crp = q.xs == g.B - 1;
+    q.crm = q.xs == 0;
+    q.wsp = q.crp ? w - (g.B - 1) * g.L : w + g.L;
+    q.wsm = q.crm ? w + (g.B - 1) * g.L : w - g.L;
   } else {
-    q.x2 = 0;
-    q.x1 = R;
+    q.xs = w;
+    q.x1 = 0;
+    q.par = w & 1;
+    q.w1p = q.w1m = w;
+    q.crp = q.xs == g.B - 1;
+    q.crm = q.xs == 0;
+    q.wsp = q.crp ? w - (g.B - 1) : w + 1;
+    q.wsm = q.crm ? w + (g.B - 1) : w - 1;
   }
-  q.p0 = (q.x1 + q.x2) & 1;
-  q.r1p = (q.x1 == g.L - 1) ? R - (g.L - 1) : R + 1;
-  q.r1m = (q.x1 == 0) ? R + (g.L - 1) : R - 1;
-  q.r2p = (q.x2 == g.L - 1) ? R - (g.L - 1) * g.L : R + g.L;
-  q.r2m = (q.x2 == 0) ? R + (g.L - 1) * g.L : R - g.L;
   return q;
 }
 
-// +x0 / -x0 neighbour words of a colour-c word whose opposite-colour word in
-// the same row is O; p = p(c, R).
+// Row index of field f of word w.
+__device__ __forceinline__ int word_row(const Geo& g, const WordNb& q, int f) {
+  const int xs = f * g.B + q.xs;
+  return g.d == 3 ? q.x1 + g.L * xs : xs;
+}
+
+// Word and field holding row R (the inverse of word_row).
+__device__ __forceinline__ void row_word(const Geo& g, int R, int& w, int& f) {
+  if (g.d == 3) {
+    const int x2 = (int)divL(g, (uint32_t)R), x1 = R - x2 * g.L;
+    f = x2 / g.B;
+    w = x1 + g.L * (x2 - f * g.B);
+  } else {
+    f = R / g.B;
+    w = R - f * g.B;
+  }
+}
+
+// Colour of the even-x0 sites of row R: (x1 + x2) & 1.
+__device__ __forceinline__ int row_parity(const Geo& g, int R) {
+  if (g.d == 3) {
+    const int x2 = (int)divL(g, (uint32_t)R);
+    return (R - x2 * g.L + x2) & 1;
+  }
+  return R & 1;
+}
+
+// The q = -1 site with rank m (counted in increasing site order) inside row
+// R, given the two colour words of R's word w and its field f.  Returns the
+// colour c and the bit b = x0 >> 1 of that site within field f.
+__device__ __forceinline__ void select_in_row(const Geo& g, int R, uint32_t Q0, uint32_t Q1, int f,
+                                              uint32_t m, int& c_out, int& b_out) {
+  const int p0 = row_parity(g, R);
+  const uint32_t q0 = (Q0 >> (f * g.H)) & g.maskH, q1 = (Q1 >> (f * g.H)) & g.maskH;
+  c_out = -1;
+  b_out = 0;
+  for (int x0 = 0; x0 < g.L; ++x0) {
+    const int c = (x0 & 1) ^ p0;
+    if ((((c ? q1 : q0) >> (x0 >> 1)) & 1u) == 0) continue;
+    if (m == 0) {
+      c_out = c;
+      b_out = x0 >> 1;
+      return;
+    }
+    --m;
+  }
+}
+
+// Field rotations of a P*H-bit word: result field f = source field f+1
+// (rot_fields_down) or f-1 (rot_fields_up), cyclically.
+__device__ __forceinline__ uint32_t rot_fields_down(const Geo& g, uint32_t X) {
+  const uint64_t XX = (uint64_t)X | ((uint64_t)X << (g.P * g.H));
+  return (uint32_t)(XX >> g.H) & g.maskW;
+}
+__device__ __forceinline__ uint32_t rot_fields_up(const Geo& g, uint32_t X) {
+  const uint64_t XX = (uint64_t)X | ((uint64_t)X << (g.P * g.H));
+  return (uint32_t)(XX >> ((g.P - 1) * g.H)) & g.maskW;
+}
+
+// +x0 / -x0 neighbour words of a colour-c word whose opposite-colour word is
+// O; p = p(c, word).  Each field rotates by one bit within itself.
 __device__ __forceinline__ void x0_neighbours(const Geo& g, uint32_t O, int p,
                                               uint32_t& nplus, uint32_t& nminus) {
-  const uint64_t OO = (uint64_t)O | ((uint64_t)O << g.H);
-  nplus = (uint32_t)(OO >> p) & g.maskH;
-  nminus = (uint32_t)(OO >> (g.H - 1 + p)) & g.maskH;
+  const uint32_t rr = ((O >> 1) & ~g.HB) | ((O & g.LB) << (g.H - 1));  // bit b <- b+1
+  const uint32_t rl = ((O << 1) & ~g.LB & g.maskW) | ((O & g.HB) >> (g.H - 1));  // bit b <- b-1
+  nplus = p ? rr : O;
+  nminus = p ? O : rl;
+}
+
+// All 2d neighbour words of the colour-c word w; Wo = the colour-(1-c) words.
+template <int D>
+__device__ __forceinline__ void neighbour_words(const Geo& g, const uint32_t* Wo, int w,
+                                                const WordNb& q, int p, uint32_t* n) {
+  x0_neighbours(g, Wo[w], p, n[0], n[1]);
+  if (D == 3) {
+    n[2] = Wo[q.w1p];
+    n[3] = Wo[q.w1m];
+    const uint32_t sp = Wo[q.wsp], sm = Wo[q.wsm];
+    n[4] = q.crp ? rot_fields_down(g, sp) : sp;
+    n[5] = q.crm ? rot_fields_up(g, sm) : sm;
+  } else {
+    const uint32_t sp = Wo[q.wsp], sm = Wo[q.wsm];
+    n[2] = q.crp ? rot_fields_down(g, sp) : sp;
+    n[3] = q.crm ? rot_fields_up(g, sm) : sm;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Lattice <-> LDS row words.  W points at 2*NR words: W[c*NR + R].
-// int8 layout: spins8[lat*N + i], +1 / -1.  Packed layout: spins32[lat*2*NR +
-// c*NR + R] exactly as in LDS.
+// Lattice <-> LDS words.  W points at 2*NW words: W[c*NW + w].
+// int8 layout: spins8[lat*N + i], +1 / -1.  Packed layout: spins32[lat*2*NW +
+// c*NW + w] exactly as in LDS.
 // ---------------------------------------------------------------------------
+// Row R as two H-bit fields: bits of the even-x0 sites and of the odd-x0 sites.
 __device__ __forceinline__ void row_from_int8(const Geo& g, const int8_t* lat, int R,
-                                              int p0, uint32_t& Weven, uint32_t& Wodd) {
+                                              uint32_t& Weven, uint32_t& Wodd) {
   uint32_t e = 0, o = 0;
   const int8_t* row = lat + (size_t)R * g.L;
   if ((g.L & 3) == 0) {
@@ -147,7 +282,6 @@ __device__ __forceinline__ void row_from_int8(const Geo& g, const int8_t* lat, i
         e |= bit << (x0 >> 1);
     }
   }
-  (void)p0;
   Weven = e;
   Wodd = o;
 }
@@ -172,40 +306,56 @@ __device__ __forceinline__ void row_to_int8(const Geo& g, int8_t* lat, int R, ui
   }
 }
 
+// Both colour words of word w of an int8 lattice.  The even-x0 sites of a
+// row have colour (x1 + x2) & 1 = par.
+__device__ __forceinline__ void word_from_int8(const Geo& g, const int8_t* lat, int w,
+                                               uint32_t& W0, uint32_t& W1) {
+  const WordNb q = word_nb(g, w);
+  uint32_t e = 0, o = 0;
+  for (int f = 0; f < g.P; ++f) {
+    uint32_t fe, fo;
+    row_from_int8(g, lat, word_row(g, q, f), fe, fo);
+    e |= fe << (f * g.H);
+    o |= fo << (f * g.H);
+  }
+  W0 = q.par ? o : e;
+  W1 = q.par ? e : o;
+}
+
+__device__ __forceinline__ void word_to_int8(const Geo& g, int8_t* lat, int w, uint32_t W0,
+                                             uint32_t W1) {
+  const WordNb q = word_nb(g, w);
+  const uint32_t e = q.par ? W1 : W0, o = q.par ? W0 : W1;
+  for (int f = 0; f < g.P; ++f)
+    row_to_int8(g, lat, word_row(g, q, f), (e >> (f * g.H)) & g.maskH, (o >> (f * g.H)) & g.maskH);
+}
+
 // Cooperative load of lattice `lat` into W by threads t = 0..T-1.
 __device__ __forceinline__ void load_lattice(const Geo& g, const void* spins, size_t lat,
                                              uint32_t* W, int t, int T) {
   if (g.layout == kLayoutPacked) {
-    const uint32_t* src = static_cast<const uint32_t*>(spins) + lat * 2 * (size_t)g.NR;
-    for (int w = t; w < 2 * g.NR; w += T) W[w] = src[w];
+    const uint32_t* src = static_cast<const uint32_t*>(spins) + lat * 2 * (size_t)g.NW;
+    for (int i = t; i < 2 * g.NW; i += T) W[i] = src[i];
   } else {
     const int8_t* src = static_cast<const int8_t*>(spins) + lat * (size_t)g.N;
-    for (int R = t; R < g.NR; R += T) {
-      const RowNb q = row_nb(g, R);
-      uint32_t e, o;
-      row_from_int8(g, src, R, q.p0, e, o);
-      // even x0 has colour p0
-      W[q.p0 * g.NR + R] = e;
-      W[(1 - q.p0) * g.NR + R] = o;
-    }
+    for (int w = t; w < g.NW; w += T) word_from_int8(g, src, w, W[w], W[g.NW + w]);
   }
 }
 
-// Cooperative store of rows R (all rows if `only_changed` is null; otherwise
-// rows whose flag word only_changed[R] or only_changed[NR + R] is non-zero).
+// Cooperative store (all words if `only_changed` is null; otherwise words w
+// whose flag only_changed[w] or only_changed[NW + w] is non-zero).
 __device__ __forceinline__ void store_lattice(const Geo& g, void* spins, size_t lat,
                                               const uint32_t* W, int t, int T,
                                               const uint32_t* only_changed = nullptr) {
   if (g.layout == kLayoutPacked) {
-    uint32_t* dst = static_cast<uint32_t*>(spins) + lat * 2 * (size_t)g.NR;
-    for (int w = t; w < 2 * g.NR; w += T)
-      if (!only_changed || only_changed[w]) dst[w] = W[w];
+    uint32_t* dst = static_cast<uint32_t*>(spins) + lat * 2 * (size_t)g.NW;
+    for (int i = t; i < 2 * g.NW; i += T)
+      if (!only_changed || only_changed[i]) dst[i] = W[i];
   } else {
     int8_t* dst = static_cast<int8_t*>(spins) + lat * (size_t)g.N;
-    for (int R = t; R < g.NR; R += T) {
-      if (only_changed && !(only_changed[R] | only_changed[g.NR + R])) continue;
-      const RowNb q = row_nb(g, R);
-      row_to_int8(g, dst, R, W[q.p0 * g.NR + R], W[(1 - q.p0) * g.NR + R]);
+    for (int w = t; w < g.NW; w += T) {
+      if (only_changed && !(only_changed[w] | only_changed[g.NW + w])) continue;
+      word_to_int8(g, dst, w, W[w], W[g.NW + w]);
     }
   }
 }

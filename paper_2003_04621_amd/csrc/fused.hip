@@ -9,6 +9,7 @@
 // k with the updated map, Houdayer seeds chosen in increasing site order.
 #include "device.h"
 #include "kernels.h"
+#include "houdayer_ops.h"
 #include "rowops.h"
 
 namespace ptsg {
@@ -26,7 +27,7 @@ struct FusedArgs {
   int64_t* mom;
   const DevCounters* ctr;
   int nmcs, hou, meas;
-  uint32_t magicNR;  // item / NR
+  uint32_t magicNW;  // item / NW
   FusedLayout lay;
 };
 
@@ -97,7 +98,7 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* lds) {
   const Geo& g = A.g;
-  const int NT = g.NT, NR = g.NR, tid = threadIdx.x, T = blockDim.x;
+  const int NT = g.NT, NW = g.NW, tid = threadIdx.x, T = blockDim.x;
   const uint32_t* W = lds + A.lay.W;
   const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
   const int32_t* sotl = reinterpret_cast<const int32_t*>(lds + A.lay.sot);
@@ -107,10 +108,10 @@ __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* l
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63, nwave = T >> 6;
   for (int k = wave; k < NT; k += nwave) {
-    const uint32_t* Wa = W + (size_t)sotl[k] * 2 * NR;
-    const uint32_t* Wb = W + (size_t)(NT + sotl[NT + k]) * 2 * NR;
+    const uint32_t* Wa = W + (size_t)sotl[k] * 2 * NW;
+    const uint32_t* Wb = W + (size_t)(NT + sotl[NT + k]) * 2 * NW;
     int neg = 0;
-    for (int w = lane; w < 2 * NR; w += 64) neg += __popc(Wa[w] ^ Wb[w]);
+    for (int w = lane; w < 2 * NW; w += 64) neg += __popc(Wa[w] ^ Wb[w]);
     if (neg) atomicAdd(&qneg[k], neg);
   }
   __syncthreads();
@@ -142,7 +143,7 @@ template <int D>
 __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* lds, int s,
                                                   uint32_t v) {
   const Geo& g = A.g;
-  const int NT = g.NT, NR = g.NR, tid = threadIdx.x, T = blockDim.x, PC = A.lay.PC;
+  const int NT = g.NT, NW = g.NW, tid = threadIdx.x, T = blockDim.x, PC = A.lay.PC;
   uint32_t* W = lds + A.lay.W;
   const uint32_t* Jl = lds + A.lay.J;  // colour 0 block first
   int32_t* El = reinterpret_cast<int32_t*>(lds + A.lay.E);
@@ -151,7 +152,7 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
   uint32_t* Cs = lds + A.lay.Cs;
   uint32_t* hcnt = lds + A.lay.hcnt;
   int32_t* hdel = reinterpret_cast<int32_t*>(lds + A.lay.hdelta);
-  const int W2 = 2 * NR;
+  const int W2 = 2 * NW;
   for (int p0 = 0; p0 < NT; p0 += PC) {
     const int np = min(PC, NT - p0);
     if (tid < np) {
@@ -164,10 +165,10 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
       const uint32_t* Wa = W + (size_t)sotl[k] * W2;
       const uint32_t* Wb = W + (size_t)(NT + sotl[NT + k]) * W2;
       int cnt = 0;
-      for (int w = tid; w < W2; w += T) {
-        const uint32_t q = Wa[w] ^ Wb[w];
-        Qs[pl * W2 + w] = q;
-        Cs[pl * W2 + w] = 0;
+      for (int i = tid; i < W2; i += T) {
+        const uint32_t q = Wa[i] ^ Wb[i];
+        Qs[pl * W2 + i] = q;
+        Cs[pl * W2 + i] = 0;
         cnt += __popc(q);
       }
       if (cnt) atomicAdd(&hcnt[pl], (uint32_t)cnt);
@@ -180,54 +181,20 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
       if (n > 0) {
         const Ctr4 r = philox10(Ctr4{(uint32_t)k, v, 0u, (kTagHou << 28) | (uint32_t)s}, g.key0, g.key1);
         const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
-        uint32_t m = (uint32_t)__umul64hi(r64, (uint64_t)n);
-        const uint32_t* Q = Qs + pl * W2;
-        for (int R = 0; R < NR; ++R) {
-          const uint32_t cr = __popc(Q[R]) + __popc(Q[NR + R]);
-          if (m >= cr) {
-            m -= cr;
-            continue;
-          }
-          const RowNb q = row_nb(g, R);
-          for (int x0 = 0; x0 < g.L; ++x0) {
-            const int c = (x0 & 1) ^ q.p0;
-            if ((Q[c * NR + R] >> (x0 >> 1)) & 1u) {
-              if (m == 0) {
-                Cs[pl * W2 + c * NR + R] = 1u << (x0 >> 1);
-                break;
-              }
-              --m;
-            }
-          }
-          break;
-        }
+        seed_in_rows(g, Qs + pl * W2, Cs + pl * W2, 0, g.NR, (uint32_t)__umul64hi(r64, (uint64_t)n));
       }
     }
     __syncthreads();
     // flood fill, all pairs of the chunk together
-    const int items = np * NR;
+    const int items = np * NW;
     int any;
     do {
       int changed = 0;
       for (int c = 0; c < 2; ++c) {
         for (int it = tid; it < items; it += T) {
-          const int pl = (int)__umulhi((uint32_t)it, A.magicNR), R = it - pl * NR;
+          const int pl = (int)__umulhi((uint32_t)it, A.magicNW), w = it - pl * NW;
           if (hcnt[pl] == 0) continue;
-          const uint32_t qw = Qs[pl * W2 + c * NR + R];
-          if (!qw) continue;
-          const uint32_t* X = Cs + pl * W2 + (1 - c) * NR;
-          const RowNb q = row_nb(g, R);
-          const int p = (c + q.x1 + q.x2) & 1;
-          uint32_t n0, n1;
-          x0_neighbours(g, X[R], p, n0, n1);
-          uint32_t nb = n0 | n1 | X[q.r1p] | X[q.r1m];
-          if (D == 3) nb |= X[q.r2p] | X[q.r2m];
-          uint32_t* Cw = Cs + pl * W2 + c * NR + R;
-          const uint32_t old = *Cw, nw = old | (qw & nb);
-          if (nw != old) {
-            *Cw = nw;
-            changed = 1;
-          }
+          if (grow_word<D>(g, Cs + pl * W2, Qs + pl * W2, c, w)) changed = 1;
         }
         if (c == 0) __syncthreads();
       }
@@ -235,41 +202,10 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
     } while (any);
     // energy change of replica a: bonds leaving the cluster, on colour-0 words
     for (int it = tid; it < items; it += T) {
-      const int pl = (int)__umulhi((uint32_t)it, A.magicNR), R = it - pl * NR;
+      const int pl = (int)__umulhi((uint32_t)it, A.magicNW), w = it - pl * NW;
       if (hcnt[pl] == 0) continue;
       const int k = p0 + pl;
-      const uint32_t* Aw = W + (size_t)sotl[k] * W2;
-      const uint32_t* Cw = Cs + pl * W2;
-      const RowNb q = row_nb(g, R);
-      const int p = q.p0;
-      const uint32_t C0 = Cw[R], A0 = Aw[R];
-      const uint32_t* C1 = Cw + NR;
-      const uint32_t* A1 = Aw + NR;
-      uint32_t cp, cm, ap, am;
-      x0_neighbours(g, C1[R], p, cp, cm);
-      x0_neighbours(g, A1[R], p, ap, am);
-      uint32_t X[2 * D], U[2 * D];
-      X[0] = C0 ^ cp;
-      U[0] = A0 ^ ap ^ Jl[0 * NR + R];
-      X[1] = C0 ^ cm;
-      U[1] = A0 ^ am ^ Jl[1 * NR + R];
-      X[2] = C0 ^ C1[q.r1p];
-      U[2] = A0 ^ A1[q.r1p] ^ Jl[2 * NR + R];
-      X[3] = C0 ^ C1[q.r1m];
-      U[3] = A0 ^ A1[q.r1m] ^ Jl[3 * NR + R];
-      if (D == 3) {
-        X[4] = C0 ^ C1[q.r2p];
-        U[4] = A0 ^ A1[q.r2p] ^ Jl[4 * NR + R];
-        X[5] = C0 ^ C1[q.r2m];
-        U[5] = A0 ^ A1[q.r2m] ^ Jl[5 * NR + R];
-      }
-      int cross = 0, cross_u = 0;
-#pragma unroll
-      for (int dd = 0; dd < 2 * D; ++dd) {
-        cross += __popc(X[dd]);
-        cross_u += __popc(X[dd] & U[dd]);
-      }
-      const int dl = 2 * (cross - 2 * cross_u);
+      const int dl = cluster_delta_word<D>(g, Cs + pl * W2, W + (size_t)sotl[k] * W2, Jl, w);
       if (dl) atomicAdd(&hdel[pl], dl);
     }
     __syncthreads();
@@ -279,11 +215,11 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
       const int k = p0 + pl;
       uint32_t* Wa = W + (size_t)sotl[k] * W2;
       uint32_t* Wb = W + (size_t)(NT + sotl[NT + k]) * W2;
-      for (int w = tid; w < W2; w += T) {
-        const uint32_t cw = Cs[pl * W2 + w];
+      for (int i = tid; i < W2; i += T) {
+        const uint32_t cw = Cs[pl * W2 + i];
         if (cw) {
-          Wa[w] ^= cw;
-          Wb[w] ^= cw;
+          Wa[i] ^= cw;
+          Wb[i] ^= cw;
         }
       }
     }
@@ -302,7 +238,7 @@ __global__ void __launch_bounds__(1024) k_mcs(FusedArgs A) {
   extern __shared__ uint32_t lds[];
   const Geo& g = A.g;
   const int T = blockDim.x, tid = threadIdx.x, s = blockIdx.x;
-  const int NR = g.NR, NT = g.NT, nslot = g.nslot, W2 = 2 * NR;
+  const int NW = g.NW, NT = g.NT, nslot = g.nslot, W2 = 2 * NW;
   uint32_t* W = lds + A.lay.W;
   uint32_t* Jl = lds + A.lay.J;
   int32_t* El = reinterpret_cast<int32_t*>(lds + A.lay.E);
@@ -313,23 +249,19 @@ __global__ void __launch_bounds__(1024) k_mcs(FusedArgs A) {
   const size_t lat0 = (size_t)s * nslot;
 
   // ---- load the sample
-  const int items = nslot * NR;
+  const int items = nslot * NW;
   if (g.layout == kLayoutPacked) {
     const uint32_t* src = static_cast<const uint32_t*>(A.spins) + lat0 * W2;
-    for (int w = tid; w < nslot * W2; w += T) W[w] = src[w];
+    for (int i = tid; i < nslot * W2; i += T) W[i] = src[i];
   } else {
     const int8_t* src = static_cast<const int8_t*>(A.spins) + lat0 * g.N;
     for (int it = tid; it < items; it += T) {
-      const int slot = (int)__umulhi((uint32_t)it, A.magicNR), R = it - slot * NR;
-      const RowNb q = row_nb(g, R);
-      uint32_t e, o;
-      row_from_int8(g, src + (size_t)slot * g.N, R, q.p0, e, o);
-      W[slot * W2 + q.p0 * NR + R] = e;
-      W[slot * W2 + (1 - q.p0) * NR + R] = o;
+      const int slot = (int)__umulhi((uint32_t)it, A.magicNW), w = it - slot * NW;
+      word_from_int8(g, src + (size_t)slot * g.N, w, W[slot * W2 + w], W[slot * W2 + NW + w]);
     }
   }
-  const uint32_t* jws = A.jw + (size_t)s * 2 * 2 * D * NR;
-  for (int w = tid; w < 2 * 2 * D * NR; w += T) Jl[w] = jws[w];
+  const uint32_t* jws = A.jw + (size_t)s * 2 * 2 * D * NW;
+  for (int i = tid; i < 2 * 2 * D * NW; i += T) Jl[i] = jws[i];
   for (int i = tid; i < nslot; i += T) El[i] = A.E[lat0 + i];
   for (int i = tid; i < 2 * NT; i += T) {
     sotl[i] = A.sot[(size_t)s * 2 * NT + i];
@@ -344,15 +276,13 @@ __global__ void __launch_bounds__(1024) k_mcs(FusedArgs A) {
   for (int step = 0; step < A.nmcs; ++step) {
     const uint32_t t = t0 + (uint32_t)step;
     for (int c = 0; c < 2; ++c) {
-      const uint32_t* Jc = Jl + c * 2 * D * NR;
+      const uint32_t* Jc = Jl + c * 2 * D * NW;
       for (int it = tid; it < items; it += T) {
-        const int slot = (int)__umulhi((uint32_t)it, A.magicNR), R = it - slot * NR;
-        const int set = slot >= NT ? 1 : 0;
+        const int slot = (int)__umulhi((uint32_t)it, A.magicNW), w = it - slot * NW;
         const int k = tosl[slot];
-        (void)set;
         int dE = 0;
-        sweep_row<D>(g, W + slot * W2, Jc, c, R, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
-                     thrl[k * 4 + 2], dE);
+        sweep_word<D>(g, W + slot * W2, Jc, c, w, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
+                      thrl[k * 4 + 2], dE);
         if (dE) atomicAdd(&El[slot], dE);
       }
       __syncthreads();
@@ -365,14 +295,12 @@ __global__ void __launch_bounds__(1024) k_mcs(FusedArgs A) {
   // ---- store the sample
   if (g.layout == kLayoutPacked) {
     uint32_t* dst = static_cast<uint32_t*>(A.spins) + lat0 * W2;
-    for (int w = tid; w < nslot * W2; w += T) dst[w] = W[w];
+    for (int i = tid; i < nslot * W2; i += T) dst[i] = W[i];
   } else {
     int8_t* dst = static_cast<int8_t*>(A.spins) + lat0 * g.N;
     for (int it = tid; it < items; it += T) {
-      const int slot = (int)__umulhi((uint32_t)it, A.magicNR), R = it - slot * NR;
-      const RowNb q = row_nb(g, R);
-      row_to_int8(g, dst + (size_t)slot * g.N, R, W[slot * W2 + q.p0 * NR + R],
-                  W[slot * W2 + (1 - q.p0) * NR + R]);
+      const int slot = (int)__umulhi((uint32_t)it, A.magicNW), w = it - slot * NW;
+      word_to_int8(g, dst + (size_t)slot * g.N, w, W[slot * W2 + w], W[slot * W2 + NW + w]);
     }
   }
   for (int i = tid; i < nslot; i += T) A.E[lat0 + i] = El[i];
@@ -394,9 +322,9 @@ bool fused_plan(const Geo& g, bool hou, FusedLayout& lay) {
     off += words;
     return (int)at;
   };
-  const size_t W2 = 2 * (size_t)g.NR;
+  const size_t W2 = 2 * (size_t)g.NW;
   lay.W = take((size_t)g.nslot * W2, 1);
-  lay.J = take(2 * 2 * (size_t)g.d * g.NR, 1);
+  lay.J = take(2 * 2 * (size_t)g.d * g.NW, 1);
   lay.E = take(g.nslot, 1);
   lay.sot = take(2 * g.NT, 1);
   lay.tos = take(2 * g.NT, 1);
@@ -442,7 +370,7 @@ hipError_t launch_mcs_fused(const Geo& g, const FusedLayout& lay, void* spins, c
   A.nmcs = nmcs;
   A.hou = hou ? 1 : 0;
   A.meas = meas ? 1 : 0;
-  A.magicNR = (uint32_t)((0x100000000ull + (uint64_t)g.NR - 1) / (uint64_t)g.NR);
+  A.magicNW = (uint32_t)((0x100000000ull + (uint64_t)g.NW - 1) / (uint64_t)g.NW);
   A.lay = lay;
   const size_t bytes = (size_t)lay.words * 4;
   const dim3 grid((unsigned)g.S), block(1024);

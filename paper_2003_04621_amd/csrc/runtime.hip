@@ -44,8 +44,8 @@ uint32_t threshold_u32(double p) {
 struct pt_job {
   Geo g{};
   hipStream_t stream = nullptr;
-  void* spins = nullptr;     // int8 [S][2NT][N] or u32 [S][2NT][2][NR]
-  uint32_t* jw = nullptr;    // [S][2][2d][NR]
+  void* spins = nullptr;     // int8 [S][2NT][N] or u32 [S][2NT][2][NW]
+  uint32_t* jw = nullptr;    // [S][2][2d][NW]
   int32_t* E = nullptr;      // [S][2NT]
   int32_t* sot = nullptr;    // [S][2][NT]
   int32_t* tos = nullptr;    // [S][2][NT]
@@ -64,7 +64,7 @@ struct pt_job {
 
   size_t spin_bytes() const {
     const size_t lat = (size_t)g.S * g.nslot;
-    return g.layout == kLayoutPacked ? lat * 2 * g.NR * sizeof(uint32_t) : lat * g.N;
+    return g.layout == kLayoutPacked ? lat * 2 * g.NW * sizeof(uint32_t) : lat * g.N;
   }
 
   void* dalloc(size_t bytes) {
@@ -109,21 +109,33 @@ int check_job(pt_job* job) {
   return PT_OK;
 }
 
+// Row of field f of word w (host copy of the device word geometry).
+int host_word_row(const Geo& g, int w, int f) {
+  if (g.d == 3) {
+    const int xs = w / g.L, x1 = w % g.L;
+    return x1 + g.L * (f * g.B + xs);
+  }
+  return f * g.B + w;
+}
+
+// int8 lattices <-> colour words (pt_get_spins / pt_set_spins, packed layout)
 void pack_host(const Geo& g, const int8_t* in, uint32_t* out) {
-  // int8 lattices -> colour-split row words (used by pt_set_spins, packed layout)
   const size_t nlat = (size_t)g.S * g.nslot;
   for (size_t lat = 0; lat < nlat; ++lat) {
     const int8_t* s = in + lat * g.N;
-    uint32_t* w = out + lat * 2 * g.NR;
-    for (int R = 0; R < g.NR; ++R) {
-      const int x1 = R % g.L, x2 = R / g.L;
-      uint32_t W[2] = {0, 0};
-      for (int x0 = 0; x0 < g.L; ++x0) {
-        const int c = (x0 + x1 + x2) & 1;
-        if (s[(size_t)R * g.L + x0] < 0) W[c] |= 1u << (x0 >> 1);
+    uint32_t* W = out + lat * 2 * g.NW;
+    for (int w = 0; w < g.NW; ++w) {
+      uint32_t c01[2] = {0, 0};
+      for (int f = 0; f < g.P; ++f) {
+        const int R = host_word_row(g, w, f);
+        const int x1 = R % g.L, x2 = R / g.L;
+        for (int x0 = 0; x0 < g.L; ++x0) {
+          const int c = (x0 + x1 + x2) & 1;
+          if (s[(size_t)R * g.L + x0] < 0) c01[c] |= 1u << (f * g.H + (x0 >> 1));
+        }
       }
-      w[R] = W[0];
-      w[g.NR + R] = W[1];
+      W[w] = c01[0];
+      W[g.NW + w] = c01[1];
     }
   }
 }
@@ -132,14 +144,17 @@ void unpack_host(const Geo& g, const uint32_t* in, int8_t* out) {
   const size_t nlat = (size_t)g.S * g.nslot;
   for (size_t lat = 0; lat < nlat; ++lat) {
     int8_t* s = out + lat * g.N;
-    const uint32_t* w = in + lat * 2 * g.NR;
-    for (int R = 0; R < g.NR; ++R) {
-      const int x1 = R % g.L, x2 = R / g.L;
-      for (int x0 = 0; x0 < g.L; ++x0) {
-        const int c = (x0 + x1 + x2) & 1;
-        s[(size_t)R * g.L + x0] = ((w[c * g.NR + R] >> (x0 >> 1)) & 1u) ? (int8_t)-1 : (int8_t)1;
+    const uint32_t* W = in + lat * 2 * g.NW;
+    for (int w = 0; w < g.NW; ++w)
+      for (int f = 0; f < g.P; ++f) {
+        const int R = host_word_row(g, w, f);
+        const int x1 = R % g.L, x2 = R / g.L;
+        for (int x0 = 0; x0 < g.L; ++x0) {
+          const int c = (x0 + x1 + x2) & 1;
+          const uint32_t bit = (W[c * g.NW + w] >> (f * g.H + (x0 >> 1))) & 1u;
+          s[(size_t)R * g.L + x0] = bit ? (int8_t)-1 : (int8_t)1;
+        }
       }
-    }
   }
 }
 
@@ -195,6 +210,19 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
   g.G = (L + 7) / 8;
   g.magicL = (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L);
   g.maskH = (g.H == 32) ? 0xFFFFFFFFu : ((1u << g.H) - 1u);
+  // fields per word: as many rows as fit, with an even block length L/P
+  g.P = 1;
+  for (int p = 32 / g.H; p >= 1; --p)
+    if (L % p == 0 && (L / p) % 2 == 0) {
+      g.P = p;
+      break;
+    }
+  g.B = L / g.P;
+  g.NW = g.NR / g.P;
+  g.maskW = (g.P * g.H == 32) ? 0xFFFFFFFFu : ((1u << (g.P * g.H)) - 1u);
+  g.LB = 0;
+  for (int f = 0; f < g.P; ++f) g.LB |= 1u << (f * g.H);
+  g.HB = g.LB << (g.H - 1);
   g.S = samples;
   g.NT = replicas;
   g.nslot = 2 * replicas;
@@ -231,7 +259,7 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
 
   const size_t maps = sizeof(int32_t) * (size_t)samples * 2 * replicas;
   job->spins = job->dalloc(job->spin_bytes());
-  job->jw = (uint32_t*)job->dalloc(sizeof(uint32_t) * (size_t)samples * 2 * 2 * dim * g.NR);
+  job->jw = (uint32_t*)job->dalloc(sizeof(uint32_t) * (size_t)samples * 2 * 2 * dim * g.NW);
   job->E = (int32_t*)job->dalloc(sizeof(int32_t) * (size_t)nlat);
   job->sot = (int32_t*)job->dalloc(maps);
   job->tos = (int32_t*)job->dalloc(maps);

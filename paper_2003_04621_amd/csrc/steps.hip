@@ -3,6 +3,7 @@
 // measurement of Eqs. (3)-(4).
 #include "device.h"
 #include "kernels.h"
+#include "rowops.h"
 
 namespace ptsg {
 
@@ -25,36 +26,40 @@ __global__ void k_init_int8(Geo g, int8_t* spins) {
 
 __global__ void k_init_packed(Geo g, uint32_t* spins) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long total = (long)g.S * g.nslot * g.NR;
+  const long total = (long)g.S * g.nslot * g.NW;
   if (idx >= total) return;
-  const long lat = idx / g.NR;
-  const int R = (int)(idx - lat * g.NR);
+  const long lat = idx / g.NW;
+  const int w = (int)(idx - lat * g.NW);
   const int s = (int)(lat / g.nslot), slot = (int)(lat - (long)s * g.nslot);
-  const RowNb q = row_nb(g, R);
+  const WordNb q = word_nb(g, w);
   uint32_t e = 0, o = 0;
-  uint32_t lastm = 0xFFFFFFFFu;
-  Ctr4 r{0, 0, 0, 0};
-  for (int x0 = 0; x0 < g.L; ++x0) {
-    const uint32_t i = (uint32_t)(x0 + g.L * R);
-    if ((i >> 2) != lastm) {
-      lastm = i >> 2;
-      r = philox10(Ctr4{lastm, 0u, (uint32_t)slot, (kTagInit << 28) | (uint32_t)s}, g.key0, g.key1);
+  for (int f = 0; f < g.P; ++f) {
+    const int R = word_row(g, q, f);
+    uint32_t lastm = 0xFFFFFFFFu;
+    Ctr4 r{0, 0, 0, 0};
+    for (int x0 = 0; x0 < g.L; ++x0) {
+      const uint32_t i = (uint32_t)(x0 + g.L * R);
+      if ((i >> 2) != lastm) {
+        lastm = i >> 2;
+        r = philox10(Ctr4{lastm, 0u, (uint32_t)slot, (kTagInit << 28) | (uint32_t)s}, g.key0,
+                     g.key1);
+      }
+      const uint32_t v = (i & 3) == 0 ? r.x : (i & 3) == 1 ? r.y : (i & 3) == 2 ? r.z : r.w;
+      const uint32_t bit = (v >> 31) << (f * g.H + (x0 >> 1));
+      if (x0 & 1)
+        o |= bit;
+      else
+        e |= bit;
     }
-    const uint32_t w = (i & 3) == 0 ? r.x : (i & 3) == 1 ? r.y : (i & 3) == 2 ? r.z : r.w;
-    const uint32_t bit = w >> 31;
-    if (x0 & 1)
-      o |= bit << (x0 >> 1);
-    else
-      e |= bit << (x0 >> 1);
   }
-  uint32_t* dst = spins + lat * 2 * (size_t)g.NR;
-  dst[q.p0 * g.NR + R] = e;
-  dst[(1 - q.p0) * g.NR + R] = o;
+  uint32_t* dst = spins + lat * 2 * (size_t)g.NW;
+  dst[w] = q.par ? o : e;
+  dst[g.NW + w] = q.par ? e : o;
 }
 
 hipError_t launch_init_spins(const Geo& g, void* spins, hipStream_t st) {
   if (g.layout == kLayoutPacked) {
-    const long total = (long)g.S * g.nslot * g.NR;
+    const long total = (long)g.S * g.nslot * g.NW;
     hipLaunchKernelGGL(k_init_packed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g,
                        static_cast<uint32_t*>(spins));
   } else {
@@ -70,35 +75,42 @@ hipError_t launch_init_spins(const Geo& g, void* spins, hipStream_t st) {
 // ---------------------------------------------------------------------------
 __global__ void k_pack_couplings(Geo g, const int8_t* __restrict__ J8, uint32_t* __restrict__ jw) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long total = (long)g.S * 2 * g.NR;
+  const long total = (long)g.S * 2 * g.NW;
   if (idx >= total) return;
-  const int R = (int)(idx % g.NR);
-  const long sc = idx / g.NR;
+  const int w = (int)(idx % g.NW);
+  const long sc = idx / g.NW;
   const int c = (int)(sc & 1), s = (int)(sc >> 1);
-  const RowNb q = row_nb(g, R);
-  const int p = (c + q.x1 + q.x2) & 1;
+  const WordNb q = word_nb(g, w);
+  const int p = (c + q.par) & 1;
   const int8_t* Js = J8 + (size_t)s * g.d * g.N;
-  uint32_t w[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < g.H; ++b) {
-    const int x0 = 2 * b + p;
-    const int i = x0 + g.L * R;
-    const int x0m = (x0 == 0) ? g.L - 1 : x0 - 1;
-    const uint32_t bit = 1u << b;
-    if (Js[0 * g.N + i] < 0) w[0] |= bit;
-    if (Js[0 * g.N + x0m + g.L * R] < 0) w[1] |= bit;
-    if (Js[1 * g.N + i] < 0) w[2] |= bit;
-    if (Js[1 * g.N + x0 + g.L * q.r1m] < 0) w[3] |= bit;
-    if (g.d == 3) {
-      if (Js[2 * g.N + i] < 0) w[4] |= bit;
-      if (Js[2 * g.N + x0 + g.L * q.r2m] < 0) w[5] |= bit;
+  uint32_t out[6] = {0, 0, 0, 0, 0, 0};
+  for (int f = 0; f < g.P; ++f) {
+    const int R = word_row(g, q, f);
+    const int x1 = (g.d == 3) ? R % g.L : R;
+    const int x2 = (g.d == 3) ? R / g.L : 0;
+    const int R1m = (g.d == 3) ? ((x1 + g.L - 1) % g.L) + g.L * x2 : (x1 + g.L - 1) % g.L;
+    const int R2m = (g.d == 3) ? x1 + g.L * ((x2 + g.L - 1) % g.L) : 0;
+    for (int b = 0; b < g.H; ++b) {
+      const int x0 = 2 * b + p;
+      const int i = x0 + g.L * R;
+      const int x0m = (x0 == 0) ? g.L - 1 : x0 - 1;
+      const uint32_t bit = 1u << (f * g.H + b);
+      if (Js[0 * g.N + i] < 0) out[0] |= bit;
+      if (Js[0 * g.N + x0m + g.L * R] < 0) out[1] |= bit;
+      if (Js[1 * g.N + i] < 0) out[2] |= bit;
+      if (Js[1 * g.N + x0 + g.L * R1m] < 0) out[3] |= bit;
+      if (g.d == 3) {
+        if (Js[2 * g.N + i] < 0) out[4] |= bit;
+        if (Js[2 * g.N + x0 + g.L * R2m] < 0) out[5] |= bit;
+      }
     }
   }
-  uint32_t* dst = jw + (((size_t)s * 2 + c) * 2 * g.d) * g.NR + R;
-  for (int dir = 0; dir < 2 * g.d; ++dir) dst[(size_t)dir * g.NR] = w[dir];
+  uint32_t* dst = jw + (((size_t)s * 2 + c) * 2 * g.d) * g.NW + w;
+  for (int dir = 0; dir < 2 * g.d; ++dir) dst[(size_t)dir * g.NW] = out[dir];
 }
 
 hipError_t launch_pack_couplings(const Geo& g, const int8_t* J8, uint32_t* jw, hipStream_t st) {
-  const long total = (long)g.S * 2 * g.NR;
+  const long total = (long)g.S * 2 * g.NW;
   hipLaunchKernelGGL(k_pack_couplings, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g, J8,
                      jw);
   return hipGetLastError();
@@ -108,11 +120,12 @@ hipError_t launch_pack_couplings(const Geo& g, const int8_t* J8, uint32_t* jw, h
 // energy recompute: every bond has exactly one colour-0 end (L even), so
 // #unsatisfied = sum over colour-0 words and the 2d directions of popc(U).
 // ---------------------------------------------------------------------------
+template <int D>
 __global__ void __launch_bounds__(256) k_energy(Geo g, const void* spins, const uint32_t* __restrict__ jw,
                                                 int32_t* E, int T, int LPB) {
   extern __shared__ uint32_t lds[];
   int* red = reinterpret_cast<int*>(lds);
-  uint32_t* W = lds + LPB + (size_t)(threadIdx.x / T) * 2 * g.NR;
+  uint32_t* W = lds + LPB + (size_t)(threadIdx.x / T) * 2 * g.NW;
   const int li = threadIdx.x / T, t = threadIdx.x - li * T;
   const long lat = (long)blockIdx.x * LPB + li;
   const bool active = lat < (long)g.S * g.nslot;
@@ -121,24 +134,9 @@ __global__ void __launch_bounds__(256) k_energy(Geo g, const void* spins, const 
   __syncthreads();
   if (active) {
     const int s = (int)(lat / g.nslot);
-    const uint32_t* jws = jw + (size_t)s * 2 * 2 * g.d * g.NR;  // colour 0
+    const uint32_t* jw0 = jw + (size_t)s * 2 * 2 * D * g.NW;  // colour 0
     int unsat = 0;
-    for (int R = t; R < g.NR; R += T) {
-      const RowNb q = row_nb(g, R);
-      const int p = q.p0;  // p(0, R)
-      const uint32_t* Wo = W + g.NR;
-      const uint32_t Wc = W[R];
-      uint32_t n0, n1;
-      x0_neighbours(g, Wo[R], p, n0, n1);
-      unsat += __popc(Wc ^ n0 ^ jws[0 * (size_t)g.NR + R]);
-      unsat += __popc(Wc ^ n1 ^ jws[1 * (size_t)g.NR + R]);
-      unsat += __popc(Wc ^ Wo[q.r1p] ^ jws[2 * (size_t)g.NR + R]);
-      unsat += __popc(Wc ^ Wo[q.r1m] ^ jws[3 * (size_t)g.NR + R]);
-      if (g.d == 3) {
-        unsat += __popc(Wc ^ Wo[q.r2p] ^ jws[4 * (size_t)g.NR + R]);
-        unsat += __popc(Wc ^ Wo[q.r2m] ^ jws[5 * (size_t)g.NR + R]);
-      }
-    }
+    for (int w = t; w < g.NW; w += T) unsat += unsatisfied_word<D>(g, W, jw0, w);
     atomicAdd(&red[li], unsat);
   }
   __syncthreads();
@@ -151,10 +149,22 @@ hipError_t launch_energy(const Geo& g, const void* spins, const uint32_t* jw, in
   size_t lds;
   sweep_shape(g, T, LPB, threads, lds);
   const long nlat = (long)g.S * g.nslot;
-  if (lds > 65536)
-    { const hipError_t ea = hipFuncSetAttribute((const void*)k_energy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); if (ea != hipSuccess) return ea; }
-  hipLaunchKernelGGL(k_energy, dim3((unsigned)((nlat + LPB - 1) / LPB)), dim3(threads), lds, st, g,
-                     spins, jw, E, T, LPB);
+  const dim3 grid((unsigned)((nlat + LPB - 1) / LPB));
+  if (g.d == 3) {
+    if (lds > 65536) {
+      const hipError_t ea = hipFuncSetAttribute((const void*)k_energy<3>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (ea != hipSuccess) return ea;
+    }
+    hipLaunchKernelGGL(k_energy<3>, grid, dim3(threads), lds, st, g, spins, jw, E, T, LPB);
+  } else {
+    if (lds > 65536) {
+      const hipError_t ea = hipFuncSetAttribute((const void*)k_energy<2>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (ea != hipSuccess) return ea;
+    }
+    hipLaunchKernelGGL(k_energy<2>, grid, dim3(threads), lds, st, g, spins, jw, E, T, LPB);
+  }
   return hipGetLastError();
 }
 
@@ -219,9 +229,9 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* spins, const
   __syncthreads();
   int neg = 0;
   if (g.layout == kLayoutPacked) {
-    const uint32_t* sa = static_cast<const uint32_t*>(spins) + ((size_t)s * g.nslot + a) * 2 * g.NR;
-    const uint32_t* sb = static_cast<const uint32_t*>(spins) + ((size_t)s * g.nslot + b) * 2 * g.NR;
-    for (int w = threadIdx.x; w < 2 * g.NR; w += blockDim.x) neg += __popc(sa[w] ^ sb[w]);
+    const uint32_t* sa = static_cast<const uint32_t*>(spins) + ((size_t)s * g.nslot + a) * 2 * g.NW;
+    const uint32_t* sb = static_cast<const uint32_t*>(spins) + ((size_t)s * g.nslot + b) * 2 * g.NW;
+    for (int w = threadIdx.x; w < 2 * g.NW; w += blockDim.x) neg += __popc(sa[w] ^ sb[w]);
   } else {
     const uint32_t* sa = reinterpret_cast<const uint32_t*>(static_cast<const int8_t*>(spins) +
                                                            ((size_t)s * g.nslot + a) * g.N);

@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, void* spins, const uint32_
   const long nlat = (long)g.S * g.nslot;
   const long lat = (long)blockIdx.x * LPB + li;
   const bool active = li < LPB && lat < nlat;
-  uint32_t* W = W0 + (size_t)li * 2 * g.NR;
+  uint32_t* W = W0 + (size_t)li * 2 * g.NW;
   if (threadIdx.x < LPB) red[threadIdx.x] = 0;
 
   int s = 0, slot = 0;
@@ -38,14 +38,14 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, void* spins, const uint32_
     load_lattice(g, spins, (size_t)lat, W, t, T);
   }
   __syncthreads();
-  const uint32_t* jws = jw + (size_t)s * 2 * 2 * D * g.NR;
+  const uint32_t* jws = jw + (size_t)s * 2 * 2 * D * g.NW;
   int dE = 0;
   for (int rep = 0; rep < nsweeps; ++rep) {
     for (int c = 0; c < 2; ++c) {
       if (active) {
-        const uint32_t* jwc = jws + (size_t)c * 2 * D * g.NR;
-        for (int R = t; R < g.NR; R += T)
-          sweep_row<D>(g, W, jwc, c, R, slot, s, t0 + (uint32_t)rep, th2, th4, th6, dE);
+        const uint32_t* jwc = jws + (size_t)c * 2 * D * g.NW;
+        for (int w = t; w < g.NW; w += T)
+          sweep_word<D>(g, W, jwc, c, w, slot, s, t0 + (uint32_t)rep, th2, th4, th6, dE);
       }
       __syncthreads();
     }
@@ -59,11 +59,11 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, void* spins, const uint32_
 }
 
 void sweep_shape(const Geo& g, int& T, int& LPB, int& threads, size_t& lds) {
-  T = g.NR < 256 ? g.NR : 256;
+  T = g.NW < 256 ? g.NW : 256;
   LPB = 256 / T;
   if (LPB < 1) LPB = 1;
   threads = T * LPB;
-  lds = sizeof(uint32_t) * ((size_t)LPB + (size_t)LPB * 2 * g.NR);
+  lds = sizeof(uint32_t) * ((size_t)LPB + (size_t)LPB * 2 * g.NW);
 }
 
 hipError_t launch_sweep(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
