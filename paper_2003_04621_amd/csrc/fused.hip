@@ -136,100 +136,139 @@ __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* l
 }
 
 // ---------------------------------------------------------------------------
-// Houdayer moves for all NT pairs of the resident sample, PC pairs at a time,
-// the pairs of a chunk growing their clusters together.
+// Wave-level helpers.  Lanes of one wavefront exchange data through LDS; the
+// wavefront issues its LDS instructions in order, so a compiler fence plus a
+// wait for outstanding LDS operations orders one lane's writes before
+// another lane's later reads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Grows both colour words w of a cluster: neighbours through other words,
+// then the closure along x0, where the two colour words of index w are each
+// other's only neighbours.  True if anything changed.
+template <int D>
+__device__ __forceinline__ bool grow_pair(const Geo& g, uint32_t* C, const uint32_t* Q, int w) {
+  const int NW = g.NW;
+  const uint32_t q0 = Q[w], q1 = Q[NW + w];
+  if (!(q0 | q1)) return false;
+  const WordNb q = word_nb(g, w);
+  const int p0 = q.par, p1 = 1 - q.par;  // p(0, w), p(1, w)
+  uint32_t n0[2 * D], n1[2 * D];
+  neighbour_words<D>(g, C + NW, w, q, p0, n0);  // colour-1 neighbours of colour-0 word
+  neighbour_words<D>(g, C, w, q, p1, n1);       // colour-0 neighbours of colour-1 word
+  uint32_t e0 = n0[2] | n0[3], e1 = n1[2] | n1[3];
+  if (D == 3) {
+    e0 |= n0[4] | n0[5];
+    e1 |= n1[4] | n1[5];
+  }
+  const uint32_t c0_old = C[w], c1_old = C[NW + w];
+  uint32_t c0 = c0_old | (q0 & (e0 | n0[0] | n0[1]));
+  uint32_t c1 = c1_old | (q1 & (e1 | n1[0] | n1[1]));
+  for (;;) {
+    uint32_t a, b;
+    x0_neighbours(g, c1, p0, a, b);
+    const uint32_t nc0 = c0 | (q0 & (a | b));
+    x0_neighbours(g, nc0, p1, a, b);
+    const uint32_t nc1 = c1 | (q1 & (a | b));
+    if (nc0 == c0 && nc1 == c1) break;
+    c0 = nc0;
+    c1 = nc1;
+  }
+  if (c0 == c0_old && c1 == c1_old) return false;
+  C[w] = c0;
+  C[NW + w] = c1;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Houdayer moves for all NT pairs of the resident sample: each wavefront
+// takes one pair at a time and grows its cluster alone, so clusters of very
+// different size (cold versus hot pairs) do not wait for one another.
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* lds, int s,
                                                   uint32_t v) {
   const Geo& g = A.g;
-  const int NT = g.NT, NW = g.NW, tid = threadIdx.x, T = blockDim.x, PC = A.lay.PC;
+  const int NT = g.NT, NW = g.NW, tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, nwave = blockDim.x >> 6;
   uint32_t* W = lds + A.lay.W;
-  const uint32_t* Jl = lds + A.lay.J;  // colour 0 block first
+  const uint32_t* Jl = lds + A.lay.J;  // colour-0 direction words first
   int32_t* El = reinterpret_cast<int32_t*>(lds + A.lay.E);
   const int32_t* sotl = reinterpret_cast<const int32_t*>(lds + A.lay.sot);
-  uint32_t* Qs = lds + A.lay.Qs;
-  uint32_t* Cs = lds + A.lay.Cs;
-  uint32_t* hcnt = lds + A.lay.hcnt;
-  int32_t* hdel = reinterpret_cast<int32_t*>(lds + A.lay.hdelta);
   const int W2 = 2 * NW;
-  for (int p0 = 0; p0 < NT; p0 += PC) {
-    const int np = min(PC, NT - p0);
-    if (tid < np) {
-      hcnt[tid] = 0;
-      hdel[tid] = 0;
+  uint32_t* Qw = lds + A.lay.Qs + (size_t)wave * 2 * W2;
+  uint32_t* Cw = Qw + W2;
+  const int rpl = (g.NR + 63) / 64;  // rows per lane for the seed search
+  for (int k = wave; k < NT; k += nwave) {
+    const int a = sotl[k], b = NT + sotl[NT + k];
+    uint32_t* Wa = W + (size_t)a * W2;
+    uint32_t* Wb = W + (size_t)b * W2;
+    int cnt = 0;
+    for (int i = lane; i < W2; i += 64) {
+      const uint32_t q = Wa[i] ^ Wb[i];
+      Qw[i] = q;
+      Cw[i] = 0;
+      cnt += __popc(q);
     }
-    __syncthreads();
-    for (int pl = 0; pl < np; ++pl) {
-      const int k = p0 + pl;
-      const uint32_t* Wa = W + (size_t)sotl[k] * W2;
-      const uint32_t* Wb = W + (size_t)(NT + sotl[NT + k]) * W2;
-      int cnt = 0;
-      for (int i = tid; i < W2; i += T) {
-        const uint32_t q = Wa[i] ^ Wb[i];
-        Qs[pl * W2 + i] = q;
-        Cs[pl * W2 + i] = 0;
-        cnt += __popc(q);
-      }
-      if (cnt) atomicAdd(&hcnt[pl], (uint32_t)cnt);
-    }
-    __syncthreads();
-    // seed of each pair: the m-th q = -1 site in increasing i
-    if (tid < np) {
-      const int pl = tid, k = p0 + pl;
-      const uint32_t n = hcnt[pl];
-      if (n > 0) {
-        const Ctr4 r = philox10(Ctr4{(uint32_t)k, v, 0u, (kTagHou << 28) | (uint32_t)s}, g.key0, g.key1);
-        const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
-        seed_in_rows(g, Qs + pl * W2, Cs + pl * W2, 0, g.NR, (uint32_t)__umul64hi(r64, (uint64_t)n));
-      }
-    }
-    __syncthreads();
-    // flood fill, all pairs of the chunk together
-    const int items = np * NW;
-    int any;
-    do {
+    const uint32_t n = (uint32_t)wave_sum(cnt);
+    if (n == 0) continue;
+    wave_lds_sync();
+    // seed: the m-th q = -1 site in increasing i; lanes own contiguous rows
+    const Ctr4 r = philox10(Ctr4{(uint32_t)k, v, 0u, (kTagHou << 28) | (uint32_t)s}, g.key0, g.key1);
+    const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
+    const uint32_t m = (uint32_t)__umul64hi(r64, (uint64_t)n);
+    const int r0 = min(g.NR, lane * rpl), r1 = min(g.NR, r0 + rpl);
+    uint32_t lc = 0;
+    for (int R = r0; R < r1; ++R) lc += row_minus_count(g, Qw, R);
+    const uint32_t incl = wave_inclusive_scan(lc, lane);
+    if (m >= incl - lc && m < incl) seed_in_rows(g, Qw, Cw, r0, r1, m - (incl - lc));
+    wave_lds_sync();
+    // flood fill until no word of the pair changes
+    for (;;) {
       int changed = 0;
-      for (int c = 0; c < 2; ++c) {
-        for (int it = tid; it < items; it += T) {
-          const int pl = (int)__umulhi((uint32_t)it, A.magicNW), w = it - pl * NW;
-          if (hcnt[pl] == 0) continue;
-          if (grow_word<D>(g, Cs + pl * W2, Qs + pl * W2, c, w)) changed = 1;
-        }
-        if (c == 0) __syncthreads();
-      }
-      any = __syncthreads_or(changed);
-    } while (any);
-    // energy change of replica a: bonds leaving the cluster, on colour-0 words
-    for (int it = tid; it < items; it += T) {
-      const int pl = (int)__umulhi((uint32_t)it, A.magicNW), w = it - pl * NW;
-      if (hcnt[pl] == 0) continue;
-      const int k = p0 + pl;
-      const int dl = cluster_delta_word<D>(g, Cs + pl * W2, W + (size_t)sotl[k] * W2, Jl, w);
-      if (dl) atomicAdd(&hdel[pl], dl);
+      for (int w = lane; w < NW; w += 64)
+        if (grow_pair<D>(g, Cw, Qw, w)) changed = 1;
+      wave_lds_sync();
+      if (!__any(changed)) break;
     }
-    __syncthreads();
-    // exchange the two replicas on the clusters
-    for (int pl = 0; pl < np; ++pl) {
-      if (hcnt[pl] == 0) continue;
-      const int k = p0 + pl;
-      uint32_t* Wa = W + (size_t)sotl[k] * W2;
-      uint32_t* Wb = W + (size_t)(NT + sotl[NT + k]) * W2;
-      for (int i = tid; i < W2; i += T) {
-        const uint32_t cw = Cs[pl * W2 + i];
-        if (cw) {
-          Wa[i] ^= cw;
-          Wb[i] ^= cw;
-        }
+    // energy change of replica a, then exchange the replicas on the cluster
+    int dl = 0;
+    for (int w = lane; w < NW; w += 64) dl += cluster_delta_word<D>(g, Cw, Wa, Jl, w);
+    const int delta = wave_sum(dl);
+    for (int i = lane; i < W2; i += 64) {
+      const uint32_t cw = Cw[i];
+      if (cw) {
+        Wa[i] ^= cw;
+        Wb[i] ^= cw;
       }
     }
-    if (tid < np && hcnt[tid] != 0) {
-      const int k = p0 + tid;
-      El[sotl[k]] += hdel[tid];
-      El[NT + sotl[NT + k]] -= hdel[tid];
+    if (lane == 0) {
+      El[a] += delta;
+      El[b] -= delta;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -337,15 +376,10 @@ bool fused_plan(const Geo& g, bool hou, FusedLayout& lay) {
   lay.PC = 0;
   lay.Qs = lay.Cs = lay.hcnt = lay.hdelta = (int)off;
   if (hou) {
-    if (off + 2 * W2 + 2 > budget) return false;
-    const size_t per = 2 * W2 + 2;
-    size_t pc = (budget - off) / per;
-    if (pc > (size_t)g.NT) pc = g.NT;
-    lay.PC = (int)pc;
-    lay.Qs = take(pc * W2, 1);
-    lay.Cs = take(pc * W2, 1);
-    lay.hcnt = take(pc, 1);
-    lay.hdelta = take(pc, 1);
+    // overlap and cluster words for each of the 16 wavefronts
+    lay.PC = 16;
+    lay.Qs = take(16 * 2 * W2, 1);
+    lay.Cs = lay.Qs;
   }
   lay.words = (int)off;
   return off <= budget;
