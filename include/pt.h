@@ -64,8 +64,10 @@ extern "C" {
 #define PT_MCS_HOUDAYER 1u
 #define PT_MCS_MEASURE 2u
 #define PT_MCS_PLAIN 4u /* force the separate per-step kernels */
+#define PT_BATCH_GRAPH 8u /* pt_batch_run: replay a captured hipGraph of the launch */
 
 typedef struct pt_job pt_job;
+typedef struct pt_batch pt_batch;
 
 /* Creates a job: copies the couplings in, draws the initial spins (one
  * Philox word per site), sets the maps to the identity, computes every
@@ -163,6 +165,37 @@ int pt_get_moments(pt_job *job, int64_t *out);
  * identical shape and layout; continuing is bit-identical to never stopping. */
 int pt_get_state(pt_job *job, void *buf, size_t *len);
 int pt_set_state(pt_job *job, const void *buf, size_t len);
+
+/* ---- batched form ---------------------------------------------------------- */
+/* Groups n >= 1 distinct jobs of the same dim (any L, replicas, samples,
+ * layout) so that pt_batch_run advances all of them in one persistent launch.
+ * The batch borrows the handles (they must outlive it) and uses the stream of
+ * jobs[0] unless pt_batch_set_stream says otherwise.  Each job's results are
+ * bit-identical to running it alone with pt_mcs: every random number is keyed
+ * by the job's own seed and sample index. */
+int pt_batch_create(pt_job *const *jobs, int32_t n, pt_batch **out);
+int pt_batch_set_stream(pt_batch *b, void *hip_stream);
+
+/* mcs Monte Carlo steps of every job (Sec. 2.4), flags as pt_mcs
+ * (PT_MCS_HOUDAYER, PT_MCS_MEASURE) plus PT_BATCH_GRAPH: the launch
+ * (queue reset, persistent kernel, counter advance) is captured once as a
+ * hipGraph per (mcs, flags, configuration) and replayed; the device counters
+ * make every replay continue the random-number streams.  Workgroups take
+ * (job, sample, replica sets) items from a device queue, largest first by
+ * default.  A job must fit one workgroup's LDS with at least one replica set
+ * resident (two for Houdayer or measurement); PT_EINVAL otherwise. */
+int pt_batch_run(pt_batch *b, int32_t mcs, uint32_t flags);
+
+/* Autotuner: times trial_mcs steps of each launch configuration (threads per
+ * workgroup 1024/512/256, one or two replica sets per item, largest-first or
+ * job order) on the batch itself, restores every job's state after each trial,
+ * and keeps the fastest.  cache_path (may be NULL) is a JSON-lines file keyed
+ * by the batch shape; a hit skips the trials. */
+int pt_batch_tune(pt_batch *b, int32_t trial_mcs, uint32_t flags, const char *cache_path);
+/* cfg3 = {threads per workgroup, replica sets per item, order} */
+int pt_batch_get_config(pt_batch *b, int32_t *cfg3);
+int pt_batch_set_config(pt_batch *b, int32_t threads, int32_t sets, int32_t order);
+int pt_batch_destroy(pt_batch *b);
 
 /* ---- plumbing ------------------------------------------------------------ */
 /* Makes the job enqueue on a HIP stream (hipStream_t; NULL = null stream). */

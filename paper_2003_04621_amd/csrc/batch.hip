@@ -1,0 +1,394 @@
+// batch.hip -- many independent jobs (any L, N_T, samples, spin layout) in
+// one persistent launch per call: a work list of (job, sample, replica sets)
+// items consumed from a device queue, the launch optionally captured once as
+// a hipGraph and replayed, and an autotuner that picks the launch shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "job.h"
+#include "kernels.h"
+#include "pt.h"
+
+using namespace ptsg;
+
+struct BatchConfig {
+  int threads = 1024;  // threads per workgroup: 256, 512 or 1024
+  int sets = 2;        // replica sets per item when both fit (2) or always one (1)
+  int order = 0;       // 0: largest items first, 1: job order
+};
+
+struct pt_batch {
+  std::vector<pt_job*> jobs;
+  int d = 3;
+  int ncu = 256;
+  hipStream_t stream = nullptr;
+  BatchConfig cfg;
+  // device work list for the last (mcs, flags, cfg)
+  FusedArgs* d_jobs = nullptr;
+  BatchItem* d_items = nullptr;
+  uint32_t* d_queue = nullptr;
+  int cap_jobs = 0, cap_items = 0;
+  int nitems = 0;
+  size_t lds_bytes = 0;
+  int blocks = 0;
+  bool built = false;
+  int built_mcs = -1;
+  uint32_t built_flags = 0;
+  BatchConfig built_cfg;
+  // captured launch (captured on a private stream, replayed on `stream`)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool graph_ok = false;
+};
+
+namespace {
+
+bool same_cfg(const BatchConfig& a, const BatchConfig& b) {
+  return a.threads == b.threads && a.sets == b.sets && a.order == b.order;
+}
+
+void drop_graph(pt_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_ok = false;
+}
+
+// Plan index of a job for the given flags and config, or -1 if it cannot be
+// resident in one workgroup.
+int job_mode(const pt_job* j, uint32_t flags, const BatchConfig& cfg) {
+  const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  if (hou) return j->fused_ok[1] ? 1 : -1;
+  if (cfg.sets == 2 && j->fused_ok[0]) return 0;
+  if (meas) return j->fused_ok[0] ? 0 : -1;
+  return j->fused_ok[2] ? 2 : (j->fused_ok[0] ? 0 : -1);
+}
+
+int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
+  if (b->built && b->built_mcs == mcs && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg))
+    return PT_OK;
+  const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  std::vector<FusedArgs> hj;
+  std::vector<BatchItem> hi;
+  std::vector<double> cost;
+  size_t lds_words = 0;
+  for (size_t jx = 0; jx < b->jobs.size(); ++jx) {
+    pt_job* j = b->jobs[jx];
+    const int mode = job_mode(j, flags, b->cfg);
+    if (mode < 0)
+      return pt_fail(PT_EINVAL, "pt_batch_run: job " + std::to_string(jx) +
+                                    " does not fit one workgroup's LDS for these flags (use pt_mcs)");
+    const int nsets = mode == 2 ? 1 : 2;
+    hj.push_back(make_fused_args(j->g, j->plan[mode], j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
+                                 j->thrpt, j->M, j->mom, j->ctr, mcs, hou, meas));
+    lds_words = std::max(lds_words, (size_t)j->plan[mode].words);
+    const double c = (double)nsets * j->g.NT * j->g.N;
+    for (int s = 0; s < j->g.S; ++s)
+      for (int c_lo = 0; c_lo < 2; c_lo += nsets) {
+        hi.push_back(BatchItem{(int)jx, s, c_lo, nsets});
+        cost.push_back(c);
+      }
+  }
+  if (b->cfg.order == 0) {
+    std::vector<size_t> idx(hi.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<BatchItem> sorted(hi.size());
+    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = hi[idx[i]];
+    hi.swap(sorted);
+  }
+  hipError_t e = hipSuccess;
+  if ((int)hj.size() > b->cap_jobs) {
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    b->d_jobs = nullptr;
+    e = hipMalloc((void**)&b->d_jobs, sizeof(FusedArgs) * hj.size());
+    if (e != hipSuccess) return pt_fail(PT_ENOMEM, "pt_batch_run: device allocation failed");
+    b->cap_jobs = (int)hj.size();
+  }
+  if ((int)hi.size() > b->cap_items) {
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_items = nullptr;
+    e = hipMalloc((void**)&b->d_items, sizeof(BatchItem) * hi.size());
+    if (e != hipSuccess) return pt_fail(PT_ENOMEM, "pt_batch_run: device allocation failed");
+    b->cap_items = (int)hi.size();
+  }
+  if (!b->d_queue) {
+    e = hipMalloc((void**)&b->d_queue, 256);
+    if (e != hipSuccess) return pt_fail(PT_ENOMEM, "pt_batch_run: device allocation failed");
+  }
+  e = hipMemcpyAsync(b->d_jobs, hj.data(), sizeof(FusedArgs) * hj.size(), hipMemcpyHostToDevice,
+                     b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_items, hi.data(), sizeof(BatchItem) * hi.size(), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  b->nitems = (int)hi.size();
+  b->lds_bytes = lds_words * 4;
+  e = prepare_batch(b->d, b->lds_bytes);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  // persistent grid: as many workgroups as can be resident at once
+  int per_cu = 1;
+  const int by_lds = (int)((160 * 1024) / std::max<size_t>(b->lds_bytes, 1));
+  const int by_waves = std::max(1, 24 / (b->cfg.threads / 64));  // <= 6 waves per SIMD at this VGPR use
+  per_cu = std::max(1, std::min(by_lds, by_waves));
+  b->blocks = std::max(1, std::min(b->ncu * per_cu, b->nitems));
+  b->built = true;
+  b->built_mcs = mcs;
+  b->built_flags = flags;
+  b->built_cfg = b->cfg;
+  drop_graph(b);
+  return PT_OK;
+}
+
+int run_once(pt_batch* b, bool use_graph) {
+  if (!use_graph) {
+    const hipError_t e = launch_batch(b->d, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems,
+                                      b->d_queue, b->blocks, b->cfg.threads, b->lds_bytes, b->stream);
+    if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+    return PT_OK;
+  }
+  if (!b->graph_ok) {
+    hipError_t e = hipSuccess;
+    if (!b->cap_stream) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t el = launch_batch(b->d, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems,
+                                         b->d_queue, b->blocks, b->cfg.threads, b->lds_bytes,
+                                         b->cap_stream);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(b->cap_stream, &g);
+      if (e == hipSuccess && el != hipSuccess) e = el;
+      if (e == hipSuccess) {
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      } else if (g) {
+        (void)hipGraphDestroy(g);
+      }
+    }
+    if (e != hipSuccess) {
+      drop_graph(b);
+      return pt_fail(PT_EDEVICE, std::string("pt_batch_run graph capture: ") + hipGetErrorString(e));
+    }
+    b->graph_ok = true;
+  }
+  const hipError_t e = hipGraphLaunch(b->exec, b->stream);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  return PT_OK;
+}
+
+// ---- state snapshot for tuning trials --------------------------------------
+struct Snap {
+  std::vector<void*> bufs;
+};
+
+int snapshot(pt_batch* b, Snap& sn, bool restore) {
+  size_t k = 0;
+  for (pt_job* j : b->jobs) {
+    const size_t lat = (size_t)j->g.S * j->g.nslot, maps = sizeof(int32_t) * (size_t)j->g.S * 2 * j->g.NT;
+    void* src[6] = {j->spins, j->E, j->sot, j->tos, j->ctr, j->mom};
+    const size_t len[6] = {j->spin_bytes(), sizeof(int32_t) * lat, maps, maps, sizeof(DevCounters),
+                           sizeof(int64_t) * 8 * (size_t)j->g.S * j->g.NT};
+    for (int i = 0; i < 6; ++i, ++k) {
+      if (!restore) {
+        void* p = nullptr;
+        if (hipMalloc(&p, len[i]) != hipSuccess) return pt_fail(PT_ENOMEM, "pt_batch_tune: snapshot allocation failed");
+        sn.bufs.push_back(p);
+        if (hipMemcpyAsync(p, src[i], len[i], hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+          return pt_fail(PT_EDEVICE, "pt_batch_tune: snapshot copy failed");
+      } else if (hipMemcpyAsync(src[i], sn.bufs[k], len[i], hipMemcpyDeviceToDevice, b->stream) !=
+                 hipSuccess) {
+        return pt_fail(PT_EDEVICE, "pt_batch_tune: restore copy failed");
+      }
+    }
+  }
+  return hipStreamSynchronize(b->stream) == hipSuccess ? PT_OK
+                                                        : pt_fail(PT_EDEVICE, "pt_batch_tune: sync failed");
+}
+
+std::string cache_key(const pt_batch* b, uint32_t flags) {
+  // dimension, flags and the sorted multiset of (L, N_T, samples, layout)
+  std::vector<std::string> parts;
+  for (const pt_job* j : b->jobs)
+    parts.push_back(std::to_string(j->g.L) + "x" + std::to_string(j->g.NT) + "x" +
+                    std::to_string(j->g.S) + "x" + std::to_string(j->g.layout));
+  std::sort(parts.begin(), parts.end());
+  std::string key = "gfx950/d" + std::to_string(b->d) + "/f" + std::to_string(flags) + "/";
+  size_t i = 0;
+  while (i < parts.size()) {
+    size_t n = 1;
+    while (i + n < parts.size() && parts[i + n] == parts[i]) ++n;
+    key += parts[i] + "*" + std::to_string(n) + ";";
+    i += n;
+  }
+  return key;
+}
+
+bool cache_lookup(const char* path, const std::string& key, BatchConfig& cfg) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    // {"key": "<key>", "threads": T, "sets": S, "order": O}
+    const std::string l(line);
+    const std::string want = "\"key\": \"" + key + "\"";
+    if (l.find(want) == std::string::npos) continue;
+    int t = 0, s = 0, o = 0;
+    const char* p = std::strstr(line, "\"threads\":");
+    const char* q = std::strstr(line, "\"sets\":");
+    const char* r = std::strstr(line, "\"order\":");
+    if (p && q && r && std::sscanf(p, "\"threads\": %d", &t) == 1 && std::sscanf(q, "\"sets\": %d", &s) == 1 &&
+        std::sscanf(r, "\"order\": %d", &o) == 1) {
+      cfg.threads = t;
+      cfg.sets = s;
+      cfg.order = o;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const BatchConfig& cfg, double ms) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"sets\": %d, \"order\": %d, \"trial_ms\": %.4f}\n",
+               key.c_str(), cfg.threads, cfg.sets, cfg.order, ms);
+  std::fclose(f);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+PT_API int pt_batch_create(pt_job* const* jobs, int32_t n, pt_batch** out) {
+  if (!jobs || !out || n < 1) return pt_fail(PT_EINVAL, "pt_batch_create: need n >= 1 jobs and an output");
+  const int d = jobs[0] ? jobs[0]->g.d : 0;
+  for (int i = 0; i < n; ++i) {
+    if (!jobs[i]) return pt_fail(PT_EINVAL, "pt_batch_create: null job");
+    if (jobs[i]->poisoned) return pt_fail(PT_ESTATE, "pt_batch_create: a job is poisoned");
+    if (jobs[i]->g.d != d) return pt_fail(PT_EINVAL, "pt_batch_create: all jobs must have the same dim");
+    for (int k = 0; k < i; ++k)
+      if (jobs[k] == jobs[i]) return pt_fail(PT_EINVAL, "pt_batch_create: a job appears twice");
+  }
+  pt_batch* b = new (std::nothrow) pt_batch();
+  if (!b) return pt_fail(PT_ENOMEM, "pt_batch_create: host allocation failed");
+  b->jobs.assign(jobs, jobs + n);
+  b->d = d;
+  b->stream = jobs[0]->stream;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    b->ncu = ncu;
+  (void)hipGetLastError();
+  *out = b;
+  return PT_OK;
+}
+
+PT_API int pt_batch_set_stream(pt_batch* b, void* hip_stream) {
+  if (!b) return pt_fail(PT_EINVAL, "null batch");
+  b->stream = (hipStream_t)hip_stream;
+  drop_graph(b);
+  return PT_OK;
+}
+
+PT_API int pt_batch_run(pt_batch* b, int32_t mcs, uint32_t flags) {
+  if (!b) return pt_fail(PT_EINVAL, "null batch");
+  if (mcs < 0) return pt_fail(PT_EINVAL, "pt_batch_run: mcs must be >= 0");
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_BATCH_GRAPH))
+    return pt_fail(PT_EINVAL, "pt_batch_run: unknown flags");
+  for (pt_job* j : b->jobs)
+    if (j->poisoned) return pt_fail(PT_ESTATE, "pt_batch_run: a job is poisoned");
+  if (mcs == 0) return PT_OK;
+  const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE);
+  if (int rc = build_worklist(b, mcs, work_flags)) return rc;
+  const int rc = run_once(b, (flags & PT_BATCH_GRAPH) != 0);
+  if (rc != PT_OK)
+    for (pt_job* j : b->jobs) j->poisoned = true;
+  return rc;
+}
+
+PT_API int pt_batch_get_config(pt_batch* b, int32_t* cfg3) {
+  if (!b || !cfg3) return pt_fail(PT_EINVAL, "null argument");
+  cfg3[0] = b->cfg.threads;
+  cfg3[1] = b->cfg.sets;
+  cfg3[2] = b->cfg.order;
+  return PT_OK;
+}
+
+PT_API int pt_batch_set_config(pt_batch* b, int32_t threads, int32_t sets, int32_t order) {
+  if (!b) return pt_fail(PT_EINVAL, "null batch");
+  if ((threads != 256 && threads != 512 && threads != 1024) || (sets != 1 && sets != 2) ||
+      (order != 0 && order != 1))
+    return pt_fail(PT_EINVAL, "pt_batch_set_config: threads in {256,512,1024}, sets in {1,2}, order in {0,1}");
+  b->cfg = BatchConfig{threads, sets, order};
+  return PT_OK;
+}
+
+PT_API int pt_batch_tune(pt_batch* b, int32_t trial_mcs, uint32_t flags, const char* cache_path) {
+  if (!b) return pt_fail(PT_EINVAL, "null batch");
+  if (trial_mcs < 1) return pt_fail(PT_EINVAL, "pt_batch_tune: trial_mcs must be >= 1");
+  const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE);
+  const std::string key = cache_key(b, work_flags);
+  BatchConfig cached;
+  if (cache_lookup(cache_path, key, cached)) {
+    b->cfg = cached;
+    return PT_OK;
+  }
+  Snap sn;
+  if (int rc = snapshot(b, sn, false)) {
+    for (void* p : sn.bufs) (void)hipFree(p);
+    return rc;
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  BatchConfig best = b->cfg;
+  double best_ms = 1e300;
+  int rc = PT_OK;
+  for (int threads : {1024, 512, 256})
+    for (int sets : {2, 1})
+      for (int order : {0, 1}) {
+        b->cfg = BatchConfig{threads, sets, order};
+        if ((rc = build_worklist(b, trial_mcs, work_flags))) break;
+        (void)hipEventRecord(e0, b->stream);
+        if ((rc = run_once(b, false))) break;
+        (void)hipEventRecord(e1, b->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = b->cfg;
+        }
+        if ((rc = snapshot(b, sn, true))) break;
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (void* p : sn.bufs) (void)hipFree(p);
+  b->cfg = best;
+  if (rc == PT_OK) cache_store(cache_path, key, best, best_ms);
+  return rc;
+}
+
+PT_API int pt_batch_destroy(pt_batch* b) {
+  if (!b) return pt_fail(PT_EINVAL, "null batch");
+  (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  (void)hipGetLastError();
+  delete b;
+  return PT_OK;
+}

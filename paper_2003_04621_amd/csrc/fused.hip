@@ -14,22 +14,6 @@
 
 namespace ptsg {
 
-struct FusedArgs {
-  Geo g;
-  void* spins;
-  const uint32_t* jw;
-  int32_t* E;
-  int32_t* sot;
-  int32_t* tos;
-  const uint32_t* thr;
-  const uint32_t* thrpt;
-  int M;
-  int64_t* mom;
-  const DevCounters* ctr;
-  int nmcs, hou, meas;
-  uint32_t magicNW;  // item / NW
-  FusedLayout lay;
-};
 
 // ---------------------------------------------------------------------------
 // Replica exchange for both sets of the resident sample.  The pass is
@@ -40,7 +24,7 @@ struct FusedArgs {
 // per set walks the chain.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* lds, int s,
-                                                  uint32_t u) {
+                                                  uint32_t u, int c_lo, int nsets) {
   const Geo& g = A.g;
   const int NT = g.NT, tid = threadIdx.x, T = blockDim.x;
   const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
@@ -50,15 +34,16 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
   uint32_t* rpt = lds + A.lay.rpt;
   uint8_t* acc = reinterpret_cast<uint8_t*>(lds + A.lay.acc);
   for (int i = tid; i < 2 * NT; i += T) sot0[i] = sotl[i];
-  for (int i = tid; i < 2 * (NT - 1); i += T) {
-    const int c = i / (NT - 1), k = i - c * (NT - 1);
+  for (int i = tid; i < nsets * (NT - 1); i += T) {
+    const int c = c_lo + i / (NT - 1), k = i - (c - c_lo) * (NT - 1);
     rpt[c * NT + k] =
         philox10(Ctr4{(uint32_t)k, u, (uint32_t)c, (kTagPT << 28) | (uint32_t)s}, g.key0, g.key1).x;
   }
   __syncthreads();
   const int per_set = (NT - 1) * NT;
-  for (int i = tid; i < 2 * per_set; i += T) {
-    const int c = i / per_set, rem = i - c * per_set, k = rem / NT, j = rem - k * NT;
+  for (int i = tid; i < nsets * per_set; i += T) {
+    const int cl = i / per_set, rem = i - cl * per_set, k = rem / NT, j = rem - k * NT;
+    const int c = c_lo + cl;
     if (j > k) continue;
     const int a = sot0[c * NT + j], b = sot0[c * NT + k + 1];
     const int32_t D = El[c * NT + b] - El[c * NT + a];
@@ -70,8 +55,8 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
     acc[(c * NT + k) * NT + j] = ok ? 1 : 0;
   }
   __syncthreads();
-  if (tid < 2) {
-    const int c = tid;
+  if (tid < nsets) {
+    const int c = c_lo + tid;
     const int32_t* m0 = sot0 + c * NT;
     int32_t* so = sotl + c * NT;
     int32_t* to = tosl + c * NT;
@@ -272,42 +257,49 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// nmcs Monte Carlo steps of sample s with replica sets [c_lo, c_lo + nsets)
+// resident in LDS.  With one set only the sweep and the exchange run (the
+// Houdayer move and the overlap need both sets).  Only the resident sets'
+// state is written back, so the two sets of a sample may run in different
+// workgroups at the same time.
+// ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(1024) k_mcs(FusedArgs A) {
-  extern __shared__ uint32_t lds[];
+__device__ void run_sample(const FusedArgs& A, uint32_t* lds, int s, int c_lo, int nsets) {
   const Geo& g = A.g;
-  const int T = blockDim.x, tid = threadIdx.x, s = blockIdx.x;
+  const int T = blockDim.x, tid = threadIdx.x;
   const int NW = g.NW, NT = g.NT, nslot = g.nslot, W2 = 2 * NW;
-  uint32_t* W = lds + A.lay.W;
+  const int slot0 = c_lo * NT, nres = nsets * NT;  // resident slots [slot0, slot0 + nres)
+  uint32_t* W = lds + A.lay.W;                     // W[(slot - slot0) * W2 + ...]
   uint32_t* Jl = lds + A.lay.J;
   int32_t* El = reinterpret_cast<int32_t*>(lds + A.lay.E);
   int32_t* sotl = reinterpret_cast<int32_t*>(lds + A.lay.sot);
   int32_t* tosl = reinterpret_cast<int32_t*>(lds + A.lay.tos);
   uint32_t* thrl = lds + A.lay.thr;
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
-  const size_t lat0 = (size_t)s * nslot;
+  const size_t lat0 = (size_t)s * nslot + slot0;
+  const bool hou = A.hou && nsets == 2, meas = A.meas && nsets == 2;
 
-  // ---- load the sample
-  const int items = nslot * NW;
+  // ---- load
+  const int items = nres * NW;
   if (g.layout == kLayoutPacked) {
     const uint32_t* src = static_cast<const uint32_t*>(A.spins) + lat0 * W2;
-    for (int i = tid; i < nslot * W2; i += T) W[i] = src[i];
+    for (int i = tid; i < nres * W2; i += T) W[i] = src[i];
   } else {
     const int8_t* src = static_cast<const int8_t*>(A.spins) + lat0 * g.N;
     for (int it = tid; it < items; it += T) {
-      const int slot = (int)__umulhi((uint32_t)it, A.magicNW), w = it - slot * NW;
-      word_from_int8(g, src + (size_t)slot * g.N, w, W[slot * W2 + w], W[slot * W2 + NW + w]);
+      const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+      word_from_int8(g, src + (size_t)ls * g.N, w, W[ls * W2 + w], W[ls * W2 + NW + w]);
     }
   }
   const uint32_t* jws = A.jw + (size_t)s * 2 * 2 * D * NW;
   for (int i = tid; i < 2 * 2 * D * NW; i += T) Jl[i] = jws[i];
-  for (int i = tid; i < nslot; i += T) El[i] = A.E[lat0 + i];
+  for (int i = tid; i < nslot; i += T) El[i] = A.E[(size_t)s * nslot + i];
   for (int i = tid; i < 2 * NT; i += T) {
     sotl[i] = A.sot[(size_t)s * 2 * NT + i];
     tosl[i] = A.tos[(size_t)s * 2 * NT + i];
   }
   for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
-  if (A.meas)
+  if (meas)
     for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
   const uint32_t t0 = A.ctr->t, u0 = A.ctr->u, v0 = A.ctr->v;
   __syncthreads();
@@ -317,43 +309,94 @@ __global__ void __launch_bounds__(1024) k_mcs(FusedArgs A) {
     for (int c = 0; c < 2; ++c) {
       const uint32_t* Jc = Jl + c * 2 * D * NW;
       for (int it = tid; it < items; it += T) {
-        const int slot = (int)__umulhi((uint32_t)it, A.magicNW), w = it - slot * NW;
+        const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+        const int slot = slot0 + ls;
         const int k = tosl[slot];
         int dE = 0;
-        sweep_word<D>(g, W + slot * W2, Jc, c, w, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
+        sweep_word<D>(g, W + ls * W2, Jc, c, w, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
                       thrl[k * 4 + 2], dE);
         if (dE) atomicAdd(&El[slot], dE);
       }
       __syncthreads();
     }
-    if (A.hou) houdayer_resident<D>(A, lds, s, v0 + (uint32_t)step);
-    exchange_resident(A, lds, s, u0 + (uint32_t)step);
-    if (A.meas) measure_resident(A, lds);
+    if (hou) houdayer_resident<D>(A, lds, s, v0 + (uint32_t)step);
+    exchange_resident(A, lds, s, u0 + (uint32_t)step, c_lo, nsets);
+    if (meas) measure_resident(A, lds);
   }
 
-  // ---- store the sample
+  // ---- store the resident sets
   if (g.layout == kLayoutPacked) {
     uint32_t* dst = static_cast<uint32_t*>(A.spins) + lat0 * W2;
-    for (int i = tid; i < nslot * W2; i += T) dst[i] = W[i];
+    for (int i = tid; i < nres * W2; i += T) dst[i] = W[i];
   } else {
     int8_t* dst = static_cast<int8_t*>(A.spins) + lat0 * g.N;
     for (int it = tid; it < items; it += T) {
-      const int slot = (int)__umulhi((uint32_t)it, A.magicNW), w = it - slot * NW;
-      word_to_int8(g, dst + (size_t)slot * g.N, w, W[slot * W2 + w], W[slot * W2 + NW + w]);
+      const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+      word_to_int8(g, dst + (size_t)ls * g.N, w, W[ls * W2 + w], W[ls * W2 + NW + w]);
     }
   }
-  for (int i = tid; i < nslot; i += T) A.E[lat0 + i] = El[i];
-  for (int i = tid; i < 2 * NT; i += T) {
-    A.sot[(size_t)s * 2 * NT + i] = sotl[i];
-    A.tos[(size_t)s * 2 * NT + i] = tosl[i];
+  for (int i = tid; i < nres; i += T) A.E[lat0 + i] = El[slot0 + i];
+  for (int i = tid; i < nres; i += T) {
+    A.sot[(size_t)s * 2 * NT + slot0 + i] = sotl[slot0 + i];
+    A.tos[(size_t)s * 2 * NT + slot0 + i] = tosl[slot0 + i];
   }
-  if (A.meas)
+  if (meas)
     for (int i = tid; i < 8 * NT; i += T) A.mom[(size_t)s * NT * 8 + i] = mom[i];
 }
 
+template <int D>
+__global__ void __launch_bounds__(1024) k_mcs(FusedArgs A, int nsets) {
+  extern __shared__ uint32_t lds[];
+  const int s = blockIdx.x / (3 - nsets);  // nsets == 1: two workgroups per sample
+  const int c_lo = nsets == 2 ? 0 : (int)(blockIdx.x & 1);
+  run_sample<D>(A, lds, s, c_lo, nsets);
+}
+
 // ---------------------------------------------------------------------------
-bool fused_plan(const Geo& g, bool hou, FusedLayout& lay) {
-  const size_t budget = 160 * 1024 / 4;  // LDS words per workgroup on gfx950
+// Persistent batch kernel: workgroups take (job, sample, sets) items from a
+// shared queue until it is empty.  Each job brings its own geometry,
+// tables, state and LDS plan.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jobs,
+                                                const BatchItem* __restrict__ items, int nitems,
+                                                uint32_t* queue) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int i = __builtin_amdgcn_readfirstlane(cur);
+    __syncthreads();
+    if (i >= nitems) break;
+    const BatchItem it = items[i];
+    const FusedArgs A = jobs[it.job];
+    if (A.nmcs > 0) run_sample<D>(A, lds, it.sample, it.c_lo, it.nsets);
+    __syncthreads();
+  }
+}
+
+__global__ void k_batch_reset(uint32_t* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
+}
+
+// Advances every job's counters by its own number of steps in this launch.
+__global__ void k_batch_advance(const FusedArgs* __restrict__ jobs, int njobs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= njobs) return;
+  const FusedArgs& A = jobs[j];
+  DevCounters* c = const_cast<DevCounters*>(A.ctr);
+  const uint32_t n = (uint32_t)A.nmcs;
+  c->t += n;
+  c->u += n;
+  if (A.hou) c->v += n;
+  if (A.meas) c->n_meas += n;
+}
+
+// ---------------------------------------------------------------------------
+bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) {
+  // LDS words per workgroup on gfx950 (160 KiB), less room for static LDS
+  const size_t budget = (160 * 1024 - 512) / 4;
   size_t off = 0;
   auto take = [&](size_t words, size_t align) {
     off = (off + align - 1) / align * align;
@@ -362,7 +405,7 @@ bool fused_plan(const Geo& g, bool hou, FusedLayout& lay) {
     return (int)at;
   };
   const size_t W2 = 2 * (size_t)g.NW;
-  lay.W = take((size_t)g.nslot * W2, 1);
+  lay.W = take((size_t)nsets * g.NT * W2, 1);
   lay.J = take(2 * 2 * (size_t)g.d * g.NW, 1);
   lay.E = take(g.nslot, 1);
   lay.sot = take(2 * g.NT, 1);
@@ -375,20 +418,20 @@ bool fused_plan(const Geo& g, bool hou, FusedLayout& lay) {
   lay.acc = take((2 * (size_t)g.NT * g.NT + 3) / 4, 1);
   lay.PC = 0;
   lay.Qs = lay.Cs = lay.hcnt = lay.hdelta = (int)off;
-  if (hou) {
-    // overlap and cluster words for each of the 16 wavefronts
-    lay.PC = 16;
-    lay.Qs = take(16 * 2 * W2, 1);
+  if (hou && nsets == 2) {
+    // overlap and cluster words for each wavefront
+    lay.PC = waves;
+    lay.Qs = take((size_t)waves * 2 * W2, 1);
     lay.Cs = lay.Qs;
   }
   lay.words = (int)off;
   return off <= budget;
 }
 
-hipError_t launch_mcs_fused(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
-                            int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
-                            const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
-                            int nmcs, bool hou, bool meas, hipStream_t st) {
+FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
+                          int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
+                          const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
+                          int nmcs, bool hou, bool meas) {
   FusedArgs A;
   A.g = g;
   A.spins = spins;
@@ -406,19 +449,43 @@ hipError_t launch_mcs_fused(const Geo& g, const FusedLayout& lay, void* spins, c
   A.meas = meas ? 1 : 0;
   A.magicNW = (uint32_t)((0x100000000ull + (uint64_t)g.NW - 1) / (uint64_t)g.NW);
   A.lay = lay;
-  const size_t bytes = (size_t)lay.words * 4;
-  const dim3 grid((unsigned)g.S), block(1024);
-  if (g.d == 3) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_mcs<3>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mcs<3>, grid, block, bytes, st, A);
+  return A;
+}
+
+template <typename K>
+static hipError_t lds_attr(K kernel, size_t bytes) {
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+hipError_t launch_mcs_fused(const FusedArgs& A, int nsets, hipStream_t st) {
+  const size_t bytes = (size_t)A.lay.words * 4;
+  const dim3 grid((unsigned)(A.g.S * (3 - nsets))), block(1024);
+  if (A.g.d == 3) {
+    if (hipError_t e = lds_attr(k_mcs<3>, bytes)) return e;
+    hipLaunchKernelGGL(k_mcs<3>, grid, block, bytes, st, A, nsets);
   } else {
-    hipError_t e = hipFuncSetAttribute((const void*)k_mcs<2>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mcs<2>, grid, block, bytes, st, A);
+    if (hipError_t e = lds_attr(k_mcs<2>, bytes)) return e;
+    hipLaunchKernelGGL(k_mcs<2>, grid, block, bytes, st, A, nsets);
   }
+  return hipGetLastError();
+}
+
+hipError_t prepare_batch(int d, size_t lds_bytes) {
+  return d == 3 ? lds_attr(k_batch<3>, lds_bytes) : lds_attr(k_batch<2>, lds_bytes);
+}
+
+hipError_t launch_batch(int d, const FusedArgs* jobs, int njobs, const BatchItem* items, int nitems,
+                        uint32_t* queue, int blocks, int threads, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, queue);
+  if (d == 3)
+    hipLaunchKernelGGL(k_batch<3>, dim3(blocks), dim3(threads), lds_bytes, st, jobs, items, nitems,
+                       queue);
+  else
+    hipLaunchKernelGGL(k_batch<2>, dim3(blocks), dim3(threads), lds_bytes, st, jobs, items, nitems,
+                       queue);
+  hipLaunchKernelGGL(k_batch_advance, dim3((unsigned)((njobs + 255) / 256)), dim3(256), 0, st, jobs,
+                     njobs);
   return hipGetLastError();
 }
 

@@ -48,15 +48,49 @@ struct FusedLayout {
   int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, Qs, Cs, hcnt, hdelta, PC, words;
 };
 
-// Plans the LDS of the fused kernel; false if one sample does not fit.
-bool fused_plan(const Geo& g, bool houdayer, FusedLayout& lay);
+// Everything one fused workgroup needs about a job, for nmcs steps.
+struct FusedArgs {
+  Geo g;
+  void* spins;
+  const uint32_t* jw;
+  int32_t* E;
+  int32_t* sot;
+  int32_t* tos;
+  const uint32_t* thr;
+  const uint32_t* thrpt;
+  int M;
+  int64_t* mom;
+  const DevCounters* ctr;
+  int nmcs, hou, meas;
+  uint32_t magicNW;  // item / NW
+  FusedLayout lay;
+};
 
-// nmcs whole Monte Carlo steps with every sample resident in LDS; the
-// counters are read, not advanced (enqueue launch_advance afterwards).
-hipError_t launch_mcs_fused(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
-                            int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
-                            const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
-                            int nmcs, bool houdayer, bool measure, hipStream_t st);
+// One work item of the persistent batch kernel: replica sets
+// [c_lo, c_lo + nsets) of sample `sample` of job `job`.
+struct BatchItem {
+  int job, sample, c_lo, nsets;
+};
+
+// Plans the LDS of a fused workgroup holding `nsets` replica sets of one
+// sample (`waves` wavefronts); false if it does not fit in 160 KiB.
+bool fused_plan(const Geo& g, bool houdayer, int nsets, int waves, FusedLayout& lay);
+
+FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
+                          int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
+                          const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
+                          int nmcs, bool houdayer, bool measure);
+
+// A.nmcs whole Monte Carlo steps of every sample (one or two workgroups per
+// sample, 1024 threads); the counters are read, not advanced (enqueue
+// launch_advance afterwards).
+hipError_t launch_mcs_fused(const FusedArgs& A, int nsets, hipStream_t st);
+
+// Persistent batch: resets the queue, runs every item to its job's nmcs, then
+// advances each job's counters.  `jobs` and `items` are device arrays.
+hipError_t prepare_batch(int d, size_t lds_bytes);
+hipError_t launch_batch(int d, const FusedArgs* jobs, int njobs, const BatchItem* items, int nitems,
+                        uint32_t* queue, int blocks, int threads, size_t lds_bytes, hipStream_t st);
 
 // Launch shape of the sweep kernel (threads per lattice T, lattices per block).
 void sweep_shape(const Geo& g, int& T, int& LPB, int& threads, size_t& lds);

@@ -10,25 +10,27 @@
 #include <string>
 #include <vector>
 
+#include "job.h"
 #include "kernels.h"
 #include "pt.h"
-
-#define PT_API extern "C" __attribute__((visibility("default")))
 
 using namespace ptsg;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+int pt_fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+const char* pt_error_text() { return g_err.c_str(); }
+
+namespace {
 
 void* (*g_alloc)(size_t, void*) = nullptr;
 void (*g_free)(void*, void*) = nullptr;
 void* g_ctx = nullptr;
-
-int fail(int code, const std::string& msg) {
-  g_err = msg;
-  return code;
-}
 
 // Acceptance probability p -> 32-bit threshold floor(2^32 p), clamped to
 // [0, 2^32 - 1]; a uniform 32-bit word r accepts iff r < threshold.
@@ -41,60 +43,12 @@ uint32_t threshold_u32(double p) {
 
 }  // namespace
 
-struct pt_job {
-  Geo g{};
-  hipStream_t stream = nullptr;
-  void* spins = nullptr;     // int8 [S][2NT][N] or u32 [S][2NT][2][NW]
-  uint32_t* jw = nullptr;    // [S][2][2d][NW]
-  int32_t* E = nullptr;      // [S][2NT]
-  int32_t* sot = nullptr;    // [S][2][NT]
-  int32_t* tos = nullptr;    // [S][2][NT]
-  uint32_t* thr = nullptr;   // [NT][4]
-  uint32_t* thrpt = nullptr; // [NT-1][M]
-  int M = 0;
-  DevCounters* ctr = nullptr;
-  int64_t* mom = nullptr;    // [S][NT][8]
-  FusedLayout plan[2];       // fused-step LDS plans without / with Houdayer
-  bool fused_ok[2] = {false, false};
-  bool poisoned = false;
-  std::vector<void*> allocs;
-  void* (*alloc_fn)(size_t, void*) = nullptr;
-  void (*free_fn)(void*, void*) = nullptr;
-  void* alloc_ctx = nullptr;
-
-  size_t spin_bytes() const {
-    const size_t lat = (size_t)g.S * g.nslot;
-    return g.layout == kLayoutPacked ? lat * 2 * g.NW * sizeof(uint32_t) : lat * g.N;
-  }
-
-  void* dalloc(size_t bytes) {
-    void* p = nullptr;
-    if (bytes == 0) bytes = 4;
-    if (alloc_fn) {
-      p = alloc_fn(bytes, alloc_ctx);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-    }
-    if (p) allocs.push_back(p);
-    return p;
-  }
-  void release() {
-    for (void* p : allocs) {
-      if (free_fn)
-        free_fn(p, alloc_ctx);
-      else
-        (void)hipFree(p);
-    }
-    allocs.clear();
-  }
-};
 
 namespace {
 
 int device_error(pt_job* job, hipError_t e, const char* where) {
   if (job) job->poisoned = true;
-  return fail(PT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+  return pt_fail(PT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
 #define PT_HIP(job, expr)                                      \
@@ -104,8 +58,8 @@ int device_error(pt_job* job, hipError_t e, const char* where) {
   } while (0)
 
 int check_job(pt_job* job) {
-  if (!job) return fail(PT_EINVAL, "null job handle");
-  if (job->poisoned) return fail(PT_ESTATE, "job is poisoned by an earlier device error");
+  if (!job) return pt_fail(PT_EINVAL, "null job handle");
+  if (job->poisoned) return pt_fail(PT_ESTATE, "job is poisoned by an earlier device error");
   return PT_OK;
 }
 
@@ -161,12 +115,12 @@ void unpack_host(const Geo& g, const uint32_t* in, int8_t* out) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-PT_API const char* pt_last_error(void) { return g_err.c_str(); }
+PT_API const char* pt_last_error(void) { return pt_error_text(); }
 PT_API const char* pt_version(void) { return "ptsg-gfx950 0.1"; }
 
 PT_API int pt_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx) {
   if ((alloc == nullptr) != (free_ == nullptr))
-    return fail(PT_EINVAL, "allocator and free hooks must both be set or both be NULL");
+    return pt_fail(PT_EINVAL, "allocator and free hooks must both be set or both be NULL");
   g_alloc = alloc;
   g_free = free_;
   g_ctx = ctx;
@@ -176,28 +130,28 @@ PT_API int pt_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, 
 PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
                       const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags) {
   g_err.clear();
-  if (!out || !couplings || !betas) return fail(PT_EINVAL, "null pointer argument");
-  if (dim != 2 && dim != 3) return fail(PT_EINVAL, "dim must be 2 or 3");
-  if (L < 4 || L > 64 || (L & 1)) return fail(PT_EINVAL, "L must be even and in [4, 64]");
-  if (samples < 1 || samples >= (1 << 28)) return fail(PT_EINVAL, "samples must be in [1, 2^28)");
-  if (replicas < 2 || replicas > 4096) return fail(PT_EINVAL, "replicas must be in [2, 4096]");
-  if (flags != PT_LAYOUT_INT8 && flags != PT_LAYOUT_PACKED) return fail(PT_EINVAL, "unknown flags");
+  if (!out || !couplings || !betas) return pt_fail(PT_EINVAL, "null pointer argument");
+  if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
+  if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
+  if (samples < 1 || samples >= (1 << 28)) return pt_fail(PT_EINVAL, "samples must be in [1, 2^28)");
+  if (replicas < 2 || replicas > 4096) return pt_fail(PT_EINVAL, "replicas must be in [2, 4096]");
+  if (flags != PT_LAYOUT_INT8 && flags != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown flags");
   for (int k = 0; k < replicas; ++k) {
     if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
-      return fail(PT_EINVAL, "betas must be finite and > 0");
+      return pt_fail(PT_EINVAL, "betas must be finite and > 0");
     if (k > 0 && !(betas[k] < betas[k - 1]))
-      return fail(PT_EINVAL, "betas must be strictly decreasing (index 0 = coldest)");
+      return pt_fail(PT_EINVAL, "betas must be strictly decreasing (index 0 = coldest)");
   }
   const long N = (dim == 3) ? (long)L * L * L : (long)L * L;
   const long ncoup = (long)samples * dim * N;
   for (long i = 0; i < ncoup; ++i)
-    if (couplings[i] != 1 && couplings[i] != -1) return fail(PT_EINVAL, "couplings must be +1 or -1");
+    if (couplings[i] != 1 && couplings[i] != -1) return pt_fail(PT_EINVAL, "couplings must be +1 or -1");
   const long nlat = (long)samples * 2 * replicas;
   if (nlat > 0x7FFFFFFFL || (long)samples * replicas > 0x7FFFFFFFL)
-    return fail(PT_EINVAL, "too many lattices for one job");
+    return pt_fail(PT_EINVAL, "too many lattices for one job");
 
   pt_job* job = new (std::nothrow) pt_job();
-  if (!job) return fail(PT_ENOMEM, "host allocation failed");
+  if (!job) return pt_fail(PT_ENOMEM, "host allocation failed");
   job->alloc_fn = g_alloc;
   job->free_fn = g_free;
   job->alloc_ctx = g_ctx;
@@ -254,8 +208,9 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
       thrpt[(size_t)k * M + m] = threshold_u32(std::exp(-(db * (double)(2 * m))));
   }
   job->M = M;
-  job->fused_ok[0] = fused_plan(g, false, job->plan[0]);
-  job->fused_ok[1] = fused_plan(g, true, job->plan[1]);
+  job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0]);
+  job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1]);
+  job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2]);
 
   const size_t maps = sizeof(int32_t) * (size_t)samples * 2 * replicas;
   job->spins = job->dalloc(job->spin_bytes());
@@ -272,7 +227,7 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
       !job->ctr || !job->mom || !J8) {
     job->release();
     delete job;
-    return fail(PT_ENOMEM, "device allocation failed");
+    return pt_fail(PT_ENOMEM, "device allocation failed");
   }
   std::vector<int32_t> ident((size_t)samples * 2 * replicas);
   for (size_t i = 0; i < ident.size(); ++i) ident[i] = (int32_t)(i % replicas);
@@ -298,7 +253,7 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
     std::string msg = std::string("pt_init: ") + hipGetErrorString(e);
     job->release();
     delete job;
-    return fail(PT_EDEVICE, msg);
+    return pt_fail(PT_EDEVICE, msg);
   }
   *out = job;
   return PT_OK;
@@ -310,7 +265,7 @@ PT_API int pt_init(pt_job** out, int32_t samples, int32_t replicas, int32_t L, i
 }
 
 PT_API int pt_destroy(pt_job* job) {
-  if (!job) return fail(PT_EINVAL, "null job handle");
+  if (!job) return pt_fail(PT_EINVAL, "null job handle");
   (void)hipStreamSynchronize(job->stream);
   (void)hipGetLastError();
   job->release();
@@ -329,7 +284,7 @@ PT_API int pt_set_stream(pt_job* job, void* hip_stream) {
 // ---------------------------------------------------------------------------
 PT_API int pt_sweep(pt_job* job, int32_t n) {
   if (int rc = check_job(job)) return rc;
-  if (n < 0) return fail(PT_EINVAL, "n must be >= 0");
+  if (n < 0) return pt_fail(PT_EINVAL, "n must be >= 0");
   const int chunk = 1000;
   for (int done = 0; done < n; done += chunk) {
     const int m = (n - done) < chunk ? (n - done) : chunk;
@@ -364,19 +319,32 @@ PT_API int pt_measure(pt_job* job) {
 
 PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   if (int rc = check_job(job)) return rc;
-  if (n < 0) return fail(PT_EINVAL, "n must be >= 0");
+  if (n < 0) return pt_fail(PT_EINVAL, "n must be >= 0");
   if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
-    return fail(PT_EINVAL, "unknown flags");
+    return pt_fail(PT_EINVAL, "unknown flags");
   const Geo& g = job->g;
   hipStream_t st = job->stream;
   const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
-  if (!(flags & PT_MCS_PLAIN) && job->fused_ok[hou ? 1 : 0]) {
+  // fused: both sets per workgroup if they fit (needed for Houdayer and the
+  // overlap), otherwise one set per workgroup for sweep + exchange
+  int mode = -1;
+  if (!(flags & PT_MCS_PLAIN)) {
+    if (hou)
+      mode = job->fused_ok[1] ? 1 : -1;
+    else if (job->fused_ok[0])
+      mode = 0;
+    else if (!meas && job->fused_ok[2])
+      mode = 2;
+  }
+  if (mode >= 0) {
+    const int nsets = mode == 2 ? 1 : 2;
     const int chunk = 500;
     for (int done = 0; done < n; done += chunk) {
       const int m = (n - done) < chunk ? (n - done) : chunk;
-      PT_HIP(job, launch_mcs_fused(g, job->plan[hou ? 1 : 0], job->spins, job->jw, job->E, job->sot,
-                                   job->tos, job->thr, job->thrpt, job->M, job->mom, job->ctr, m,
-                                   hou, meas, st));
+      const FusedArgs A = make_fused_args(g, job->plan[mode], job->spins, job->jw, job->E, job->sot,
+                                          job->tos, job->thr, job->thrpt, job->M, job->mom, job->ctr,
+                                          m, hou, meas);
+      PT_HIP(job, launch_mcs_fused(A, nsets, st));
       PT_HIP(job, launch_advance(job->ctr,
                                  CounterStep{(uint32_t)m, (uint32_t)m, hou ? (uint32_t)m : 0u,
                                              meas ? (uint32_t)m : 0u},
@@ -401,7 +369,7 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
 // ---------------------------------------------------------------------------
 PT_API int pt_get_counters(pt_job* job, uint64_t* out) {
   if (int rc = check_job(job)) return rc;
-  if (!out) return fail(PT_EINVAL, "null output");
+  if (!out) return pt_fail(PT_EINVAL, "null output");
   DevCounters c;
   PT_HIP(job, hipMemcpyAsync(&c, job->ctr, sizeof(c), hipMemcpyDeviceToHost, job->stream));
   PT_HIP(job, hipStreamSynchronize(job->stream));
@@ -414,7 +382,7 @@ PT_API int pt_get_counters(pt_job* job, uint64_t* out) {
 
 PT_API int pt_get_spins(pt_job* job, int8_t* out) {
   if (int rc = check_job(job)) return rc;
-  if (!out) return fail(PT_EINVAL, "null output");
+  if (!out) return pt_fail(PT_EINVAL, "null output");
   const Geo& g = job->g;
   if (g.layout == kLayoutPacked) {
     std::vector<uint32_t> tmp(job->spin_bytes() / sizeof(uint32_t));
@@ -431,11 +399,11 @@ PT_API int pt_get_spins(pt_job* job, int8_t* out) {
 
 PT_API int pt_set_spins(pt_job* job, const int8_t* in) {
   if (int rc = check_job(job)) return rc;
-  if (!in) return fail(PT_EINVAL, "null input");
+  if (!in) return pt_fail(PT_EINVAL, "null input");
   const Geo& g = job->g;
   const size_t n = (size_t)g.S * g.nslot * g.N;
   for (size_t i = 0; i < n; ++i)
-    if (in[i] != 1 && in[i] != -1) return fail(PT_EINVAL, "spins must be +1 or -1");
+    if (in[i] != 1 && in[i] != -1) return pt_fail(PT_EINVAL, "spins must be +1 or -1");
   if (g.layout == kLayoutPacked) {
     std::vector<uint32_t> tmp(job->spin_bytes() / sizeof(uint32_t));
     pack_host(g, in, tmp.data());
@@ -453,7 +421,7 @@ PT_API int pt_set_spins(pt_job* job, const int8_t* in) {
 
 PT_API int pt_get_energies(pt_job* job, int32_t* out) {
   if (int rc = check_job(job)) return rc;
-  if (!out) return fail(PT_EINVAL, "null output");
+  if (!out) return pt_fail(PT_EINVAL, "null output");
   const size_t n = (size_t)job->g.S * job->g.nslot;
   PT_HIP(job, hipMemcpyAsync(out, job->E, sizeof(int32_t) * n, hipMemcpyDeviceToHost, job->stream));
   PT_HIP(job, hipStreamSynchronize(job->stream));
@@ -473,7 +441,7 @@ PT_API int pt_get_maps(pt_job* job, int32_t* slot_of_temp, int32_t* temp_of_slot
 
 PT_API int pt_get_moments(pt_job* job, int64_t* out) {
   if (int rc = check_job(job)) return rc;
-  if (!out) return fail(PT_EINVAL, "null output");
+  if (!out) return pt_fail(PT_EINVAL, "null output");
   const size_t n = (size_t)job->g.S * job->g.NT;
   std::vector<int64_t> m(8 * n);
   PT_HIP(job, hipMemcpyAsync(m.data(), job->mom, sizeof(int64_t) * m.size(), hipMemcpyDeviceToHost,
@@ -559,13 +527,13 @@ size_t state_size(const pt_job* job) {
 
 PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   if (int rc = check_job(job)) return rc;
-  if (!len) return fail(PT_EINVAL, "null length");
+  if (!len) return pt_fail(PT_EINVAL, "null length");
   const size_t need = state_size(job);
   if (!buf) {
     *len = need;
     return PT_OK;
   }
-  if (*len < need) return fail(PT_EINVAL, "state buffer too small");
+  if (*len < need) return pt_fail(PT_EINVAL, "state buffer too small");
   const Geo& g = job->g;
   char* p = static_cast<char*>(buf);
   StateHeader h{kStateMagic, g.S, g.NT, g.L, g.d, g.layout, 0, (uint64_t)job->spin_bytes()};
@@ -592,14 +560,14 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
 
 PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
   if (int rc = check_job(job)) return rc;
-  if (!buf) return fail(PT_EINVAL, "null state buffer");
-  if (len != state_size(job)) return fail(PT_EINVAL, "state size does not match this job");
+  if (!buf) return pt_fail(PT_EINVAL, "null state buffer");
+  if (len != state_size(job)) return pt_fail(PT_EINVAL, "state size does not match this job");
   const Geo& g = job->g;
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (h.magic != kStateMagic || h.S != g.S || h.NT != g.NT || h.L != g.L || h.d != g.d ||
       h.layout != g.layout || h.spin_bytes != job->spin_bytes())
-    return fail(PT_EINVAL, "state was taken from a job of another shape or layout");
+    return pt_fail(PT_EINVAL, "state was taken from a job of another shape or layout");
   const char* p = static_cast<const char*>(buf) + sizeof(h);
   const size_t lat = (size_t)g.S * g.nslot, maps = sizeof(int32_t) * (size_t)g.S * 2 * g.NT;
   hipStream_t st = job->stream;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libptsg.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
 PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
-PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN = 1, 2, 4
+PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE"}
 
@@ -29,6 +29,8 @@ EXPORTS = [
     "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_state", "pt_set_state",
     "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
+    "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
+    "pt_batch_get_config", "pt_batch_set_config", "pt_batch_destroy",
 ]
 
 
@@ -62,6 +64,10 @@ def lib():
             "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
             "pt_get_state": [P, P, C.POINTER(C.c_size_t)], "pt_set_state": [P, P, C.c_size_t],
             "pt_set_stream": [P, P], "pt_set_allocator": [_ALLOC, _FREE, P],
+            "pt_batch_create": [P, I32, C.POINTER(P)], "pt_batch_set_stream": [P, P],
+            "pt_batch_run": [P, I32, U32], "pt_batch_tune": [P, I32, U32, C.c_char_p],
+            "pt_batch_get_config": [P, P], "pt_batch_set_config": [P, I32, I32, I32],
+            "pt_batch_destroy": [P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -274,3 +280,65 @@ def pt_get_state(job: Job) -> bytes:
 def pt_set_state(job: Job, state: bytes) -> None:
     buf = C.create_string_buffer(state, len(state))
     _check(lib().pt_set_state(job.h, C.cast(buf, C.c_void_p), len(state)))
+
+
+# --------------------------------------------------------------------------
+# batched form
+# --------------------------------------------------------------------------
+class Batch:
+    """Owning handle of a pt_batch; keeps its jobs alive."""
+
+    def __init__(self, handle, jobs):
+        self.h = handle
+        self.jobs = list(jobs)
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().pt_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def pt_batch_create(jobs, stream=None) -> Batch:
+    arr = (C.c_void_p * len(jobs))(*[j.h for j in jobs])
+    h = C.c_void_p()
+    _check(lib().pt_batch_create(arr, len(jobs), C.byref(h)))
+    b = Batch(h, jobs)
+    if stream is not None:
+        raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        _check(lib().pt_batch_set_stream(b.h, C.c_void_p(raw)))
+    return b
+
+
+def _flags(houdayer, measure, graph=False):
+    return ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
+            | (PT_BATCH_GRAPH if graph else 0))
+
+
+def pt_batch_run(batch: Batch, mcs: int, houdayer=False, measure=False, graph=False) -> None:
+    _check(lib().pt_batch_run(batch.h, int(mcs), _flags(houdayer, measure, graph)))
+
+
+def pt_batch_tune(batch: Batch, trial_mcs: int = 3, houdayer=False, measure=False,
+                  cache_path: str | None = None) -> tuple:
+    path = cache_path.encode() if cache_path else None
+    _check(lib().pt_batch_tune(batch.h, int(trial_mcs), _flags(houdayer, measure), path))
+    return pt_batch_get_config(batch)
+
+
+def pt_batch_get_config(batch: Batch) -> tuple:
+    out = np.zeros(3, np.int32)
+    _check(lib().pt_batch_get_config(batch.h, _p(out)))
+    return tuple(int(v) for v in out)
+
+
+def pt_batch_set_config(batch: Batch, threads: int, sets: int, order: int) -> None:
+    _check(lib().pt_batch_set_config(batch.h, int(threads), int(sets), int(order)))
+
+
+def pt_batch_destroy(batch: Batch) -> None:
+    if batch.h:
+        _check(lib().pt_batch_destroy(batch.h))
+        batch.h = None

@@ -1,0 +1,154 @@
+"""GPU tests of the batched form: jobs of mixed shape in one persistent launch
+must reproduce, bit for bit, each job run alone and the CPU oracle."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_04621_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2003_04621_amd import pt as _pt
+    _pt.lib()
+    return _pt
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def state(pt, job):
+    return (pt.pt_get_spins(job), pt.pt_get_energies(job), *pt.pt_get_maps(job),
+            tuple(sorted(pt.pt_get_counters(job).items())),
+            {k: np.asarray(v).copy() for k, v in pt.pt_get_moments(job).items()})
+
+
+def same_state(a, b):
+    for x, y in zip(a[:4], b[:4]):
+        if not (np.asarray(x) == np.asarray(y)).all():
+            return False
+    if a[4] != b[4]:
+        return False
+    return all((a[5][k] == b[5][k]).all() for k in a[5])
+
+
+def matches_oracle(pt, job, ref):
+    assert (pt.pt_get_spins(job) == ref.spins()).all()
+    assert (pt.pt_get_energies(job) == ref.energies()).all()
+    for a, b in zip(pt.pt_get_maps(job), ref.maps()):
+        assert (a == b).all()
+    assert pt.pt_get_counters(job) == ref.counters()
+    gm, rm = pt.pt_get_moments(job), ref.moments()
+    for k in rm:
+        assert (np.asarray(gm[k]) == np.asarray(rm[k]).astype(np.asarray(gm[k]).dtype)).all(), k
+
+
+SHAPES_3D = [  # (L, samples, replicas, layout)
+    (4, 2, 3, 0), (6, 1, 4, 1), (8, 3, 5, 0), (12, 2, 3, 1), (16, 1, 6, 0), (8, 1, 2, 1),
+]
+
+
+def make_jobs(pt, shapes, dim, seed0=10):
+    jobs, refs = [], []
+    for n, (L, S, NT, layout) in enumerate(shapes):
+        J = W.couplings_pm_j(S, L, dim, seed0 + n)
+        b = W.geometric_betas(0.5, 2.2, NT)
+        jobs.append(pt.pt_init(S, NT, L, dim, J, b, 1000 + n, layout=layout))
+        refs.append(oracle.OracleJob(S, NT, L, dim, J, b, 1000 + n))
+    return jobs, refs
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle_3d(pt, graph):
+    say(f"batch 3d graph={graph}")
+    jobs, refs = make_jobs(pt, SHAPES_3D, 3)
+    batch = pt.pt_batch_create(jobs)
+    for rnd in range(3):
+        pt.pt_batch_run(batch, 4, measure=True, graph=graph)
+        for r in refs:
+            r.mcs(4, measure=True)
+        for j, r in zip(jobs, refs):
+            matches_oracle(pt, j, r)
+    pt.pt_batch_destroy(batch)
+
+
+def test_batch_houdayer_2d(pt):
+    shapes = [(16, 2, 4, 0), (8, 3, 3, 1), (64, 1, 3, 0), (6, 2, 2, 1)]
+    jobs, refs = make_jobs(pt, shapes, 2, seed0=50)
+    batch = pt.pt_batch_create(jobs)
+    pt.pt_batch_run(batch, 5, houdayer=True, measure=True, graph=True)
+    pt.pt_batch_run(batch, 5, houdayer=True, measure=True, graph=True)
+    for r in refs:
+        r.mcs(10, houdayer=True, measure=True)
+    for j, r in zip(jobs, refs):
+        matches_oracle(pt, j, r)
+
+
+@pytest.mark.parametrize("cfg", [(1024, 1, 0), (512, 2, 1), (256, 1, 1), (256, 2, 0)])
+def test_batch_configs_agree(pt, cfg):
+    say(f"batch config {cfg}")
+    jobs, refs = make_jobs(pt, SHAPES_3D, 3, seed0=70)
+    batch = pt.pt_batch_create(jobs)
+    pt.pt_batch_set_config(batch, *cfg)
+    pt.pt_batch_run(batch, 6)
+    for r in refs:
+        r.mcs(6)
+    for j, r in zip(jobs, refs):
+        matches_oracle(pt, j, r)
+
+
+def test_batch_equals_alone(pt):
+    """The same job gives the same result alone and inside a mixed batch."""
+    shapes = [(8, 2, 4, 0), (16, 1, 3, 1), (12, 3, 5, 0)]
+    jobs, _ = make_jobs(pt, shapes, 3, seed0=90)
+    alone, _ = make_jobs(pt, shapes, 3, seed0=90)
+    batch = pt.pt_batch_create(jobs)
+    pt.pt_batch_run(batch, 7, measure=True, graph=True)
+    for a in alone:
+        pt.pt_mcs(a, 7, measure=True)
+    for j, a in zip(jobs, alone):
+        assert same_state(state(pt, j), state(pt, a))
+
+
+def test_tuner_restores_state_and_caches(pt):
+    jobs, refs = make_jobs(pt, SHAPES_3D, 3, seed0=110)
+    batch = pt.pt_batch_create(jobs)
+    pt.pt_batch_run(batch, 2)
+    for r in refs:
+        r.mcs(2)
+    before = [state(pt, j) for j in jobs]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.jsonl")
+        cfg = pt.pt_batch_tune(batch, 2, cache_path=path)
+        assert cfg[0] in (256, 512, 1024) and cfg[1] in (1, 2) and cfg[2] in (0, 1)
+        assert os.path.exists(path) and "threads" in open(path).read()
+        for j, s0 in zip(jobs, before):
+            assert same_state(state(pt, j), s0)
+        pt.pt_batch_set_config(batch, 256, 1, 1)
+        assert pt.pt_batch_tune(batch, 2, cache_path=path) == cfg   # cache hit
+    pt.pt_batch_run(batch, 3, graph=True)
+    for r in refs:
+        r.mcs(3)
+    for j, r in zip(jobs, refs):
+        matches_oracle(pt, j, r)
+
+
+def test_batch_rejects_oversized_and_mixed_dims(pt):
+    big = pt.pt_init(1, 48, 64, 3, W.couplings_pm_j(1, 64, 3, 1), W.geometric_betas(0.9, 2, 48), 1)
+    batch = pt.pt_batch_create([big])
+    with pytest.raises(pt.PTError):
+        pt.pt_batch_run(batch, 1)
+    j2 = pt.pt_init(1, 2, 8, 2, W.couplings_pm_j(1, 8, 2, 1), np.array([1.0, 0.5]), 1)
+    j3 = pt.pt_init(1, 2, 8, 3, W.couplings_pm_j(1, 8, 3, 1), np.array([1.0, 0.5]), 1)
+    with pytest.raises(pt.PTError):
+        pt.pt_batch_create([j2, j3])
+    with pytest.raises(pt.PTError):
+        pt.pt_batch_create([j2, j2])
