@@ -68,6 +68,27 @@ extern "C" {
 
 typedef struct pt_job pt_job;
 typedef struct pt_batch pt_batch;
+typedef struct pt_server pt_server;
+
+/* A request to the server: one job (arrays are copied at submission). */
+typedef struct {
+  int32_t dim, L, replicas, samples; /* as pt_init */
+  const double *betas;               /* [replicas] */
+  const int8_t *couplings;           /* [samples][dim][L^dim] */
+  uint64_t seed;
+  int32_t sweeps;                    /* Monte Carlo steps in total */
+  int32_t burn_in;                   /* steps before the first measurement */
+  uint32_t flags;                    /* PT_MCS_HOUDAYER or 0 */
+  uint32_t layout;                   /* PT_LAYOUT_INT8 or PT_LAYOUT_PACKED */
+} pt_request;
+
+/* The outcome of a request; times in seconds since pt_server_start. */
+typedef struct {
+  int32_t status; /* PT_OK, or the error that ended the request */
+  int32_t reserved;
+  int64_t n_meas;
+  double t_submit, t_admit, t_done;
+} pt_result;
 
 /* Creates a job: copies the couplings in, draws the initial spins (one
  * Philox word per site), sets the maps to the identity, computes every
@@ -196,6 +217,30 @@ int pt_batch_tune(pt_batch *b, int32_t trial_mcs, uint32_t flags, const char *ca
 int pt_batch_get_config(pt_batch *b, int32_t *cfg3);
 int pt_batch_set_config(pt_batch *b, int32_t threads, int32_t sets, int32_t order);
 int pt_batch_destroy(pt_batch *b);
+
+/* ---- served form ----------------------------------------------------------- */
+/* Starts a request server on the current device with its own worker thread
+ * and streams.  Requests are admitted in arrival order while the device bytes
+ * of the admitted jobs stay within hbm_budget (a request that alone exceeds
+ * it fails with PT_ENOMEM); admitted jobs stay resident and advance together,
+ * steps_per_round Monte Carlo steps per round in one persistent batch launch
+ * (continuous batching: admissions and completions happen between rounds).
+ * Each job measures every step after its burn-in; on completion its
+ * disorder-averaged observables are kept for pt_server_poll and its memory is
+ * released.  Device memory comes from hipMalloc, not the allocator hooks. */
+int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server **out);
+/* Copies the request and queues it; *ticket identifies it.  PT_EINVAL for
+ * arguments pt_init would reject (or burn_in outside [0, sweeps]). */
+int pt_server_submit(pt_server *s, const pt_request *req, uint64_t *ticket);
+/* Returns 1 while the request is queued or running; PT_OK once it finished,
+ * filling *out and (if not NULL) disorder [replicas][6] as pt_observables,
+ * after which the ticket is forgotten; PT_EINVAL for an unknown ticket. */
+int pt_server_poll(pt_server *s, uint64_t ticket, pt_result *out, double *disorder);
+/* out[8] = {attempted flips completed, busy seconds, rounds, admitted,
+ *           completed, peak admitted bytes, peak concurrent jobs, uptime s} */
+int pt_server_stats(pt_server *s, double *out);
+/* Finishes every queued and running request, then stops the server. */
+int pt_server_stop(pt_server *s);
 
 /* ---- plumbing ------------------------------------------------------------ */
 /* Makes the job enqueue on a HIP stream (hipStream_t; NULL = null stream). */

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libptsg.so")
-SOURCES = ["runtime.hip", "batch.hip", "sweep.hip", "steps.hip", "houdayer.hip", "fused.hip"]
+SOURCES = ["runtime.hip", "batch.hip", "server.hip", "sweep.hip", "steps.hip", "houdayer.hip", "fused.hip"]
 
 # Packed FP32 instructions are disabled on purpose (no float code needs them).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

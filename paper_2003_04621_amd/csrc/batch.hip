@@ -71,16 +71,17 @@ int job_mode(const pt_job* j, uint32_t flags, const BatchConfig& cfg) {
   return j->fused_ok[2] ? 2 : (j->fused_ok[0] ? 0 : -1);
 }
 
-int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
-  if (b->built && b->built_mcs == mcs && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg))
-    return PT_OK;
-  const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+// Work list for per-job step counts and flags (jobs with 0 steps get no item).
+int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vector<uint32_t>& jflags) {
   std::vector<FusedArgs> hj;
   std::vector<BatchItem> hi;
   std::vector<double> cost;
   size_t lds_words = 0;
   for (size_t jx = 0; jx < b->jobs.size(); ++jx) {
     pt_job* j = b->jobs[jx];
+    const uint32_t flags = jflags[jx];
+    const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+    const int mcs = steps[jx];
     const int mode = job_mode(j, flags, b->cfg);
     if (mode < 0)
       return pt_fail(PT_EINVAL, "pt_batch_run: job " + std::to_string(jx) +
@@ -89,7 +90,8 @@ int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
     hj.push_back(make_fused_args(j->g, j->plan[mode], j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
                                  j->thrpt, j->M, j->mom, j->ctr, mcs, hou, meas));
     lds_words = std::max(lds_words, (size_t)j->plan[mode].words);
-    const double c = (double)nsets * j->g.NT * j->g.N;
+    if (mcs <= 0) continue;
+    const double c = (double)nsets * j->g.NT * j->g.N * mcs;
     for (int s = 0; s < j->g.S; ++s)
       for (int c_lo = 0; c_lo < 2; c_lo += nsets) {
         hi.push_back(BatchItem{(int)jx, s, c_lo, nsets});
@@ -125,7 +127,7 @@ int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
   }
   e = hipMemcpyAsync(b->d_jobs, hj.data(), sizeof(FusedArgs) * hj.size(), hipMemcpyHostToDevice,
                      b->stream);
-  if (e == hipSuccess)
+  if (e == hipSuccess && !hi.empty())
     e = hipMemcpyAsync(b->d_items, hi.data(), sizeof(BatchItem) * hi.size(), hipMemcpyHostToDevice,
                        b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -140,15 +142,26 @@ int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
   const int by_waves = std::max(1, 24 / (b->cfg.threads / 64));  // <= 6 waves per SIMD at this VGPR use
   per_cu = std::max(1, std::min(by_lds, by_waves));
   b->blocks = std::max(1, std::min(b->ncu * per_cu, b->nitems));
-  b->built = true;
-  b->built_mcs = mcs;
-  b->built_flags = flags;
-  b->built_cfg = b->cfg;
+  b->built = false;
   drop_graph(b);
   return PT_OK;
 }
 
+int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
+  if (b->built && b->built_mcs == mcs && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg))
+    return PT_OK;
+  const std::vector<int> steps(b->jobs.size(), mcs);
+  const std::vector<uint32_t> fl(b->jobs.size(), flags);
+  if (int rc = build_worklist_ex(b, steps, fl)) return rc;
+  b->built = true;
+  b->built_mcs = mcs;
+  b->built_flags = flags;
+  b->built_cfg = b->cfg;
+  return PT_OK;
+}
+
 int run_once(pt_batch* b, bool use_graph) {
+  if (b->nitems == 0) return PT_OK;
   if (!use_graph) {
     const hipError_t e = launch_batch(b->d, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems,
                                       b->d_queue, b->blocks, b->cfg.threads, b->lds_bytes, b->stream);
@@ -268,6 +281,41 @@ void cache_store(const char* path, const std::string& key, const BatchConfig& cf
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Internal entry points for the request server: one launch over a changing
+// set of resident jobs with per-job step counts and flags.
+pt_batch* batch_new(hipStream_t st) {
+  pt_batch* b = new (std::nothrow) pt_batch();
+  if (!b) return nullptr;
+  b->stream = st;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    b->ncu = ncu;
+  (void)hipGetLastError();
+  return b;
+}
+
+int batch_round(pt_batch* b, const std::vector<pt_job*>& jobs, const std::vector<int>& steps,
+                const std::vector<uint32_t>& flags) {
+  if (jobs.empty()) return PT_OK;
+  b->jobs = jobs;
+  b->d = jobs[0]->g.d;
+  if (int rc = build_worklist_ex(b, steps, flags)) return rc;
+  return run_once(b, false);
+}
+
+void batch_free(pt_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  (void)hipGetLastError();
+  delete b;
+}
 
 // ---------------------------------------------------------------------------
 PT_API int pt_batch_create(pt_job* const* jobs, int32_t n, pt_batch** out) {

@@ -64,3 +64,21 @@ struct pt_job {
     allocs.clear();
   }
 };
+
+// Batch internals used by the request server (batch.hip).
+struct pt_batch;
+pt_batch* batch_new(hipStream_t st);
+int batch_round(pt_batch* b, const std::vector<pt_job*>& jobs, const std::vector<int>& steps,
+                const std::vector<uint32_t>& flags);
+void batch_free(pt_batch* b);
+// Whether job j can run `flags` fused with at least one replica set resident.
+bool job_is_resident(const pt_job* j, uint32_t flags);
+// Device bytes a job of this shape allocates (an upper bound).
+size_t job_device_bytes(int S, int NT, int L, int d, int layout, const double* betas);
+// Length of a row of the exchange threshold table.
+int pt_table_len(const double* betas, int NT, int d, long N);
+// pt_init_ex with explicit allocation hooks (NULL: hipMalloc / hipFree).
+int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
+               const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags,
+               void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx,
+               hipStream_t stream);

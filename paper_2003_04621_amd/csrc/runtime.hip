@@ -32,6 +32,15 @@ void* (*g_alloc)(size_t, void*) = nullptr;
 void (*g_free)(void*, void*) = nullptr;
 void* g_ctx = nullptr;
 
+// Row fields per 32-bit word: as many rows of L/2 bits as fit, with an even
+// block length L/P so that all fields of a word share their checkerboard
+// offset.
+int fields_per_word(int L) {
+  for (int p = 32 / (L / 2); p >= 1; --p)
+    if (L % p == 0 && (L / p) % 2 == 0) return p;
+  return 1;
+}
+
 // Acceptance probability p -> 32-bit threshold floor(2^32 p), clamped to
 // [0, 2^32 - 1]; a uniform 32-bit word r accepts iff r < threshold.
 uint32_t threshold_u32(double p) {
@@ -127,8 +136,10 @@ PT_API int pt_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, 
   return PT_OK;
 }
 
-PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
-                      const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags) {
+int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
+               const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags,
+               void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx,
+               hipStream_t stream) {
   g_err.clear();
   if (!out || !couplings || !betas) return pt_fail(PT_EINVAL, "null pointer argument");
   if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
@@ -152,9 +163,10 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
 
   pt_job* job = new (std::nothrow) pt_job();
   if (!job) return pt_fail(PT_ENOMEM, "host allocation failed");
-  job->alloc_fn = g_alloc;
-  job->free_fn = g_free;
-  job->alloc_ctx = g_ctx;
+  job->alloc_fn = alloc;
+  job->free_fn = free_;
+  job->alloc_ctx = ctx;
+  job->stream = stream;
   Geo& g = job->g;
   g.L = L;
   g.d = dim;
@@ -164,13 +176,7 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
   g.G = (L + 7) / 8;
   g.magicL = (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L);
   g.maskH = (g.H == 32) ? 0xFFFFFFFFu : ((1u << g.H) - 1u);
-  // fields per word: as many rows as fit, with an even block length L/P
-  g.P = 1;
-  for (int p = 32 / g.H; p >= 1; --p)
-    if (L % p == 0 && (L / p) % 2 == 0) {
-      g.P = p;
-      break;
-    }
+  g.P = fields_per_word(L);
   g.B = L / g.P;
   g.NW = g.NR / g.P;
   g.maskW = (g.P * g.H == 32) ? 0xFFFFFFFFu : ((1u << (g.P * g.H)) - 1u);
@@ -192,14 +198,7 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
       thr[(size_t)k * 4 + (m - 1)] = threshold_u32(std::exp(-(betas[k] * dE)));
     }
   // Exchange thresholds: D = 2m, row length M = first m where every row is 0.
-  int M = 1;
-  const long mmax = (long)dim * N;
-  for (int k = 0; k + 1 < replicas; ++k) {
-    const double db = betas[k] - betas[k + 1];
-    long m = 1;
-    while (m <= mmax && threshold_u32(std::exp(-(db * (double)(2 * m)))) != 0u) ++m;
-    if (m > M) M = (int)m;
-  }
+  const int M = pt_table_len(betas, replicas, dim, N);
   std::vector<uint32_t> thrpt((size_t)(replicas - 1) * M, 0u);
   for (int k = 0; k + 1 < replicas; ++k) {
     const double db = betas[k] - betas[k + 1];
@@ -257,6 +256,41 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
   }
   *out = job;
   return PT_OK;
+}
+
+PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
+                      const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags) {
+  return job_create(out, samples, replicas, L, dim, couplings, betas, seed, flags, g_alloc, g_free,
+                    g_ctx, nullptr);
+}
+
+bool job_is_resident(const pt_job* j, uint32_t flags) {
+  if (flags & PT_MCS_HOUDAYER) return j->fused_ok[1];
+  if (flags & PT_MCS_MEASURE) return j->fused_ok[0];
+  return j->fused_ok[0] || j->fused_ok[2];
+}
+
+int pt_table_len(const double* betas, int NT, int d, long N) {
+  int M = 1;
+  const long mmax = (long)d * N;
+  for (int k = 0; k + 1 < NT; ++k) {
+    const double db = betas[k] - betas[k + 1];
+    long m = 1;
+    while (m <= mmax && threshold_u32(std::exp(-(db * (double)(2 * m)))) != 0u) ++m;
+    if (m > M) M = (int)m;
+  }
+  return M;
+}
+
+size_t job_device_bytes(int S, int NT, int L, int d, int layout, const double* betas) {
+  const size_t N = (d == 3) ? (size_t)L * L * L : (size_t)L * L;
+  const size_t NW = N / L / fields_per_word(L);
+  const size_t lat = (size_t)S * 2 * NT;
+  const size_t spins = layout == PT_LAYOUT_PACKED ? lat * 2 * NW * 4 : lat * N;
+  const size_t jw = (size_t)S * 2 * 2 * d * NW * 4;
+  const size_t small = sizeof(int32_t) * (lat + 4 * (size_t)S * NT) + sizeof(int64_t) * 8 * S * NT +
+                       sizeof(uint32_t) * (size_t)NT * (4 + pt_table_len(betas, NT, d, (long)N)) + 4096;
+  return spins + jw + (size_t)S * d * N + small;
 }
 
 PT_API int pt_init(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,

@@ -1,0 +1,345 @@
+// server.hip -- continuous-batching request server for parallel-tempering jobs.
+//
+// Requests are admitted in arrival order while their device memory fits the
+// HBM budget, stay resident on the device, and advance together: every round
+// runs up to `steps_per_round` Monte Carlo steps of every active job in one
+// persistent batch launch (jobs too large for one workgroup's LDS run their
+// per-step kernels on a second stream at the same time).  A job measures only
+// after its burn-in; when its steps are done its observables are read out,
+// its memory is released and the next request is admitted.  Results depend
+// only on the request, never on what else ran beside it.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "job.h"
+#include "pt.h"
+
+namespace {
+
+struct Request {
+  uint64_t ticket = 0;
+  int dim = 3, L = 0, NT = 0, S = 0, sweeps = 0, burn_in = 0;
+  uint32_t flags = 0, layout = 0;
+  uint64_t seed = 0;
+  std::vector<double> betas;
+  std::vector<int8_t> J;
+  double t_submit = 0;
+};
+
+struct Active {
+  Request req;
+  pt_job* job = nullptr;
+  int done = 0;
+  size_t bytes = 0;
+  double t_admit = 0;
+};
+
+struct Finished {
+  int status = 0;
+  int64_t n_meas = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  std::vector<double> disorder;  // [NT][6]
+};
+
+}  // namespace
+
+struct pt_server {
+  size_t budget = 0, used = 0;
+  int steps_per_round = 100;
+  int device = 0;
+  hipStream_t st_main = nullptr, st_side = nullptr;
+  pt_batch* batch[2] = {nullptr, nullptr};  // 2D and 3D jobs
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<Request> pending;
+  std::vector<Active> active;
+  std::unordered_map<uint64_t, Finished> finished;
+  uint64_t next_ticket = 1;
+  bool stopping = false;
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0;
+  // statistics
+  double flips = 0, busy = 0;
+  uint64_t rounds = 0, admitted = 0, completed = 0;
+  size_t peak_used = 0;
+  int max_active = 0;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+void finish(pt_server* sv, Active& a, int status) {
+  Finished f;
+  f.status = status;
+  f.t_submit = a.req.t_submit;
+  f.t_admit = a.t_admit;
+  f.disorder.assign((size_t)a.req.NT * 6, 0.0);
+  if (status == PT_OK && a.job) {
+    int64_t n = 0;
+    const int rc = pt_observables(a.job, nullptr, f.disorder.data(), &n);
+    if (rc != PT_OK) f.status = rc;
+    f.n_meas = n;
+  }
+  if (a.job) pt_destroy(a.job);
+  a.job = nullptr;
+  f.t_done = sv->now();
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->used -= a.bytes;
+  sv->completed += 1;
+  sv->finished[a.req.ticket] = std::move(f);
+  sv->cv_done.notify_all();
+}
+
+void fail_request(pt_server* sv, const Request& r, int status) {
+  Finished f;
+  f.status = status;
+  f.t_submit = r.t_submit;
+  f.t_admit = f.t_done = sv->now();
+  f.disorder.assign((size_t)r.NT * 6, 0.0);
+  sv->finished[r.ticket] = std::move(f);
+  sv->cv_done.notify_all();
+}
+
+void serve(pt_server* sv) {
+  (void)hipSetDevice(sv->device);
+  for (;;) {
+    std::vector<Request> admit;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv.wait(lk, [&] { return sv->stopping || !sv->pending.empty() || !sv->active.empty(); });
+      if (sv->stopping && sv->pending.empty() && sv->active.empty()) break;
+      // admission in arrival order while the budget holds
+      size_t used = sv->used;
+      while (!sv->pending.empty()) {
+        Request& r = sv->pending.front();
+        const size_t need = job_device_bytes(r.S, r.NT, r.L, r.dim, (int)r.layout, r.betas.data());
+        if (need > sv->budget) {
+          fail_request(sv, r, PT_ENOMEM);
+          sv->pending.pop_front();
+          continue;
+        }
+        if (used + need > sv->budget) break;
+        used += need;
+        admit.push_back(std::move(r));
+        sv->pending.pop_front();
+      }
+      sv->used = used;
+      if (used > sv->peak_used) sv->peak_used = used;
+    }
+    for (Request& r : admit) {
+      Active a;
+      a.bytes = job_device_bytes(r.S, r.NT, r.L, r.dim, (int)r.layout, r.betas.data());
+      a.t_admit = sv->now();
+      const int rc = job_create(&a.job, r.S, r.NT, r.L, r.dim, r.J.data(), r.betas.data(), r.seed,
+                                r.layout, nullptr, nullptr, nullptr, sv->st_main);
+      a.req = std::move(r);
+      a.req.J.clear();
+      a.req.J.shrink_to_fit();
+      if (rc != PT_OK) {
+        a.job = nullptr;
+        finish(sv, a, rc);
+        continue;
+      }
+      sv->active.push_back(std::move(a));
+      sv->admitted += 1;
+    }
+    if (sv->active.empty()) continue;
+    if ((int)sv->active.size() > sv->max_active) sv->max_active = (int)sv->active.size();
+
+    // one round: every active job advances, measuring after its burn-in
+    const double t_round = sv->now();
+    std::vector<pt_job*> res_jobs[2];
+    std::vector<int> res_steps[2];
+    std::vector<uint32_t> res_flags[2];
+    std::vector<size_t> side;
+    double round_flips = 0;
+    std::vector<int> steps(sv->active.size());
+    std::vector<uint32_t> flags(sv->active.size());
+    for (size_t i = 0; i < sv->active.size(); ++i) {
+      Active& a = sv->active[i];
+      const int left = a.req.sweeps - a.done;
+      int n = left < sv->steps_per_round ? left : sv->steps_per_round;
+      uint32_t f = a.req.flags & PT_MCS_HOUDAYER;
+      if (a.done < a.req.burn_in) {
+        const int to_burn = a.req.burn_in - a.done;
+        if (n > to_burn) n = to_burn;
+      } else {
+        f |= PT_MCS_MEASURE;
+      }
+      steps[i] = n;
+      flags[i] = f;
+      round_flips += (double)n * a.job->g.S * a.job->g.nslot * a.job->g.N;
+      if (job_is_resident(a.job, f)) {
+        const int b = a.job->g.d == 3 ? 1 : 0;
+        res_jobs[b].push_back(a.job);
+        res_steps[b].push_back(n);
+        res_flags[b].push_back(f);
+      } else {
+        side.push_back(i);
+      }
+    }
+    int rc = PT_OK;
+    for (int b = 0; b < 2 && rc == PT_OK; ++b)
+      rc = batch_round(sv->batch[b], res_jobs[b], res_steps[b], res_flags[b]);
+    for (size_t i : side) {
+      if (rc != PT_OK) break;
+      Active& a = sv->active[i];
+      a.job->stream = sv->st_side;
+      rc = pt_mcs(a.job, steps[i], flags[i]);
+      a.job->stream = sv->st_main;
+    }
+    if (rc == PT_OK && hipStreamSynchronize(sv->st_main) != hipSuccess) rc = PT_EDEVICE;
+    if (rc == PT_OK && hipStreamSynchronize(sv->st_side) != hipSuccess) rc = PT_EDEVICE;
+    sv->busy += sv->now() - t_round;
+    sv->rounds += 1;
+    if (rc == PT_OK) sv->flips += round_flips;
+    // completions
+    std::vector<Active> still;
+    for (size_t i = 0; i < sv->active.size(); ++i) {
+      Active& a = sv->active[i];
+      if (rc != PT_OK) {
+        finish(sv, a, rc);
+        continue;
+      }
+      a.done += steps[i];
+      if (a.done >= a.req.sweeps)
+        finish(sv, a, PT_OK);
+      else
+        still.push_back(std::move(a));
+    }
+    sv->active.swap(still);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+PT_API int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server** out) {
+  if (!out || hbm_budget == 0 || steps_per_round < 1)
+    return pt_fail(PT_EINVAL, "pt_server_start: need a budget > 0, steps_per_round >= 1, an output");
+  pt_server* sv = new (std::nothrow) pt_server();
+  if (!sv) return pt_fail(PT_ENOMEM, "pt_server_start: host allocation failed");
+  sv->budget = hbm_budget;
+  sv->steps_per_round = steps_per_round;
+  sv->t0 = std::chrono::steady_clock::now();
+  (void)hipGetDevice(&sv->device);
+  if (hipStreamCreateWithFlags(&sv->st_main, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&sv->st_side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    delete sv;
+    return pt_fail(PT_EDEVICE, "pt_server_start: stream creation failed");
+  }
+  sv->batch[0] = batch_new(sv->st_main);
+  sv->batch[1] = batch_new(sv->st_main);
+  if (!sv->batch[0] || !sv->batch[1]) {
+    batch_free(sv->batch[0]);
+    batch_free(sv->batch[1]);
+    delete sv;
+    return pt_fail(PT_ENOMEM, "pt_server_start: host allocation failed");
+  }
+  sv->worker = std::thread(serve, sv);
+  *out = sv;
+  return PT_OK;
+}
+
+PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* ticket) {
+  if (!sv || !req || !ticket) return pt_fail(PT_EINVAL, "pt_server_submit: null argument");
+  if (!req->betas || !req->couplings) return pt_fail(PT_EINVAL, "pt_server_submit: null arrays");
+  if (req->dim != 2 && req->dim != 3) return pt_fail(PT_EINVAL, "pt_server_submit: dim must be 2 or 3");
+  if (req->L < 4 || req->L > 64 || (req->L & 1))
+    return pt_fail(PT_EINVAL, "pt_server_submit: L must be even and in [4, 64]");
+  if (req->samples < 1 || req->replicas < 2 || req->sweeps < 0 || req->burn_in < 0 ||
+      req->burn_in > req->sweeps)
+    return pt_fail(PT_EINVAL, "pt_server_submit: need samples >= 1, replicas >= 2, 0 <= burn_in <= sweeps");
+  if (req->flags & ~(uint32_t)PT_MCS_HOUDAYER) return pt_fail(PT_EINVAL, "pt_server_submit: unknown flags");
+  if (req->layout != PT_LAYOUT_INT8 && req->layout != PT_LAYOUT_PACKED)
+    return pt_fail(PT_EINVAL, "pt_server_submit: unknown layout");
+  for (int k = 0; k < req->replicas; ++k)
+    if (!(req->betas[k] > 0.0) || (k > 0 && !(req->betas[k] < req->betas[k - 1])))
+      return pt_fail(PT_EINVAL, "pt_server_submit: betas must be > 0 and strictly decreasing");
+  const size_t N = req->dim == 3 ? (size_t)req->L * req->L * req->L : (size_t)req->L * req->L;
+  const size_t nJ = (size_t)req->samples * req->dim * N;
+  for (size_t i = 0; i < nJ; ++i)
+    if (req->couplings[i] != 1 && req->couplings[i] != -1)
+      return pt_fail(PT_EINVAL, "pt_server_submit: couplings must be +1 or -1");
+  Request r;
+  r.dim = req->dim;
+  r.L = req->L;
+  r.NT = req->replicas;
+  r.S = req->samples;
+  r.sweeps = req->sweeps;
+  r.burn_in = req->burn_in;
+  r.flags = req->flags;
+  r.layout = req->layout;
+  r.seed = req->seed;
+  r.betas.assign(req->betas, req->betas + req->replicas);
+  r.J.assign(req->couplings, req->couplings + nJ);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->stopping) return pt_fail(PT_ESTATE, "pt_server_submit: server is stopping");
+  r.ticket = sv->next_ticket++;
+  r.t_submit = sv->now();
+  *ticket = r.ticket;
+  sv->pending.push_back(std::move(r));
+  sv->cv.notify_all();
+  return PT_OK;
+}
+
+PT_API int pt_server_poll(pt_server* sv, uint64_t ticket, pt_result* out, double* disorder) {
+  if (!sv || !out) return pt_fail(PT_EINVAL, "pt_server_poll: null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->finished.find(ticket);
+  if (it == sv->finished.end()) {
+    if (ticket == 0 || ticket >= sv->next_ticket) return pt_fail(PT_EINVAL, "pt_server_poll: unknown ticket");
+    return 1;  // queued or running
+  }
+  const Finished& f = it->second;
+  out->status = f.status;
+  out->n_meas = f.n_meas;
+  out->t_submit = f.t_submit;
+  out->t_admit = f.t_admit;
+  out->t_done = f.t_done;
+  if (disorder) std::copy(f.disorder.begin(), f.disorder.end(), disorder);
+  sv->finished.erase(it);
+  return PT_OK;
+}
+
+PT_API int pt_server_stats(pt_server* sv, double* out) {
+  if (!sv || !out) return pt_fail(PT_EINVAL, "pt_server_stats: null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  out[0] = sv->flips;
+  out[1] = sv->busy;
+  out[2] = (double)sv->rounds;
+  out[3] = (double)sv->admitted;
+  out[4] = (double)sv->completed;
+  out[5] = (double)sv->peak_used;
+  out[6] = (double)sv->max_active;
+  out[7] = sv->now();
+  return PT_OK;
+}
+
+PT_API int pt_server_stop(pt_server* sv) {
+  if (!sv) return pt_fail(PT_EINVAL, "null server");
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stopping = true;
+    sv->cv.notify_all();
+  }
+  if (sv->worker.joinable()) sv->worker.join();
+  batch_free(sv->batch[0]);
+  batch_free(sv->batch[1]);
+  (void)hipStreamDestroy(sv->st_main);
+  (void)hipStreamDestroy(sv->st_side);
+  (void)hipGetLastError();
+  delete sv;
+  return PT_OK;
+}

@@ -31,7 +31,20 @@ EXPORTS = [
     "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
     "pt_batch_get_config", "pt_batch_set_config", "pt_batch_destroy",
+    "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_stats", "pt_server_stop",
 ]
+
+
+class PTRequest(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("L", C.c_int32), ("replicas", C.c_int32),
+                ("samples", C.c_int32), ("betas", C.c_void_p), ("couplings", C.c_void_p),
+                ("seed", C.c_uint64), ("sweeps", C.c_int32), ("burn_in", C.c_int32),
+                ("flags", C.c_uint32), ("layout", C.c_uint32)]
+
+
+class PTResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("n_meas", C.c_int64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
 class PTError(RuntimeError):
@@ -68,6 +81,10 @@ def lib():
             "pt_batch_run": [P, I32, U32], "pt_batch_tune": [P, I32, U32, C.c_char_p],
             "pt_batch_get_config": [P, P], "pt_batch_set_config": [P, I32, I32, I32],
             "pt_batch_destroy": [P],
+            "pt_server_start": [C.c_size_t, I32, C.POINTER(P)],
+            "pt_server_submit": [P, C.POINTER(PTRequest), C.POINTER(C.c_uint64)],
+            "pt_server_poll": [P, C.c_uint64, C.POINTER(PTResult), P],
+            "pt_server_stats": [P, P], "pt_server_stop": [P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -342,3 +359,67 @@ def pt_batch_destroy(batch: Batch) -> None:
     if batch.h:
         _check(lib().pt_batch_destroy(batch.h))
         batch.h = None
+
+
+# --------------------------------------------------------------------------
+# served form
+# --------------------------------------------------------------------------
+class Server:
+    def __init__(self, handle):
+        self.h = handle
+        self.replicas = {}
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().pt_server_stop(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def pt_server_start(hbm_budget: int, steps_per_round: int = 100) -> Server:
+    h = C.c_void_p()
+    _check(lib().pt_server_start(C.c_size_t(int(hbm_budget)), int(steps_per_round), C.byref(h)))
+    return Server(h)
+
+
+def pt_server_submit(server: Server, dim, L, replicas, samples, betas, couplings, seed, sweeps,
+                     burn_in, houdayer=False, layout=PT_LAYOUT_INT8) -> int:
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    J = np.ascontiguousarray(couplings, dtype=np.int8)
+    req = PTRequest(int(dim), int(L), int(replicas), int(samples), b.ctypes.data, J.ctypes.data,
+                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps), int(burn_in),
+                    PT_MCS_HOUDAYER if houdayer else 0, int(layout))
+    t = C.c_uint64(0)
+    _check(lib().pt_server_submit(server.h, C.byref(req), C.byref(t)))
+    server.replicas[t.value] = int(replicas)
+    return t.value
+
+
+def pt_server_poll(server: Server, ticket: int):
+    """None while pending; else (status, n_meas, t_submit, t_admit, t_done, disorder)."""
+    res = PTResult()
+    nt = server.replicas[ticket]
+    dis = np.zeros((nt, 6), np.float64)
+    rc = lib().pt_server_poll(server.h, C.c_uint64(ticket), C.byref(res), _p(dis))
+    if rc == 1:
+        return None
+    _check(rc)
+    del server.replicas[ticket]
+    return dict(status=res.status, n_meas=res.n_meas, t_submit=res.t_submit,
+                t_admit=res.t_admit, t_done=res.t_done, disorder=dis)
+
+
+def pt_server_stats(server: Server) -> dict:
+    out = np.zeros(8, np.float64)
+    _check(lib().pt_server_stats(server.h, _p(out)))
+    keys = ["flips", "busy_s", "rounds", "admitted", "completed", "peak_bytes", "peak_jobs",
+            "uptime_s"]
+    return dict(zip(keys, out.tolist()))
+
+
+def pt_server_stop(server: Server) -> None:
+    if server.h:
+        _check(lib().pt_server_stop(server.h))
+        server.h = None

@@ -1,0 +1,130 @@
+"""GPU tests of the served form: requests admitted by HBM budget, advanced in
+continuous batches, must give the same observables as the same job run alone
+(bit-identical FP64 values from identical integer moments)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2003_04621_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2003_04621_amd import pt as _pt
+    _pt.lib()
+    return _pt
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+REQUESTS = [  # (dim, L, replicas, samples, sweeps, burn_in, houdayer, layout)
+    (3, 8, 4, 2, 30, 10, False, 0),
+    (3, 16, 6, 1, 25, 12, False, 1),
+    (2, 64, 3, 1, 20, 5, True, 0),
+    (3, 12, 5, 3, 17, 0, False, 0),
+    (3, 48, 8, 1, 9, 4, False, 0),      # too large for one workgroup: per-step kernels
+    (2, 16, 4, 2, 33, 11, True, 1),
+    (3, 8, 3, 1, 0, 0, False, 0),        # nothing to do
+    (3, 24, 4, 1, 14, 7, False, 1),
+]
+
+
+def _inputs(n, spec):
+    dim, L, NT, S, sweeps, burn, hou, layout = spec
+    J = W.couplings_pm_j(S, L, dim, 500 + n)
+    b = W.geometric_betas(0.6, 2.0, NT)
+    return J, b, 900 + n
+
+
+def _alone(pt, n, spec):
+    dim, L, NT, S, sweeps, burn, hou, layout = spec
+    J, b, seed = _inputs(n, spec)
+    job = pt.pt_init(S, NT, L, dim, J, b, seed, layout=layout)
+    pt.pt_mcs(job, burn, houdayer=hou)
+    pt.pt_mcs(job, sweeps - burn, houdayer=hou, measure=True)
+    _, dis, nm = pt.pt_observables(job)
+    pt.pt_destroy(job)
+    return dis, nm
+
+
+def _wait(pt, srv, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for n, t in tickets.items():
+            if n in out:
+                continue
+            r = pt.pt_server_poll(srv, t)
+            if r is not None:
+                out[n] = r
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.01)
+    return out
+
+
+def test_server_matches_alone_and_respects_budget(pt):
+    budget = 24 << 20
+    srv = pt.pt_server_start(budget, steps_per_round=7)
+    tickets = {}
+    for n, spec in enumerate(REQUESTS):
+        dim, L, NT, S, sweeps, burn, hou, layout = spec
+        J, b, seed = _inputs(n, spec)
+        say(f"submit {spec}")
+        tickets[n] = pt.pt_server_submit(srv, dim, L, NT, S, b, J, seed, sweeps, burn, hou, layout)
+    res = _wait(pt, srv, tickets)
+    stats = pt.pt_server_stats(srv)
+    pt.pt_server_stop(srv)
+    assert stats["peak_bytes"] <= budget
+    assert stats["completed"] == len(REQUESTS)
+    for n, spec in enumerate(REQUESTS):
+        r = res[n]
+        assert r["status"] == 0, (spec, r["status"])
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+        dis, nm = _alone(pt, n, spec)
+        assert r["n_meas"] == nm == spec[4] - spec[5]
+        if nm > 0:
+            assert np.array_equal(r["disorder"], dis), spec
+
+
+def test_server_same_result_alone_and_in_mix(pt):
+    spec = (3, 16, 6, 2, 21, 9, False, 0)
+    J, b, seed = _inputs(77, spec)
+    dim, L, NT, S, sweeps, burn, hou, layout = spec
+    alone = pt.pt_server_start(1 << 30, steps_per_round=5)
+    t = pt.pt_server_submit(alone, dim, L, NT, S, b, J, seed, sweeps, burn, hou, layout)
+    r_alone = _wait(pt, alone, {0: t})[0]
+    pt.pt_server_stop(alone)
+    mix = pt.pt_server_start(8 << 20, steps_per_round=4)
+    tickets = {}
+    for n, other in enumerate(REQUESTS[:6]):
+        Jo, bo, so = _inputs(n, other)
+        tickets[n] = pt.pt_server_submit(mix, other[0], other[1], other[2], other[3], bo, Jo, so,
+                                         other[4], other[5], other[6], other[7])
+        if n == 2:
+            tickets["x"] = pt.pt_server_submit(mix, dim, L, NT, S, b, J, seed, sweeps, burn, hou,
+                                               layout)
+    res = _wait(pt, mix, tickets)
+    pt.pt_server_stop(mix)
+    assert np.array_equal(res["x"]["disorder"], r_alone["disorder"])
+    assert res["x"]["n_meas"] == r_alone["n_meas"] == sweeps - burn
+
+
+def test_server_rejects_oversized_and_bad_requests(pt):
+    srv = pt.pt_server_start(1 << 20, steps_per_round=3)
+    spec = (3, 32, 16, 1, 5, 0, False, 0)
+    J, b, seed = _inputs(1, spec)
+    t = pt.pt_server_submit(srv, 3, 32, 16, 1, b, J, seed, 5, 0)
+    r = _wait(pt, srv, {0: t})[0]
+    assert r["status"] == pt.PT_ENOMEM
+    with pytest.raises(pt.PTError):
+        pt.pt_server_submit(srv, 3, 32, 16, 1, b, J, seed, 5, 6)      # burn_in > sweeps
+    with pytest.raises(pt.PTError):
+        pt.pt_server_submit(srv, 3, 31, 16, 1, b, J, seed, 5, 0)      # odd L
+    pt.pt_server_stop(srv)
