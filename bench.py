@@ -59,6 +59,122 @@ def cpu_baseline(wl, budget_s: float):
                       f"{n} Monte Carlo steps, {dt:.1f} s single-threaded"}
 
 
+def batched_mix(pt, torch, W, args):
+    """Jobs of uneven size in one persistent launch: 2000 jobs of one sample,
+    400 each at L = 8, 12, 16, 24, 32, 24 temperatures (geometric T in
+    [0.9, 2.0]), sweep + exchange steps replayed from a captured hipGraph,
+    launch shape chosen by the autotuner; int8 and packed spin layouts."""
+    Ls = [8, 12, 16, 24, 32]
+    per_L = args.batch_jobs // len(Ls)
+    NT = 24
+    betas = W.geometric_betas(0.9, 2.0, NT)
+    out = {"workload": f"{per_L * len(Ls)} jobs x 1 sample x 2 x {NT} temperatures, 3D +-J, "
+                       f"L in {Ls} (1:1:1:1:1)", "steps": args.batch_steps}
+    for layout_name, layout in (("int8", pt.PT_LAYOUT_INT8), ("packed", pt.PT_LAYOUT_PACKED)):
+        jobs = []
+        n = 0
+        for L in Ls:
+            for _ in range(per_L):
+                J = W.couplings_pm_j(1, L, 3, 1000 + n)
+                jobs.append(pt.pt_init(1, NT, L, 3, J, betas, 2000 + n, layout=layout))
+                n += 1
+        flips = sum(2 * NT * j.N for j in jobs)
+        batch = pt.pt_batch_create(jobs)
+        cfg = pt.pt_batch_tune(batch, 3, cache_path=args.tune_cache)
+        pt.pt_batch_run(batch, args.batch_chunk, graph=True)        # capture + warm-up
+        torch.cuda.synchronize()
+        reps = max(1, args.batch_steps // args.batch_chunk)
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            pt.pt_batch_run(batch, args.batch_chunk, graph=True)
+            b.record(stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        value = flips * args.batch_chunk * reps / dt / 1e9
+        achieved = OPS_PER_FLIP * flips * args.batch_chunk / (launch_ms * 1e-3) / 1e12
+        # the same steps, one job per launch (no batch, no graph)
+        plain_steps = 2
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(plain_steps):
+            for j in jobs:
+                pt.pt_mcs(j, 1)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - tp
+        plain = flips * plain_steps / dtp / 1e9
+        out[layout_name] = {
+            "value": round(value, 2), "unit": "flips/ns", "tuned_config": list(cfg),
+            "graph_replays": reps, "steps_per_replay": args.batch_chunk,
+            "launch_ms": round(launch_ms, 3),
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                         "peak": round(PEAK_VALU_OPS / 1e12, 3), "unit": "TOP/s",
+                         "frac": round(achieved / (PEAK_VALU_OPS / 1e12), 4)},
+            "plain_one_job_per_launch": round(plain, 3),
+            "speedup_vs_plain": round(value / plain, 1)}
+        pt.pt_batch_destroy(batch)
+        for j in jobs:
+            pt.pt_destroy(j)
+        del jobs
+    return out
+
+
+def served(pt, torch, W, args, capacity_flips_per_ns):
+    """Poisson arrivals of 3D +-J PT requests: L uniform in {16, 24, 32, 48},
+    16..48 temperatures, 10^3..10^4 steps (log-uniform), half of them burn-in;
+    admission by an HBM budget; p50/p99 of completion minus submission."""
+    rng = np.random.default_rng(args.serve_seed)
+    n = args.serve_requests
+    Ls = rng.choice([16, 24, 32, 48], size=n)
+    NTs = rng.integers(16, 49, size=n)
+    sweeps = np.exp(rng.uniform(np.log(1e3), np.log(1e4), size=n)).astype(int)
+    flips = 2 * NTs * Ls.astype(np.int64) ** 3 * sweeps
+    mean_flips = float(flips.mean())
+    lam = args.serve_load * capacity_flips_per_ns * 1e9 / mean_flips       # jobs per second
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n))
+    reqs = []
+    for i in range(n):
+        L, NT = int(Ls[i]), int(NTs[i])
+        reqs.append((L, NT, W.couplings_pm_j(1, L, 3, 5000 + i), W.geometric_betas(0.9, 2.0, NT),
+                     int(sweeps[i])))
+    srv = pt.pt_server_start(args.serve_budget << 20, steps_per_round=args.serve_round)
+    tickets, results = {}, {}
+    t0 = time.perf_counter()
+    i = 0
+    while len(results) < n:
+        now = time.perf_counter() - t0
+        while i < n and arrivals[i] <= now:
+            L, NT, J, b, sw = reqs[i]
+            tickets[i] = pt.pt_server_submit(srv, 3, L, NT, 1, b, J, 7000 + i, sw, sw // 2)
+            i += 1
+        for k in list(tickets):
+            r = pt.pt_server_poll(srv, tickets[k])
+            if r is not None:
+                results[k] = r
+                del tickets[k]
+        time.sleep(0.002)
+    stats = pt.pt_server_stats(srv)
+    pt.pt_server_stop(srv)
+    lat = np.array([results[k]["t_done"] - results[k]["t_submit"] for k in range(n)])
+    span = max(r["t_done"] for r in results.values()) - min(r["t_submit"] for r in results.values())
+    bad = sum(1 for r in results.values() if r["status"] != 0)
+    return {"workload": f"{n} requests, Poisson arrivals at {lam:.2f}/s "
+                        f"({args.serve_load:.0%} of {capacity_flips_per_ns:.0f} flips/ns), 3D +-J, "
+                        "L in {16,24,32,48}, 16-48 temperatures, 1e3-1e4 steps (half burn-in)",
+            "hbm_budget_mib": args.serve_budget, "steps_per_round": args.serve_round,
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "value": round(stats["flips"] / span / 1e9, 2), "unit": "flips/ns",
+            "busy_fraction": round(stats["busy_s"] / span, 3),
+            "peak_concurrent_jobs": int(stats["peak_jobs"]),
+            "peak_admitted_mib": round(stats["peak_bytes"] / 2 ** 20, 1),
+            "failed": bad}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +186,17 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=300,
                     help="steps re-timed with one launch per kernel (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-jobs", type=int, default=2000)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-chunk", type=int, default=100)
+    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-budget", type=int, default=512, help="MiB")
+    ap.add_argument("--serve-round", type=int, default=100)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-seed", type=int, default=31)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic-bytes", type=float, default=None,
                     help="HBM bytes per sweep launch measured with rocprofv3 counters")
@@ -130,7 +257,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TOP/s", "frac": round(achieved / peak, 4),
                 "traffic": args.traffic_bytes,
-                "kernel": f"k_mcs<{wl.dim}> ({chunk} steps per launch)",
+                "kernel": f"k_batch<{wl.dim}> ({chunk} steps per launch)",
                 "launch_ms": round(launch_ms, 4)}
 
     # the same steps as separate per-step launches, for the fused/plain ratio
@@ -150,6 +277,15 @@ def main():
     _, dis, n_meas = pt.pt_observables(job)
     pt.pt_destroy(job)
 
+    batched = None
+    if not args.no_batched:
+        print("# batched form", file=sys.stderr, flush=True)
+        batched = batched_mix(pt, torch, W, args)
+    serve = None
+    if not args.no_served:
+        print("# served form", file=sys.stderr, flush=True)
+        cap = batched["packed"]["value"] if batched else value
+        serve = served(pt, torch, W, args, cap)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds)
@@ -167,6 +303,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_form": plain,
+        "batched": batched,
+        "served": serve,
         "e_coldest": round(float(dis[0, 0]), 6), "binder_coldest": round(float(dis[0, 5]), 6),
     }
     print(json.dumps(out), flush=True)

@@ -146,12 +146,21 @@ int pt_houdayer(pt_job *job);
 int pt_measure(pt_job *job);
 
 /* n Monte Carlo steps (Sec. 2.4): sweep, Houdayer if flags has
- * PT_MCS_HOUDAYER, exchange, measure if flags has PT_MCS_MEASURE.  When all
- * 2*replicas configurations of one sample fit in a workgroup's LDS the steps
- * run fused (one workgroup per sample, the sample resident on chip for the
- * whole launch); PT_MCS_PLAIN forces one launch per step and kernel.  Both
- * forms give bit-identical results. */
+ * PT_MCS_HOUDAYER, exchange, measure if flags has PT_MCS_MEASURE.  The steps
+ * run fused, the configurations resident in LDS for the whole launch, with
+ * the first plan that fits a workgroup (pt_get_plan): both replica sets of a
+ * sample in one workgroup; one set per workgroup (no measurement, no
+ * Houdayer); or, without Houdayer, the sample's configurations split over
+ * several workgroups that meet once per step.  With no such plan, or with
+ * PT_MCS_PLAIN, one launch per step and kernel.  All forms give
+ * bit-identical results. */
 int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
+
+/* The plan pt_mcs takes for these flags, int32 [4]: mode (0 both sets per
+ * workgroup, 1 the same with Houdayer, 2 one set per workgroup, 3 split
+ * sample, -1 per-step kernels), workgroups per sample, configurations per
+ * workgroup, and LDS bytes per workgroup (0 for mode -1).  Host only. */
+int pt_get_plan(pt_job *job, uint32_t flags, int32_t *out4);
 
 /* Observables from the accumulated moments, in double precision.
  *   per_sample [samples][replicas][5]: <e>, <q>, <|q|>, <q^2>, <q^4>

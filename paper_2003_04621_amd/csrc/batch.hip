@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,9 +46,31 @@ struct pt_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool graph_ok = false;
+  bool has_split = false;  // the work list holds split samples
 };
 
 namespace {
+
+// Launches holding split samples are ordered one after another across all
+// streams of the process (per device): two of them running side by side
+// could each hold part of the machine while waiting for workgroups that only
+// the other one's exit would make room for.
+std::mutex g_split_mu;
+hipEvent_t g_split_ev[64] = {};
+
+template <typename F>
+hipError_t ordered_split_launch(hipStream_t st, F&& launch) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  if (!g_split_ev[dev]) e = hipEventCreateWithFlags(&g_split_ev[dev], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, g_split_ev[dev], 0);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(g_split_ev[dev], st);
+  return e;
+}
 
 bool same_cfg(const BatchConfig& a, const BatchConfig& b) {
   return a.threads == b.threads && a.sets == b.sets && a.order == b.order;
@@ -61,20 +84,23 @@ void drop_graph(pt_batch* b) {
   b->graph_ok = false;
 }
 
-// Plan index of a job for the given flags and config, or -1 if it cannot be
-// resident in one workgroup.
+// Plan of a job for the given flags and config: 0 both sets per workgroup,
+// 1 the same with Houdayer room, 2 one set per workgroup, 3 split sample; -1
+// if none exists.
 int job_mode(const pt_job* j, uint32_t flags, const BatchConfig& cfg) {
   const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
   if (hou) return j->fused_ok[1] ? 1 : -1;
   if (cfg.sets == 2 && j->fused_ok[0]) return 0;
-  if (meas) return j->fused_ok[0] ? 0 : -1;
-  return j->fused_ok[2] ? 2 : (j->fused_ok[0] ? 0 : -1);
+  if (meas) return j->fused_ok[0] ? 0 : (j->split_ok ? 3 : -1);
+  if (j->fused_ok[2]) return 2;
+  if (j->fused_ok[0]) return 0;
+  return j->split_ok ? 3 : -1;
 }
 
 // Work list for per-job step counts and flags (jobs with 0 steps get no item).
 int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vector<uint32_t>& jflags) {
   std::vector<FusedArgs> hj;
-  std::vector<BatchItem> hi;
+  std::vector<BatchItem> hi, split;
   std::vector<double> cost;
   size_t lds_words = 0;
   for (size_t jx = 0; jx < b->jobs.size(); ++jx) {
@@ -86,6 +112,24 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     if (mode < 0)
       return pt_fail(PT_EINVAL, "pt_batch_run: job " + std::to_string(jx) +
                                     " does not fit one workgroup's LDS for these flags (use pt_mcs)");
+    if (mode == 3) {
+      FusedArgs A = make_fused_args(j->g, j->split_lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
+                                    j->thrpt, j->M, j->mom, j->ctr, mcs, false, meas);
+      A.parts = j->split_parts;
+      A.R = j->split_R;
+      A.jlds = j->split_jlds;
+      A.Ex = j->Ex;
+      A.snap = j->snap;
+      A.bar = j->bar;
+      hj.push_back(A);
+      lds_words = std::max(lds_words, (size_t)j->split_lay.words);
+      if (mcs <= 0) continue;
+      // the parts of a sample are consecutive, and split samples go first so
+      // that all parts are taken while every workgroup is still free
+      for (int s = 0; s < j->g.S; ++s)
+        for (int p = 0; p < j->split_parts; ++p) split.push_back(BatchItem{(int)jx, s, p, 0});
+      continue;
+    }
     const int nsets = mode == 2 ? 1 : 2;
     hj.push_back(make_fused_args(j->g, j->plan[mode], j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
                                  j->thrpt, j->M, j->mom, j->ctr, mcs, hou, meas));
@@ -106,6 +150,8 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     for (size_t i = 0; i < idx.size(); ++i) sorted[i] = hi[idx[i]];
     hi.swap(sorted);
   }
+  hi.insert(hi.begin(), split.begin(), split.end());
+  b->has_split = !split.empty();
   hipError_t e = hipSuccess;
   if ((int)hj.size() > b->cap_jobs) {
     if (b->d_jobs) (void)hipFree(b->d_jobs);
@@ -163,8 +209,11 @@ int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
 int run_once(pt_batch* b, bool use_graph) {
   if (b->nitems == 0) return PT_OK;
   if (!use_graph) {
-    const hipError_t e = launch_batch(b->d, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems,
-                                      b->d_queue, b->blocks, b->cfg.threads, b->lds_bytes, b->stream);
+    auto launch = [&] {
+      return launch_batch(b->d, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems, b->d_queue,
+                          b->blocks, b->cfg.threads, b->lds_bytes, b->stream);
+    };
+    const hipError_t e = b->has_split ? ordered_split_launch(b->stream, launch) : launch();
     if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
     return PT_OK;
   }
@@ -192,7 +241,8 @@ int run_once(pt_batch* b, bool use_graph) {
     }
     b->graph_ok = true;
   }
-  const hipError_t e = hipGraphLaunch(b->exec, b->stream);
+  auto replay = [&] { return hipGraphLaunch(b->exec, b->stream); };
+  const hipError_t e = b->has_split ? ordered_split_launch(b->stream, replay) : replay();
   if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
   return PT_OK;
 }
@@ -305,6 +355,19 @@ int batch_round(pt_batch* b, const std::vector<pt_job*>& jobs, const std::vector
   if (int rc = build_worklist_ex(b, steps, flags)) return rc;
   return run_once(b, false);
 }
+
+int batch_run_job(pt_batch* b, pt_job* job, int mcs, uint32_t flags) {
+  if (b->jobs.size() != 1 || b->jobs[0] != job) {
+    b->jobs.assign(1, job);
+    b->d = job->g.d;
+    b->built = false;
+  }
+  b->stream = job->stream;
+  if (int rc = build_worklist(b, mcs, flags)) return rc;
+  return run_once(b, false);
+}
+
+int job_plan_mode(const pt_job* j, uint32_t flags) { return job_mode(j, flags, BatchConfig{}); }
 
 void batch_free(pt_batch* b) {
   if (!b) return;

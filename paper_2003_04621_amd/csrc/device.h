@@ -78,13 +78,14 @@ __device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t k1) {
 }
 
 // (mask << 1) | (r < t): the borrow of r - t shifted into the mask, two VALU
-// instructions (t wave-uniform).
+// instructions.  t is a per-lane value (lanes of one wavefront may serve
+// lattices at different temperatures).
 __device__ __forceinline__ uint32_t shift_in_less(uint32_t mask, uint32_t r, uint32_t t) {
   uint32_t out, tmp;
-  asm("v_subrev_co_u32_e32 %1, vcc, %3, %2\n\t"
+  asm("v_sub_co_u32_e32 %1, vcc, %2, %3\n\t"
       "v_addc_co_u32_e32 %0, vcc, %4, %4, vcc"
       : "=v"(out), "=&v"(tmp)
-      : "v"(r), "s"(t), "v"(mask)
+      : "v"(r), "v"(t), "v"(mask)
       : "vcc");
   return out;
 }

@@ -79,6 +79,26 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// Moments of one temperature from the energies of its two replicas and the
+// number of sites where they differ: sum E (both replicas), sum E^2, q, |q|,
+// q^2 and q^4 as a 128-bit (lo, hi) pair, with Q = N q = N - 2 neg.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void add_moments(const Geo& g, int64_t* m, int32_t ea, int32_t eb, int neg) {
+  const int64_t Q = (int64_t)g.N - 2 * (int64_t)neg;
+  const int64_t Ea = ea, Eb = eb;
+  m[0] += Ea + Eb;
+  m[1] += Ea * Ea + Eb * Eb;
+  m[2] += Q;
+  m[3] += Q < 0 ? -Q : Q;
+  const uint64_t q2 = (uint64_t)(Q * Q);
+  m[4] += (int64_t)q2;
+  const uint64_t q4lo = q2 * q2, q4hi = __umul64hi(q2, q2);
+  const uint64_t lo = (uint64_t)m[5] + q4lo;
+  m[5] = (int64_t)lo;
+  m[6] = (int64_t)((uint64_t)m[6] + q4hi + (lo < q4lo ? 1u : 0u));
+}
+
+// ---------------------------------------------------------------------------
 // Measurement of every temperature of the resident sample.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* lds) {
@@ -100,23 +120,8 @@ __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* l
     if (neg) atomicAdd(&qneg[k], neg);
   }
   __syncthreads();
-  if (tid < NT) {
-    const int k = tid;
-    const int a = sotl[k], b = NT + sotl[NT + k];
-    const int64_t Q = (int64_t)g.N - 2 * (int64_t)qneg[k];
-    const int64_t Ea = El[a], Eb = El[b];
-    int64_t* m = mom + (size_t)k * 8;
-    m[0] += Ea + Eb;
-    m[1] += Ea * Ea + Eb * Eb;
-    m[2] += Q;
-    m[3] += Q < 0 ? -Q : Q;
-    const uint64_t q2 = (uint64_t)(Q * Q);
-    m[4] += (int64_t)q2;
-    const uint64_t q4lo = q2 * q2, q4hi = __umul64hi(q2, q2);
-    const uint64_t lo = (uint64_t)m[5] + q4lo;
-    m[5] = (int64_t)lo;
-    m[6] = (int64_t)((uint64_t)m[6] + q4hi + (lo < q4lo ? 1u : 0u));
-  }
+  for (int k = tid; k < NT; k += T)
+    add_moments(g, mom + (size_t)k * 8, El[sotl[k]], El[NT + sotl[NT + k]], qneg[k]);
   __syncthreads();
 }
 
@@ -264,7 +269,7 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
 // workgroups at the same time.
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ void run_sample(const FusedArgs& A, uint32_t* lds, int s, int c_lo, int nsets) {
+__device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, int s, int c_lo, int nsets) {
   const Geo& g = A.g;
   const int T = blockDim.x, tid = threadIdx.x;
   const int NW = g.NW, NT = g.NT, nslot = g.nslot, W2 = 2 * NW;
@@ -344,12 +349,179 @@ __device__ void run_sample(const FusedArgs& A, uint32_t* lds, int s, int c_lo, i
     for (int i = tid; i < 8 * NT; i += T) A.mom[(size_t)s * NT * 8 + i] = mom[i];
 }
 
+// ---------------------------------------------------------------------------
+// Samples too large for one workgroup.  The 2 N_T configurations of a sample
+// are split into `parts` groups of R slots, one workgroup each, for all steps
+// of the launch: a replica exchange only relabels temperatures, so a
+// configuration never changes workgroup.  Each step every part publishes the
+// energies of its slots (and, when measuring, their configurations) to
+// parity-double-buffered global scratch and meets the other parts at a
+// per-sample counter barrier; then every part takes the same exchange
+// decisions from the same energies and Philox words, so the maps agree
+// without further communication, and temperature k is measured by part
+// k mod parts from the published configurations.  A part overwrites a
+// parity buffer two steps later, after a barrier that every reader of it has
+// passed.
+// ---------------------------------------------------------------------------
+
+// About 60 s of the 100 MHz constant clock: far beyond any legitimate wait
+// (all parts of a sample are taken from the queue together), so reaching it
+// means the job's state can no longer be trusted.
+constexpr uint64_t kBarrierTicks = 6000000000ull;
+
+// Arrives at a sample's barrier and waits for `target` arrivals in all.
+// Returns false if the wait gave up; the job's fault word is then set, and
+// every later wait of the job gives up at once.
+__device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uint32_t* fault,
+                                             int* flag) {
+  __threadfence();  // this thread's published data, device-wide
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 > kBarrierTicks) {
+        __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *flag = good;
+  }
+  __syncthreads();
+  __threadfence();  // the other parts' data, for every thread
+  return *flag != 0;
+}
+
+// Overlap and moments of the temperatures this part owns (k = part mod
+// parts), from the configurations published this step (`pub`: [nslot][2NW]).
+__device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds, int part,
+                                              const uint32_t* pub) {
+  const Geo& g = A.g;
+  const int NT = g.NT, W2 = 2 * g.NW, tid = threadIdx.x, T = blockDim.x;
+  const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
+  const int32_t* sotl = reinterpret_cast<const int32_t*>(lds + A.lay.sot);
+  int32_t* qneg = reinterpret_cast<int32_t*>(lds + A.lay.qneg);
+  int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
+  for (int k = part + tid * A.parts; k < NT; k += T * A.parts) qneg[k] = 0;
+  __syncthreads();
+  for (int k = part; k < NT; k += A.parts) {
+    const uint32_t* Wa = pub + (size_t)sotl[k] * W2;
+    const uint32_t* Wb = pub + (size_t)(NT + sotl[NT + k]) * W2;
+    int neg = 0;
+    for (int i = tid; i < W2; i += T) neg += __popc(Wa[i] ^ Wb[i]);
+    neg = wave_sum(neg);
+    if ((tid & 63) == 0 && neg) atomicAdd(&qneg[k], neg);
+  }
+  __syncthreads();
+  for (int k = part + tid * A.parts; k < NT; k += T * A.parts)
+    add_moments(g, mom + (size_t)k * 8, El[sotl[k]], El[NT + sotl[NT + k]], qneg[k]);
+  __syncthreads();
+}
+
+// nmcs Monte Carlo steps (sweep, exchange, measurement) of part `part` of
+// split sample s.
 template <int D>
-__global__ void __launch_bounds__(1024) k_mcs(FusedArgs A, int nsets) {
-  extern __shared__ uint32_t lds[];
-  const int s = blockIdx.x / (3 - nsets);  // nsets == 1: two workgroups per sample
-  const int c_lo = nsets == 2 ? 0 : (int)(blockIdx.x & 1);
-  run_sample<D>(A, lds, s, c_lo, nsets);
+__device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int s, int part,
+                                          int* flag) {
+  const Geo& g = A.g;
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int NW = g.NW, NT = g.NT, nslot = g.nslot, W2 = 2 * NW;
+  const int slot0 = part * A.R, nres = min(A.R, nslot - slot0);
+  uint32_t* W = lds + A.lay.W;
+  int32_t* El = reinterpret_cast<int32_t*>(lds + A.lay.E);
+  int32_t* sotl = reinterpret_cast<int32_t*>(lds + A.lay.sot);
+  int32_t* tosl = reinterpret_cast<int32_t*>(lds + A.lay.tos);
+  uint32_t* thrl = lds + A.lay.thr;
+  int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
+  const size_t lat0 = (size_t)s * nslot + slot0;
+  const bool meas = A.meas != 0;
+
+  // ---- load this part's slots and the sample's shared state
+  const int items = nres * NW;
+  if (g.layout == kLayoutPacked) {
+    const uint32_t* src = static_cast<const uint32_t*>(A.spins) + lat0 * W2;
+    for (int i = tid; i < nres * W2; i += T) W[i] = src[i];
+  } else {
+    const int8_t* src = static_cast<const int8_t*>(A.spins) + lat0 * g.N;
+    for (int it = tid; it < items; it += T) {
+      const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+      word_from_int8(g, src + (size_t)ls * g.N, w, W[ls * W2 + w], W[ls * W2 + NW + w]);
+    }
+  }
+  const uint32_t* Jsrc = A.jw + (size_t)s * 2 * 2 * D * NW;
+  if (A.jlds) {
+    uint32_t* Jl = lds + A.lay.J;
+    for (int i = tid; i < 2 * 2 * D * NW; i += T) Jl[i] = Jsrc[i];
+    Jsrc = Jl;
+  }
+  for (int i = tid; i < nslot; i += T) El[i] = A.E[(size_t)s * nslot + i];
+  for (int i = tid; i < 2 * NT; i += T) {
+    sotl[i] = A.sot[(size_t)s * 2 * NT + i];
+    tosl[i] = A.tos[(size_t)s * 2 * NT + i];
+  }
+  for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
+  if (meas)
+    for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
+  const uint32_t t0 = A.ctr->t, u0 = A.ctr->u;
+  uint32_t* bar = A.bar + s;
+  uint32_t* fault = A.bar + g.S;
+  int32_t* Ex = A.Ex + (size_t)s * 2 * nslot;
+  uint32_t* snap = A.snap + (size_t)s * 2 * nslot * W2;
+  __syncthreads();
+
+  for (int step = 0; step < A.nmcs; ++step) {
+    const uint32_t t = t0 + (uint32_t)step;
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t* Jc = Jsrc + c * 2 * D * NW;
+      for (int it = tid; it < items; it += T) {
+        const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+        const int slot = slot0 + ls;
+        const int k = tosl[slot];
+        int dE = 0;
+        sweep_word<D>(g, W + ls * W2, Jc, c, w, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
+                      thrl[k * 4 + 2], dE);
+        if (dE) atomicAdd(&El[slot], dE);
+      }
+      __syncthreads();
+    }
+    // publish, meet, and take the sample-wide steps
+    const int par = step & 1;
+    for (int i = tid; i < nres; i += T) Ex[par * nslot + slot0 + i] = El[slot0 + i];
+    if (meas) {
+      uint32_t* dst = snap + ((size_t)par * nslot + slot0) * W2;
+      for (int i = tid; i < nres * W2; i += T) dst[i] = W[i];
+    }
+    if (!part_barrier(bar, (uint32_t)(A.parts * (step + 1)), fault, flag)) break;
+    for (int i = tid; i < nslot; i += T) El[i] = Ex[par * nslot + i];
+    __syncthreads();
+    exchange_resident(A, lds, s, u0 + (uint32_t)step, 0, 2);
+    if (meas) measure_split(A, lds, part, snap + (size_t)par * nslot * W2);
+  }
+
+  // ---- store this part's slots; part 0 stores the maps, owners the moments
+  if (g.layout == kLayoutPacked) {
+    uint32_t* dst = static_cast<uint32_t*>(A.spins) + lat0 * W2;
+    for (int i = tid; i < nres * W2; i += T) dst[i] = W[i];
+  } else {
+    int8_t* dst = static_cast<int8_t*>(A.spins) + lat0 * g.N;
+    for (int it = tid; it < items; it += T) {
+      const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+      word_to_int8(g, dst + (size_t)ls * g.N, w, W[ls * W2 + w], W[ls * W2 + NW + w]);
+    }
+  }
+  for (int i = tid; i < nres; i += T) A.E[lat0 + i] = El[slot0 + i];
+  if (part == 0)
+    for (int i = tid; i < 2 * NT; i += T) {
+      A.sot[(size_t)s * 2 * NT + i] = sotl[i];
+      A.tos[(size_t)s * 2 * NT + i] = tosl[i];
+    }
+  if (meas)
+    for (int k = part; k < NT; k += A.parts)
+      for (int i = tid; i < 8; i += T) A.mom[((size_t)s * NT + k) * 8 + i] = mom[k * 8 + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -362,7 +534,7 @@ __global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jo
                                                 const BatchItem* __restrict__ items, int nitems,
                                                 uint32_t* queue) {
   extern __shared__ uint32_t lds[];
-  __shared__ int cur;
+  __shared__ int cur, flag;
   for (;;) {
     if (threadIdx.x == 0) cur = (int)atomicAdd(queue, 1u);
     __syncthreads();
@@ -371,13 +543,26 @@ __global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jo
     if (i >= nitems) break;
     const BatchItem it = items[i];
     const FusedArgs A = jobs[it.job];
-    if (A.nmcs > 0) run_sample<D>(A, lds, it.sample, it.c_lo, it.nsets);
+    if (A.nmcs > 0) {
+      if (it.nsets == 0)
+        run_split<D>(A, lds, it.sample, it.c_lo, &flag);
+      else
+        run_sample<D>(A, lds, it.sample, it.c_lo, it.nsets);
+    }
     __syncthreads();
   }
 }
 
-__global__ void k_batch_reset(uint32_t* queue) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
+// Clears the queue and the barrier counters of every split job (block j
+// serves job j - 1).
+__global__ void k_batch_reset(const FusedArgs* __restrict__ jobs, uint32_t* queue) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *queue = 0u;
+    return;
+  }
+  const FusedArgs& A = jobs[blockIdx.x - 1];
+  if (A.parts == 0) return;
+  for (int i = threadIdx.x; i < A.g.S; i += blockDim.x) A.bar[i] = 0u;
 }
 
 // Advances every job's counters by its own number of steps in this launch.
@@ -428,6 +613,49 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) 
   return off <= budget;
 }
 
+bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
+  const size_t budget = (160 * 1024 - 512) / 4;
+  const size_t W2 = 2 * (size_t)g.NW, Jw = 2 * 2 * (size_t)g.d * g.NW;
+  for (int jl = 1; jl >= 0; --jl) {
+    // everything but the slots' words
+    size_t fixed = jl ? Jw : 0;
+    fixed += g.nslot + 3 * 2 * (size_t)g.NT + 4 * (size_t)g.NT;
+    fixed = (fixed + 1) / 2 * 2 + 16 * (size_t)g.NT;
+    fixed += g.NT + 2 * (size_t)g.NT + (2 * (size_t)g.NT * g.NT + 3) / 4;
+    if (fixed >= budget) continue;
+    const size_t rmax = std::min<size_t>((budget - fixed) / W2, (size_t)g.nslot);
+    if (rmax < 1 || (jl && rmax < std::min(g.nslot, 8))) continue;
+    const int p = (int)((g.nslot + rmax - 1) / rmax);
+    if (p > kMaxParts) continue;
+    R = (g.nslot + p - 1) / p;
+    parts = (g.nslot + R - 1) / R;
+    jlds = jl;
+    size_t off = 0;
+    auto take = [&](size_t words, size_t align) {
+      off = (off + align - 1) / align * align;
+      const size_t at = off;
+      off += words;
+      return (int)at;
+    };
+    lay.W = take((size_t)R * W2, 1);
+    lay.J = take(jl ? Jw : 0, 1);
+    lay.E = take(g.nslot, 1);
+    lay.sot = take(2 * g.NT, 1);
+    lay.tos = take(2 * g.NT, 1);
+    lay.sot0 = take(2 * g.NT, 1);
+    lay.thr = take(4 * g.NT, 1);
+    lay.mom = take(16 * (size_t)g.NT, 2);
+    lay.qneg = take(g.NT, 1);
+    lay.rpt = take(2 * g.NT, 1);
+    lay.acc = take((2 * (size_t)g.NT * g.NT + 3) / 4, 1);
+    lay.PC = 0;
+    lay.Qs = lay.Cs = lay.hcnt = lay.hdelta = (int)off;
+    lay.words = (int)off;
+    return off <= budget;
+  }
+  return false;
+}
+
 FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
                           int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
                           const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
@@ -449,6 +677,10 @@ FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, con
   A.meas = meas ? 1 : 0;
   A.magicNW = (uint32_t)((0x100000000ull + (uint64_t)g.NW - 1) / (uint64_t)g.NW);
   A.lay = lay;
+  A.parts = A.R = A.jlds = 0;
+  A.Ex = nullptr;
+  A.snap = nullptr;
+  A.bar = nullptr;
   return A;
 }
 
@@ -458,26 +690,13 @@ static hipError_t lds_attr(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-hipError_t launch_mcs_fused(const FusedArgs& A, int nsets, hipStream_t st) {
-  const size_t bytes = (size_t)A.lay.words * 4;
-  const dim3 grid((unsigned)(A.g.S * (3 - nsets))), block(1024);
-  if (A.g.d == 3) {
-    if (hipError_t e = lds_attr(k_mcs<3>, bytes)) return e;
-    hipLaunchKernelGGL(k_mcs<3>, grid, block, bytes, st, A, nsets);
-  } else {
-    if (hipError_t e = lds_attr(k_mcs<2>, bytes)) return e;
-    hipLaunchKernelGGL(k_mcs<2>, grid, block, bytes, st, A, nsets);
-  }
-  return hipGetLastError();
-}
-
 hipError_t prepare_batch(int d, size_t lds_bytes) {
   return d == 3 ? lds_attr(k_batch<3>, lds_bytes) : lds_attr(k_batch<2>, lds_bytes);
 }
 
 hipError_t launch_batch(int d, const FusedArgs* jobs, int njobs, const BatchItem* items, int nitems,
                         uint32_t* queue, int blocks, int threads, size_t lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, queue);
+  hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)njobs + 1), dim3(256), 0, st, jobs, queue);
   if (d == 3)
     hipLaunchKernelGGL(k_batch<3>, dim3(blocks), dim3(threads), lds_bytes, st, jobs, items, nitems,
                        queue);

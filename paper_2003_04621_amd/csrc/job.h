@@ -31,7 +31,16 @@ struct pt_job {
   // fused-step LDS plans: both sets without / with Houdayer, one set
   ptsg::FusedLayout plan[3];
   bool fused_ok[3] = {false, false, false};
+  // split-sample plan (samples whose sets do not fit one workgroup) and its
+  // scratch: published energies / configurations and barrier counters
+  ptsg::FusedLayout split_lay{};
+  bool split_ok = false;
+  int split_parts = 0, split_R = 0, split_jlds = 0;
+  int32_t* Ex = nullptr;     // [S][2][2NT]
+  uint32_t* snap = nullptr;  // [S][2][2NT][2NW]
+  uint32_t* bar = nullptr;   // [S] barrier counters + fault word
   bool poisoned = false;
+  struct pt_batch* self_batch = nullptr;  // one-job batch behind pt_mcs
   std::vector<void*> allocs;
   void* (*alloc_fn)(size_t, void*) = nullptr;
   void (*free_fn)(void*, void*) = nullptr;
@@ -71,8 +80,17 @@ pt_batch* batch_new(hipStream_t st);
 int batch_round(pt_batch* b, const std::vector<pt_job*>& jobs, const std::vector<int>& steps,
                 const std::vector<uint32_t>& flags);
 void batch_free(pt_batch* b);
-// Whether job j can run `flags` fused with at least one replica set resident.
+// mcs fused steps of one job through its own one-job batch (work list cached
+// while mcs and flags repeat).
+int batch_run_job(pt_batch* b, pt_job* job, int mcs, uint32_t flags);
+// Whether job j can run `flags` fused (some workgroup plan fits).
 bool job_is_resident(const pt_job* j, uint32_t flags);
+// The fused plan a job alone takes for `flags` (as pt_get_plan), -1 if none.
+int job_plan_mode(const pt_job* j, uint32_t flags);
+// Whether a job of this shape needs the split-sample scratch (its two
+// replica sets do not fit one workgroup together, but a split plan exists),
+// and how many bytes that scratch takes.
+size_t split_scratch_bytes(const ptsg::Geo& g);
 // Device bytes a job of this shape allocates (an upper bound).
 size_t job_device_bytes(int S, int NT, int L, int d, int layout, const double* betas);
 // Length of a row of the exchange threshold table.

@@ -64,27 +64,40 @@ struct FusedArgs {
   int nmcs, hou, meas;
   uint32_t magicNW;  // item / NW
   FusedLayout lay;
+  // Split samples (parts > 0): part p of a sample holds slots [p R, p R + R),
+  // couplings in LDS iff jlds.  Ex [S][2][nslot] and snap [S][2][nslot][2NW]
+  // are the parity-buffered published energies and configurations, bar [S+1]
+  // the per-sample barrier counters followed by the job's fault word.
+  int parts, R, jlds;
+  int32_t* Ex;
+  uint32_t* snap;
+  uint32_t* bar;
 };
 
 // One work item of the persistent batch kernel: replica sets
-// [c_lo, c_lo + nsets) of sample `sample` of job `job`.
+// [c_lo, c_lo + nsets) of sample `sample` of job `job`, or with nsets == 0
+// part c_lo of a split sample (the parts of a sample are consecutive items).
 struct BatchItem {
   int job, sample, c_lo, nsets;
 };
+
+// Most workgroups one split sample may use (all of them must be running at
+// the same time).
+constexpr int kMaxParts = 64;
 
 // Plans the LDS of a fused workgroup holding `nsets` replica sets of one
 // sample (`waves` wavefronts); false if it does not fit in 160 KiB.
 bool fused_plan(const Geo& g, bool houdayer, int nsets, int waves, FusedLayout& lay);
 
+// Plans a split sample: the fewest parts (<= kMaxParts) whose R slots fit one
+// workgroup's LDS, with the couplings in LDS when that still leaves room for
+// min(2 N_T, 8) slots.  False if even one slot does not fit.
+bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds);
+
 FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
                           int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
                           const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
                           int nmcs, bool houdayer, bool measure);
-
-// A.nmcs whole Monte Carlo steps of every sample (one or two workgroups per
-// sample, 1024 threads); the counters are read, not advanced (enqueue
-// launch_advance afterwards).
-hipError_t launch_mcs_fused(const FusedArgs& A, int nsets, hipStream_t st);
 
 // Persistent batch: resets the queue, runs every item to its job's nmcs, then
 // advances each job's counters.  `jobs` and `items` are device arrays.

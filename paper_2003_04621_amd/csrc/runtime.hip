@@ -50,6 +50,34 @@ uint32_t threshold_u32(double p) {
   return (uint32_t)v;
 }
 
+
+// Lattice and word geometry of a job (Sec. 2.2 layout).
+Geo make_geo(int S, int NT, int L, int dim, int layout, uint64_t seed) {
+  Geo g{};
+  g.L = L;
+  g.d = dim;
+  g.N = dim == 3 ? L * L * L : L * L;
+  g.NR = g.N / L;
+  g.H = L / 2;
+  g.G = (L + 7) / 8;
+  g.magicL = (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L);
+  g.maskH = (g.H == 32) ? 0xFFFFFFFFu : ((1u << g.H) - 1u);
+  g.P = fields_per_word(L);
+  g.B = L / g.P;
+  g.NW = g.NR / g.P;
+  g.maskW = (g.P * g.H == 32) ? 0xFFFFFFFFu : ((1u << (g.P * g.H)) - 1u);
+  g.LB = 0;
+  for (int f = 0; f < g.P; ++f) g.LB |= 1u << (f * g.H);
+  g.HB = g.LB << (g.H - 1);
+  g.S = S;
+  g.NT = NT;
+  g.nslot = 2 * NT;
+  g.layout = layout;
+  g.key0 = (uint32_t)seed;
+  g.key1 = (uint32_t)(seed >> 32);
+  return g;
+}
+
 }  // namespace
 
 
@@ -69,6 +97,22 @@ int device_error(pt_job* job, hipError_t e, const char* where) {
 int check_job(pt_job* job) {
   if (!job) return pt_fail(PT_EINVAL, "null job handle");
   if (job->poisoned) return pt_fail(PT_ESTATE, "job is poisoned by an earlier device error");
+  return PT_OK;
+}
+
+// Waits for the job's stream and fails if a split sample's barrier gave up
+// (the job's state is then unusable).
+int check_fault(pt_job* job) {
+  if (!job->bar) return PT_OK;
+  uint32_t fault = 0;
+  hipError_t e = hipMemcpyAsync(&fault, job->bar + job->g.S, sizeof(fault), hipMemcpyDeviceToHost,
+                                job->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(job->stream);
+  if (e != hipSuccess) return device_error(job, e, "pt_get_*");
+  if (fault) {
+    job->poisoned = true;
+    return pt_fail(PT_EDEVICE, "a split sample's workgroups lost contact (barrier timed out)");
+  }
   return PT_OK;
 }
 
@@ -167,28 +211,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   job->free_fn = free_;
   job->alloc_ctx = ctx;
   job->stream = stream;
-  Geo& g = job->g;
-  g.L = L;
-  g.d = dim;
-  g.N = (int)N;
-  g.NR = (int)(N / L);
-  g.H = L / 2;
-  g.G = (L + 7) / 8;
-  g.magicL = (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L);
-  g.maskH = (g.H == 32) ? 0xFFFFFFFFu : ((1u << g.H) - 1u);
-  g.P = fields_per_word(L);
-  g.B = L / g.P;
-  g.NW = g.NR / g.P;
-  g.maskW = (g.P * g.H == 32) ? 0xFFFFFFFFu : ((1u << (g.P * g.H)) - 1u);
-  g.LB = 0;
-  for (int f = 0; f < g.P; ++f) g.LB |= 1u << (f * g.H);
-  g.HB = g.LB << (g.H - 1);
-  g.S = samples;
-  g.NT = replicas;
-  g.nslot = 2 * replicas;
-  g.layout = (int)flags;
-  g.key0 = (uint32_t)seed;
-  g.key1 = (uint32_t)(seed >> 32);
+  job->g = make_geo(samples, replicas, L, dim, (int)flags, seed);
+  const Geo& g = job->g;
 
   // Metropolis thresholds: x = 2m (m = 1..d), energy change 4m.
   std::vector<uint32_t> thr((size_t)replicas * 4, 0u);
@@ -210,6 +234,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0]);
   job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1]);
   job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2]);
+  job->split_ok = !job->fused_ok[0] &&
+                  split_plan(g, job->split_lay, job->split_parts, job->split_R, job->split_jlds);
 
   const size_t maps = sizeof(int32_t) * (size_t)samples * 2 * replicas;
   job->spins = job->dalloc(job->spin_bytes());
@@ -222,8 +248,16 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   job->ctr = (DevCounters*)job->dalloc(sizeof(DevCounters));
   job->mom = (int64_t*)job->dalloc(sizeof(int64_t) * 8 * (size_t)samples * replicas);
   int8_t* J8 = (int8_t*)job->dalloc((size_t)ncoup);
+  bool split_mem = true;
+  if (job->split_ok) {
+    const size_t W2 = 2 * (size_t)g.NW, per = (size_t)samples * 2 * g.nslot;
+    job->Ex = (int32_t*)job->dalloc(sizeof(int32_t) * per);
+    job->snap = (uint32_t*)job->dalloc(sizeof(uint32_t) * per * W2);
+    job->bar = (uint32_t*)job->dalloc(sizeof(uint32_t) * ((size_t)samples + 1));
+    split_mem = job->Ex && job->snap && job->bar;
+  }
   if (!job->spins || !job->jw || !job->E || !job->sot || !job->tos || !job->thr || !job->thrpt ||
-      !job->ctr || !job->mom || !J8) {
+      !job->ctr || !job->mom || !J8 || !split_mem) {
     job->release();
     delete job;
     return pt_fail(PT_ENOMEM, "device allocation failed");
@@ -244,6 +278,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   step(hipMemcpyAsync(job->tos, ident.data(), maps, hipMemcpyHostToDevice, st));
   step(hipMemsetAsync(job->ctr, 0, sizeof(DevCounters), st));
   step(hipMemsetAsync(job->mom, 0, sizeof(int64_t) * 8 * (size_t)samples * replicas, st));
+  if (job->bar) step(hipMemsetAsync(job->bar, 0, sizeof(uint32_t) * ((size_t)samples + 1), st));
   step(launch_pack_couplings(g, J8, job->jw, st));
   step(launch_init_spins(g, job->spins, st));
   step(launch_energy(g, job->spins, job->jw, job->E, st));
@@ -266,8 +301,7 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
 
 bool job_is_resident(const pt_job* j, uint32_t flags) {
   if (flags & PT_MCS_HOUDAYER) return j->fused_ok[1];
-  if (flags & PT_MCS_MEASURE) return j->fused_ok[0];
-  return j->fused_ok[0] || j->fused_ok[2];
+  return j->fused_ok[0] || j->fused_ok[2] || j->split_ok;
 }
 
 int pt_table_len(const double* betas, int NT, int d, long N) {
@@ -282,6 +316,14 @@ int pt_table_len(const double* betas, int NT, int d, long N) {
   return M;
 }
 
+size_t split_scratch_bytes(const Geo& g) {
+  FusedLayout lay;
+  int parts, R, jlds;
+  if (fused_plan(g, false, 2, 16, lay) || !split_plan(g, lay, parts, R, jlds)) return 0;
+  const size_t per = (size_t)g.S * 2 * g.nslot;
+  return sizeof(int32_t) * per + sizeof(uint32_t) * per * 2 * g.NW + sizeof(uint32_t) * (g.S + 1);
+}
+
 size_t job_device_bytes(int S, int NT, int L, int d, int layout, const double* betas) {
   const size_t N = (d == 3) ? (size_t)L * L * L : (size_t)L * L;
   const size_t NW = N / L / fields_per_word(L);
@@ -290,7 +332,7 @@ size_t job_device_bytes(int S, int NT, int L, int d, int layout, const double* b
   const size_t jw = (size_t)S * 2 * 2 * d * NW * 4;
   const size_t small = sizeof(int32_t) * (lat + 4 * (size_t)S * NT) + sizeof(int64_t) * 8 * S * NT +
                        sizeof(uint32_t) * (size_t)NT * (4 + pt_table_len(betas, NT, d, (long)N)) + 4096;
-  return spins + jw + (size_t)S * d * N + small;
+  return spins + jw + (size_t)S * d * N + small + split_scratch_bytes(make_geo(S, NT, L, d, layout, 0));
 }
 
 PT_API int pt_init(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
@@ -302,6 +344,7 @@ PT_API int pt_destroy(pt_job* job) {
   if (!job) return pt_fail(PT_EINVAL, "null job handle");
   (void)hipStreamSynchronize(job->stream);
   (void)hipGetLastError();
+  if (job->self_batch) batch_free(job->self_batch);
   job->release();
   delete job;
   return PT_OK;
@@ -359,30 +402,20 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   const Geo& g = job->g;
   hipStream_t st = job->stream;
   const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
-  // fused: both sets per workgroup if they fit (needed for Houdayer and the
-  // overlap), otherwise one set per workgroup for sweep + exchange
-  int mode = -1;
-  if (!(flags & PT_MCS_PLAIN)) {
-    if (hou)
-      mode = job->fused_ok[1] ? 1 : -1;
-    else if (job->fused_ok[0])
-      mode = 0;
-    else if (!meas && job->fused_ok[2])
-      mode = 2;
-  }
-  if (mode >= 0) {
-    const int nsets = mode == 2 ? 1 : 2;
+  // fused through the job's one-job batch whenever a workgroup plan exists:
+  // both sets per workgroup, one set per workgroup (no overlap needed), or
+  // the sample split over several workgroups (no Houdayer move)
+  if (!(flags & PT_MCS_PLAIN) && job_is_resident(job, flags)) {
+    if (!job->self_batch) job->self_batch = batch_new(st);
+    if (!job->self_batch) return pt_fail(PT_ENOMEM, "pt_mcs: host allocation failed");
     const int chunk = 500;
     for (int done = 0; done < n; done += chunk) {
       const int m = (n - done) < chunk ? (n - done) : chunk;
-      const FusedArgs A = make_fused_args(g, job->plan[mode], job->spins, job->jw, job->E, job->sot,
-                                          job->tos, job->thr, job->thrpt, job->M, job->mom, job->ctr,
-                                          m, hou, meas);
-      PT_HIP(job, launch_mcs_fused(A, nsets, st));
-      PT_HIP(job, launch_advance(job->ctr,
-                                 CounterStep{(uint32_t)m, (uint32_t)m, hou ? (uint32_t)m : 0u,
-                                             meas ? (uint32_t)m : 0u},
-                                 st));
+      const int rc = batch_run_job(job->self_batch, job, m, flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE));
+      if (rc != PT_OK) {
+        job->poisoned = rc == PT_EDEVICE;
+        return rc;
+      }
     }
     return PT_OK;
   }
@@ -398,11 +431,34 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   return PT_OK;
 }
 
+PT_API int pt_get_plan(pt_job* job, uint32_t flags, int32_t* out4) {
+  if (int rc = check_job(job)) return rc;
+  if (!out4) return pt_fail(PT_EINVAL, "null output");
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
+    return pt_fail(PT_EINVAL, "unknown flags");
+  const Geo& g = job->g;
+  const int mode = (flags & PT_MCS_PLAIN) ? -1 : job_plan_mode(job, flags);
+  out4[0] = mode;
+  if (mode < 0) {
+    out4[1] = out4[2] = out4[3] = 0;
+  } else if (mode == 3) {
+    out4[1] = job->split_parts;
+    out4[2] = job->split_R;
+    out4[3] = 4 * job->split_lay.words;
+  } else {
+    out4[1] = mode == 2 ? 2 : 1;
+    out4[2] = mode == 2 ? g.NT : g.nslot;
+    out4[3] = 4 * job->plan[mode].words;
+  }
+  return PT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // synchronous state access
 // ---------------------------------------------------------------------------
 PT_API int pt_get_counters(pt_job* job, uint64_t* out) {
   if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
   if (!out) return pt_fail(PT_EINVAL, "null output");
   DevCounters c;
   PT_HIP(job, hipMemcpyAsync(&c, job->ctr, sizeof(c), hipMemcpyDeviceToHost, job->stream));
@@ -416,6 +472,7 @@ PT_API int pt_get_counters(pt_job* job, uint64_t* out) {
 
 PT_API int pt_get_spins(pt_job* job, int8_t* out) {
   if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
   if (!out) return pt_fail(PT_EINVAL, "null output");
   const Geo& g = job->g;
   if (g.layout == kLayoutPacked) {
@@ -455,6 +512,7 @@ PT_API int pt_set_spins(pt_job* job, const int8_t* in) {
 
 PT_API int pt_get_energies(pt_job* job, int32_t* out) {
   if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
   if (!out) return pt_fail(PT_EINVAL, "null output");
   const size_t n = (size_t)job->g.S * job->g.nslot;
   PT_HIP(job, hipMemcpyAsync(out, job->E, sizeof(int32_t) * n, hipMemcpyDeviceToHost, job->stream));
@@ -464,6 +522,7 @@ PT_API int pt_get_energies(pt_job* job, int32_t* out) {
 
 PT_API int pt_get_maps(pt_job* job, int32_t* slot_of_temp, int32_t* temp_of_slot) {
   if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
   const size_t n = sizeof(int32_t) * (size_t)job->g.S * 2 * job->g.NT;
   if (slot_of_temp)
     PT_HIP(job, hipMemcpyAsync(slot_of_temp, job->sot, n, hipMemcpyDeviceToHost, job->stream));
@@ -475,6 +534,7 @@ PT_API int pt_get_maps(pt_job* job, int32_t* slot_of_temp, int32_t* temp_of_slot
 
 PT_API int pt_get_moments(pt_job* job, int64_t* out) {
   if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
   if (!out) return pt_fail(PT_EINVAL, "null output");
   const size_t n = (size_t)job->g.S * job->g.NT;
   std::vector<int64_t> m(8 * n);
@@ -488,6 +548,7 @@ PT_API int pt_get_moments(pt_job* job, int64_t* out) {
 
 PT_API int pt_observables(pt_job* job, double* per_sample, double* disorder, int64_t* n_meas) {
   if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
   const Geo& g = job->g;
   const size_t n = (size_t)g.S * g.NT;
   std::vector<int64_t> m(8 * n);
@@ -561,6 +622,7 @@ size_t state_size(const pt_job* job) {
 
 PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
   if (!len) return pt_fail(PT_EINVAL, "null length");
   const size_t need = state_size(job);
   if (!buf) {

@@ -142,10 +142,11 @@ def test_tuner_restores_state_and_caches(pt):
 
 
 def test_batch_rejects_oversized_and_mixed_dims(pt):
+    # a Houdayer move needs both replica sets of a sample in one workgroup
     big = pt.pt_init(1, 48, 64, 3, W.couplings_pm_j(1, 64, 3, 1), W.geometric_betas(0.9, 2, 48), 1)
     batch = pt.pt_batch_create([big])
     with pytest.raises(pt.PTError):
-        pt.pt_batch_run(batch, 1)
+        pt.pt_batch_run(batch, 1, houdayer=True)
     j2 = pt.pt_init(1, 2, 8, 2, W.couplings_pm_j(1, 8, 2, 1), np.array([1.0, 0.5]), 1)
     j3 = pt.pt_init(1, 2, 8, 3, W.couplings_pm_j(1, 8, 3, 1), np.array([1.0, 0.5]), 1)
     with pytest.raises(pt.PTError):
