@@ -6,11 +6,17 @@ replica sets x 32 temperatures (geometric T in [0.9, 2.0]), int8 spins and
 couplings.  One step = one Monte Carlo step of the whole path: a checkerboard
 Metropolis sweep of all 64,000 lattices, one replica-exchange pass and one
 measurement (E, overlap moments).  All inputs are resident on the GPU before
-the timed region.  Steps run fused (one workgroup per sample, the sample
-resident in LDS, `--chunk` steps per launch); the same steps with one launch
-per kernel are timed afterwards for comparison.
+the timed region.  Steps run fused (the persistent kernel, one sample per
+workgroup resident in LDS, `--chunk` steps per launch); the same steps with
+one launch per kernel are timed afterwards for comparison.
 
-Prints one JSON line: spin flips/ns over the timed steps, the sweep kernel's
+Also measured (each its own JSON object): the batched form (2000 jobs of
+uneven L in one graph-replayed persistent launch, int8 and packed layouts,
+against one job per launch) and the served form (Poisson arrivals of mixed-L
+requests at 70% of the measured capacity, HBM-budget admission; p50/p99
+latency and delivered flips/ns).
+
+Prints one JSON line: spin flips/ns over the timed steps, the fused kernel's
 roofline position (VALU-bound: integer issue slots), and the CPU oracle's
 rate on a bounded sample of the same workload.
 """
@@ -99,6 +105,8 @@ def batched_mix(pt, torch, W, args):
         achieved = OPS_PER_FLIP * flips * args.batch_chunk / (launch_ms * 1e-3) / 1e12
         # the same steps, one job per launch (no batch, no graph)
         plain_steps = 2
+        for j in jobs:
+            pt.pt_mcs(j, 1)              # each job's own launch list, built once
         torch.cuda.synchronize()
         tp = time.perf_counter()
         for _ in range(plain_steps):
@@ -123,48 +131,74 @@ def batched_mix(pt, torch, W, args):
     return out
 
 
-def served(pt, torch, W, args, capacity_flips_per_ns):
-    """Poisson arrivals of 3D +-J PT requests: L uniform in {16, 24, 32, 48},
-    16..48 temperatures, 10^3..10^4 steps (log-uniform), half of them burn-in;
-    admission by an HBM budget; p50/p99 of completion minus submission."""
-    rng = np.random.default_rng(args.serve_seed)
-    n = args.serve_requests
+def _requests(W, rng, n, seed0):
+    """n requests of the served mix: 3D +-J, one sample, L uniform in
+    {16, 24, 32, 48}, 16..48 temperatures, 10^3..10^4 steps (log-uniform),
+    half of them burn-in."""
     Ls = rng.choice([16, 24, 32, 48], size=n)
     NTs = rng.integers(16, 49, size=n)
     sweeps = np.exp(rng.uniform(np.log(1e3), np.log(1e4), size=n)).astype(int)
-    flips = 2 * NTs * Ls.astype(np.int64) ** 3 * sweeps
-    mean_flips = float(flips.mean())
-    lam = args.serve_load * capacity_flips_per_ns * 1e9 / mean_flips       # jobs per second
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n))
     reqs = []
     for i in range(n):
         L, NT = int(Ls[i]), int(NTs[i])
-        reqs.append((L, NT, W.couplings_pm_j(1, L, 3, 5000 + i), W.geometric_betas(0.9, 2.0, NT),
-                     int(sweeps[i])))
+        reqs.append(dict(L=L, NT=NT, J=W.couplings_pm_j(1, L, 3, seed0 + i),
+                         betas=W.geometric_betas(0.9, 2.0, NT), seed=seed0 + 2000 + i,
+                         sweeps=int(sweeps[i]), flips=2 * NT * L ** 3 * int(sweeps[i])))
+    return reqs
+
+
+def _serve(pt, args, reqs, arrivals):
+    """Submits reqs[i] at arrivals[i] seconds and waits for every result."""
     srv = pt.pt_server_start(args.serve_budget << 20, steps_per_round=args.serve_round)
+    n = len(reqs)
     tickets, results = {}, {}
     t0 = time.perf_counter()
+    t_note = t0
     i = 0
     while len(results) < n:
         now = time.perf_counter() - t0
+        if now + t0 - t_note > 15.0:
+            t_note = now + t0
+            print(f"# served: {len(results)}/{n} done, {i} submitted, {now:.0f} s",
+                  file=sys.stderr, flush=True)
         while i < n and arrivals[i] <= now:
-            L, NT, J, b, sw = reqs[i]
-            tickets[i] = pt.pt_server_submit(srv, 3, L, NT, 1, b, J, 7000 + i, sw, sw // 2)
+            r = reqs[i]
+            tickets[i] = pt.pt_server_submit(srv, 3, r["L"], r["NT"], 1, r["betas"], r["J"],
+                                             r["seed"], r["sweeps"], r["sweeps"] // 2)
             i += 1
         for k in list(tickets):
-            r = pt.pt_server_poll(srv, tickets[k])
-            if r is not None:
-                results[k] = r
+            res = pt.pt_server_poll(srv, tickets[k])
+            if res is not None:
+                results[k] = res
                 del tickets[k]
         time.sleep(0.002)
     stats = pt.pt_server_stats(srv)
     pt.pt_server_stop(srv)
-    lat = np.array([results[k]["t_done"] - results[k]["t_submit"] for k in range(n)])
     span = max(r["t_done"] for r in results.values()) - min(r["t_submit"] for r in results.values())
+    lat = np.array([results[k]["t_done"] - results[k]["t_submit"] for k in range(n)])
     bad = sum(1 for r in results.values() if r["status"] != 0)
-    return {"workload": f"{n} requests, Poisson arrivals at {lam:.2f}/s "
-                        f"({args.serve_load:.0%} of {capacity_flips_per_ns:.0f} flips/ns), 3D +-J, "
+    return stats, span, lat, bad
+
+
+def served(pt, torch, W, args):
+    """Served form.  Capacity is measured first: a burst of requests of the
+    mix submitted at once, flips per second from first submission to last
+    result.  Then Poisson arrivals at `serve_load` of that capacity; p50/p99
+    of completion minus submission and the flips/ns actually delivered."""
+    rng = np.random.default_rng(args.serve_seed)
+    burst = _requests(W, rng, args.serve_burst, 9000)
+    stats, span, _, bad_b = _serve(pt, args, burst, np.zeros(len(burst)))
+    capacity = stats["flips"] / span / 1e9
+    reqs = _requests(W, rng, args.serve_requests, 5000)
+    mean_flips = float(np.mean([r["flips"] for r in reqs]))
+    lam = args.serve_load * capacity * 1e9 / mean_flips       # jobs per second
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+    stats, span, lat, bad = _serve(pt, args, reqs, arrivals)
+    return {"workload": f"{len(reqs)} requests, Poisson arrivals at {lam:.2f}/s "
+                        f"({args.serve_load:.0%} of the measured capacity), 3D +-J, one sample, "
                         "L in {16,24,32,48}, 16-48 temperatures, 1e3-1e4 steps (half burn-in)",
+            "capacity": {"value": round(capacity, 2), "unit": "flips/ns",
+                         "burst_requests": len(burst), "seconds": round(span, 3)},
             "hbm_budget_mib": args.serve_budget, "steps_per_round": args.serve_round,
             "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
             "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
@@ -172,7 +206,7 @@ def served(pt, torch, W, args, capacity_flips_per_ns):
             "busy_fraction": round(stats["busy_s"] / span, 3),
             "peak_concurrent_jobs": int(stats["peak_jobs"]),
             "peak_admitted_mib": round(stats["peak_bytes"] / 2 ** 20, 1),
-            "failed": bad}
+            "failed": bad + bad_b}
 
 
 def main():
@@ -192,7 +226,8 @@ def main():
     ap.add_argument("--batch-chunk", type=int, default=100)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-burst", type=int, default=100, help="requests of the capacity burst")
     ap.add_argument("--serve-budget", type=int, default=512, help="MiB")
     ap.add_argument("--serve-round", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.7)
@@ -284,8 +319,7 @@ def main():
     serve = None
     if not args.no_served:
         print("# served form", file=sys.stderr, flush=True)
-        cap = batched["packed"]["value"] if batched else value
-        serve = served(pt, torch, W, args, cap)
+        serve = served(pt, torch, W, args)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds)

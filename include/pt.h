@@ -212,8 +212,12 @@ int pt_batch_set_stream(pt_batch *b, void *hip_stream);
  * hipGraph per (mcs, flags, configuration) and replayed; the device counters
  * make every replay continue the random-number streams.  Workgroups take
  * (job, sample, replica sets) items from a device queue, largest first by
- * default.  A job must fit one workgroup's LDS with at least one replica set
- * resident (two for Houdayer or measurement); PT_EINVAL otherwise. */
+ * default; each job runs the plan pt_get_plan reports for these flags.  The
+ * parts of a split sample are queued first and consecutively, and launches
+ * holding split samples are ordered across the process's streams (their
+ * workgroups wait for one another once per step).  PT_EINVAL if a job has no
+ * plan for these flags (Houdayer on a sample whose two sets do not fit one
+ * workgroup). */
 int pt_batch_run(pt_batch *b, int32_t mcs, uint32_t flags);
 
 /* Autotuner: times trial_mcs steps of each launch configuration (threads per

@@ -371,10 +371,14 @@ constexpr uint64_t kBarrierTicks = 6000000000ull;
 
 // Arrives at a sample's barrier and waits for `target` arrivals in all.
 // Returns false if the wait gave up; the job's fault word is then set, and
-// every later wait of the job gives up at once.
+// every later wait of the job gives up at once.  Only thread 0 synchronises
+// with the other parts: every wavefront first waits until its own stores have
+// completed (they are then in this XCD's L2, whose dirty lines thread 0's
+// release writes back), and the workgroup barrier after thread 0's acquire
+// (which invalidates the caches) orders every later load after it.
 __device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uint32_t* fault,
                                              int* flag) {
-  __threadfence();  // this thread's published data, device-wide
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -392,7 +396,6 @@ __device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uin
     *flag = good;
   }
   __syncthreads();
-  __threadfence();  // the other parts' data, for every thread
   return *flag != 0;
 }
 
@@ -408,13 +411,16 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
   for (int k = part + tid * A.parts; k < NT; k += T * A.parts) qneg[k] = 0;
   __syncthreads();
-  for (int k = part; k < NT; k += A.parts) {
-    const uint32_t* Wa = pub + (size_t)sotl[k] * W2;
-    const uint32_t* Wb = pub + (size_t)(NT + sotl[NT + k]) * W2;
-    int neg = 0;
-    for (int i = tid; i < W2; i += T) neg += __popc(Wa[i] ^ Wb[i]);
-    neg = wave_sum(neg);
-    if ((tid & 63) == 0 && neg) atomicAdd(&qneg[k], neg);
+  // all owned temperatures' words in one flat loop, so that many loads are in
+  // flight at once
+  const int nk = (NT - part + A.parts - 1) / A.parts, total = nk * W2;
+#pragma unroll 4
+  for (int idx = tid; idx < total; idx += T) {
+    const int kl = idx / W2, i = idx - kl * W2;
+    const int k = part + kl * A.parts;
+    const uint32_t a = pub[(size_t)sotl[k] * W2 + i], b = pub[(size_t)(NT + sotl[NT + k]) * W2 + i];
+    const int neg = __popc(a ^ b);
+    if (neg) atomicAdd(&qneg[k], neg);
   }
   __syncthreads();
   for (int k = part + tid * A.parts; k < NT; k += T * A.parts)

@@ -19,22 +19,26 @@ template <int D>
 __device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint32_t* __restrict__ jw,
                                            int c, int w, int slot, int s, uint32_t tcount,
                                            uint32_t th2, uint32_t th4, uint32_t th6, int& dE) {
+  // coupling words first: their loads overlap the neighbour loads
+  const size_t js = (size_t)g.NW;
+  uint32_t jv[2 * D];
+#pragma unroll
+  for (int dir = 0; dir < 2 * D; ++dir) jv[dir] = jw[dir * js + w];
   const WordNb q = word_nb(g, w);
   const int p = (c + q.par) & 1;
   const uint32_t* Wo = W + (1 - c) * g.NW;
   const uint32_t Wc = W[c * g.NW + w];
   uint32_t n[2 * D];
   neighbour_words<D>(g, Wo, w, q, p, n);
-  const size_t js = (size_t)g.NW;
   // unsatisfied-bond words and their bit-sliced count u = 4 u2 + 2 u1 + u0
-  const uint32_t U0 = bop3<kXor3>(Wc, n[0], jw[0 * js + w]);
-  const uint32_t U1 = bop3<kXor3>(Wc, n[1], jw[1 * js + w]);
-  const uint32_t U2 = bop3<kXor3>(Wc, n[2], jw[2 * js + w]);
-  const uint32_t U3 = bop3<kXor3>(Wc, n[3], jw[3 * js + w]);
+  const uint32_t U0 = bop3<kXor3>(Wc, n[0], jv[0]);
+  const uint32_t U1 = bop3<kXor3>(Wc, n[1], jv[1]);
+  const uint32_t U2 = bop3<kXor3>(Wc, n[2], jv[2]);
+  const uint32_t U3 = bop3<kXor3>(Wc, n[3], jv[3]);
   uint32_t u0, u1, u2;
   if (D == 3) {
-    const uint32_t U4 = bop3<kXor3>(Wc, n[4], jw[4 * js + w]);
-    const uint32_t U5 = bop3<kXor3>(Wc, n[5], jw[5 * js + w]);
+    const uint32_t U4 = bop3<kXor3>(Wc, n[4], jv[4]);
+    const uint32_t U5 = bop3<kXor3>(Wc, n[5], jv[5]);
     const uint32_t s1 = bop3<kXor3>(U0, U1, U2), c1 = bop3<kMaj3>(U0, U1, U2);
     const uint32_t s2 = bop3<kXor3>(U3, U4, U5), c2 = bop3<kMaj3>(U3, U4, U5);
     u0 = s1 ^ s2;

@@ -94,6 +94,11 @@ def workload(name: str) -> Workload:
     2d_l64  : 2D +-J, L=64, 500 samples x 24 temperatures, T in [0.2, 1.6]
               on the power-law ladder with phi = phi*(64), 5000 sweeps of
               Metropolis + Houdayer + exchange.
+    3d_l48  : 3D +-J, L=48, 64 samples x 32 temperatures, T in [0.9, 2.0]
+              geometric (the largest served size; each sample's 64
+              configurations span several workgroups).
+    3d_l32  : 3D +-J, L=32, 128 samples x 32 temperatures, T in [0.9, 2.0]
+              geometric (served size, split over two workgroups).
     """
     if name == "small3d":
         return Workload(name, 3, 8, 8, 16, geometric_betas(0.9, 2.0, 16), 1000, False)
@@ -102,4 +107,8 @@ def workload(name: str) -> Workload:
     if name == "2d_l64":
         return Workload(name, 2, 64, 500, 24, power_law_betas(0.2, 1.6, 24, phi_star(64)),
                         5000, True)
+    if name == "3d_l48":
+        return Workload(name, 3, 48, 64, 32, geometric_betas(0.9, 2.0, 32), 10000, False)
+    if name == "3d_l32":
+        return Workload(name, 3, 32, 128, 32, geometric_betas(0.9, 2.0, 32), 10000, False)
     raise KeyError(name)

@@ -153,3 +153,32 @@ def test_batch_rejects_oversized_and_mixed_dims(pt):
         pt.pt_batch_create([j2, j3])
     with pytest.raises(pt.PTError):
         pt.pt_batch_create([j2, j2])
+
+
+def test_full_size_batched_mix_sampled(pt):
+    """The batched workload at full size (2000 one-sample jobs, 400 each at
+    L = 8, 12, 16, 24, 32, 24 temperatures) in one persistent launch replayed
+    from a graph; two jobs of each L re-run by the oracle."""
+    Ls, per_L, NT = [8, 12, 16, 24, 32], 400, 24
+    b = W.geometric_betas(0.9, 2.0, NT)
+    jobs, picks = [], []
+    n = 0
+    for L in Ls:
+        for i in range(per_L):
+            jobs.append(pt.pt_init(1, NT, L, 3, W.couplings_pm_j(1, L, 3, 1000 + n), b, 2000 + n))
+            if i in (0, per_L - 1):
+                picks.append(n)
+            n += 1
+    say(f"batched mix: {len(jobs)} jobs")
+    batch = pt.pt_batch_create(jobs)
+    pt.pt_batch_run(batch, 3, graph=True)
+    pt.pt_batch_run(batch, 3, graph=True)
+    for n in picks:
+        L = Ls[n // per_L]
+        ref = oracle.OracleJob(1, NT, L, 3, W.couplings_pm_j(1, L, 3, 1000 + n), b, 2000 + n)
+        ref.mcs(6)
+        say(f"check job {n} (L={L})")
+        matches_oracle(pt, jobs[n], ref)
+    pt.pt_batch_destroy(batch)
+    for j in jobs:
+        pt.pt_destroy(j)

@@ -231,3 +231,22 @@ def test_fused_steps_equal_plain_and_oracle(pt, d, L, S, NT, layout, hou, meas):
         ref.mcs(n, houdayer=hou, measure=meas)
         compare(pt, fused, ref, f"fused after {n}")
         compare(pt, plain, ref, f"plain after {n}")
+
+
+def test_full_run_small3d(pt):
+    """The whole 3D L=8 workload: 8 samples x 16 temperatures, 1000 steps of
+    sweep + exchange, measured over the second half; every bit of the final
+    state and the observables against the oracle."""
+    wl = W.workload("small3d")
+    say(f"case {wl.name} S={wl.samples} NT={wl.replicas} L={wl.L} sweeps={wl.sweeps}")
+    J = wl.couplings()
+    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed)
+    ref = oracle.OracleJob(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed)
+    half = wl.sweeps // 2
+    pt.pt_mcs(job, half)
+    pt.pt_mcs(job, wl.sweeps - half, measure=True)
+    ref.mcs(half)
+    ref.mcs(wl.sweeps - half, measure=True)
+    compare(pt, job, ref, "small3d full run")
+    compare_observables(pt, job, ref)
+    pt.pt_destroy(job)

@@ -42,6 +42,7 @@ SPLIT_CASES = [
     (3, 48, 1, 8, 0, 2),     # couplings read from global memory
     (3, 24, 1, 48, 1, 2),    # two fields per word
     (2, 64, 1, 160, 0, 2),   # 2D
+    (3, 48, 1, 48, 1, 12),   # the largest served shape: 12 parts of 8
 ]
 
 
@@ -106,3 +107,4 @@ def test_split_in_mixed_batch(pt, graph):
         for j, r in zip(jobs, refs):
             matches_oracle(pt, j, r, f"round {rnd}")
     pt.pt_batch_destroy(batch)
+
