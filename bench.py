@@ -148,10 +148,13 @@ def _requests(W, rng, n, seed0):
 
 
 def _serve(pt, args, reqs, arrivals):
-    """Submits reqs[i] at arrivals[i] seconds and waits for every result."""
+    """Submits reqs[i] at arrivals[i] seconds and waits for every result.
+    Also returns (seconds, flips) on the server's clock at the moment the
+    last request was admitted: until then the queue was never empty."""
     srv = pt.pt_server_start(args.serve_budget << 20, steps_per_round=args.serve_round)
     n = len(reqs)
     tickets, results = {}, {}
+    saturated = None
     t0 = time.perf_counter()
     t_note = t0
     i = 0
@@ -166,6 +169,10 @@ def _serve(pt, args, reqs, arrivals):
             tickets[i] = pt.pt_server_submit(srv, 3, r["L"], r["NT"], 1, r["betas"], r["J"],
                                              r["seed"], r["sweeps"], r["sweeps"] // 2)
             i += 1
+        if saturated is None and i == n:
+            st = pt.pt_server_stats(srv)
+            if st["admitted"] >= n:
+                saturated = (st["uptime_s"], st["flips"])
         for k in list(tickets):
             res = pt.pt_server_poll(srv, tickets[k])
             if res is not None:
@@ -177,32 +184,37 @@ def _serve(pt, args, reqs, arrivals):
     span = max(r["t_done"] for r in results.values()) - min(r["t_submit"] for r in results.values())
     lat = np.array([results[k]["t_done"] - results[k]["t_submit"] for k in range(n)])
     bad = sum(1 for r in results.values() if r["status"] != 0)
-    return stats, span, lat, bad
+    return stats, span, lat, bad, saturated
 
 
 def served(pt, torch, W, args):
     """Served form.  Capacity is measured first: a burst of requests of the
-    mix submitted at once, flips per second from first submission to last
-    result.  Then Poisson arrivals at `serve_load` of that capacity; p50/p99
-    of completion minus submission and the flips/ns actually delivered."""
+    mix submitted at once, more than the HBM budget admits together; flips
+    per second while the queue is non-empty (until the last request is
+    admitted).  Then Poisson arrivals at `serve_load` of that capacity;
+    p50/p99 of completion minus submission and the flips/ns delivered."""
     rng = np.random.default_rng(args.serve_seed)
     burst = _requests(W, rng, args.serve_burst, 9000)
-    stats, span, _, bad_b = _serve(pt, args, burst, np.zeros(len(burst)))
-    capacity = stats["flips"] / span / 1e9
+    stats_b, span_b, _, bad_b, sat = _serve(pt, args, burst, np.zeros(len(burst)))
+    t_sat, flips_sat = sat if sat and sat[0] > 0 else (span_b, stats_b["flips"])
+    capacity = flips_sat / t_sat / 1e9
     reqs = _requests(W, rng, args.serve_requests, 5000)
     mean_flips = float(np.mean([r["flips"] for r in reqs]))
     lam = args.serve_load * capacity * 1e9 / mean_flips       # jobs per second
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
-    stats, span, lat, bad = _serve(pt, args, reqs, arrivals)
+    stats, span, lat, bad, _ = _serve(pt, args, reqs, arrivals)
     return {"workload": f"{len(reqs)} requests, Poisson arrivals at {lam:.2f}/s "
                         f"({args.serve_load:.0%} of the measured capacity), 3D +-J, one sample, "
                         "L in {16,24,32,48}, 16-48 temperatures, 1e3-1e4 steps (half burn-in)",
             "capacity": {"value": round(capacity, 2), "unit": "flips/ns",
-                         "burst_requests": len(burst), "seconds": round(span, 3)},
+                         "burst_requests": len(burst), "saturated_seconds": round(t_sat, 3),
+                         "burst_seconds": round(span_b, 3),
+                         "burst_flips_per_ns": round(stats_b["flips"] / span_b / 1e9, 2)},
             "hbm_budget_mib": args.serve_budget, "steps_per_round": args.serve_round,
             "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
             "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
             "value": round(stats["flips"] / span / 1e9, 2), "unit": "flips/ns",
+            "seconds": round(span, 3),
             "busy_fraction": round(stats["busy_s"] / span, 3),
             "peak_concurrent_jobs": int(stats["peak_jobs"]),
             "peak_admitted_mib": round(stats["peak_bytes"] / 2 ** 20, 1),
@@ -227,7 +239,7 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-burst", type=int, default=100, help="requests of the capacity burst")
+    ap.add_argument("--serve-burst", type=int, default=300, help="requests of the capacity burst")
     ap.add_argument("--serve-budget", type=int, default=512, help="MiB")
     ap.add_argument("--serve-round", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.7)

@@ -226,7 +226,10 @@ int pt_batch_run(pt_batch *b, int32_t mcs, uint32_t flags);
  * and keeps the fastest.  cache_path (may be NULL) is a JSON-lines file keyed
  * by the batch shape; a hit skips the trials. */
 int pt_batch_tune(pt_batch *b, int32_t trial_mcs, uint32_t flags, const char *cache_path);
-/* cfg3 = {threads per workgroup, replica sets per item, order} */
+/* cfg3 = {threads per workgroup, replica sets per item, order}.  threads 0
+ * (the default) picks per launch the size that keeps the most workgroups
+ * resident per CU with at least 16 wavefronts (from the launch's LDS plan and
+ * its kernel's registers); get_config then reports the size last used. */
 int pt_batch_get_config(pt_batch *b, int32_t *cfg3);
 int pt_batch_set_config(pt_batch *b, int32_t threads, int32_t sets, int32_t order);
 int pt_batch_destroy(pt_batch *b);

@@ -16,7 +16,14 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wno-unused-command-line-argument"]
 
 
+PROBE = os.path.join(HERE, "rate_probe")
+PROBE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+               "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
+
+
 def build(verbose: bool = False) -> str:
+    """Builds libptsg.so and the instruction-rate probe (measurement support
+    for the roofline, not linked into the library)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp]
@@ -25,6 +32,11 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    probe = [hipcc] + PROBE_FLAGS + ["-o", PROBE + ".tmp", os.path.join(CSRC, "rate_probe.hip")]
+    if verbose:
+        print(" ".join(probe), flush=True)
+    subprocess.run(probe, check=True)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

@@ -18,7 +18,7 @@
 using namespace ptsg;
 
 struct BatchConfig {
-  int threads = 1024;  // threads per workgroup: 256, 512 or 1024
+  int threads = 0;     // threads per workgroup: 256, 512 or 1024; 0 = chosen per launch
   int sets = 2;        // replica sets per item when both fit (2) or always one (1)
   int order = 0;       // 0: largest items first, 1: job order
 };
@@ -47,6 +47,8 @@ struct pt_batch {
   hipGraphExec_t exec = nullptr;
   bool graph_ok = false;
   bool has_split = false;  // the work list holds split samples
+  int feat = 0;            // kinds of work in the work list (kFeat*)
+  int threads = 1024;      // threads per workgroup of the built launch
 };
 
 namespace {
@@ -103,6 +105,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
   std::vector<BatchItem> hi, split;
   std::vector<double> cost;
   size_t lds_words = 0;
+  int feat = 0;
   for (size_t jx = 0; jx < b->jobs.size(); ++jx) {
     pt_job* j = b->jobs[jx];
     const uint32_t flags = jflags[jx];
@@ -112,6 +115,9 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     if (mode < 0)
       return pt_fail(PT_EINVAL, "pt_batch_run: job " + std::to_string(jx) +
                                     " does not fit one workgroup's LDS for these flags (use pt_mcs)");
+    if (mcs > 0 && meas) feat |= kFeatMeas;
+    if (mcs > 0 && hou) feat |= kFeatHou;
+    if (mcs > 0 && mode == 3) feat |= kFeatSplit;
     if (mode == 3) {
       FusedArgs A = make_fused_args(j->g, j->split_lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
                                     j->thrpt, j->M, j->mom, j->ctr, mcs, false, meas);
@@ -180,14 +186,38 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
   if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
   b->nitems = (int)hi.size();
   b->lds_bytes = lds_words * 4;
-  e = prepare_batch(b->d, b->lds_bytes);
+  b->feat = feat;
+  int vgprs = 128;
+  e = prepare_batch(b->d, feat, b->lds_bytes, &vgprs);
   if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
-  // persistent grid: as many workgroups as can be resident at once
-  int per_cu = 1;
-  const int by_lds = (int)((160 * 1024) / std::max<size_t>(b->lds_bytes, 1));
-  const int by_waves = std::max(1, 24 / (b->cfg.threads / 64));  // <= 6 waves per SIMD at this VGPR use
-  per_cu = std::max(1, std::min(by_lds, by_waves));
-  b->blocks = std::max(1, std::min(b->ncu * per_cu, b->nitems));
+  // persistent grid: as many workgroups as can be resident at once (LDS per
+  // CU; wavefronts per SIMD from the kernel's VGPRs, 512 per lane, at most 8).
+  // Unless configured, the workgroup size is the one that keeps the most
+  // workgroups resident per CU with at least 16 wavefronts, else the most
+  // wavefronts: several workgroups per CU fill each other's barriers and
+  // serial exchange passes.
+  const int by_lds = (int)((160 * 1024) / std::max<size_t>(b->lds_bytes + 64, 1));
+  const int waves_simd = std::max(1, std::min(8, 512 / std::max(8, (vgprs + 7) / 8 * 8)));
+  auto resident = [&](int threads) {
+    const int by_waves = std::max(1, waves_simd * 4 / std::max(1, threads / 64));
+    return std::max(1, std::min(by_lds, by_waves));
+  };
+  int threads = b->cfg.threads;
+  if (threads == 0) {
+    int best_wg = -1, best_waves = -1;
+    for (int t : {1024, 512, 256}) {
+      const int wg = resident(t), waves = wg * t / 64;
+      const bool ok = waves >= 16, best_ok = best_waves >= 16;
+      if (best_wg < 0 || (ok && !best_ok) || (ok && best_ok && wg > best_wg) ||
+          (!ok && !best_ok && waves > best_waves)) {
+        best_wg = wg;
+        best_waves = waves;
+        threads = t;
+      }
+    }
+  }
+  b->threads = threads;
+  b->blocks = std::max(1, std::min(b->ncu * resident(threads), b->nitems));
   b->built = false;
   drop_graph(b);
   return PT_OK;
@@ -210,8 +240,8 @@ int run_once(pt_batch* b, bool use_graph) {
   if (b->nitems == 0) return PT_OK;
   if (!use_graph) {
     auto launch = [&] {
-      return launch_batch(b->d, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems, b->d_queue,
-                          b->blocks, b->cfg.threads, b->lds_bytes, b->stream);
+      return launch_batch(b->d, b->feat, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems,
+                          b->d_queue, b->blocks, b->threads, b->lds_bytes, b->stream);
     };
     const hipError_t e = b->has_split ? ordered_split_launch(b->stream, launch) : launch();
     if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
@@ -222,9 +252,9 @@ int run_once(pt_batch* b, bool use_graph) {
     if (!b->cap_stream) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      const hipError_t el = launch_batch(b->d, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems,
-                                         b->d_queue, b->blocks, b->cfg.threads, b->lds_bytes,
-                                         b->cap_stream);
+      const hipError_t el = launch_batch(b->d, b->feat, b->d_jobs, (int)b->jobs.size(), b->d_items,
+                                         b->nitems, b->d_queue, b->blocks, b->threads,
+                                         b->lds_bytes, b->cap_stream);
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(b->cap_stream, &g);
       if (e == hipSuccess && el != hipSuccess) e = el;
@@ -430,7 +460,7 @@ PT_API int pt_batch_run(pt_batch* b, int32_t mcs, uint32_t flags) {
 
 PT_API int pt_batch_get_config(pt_batch* b, int32_t* cfg3) {
   if (!b || !cfg3) return pt_fail(PT_EINVAL, "null argument");
-  cfg3[0] = b->cfg.threads;
+  cfg3[0] = b->cfg.threads == 0 && b->built ? b->threads : b->cfg.threads;
   cfg3[1] = b->cfg.sets;
   cfg3[2] = b->cfg.order;
   return PT_OK;
@@ -438,9 +468,10 @@ PT_API int pt_batch_get_config(pt_batch* b, int32_t* cfg3) {
 
 PT_API int pt_batch_set_config(pt_batch* b, int32_t threads, int32_t sets, int32_t order) {
   if (!b) return pt_fail(PT_EINVAL, "null batch");
-  if ((threads != 256 && threads != 512 && threads != 1024) || (sets != 1 && sets != 2) ||
-      (order != 0 && order != 1))
-    return pt_fail(PT_EINVAL, "pt_batch_set_config: threads in {256,512,1024}, sets in {1,2}, order in {0,1}");
+  if ((threads != 0 && threads != 256 && threads != 512 && threads != 1024) ||
+      (sets != 1 && sets != 2) || (order != 0 && order != 1))
+    return pt_fail(PT_EINVAL,
+                   "pt_batch_set_config: threads in {0 (auto),256,512,1024}, sets in {1,2}, order in {0,1}");
   b->cfg = BatchConfig{threads, sets, order};
   return PT_OK;
 }

@@ -7,6 +7,8 @@
 // Results are bit-identical to the per-step kernels: the same row update
 // (rowops.h), the same Philox counters, exchange decisions taken in ascending
 // k with the updated map, Houdayer seeds chosen in increasing site order.
+#include <utility>
+
 #include "device.h"
 #include "kernels.h"
 #include "houdayer_ops.h"
@@ -268,7 +270,7 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
 // state is written back, so the two sets of a sample may run in different
 // workgroups at the same time.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, bool HOU, bool MEAS>
 __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, int s, int c_lo, int nsets) {
   const Geo& g = A.g;
   const int T = blockDim.x, tid = threadIdx.x;
@@ -282,7 +284,7 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
   uint32_t* thrl = lds + A.lay.thr;
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
   const size_t lat0 = (size_t)s * nslot + slot0;
-  const bool hou = A.hou && nsets == 2, meas = A.meas && nsets == 2;
+  const bool hou = HOU && A.hou && nsets == 2, meas = MEAS && A.meas && nsets == 2;
 
   // ---- load
   const int items = nres * NW;
@@ -430,7 +432,7 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
 
 // nmcs Monte Carlo steps (sweep, exchange, measurement) of part `part` of
 // split sample s.
-template <int D>
+template <int D, bool MEAS>
 __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int s, int part,
                                           int* flag) {
   const Geo& g = A.g;
@@ -444,7 +446,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
   uint32_t* thrl = lds + A.lay.thr;
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
   const size_t lat0 = (size_t)s * nslot + slot0;
-  const bool meas = A.meas != 0;
+  const bool meas = MEAS && A.meas != 0;
 
   // ---- load this part's slots and the sample's shared state
   const int items = nres * NW;
@@ -533,12 +535,17 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
 // ---------------------------------------------------------------------------
 // Persistent batch kernel: workgroups take (job, sample, sets) items from a
 // shared queue until it is empty.  Each job brings its own geometry,
-// tables, state and LDS plan.
+// tables, state and LDS plan.  F says which kinds of work the launch holds
+// (kFeatHou, kFeatMeas, kFeatSplit): code for the others is left out, which
+// keeps the register count, and so the number of resident wavefronts, of a
+// launch as low as its work allows.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int F>
 __global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jobs,
                                                 const BatchItem* __restrict__ items, int nitems,
                                                 uint32_t* queue) {
+  constexpr bool kHou = (F & kFeatHou) != 0, kMeas = (F & kFeatMeas) != 0;
+  constexpr bool kSplit = (F & kFeatSplit) != 0;
   extern __shared__ uint32_t lds[];
   __shared__ int cur, flag;
   for (;;) {
@@ -550,10 +557,10 @@ __global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jo
     const BatchItem it = items[i];
     const FusedArgs A = jobs[it.job];
     if (A.nmcs > 0) {
-      if (it.nsets == 0)
-        run_split<D>(A, lds, it.sample, it.c_lo, &flag);
+      if (kSplit && it.nsets == 0)
+        run_split<D, kMeas>(A, lds, it.sample, it.c_lo, &flag);
       else
-        run_sample<D>(A, lds, it.sample, it.c_lo, it.nsets);
+        run_sample<D, kHou, kMeas>(A, lds, it.sample, it.c_lo, it.nsets);
     }
     __syncthreads();
   }
@@ -696,19 +703,39 @@ static hipError_t lds_attr(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-hipError_t prepare_batch(int d, size_t lds_bytes) {
-  return d == 3 ? lds_attr(k_batch<3>, lds_bytes) : lds_attr(k_batch<2>, lds_bytes);
+namespace {
+using BatchKernel = void (*)(const FusedArgs*, const BatchItem*, int, uint32_t*);
+
+template <int D, int... F>
+constexpr BatchKernel pick(int feat, std::integer_sequence<int, F...>) {
+  BatchKernel k = nullptr;
+  ((k = (feat == F ? &k_batch<D, F> : k)), ...);
+  return k;
 }
 
-hipError_t launch_batch(int d, const FusedArgs* jobs, int njobs, const BatchItem* items, int nitems,
-                        uint32_t* queue, int blocks, int threads, size_t lds_bytes, hipStream_t st) {
+BatchKernel batch_kernel(int d, int feat) {
+  using All = std::make_integer_sequence<int, 8>;
+  return d == 3 ? pick<3>(feat & 7, All{}) : pick<2>(feat & 7, All{});
+}
+}  // namespace
+
+hipError_t prepare_batch(int d, int feat, size_t lds_bytes, int* vgprs) {
+  const BatchKernel k = batch_kernel(d, feat);
+  hipError_t e = lds_attr(k, lds_bytes);
+  if (e == hipSuccess && vgprs) {
+    hipFuncAttributes at{};
+    e = hipFuncGetAttributes(&at, (const void*)k);
+    *vgprs = at.numRegs;
+  }
+  return e;
+}
+
+hipError_t launch_batch(int d, int feat, const FusedArgs* jobs, int njobs, const BatchItem* items,
+                        int nitems, uint32_t* queue, int blocks, int threads, size_t lds_bytes,
+                        hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)njobs + 1), dim3(256), 0, st, jobs, queue);
-  if (d == 3)
-    hipLaunchKernelGGL(k_batch<3>, dim3(blocks), dim3(threads), lds_bytes, st, jobs, items, nitems,
-                       queue);
-  else
-    hipLaunchKernelGGL(k_batch<2>, dim3(blocks), dim3(threads), lds_bytes, st, jobs, items, nitems,
-                       queue);
+  hipLaunchKernelGGL(batch_kernel(d, feat), dim3(blocks), dim3(threads), lds_bytes, st, jobs, items,
+                     nitems, queue);
   hipLaunchKernelGGL(k_batch_advance, dim3((unsigned)((njobs + 255) / 256)), dim3(256), 0, st, jobs,
                      njobs);
   return hipGetLastError();

@@ -99,11 +99,18 @@ FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, con
                           const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
                           int nmcs, bool houdayer, bool measure);
 
+// Kinds of work a batch launch holds; the launch runs the kernel compiled for
+// exactly that set.
+constexpr int kFeatHou = 1, kFeatMeas = 2, kFeatSplit = 4;
+
 // Persistent batch: resets the queue, runs every item to its job's nmcs, then
 // advances each job's counters.  `jobs` and `items` are device arrays.
-hipError_t prepare_batch(int d, size_t lds_bytes);
-hipError_t launch_batch(int d, const FusedArgs* jobs, int njobs, const BatchItem* items, int nitems,
-                        uint32_t* queue, int blocks, int threads, size_t lds_bytes, hipStream_t st);
+// prepare_batch sets the kernel's dynamic LDS limit and reports its VGPRs
+// per lane.
+hipError_t prepare_batch(int d, int feat, size_t lds_bytes, int* vgprs);
+hipError_t launch_batch(int d, int feat, const FusedArgs* jobs, int njobs, const BatchItem* items,
+                        int nitems, uint32_t* queue, int blocks, int threads, size_t lds_bytes,
+                        hipStream_t st);
 
 // Launch shape of the sweep kernel (threads per lattice T, lattices per block).
 void sweep_shape(const Geo& g, int& T, int& LPB, int& threads, size_t& lds);

@@ -3,11 +3,13 @@
 // Requests are admitted in arrival order while their device memory fits the
 // HBM budget, stay resident on the device, and advance together: every round
 // runs up to `steps_per_round` Monte Carlo steps of every active job in one
-// persistent batch launch (jobs too large for one workgroup's LDS run their
-// per-step kernels on a second stream at the same time).  A job measures only
-// after its burn-in; when its steps are done its observables are read out,
-// its memory is released and the next request is admitted.  Results depend
-// only on the request, never on what else ran beside it.
+// persistent batch launch (jobs with no workgroup plan run their per-step
+// kernels on a second stream at the same time).  A job measures only after
+// its burn-in.  While a round runs on the GPU, the worker thread reads out
+// and releases the jobs that finished in the previous round and creates the
+// newly admitted ones on a third stream, from a stream-ordered memory pool,
+// so that job set-up and tear-down overlap the rounds.  Results depend only
+// on the request, never on what else ran beside it.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -54,7 +56,8 @@ struct pt_server {
   size_t budget = 0, used = 0;
   int steps_per_round = 100;
   int device = 0;
-  hipStream_t st_main = nullptr, st_side = nullptr;
+  hipStream_t st_main = nullptr, st_side = nullptr, st_admit = nullptr;
+  hipMemPool_t pool = nullptr;  // device memory of the jobs
   pt_batch* batch[2] = {nullptr, nullptr};  // 2D and 3D jobs
   std::mutex mu;
   std::condition_variable cv, cv_done;
@@ -78,7 +81,25 @@ struct pt_server {
 
 namespace {
 
+// Job memory from the server's stream-ordered pool: allocated and released
+// on st_admit, never while a round that uses it can still run.
+void* pool_alloc(size_t bytes, void* ctx) {
+  pt_server* sv = static_cast<pt_server*>(ctx);
+  void* p = nullptr;
+  if (hipMallocFromPoolAsync(&p, bytes, sv->pool, sv->st_admit) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void pool_free(void* p, void* ctx) {
+  pt_server* sv = static_cast<pt_server*>(ctx);
+  (void)hipFreeAsync(p, sv->st_admit);
+}
+
 void finish(pt_server* sv, Active& a, int status) {
+  if (a.job) a.job->stream = sv->st_admit;  // the next round may already run on st_main
   Finished f;
   f.status = status;
   f.t_submit = a.req.t_submit;
@@ -110,50 +131,70 @@ void fail_request(pt_server* sv, const Request& r, int status) {
   sv->cv_done.notify_all();
 }
 
+// Takes queued requests in arrival order while the budget holds.
+std::vector<Request> take_admissions(pt_server* sv) {
+  std::vector<Request> admit;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  size_t used = sv->used;
+  while (!sv->pending.empty()) {
+    Request& r = sv->pending.front();
+    const size_t need = job_device_bytes(r.S, r.NT, r.L, r.dim, (int)r.layout, r.betas.data());
+    if (need > sv->budget) {
+      fail_request(sv, r, PT_ENOMEM);
+      sv->pending.pop_front();
+      continue;
+    }
+    if (used + need > sv->budget) break;
+    used += need;
+    admit.push_back(std::move(r));
+    sv->pending.pop_front();
+  }
+  sv->used = used;
+  if (used > sv->peak_used) sv->peak_used = used;
+  return admit;
+}
+
+// Creates the admitted jobs on st_admit (they join the next round).
+void create_jobs(pt_server* sv, std::vector<Request>& admit, std::vector<Active>& ready) {
+  for (Request& r : admit) {
+    Active a;
+    a.bytes = job_device_bytes(r.S, r.NT, r.L, r.dim, (int)r.layout, r.betas.data());
+    a.t_admit = sv->now();
+    const int rc = job_create(&a.job, r.S, r.NT, r.L, r.dim, r.J.data(), r.betas.data(), r.seed,
+                              r.layout, pool_alloc, pool_free, sv, sv->st_admit);
+    a.req = std::move(r);
+    a.req.J.clear();
+    a.req.J.shrink_to_fit();
+    if (rc != PT_OK) {
+      a.job = nullptr;
+      finish(sv, a, rc);
+      continue;
+    }
+    a.job->stream = sv->st_main;
+    ready.push_back(std::move(a));
+    sv->admitted += 1;
+  }
+}
+
 void serve(pt_server* sv) {
   (void)hipSetDevice(sv->device);
+  std::vector<Active> done;  // finished in the last round, not yet read out
   for (;;) {
-    std::vector<Request> admit;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv.wait(lk, [&] { return sv->stopping || !sv->pending.empty() || !sv->active.empty(); });
-      if (sv->stopping && sv->pending.empty() && sv->active.empty()) break;
-      // admission in arrival order while the budget holds
-      size_t used = sv->used;
-      while (!sv->pending.empty()) {
-        Request& r = sv->pending.front();
-        const size_t need = job_device_bytes(r.S, r.NT, r.L, r.dim, (int)r.layout, r.betas.data());
-        if (need > sv->budget) {
-          fail_request(sv, r, PT_ENOMEM);
-          sv->pending.pop_front();
-          continue;
-        }
-        if (used + need > sv->budget) break;
-        used += need;
-        admit.push_back(std::move(r));
-        sv->pending.pop_front();
-      }
-      sv->used = used;
-      if (used > sv->peak_used) sv->peak_used = used;
+      sv->cv.wait(lk, [&] {
+        return sv->stopping || !sv->pending.empty() || !sv->active.empty() || !done.empty();
+      });
+      if (sv->stopping && sv->pending.empty() && sv->active.empty() && done.empty()) break;
     }
-    for (Request& r : admit) {
-      Active a;
-      a.bytes = job_device_bytes(r.S, r.NT, r.L, r.dim, (int)r.layout, r.betas.data());
-      a.t_admit = sv->now();
-      const int rc = job_create(&a.job, r.S, r.NT, r.L, r.dim, r.J.data(), r.betas.data(), r.seed,
-                                r.layout, nullptr, nullptr, nullptr, sv->st_main);
-      a.req = std::move(r);
-      a.req.J.clear();
-      a.req.J.shrink_to_fit();
-      if (rc != PT_OK) {
-        a.job = nullptr;
-        finish(sv, a, rc);
-        continue;
-      }
-      sv->active.push_back(std::move(a));
-      sv->admitted += 1;
+    if (sv->active.empty()) {
+      // nothing on the GPU: read out, then admit, before the first round
+      for (Active& a : done) finish(sv, a, PT_OK);
+      done.clear();
+      std::vector<Request> admit = take_admissions(sv);
+      create_jobs(sv, admit, sv->active);
+      if (sv->active.empty()) continue;
     }
-    if (sv->active.empty()) continue;
     if ((int)sv->active.size() > sv->max_active) sv->max_active = (int)sv->active.size();
 
     // one round: every active job advances, measuring after its burn-in
@@ -198,6 +239,17 @@ void serve(pt_server* sv) {
       rc = pt_mcs(a.job, steps[i], flags[i]);
       a.job->stream = sv->st_main;
     }
+
+    // while the round runs: read out and release the last round's finished
+    // jobs, then create the newly admitted ones
+    for (Active& a : done) finish(sv, a, PT_OK);
+    done.clear();
+    std::vector<Active> ready;
+    if (rc == PT_OK) {
+      std::vector<Request> admit = take_admissions(sv);
+      create_jobs(sv, admit, ready);
+    }
+
     if (rc == PT_OK && hipStreamSynchronize(sv->st_main) != hipSuccess) rc = PT_EDEVICE;
     if (rc == PT_OK && hipStreamSynchronize(sv->st_side) != hipSuccess) rc = PT_EDEVICE;
     sv->busy += sv->now() - t_round;
@@ -213,10 +265,11 @@ void serve(pt_server* sv) {
       }
       a.done += steps[i];
       if (a.done >= a.req.sweeps)
-        finish(sv, a, PT_OK);
+        done.push_back(std::move(a));
       else
         still.push_back(std::move(a));
     }
+    for (Active& a : ready) still.push_back(std::move(a));
     sv->active.swap(still);
   }
 }
@@ -233,11 +286,24 @@ PT_API int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server
   sv->steps_per_round = steps_per_round;
   sv->t0 = std::chrono::steady_clock::now();
   (void)hipGetDevice(&sv->device);
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = sv->device;
+  uint64_t keep = UINT64_MAX;  // freed blocks stay in the pool for reuse
   if (hipStreamCreateWithFlags(&sv->st_main, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&sv->st_side, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&sv->st_side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&sv->st_admit, hipStreamNonBlocking) != hipSuccess ||
+      hipMemPoolCreate(&sv->pool, &props) != hipSuccess ||
+      hipMemPoolSetAttribute(sv->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
     (void)hipGetLastError();
+    if (sv->st_main) (void)hipStreamDestroy(sv->st_main);
+    if (sv->st_side) (void)hipStreamDestroy(sv->st_side);
+    if (sv->st_admit) (void)hipStreamDestroy(sv->st_admit);
+    if (sv->pool) (void)hipMemPoolDestroy(sv->pool);
     delete sv;
-    return pt_fail(PT_EDEVICE, "pt_server_start: stream creation failed");
+    return pt_fail(PT_EDEVICE, "pt_server_start: stream or memory pool creation failed");
   }
   sv->batch[0] = batch_new(sv->st_main);
   sv->batch[1] = batch_new(sv->st_main);
@@ -337,8 +403,11 @@ PT_API int pt_server_stop(pt_server* sv) {
   if (sv->worker.joinable()) sv->worker.join();
   batch_free(sv->batch[0]);
   batch_free(sv->batch[1]);
+  (void)hipStreamSynchronize(sv->st_admit);
   (void)hipStreamDestroy(sv->st_main);
   (void)hipStreamDestroy(sv->st_side);
+  (void)hipStreamDestroy(sv->st_admit);
+  (void)hipMemPoolDestroy(sv->pool);
   (void)hipGetLastError();
   delete sv;
   return PT_OK;

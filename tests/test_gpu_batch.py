@@ -92,7 +92,7 @@ def test_batch_houdayer_2d(pt):
         matches_oracle(pt, j, r)
 
 
-@pytest.mark.parametrize("cfg", [(1024, 1, 0), (512, 2, 1), (256, 1, 1), (256, 2, 0)])
+@pytest.mark.parametrize("cfg", [(1024, 1, 0), (512, 2, 1), (256, 1, 1), (256, 2, 0), (0, 2, 0)])
 def test_batch_configs_agree(pt, cfg):
     say(f"batch config {cfg}")
     jobs, refs = make_jobs(pt, SHAPES_3D, 3, seed0=70)
