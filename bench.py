@@ -33,14 +33,23 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes, one 32-bit VALU op per lane per clock
-# at 2.4 GHz (a wave64 instruction occupies a SIMD for 4 clocks).
-PEAK_VALU_OPS = 256 * 64 * 2.4e9
-# Algorithmic integer work per attempted flip: the site's share of one
-# Philox4x32-10 call (10 rounds x (2 32x32->64 multiplies + 2 three-input
-# xors) per 4 words = 10 ops) plus the threshold compare (1 op).  The local
-# field and the classification are bit-sliced over a row word and not counted.
-OPS_PER_FLIP = 11
+# MI355X VALU peak: 256 CUs x 128 32-bit lanes per clock x 2.4 GHz = 78.6 T
+# lane-operations/s, the rate behind the published 157.3 TFLOP/s fp32 vector
+# figure (an FMA counts two flops).  paper_2003_04621_amd/rate_probe measures
+# on the GPU 0.72-0.79 of this for plain integer ops (v_add_u32, v_bitop3_b32)
+# and half of it for the 32x32->64-bit multiply (v_mad_u64_u32), which
+# therefore costs two issue slots.
+PEAK_VALU_OPS = 256 * 128 * 2.4e9
+# Algorithmic work per attempted flip, in issue slots: the site's share of one
+# Philox4x32-10 call (10 rounds x 2 multiplies x 2 slots + 10 x 2 three-input
+# xors, over 4 words = 15) plus the threshold compare (1).  The bit-sliced
+# local field and classification (amortised over 16-32 sites of a word) are
+# not counted.
+OPS_PER_FLIP = 16
+# HBM bytes per 500-step launch of the fused kernel on the 3d_l16 workload
+# (int8 layout), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
+# copy's readings (profiles/k_batch_3d_l16_hbm_traffic.md).
+TRAFFIC_3D_L16_INT8_500 = 5.34e8
 
 
 def cpu_baseline(wl, budget_s: float):
@@ -303,7 +312,9 @@ def main():
     peak = PEAK_VALU_OPS / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TOP/s", "frac": round(achieved / peak, 4),
-                "traffic": args.traffic_bytes,
+                "traffic": (args.traffic_bytes if args.traffic_bytes is not None else
+                            TRAFFIC_3D_L16_INT8_500
+                            if (wl.name, args.layout, chunk) == ("3d_l16", "int8", 500) else None),
                 "kernel": f"k_batch<{wl.dim}> ({chunk} steps per launch)",
                 "launch_ms": round(launch_ms, 4)}
 
