@@ -155,11 +155,62 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
   return v;
 }
 
+// Upward fill along the chain F_0, G_0, F_1, G_1, ... of every row field,
+// where F_b -> G_b and G_b -> F_(b+1) (no link across a field boundary; nLB
+// clears the lowest bit of each field): from seeds SF <= MF, SG <= MG, the
+// sites of the masks MF, MG reachable by increasing steps.  F sites that can
+// be entered from below form runs of R; adding the entry points Z to R
+// carries through each run up to its first gap, so (R + Z) ^ R marks the
+// reached bits of the run (an entry point already inside a carry is lost
+// from the sum, hence the | Z).
+__device__ __forceinline__ void chain_fill_up(uint32_t SF, uint32_t SG, uint32_t MF, uint32_t MG,
+                                              uint32_t nLB, uint32_t& UF, uint32_t& UG) {
+  const uint32_t Sp = SF | ((SG << 1) & nLB & MF);
+  const uint32_t R = (MG << 1) & MF & nLB;
+  const uint32_t Z = (Sp << 1) & R;
+  const uint32_t V = (R & ((R + Z) ^ R)) | Z;
+  UF = Sp | V;
+  UG = SG | (UF & MG);
+}
+
+// Closure of the cluster words c0, c1 of one word index along x0 (the two
+// colour words hold each row's even and odd sites): every site of q linked to
+// the cluster through a run of q sites of its row, periodic in x0.  The even
+// sites E and odd sites O of a row alternate E_0 O_0 E_1 O_1 ...; an upward
+// fill and a bit-reversed (downward) fill cover each run from its lowest to
+// its highest seed, and a run through the row's end is continued from its
+// other end in one more pass.
+__device__ __forceinline__ void x0_closure(const Geo& g, uint32_t& c0, uint32_t& c1, uint32_t q0,
+                                           uint32_t q1, int p0) {
+  uint32_t SE = p0 ? c1 : c0, SO = p0 ? c0 : c1;
+  const uint32_t ME = p0 ? q1 : q0, MO = p0 ? q0 : q1;
+  const uint32_t rME = __builtin_bitreverse32(ME), rMO = __builtin_bitreverse32(MO);
+  const uint32_t nLB = ~g.LB, nLBr = ~__builtin_bitreverse32(g.HB);
+  for (;;) {
+    uint32_t UE, UO, DO, DE;
+    chain_fill_up(SE, SO, ME, MO, nLB, UE, UO);
+    chain_fill_up(__builtin_bitreverse32(SO), __builtin_bitreverse32(SE), rMO, rME, nLBr, DO, DE);
+    const uint32_t E = UE | __builtin_bitreverse32(DE), O = UO | __builtin_bitreverse32(DO);
+    const uint32_t nE = E | (((O & g.HB) >> (g.H - 1)) & ME);  // O_(H-1) -> E_0
+    const uint32_t nO = O | (((E & g.LB) << (g.H - 1)) & MO);  // E_0 -> O_(H-1)
+    if (nE == E && nO == O) {
+      c0 = p0 ? O : E;
+      c1 = p0 ? E : O;
+      return;
+    }
+    SE = nE;
+    SO = nO;
+  }
+}
+
 // Grows both colour words w of a cluster: neighbours through other words,
 // then the closure along x0, where the two colour words of index w are each
-// other's only neighbours.  True if anything changed.
+// other's only neighbours.  True if anything changed.  Stored cluster words
+// are closed along x0, so without new bits from other words there is nothing
+// to do, except on the first pass (`first`), which closes the seed.
 template <int D>
-__device__ __forceinline__ bool grow_pair(const Geo& g, uint32_t* C, const uint32_t* Q, int w) {
+__device__ __forceinline__ bool grow_pair(const Geo& g, uint32_t* C, const uint32_t* Q, int w,
+                                          bool first) {
   const int NW = g.NW;
   const uint32_t q0 = Q[w], q1 = Q[NW + w];
   if (!(q0 | q1)) return false;
@@ -174,18 +225,10 @@ __device__ __forceinline__ bool grow_pair(const Geo& g, uint32_t* C, const uint3
     e1 |= n1[4] | n1[5];
   }
   const uint32_t c0_old = C[w], c1_old = C[NW + w];
-  uint32_t c0 = c0_old | (q0 & (e0 | n0[0] | n0[1]));
-  uint32_t c1 = c1_old | (q1 & (e1 | n1[0] | n1[1]));
-  for (;;) {
-    uint32_t a, b;
-    x0_neighbours(g, c1, p0, a, b);
-    const uint32_t nc0 = c0 | (q0 & (a | b));
-    x0_neighbours(g, nc0, p1, a, b);
-    const uint32_t nc1 = c1 | (q1 & (a | b));
-    if (nc0 == c0 && nc1 == c1) break;
-    c0 = nc0;
-    c1 = nc1;
-  }
+  uint32_t c0 = c0_old | (q0 & e0);
+  uint32_t c1 = c1_old | (q1 & e1);
+  if (!(c0 | c1) || (!first && c0 == c0_old && c1 == c1_old)) return false;
+  x0_closure(g, c0, c1, q0, q1, p0);
   if (c0 == c0_old && c1 == c1_old) return false;
   C[w] = c0;
   C[NW + w] = c1;
@@ -236,10 +279,10 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
     if (m >= incl - lc && m < incl) seed_in_rows(g, Qw, Cw, r0, r1, m - (incl - lc));
     wave_lds_sync();
     // flood fill until no word of the pair changes
-    for (;;) {
+    for (bool first = true;; first = false) {
       int changed = 0;
       for (int w = lane; w < NW; w += 64)
-        if (grow_pair<D>(g, Cw, Qw, w)) changed = 1;
+        if (grow_pair<D>(g, Cw, Qw, w, first)) changed = 1;
       wave_lds_sync();
       if (!__any(changed)) break;
     }
