@@ -236,6 +236,69 @@ __device__ __forceinline__ bool grow_pair(const Geo& g, uint32_t* C, const uint3
 }
 
 // ---------------------------------------------------------------------------
+// Column fills for a square lattice of 64 rows held one row per lane (2D,
+// L = 64: one field per word, word = row).  The vertical neighbour of bit b
+// of a colour-c row word is bit b of the colour-(1 - c) word of the next row,
+// so the chain X_r = colour (r & 1) word of row r (and Y, the other colour)
+// links equal bits of consecutive lanes.  Filling a chain from its cluster
+// bits through its q bits is a scan with the associative operator
+// (q1, c1) then (q2, c2) -> (q1 & q2, c2 | (q2 & c1)): within rows of 16
+// lanes by DPP row shifts, across rows through the row totals read back as
+// wavefront constants.  The periodic link between lanes 63 and 0 is added
+// afterwards; the flood loop repeats until nothing changes.
+// ---------------------------------------------------------------------------
+template <bool kUp>
+__device__ __forceinline__ uint32_t chain_scan(uint32_t c, uint32_t q, int lane) {
+  uint32_t Pq = q, Pc = c;
+#define PT_SCAN_STEP(CTRL)                                                        \
+  {                                                                               \
+    const uint32_t uq = (uint32_t)__builtin_amdgcn_update_dpp(                    \
+        (int)0xFFFFFFFF, (int)Pq, CTRL, 0xF, 0xF, false);                         \
+    const uint32_t uc = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Pc, CTRL, 0xF, 0xF, false); \
+    Pc |= Pq & uc;                                                                \
+    Pq &= uq;                                                                     \
+  }
+  if (kUp) {  // from lower lanes: row_shr
+    PT_SCAN_STEP(0x111) PT_SCAN_STEP(0x112) PT_SCAN_STEP(0x114) PT_SCAN_STEP(0x118)
+  } else {    // from higher lanes: row_shl
+    PT_SCAN_STEP(0x101) PT_SCAN_STEP(0x102) PT_SCAN_STEP(0x104) PT_SCAN_STEP(0x108)
+  }
+#undef PT_SCAN_STEP
+  // row totals: the last lane of each row going up, the first going down
+  const int e = kUp ? 15 : 0;
+  const uint32_t aq0 = __builtin_amdgcn_readlane(Pq, 0 + e), ac0 = __builtin_amdgcn_readlane(Pc, 0 + e);
+  const uint32_t aq1 = __builtin_amdgcn_readlane(Pq, 16 + e), ac1 = __builtin_amdgcn_readlane(Pc, 16 + e);
+  const uint32_t aq2 = __builtin_amdgcn_readlane(Pq, 32 + e), ac2 = __builtin_amdgcn_readlane(Pc, 32 + e);
+  const uint32_t aq3 = __builtin_amdgcn_readlane(Pq, 48 + e), ac3 = __builtin_amdgcn_readlane(Pc, 48 + e);
+  const int row = lane >> 4;
+  uint32_t inc;  // what enters this lane's row from the rows before it in scan order
+  if (kUp) {
+    const uint32_t e1 = ac0;
+    const uint32_t e2c = ac1 | (aq1 & e1);
+    const uint32_t e3c = ac2 | (aq2 & e2c);
+    inc = row == 0 ? 0u : row == 1 ? e1 : row == 2 ? e2c : e3c;
+  } else {
+    const uint32_t s2 = ac3;
+    const uint32_t s1c = ac2 | (aq2 & s2);
+    const uint32_t s0c = ac1 | (aq1 & s1c);
+    inc = row == 3 ? 0u : row == 2 ? s2 : row == 1 ? s1c : s0c;
+  }
+  (void)aq0;
+  (void)aq3;
+  return Pc | (Pq & inc);
+}
+
+// Both-direction fill of one chain plus the periodic link between lanes 63
+// and 0.
+__device__ __forceinline__ uint32_t chain_fill(uint32_t c, uint32_t q, int lane) {
+  uint32_t f = chain_scan<true>(c, q, lane) | chain_scan<false>(c, q, lane);
+  const uint32_t top = __builtin_amdgcn_readlane(f, 63), bottom = __builtin_amdgcn_readlane(f, 0);
+  if (lane == 0) f |= q & top;
+  if (lane == 63) f |= q & bottom;
+  return f;
+}
+
+// ---------------------------------------------------------------------------
 // Houdayer moves for all NT pairs of the resident sample: each wavefront
 // takes one pair at a time and grows its cluster alone, so clusters of very
 // different size (cold versus hot pairs) do not wait for one another.
@@ -279,12 +342,32 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
     if (m >= incl - lc && m < incl) seed_in_rows(g, Qw, Cw, r0, r1, m - (incl - lc));
     wave_lds_sync();
     // flood fill until no word of the pair changes
-    for (bool first = true;; first = false) {
-      int changed = 0;
-      for (int w = lane; w < NW; w += 64)
-        if (grow_pair<D>(g, Cw, Qw, w, first)) changed = 1;
+    if (D == 2 && NW == 64 && g.P == 1) {
+      // one row per lane: column fills by lane scans, rows closed along x0
+      const uint32_t q0 = Qw[lane], q1 = Qw[NW + lane];
+      const bool odd = lane & 1;
+      uint32_t c0 = Cw[lane], c1 = Cw[NW + lane];
+      for (;;) {
+        const uint32_t x = chain_fill(odd ? c1 : c0, odd ? q1 : q0, lane);
+        const uint32_t y = chain_fill(odd ? c0 : c1, odd ? q0 : q1, lane);
+        uint32_t n0 = odd ? y : x, n1 = odd ? x : y;
+        x0_closure(g, n0, n1, q0, q1, lane & 1);
+        const bool changed = n0 != c0 || n1 != c1;
+        c0 = n0;
+        c1 = n1;
+        if (!__any(changed)) break;
+      }
+      Cw[lane] = c0;
+      Cw[NW + lane] = c1;
       wave_lds_sync();
-      if (!__any(changed)) break;
+    } else {
+      for (bool first = true;; first = false) {
+        int changed = 0;
+        for (int w = lane; w < NW; w += 64)
+          if (grow_pair<D>(g, Cw, Qw, w, first)) changed = 1;
+        wave_lds_sync();
+        if (!__any(changed)) break;
+      }
     }
     // energy change of replica a, then exchange the replicas on the cluster
     int dl = 0;
