@@ -298,6 +298,76 @@ __device__ __forceinline__ uint32_t chain_fill(uint32_t c, uint32_t q, int lane)
   return f;
 }
 
+// Houdayer moves of a 2D sample with 64 rows (L = 64), one wavefront per
+// pair at a time and one row per lane, everything in registers: overlap,
+// seed (a scan over lanes in site order), flood fill by column scans and row
+// closures, energy change from the bonds leaving the cluster (vertical
+// neighbours taken from the adjacent lanes), exchange on the cluster.
+__device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const uint32_t* Jl,
+                                                int32_t* El, const int32_t* sotl, int s, uint32_t v,
+                                                int wave, int nwave, int lane) {
+  const int NT = g.NT;
+  const bool odd = lane & 1;  // parity of the row = p(0, row)
+  for (int k = wave; k < NT; k += nwave) {
+    const int a = sotl[k], b = NT + sotl[NT + k];
+    uint32_t* Wa = W + (size_t)a * 128;
+    uint32_t* Wb = W + (size_t)b * 128;
+    const uint32_t a0 = Wa[lane], a1 = Wa[64 + lane], b0 = Wb[lane], b1 = Wb[64 + lane];
+    const uint32_t q0 = a0 ^ b0, q1 = a1 ^ b1;
+    const uint32_t lc = __popc(q0) + __popc(q1);
+    const uint32_t n = (uint32_t)wave_sum((int)lc);
+    if (n == 0) continue;
+    // seed: the m-th q = -1 site in increasing site order (row by row)
+    const Ctr4 r = philox10(Ctr4{(uint32_t)k, v, 0u, (kTagHou << 28) | (uint32_t)s}, g.key0, g.key1);
+    const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
+    const uint32_t m = (uint32_t)__umul64hi(r64, (uint64_t)n);
+    const uint32_t incl = wave_inclusive_scan(lc, lane);
+    uint32_t c0 = 0, c1 = 0;
+    if (m >= incl - lc && m < incl) {
+      int c, bb;
+      select_in_row(g, lane, q0, q1, 0, m - (incl - lc), c, bb);
+      if (c == 0) c0 = 1u << bb;
+      if (c == 1) c1 = 1u << bb;
+    }
+    for (;;) {
+      const uint32_t x = chain_fill(odd ? c1 : c0, odd ? q1 : q0, lane);
+      const uint32_t y = chain_fill(odd ? c0 : c1, odd ? q0 : q1, lane);
+      uint32_t n0 = odd ? y : x, n1 = odd ? x : y;
+      x0_closure(g, n0, n1, q0, q1, odd);
+      const bool changed = n0 != c0 || n1 != c1;
+      c0 = n0;
+      c1 = n1;
+      if (!__any(changed)) break;
+    }
+    // energy change of replica a over the bonds of the colour-0 sites (each
+    // bond has one): +x0, -x0 in the row, +x1, -x1 in the next/previous row
+    uint32_t nc[4], na[4];
+    x0_neighbours(g, c1, odd, nc[0], nc[1]);
+    x0_neighbours(g, a1, odd, na[0], na[1]);
+    nc[2] = __shfl(c1, (lane + 1) & 63, 64);
+    nc[3] = __shfl(c1, (lane + 63) & 63, 64);
+    na[2] = __shfl(a1, (lane + 1) & 63, 64);
+    na[3] = __shfl(a1, (lane + 63) & 63, 64);
+    int cross = 0, cross_u = 0;
+#pragma unroll
+    for (int dir = 0; dir < 4; ++dir) {
+      const uint32_t X = c0 ^ nc[dir];
+      const uint32_t U = a0 ^ na[dir] ^ Jl[dir * 64 + lane];
+      cross += __popc(X);
+      cross_u += __popc(X & U);
+    }
+    const int delta = wave_sum(2 * (cross - 2 * cross_u));
+    Wa[lane] = a0 ^ c0;
+    Wa[64 + lane] = a1 ^ c1;
+    Wb[lane] = b0 ^ c0;
+    Wb[64 + lane] = b1 ^ c1;
+    if (lane == 0) {
+      El[a] += delta;
+      El[b] -= delta;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Houdayer moves for all NT pairs of the resident sample: each wavefront
 // takes one pair at a time and grows its cluster alone, so clusters of very
@@ -317,6 +387,11 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
   uint32_t* Qw = lds + A.lay.Qs + (size_t)wave * 2 * W2;
   uint32_t* Cw = Qw + W2;
   const int rpl = (g.NR + 63) / 64;  // rows per lane for the seed search
+  if (D == 2 && NW == 64 && g.P == 1) {
+    houdayer_rows64(g, W, Jl, El, sotl, s, v, wave, nwave, lane);
+    __syncthreads();
+    return;
+  }
   for (int k = wave; k < NT; k += nwave) {
     const int a = sotl[k], b = NT + sotl[NT + k];
     uint32_t* Wa = W + (size_t)a * W2;
@@ -342,32 +417,12 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
     if (m >= incl - lc && m < incl) seed_in_rows(g, Qw, Cw, r0, r1, m - (incl - lc));
     wave_lds_sync();
     // flood fill until no word of the pair changes
-    if (D == 2 && NW == 64 && g.P == 1) {
-      // one row per lane: column fills by lane scans, rows closed along x0
-      const uint32_t q0 = Qw[lane], q1 = Qw[NW + lane];
-      const bool odd = lane & 1;
-      uint32_t c0 = Cw[lane], c1 = Cw[NW + lane];
-      for (;;) {
-        const uint32_t x = chain_fill(odd ? c1 : c0, odd ? q1 : q0, lane);
-        const uint32_t y = chain_fill(odd ? c0 : c1, odd ? q0 : q1, lane);
-        uint32_t n0 = odd ? y : x, n1 = odd ? x : y;
-        x0_closure(g, n0, n1, q0, q1, lane & 1);
-        const bool changed = n0 != c0 || n1 != c1;
-        c0 = n0;
-        c1 = n1;
-        if (!__any(changed)) break;
-      }
-      Cw[lane] = c0;
-      Cw[NW + lane] = c1;
+    for (bool first = true;; first = false) {
+      int changed = 0;
+      for (int w = lane; w < NW; w += 64)
+        if (grow_pair<D>(g, Cw, Qw, w, first)) changed = 1;
       wave_lds_sync();
-    } else {
-      for (bool first = true;; first = false) {
-        int changed = 0;
-        for (int w = lane; w < NW; w += 64)
-          if (grow_pair<D>(g, Cw, Qw, w, first)) changed = 1;
-        wave_lds_sync();
-        if (!__any(changed)) break;
-      }
+      if (!__any(changed)) break;
     }
     // energy change of replica a, then exchange the replicas on the cluster
     int dl = 0;
