@@ -103,6 +103,7 @@ int job_mode(const pt_job* j, uint32_t flags, const BatchConfig& cfg) {
 int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vector<uint32_t>& jflags) {
   std::vector<FusedArgs> hj;
   std::vector<BatchItem> hi, split;
+  std::vector<std::pair<double, size_t>> split_groups;  // (cost of a part, first item)
   std::vector<double> cost;
   size_t lds_words = 0;
   int feat = 0;
@@ -132,8 +133,10 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
       if (mcs <= 0) continue;
       // the parts of a sample are consecutive, and split samples go first so
       // that all parts are taken while every workgroup is still free
-      for (int s = 0; s < j->g.S; ++s)
+      for (int s = 0; s < j->g.S; ++s) {
+        split_groups.push_back({(double)j->split_R * j->g.N * mcs, split.size()});
         for (int p = 0; p < j->split_parts; ++p) split.push_back(BatchItem{(int)jx, s, p, 0});
+      }
       continue;
     }
     const int nsets = mode == 2 ? 1 : 2;
@@ -155,6 +158,20 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     std::vector<BatchItem> sorted(hi.size());
     for (size_t i = 0; i < idx.size(); ++i) sorted[i] = hi[idx[i]];
     hi.swap(sorted);
+  }
+  if (b->cfg.order == 0 && split_groups.size() > 1) {
+    // split samples longest parts first, each sample's parts kept together
+    std::stable_sort(split_groups.begin(), split_groups.end(),
+                     [](const std::pair<double, size_t>& x, const std::pair<double, size_t>& y) {
+                       return x.first > y.first;
+                     });
+    std::vector<BatchItem> sorted;
+    sorted.reserve(split.size());
+    for (const auto& gr : split_groups) {
+      const size_t end = gr.second + (size_t)b->jobs[split[gr.second].job]->split_parts;
+      for (size_t i = gr.second; i < end; ++i) sorted.push_back(split[i]);
+    }
+    split.swap(sorted);
   }
   hi.insert(hi.begin(), split.begin(), split.end());
   b->has_split = !split.empty();
@@ -398,6 +415,23 @@ int batch_run_job(pt_batch* b, pt_job* job, int mcs, uint32_t flags) {
 }
 
 int job_plan_mode(const pt_job* j, uint32_t flags) { return job_mode(j, flags, BatchConfig{}); }
+
+void job_items(const pt_job* j, uint32_t flags, int& items, double& item_flips) {
+  const int mode = job_mode(j, flags, BatchConfig{});
+  const double lat = (double)j->g.N;
+  if (mode == 3) {
+    items = j->g.S * j->split_parts;
+    item_flips = lat * j->split_R;
+  } else if (mode == 2) {
+    items = j->g.S * 2;
+    item_flips = lat * j->g.NT;
+  } else {
+    items = j->g.S;
+    item_flips = lat * (mode < 0 ? j->g.NT : j->g.nslot);
+  }
+}
+
+int batch_slots(const pt_batch* b) { return b->ncu; }
 
 void batch_free(pt_batch* b) {
   if (!b) return;

@@ -87,6 +87,11 @@ int batch_run_job(pt_batch* b, pt_job* job, int mcs, uint32_t flags);
 bool job_is_resident(const pt_job* j, uint32_t flags);
 // The fused plan a job alone takes for `flags` (as pt_get_plan), -1 if none.
 int job_plan_mode(const pt_job* j, uint32_t flags);
+// Work items one step of the job makes for `flags`, and attempted flips per
+// step of its largest item.
+void job_items(const pt_job* j, uint32_t flags, int& items, double& item_flips);
+// Compute units of the batch's device (workgroup slots of a one-per-CU plan).
+int batch_slots(const pt_batch* b);
 // Whether a job of this shape needs the split-sample scratch (its two
 // replica sets do not fit one workgroup together, but a split plan exists),
 // and how many bytes that scratch takes.

@@ -206,10 +206,32 @@ void serve(pt_server* sv) {
     double round_flips = 0;
     std::vector<int> steps(sv->active.size());
     std::vector<uint32_t> flags(sv->active.size());
+    // Round length: steps_per_round steps of the job with the largest work
+    // item.  When every item gets a workgroup of its own, jobs with smaller
+    // items take proportionally more steps, so that all items of the round
+    // last about as long and no workgroup idles until the round ends.
+    std::vector<double> item_flips(sv->active.size());
+    int total_items = 0;
+    double f_max = 0;
+    for (size_t i = 0; i < sv->active.size(); ++i) {
+      Active& a = sv->active[i];
+      const uint32_t f = (a.req.flags & PT_MCS_HOUDAYER) |
+                         (a.done < a.req.burn_in ? 0u : (uint32_t)PT_MCS_MEASURE);
+      int items = 0;
+      job_items(a.job, f, items, item_flips[i]);
+      total_items += items;
+      if (item_flips[i] > f_max) f_max = item_flips[i];
+    }
+    const bool stretch = total_items <= batch_slots(sv->batch[1]);
     for (size_t i = 0; i < sv->active.size(); ++i) {
       Active& a = sv->active[i];
       const int left = a.req.sweeps - a.done;
-      int n = left < sv->steps_per_round ? left : sv->steps_per_round;
+      int quota = sv->steps_per_round;
+      if (stretch && item_flips[i] > 0) {
+        const double q = (double)sv->steps_per_round * f_max / item_flips[i];
+        quota = q > 1e9 ? 1000000000 : (int)q;
+      }
+      int n = left < quota ? left : quota;
       uint32_t f = a.req.flags & PT_MCS_HOUDAYER;
       if (a.done < a.req.burn_in) {
         const int to_burn = a.req.burn_in - a.done;
