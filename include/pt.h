@@ -162,6 +162,16 @@ int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
  * workgroup, and LDS bytes per workgroup (0 for mode -1).  Host only. */
 int pt_get_plan(pt_job *job, uint32_t flags, int32_t *out4);
 
+/* The same report for a job of this shape before it exists (host only, no
+ * device call): a plan depends on dim, L and replicas, not on samples. */
+int pt_plan_query(int32_t dim, int32_t L, int32_t replicas, uint32_t flags, int32_t *out4);
+
+/* Upper bound of the device bytes pt_init_ex allocates for this shape
+ * (including the split-sample scratch when the plan needs it); the request
+ * server admits by this figure.  Host only; PT_EINVAL as pt_init_ex. */
+int pt_job_bytes(int32_t samples, int32_t replicas, int32_t L, int32_t dim, uint32_t layout,
+                 const double *betas, uint64_t *out);
+
 /* Observables from the accumulated moments, in double precision.
  *   per_sample [samples][replicas][5]: <e>, <q>, <|q|>, <q^2>, <q^4>
  *   disorder   [replicas][6]: the same averaged over samples (integer

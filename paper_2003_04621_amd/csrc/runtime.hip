@@ -83,6 +83,34 @@ Geo make_geo(int S, int NT, int L, int dim, int layout, uint64_t seed) {
 
 namespace {
 
+// The LDS plans of a job of geometry job->g (host only).
+void plan_job(pt_job* job) {
+  const Geo& g = job->g;
+  job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0]);
+  job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1]);
+  job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2]);
+  job->split_ok = !job->fused_ok[0] &&
+                  split_plan(g, job->split_lay, job->split_parts, job->split_R, job->split_jlds);
+}
+
+// pt_get_plan's report for a planned job.
+void plan_report(const pt_job* job, uint32_t flags, int32_t* out4) {
+  const Geo& g = job->g;
+  const int mode = (flags & PT_MCS_PLAIN) ? -1 : job_plan_mode(job, flags);
+  out4[0] = mode;
+  if (mode < 0) {
+    out4[1] = out4[2] = out4[3] = 0;
+  } else if (mode == 3) {
+    out4[1] = job->split_parts;
+    out4[2] = job->split_R;
+    out4[3] = 4 * job->split_lay.words;
+  } else {
+    out4[1] = mode == 2 ? 2 : 1;
+    out4[2] = mode == 2 ? g.NT : g.nslot;
+    out4[3] = 4 * job->plan[mode].words;
+  }
+}
+
 int device_error(pt_job* job, hipError_t e, const char* where) {
   if (job) job->poisoned = true;
   return pt_fail(PT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
@@ -231,11 +259,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
       thrpt[(size_t)k * M + m] = threshold_u32(std::exp(-(db * (double)(2 * m))));
   }
   job->M = M;
-  job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0]);
-  job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1]);
-  job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2]);
-  job->split_ok = !job->fused_ok[0] &&
-                  split_plan(g, job->split_lay, job->split_parts, job->split_R, job->split_jlds);
+  plan_job(job);
 
   const size_t maps = sizeof(int32_t) * (size_t)samples * 2 * replicas;
   job->spins = job->dalloc(job->spin_bytes());
@@ -436,20 +460,35 @@ PT_API int pt_get_plan(pt_job* job, uint32_t flags, int32_t* out4) {
   if (!out4) return pt_fail(PT_EINVAL, "null output");
   if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
     return pt_fail(PT_EINVAL, "unknown flags");
-  const Geo& g = job->g;
-  const int mode = (flags & PT_MCS_PLAIN) ? -1 : job_plan_mode(job, flags);
-  out4[0] = mode;
-  if (mode < 0) {
-    out4[1] = out4[2] = out4[3] = 0;
-  } else if (mode == 3) {
-    out4[1] = job->split_parts;
-    out4[2] = job->split_R;
-    out4[3] = 4 * job->split_lay.words;
-  } else {
-    out4[1] = mode == 2 ? 2 : 1;
-    out4[2] = mode == 2 ? g.NT : g.nslot;
-    out4[3] = 4 * job->plan[mode].words;
-  }
+  plan_report(job, flags, out4);
+  return PT_OK;
+}
+
+PT_API int pt_plan_query(int32_t dim, int32_t L, int32_t replicas, uint32_t flags, int32_t* out4) {
+  if (!out4) return pt_fail(PT_EINVAL, "null output");
+  if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
+  if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
+  if (replicas < 2) return pt_fail(PT_EINVAL, "replicas must be >= 2");
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
+    return pt_fail(PT_EINVAL, "unknown flags");
+  pt_job job;
+  job.g = make_geo(1, replicas, L, dim, PT_LAYOUT_INT8, 0);
+  plan_job(&job);
+  plan_report(&job, flags, out4);
+  return PT_OK;
+}
+
+PT_API int pt_job_bytes(int32_t samples, int32_t replicas, int32_t L, int32_t dim, uint32_t layout,
+                        const double* betas, uint64_t* out) {
+  if (!out || !betas) return pt_fail(PT_EINVAL, "null argument");
+  if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
+  if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
+  if (samples < 1 || replicas < 2) return pt_fail(PT_EINVAL, "need samples >= 1 and replicas >= 2");
+  if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown layout");
+  for (int k = 0; k < replicas; ++k)
+    if (!(betas[k] > 0.0) || (k > 0 && !(betas[k] < betas[k - 1])))
+      return pt_fail(PT_EINVAL, "betas must be > 0 and strictly decreasing");
+  *out = (uint64_t)job_device_bytes(samples, replicas, L, dim, (int)layout, betas);
   return PT_OK;
 }
 

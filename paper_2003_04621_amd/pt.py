@@ -26,7 +26,7 @@ _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVIC
 
 EXPORTS = [
     "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_measure", "pt_mcs",
-    "pt_get_plan", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
+    "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_state", "pt_set_state",
     "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
@@ -72,7 +72,8 @@ def lib():
             "pt_init": [C.POINTER(P), I32, I32, I32, I32, P, P, U64],
             "pt_init_ex": [C.POINTER(P), I32, I32, I32, I32, P, P, U64, U32],
             "pt_sweep": [P, I32], "pt_exchange": [P], "pt_houdayer": [P], "pt_measure": [P],
-            "pt_mcs": [P, I32, U32], "pt_get_plan": [P, U32, P], "pt_observables": [P, P, P, P], "pt_destroy": [P],
+            "pt_mcs": [P, I32, U32], "pt_get_plan": [P, U32, P], "pt_plan_query": [I32, I32, I32, U32, P],
+            "pt_job_bytes": [I32, I32, I32, I32, U32, P, P], "pt_observables": [P, P, P, P], "pt_destroy": [P],
             "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
             "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
             "pt_get_state": [P, P, C.POINTER(C.c_size_t)], "pt_set_state": [P, P, C.c_size_t],
@@ -241,6 +242,27 @@ def pt_get_plan(job: Job, houdayer=False, measure=False, plain=False) -> dict:
     out = np.zeros(4, np.int32)
     _check(lib().pt_get_plan(job.h, flags, _p(out)))
     return dict(mode=int(out[0]), parts=int(out[1]), per_part=int(out[2]), lds_bytes=int(out[3]))
+
+
+def pt_plan_query(dim: int, L: int, replicas: int, houdayer=False, measure=False,
+                  plain=False) -> dict:
+    """pt_get_plan's report for a job of this shape, without creating it
+    (host only)."""
+    flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
+             | (PT_MCS_PLAIN if plain else 0))
+    out = np.zeros(4, np.int32)
+    _check(lib().pt_plan_query(int(dim), int(L), int(replicas), flags, _p(out)))
+    return dict(mode=int(out[0]), parts=int(out[1]), per_part=int(out[2]), lds_bytes=int(out[3]))
+
+
+def pt_job_bytes(samples: int, replicas: int, L: int, dim: int, betas, layout: int = PT_LAYOUT_INT8) -> int:
+    """Upper bound of the device bytes of a job of this shape (host only)."""
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    if b.size != replicas:
+        raise PTError(PT_EINVAL, "betas must have `replicas` entries")
+    out = np.zeros(1, np.uint64)
+    _check(lib().pt_job_bytes(int(samples), int(replicas), int(L), int(dim), int(layout), _p(b), _p(out)))
+    return int(out[0])
 
 
 def pt_observables(job: Job):

@@ -108,3 +108,35 @@ def test_split_in_mixed_batch(pt, graph):
             matches_oracle(pt, j, r, f"round {rnd}")
     pt.pt_batch_destroy(batch)
 
+
+
+def test_plan_query_matches_jobs_and_byte_bound(pt):
+    """pt_plan_query (host only) reports the plan a created job takes, and
+    pt_job_bytes bounds what the job allocates."""
+    import torch
+    sizes = []
+
+    def alloc(size, ctx):
+        sizes.append(int(size))
+        return torch.cuda.caching_allocator_alloc(int(size))
+
+    def free(ptr, ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+    pt.pt_set_allocator(alloc, free)
+    try:
+        for d, L, S, NT, layout in [(3, 16, 3, 8, 0), (3, 32, 2, 24, 1), (3, 48, 1, 48, 0),
+                                    (2, 64, 2, 24, 0), (2, 12, 4, 5, 1), (3, 64, 1, 8, 0)]:
+            say(f"plan/bytes d={d} L={L} S={S} NT={NT} layout={layout}")
+            J = W.couplings_pm_j(S, L, d, 7)
+            b = W.geometric_betas(0.9, 2.0, NT)
+            sizes.clear()
+            job = pt.pt_init(S, NT, L, d, J, b, 11, layout=layout)
+            assert sum(sizes) <= pt.pt_job_bytes(S, NT, L, d, b, layout=layout)
+            for hou, meas in [(False, False), (False, True), (True, True)]:
+                assert pt.pt_get_plan(job, houdayer=hou, measure=meas) == \
+                    pt.pt_plan_query(d, L, NT, houdayer=hou, measure=meas)
+            pt.pt_destroy(job)
+    finally:
+        pt.pt_set_allocator(None, None)
