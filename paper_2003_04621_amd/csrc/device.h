@@ -90,6 +90,47 @@ __device__ __forceinline__ uint32_t shift_in_less(uint32_t mask, uint32_t r, uin
   return out;
 }
 
+// 3D acceptance planes from two compares per site: with th6 <= th4 <= th2 the
+// number of thresholds above r is k = 2 [r < th4] + [r < (r < th4 ? th6 : th2)],
+// shifted in as bit planes K1 (the first term) and K0.  Two sites per block,
+// r1 shifted in before r2, so that each select reads its compare's lane mask
+// two instructions after it was written; carries out of the adds go to vcc.
+__device__ __forceinline__ void shift_in_k_pair(uint32_t& K1, uint32_t& K0, uint32_t r1, uint32_t r2,
+                                                uint32_t th2, uint32_t th4, uint32_t th6) {
+  uint32_t t, ta, tb;
+  uint64_t sa, sb;
+  asm("v_sub_co_u32_e64 %[t], %[sa], %[r1], %[th4]\n\t"
+      "v_addc_co_u32_e64 %[k1], vcc, %[k1], %[k1], %[sa]\n\t"
+      "v_sub_co_u32_e64 %[t], %[sb], %[r2], %[th4]\n\t"
+      "v_addc_co_u32_e64 %[k1], vcc, %[k1], %[k1], %[sb]\n\t"
+      "v_cndmask_b32_e64 %[ta], %[th2], %[th6], %[sa]\n\t"
+      "v_cndmask_b32_e64 %[tb], %[th2], %[th6], %[sb]\n\t"
+      "v_sub_co_u32_e32 %[t], vcc, %[r1], %[ta]\n\t"
+      "v_addc_co_u32_e32 %[k0], vcc, %[k0], %[k0], vcc\n\t"
+      "v_sub_co_u32_e32 %[t], vcc, %[r2], %[tb]\n\t"
+      "v_addc_co_u32_e32 %[k0], vcc, %[k0], %[k0], vcc"
+      : [k1] "+v"(K1), [k0] "+v"(K0), [t] "=&v"(t), [ta] "=&v"(ta), [tb] "=&v"(tb),
+        [sa] "=&s"(sa), [sb] "=&s"(sb)
+      : [r1] "v"(r1), [r2] "v"(r2), [th2] "v"(th2), [th4] "v"(th4), [th6] "v"(th6)
+      : "vcc");
+}
+
+// The same for one site.
+__device__ __forceinline__ void shift_in_k_one(uint32_t& K1, uint32_t& K0, uint32_t r, uint32_t th2,
+                                               uint32_t th4, uint32_t th6) {
+  uint32_t t, ta;
+  uint64_t sa;
+  asm("v_sub_co_u32_e64 %[t], %[sa], %[r], %[th4]\n\t"
+      "v_addc_co_u32_e64 %[k1], vcc, %[k1], %[k1], %[sa]\n\t"
+      "s_nop 1\n\t"
+      "v_cndmask_b32_e64 %[ta], %[th2], %[th6], %[sa]\n\t"
+      "v_sub_co_u32_e32 %[t], vcc, %[r], %[ta]\n\t"
+      "v_addc_co_u32_e32 %[k0], vcc, %[k0], %[k0], vcc"
+      : [k1] "+v"(K1), [k0] "+v"(K0), [t] "=&v"(t), [ta] "=&v"(ta), [sa] "=&s"(sa)
+      : [r] "v"(r), [th2] "v"(th2), [th4] "v"(th4), [th6] "v"(th6)
+      : "vcc");
+}
+
 // Counter tags (top four bits of the fourth counter word).
 constexpr uint32_t kTagInit = 2u, kTagMetro = 3u, kTagPT = 4u, kTagHou = 5u;
 

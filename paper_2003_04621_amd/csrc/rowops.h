@@ -55,8 +55,9 @@ __device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint
 
   // Comparison planes: one Philox call per four sites of a row field.  Bits
   // are shifted in from the top site of the top field down, so that bit
-  // f*H + b ends up holding site b of field f.
-  uint32_t C1 = 0, C2 = 0, C3 = 0;
+  // f*H + b ends up holding site b of field f.  In 3D the three nested
+  // threshold tests come from two compares per site (shift_in_k_pair).
+  uint32_t C1 = 0, C2 = 0, C3 = 0;  // 2D: [r < th2], [r < th4]; 3D: K1, K0 (below)
   const uint32_t c1w = 2u * tcount + (uint32_t)c;
   const uint32_t c3w = (kTagMetro << 28) | (uint32_t)s;
   for (int f = g.P - 1; f >= 0; --f) {
@@ -65,25 +66,40 @@ __device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint
       const Ctr4 r = philox10(Ctr4{R * (uint32_t)g.G + (uint32_t)grp, c1w, (uint32_t)slot, c3w},
                               g.key0, g.key1);
       const int nv = g.H - 4 * grp;  // sites of this row field served by the call
-      if (nv >= 4) {
-        C1 = shift_in_less(C1, r.w, th2);
-        C2 = shift_in_less(C2, r.w, th4);
-        if (D == 3) C3 = shift_in_less(C3, r.w, th6);
+      if (D == 3) {
+        if (nv >= 4) {
+          shift_in_k_pair(C1, C2, r.w, r.z, th2, th4, th6);
+        } else if (nv == 3) {
+          shift_in_k_one(C1, C2, r.z, th2, th4, th6);
+        }
+        if (nv >= 2)
+          shift_in_k_pair(C1, C2, r.y, r.x, th2, th4, th6);
+        else
+          shift_in_k_one(C1, C2, r.x, th2, th4, th6);
+      } else {
+        if (nv >= 4) {
+          C1 = shift_in_less(C1, r.w, th2);
+          C2 = shift_in_less(C2, r.w, th4);
+        }
+        if (nv >= 3) {
+          C1 = shift_in_less(C1, r.z, th2);
+          C2 = shift_in_less(C2, r.z, th4);
+        }
+        if (nv >= 2) {
+          C1 = shift_in_less(C1, r.y, th2);
+          C2 = shift_in_less(C2, r.y, th4);
+        }
+        C1 = shift_in_less(C1, r.x, th2);
+        C2 = shift_in_less(C2, r.x, th4);
       }
-      if (nv >= 3) {
-        C1 = shift_in_less(C1, r.z, th2);
-        C2 = shift_in_less(C2, r.z, th4);
-        if (D == 3) C3 = shift_in_less(C3, r.z, th6);
-      }
-      if (nv >= 2) {
-        C1 = shift_in_less(C1, r.y, th2);
-        C2 = shift_in_less(C2, r.y, th4);
-        if (D == 3) C3 = shift_in_less(C3, r.y, th6);
-      }
-      C1 = shift_in_less(C1, r.x, th2);
-      C2 = shift_in_less(C2, r.x, th4);
-      if (D == 3) C3 = shift_in_less(C3, r.x, th6);
     }
+  }
+  if (D == 3) {
+    // K1 = [r < th4] and K0 as above: [r < th2] = K1 | K0, [r < th6] = K1 & K0
+    const uint32_t K1 = C1, K0 = C2;
+    C1 = K1 | K0;
+    C2 = K1;
+    C3 = K1 & K0;
   }
 
   // Truth tables over (u2, u1, u0) are indexed by u itself.  The planes are
