@@ -60,15 +60,26 @@ __device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint
   uint32_t C1 = 0, C2 = 0, C3 = 0;  // 2D: [r < th2], [r < th4]; 3D: K1, K0 (below)
   const uint32_t c1w = 2u * tcount + (uint32_t)c;
   const uint32_t c3w = (kTagMetro << 28) | (uint32_t)s;
-  if (D == 3 && (g.H & 3) == 0) {
+  if ((g.H & 3) == 0) {
     // every call serves four sites (L a multiple of 8): no partial groups
     for (int f = g.P - 1; f >= 0; --f) {
       const uint32_t R = (uint32_t)word_row(g, q, f);
       for (int grp = g.G - 1; grp >= 0; --grp) {
         const Ctr4 r = philox10(Ctr4{R * (uint32_t)g.G + (uint32_t)grp, c1w, (uint32_t)slot, c3w},
                                 g.key0, g.key1);
-        shift_in_k_pair(C1, C2, r.w, r.z, th2, th4, th6);
-        shift_in_k_pair(C1, C2, r.y, r.x, th2, th4, th6);
+        if (D == 3) {
+          shift_in_k_pair(C1, C2, r.w, r.z, th2, th4, th6);
+          shift_in_k_pair(C1, C2, r.y, r.x, th2, th4, th6);
+        } else {
+          C1 = shift_in_less(C1, r.w, th2);
+          C2 = shift_in_less(C2, r.w, th4);
+          C1 = shift_in_less(C1, r.z, th2);
+          C2 = shift_in_less(C2, r.z, th4);
+          C1 = shift_in_less(C1, r.y, th2);
+          C2 = shift_in_less(C2, r.y, th4);
+          C1 = shift_in_less(C1, r.x, th2);
+          C2 = shift_in_less(C2, r.x, th4);
+        }
       }
     }
   } else {
