@@ -315,7 +315,7 @@ def main():
                 "traffic": (args.traffic_bytes if args.traffic_bytes is not None else
                             TRAFFIC_3D_L16_INT8_500
                             if (wl.name, args.layout, chunk) == ("3d_l16", "int8", 500) else None),
-                "kernel": f"k_batch<{wl.dim}> ({chunk} steps per launch)",
+                "kernel": f"k_batch<{wl.dim}, {2 | (1 if wl.houdayer else 0)}> ({chunk} steps per launch)",
                 "launch_ms": round(launch_ms, 4)}
 
     # the same steps as separate per-step launches, for the fused/plain ratio
