@@ -262,12 +262,20 @@ __device__ __forceinline__ void select_in_row(const Geo& g, int R, uint32_t Q0, 
 // Field rotations of a P*H-bit word: result field f = source field f+1
 // (rot_fields_down) or f-1 (rot_fields_up), cyclically.
 __device__ __forceinline__ uint32_t rot_fields_down(const Geo& g, uint32_t X) {
+  if (g.P * g.H == 32) return __builtin_amdgcn_alignbit(X, X, (uint32_t)g.H);  // rotate right
   const uint64_t XX = (uint64_t)X | ((uint64_t)X << (g.P * g.H));
   return (uint32_t)(XX >> g.H) & g.maskW;
 }
 __device__ __forceinline__ uint32_t rot_fields_up(const Geo& g, uint32_t X) {
+  if (g.P * g.H == 32) return __builtin_amdgcn_alignbit(X, X, (uint32_t)(32 - g.H));
   const uint64_t XX = (uint64_t)X | ((uint64_t)X << (g.P * g.H));
   return (uint32_t)(XX >> ((g.P - 1) * g.H)) & g.maskW;
+}
+
+// a if take else b, without a branch.
+__device__ __forceinline__ uint32_t pick(bool take, uint32_t a, uint32_t b) {
+  const uint32_t m = 0u - (uint32_t)take;
+  return (a & m) | (b & ~m);
 }
 
 // +x0 / -x0 neighbour words of a colour-c word whose opposite-colour word is
@@ -289,12 +297,12 @@ __device__ __forceinline__ void neighbour_words(const Geo& g, const uint32_t* Wo
     n[2] = Wo[q.w1p];
     n[3] = Wo[q.w1m];
     const uint32_t sp = Wo[q.wsp], sm = Wo[q.wsm];
-    n[4] = q.crp ? rot_fields_down(g, sp) : sp;
-    n[5] = q.crm ? rot_fields_up(g, sm) : sm;
+    n[4] = pick(q.crp, rot_fields_down(g, sp), sp);
+    n[5] = pick(q.crm, rot_fields_up(g, sm), sm);
   } else {
     const uint32_t sp = Wo[q.wsp], sm = Wo[q.wsm];
-    n[2] = q.crp ? rot_fields_down(g, sp) : sp;
-    n[3] = q.crm ? rot_fields_up(g, sm) : sm;
+    n[2] = pick(q.crp, rot_fields_down(g, sp), sp);
+    n[3] = pick(q.crm, rot_fields_up(g, sm), sm);
   }
 }
 
