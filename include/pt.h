@@ -253,8 +253,13 @@ int pt_batch_destroy(pt_batch *b);
  * (continuous batching: admissions and completions happen between rounds).
  * Each job measures every step after its burn-in; on completion its
  * disorder-averaged observables are kept for pt_server_poll and its memory is
- * released.  Device memory comes from hipMalloc, not the allocator hooks. */
+ * released.  Job set-up and read-out overlap the running round on a stream of
+ * their own; device memory comes from a stream-ordered pool owned by the
+ * server (not the allocator hooks) and returns to it when a job finishes. */
 int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server **out);
+/* A round gives each job up to steps_per_round steps; when every work item of
+ * the round has a workgroup of its own, jobs whose items are smaller than the
+ * largest get proportionally more, so that all items take about as long. */
 /* Copies the request and queues it; *ticket identifies it.  PT_EINVAL for
  * arguments pt_init would reject (or burn_in outside [0, sweeps]). */
 int pt_server_submit(pt_server *s, const pt_request *req, uint64_t *ticket);

@@ -1,8 +1,9 @@
 // fused.hip -- whole Monte Carlo steps (Sec. 2.4: Metropolis sweep, Houdayer
-// move per same-temperature pair, replica-exchange pass, measurement) for one
-// disorder sample per workgroup, every configuration of the sample resident
-// in LDS as colour-split row words for all steps of the launch.  HBM is
-// touched only to load the sample at the start and store it at the end.
+// move per same-temperature pair, replica-exchange pass, measurement) in one
+// persistent kernel.  A workgroup holds one disorder sample (or one replica
+// set of it, or one part of a sample too large for a workgroup) resident in
+// LDS as colour-split row words for all steps of the launch; HBM is touched
+// only to load the configurations at the start and store them at the end.
 //
 // Results are bit-identical to the per-step kernels: the same row update
 // (rowops.h), the same Philox counters, exchange decisions taken in ascending
@@ -796,12 +797,11 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) 
   lay.rpt = take(2 * g.NT, 1);
   lay.acc = take((2 * (size_t)g.NT * g.NT + 3) / 4, 1);
   lay.PC = 0;
-  lay.Qs = lay.Cs = lay.hcnt = lay.hdelta = (int)off;
+  lay.Qs = (int)off;
   if (hou && nsets == 2) {
     // overlap and cluster words for each wavefront
     lay.PC = waves;
     lay.Qs = take((size_t)waves * 2 * W2, 1);
-    lay.Cs = lay.Qs;
   }
   lay.words = (int)off;
   return off <= budget;
@@ -843,7 +843,7 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
     lay.rpt = take(2 * g.NT, 1);
     lay.acc = take((2 * (size_t)g.NT * g.NT + 3) / 4, 1);
     lay.PC = 0;
-    lay.Qs = lay.Cs = lay.hcnt = lay.hdelta = (int)off;
+    lay.Qs = (int)off;
     lay.words = (int)off;
     return off <= budget;
   }

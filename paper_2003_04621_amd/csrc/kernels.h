@@ -42,10 +42,12 @@ hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E,
 // kernels that read them).
 hipError_t launch_advance(DevCounters* ctr, CounterStep step, hipStream_t st);
 
-// LDS word offsets of the fused Monte Carlo step kernel (one sample per
-// workgroup).  PC = Houdayer pairs processed together.
+// LDS word offsets of the fused Monte Carlo step kernel: configurations W,
+// couplings J, energies E, maps sot/tos (and the pre-pass copy sot0),
+// threshold rows, moments, overlap counts, exchange randoms and decision
+// matrix, and the Houdayer words Qs of PC wavefronts; `words` in all.
 struct FusedLayout {
-  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, Qs, Cs, hcnt, hdelta, PC, words;
+  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, Qs, PC, words;
 };
 
 // Everything one fused workgroup needs about a job, for nmcs steps.
