@@ -174,19 +174,17 @@ __device__ __forceinline__ void chain_fill_up(uint32_t SF, uint32_t SG, uint32_t
   UG = SG | (UF & MG);
 }
 
-// Closure of the cluster words c0, c1 of one word index along x0 (the two
-// colour words hold each row's even and odd sites): every site of q linked to
-// the cluster through a run of q sites of its row, periodic in x0.  The even
-// sites E and odd sites O of a row alternate E_0 O_0 E_1 O_1 ...; an upward
-// fill and a bit-reversed (downward) fill cover each run from its lowest to
-// its highest seed, and a run through the row's end is continued from its
-// other end in one more pass.
-__device__ __forceinline__ void x0_closure(const Geo& g, uint32_t& c0, uint32_t& c1, uint32_t q0,
-                                           uint32_t q1, int p0) {
-  uint32_t SE = p0 ? c1 : c0, SO = p0 ? c0 : c1;
-  const uint32_t ME = p0 ? q1 : q0, MO = p0 ? q0 : q1;
-  const uint32_t rME = __builtin_bitreverse32(ME), rMO = __builtin_bitreverse32(MO);
+// Closure along x0 of the cluster words of one word index in row form: E and
+// O hold the even and odd sites of each row field (E_0 O_0 E_1 O_1 ...), ME
+// and MO the q sites, rME and rMO their bit reversals.  Every site of q
+// linked to the cluster through a run of q sites of its row is added,
+// periodic in x0: an upward fill and a bit-reversed (downward) fill cover
+// each run from its lowest to its highest seed, and a run through the row's
+// end is continued from its other end in one more pass.
+__device__ __forceinline__ void row_closure(const Geo& g, uint32_t& E_io, uint32_t& O_io,
+                                            uint32_t ME, uint32_t MO, uint32_t rME, uint32_t rMO) {
   const uint32_t nLB = ~g.LB, nLBr = ~__builtin_bitreverse32(g.HB);
+  uint32_t SE = E_io, SO = O_io;
   for (;;) {
     uint32_t UE, UO, DO, DE;
     chain_fill_up(SE, SO, ME, MO, nLB, UE, UO);
@@ -195,13 +193,24 @@ __device__ __forceinline__ void x0_closure(const Geo& g, uint32_t& c0, uint32_t&
     const uint32_t nE = E | (((O & g.HB) >> (g.H - 1)) & ME);  // O_(H-1) -> E_0
     const uint32_t nO = O | (((E & g.LB) << (g.H - 1)) & MO);  // E_0 -> O_(H-1)
     if (nE == E && nO == O) {
-      c0 = p0 ? O : E;
-      c1 = p0 ? E : O;
+      E_io = E;
+      O_io = O;
       return;
     }
     SE = nE;
     SO = nO;
   }
+}
+
+// The same closure for the colour words c0, c1 of a word whose rows have
+// parity p0 (the even sites of a row have colour p0).
+__device__ __forceinline__ void x0_closure(const Geo& g, uint32_t& c0, uint32_t& c1, uint32_t q0,
+                                           uint32_t q1, int p0) {
+  uint32_t E = p0 ? c1 : c0, O = p0 ? c0 : c1;
+  const uint32_t ME = p0 ? q1 : q0, MO = p0 ? q0 : q1;
+  row_closure(g, E, O, ME, MO, __builtin_bitreverse32(ME), __builtin_bitreverse32(MO));
+  c0 = p0 ? O : E;
+  c1 = p0 ? E : O;
 }
 
 // Grows both colour words w of a cluster: neighbours through other words,
@@ -238,83 +247,113 @@ __device__ __forceinline__ bool grow_pair(const Geo& g, uint32_t* C, const uint3
 
 // ---------------------------------------------------------------------------
 // Column fills for a square lattice of 64 rows held one row per lane (2D,
-// L = 64: one field per word, word = row).  The vertical neighbour of bit b
-// of a colour-c row word is bit b of the colour-(1 - c) word of the next row,
-// so the chain X_r = colour (r & 1) word of row r (and Y, the other colour)
-// links equal bits of consecutive lanes.  Filling a chain from its cluster
-// bits through its q bits is a scan with the associative operator
-// (q1, c1) then (q2, c2) -> (q1 & q2, c2 | (q2 & c1)): within rows of 16
-// lanes by DPP row shifts, across rows through the row totals read back as
-// wavefront constants.  The periodic link between lanes 63 and 0 is added
-// afterwards; the flood loop repeats until nothing changes.
+// L = 64: one field per word, word = row).  The even sites of row r have
+// colour r & 1, and the site above bit b of row r's even-site word is bit b
+// of row r + 1's even-site word (likewise for the odd sites), so the chain
+// X_r = even-site word of row r (and Y, the odd-site words) links equal bits
+// of consecutive lanes, periodically (lane 63 to lane 0).  Filling a chain
+// from its cluster bits through its q bits is a scan with the associative
+// operator (q1, c1) then (q2, c2) -> (q1 & q2, c2 | (q2 & c1)).  Upward it
+// runs over rows of 16 lanes by DPP row shifts and then across rows by the
+// DPP broadcasts of lanes 15 and 31; downward by row shifts and then across
+// rows through the four row totals read back as wavefront constants.  The
+// AND-of-q half of every step depends on q alone and is computed once per
+// pair; each fill then costs one DPP move and one AND-OR per step.
 // ---------------------------------------------------------------------------
-template <bool kUp>
-__device__ __forceinline__ uint32_t chain_scan(uint32_t c, uint32_t q, int lane) {
-  uint32_t Pq = q, Pc = c;
-#define PT_SCAN_STEP(CTRL)                                                        \
-  {                                                                               \
-    const uint32_t uq = (uint32_t)__builtin_amdgcn_update_dpp(                    \
-        (int)0xFFFFFFFF, (int)Pq, CTRL, 0xF, 0xF, false);                         \
-    const uint32_t uc = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Pc, CTRL, 0xF, 0xF, false); \
-    Pc |= Pq & uc;                                                                \
-    Pq &= uq;                                                                     \
-  }
-  if (kUp) {  // from lower lanes: row_shr
-    PT_SCAN_STEP(0x111) PT_SCAN_STEP(0x112) PT_SCAN_STEP(0x114) PT_SCAN_STEP(0x118)
-  } else {    // from higher lanes: row_shl
-    PT_SCAN_STEP(0x101) PT_SCAN_STEP(0x102) PT_SCAN_STEP(0x104) PT_SCAN_STEP(0x108)
-  }
-#undef PT_SCAN_STEP
-  // row totals: the last lane of each row going up, the first going down
-  const int e = kUp ? 15 : 0;
-  const uint32_t aq0 = __builtin_amdgcn_readlane(Pq, 0 + e), ac0 = __builtin_amdgcn_readlane(Pc, 0 + e);
-  const uint32_t aq1 = __builtin_amdgcn_readlane(Pq, 16 + e), ac1 = __builtin_amdgcn_readlane(Pc, 16 + e);
-  const uint32_t aq2 = __builtin_amdgcn_readlane(Pq, 32 + e), ac2 = __builtin_amdgcn_readlane(Pc, 32 + e);
-  const uint32_t aq3 = __builtin_amdgcn_readlane(Pq, 48 + e), ac3 = __builtin_amdgcn_readlane(Pc, 48 + e);
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_ones(uint32_t x) {  // lanes without a source: ~0
+  return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_zero(uint32_t x) {  // lanes without a source: 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, ROWS == 0xF);
+}
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
+constexpr int kBcast15 = 0x142, kBcast31 = 0x143;  // to rows 1, 3 / rows 2, 3
+
+struct ColumnChain {
+  uint32_t q;
+  uint32_t p1, p2, p3, p4, p5, p6;  // upward: AND of q over the lanes each step has joined
+  uint32_t d1, d2, d3;              // downward, within the row
+  uint32_t m0, m1, m2, m3;          // AND of q from the lane to the top of its row, row r only
+  uint32_t t0, t1, t2, t3;          // AND of q over all of row r (wavefront constants)
+};
+
+__device__ __forceinline__ ColumnChain column_chain(uint32_t q, int lane) {
+  ColumnChain h;
+  h.q = q;
+  uint32_t p = q;
+  h.p1 = p = p & dpp_ones<kRowShr1>(p);
+  h.p2 = p = p & dpp_ones<kRowShr2>(p);
+  h.p3 = p = p & dpp_ones<kRowShr4>(p);
+  h.p4 = p = p & dpp_ones<kRowShr8>(p);
+  h.p5 = p = p & dpp_ones<kBcast15, 0xA>(p);
+  h.p6 = p & dpp_ones<kBcast31, 0xC>(p);
+  uint32_t d = q;
+  h.d1 = d = d & dpp_ones<kRowShl1>(d);
+  h.d2 = d = d & dpp_ones<kRowShl2>(d);
+  h.d3 = d = d & dpp_ones<kRowShl4>(d);
+  d &= dpp_ones<kRowShl8>(d);
   const int row = lane >> 4;
-  uint32_t inc;  // what enters this lane's row from the rows before it in scan order
-  if (kUp) {
-    const uint32_t e1 = ac0;
-    const uint32_t e2c = ac1 | (aq1 & e1);
-    const uint32_t e3c = ac2 | (aq2 & e2c);
-    inc = row == 0 ? 0u : row == 1 ? e1 : row == 2 ? e2c : e3c;
-  } else {
-    const uint32_t s2 = ac3;
-    const uint32_t s1c = ac2 | (aq2 & s2);
-    const uint32_t s0c = ac1 | (aq1 & s1c);
-    inc = row == 3 ? 0u : row == 2 ? s2 : row == 1 ? s1c : s0c;
-  }
-  (void)aq0;
-  (void)aq3;
-  return Pc | (Pq & inc);
+  h.m0 = row == 0 ? d : 0u;
+  h.m1 = row == 1 ? d : 0u;
+  h.m2 = row == 2 ? d : 0u;
+  h.m3 = row == 3 ? d : 0u;
+  h.t0 = (uint32_t)__builtin_amdgcn_readlane((int)d, 0);
+  h.t1 = (uint32_t)__builtin_amdgcn_readlane((int)d, 16);
+  h.t2 = (uint32_t)__builtin_amdgcn_readlane((int)d, 32);
+  h.t3 = (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
+  return h;
 }
 
-// Both-direction fill of one chain plus the periodic link between lanes 63
-// and 0.
-__device__ __forceinline__ uint32_t chain_fill(uint32_t c, uint32_t q, int lane) {
-  uint32_t f = chain_scan<true>(c, q, lane) | chain_scan<false>(c, q, lane);
-  const uint32_t top = __builtin_amdgcn_readlane(f, 63), bottom = __builtin_amdgcn_readlane(f, 0);
-  if (lane == 0) f |= q & top;
-  if (lane == 63) f |= q & bottom;
-  return f;
+// Every q bit of the chain connected along it (periodically) to a bit of c,
+// for c a subset of q.
+__device__ __forceinline__ uint32_t column_fill(const ColumnChain& h, uint32_t c) {
+  // upward; then what reaches lane 63 continues from lane 0
+  uint32_t u = c;
+  u |= dpp_zero<kRowShr1>(u) & h.q;
+  u |= dpp_zero<kRowShr2>(u) & h.p1;
+  u |= dpp_zero<kRowShr4>(u) & h.p2;
+  u |= dpp_zero<kRowShr8>(u) & h.p3;
+  u |= dpp_zero<kBcast15, 0xA>(u) & h.p4;
+  u |= dpp_zero<kBcast31, 0xC>(u) & h.p5;
+  u |= h.p6 & (uint32_t)__builtin_amdgcn_readlane((int)u, 63);
+  // downward within rows, then across rows from the reach at each row's
+  // lowest lane: r0 (lane 0, without the wrap) goes on from lane 63
+  uint32_t d = c;
+  d |= dpp_zero<kRowShl1>(d) & h.q;
+  d |= dpp_zero<kRowShl2>(d) & h.d1;
+  d |= dpp_zero<kRowShl4>(d) & h.d2;
+  d |= dpp_zero<kRowShl8>(d) & h.d3;
+  const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)d, 0);
+  const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)d, 16);
+  const uint32_t c2 = (uint32_t)__builtin_amdgcn_readlane((int)d, 32);
+  const uint32_t c3 = (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
+  const uint32_t r0 = c0 | (h.t0 & (c1 | (h.t1 & (c2 | (h.t2 & c3)))));
+  const uint32_t r48 = c3 | (h.t3 & r0);
+  const uint32_t r32 = c2 | (h.t2 & r48);
+  const uint32_t r16 = c1 | (h.t1 & r32);
+  d |= (h.m0 & r16) | (h.m1 & r32) | (h.m2 & r48) | (h.m3 & r0);
+  return u | d;
 }
 
 // Houdayer moves of a 2D sample with 64 rows (L = 64), one wavefront per
 // pair at a time and one row per lane, everything in registers: overlap,
-// seed (a scan over lanes in site order), flood fill by column scans and row
-// closures, energy change from the bonds leaving the cluster (vertical
-// neighbours taken from the adjacent lanes), exchange on the cluster.
+// seed (a scan over lanes in site order), flood fill alternating column
+// fills and row closures until one of them adds nothing, energy change from
+// the bonds leaving the cluster (vertical neighbours taken from the adjacent
+// lanes), exchange on the cluster.
 __device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const uint32_t* Jl,
                                                 int32_t* El, const int32_t* sotl, int s, uint32_t v,
                                                 int wave, int nwave, int lane) {
   const int NT = g.NT;
-  const bool odd = lane & 1;  // parity of the row = p(0, row)
+  const bool odd = lane & 1;  // parity of the row = colour of its even sites
   for (int k = wave; k < NT; k += nwave) {
     const int a = sotl[k], b = NT + sotl[NT + k];
     uint32_t* Wa = W + (size_t)a * 128;
     uint32_t* Wb = W + (size_t)b * 128;
-    const uint32_t a0 = Wa[lane], a1 = Wa[64 + lane], b0 = Wb[lane], b1 = Wb[64 + lane];
-    const uint32_t q0 = a0 ^ b0, q1 = a1 ^ b1;
+    const uint32_t q0 = Wa[lane] ^ Wb[lane], q1 = Wa[64 + lane] ^ Wb[64 + lane];
     const uint32_t lc = __popc(q0) + __popc(q1);
     const uint32_t n = (uint32_t)wave_sum((int)lc);
     if (n == 0) continue;
@@ -323,23 +362,29 @@ __device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const
     const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
     const uint32_t m = (uint32_t)__umul64hi(r64, (uint64_t)n);
     const uint32_t incl = wave_inclusive_scan(lc, lane);
-    uint32_t c0 = 0, c1 = 0;
+    uint32_t X = 0, Y = 0;  // cluster: even-site and odd-site words of the row
     if (m >= incl - lc && m < incl) {
       int c, bb;
       select_in_row(g, lane, q0, q1, 0, m - (incl - lc), c, bb);
-      if (c == 0) c0 = 1u << bb;
-      if (c == 1) c1 = 1u << bb;
+      if (c == (int)odd) X = 1u << bb;
+      if (c == 1 - (int)odd) Y = 1u << bb;
     }
+    const uint32_t qx = odd ? q1 : q0, qy = odd ? q0 : q1;
+    const uint32_t rqx = __builtin_bitreverse32(qx), rqy = __builtin_bitreverse32(qy);
+    row_closure(g, X, Y, qx, qy, rqx, rqy);
+    const ColumnChain hx = column_chain(qx, lane), hy = column_chain(qy, lane);
     for (;;) {
-      const uint32_t x = chain_fill(odd ? c1 : c0, odd ? q1 : q0, lane);
-      const uint32_t y = chain_fill(odd ? c0 : c1, odd ? q0 : q1, lane);
-      uint32_t n0 = odd ? y : x, n1 = odd ? x : y;
-      x0_closure(g, n0, n1, q0, q1, odd);
-      const bool changed = n0 != c0 || n1 != c1;
-      c0 = n0;
-      c1 = n1;
-      if (!__any(changed)) break;
+      uint32_t nx = column_fill(hx, X), ny = column_fill(hy, Y);
+      if (!__any(nx != X || ny != Y)) break;
+      X = nx;
+      Y = ny;
+      row_closure(g, nx, ny, qx, qy, rqx, rqy);
+      if (!__any(nx != X || ny != Y)) break;
+      X = nx;
+      Y = ny;
     }
+    const uint32_t c0 = odd ? Y : X, c1 = odd ? X : Y;
+    const uint32_t a0 = Wa[lane], a1 = Wa[64 + lane], b0 = Wb[lane], b1 = Wb[64 + lane];
     // energy change of replica a over the bonds of the colour-0 sites (each
     // bond has one): +x0, -x0 in the row, +x1, -x1 in the next/previous row
     uint32_t nc[4], na[4];

@@ -214,6 +214,25 @@ def test_full_size_2d_l64_houdayer_sampled(pt):
         assert (a[picks] == b).all()
 
 
+def test_2d_l64_houdayer_long_cold(pt):
+    """2D L=64 at the workload's lowest temperatures for 300 steps of sweep,
+    Houdayer move, exchange and measurement: overlap clusters grow large and
+    cross the periodic boundary in both directions, which exercises every
+    branch of the in-register cluster fill."""
+    S, NT = 2, 8
+    betas = W.power_law_betas(0.2, 0.6, NT, W.phi_star(64))
+    J = W.couplings_pm_j(S, 64, 2, 4242)
+    say(f"case 2d L=64 S={S} NT={NT} cold, 300 steps")
+    job = pt.pt_init(S, NT, 64, 2, J, betas, 99)
+    ref = oracle.OracleJob(S, NT, 64, 2, J, betas, 99)
+    for n in (150, 150):
+        pt.pt_mcs(job, n, houdayer=True, measure=True)
+        ref.mcs(n, houdayer=True, measure=True)
+        compare(pt, job, ref, f"after {n}")
+    compare_observables(pt, job, ref)
+    pt.pt_destroy(job)
+
+
 @pytest.mark.parametrize("d,L,S,NT,layout,hou,meas", [
     (3, 8, 3, 5, 0, False, True), (3, 16, 2, 6, 1, True, True), (2, 64, 2, 5, 0, True, True),
     (2, 6, 3, 3, 1, True, False), (3, 12, 2, 4, 0, False, False), (2, 16, 4, 7, 0, True, True),
