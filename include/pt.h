@@ -231,17 +231,27 @@ int pt_batch_set_stream(pt_batch *b, void *hip_stream);
 int pt_batch_run(pt_batch *b, int32_t mcs, uint32_t flags);
 
 /* Autotuner: times trial_mcs steps of each launch configuration (threads per
- * workgroup 1024/512/256, one or two replica sets per item, largest-first or
+ * workgroup 1024/768/512/256, one or two replica sets per item, largest-first or
  * job order) on the batch itself, restores every job's state after each trial,
  * and keeps the fastest.  cache_path (may be NULL) is a JSON-lines file keyed
  * by the batch shape; a hit skips the trials. */
 int pt_batch_tune(pt_batch *b, int32_t trial_mcs, uint32_t flags, const char *cache_path);
 /* cfg3 = {threads per workgroup, replica sets per item, order}.  threads 0
- * (the default) picks per launch the size that keeps the most workgroups
- * resident per CU with at least 16 wavefronts (from the launch's LDS plan and
- * its kernel's registers); get_config then reports the size last used. */
+ * (the default) picks per launch one of 1024/768/512/256 threads (a multiple
+ * of four wavefronts, so that a CU's four SIMDs carry equal shares): with no
+ * more items than CUs the largest; otherwise the one with the most wavefronts
+ * resident per CU (the runtime's occupancy for the launch's LDS plan and
+ * kernel), then two or more workgroups per CU, then the larger size;
+ * get_config then reports the size last used. */
 int pt_batch_get_config(pt_batch *b, int32_t *cfg3);
+/* threads: 0 (automatic) or a multiple of 64 up to 1024; sets: 1 or 2
+ * replica sets per item when a sample's two sets may run apart; order: 0
+ * largest items first, 1 job order.  PT_EINVAL otherwise. */
 int pt_batch_set_config(pt_batch *b, int32_t threads, int32_t sets, int32_t order);
+/* out3 = {workgroups, threads per workgroup, workgroups resident per CU} of
+ * the grid the batch last built (the runtime's occupancy for the launch's
+ * kernel, LDS plan and workgroup size); zeros before the first run. */
+int pt_batch_launch_shape(pt_batch *b, int32_t *out3);
 int pt_batch_destroy(pt_batch *b);
 
 /* ---- served form ----------------------------------------------------------- */

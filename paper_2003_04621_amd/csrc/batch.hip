@@ -48,7 +48,8 @@ struct pt_batch {
   bool graph_ok = false;
   bool has_split = false;  // the work list holds split samples
   int feat = 0;            // kinds of work in the work list (kFeat*)
-  int threads = 1024;      // threads per workgroup of the built launch
+  int threads = 0;         // threads per workgroup of the built launch
+  int per_cu = 0;          // workgroups of that size resident per CU
 };
 
 namespace {
@@ -204,37 +205,53 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
   b->nitems = (int)hi.size();
   b->lds_bytes = lds_words * 4;
   b->feat = feat;
-  int vgprs = 128;
-  e = prepare_batch(b->d, feat, b->lds_bytes, &vgprs);
+  e = prepare_batch(b->d, feat, b->lds_bytes, nullptr);
   if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
-  // persistent grid: as many workgroups as can be resident at once (LDS per
-  // CU; wavefronts per SIMD from the kernel's VGPRs, 512 per lane, at most 8).
-  // Unless configured, the workgroup size is the one that keeps the most
-  // workgroups resident per CU with at least 16 wavefronts, else the most
-  // wavefronts: several workgroups per CU fill each other's barriers and
-  // serial exchange passes.
-  const int by_lds = (int)((160 * 1024) / std::max<size_t>(b->lds_bytes + 64, 1));
-  const int waves_simd = std::max(1, std::min(8, 512 / std::max(8, (vgprs + 7) / 8 * 8)));
+  // persistent grid: as many workgroups as can be resident at once (the
+  // runtime's occupancy for this kernel, LDS plan and workgroup size).
+  // Unless configured, the workgroup size is a multiple of four wavefronts,
+  // so that every SIMD of a CU holds the same number of them (a CU places a
+  // workgroup's wavefronts on its four SIMDs in turn; with 6 or 10 per
+  // workgroup two SIMDs carry more than the others and set the pace).  With
+  // no more items than CUs each item runs alone, on the largest workgroup;
+  // otherwise the size with the most wavefronts per CU, then at least two
+  // workgroups per CU (they fill each other's barriers and serial exchange
+  // passes), then the larger workgroup (fewer items in flight leave fewer
+  // CUs idle at the end).
   auto resident = [&](int threads) {
-    const int by_waves = std::max(1, waves_simd * 4 / std::max(1, threads / 64));
-    return std::max(1, std::min(by_lds, by_waves));
+    int n = 0;
+    if (batch_residency(b->d, feat, threads, b->lds_bytes, &n) != hipSuccess) n = 0;
+    return n;
   };
   int threads = b->cfg.threads;
   if (threads == 0) {
-    int best_wg = -1, best_waves = -1;
-    for (int t : {1024, 512, 256}) {
-      const int wg = resident(t), waves = wg * t / 64;
-      const bool ok = waves >= 16, best_ok = best_waves >= 16;
-      if (best_wg < 0 || (ok && !best_ok) || (ok && best_ok && wg > best_wg) ||
-          (!ok && !best_ok && waves > best_waves)) {
-        best_wg = wg;
+    int best_n = 0, best_waves = 0;
+    for (int t : {1024, 768, 512, 256}) {
+      const int n = resident(t), waves = n * t / 64;
+      if (n < 1) continue;
+      bool better;
+      if (best_n == 0) {
+        better = true;
+      } else if (b->nitems <= b->ncu) {
+        better = false;  // sizes are tried largest first
+      } else {
+        better = waves > best_waves || (waves == best_waves && n >= 2 && best_n < 2);
+      }
+      if (better) {
+        best_n = n;
         best_waves = waves;
         threads = t;
       }
     }
+    if (threads == 0) threads = 256;
   }
+  const int per_cu = resident(threads);
+  if (per_cu < 1)
+    return pt_fail(PT_EINVAL, "pt_batch_run: no workgroup of " + std::to_string(threads) +
+                                  " threads fits a CU with this launch's LDS and registers");
   b->threads = threads;
-  b->blocks = std::max(1, std::min(b->ncu * resident(threads), b->nitems));
+  b->per_cu = per_cu;
+  b->blocks = std::max(1, std::min(b->ncu * per_cu, b->nitems));
   b->built = false;
   drop_graph(b);
   return PT_OK;
@@ -500,12 +517,21 @@ PT_API int pt_batch_get_config(pt_batch* b, int32_t* cfg3) {
   return PT_OK;
 }
 
+PT_API int pt_batch_launch_shape(pt_batch* b, int32_t* out3) {
+  if (!b || !out3) return pt_fail(PT_EINVAL, "null argument");
+  out3[0] = b->blocks;
+  out3[1] = b->threads;
+  out3[2] = b->per_cu;
+  return PT_OK;
+}
+
 PT_API int pt_batch_set_config(pt_batch* b, int32_t threads, int32_t sets, int32_t order) {
   if (!b) return pt_fail(PT_EINVAL, "null batch");
-  if ((threads != 0 && threads != 256 && threads != 512 && threads != 1024) ||
-      (sets != 1 && sets != 2) || (order != 0 && order != 1))
+  if (threads < 0 || threads > 1024 || threads % 64 != 0 || (sets != 1 && sets != 2) ||
+      (order != 0 && order != 1))
     return pt_fail(PT_EINVAL,
-                   "pt_batch_set_config: threads in {0 (auto),256,512,1024}, sets in {1,2}, order in {0,1}");
+                   "pt_batch_set_config: threads 0 (auto) or a multiple of 64 up to 1024, sets in "
+                   "{1,2}, order in {0,1}");
   b->cfg = BatchConfig{threads, sets, order};
   return PT_OK;
 }
@@ -531,7 +557,7 @@ PT_API int pt_batch_tune(pt_batch* b, int32_t trial_mcs, uint32_t flags, const c
   BatchConfig best = b->cfg;
   double best_ms = 1e300;
   int rc = PT_OK;
-  for (int threads : {1024, 512, 256})
+  for (int threads : {1024, 768, 512, 256})
     for (int sets : {2, 1})
       for (int order : {0, 1}) {
         b->cfg = BatchConfig{threads, sets, order};

@@ -23,8 +23,9 @@ namespace ptsg {
 // sequential in k, but every decision depends only on which configuration is
 // carried up from below: with the pre-pass map m0, the configuration at
 // position k before step k is m0[j] for some j <= k, and b = m0[k+1].  All
-// candidate decisions acc[c][k][j] are evaluated in parallel, then one lane
-// per set walks the chain.
+// candidate decisions (c, k, j) are evaluated in parallel and kept as bits
+// (one wavefront ballot per 64 of them), then one lane per set walks the
+// chain.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* lds, int s,
                                                   uint32_t u, int c_lo, int nsets) {
@@ -35,7 +36,8 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
   int32_t* tosl = reinterpret_cast<int32_t*>(lds + A.lay.tos);
   int32_t* sot0 = reinterpret_cast<int32_t*>(lds + A.lay.sot0);
   uint32_t* rpt = lds + A.lay.rpt;
-  uint8_t* acc = reinterpret_cast<uint8_t*>(lds + A.lay.acc);
+  uint32_t* acc = lds + A.lay.acc;  // bit j of row (c, k): rows of NB bits, c-major
+  const int NB = (NT + 31) & ~31;
   for (int i = tid; i < 2 * NT; i += T) sot0[i] = sotl[i];
   for (int i = tid; i < nsets * (NT - 1); i += T) {
     const int c = c_lo + i / (NT - 1), k = i - (c - c_lo) * (NT - 1);
@@ -43,19 +45,29 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
         philox10(Ctr4{(uint32_t)k, u, (uint32_t)c, (kTagPT << 28) | (uint32_t)s}, g.key0, g.key1).x;
   }
   __syncthreads();
-  const int per_set = (NT - 1) * NT;
-  for (int i = tid; i < nsets * per_set; i += T) {
-    const int cl = i / per_set, rem = i - cl * per_set, k = rem / NT, j = rem - k * NT;
-    const int c = c_lo + cl;
-    if (j > k) continue;
-    const int a = sot0[c * NT + j], b = sot0[c * NT + k + 1];
-    const int32_t D = El[c * NT + b] - El[c * NT + a];
-    bool ok = D <= 0;
-    if (!ok) {
-      const int m = D >> 1;
-      ok = m < A.M && rpt[c * NT + k] < A.thrpt[(size_t)k * A.M + m];
+  {
+    const int lane = tid & 63, total = nsets * (NT - 1) * NB;  // a multiple of 32
+    uint32_t* accs = acc + (size_t)c_lo * (NT - 1) * (NB >> 5);
+    for (int base = tid - lane; base < total; base += T) {  // uniform per wavefront
+      const int i = base + lane;
+      bool ok = false;
+      if (i < total) {
+        const int row = i / NB, j = i - row * NB;
+        const int cl = row / (NT - 1), k = row - cl * (NT - 1), c = c_lo + cl;
+        if (j <= k) {
+          const int a = sot0[c * NT + j], b = sot0[c * NT + k + 1];
+          const int32_t D = El[c * NT + b] - El[c * NT + a];
+          ok = D <= 0;
+          if (!ok) {
+            const int m = D >> 1;
+            ok = m < A.M && rpt[c * NT + k] < A.thrpt[(size_t)k * A.M + m];
+          }
+        }
+      }
+      const uint64_t bits = __ballot(ok);
+      if (lane == 0) accs[base >> 5] = (uint32_t)bits;
+      if (lane == 32 && base + 32 < total) accs[(base >> 5) + 1] = (uint32_t)(bits >> 32);
     }
-    acc[(c * NT + k) * NT + j] = ok ? 1 : 0;
   }
   __syncthreads();
   if (tid < nsets) {
@@ -63,10 +75,11 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
     const int32_t* m0 = sot0 + c * NT;
     int32_t* so = sotl + c * NT;
     int32_t* to = tosl + c * NT;
+    const uint32_t* arow = acc + (size_t)c * (NT - 1) * (NB >> 5);
     int cur = 0;
     for (int k = 0; k + 1 < NT; ++k) {
       int fin;
-      if (acc[(c * NT + k) * NT + cur]) {
+      if ((arow[k * (NB >> 5) + (cur >> 5)] >> (cur & 31)) & 1u) {
         fin = m0[k + 1];
       } else {
         fin = m0[cur];
@@ -840,7 +853,7 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) 
   lay.mom = take(16 * (size_t)g.NT, 2);
   lay.qneg = take(g.NT, 1);
   lay.rpt = take(2 * g.NT, 1);
-  lay.acc = take((2 * (size_t)g.NT * g.NT + 3) / 4, 1);
+  lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
   lay.PC = 0;
   lay.Qs = (int)off;
   if (hou && nsets == 2) {
@@ -860,7 +873,7 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
     size_t fixed = jl ? Jw : 0;
     fixed += g.nslot + 3 * 2 * (size_t)g.NT + 4 * (size_t)g.NT;
     fixed = (fixed + 1) / 2 * 2 + 16 * (size_t)g.NT;
-    fixed += g.NT + 2 * (size_t)g.NT + (2 * (size_t)g.NT * g.NT + 3) / 4;
+    fixed += g.NT + 2 * (size_t)g.NT + 2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32);
     if (fixed >= budget) continue;
     const size_t rmax = std::min<size_t>((budget - fixed) / W2, (size_t)g.nslot);
     if (rmax < 1 || (jl && rmax < std::min(g.nslot, 8))) continue;
@@ -886,7 +899,7 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
     lay.mom = take(16 * (size_t)g.NT, 2);
     lay.qneg = take(g.NT, 1);
     lay.rpt = take(2 * g.NT, 1);
-    lay.acc = take((2 * (size_t)g.NT * g.NT + 3) / 4, 1);
+    lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
     lay.PC = 0;
     lay.Qs = (int)off;
     lay.words = (int)off;
@@ -954,6 +967,13 @@ hipError_t prepare_batch(int d, int feat, size_t lds_bytes, int* vgprs) {
     *vgprs = at.numRegs;
   }
   return e;
+}
+
+// Workgroups of `threads` threads with lds_bytes of LDS each that can be
+// resident on one CU at once, as the runtime computes it for this kernel.
+hipError_t batch_residency(int d, int feat, int threads, size_t lds_bytes, int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, batch_kernel(d, feat), threads,
+                                                      lds_bytes);
 }
 
 hipError_t launch_batch(int d, int feat, const FusedArgs* jobs, int njobs, const BatchItem* items,

@@ -110,6 +110,9 @@ constexpr int kFeatHou = 1, kFeatMeas = 2, kFeatSplit = 4;
 // prepare_batch sets the kernel's dynamic LDS limit and reports its VGPRs
 // per lane.
 hipError_t prepare_batch(int d, int feat, size_t lds_bytes, int* vgprs);
+// Workgroups of `threads` threads, lds_bytes of dynamic LDS each, that the
+// runtime can keep resident on one CU at once for this kernel.
+hipError_t batch_residency(int d, int feat, int threads, size_t lds_bytes, int* per_cu);
 hipError_t launch_batch(int d, int feat, const FusedArgs* jobs, int njobs, const BatchItem* items,
                         int nitems, uint32_t* queue, int blocks, int threads, size_t lds_bytes,
                         hipStream_t st);

@@ -30,7 +30,7 @@ EXPORTS = [
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_state", "pt_set_state",
     "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
-    "pt_batch_get_config", "pt_batch_set_config", "pt_batch_destroy",
+    "pt_batch_get_config", "pt_batch_set_config", "pt_batch_launch_shape", "pt_batch_destroy",
     "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_stats", "pt_server_stop",
 ]
 
@@ -81,6 +81,7 @@ def lib():
             "pt_batch_create": [P, I32, C.POINTER(P)], "pt_batch_set_stream": [P, P],
             "pt_batch_run": [P, I32, U32], "pt_batch_tune": [P, I32, U32, C.c_char_p],
             "pt_batch_get_config": [P, P], "pt_batch_set_config": [P, I32, I32, I32],
+            "pt_batch_launch_shape": [P, P],
             "pt_batch_destroy": [P],
             "pt_server_start": [C.c_size_t, I32, C.POINTER(P)],
             "pt_server_submit": [P, C.POINTER(PTRequest), C.POINTER(C.c_uint64)],
@@ -383,6 +384,14 @@ def pt_batch_get_config(batch: Batch) -> tuple:
     out = np.zeros(3, np.int32)
     _check(lib().pt_batch_get_config(batch.h, _p(out)))
     return tuple(int(v) for v in out)
+
+
+def pt_batch_launch_shape(batch: Batch) -> dict:
+    """The grid of the batch's last launch: workgroups, threads per workgroup
+    and workgroups resident per CU."""
+    out = np.zeros(3, np.int32)
+    _check(lib().pt_batch_launch_shape(batch.h, _p(out)))
+    return {"blocks": int(out[0]), "threads": int(out[1]), "per_cu": int(out[2])}
 
 
 def pt_batch_set_config(batch: Batch, threads: int, sets: int, order: int) -> None:

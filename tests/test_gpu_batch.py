@@ -92,7 +92,8 @@ def test_batch_houdayer_2d(pt):
         matches_oracle(pt, j, r)
 
 
-@pytest.mark.parametrize("cfg", [(1024, 1, 0), (512, 2, 1), (256, 1, 1), (256, 2, 0), (0, 2, 0)])
+@pytest.mark.parametrize("cfg", [(1024, 1, 0), (512, 2, 1), (256, 1, 1), (256, 2, 0), (0, 2, 0),
+                                 (768, 2, 0), (320, 2, 1), (448, 1, 0), (64, 2, 0)])
 def test_batch_configs_agree(pt, cfg):
     say(f"batch config {cfg}")
     jobs, refs = make_jobs(pt, SHAPES_3D, 3, seed0=70)
@@ -103,6 +104,42 @@ def test_batch_configs_agree(pt, cfg):
         r.mcs(6)
     for j, r in zip(jobs, refs):
         matches_oracle(pt, j, r)
+
+
+def test_launch_shape(pt):
+    """The automatic grid: whole multiples of four wavefronts per workgroup,
+    every workgroup resident at once, the largest size when items <= CUs,
+    and for the 3D L=16 x 32-temperature workload shape at least two
+    workgroups and 16 wavefronts per CU."""
+    import torch
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    say(f"launch shape, {ncu} CUs")
+    jobs, _ = make_jobs(pt, SHAPES_3D, 3, seed0=130)
+    batch = pt.pt_batch_create(jobs)
+    assert pt.pt_batch_launch_shape(batch) == {"blocks": 0, "threads": 0, "per_cu": 0}
+    pt.pt_batch_run(batch, 1)
+    shape = pt.pt_batch_launch_shape(batch)
+    items = sum(j.S for j in jobs)
+    assert items <= ncu and shape["threads"] == 1024 and shape["blocks"] == items
+    for bad in (32, 100, 1088, -64):
+        with pytest.raises(pt.PTError):
+            pt.pt_batch_set_config(batch, bad, 2, 0)
+    pt.pt_batch_set_config(batch, 320, 2, 0)
+    pt.pt_batch_run(batch, 1)
+    assert pt.pt_batch_launch_shape(batch)["threads"] == 320
+    pt.pt_batch_destroy(batch)
+    S = 4 * ncu
+    J = W.couplings_pm_j(S, 16, 3, 5)
+    big = pt.pt_init(S, 32, 16, 3, J, W.geometric_betas(0.9, 2.0, 32), 3)
+    batch = pt.pt_batch_create([big])
+    pt.pt_batch_run(batch, 1, measure=True)
+    shape = pt.pt_batch_launch_shape(batch)
+    say(f"3D L=16 x 32, {S} samples: {shape}")
+    assert shape["threads"] % 256 == 0 and shape["per_cu"] >= 2
+    assert shape["per_cu"] * shape["threads"] // 64 >= 16
+    assert shape["blocks"] == min(S, ncu * shape["per_cu"])
+    pt.pt_batch_destroy(batch)
+    pt.pt_destroy(big)
 
 
 def test_batch_equals_alone(pt):
@@ -128,7 +165,7 @@ def test_tuner_restores_state_and_caches(pt):
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.jsonl")
         cfg = pt.pt_batch_tune(batch, 2, cache_path=path)
-        assert cfg[0] in (256, 512, 1024) and cfg[1] in (1, 2) and cfg[2] in (0, 1)
+        assert cfg[0] in (256, 512, 768, 1024) and cfg[1] in (1, 2) and cfg[2] in (0, 1)
         assert os.path.exists(path) and "threads" in open(path).read()
         for j, s0 in zip(jobs, before):
             assert same_state(state(pt, j), s0)

@@ -47,8 +47,12 @@ def test_resident_plans_are_monotone_in_replicas(lib):
 
 def test_plain_flag_and_known_shapes(lib):
     assert pt.pt_plan_query(3, 16, 32, measure=True, plain=True)["mode"] == -1
-    assert pt.pt_plan_query(3, 16, 32, measure=True) == {"mode": 0, "parts": 1, "per_part": 64,
-                                                           "lds_bytes": 41856}
+    # 3D L=16, 32 temperatures: spins 32768 B, couplings 3072 B, energies, maps,
+    # thresholds, moments, exchange randoms and the exchange decisions as bits;
+    # four such workgroups fit one CU's 160 KiB of LDS
+    p = pt.pt_plan_query(3, 16, 32, measure=True)
+    assert p == {"mode": 0, "parts": 1, "per_part": 64, "lds_bytes": 40056}
+    assert 4 * p["lds_bytes"] <= 160 * 1024
     p = pt.pt_plan_query(3, 48, 48, measure=True)
     assert p["mode"] == 3 and p["parts"] == 12 and p["per_part"] == 8
     assert pt.pt_plan_query(2, 64, 24, houdayer=True, measure=True)["mode"] == 1
