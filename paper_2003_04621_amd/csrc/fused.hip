@@ -19,6 +19,46 @@ namespace ptsg {
 
 
 // ---------------------------------------------------------------------------
+// Wave-level helpers.  Lanes of one wavefront exchange data through LDS; the
+// wavefront issues its LDS instructions in order, so a compiler fence plus a
+// wait for outstanding LDS operations orders one lane's writes before
+// another lane's later reads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_ones(uint32_t x) {  // lanes without a source: ~0
+  return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_zero(uint32_t x) {  // lanes without a source: 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, ROWS == 0xF);
+}
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
+constexpr int kBcast15 = 0x142, kBcast31 = 0x143;  // to rows 1, 3 / rows 2, 3
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
 // Replica exchange for both sets of the resident sample.  The pass is
 // sequential in k, but every decision depends only on which configuration is
 // carried up from below: with the pre-pass map m0, the configuration at
@@ -97,25 +137,31 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
 // ---------------------------------------------------------------------------
 // Moments of one temperature from the energies of its two replicas and the
 // number of sites where they differ: sum E (both replicas), sum E^2, q, |q|,
-// q^2 and q^4 as a 128-bit (lo, hi) pair, with Q = N q = N - 2 neg.
+// q^2 and q^4 as a 128-bit (lo, hi) pair, with Q = N q = N - 2 neg.  Each
+// word is added in place with a 64-bit LDS atomic (one thread per
+// temperature, so the atomics only keep the compiler from holding all eight
+// words in registers at once); the carry out of the low q^4 word comes from
+// the value it replaced.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void add_moments(const Geo& g, int64_t* m, int32_t ea, int32_t eb, int neg) {
   const int64_t Q = (int64_t)g.N - 2 * (int64_t)neg;
   const int64_t Ea = ea, Eb = eb;
-  m[0] += Ea + Eb;
-  m[1] += Ea * Ea + Eb * Eb;
-  m[2] += Q;
-  m[3] += Q < 0 ? -Q : Q;
+  unsigned long long* u = reinterpret_cast<unsigned long long*>(m);
+  atomicAdd(u + 0, (unsigned long long)(Ea + Eb));
+  atomicAdd(u + 1, (unsigned long long)(Ea * Ea + Eb * Eb));
+  atomicAdd(u + 2, (unsigned long long)Q);
+  atomicAdd(u + 3, (unsigned long long)(Q < 0 ? -Q : Q));
   const uint64_t q2 = (uint64_t)(Q * Q);
-  m[4] += (int64_t)q2;
+  atomicAdd(u + 4, (unsigned long long)q2);
   const uint64_t q4lo = q2 * q2, q4hi = __umul64hi(q2, q2);
-  const uint64_t lo = (uint64_t)m[5] + q4lo;
-  m[5] = (int64_t)lo;
-  m[6] = (int64_t)((uint64_t)m[6] + q4hi + (lo < q4lo ? 1u : 0u));
+  const uint64_t old = atomicAdd(u + 5, (unsigned long long)q4lo);
+  atomicAdd(u + 6, (unsigned long long)(q4hi + (old + q4lo < old ? 1u : 0u)));
 }
 
 // ---------------------------------------------------------------------------
-// Measurement of every temperature of the resident sample.
+// Measurement of every temperature of the resident sample: one wavefront per
+// temperature counts the sites where its two replicas differ and adds the
+// moments.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* lds) {
   const Geo& g = A.g;
@@ -123,51 +169,20 @@ __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* l
   const uint32_t* W = lds + A.lay.W;
   const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
   const int32_t* sotl = reinterpret_cast<const int32_t*>(lds + A.lay.sot);
-  int32_t* qneg = reinterpret_cast<int32_t*>(lds + A.lay.qneg);
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
-  if (tid < NT) qneg[tid] = 0;
-  __syncthreads();
   const int wave = tid >> 6, lane = tid & 63, nwave = T >> 6;
   for (int k = wave; k < NT; k += nwave) {
-    const uint32_t* Wa = W + (size_t)sotl[k] * 2 * NW;
-    const uint32_t* Wb = W + (size_t)(NT + sotl[NT + k]) * 2 * NW;
+    const int a = sotl[k], b = NT + sotl[NT + k];
+    const uint32_t* Wa = W + (size_t)a * 2 * NW;
+    const uint32_t* Wb = W + (size_t)b * 2 * NW;
     int neg = 0;
     for (int w = lane; w < 2 * NW; w += 64) neg += __popc(Wa[w] ^ Wb[w]);
-    if (neg) atomicAdd(&qneg[k], neg);
+    neg = wave_sum(neg);
+    if (lane == 0) add_moments(g, mom + (size_t)k * 8, El[a], El[b], neg);
   }
   __syncthreads();
-  for (int k = tid; k < NT; k += T)
-    add_moments(g, mom + (size_t)k * 8, El[sotl[k]], El[NT + sotl[NT + k]], qneg[k]);
-  __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// Wave-level helpers.  Lanes of one wavefront exchange data through LDS; the
-// wavefront issues its LDS instructions in order, so a compiler fence plus a
-// wait for outstanding LDS operations orders one lane's writes before
-// another lane's later reads.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
 
 // Upward fill along the chain F_0, G_0, F_1, G_1, ... of every row field,
 // where F_b -> G_b and G_b -> F_(b+1) (no link across a field boundary; nLB
@@ -273,18 +288,6 @@ __device__ __forceinline__ bool grow_pair(const Geo& g, uint32_t* C, const uint3
 // AND-of-q half of every step depends on q alone and is computed once per
 // pair; each fill then costs one DPP move and one AND-OR per step.
 // ---------------------------------------------------------------------------
-template <int CTRL, int ROWS = 0xF>
-__device__ __forceinline__ uint32_t dpp_ones(uint32_t x) {  // lanes without a source: ~0
-  return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, CTRL, ROWS, 0xF, false);
-}
-template <int CTRL, int ROWS = 0xF>
-__device__ __forceinline__ uint32_t dpp_zero(uint32_t x) {  // lanes without a source: 0
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, ROWS == 0xF);
-}
-constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
-constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
-constexpr int kBcast15 = 0x142, kBcast31 = 0x143;  // to rows 1, 3 / rows 2, 3
-
 struct ColumnChain {
   uint32_t q;
   uint32_t p1, p2, p3, p4, p5, p6;  // upward: AND of q over the lanes each step has joined
@@ -504,6 +507,53 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// One Metropolis sweep (colour 0, then colour 1) of the resident
+// configurations ls in [0, nres): configuration ls is slot slot0 + ls, its
+// words at W + ls * 2 NW, its couplings J (colour-c direction words at
+// J + c * 2 D NW).  A configuration's colour-1 update reads only its own
+// colour-0 words, so when each configuration's words fall to one wavefront
+// (NW a multiple or a divisor of 64: the 64-item units of a configuration,
+// or the whole configurations of a unit, all go to the same wavefront) every
+// wavefront runs both half-sweeps of its configurations back to back,
+// ordered by a wavefront-level LDS fence; otherwise the workgroup meets
+// between the colours.  Ends with a workgroup barrier.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_t* J, uint32_t* W,
+                                               int32_t* El, const int32_t* tosl,
+                                               const uint32_t* thrl, int slot0, int nres, int s,
+                                               uint32_t t) {
+  const Geo& g = A.g;
+  const int NW = g.NW, W2 = 2 * NW, items = nres * NW, tid = threadIdx.x, T = blockDim.x;
+  auto update = [&](int it, int c) {
+    const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+    const int slot = slot0 + ls;
+    const int k = tosl[slot];
+    int dE = 0;
+    sweep_word<D>(g, W + ls * W2, J + c * 2 * D * NW, c, w, slot, s, t, thrl[k * 4 + 0],
+                  thrl[k * 4 + 1], thrl[k * 4 + 2], dE);
+    if (dE) atomicAdd(&El[slot], dE);
+  };
+  if (NW % 64 == 0 || 64 % NW == 0) {
+    const int m = NW >= 64 ? NW >> 6 : 1;  // units per configuration (or 1)
+    const int nunits = (items + 63) >> 6, lane = tid & 63, step = (T >> 6) * m;
+    for (int c = 0; c < 2; ++c) {
+      for (int u0 = (tid >> 6) * m; u0 < nunits; u0 += step)
+        for (int u = u0; u < u0 + m; ++u) {
+          const int it = (u << 6) + lane;
+          if (it < items) update(it, c);
+        }
+      if (c == 0) wave_lds_sync();
+    }
+  } else {
+    for (int it = tid; it < items; it += T) update(it, 0);
+    __syncthreads();
+    for (int it = tid; it < items; it += T) update(it, 1);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // nmcs Monte Carlo steps of sample s with replica sets [c_lo, c_lo + nsets)
 // resident in LDS.  With one set only the sweep and the exchange run (the
 // Houdayer move and the overlap need both sets).  Only the resident sets'
@@ -553,19 +603,7 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
 
   for (int step = 0; step < A.nmcs; ++step) {
     const uint32_t t = t0 + (uint32_t)step;
-    for (int c = 0; c < 2; ++c) {
-      const uint32_t* Jc = Jl + c * 2 * D * NW;
-      for (int it = tid; it < items; it += T) {
-        const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
-        const int slot = slot0 + ls;
-        const int k = tosl[slot];
-        int dE = 0;
-        sweep_word<D>(g, W + ls * W2, Jc, c, w, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
-                      thrl[k * 4 + 2], dE);
-        if (dE) atomicAdd(&El[slot], dE);
-      }
-      __syncthreads();
-    }
+    sweep_resident<D>(A, Jl, W, El, tosl, thrl, slot0, nres, s, t);
     if (hou) houdayer_resident<D>(A, lds, s, v0 + (uint32_t)step);
     exchange_resident(A, lds, s, u0 + (uint32_t)step, c_lo, nsets);
     if (meas) measure_resident(A, lds);
@@ -723,19 +761,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
 
   for (int step = 0; step < A.nmcs; ++step) {
     const uint32_t t = t0 + (uint32_t)step;
-    for (int c = 0; c < 2; ++c) {
-      const uint32_t* Jc = Jsrc + c * 2 * D * NW;
-      for (int it = tid; it < items; it += T) {
-        const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
-        const int slot = slot0 + ls;
-        const int k = tosl[slot];
-        int dE = 0;
-        sweep_word<D>(g, W + ls * W2, Jc, c, w, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
-                      thrl[k * 4 + 2], dE);
-        if (dE) atomicAdd(&El[slot], dE);
-      }
-      __syncthreads();
-    }
+    sweep_resident<D>(A, Jsrc, W, El, tosl, thrl, slot0, nres, s, t);
     // publish, meet, and take the sample-wide steps
     const int par = step & 1;
     for (int i = tid; i < nres; i += T) Ex[par * nslot + slot0 + i] = El[slot0 + i];
@@ -786,7 +812,10 @@ __global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jo
                                                 uint32_t* queue) {
   constexpr bool kHou = (F & kFeatHou) != 0, kMeas = (F & kFeatMeas) != 0;
   constexpr bool kSplit = (F & kFeatSplit) != 0;
-  extern __shared__ uint32_t lds[];
+  // 16-byte aligned: the moment words are updated with 64-bit LDS atomics,
+  // which need naturally aligned addresses (the plan offsets are 8-byte
+  // aligned relative to this base)
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int cur, flag;
   for (;;) {
     if (threadIdx.x == 0) cur = (int)atomicAdd(queue, 1u);
