@@ -354,6 +354,25 @@ __device__ __forceinline__ uint32_t column_fill(const ColumnChain& h, uint32_t c
   return u | d;
 }
 
+// The q site of rank m (counted in increasing x0) of a 64-site row held as
+// its even-site word E and odd-site word O (site x0 = 2b + e is bit b of E
+// for e = 0, of O for e = 1): sets that bit in SE or SO.  f(b), the number of
+// q sites with x0 < 2b, is nondecreasing; a binary search finds the largest
+// b with f(b) <= m, whose pair of sites holds the one sought.
+__device__ __forceinline__ void rank_in_row64(uint32_t E, uint32_t O, uint32_t m, uint32_t& SE,
+                                              uint32_t& SO) {
+  int b = 0;
+#pragma unroll
+  for (int st = 16; st >= 1; st >>= 1) {
+    const uint32_t lm = (1u << (b + st)) - 1u;
+    if ((uint32_t)(__popc(E & lm) + __popc(O & lm)) <= m) b += st;
+  }
+  const uint32_t lm = (1u << b) - 1u;
+  const bool even = ((E >> b) & 1u) && (uint32_t)(__popc(E & lm) + __popc(O & lm)) == m;
+  SE = even ? 1u << b : 0u;
+  SO = even ? 0u : 1u << b;
+}
+
 // Houdayer moves of a 2D sample with 64 rows (L = 64), one wavefront per
 // pair at a time and one row per lane, everything in registers: overlap,
 // seed (a scan over lanes in site order), flood fill alternating column
@@ -370,22 +389,24 @@ __device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const
     uint32_t* Wa = W + (size_t)a * 128;
     uint32_t* Wb = W + (size_t)b * 128;
     const uint32_t q0 = Wa[lane] ^ Wb[lane], q1 = Wa[64 + lane] ^ Wb[64 + lane];
+    const uint32_t qx = odd ? q1 : q0, qy = odd ? q0 : q1;
+    // q = -1 sites up to and including this row (a DPP scan over the rows)
     const uint32_t lc = __popc(q0) + __popc(q1);
-    const uint32_t n = (uint32_t)wave_sum((int)lc);
+    uint32_t incl = lc;
+    incl += dpp_zero<kRowShr1>(incl);
+    incl += dpp_zero<kRowShr2>(incl);
+    incl += dpp_zero<kRowShr4>(incl);
+    incl += dpp_zero<kRowShr8>(incl);
+    incl += dpp_zero<kBcast15, 0xA>(incl);
+    incl += dpp_zero<kBcast31, 0xC>(incl);
+    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     if (n == 0) continue;
     // seed: the m-th q = -1 site in increasing site order (row by row)
     const Ctr4 r = philox10(Ctr4{(uint32_t)k, v, 0u, (kTagHou << 28) | (uint32_t)s}, g.key0, g.key1);
     const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
     const uint32_t m = (uint32_t)__umul64hi(r64, (uint64_t)n);
-    const uint32_t incl = wave_inclusive_scan(lc, lane);
     uint32_t X = 0, Y = 0;  // cluster: even-site and odd-site words of the row
-    if (m >= incl - lc && m < incl) {
-      int c, bb;
-      select_in_row(g, lane, q0, q1, 0, m - (incl - lc), c, bb);
-      if (c == (int)odd) X = 1u << bb;
-      if (c == 1 - (int)odd) Y = 1u << bb;
-    }
-    const uint32_t qx = odd ? q1 : q0, qy = odd ? q0 : q1;
+    if (m >= incl - lc && m < incl) rank_in_row64(qx, qy, m - (incl - lc), X, Y);
     const uint32_t rqx = __builtin_bitreverse32(qx), rqy = __builtin_bitreverse32(qy);
     row_closure(g, X, Y, qx, qy, rqx, rqy);
     const ColumnChain hx = column_chain(qx, lane), hy = column_chain(qy, lane);
