@@ -18,6 +18,12 @@
 namespace ptsg {
 
 
+// 2D samples of 64 rows with one row per word get the in-register Houdayer
+// move (one row per lane).
+__host__ __device__ inline bool rows64_houdayer(const Geo& g) {
+  return g.d == 2 && g.NW == 64 && g.P == 1;
+}
+
 // ---------------------------------------------------------------------------
 // Wave-level helpers.  Lanes of one wavefront exchange data through LDS; the
 // wavefront issues its LDS instructions in order, so a compiler fence plus a
@@ -42,6 +48,7 @@ __device__ __forceinline__ uint32_t dpp_zero(uint32_t x) {  // lanes without a s
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
 constexpr int kBcast15 = 0x142, kBcast31 = 0x143;  // to rows 1, 3 / rows 2, 3
+constexpr int kWaveRol1 = 0x134, kWaveRor1 = 0x13C;  // lane i takes lane i + 1 / i - 1 (mod 64)
 
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
@@ -381,10 +388,19 @@ __device__ __forceinline__ void rank_in_row64(uint32_t E, uint32_t O, uint32_t m
 // lanes), exchange on the cluster.
 __device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const uint32_t* Jl,
                                                 int32_t* El, const int32_t* sotl, int s, uint32_t v,
-                                                int wave, int nwave, int lane) {
+                                                uint32_t* hctr, int lane) {
   const int NT = g.NT;
   const bool odd = lane & 1;  // parity of the row = colour of its even sites
-  for (int k = wave; k < NT; k += nwave) {
+  for (;;) {
+    // pairs from the hottest down (clusters grow larger and take more
+    // passes at high temperature), each to the next free wavefront.  Every
+    // lane adds 1 (one 64-count LDS atomic per take) and all read lane 0's
+    // result: a take under a lane-0 branch would let the compiler run the
+    // other lanes on into the next pair without it.  The counter is cleared
+    // after each Houdayer phase.
+    const uint32_t i = (uint32_t)__builtin_amdgcn_readfirstlane((int)atomicAdd(hctr, 1u)) >> 6;
+    if (i >= (uint32_t)NT) break;
+    const int k = NT - 1 - (int)i;
     const int a = sotl[k], b = NT + sotl[NT + k];
     uint32_t* Wa = W + (size_t)a * 128;
     uint32_t* Wb = W + (size_t)b * 128;
@@ -427,10 +443,10 @@ __device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const
     uint32_t nc[4], na[4];
     x0_neighbours(g, c1, odd, nc[0], nc[1]);
     x0_neighbours(g, a1, odd, na[0], na[1]);
-    nc[2] = __shfl(c1, (lane + 1) & 63, 64);
-    nc[3] = __shfl(c1, (lane + 63) & 63, 64);
-    na[2] = __shfl(a1, (lane + 1) & 63, 64);
-    na[3] = __shfl(a1, (lane + 63) & 63, 64);
+    nc[2] = dpp_ones<kWaveRol1>(c1);  // row + 1 (lane 63 takes lane 0)
+    nc[3] = dpp_ones<kWaveRor1>(c1);  // row - 1
+    na[2] = dpp_ones<kWaveRol1>(a1);
+    na[3] = dpp_ones<kWaveRor1>(a1);
     int cross = 0, cross_u = 0;
 #pragma unroll
     for (int dir = 0; dir < 4; ++dir) {
@@ -439,7 +455,14 @@ __device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const
       cross += __popc(X);
       cross_u += __popc(X & U);
     }
-    const int delta = wave_sum(2 * (cross - 2 * cross_u));
+    uint32_t dsum = (uint32_t)(2 * (cross - 2 * cross_u));
+    dsum += dpp_zero<kRowShr1>(dsum);
+    dsum += dpp_zero<kRowShr2>(dsum);
+    dsum += dpp_zero<kRowShr4>(dsum);
+    dsum += dpp_zero<kRowShr8>(dsum);
+    dsum += dpp_zero<kBcast15, 0xA>(dsum);
+    dsum += dpp_zero<kBcast31, 0xC>(dsum);
+    const int delta = __builtin_amdgcn_readlane((int)dsum, 63);
     Wa[lane] = a0 ^ c0;
     Wa[64 + lane] = a1 ^ c1;
     Wb[lane] = b0 ^ c0;
@@ -470,9 +493,10 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
   uint32_t* Qw = lds + A.lay.Qs + (size_t)wave * 2 * W2;
   uint32_t* Cw = Qw + W2;
   const int rpl = (g.NR + 63) / 64;  // rows per lane for the seed search
-  if (D == 2 && NW == 64 && g.P == 1) {
-    houdayer_rows64(g, W, Jl, El, sotl, s, v, wave, nwave, lane);
+  if (D == 2 && rows64_houdayer(g)) {
+    houdayer_rows64(g, W, Jl, El, sotl, s, v, lds + A.lay.hq, lane);
     __syncthreads();
+    if (tid == 0) lds[A.lay.hq] = 0u;  // the next use is behind the step's barriers
     return;
   }
   for (int k = wave; k < NT; k += nwave) {
@@ -619,6 +643,7 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
   for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
   if (meas)
     for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
+  if (hou && tid == 0) lds[A.lay.hq] = 0u;
   const uint32_t t0 = A.ctr->t, u0 = A.ctr->u, v0 = A.ctr->v;
   __syncthreads();
 
@@ -906,10 +931,14 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) 
   lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
   lay.PC = 0;
   lay.Qs = (int)off;
+  lay.hq = (int)off;
   if (hou && nsets == 2) {
-    // overlap and cluster words for each wavefront
-    lay.PC = waves;
-    lay.Qs = take((size_t)waves * 2 * W2, 1);
+    lay.hq = take(1, 1);  // Houdayer pair counter
+    if (!rows64_houdayer(g)) {
+      // overlap and cluster words for each wavefront
+      lay.PC = waves;
+      lay.Qs = take((size_t)waves * 2 * W2, 1);
+    }
   }
   lay.words = (int)off;
   return off <= budget;
@@ -952,6 +981,7 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
     lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
     lay.PC = 0;
     lay.Qs = (int)off;
+    lay.hq = (int)off;
     lay.words = (int)off;
     return off <= budget;
   }

@@ -47,7 +47,7 @@ hipError_t launch_advance(DevCounters* ctr, CounterStep step, hipStream_t st);
 // threshold rows, moments, overlap counts, exchange randoms and decision
 // matrix, and the Houdayer words Qs of PC wavefronts; `words` in all.
 struct FusedLayout {
-  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, Qs, PC, words;
+  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, Qs, PC, hq, words;
 };
 
 // Everything one fused workgroup needs about a job, for nmcs steps.
