@@ -167,6 +167,63 @@ struct CounterStep {
   uint32_t dt, du, dv, dm;
 };
 
+// The geometry fields of Geo, a function of L and d alone.  Fields per word:
+// the most row fields of H = L/2 bits that fit 32 bits with a block length
+// L/P that keeps every field of a word at the same checkerboard offset.
+__host__ __device__ constexpr int fields_per_word(int L) {
+  for (int p = 32 / (L / 2); p >= 1; --p)
+    if (L % p == 0 && (L / p) % 2 == 0) return p;
+  return 1;
+}
+
+__host__ __device__ constexpr Geo geo_shape(int L, int d) {
+  Geo g{};
+  g.L = L;
+  g.d = d;
+  g.N = d == 3 ? L * L * L : L * L;
+  g.NR = g.N / L;
+  g.H = L / 2;
+  g.G = (L + 7) / 8;
+  g.magicL = (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L);
+  g.maskH = (g.H == 32) ? 0xFFFFFFFFu : ((1u << g.H) - 1u);
+  g.P = fields_per_word(L);
+  g.B = L / g.P;
+  g.NW = g.NR / g.P;
+  g.maskW = (g.P * g.H == 32) ? 0xFFFFFFFFu : ((1u << (g.P * g.H)) - 1u);
+  g.LB = 0;
+  for (int f = 0; f < g.P; ++f) g.LB |= 1u << (f * g.H);
+  g.HB = g.LB << (g.H - 1);
+  return g;
+}
+
+// g with its geometry fields replaced by compile-time constants for the
+// shape (L, D) (LS = L; LS = 0 leaves g as it is), so that the compiler folds
+// them; the caller has checked that g has this shape.
+template <int D, int LS>
+__device__ __forceinline__ Geo fixed_shape(const Geo& g) {
+  if constexpr (LS == 0) {
+    return g;
+  } else {
+    constexpr Geo k = geo_shape(LS, D);
+    Geo c = g;
+    c.L = k.L;
+    c.d = k.d;
+    c.N = k.N;
+    c.NR = k.NR;
+    c.H = k.H;
+    c.G = k.G;
+    c.P = k.P;
+    c.B = k.B;
+    c.NW = k.NW;
+    c.magicL = k.magicL;
+    c.maskH = k.maskH;
+    c.maskW = k.maskW;
+    c.LB = k.LB;
+    c.HB = k.HB;
+    return c;
+  }
+}
+
 __device__ __forceinline__ uint32_t divL(const Geo& g, uint32_t x) {
   return __umulhi(x, g.magicL);
 }

@@ -563,15 +563,14 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
 // ordered by a wavefront-level LDS fence; otherwise the workgroup meets
 // between the colours.  Ends with a workgroup barrier.
 // ---------------------------------------------------------------------------
-template <int D>
-__device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_t* J, uint32_t* W,
-                                               int32_t* El, const int32_t* tosl,
-                                               const uint32_t* thrl, int slot0, int nres, int s,
-                                               uint32_t t) {
-  const Geo& g = A.g;
+template <int D, int LS>
+__device__ __forceinline__ void sweep_resident_shape(const Geo& g, const FusedArgs& A,
+                                                     const uint32_t* J, uint32_t* W, int32_t* El,
+                                                     const int32_t* tosl, const uint32_t* thrl,
+                                                     int slot0, int nres, int s, uint32_t t) {
   const int NW = g.NW, W2 = 2 * NW, items = nres * NW, tid = threadIdx.x, T = blockDim.x;
   auto update = [&](int it, int c) {
-    const int ls = (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
+    const int ls = LS ? it / NW : (int)__umulhi((uint32_t)it, A.magicNW), w = it - ls * NW;
     const int slot = slot0 + ls;
     const int k = tosl[slot];
     int dE = 0;
@@ -596,6 +595,21 @@ __device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_
     for (int it = tid; it < items; it += T) update(it, 1);
   }
   __syncthreads();
+}
+
+// The sweep with the geometry of the shape the workloads run most (3D L = 16,
+// 2D L = 64) folded to compile-time constants, else from g.
+template <int D>
+__device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_t* J, uint32_t* W,
+                                               int32_t* El, const int32_t* tosl,
+                                               const uint32_t* thrl, int slot0, int nres, int s,
+                                               uint32_t t) {
+  constexpr int kFixedL = D == 3 ? 16 : 64;
+  if (A.g.L == kFixedL)
+    sweep_resident_shape<D, kFixedL>(fixed_shape<D, kFixedL>(A.g), A, J, W, El, tosl, thrl, slot0,
+                                     nres, s, t);
+  else
+    sweep_resident_shape<D, 0>(A.g, A, J, W, El, tosl, thrl, slot0, nres, s, t);
 }
 
 // ---------------------------------------------------------------------------

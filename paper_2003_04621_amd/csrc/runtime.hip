@@ -32,15 +32,6 @@ void* (*g_alloc)(size_t, void*) = nullptr;
 void (*g_free)(void*, void*) = nullptr;
 void* g_ctx = nullptr;
 
-// Row fields per 32-bit word: as many rows of L/2 bits as fit, with an even
-// block length L/P so that all fields of a word share their checkerboard
-// offset.
-int fields_per_word(int L) {
-  for (int p = 32 / (L / 2); p >= 1; --p)
-    if (L % p == 0 && (L / p) % 2 == 0) return p;
-  return 1;
-}
-
 // Acceptance probability p -> 32-bit threshold floor(2^32 p), clamped to
 // [0, 2^32 - 1]; a uniform 32-bit word r accepts iff r < threshold.
 uint32_t threshold_u32(double p) {
@@ -53,22 +44,7 @@ uint32_t threshold_u32(double p) {
 
 // Lattice and word geometry of a job (Sec. 2.2 layout).
 Geo make_geo(int S, int NT, int L, int dim, int layout, uint64_t seed) {
-  Geo g{};
-  g.L = L;
-  g.d = dim;
-  g.N = dim == 3 ? L * L * L : L * L;
-  g.NR = g.N / L;
-  g.H = L / 2;
-  g.G = (L + 7) / 8;
-  g.magicL = (uint32_t)((0x100000000ull + (uint64_t)L - 1) / (uint64_t)L);
-  g.maskH = (g.H == 32) ? 0xFFFFFFFFu : ((1u << g.H) - 1u);
-  g.P = fields_per_word(L);
-  g.B = L / g.P;
-  g.NW = g.NR / g.P;
-  g.maskW = (g.P * g.H == 32) ? 0xFFFFFFFFu : ((1u << (g.P * g.H)) - 1u);
-  g.LB = 0;
-  for (int f = 0; f < g.P; ++f) g.LB |= 1u << (f * g.H);
-  g.HB = g.LB << (g.H - 1);
+  Geo g = geo_shape(L, dim);
   g.S = S;
   g.NT = NT;
   g.nslot = 2 * NT;
