@@ -494,7 +494,7 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
   uint32_t* Cw = Qw + W2;
   const int rpl = (g.NR + 63) / 64;  // rows per lane for the seed search
   if (D == 2 && rows64_houdayer(g)) {
-    houdayer_rows64(g, W, Jl, El, sotl, s, v, lds + A.lay.hq, lane);
+    houdayer_rows64(fixed_shape<2, 64>(g), W, Jl, El, sotl, s, v, lds + A.lay.hq, lane);
     __syncthreads();
     if (tid == 0) lds[A.lay.hq] = 0u;  // the next use is behind the step's barriers
     return;
@@ -560,8 +560,9 @@ __device__ __forceinline__ void houdayer_resident(const FusedArgs& A, uint32_t* 
 // (NW a multiple or a divisor of 64: the 64-item units of a configuration,
 // or the whole configurations of a unit, all go to the same wavefront) every
 // wavefront runs both half-sweeps of its configurations back to back,
-// ordered by a wavefront-level LDS fence; otherwise the workgroup meets
-// between the colours.  Ends with a workgroup barrier.
+// ordered by a wavefront-level LDS fence, as long as that spreads the words
+// over the wavefronts as evenly as the flat loop; otherwise the workgroup
+// meets between the colours.  Ends with a workgroup barrier.
 // ---------------------------------------------------------------------------
 template <int D, int LS>
 __device__ __forceinline__ void sweep_resident_shape(const Geo& g, const FusedArgs& A,
@@ -578,7 +579,14 @@ __device__ __forceinline__ void sweep_resident_shape(const Geo& g, const FusedAr
                   thrl[k * 4 + 1], thrl[k * 4 + 2], dE);
     if (dE) atomicAdd(&El[slot], dE);
   };
-  if (NW % 64 == 0 || 64 % NW == 0) {
+  // whole configurations per wavefront only where that loads the wavefronts
+  // as evenly as the flat loop (a split part can hold fewer configurations
+  // than there are wavefronts)
+  const int nwave = T >> 6;
+  const bool owned =
+      64 % NW == 0 ||
+      (NW % 64 == 0 && (nres + nwave - 1) / nwave * nwave * NW <= (items + T - 1) / T * T);
+  if (owned) {
     const int m = NW >= 64 ? NW >> 6 : 1;  // units per configuration (or 1)
     const int nunits = (items + 63) >> 6, lane = tid & 63, step = (T >> 6) * m;
     for (int c = 0; c < 2; ++c) {
