@@ -9,6 +9,8 @@
 #include <cstdint>
 #include <cstdio>
 
+#include "device.h"
+
 namespace {
 
 constexpr int kChains = 16;
@@ -77,6 +79,40 @@ double rate(uint32_t* d, int blocks, int iters) {
   return (double)blocks * 256 * iters * kChains * (OP == 6 ? 2 : 1) / (ms * 1e-3);
 }
 
+// The sweep's inner loop without the rest of the word update: one
+// Philox4x32-10 call per iteration (counter as the sweep forms it) and the 3D
+// acceptance planes of its four words.  Its rate bounds the fused kernel from
+// above for this instruction sequence.
+__global__ void __launch_bounds__(256) philox_sites(uint32_t* out, uint32_t k0, uint32_t k1,
+                                                    int iters) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t C1 = 0, C2 = 0;
+  for (int i = iters - 1; i >= 0; --i) {
+    const ptsg::Ctr4 r =
+        ptsg::philox10(ptsg::Ctr4{(uint32_t)i, gid, 7u, 3u << 28}, k0, k1);
+    ptsg::shift_in_k_pair(C1, C2, r.w, r.z, 0x80000000u, 0x40000000u, 0x20000000u);
+    ptsg::shift_in_k_pair(C1, C2, r.y, r.x, 0x80000000u, 0x40000000u, 0x20000000u);
+  }
+  out[gid] = C1 ^ (3u * C2);
+}
+
+double philox_rate(uint32_t* d, int ncu, int waves_per_cu, int iters) {
+  const int blocks = ncu * waves_per_cu / 4;
+  hipEvent_t e0, e1;
+  CHECK(hipEventCreate(&e0));
+  CHECK(hipEventCreate(&e1));
+  hipLaunchKernelGGL(philox_sites, dim3(blocks), dim3(256), 0, 0, d, 1u, 2u, 16);
+  CHECK(hipEventRecord(e0));
+  hipLaunchKernelGGL(philox_sites, dim3(blocks), dim3(256), 0, 0, d, 1u, 2u, iters);
+  CHECK(hipEventRecord(e1));
+  CHECK(hipEventSynchronize(e1));
+  float ms = 0;
+  CHECK(hipEventElapsedTime(&ms, e0, e1));
+  CHECK(hipEventDestroy(e0));
+  CHECK(hipEventDestroy(e1));
+  return (double)blocks * 256 * iters * 4 / (ms * 1e6);  // sites per ns
+}
+
 }  // namespace
 
 int main() {
@@ -98,6 +134,11 @@ int main() {
   std::printf("clock attribute: %d kHz\n", clk);
   for (int i = 0; i < 7; ++i)
     std::printf("%-16s %7.2f T lane-ops/s  %.3f of v_add_u32\n", names[i], r[i] / 1e12, r[i] / r[0]);
+  int ncu = 0;
+  CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0));
+  for (int w : {8, 16, 24, 32})  // at most 32 wavefronts per CU: within the buffer
+    std::printf("Philox4x32-10 + 3D compares, %2d wavefronts/CU: %6.0f sites/ns\n", w,
+                philox_rate(d, ncu, w, 4096));
   CHECK(hipFree(d));
   return 0;
 }
