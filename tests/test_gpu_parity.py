@@ -214,6 +214,26 @@ def test_full_size_2d_l64_houdayer_sampled(pt):
         assert (a[picks] == b).all()
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_3d_l16_long(pt, layout):
+    """3D L=16 (the shape whose sweep runs with compile-time geometry) for 300
+    steps of sweep, exchange and measurement at 8 temperatures across the
+    workload's range; every bit of the state and the observables against the
+    oracle."""
+    S, NT = 2, 8
+    betas = W.geometric_betas(0.9, 2.0, NT)
+    J = W.couplings_pm_j(S, 16, 3, 1616)
+    say(f"case 3d L=16 S={S} NT={NT} layout={layout}, 300 steps")
+    job = pt.pt_init(S, NT, 16, 3, J, betas, 5150 + layout, layout=layout)
+    ref = oracle.OracleJob(S, NT, 16, 3, J, betas, 5150 + layout)
+    for n in (100, 200):
+        pt.pt_mcs(job, n, measure=True)
+        ref.mcs(n, measure=True)
+        compare(pt, job, ref, f"after {n}")
+    compare_observables(pt, job, ref)
+    pt.pt_destroy(job)
+
+
 def test_2d_l64_houdayer_long_cold(pt):
     """2D L=64 at the workload's lowest temperatures for 300 steps of sweep,
     Houdayer move, exchange and measurement: overlap clusters grow large and
