@@ -74,24 +74,37 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
 // (one wavefront ballot per 64 of them), then one lane per set walks the
 // chain.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* lds, int s,
-                                                  uint32_t u, int c_lo, int nsets) {
+// The inputs of pass u that the step's sweep and Houdayer move do not change:
+// the map before the pass and one Philox word per (set, k).  Written before
+// the sweep, so that the sweep's closing barrier orders them before the
+// decisions.
+__device__ __forceinline__ void exchange_prepare(const FusedArgs& A, uint32_t* lds, int s,
+                                                 uint32_t u, int c_lo, int nsets) {
   const Geo& g = A.g;
   const int NT = g.NT, tid = threadIdx.x, T = blockDim.x;
-  const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
-  int32_t* sotl = reinterpret_cast<int32_t*>(lds + A.lay.sot);
-  int32_t* tosl = reinterpret_cast<int32_t*>(lds + A.lay.tos);
+  const int32_t* sotl = reinterpret_cast<const int32_t*>(lds + A.lay.sot);
   int32_t* sot0 = reinterpret_cast<int32_t*>(lds + A.lay.sot0);
   uint32_t* rpt = lds + A.lay.rpt;
-  uint32_t* acc = lds + A.lay.acc;  // bit j of row (c, k): rows of NB bits, c-major
-  const int NB = (NT + 31) & ~31;
   for (int i = tid; i < 2 * NT; i += T) sot0[i] = sotl[i];
   for (int i = tid; i < nsets * (NT - 1); i += T) {
     const int c = c_lo + i / (NT - 1), k = i - (c - c_lo) * (NT - 1);
     rpt[c * NT + k] =
         philox10(Ctr4{(uint32_t)k, u, (uint32_t)c, (kTagPT << 28) | (uint32_t)s}, g.key0, g.key1).x;
   }
-  __syncthreads();
+}
+
+// The pass itself, after exchange_prepare and a workgroup barrier.
+__device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* lds, int c_lo,
+                                                  int nsets) {
+  const Geo& g = A.g;
+  const int NT = g.NT, tid = threadIdx.x, T = blockDim.x;
+  const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
+  int32_t* sotl = reinterpret_cast<int32_t*>(lds + A.lay.sot);
+  int32_t* tosl = reinterpret_cast<int32_t*>(lds + A.lay.tos);
+  const int32_t* sot0 = reinterpret_cast<const int32_t*>(lds + A.lay.sot0);
+  const uint32_t* rpt = lds + A.lay.rpt;
+  uint32_t* acc = lds + A.lay.acc;  // bit j of row (c, k): rows of NB bits, c-major
+  const int NB = (NT + 31) & ~31;
   {
     const int lane = tid & 63, total = nsets * (NT - 1) * NB;  // a multiple of 32
     uint32_t* accs = acc + (size_t)c_lo * (NT - 1) * (NB >> 5);
@@ -671,9 +684,10 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
 
   for (int step = 0; step < A.nmcs; ++step) {
     const uint32_t t = t0 + (uint32_t)step;
+    exchange_prepare(A, lds, s, u0 + (uint32_t)step, c_lo, nsets);
     sweep_resident<D>(A, Jl, W, El, tosl, thrl, slot0, nres, s, t);
     if (hou) houdayer_resident<D>(A, lds, s, v0 + (uint32_t)step);
-    exchange_resident(A, lds, s, u0 + (uint32_t)step, c_lo, nsets);
+    exchange_resident(A, lds, c_lo, nsets);
     if (meas) measure_resident(A, lds);
   }
 
@@ -829,6 +843,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
 
   for (int step = 0; step < A.nmcs; ++step) {
     const uint32_t t = t0 + (uint32_t)step;
+    exchange_prepare(A, lds, s, u0 + (uint32_t)step, 0, 2);
     sweep_resident<D>(A, Jsrc, W, El, tosl, thrl, slot0, nres, s, t);
     // publish, meet, and take the sample-wide steps
     const int par = step & 1;
@@ -840,7 +855,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     if (!part_barrier(bar, (uint32_t)(A.parts * (step + 1)), fault, flag)) break;
     for (int i = tid; i < nslot; i += T) El[i] = Ex[par * nslot + i];
     __syncthreads();
-    exchange_resident(A, lds, s, u0 + (uint32_t)step, 0, 2);
+    exchange_resident(A, lds, 0, 2);
     if (meas) measure_split(A, lds, part, snap + (size_t)par * nslot * W2);
   }
 
