@@ -50,6 +50,19 @@ constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0
 constexpr int kBcast15 = 0x142, kBcast31 = 0x143;  // to rows 1, 3 / rows 2, 3
 constexpr int kWaveRol1 = 0x134, kWaveRor1 = 0x13C;  // lane i takes lane i + 1 / i - 1 (mod 64)
 
+// Sum over the wavefront as a wavefront constant, by DPP: row prefix sums,
+// then the broadcasts of lanes 15 and 31 carry them on, so that lane 63 ends
+// with the total (no LDS round trips).
+__device__ __forceinline__ int wave_total(int v) {
+  v += (int)dpp_zero<kRowShr1>((uint32_t)v);
+  v += (int)dpp_zero<kRowShr2>((uint32_t)v);
+  v += (int)dpp_zero<kRowShr4>((uint32_t)v);
+  v += (int)dpp_zero<kRowShr8>((uint32_t)v);
+  v += (int)dpp_zero<kBcast15, 0xA>((uint32_t)v);
+  v += (int)dpp_zero<kBcast31, 0xC>((uint32_t)v);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -197,7 +210,7 @@ __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* l
     const uint32_t* Wb = W + (size_t)b * 2 * NW;
     int neg = 0;
     for (int w = lane; w < 2 * NW; w += 64) neg += __popc(Wa[w] ^ Wb[w]);
-    neg = wave_sum(neg);
+    neg = wave_total(neg);
     if (lane == 0) add_moments(g, mom + (size_t)k * 8, El[a], El[b], neg);
   }
   __syncthreads();
