@@ -631,19 +631,34 @@ __device__ __forceinline__ void sweep_resident_shape(const Geo& g, const FusedAr
   __syncthreads();
 }
 
-// The sweep with the geometry of the shape the workloads run most (3D L = 16,
-// 2D L = 64) folded to compile-time constants, else from g.
-template <int D>
+// The sweep with the geometry of the shapes the workloads run most folded to
+// compile-time constants (3D L = 16, 2D L = 64; for split samples, which run
+// one workgroup per CU whatever their registers, also 3D L = 32 and 48), else
+// from g.
+template <int D, bool kSplitShapes = false>
 __device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_t* J, uint32_t* W,
                                                int32_t* El, const int32_t* tosl,
                                                const uint32_t* thrl, int slot0, int nres, int s,
                                                uint32_t t) {
   constexpr int kFixedL = D == 3 ? 16 : 64;
-  if (A.g.L == kFixedL)
+  if (A.g.L == kFixedL) {
     sweep_resident_shape<D, kFixedL>(fixed_shape<D, kFixedL>(A.g), A, J, W, El, tosl, thrl, slot0,
                                      nres, s, t);
-  else
-    sweep_resident_shape<D, 0>(A.g, A, J, W, El, tosl, thrl, slot0, nres, s, t);
+    return;
+  }
+  if constexpr (kSplitShapes && D == 3) {
+    if (A.g.L == 32) {
+      sweep_resident_shape<3, 32>(fixed_shape<3, 32>(A.g), A, J, W, El, tosl, thrl, slot0, nres,
+                                  s, t);
+      return;
+    }
+    if (A.g.L == 48) {
+      sweep_resident_shape<3, 48>(fixed_shape<3, 48>(A.g), A, J, W, El, tosl, thrl, slot0, nres,
+                                  s, t);
+      return;
+    }
+  }
+  sweep_resident_shape<D, 0>(A.g, A, J, W, El, tosl, thrl, slot0, nres, s, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -857,7 +872,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
   for (int step = 0; step < A.nmcs; ++step) {
     const uint32_t t = t0 + (uint32_t)step;
     exchange_prepare(A, lds, s, u0 + (uint32_t)step, 0, 2);
-    sweep_resident<D>(A, Jsrc, W, El, tosl, thrl, slot0, nres, s, t);
+    sweep_resident<D, true>(A, Jsrc, W, El, tosl, thrl, slot0, nres, s, t);
     // publish, meet, and take the sample-wide steps
     const int par = step & 1;
     for (int i = tid; i < nres; i += T) Ex[par * nslot + slot0 + i] = El[slot0 + i];
