@@ -612,7 +612,26 @@ __device__ __forceinline__ void sweep_resident_shape(const Geo& g, const FusedAr
   const bool owned =
       64 % NW == 0 ||
       (NW % 64 == 0 && (nres + nwave - 1) / nwave * nwave * NW <= (items + T - 1) / T * T);
-  if (owned) {
+  constexpr bool kWordPerLane = LS != 0 && geo_shape(LS, D).NW == 64;
+  if constexpr (kWordPerLane) {
+    // every unit is one configuration and lane w always updates word w: the
+    // word's coupling words are loaded once per colour
+    const int nunits = nres, lane = tid & 63, step = T >> 6;
+    for (int c = 0; c < 2; ++c) {
+      uint32_t jv[2 * D];
+#pragma unroll
+      for (int dir = 0; dir < 2 * D; ++dir) jv[dir] = J[(c * 2 * D + dir) * NW + lane];
+      for (int u = tid >> 6; u < nunits; u += step) {
+        const int slot = slot0 + u;
+        const int k = tosl[slot];
+        int dE = 0;
+        sweep_word_j<D>(g, W + u * W2, jv, c, lane, slot, s, t, thrl[k * 4 + 0], thrl[k * 4 + 1],
+                        thrl[k * 4 + 2], dE);
+        if (dE) atomicAdd(&El[slot], dE);
+      }
+      if (c == 0) wave_lds_sync();
+    }
+  } else if (owned) {
     const int m = NW >= 64 ? NW >> 6 : 1;  // units per configuration (or 1)
     const int nunits = (items + 63) >> 6, lane = tid & 63, step = (T >> 6) * m;
     for (int c = 0; c < 2; ++c) {

@@ -15,15 +15,11 @@
 
 namespace ptsg {
 
+// jv: the word's 2d coupling words (colour c, direction-major).
 template <int D>
-__device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint32_t* __restrict__ jw,
-                                           int c, int w, int slot, int s, uint32_t tcount,
-                                           uint32_t th2, uint32_t th4, uint32_t th6, int& dE) {
-  // coupling words first: their loads overlap the neighbour loads
-  const size_t js = (size_t)g.NW;
-  uint32_t jv[2 * D];
-#pragma unroll
-  for (int dir = 0; dir < 2 * D; ++dir) jv[dir] = jw[dir * js + w];
+__device__ __forceinline__ void sweep_word_j(const Geo& g, uint32_t* W, const uint32_t (&jv)[2 * D],
+                                             int c, int w, int slot, int s, uint32_t tcount,
+                                             uint32_t th2, uint32_t th4, uint32_t th6, int& dE) {
   const WordNb q = word_nb(g, w);
   const int p = (c + q.par) & 1;
   const uint32_t* Wo = W + (1 - c) * g.NW;
@@ -143,6 +139,19 @@ __device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint
   }
   dE += 4 * (D * __popc(F) - (__popc(F & u0) + 2 * __popc(F & u1) + 4 * __popc(F & u2)));
   W[c * g.NW + w] = Wc ^ F;
+}
+
+// The same with the coupling words loaded here (their loads overlap the
+// neighbour loads).
+template <int D>
+__device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint32_t* __restrict__ jw,
+                                           int c, int w, int slot, int s, uint32_t tcount,
+                                           uint32_t th2, uint32_t th4, uint32_t th6, int& dE) {
+  const size_t js = (size_t)g.NW;
+  uint32_t jv[2 * D];
+#pragma unroll
+  for (int dir = 0; dir < 2 * D; ++dir) jv[dir] = jw[dir * js + w];
+  sweep_word_j<D>(g, W, jv, c, w, slot, s, tcount, th2, th4, th6, dE);
 }
 
 // Number of unsatisfied bonds of the colour-0 word w (every bond has exactly
