@@ -11,6 +11,7 @@ ctypes.  Build with :func:`build` (gcc -O2, no fast-math, no intrinsics).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -81,6 +82,7 @@ def _declare(L):
     L.or_get_maps.argtypes = [P, P, P]
     L.or_get_counters.argtypes = [P, P]
     L.or_get_moments.argtypes = [P, P, P, P, P, P, P]
+    L.or_get_walk.argtypes = [P, P, P, P]
     L.or_pt_table_len.argtypes = [P]
     L.or_pt_table_len.restype = C.c_int
     L.or_get_pt_table.argtypes = [P, P]
@@ -279,9 +281,82 @@ class OracleJob:
         lib().or_get_pt_table(self._h, _p(out))
         return out
 
+    def walk(self):
+        """Replica-walk state after the last exchange pass (Sec. 2.3): slot
+        labels [S][2NT] (0 none, 1 going up, 2 going down), the pass at which
+        each slot's current round trip began [S][2NT], and the round-trip bins
+        [S][32][3] (trips ended in passes [2^b, 2^(b+1)): count, sum of
+        lengths, sum of squared lengths)."""
+        lab = np.zeros((self.S, 2 * self.NT), np.int32)
+        beg = np.zeros((self.S, 2 * self.NT), np.uint32)
+        trips = np.zeros((self.S, 32, 3), np.uint64)
+        lib().or_get_walk(self._h, _p(lab), _p(beg), _p(trips))
+        return lab, beg, trips
+
     def observables(self):
         ps = np.zeros((self.S, self.NT, 5), np.float64)
         dis = np.zeros((self.NT, 6), np.float64)
         n = np.zeros(1, np.int64)
         lib().or_observables(self._h, _p(ps), _p(dis), _p(n))
         return ps, dis, int(n[0])
+
+
+# --------------------------------------------------------------------------
+# Round-trip time summary (Sec. 2.3)
+# --------------------------------------------------------------------------
+def tunnel_summary(trips, passes):
+    """Round-trip time estimates from round-trip bins.
+
+    trips: integer array [..., 32, 3] (count, sum of lengths, sum of squared
+    lengths per logarithmic bin b of the pass at which a trip ended); every
+    leading index is pooled.  passes: exchange passes done so far.
+
+    Returns (tau_b[32], err_b[32], tau, equilibrated):
+      tau_b = sum of lengths / count of bin b (nan when empty);
+      err_b = standard error of that mean, sqrt((C Q - D^2) / (C^2 (C - 1)))
+              with C, D, Q the bin's count, sum and sum of squares (nan when
+              C < 2);
+      tau   = all lengths over all trips (nan when there is none);
+      equilibrated = 1 when the last three complete bins (bin b is complete
+              once passes >= 2^(b+1) - 1) each hold two or more trips and
+              every two of them differ by at most twice the root sum of
+              squares of their errors -- the logarithmic-binning check, read
+              as agreement of the last three bins within two standard errors.
+    """
+    t = np.asarray(trips, dtype=np.uint64).reshape(-1, 32, 3)
+    C = [0] * 32
+    D = [0] * 32
+    Q = [0] * 32
+    for row in t:
+        for b in range(32):
+            C[b] += int(row[b][0])
+            D[b] += int(row[b][1])
+            Q[b] += int(row[b][2])
+    tau_b = np.full(32, np.nan)
+    err_b = np.full(32, np.nan)
+    for b in range(32):
+        if C[b] > 0:
+            tau_b[b] = D[b] / C[b]
+        if C[b] > 1:
+            num = C[b] * Q[b] - D[b] * D[b]
+            err_b[b] = math.sqrt(float(num) / (float(C[b]) * float(C[b]) * float(C[b] - 1)))
+    ctot, dtot = sum(C), sum(D)
+    tau = dtot / ctot if ctot > 0 else float("nan")
+    top = -1
+    while top + 1 < 32 and (1 << (top + 2)) - 1 <= passes:
+        top += 1
+    eq = 0
+    if top >= 2:
+        last = [top - 2, top - 1, top]
+        eq = 1
+        for b in last:
+            if C[b] < 2:
+                eq = 0
+        if eq:
+            for i in range(3):
+                for j in range(i + 1, 3):
+                    a, b = last[i], last[j]
+                    lim = 2.0 * math.sqrt(err_b[a] ** 2 + err_b[b] ** 2)
+                    if abs(tau_b[a] - tau_b[b]) > lim:
+                        eq = 0
+    return tau_b, err_b, tau, eq

@@ -20,6 +20,8 @@
  *   - One Monte Carlo step = Metropolis sweep, Houdayer move per same-T pair,
  *     PT update over neighbouring-T pairs: Sec. 2.4 (enumerated update scheme).
  *   - Counter-based Philox random numbers: Sec. 3 (Salmon et al. 2011).
+ *   - Round-trip (tunnelling) time of the replica walk in temperature space
+ *     and its logarithmically binned time series: Sec. 2.3.
  *
  * Readings where the paper is silent (all documented in the design notes):
  *   checkerboard order (colour 0 then colour 1, increasing site index inside a
@@ -225,6 +227,9 @@ typedef struct {
   uint64_t t, u, v, n_meas;
   int64_t *mE, *mE2, *mQ, *mAQ, *mQ2; /* [S][NT] */
   unsigned __int128 *mQ4;             /* [S][NT] */
+  int32_t *wlab;          /* [S][2NT]: walk label of slot (0 none, 1 up, 2 down) */
+  uint32_t *wbeg;         /* [S][2NT]: pass at which its current round trip began */
+  uint64_t *trip;         /* [S][32][3]: per log2 bin: trips, sum len, sum len^2 */
 } or_job;
 
 static int8_t *or_lat(or_job *jb, int s, int slot) {
@@ -276,6 +281,9 @@ OR_EXPORT or_job *or_create(int S, int NT, int L, int d, const int8_t *J,
   jb->mAQ = (int64_t *)calloc(ST, sizeof(int64_t));
   jb->mQ2 = (int64_t *)calloc(ST, sizeof(int64_t));
   jb->mQ4 = (unsigned __int128 *)calloc(ST, sizeof(unsigned __int128));
+  jb->wlab = (int32_t *)calloc((size_t)S * jb->nslot, sizeof(int32_t));
+  jb->wbeg = (uint32_t *)calloc((size_t)S * jb->nslot, sizeof(uint32_t));
+  jb->trip = (uint64_t *)calloc((size_t)S * 32 * 3, sizeof(uint64_t));
   /* initial spins: one Philox word per site, s = -1 iff its top bit is set */
   for (int s = 0; s < S; ++s)
     for (int r = 0; r < jb->nslot; ++r) {
@@ -302,7 +310,7 @@ OR_EXPORT void or_destroy(or_job *jb) {
   free(jb->sample_key); free(jb->J); free(jb->s); free(jb->E);
   free(jb->sot); free(jb->tos); free(jb->beta); free(jb->thr); free(jb->thrpt);
   free(jb->mE); free(jb->mE2); free(jb->mQ); free(jb->mAQ); free(jb->mQ2);
-  free(jb->mQ4);
+  free(jb->mQ4); free(jb->wlab); free(jb->wbeg); free(jb->trip);
   free(jb);
 }
 
@@ -354,6 +362,48 @@ OR_EXPORT void or_sweep(or_job *jb, int n) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Replica walk and round-trip time (Sec. 2.3).  The round-trip or tunnelling */
+/* time is the expected number of Monte Carlo steps a configuration needs to   */
+/* travel from the lowest temperature to the highest and back.  Reading:       */
+/* every stored configuration (slot) is looked at after each exchange pass,    */
+/* numbered m = 1, 2, ... (the pass counter after the pass).  A slot carries a */
+/* label: 0 until it first sits at the lowest temperature; 1 ("going up") from */
+/* then on; 2 ("going down") once it reaches the highest temperature while     */
+/* labelled 1.  When a slot labelled 2 is back at the lowest temperature, one  */
+/* round trip ends; its length is m minus the pass at which the label last    */
+/* became 1, and the label becomes 1 again with the new trip beginning at m.   */
+/* Slots revisiting the lowest temperature while labelled 1 change nothing.   */
+/* A trip ending at pass m is filed in the logarithmic bin floor(log2 m) of    */
+/* its sample (both replica sets together): count, sum of lengths, sum of      */
+/* squared lengths.  Houdayer moves exchange spins, not slots, and do not     */
+/* enter.  Called once per set and pass, after the pass.                       */
+/* ------------------------------------------------------------------------ */
+static void or_walk_observe(or_job *jb, int s, int c, uint64_t m) {
+  const int NT = jb->NT;
+  for (int j = 0; j < NT; ++j) {
+    const size_t o = (size_t)s * jb->nslot + (size_t)c * NT + j;
+    const int k = jb->tos[((size_t)s * 2 + c) * NT + j];
+    if (k == 0) {
+      if (jb->wlab[o] == 2) {
+        uint64_t len = m - (uint64_t)jb->wbeg[o];
+        int bin = 0;
+        while ((m >> (bin + 1)) != 0) ++bin;
+        uint64_t *t = &jb->trip[((size_t)s * 32 + bin) * 3];
+        t[0] += 1;
+        t[1] += len;
+        t[2] += len * len;
+      }
+      if (jb->wlab[o] != 1) {
+        jb->wlab[o] = 1;
+        jb->wbeg[o] = (uint32_t)m;
+      }
+    } else if (k == NT - 1 && jb->wlab[o] == 1) {
+      jb->wlab[o] = 2;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Parallel-tempering pass (Sec. 2.2, Eq. (5); temperatures are exchanged,    */
 /* not configurations, via two index arrays, Sec. 3).  For each sample and     */
 /* each replica set c separately, k = 0 .. NT-2 in ascending order.            */
@@ -385,6 +435,7 @@ OR_EXPORT void or_exchange(or_job *jb) {
           tos[b] = k; tos[a] = k + 1;
         }
       }
+      or_walk_observe(jb, s, c, jb->u + 1);
     }
   jb->u += 1;
 }
@@ -599,6 +650,14 @@ OR_EXPORT void or_get_moments(const or_job *jb, int64_t *mE, int64_t *mE2,
     mQ4_lohi[2 * o] = (uint64_t)jb->mQ4[o];
     mQ4_lohi[2 * o + 1] = (uint64_t)(jb->mQ4[o] >> 64);
   }
+}
+/* Walk labels and trip beginnings [S][2NT]; round-trip bins [S][32][3]. */
+OR_EXPORT void or_get_walk(const or_job *jb, int32_t *label, uint32_t *begin,
+                           uint64_t *trips) {
+  size_t n = (size_t)jb->S * jb->nslot;
+  if (label) memcpy(label, jb->wlab, sizeof(int32_t) * n);
+  if (begin) memcpy(begin, jb->wbeg, sizeof(uint32_t) * n);
+  if (trips) memcpy(trips, jb->trip, sizeof(uint64_t) * (size_t)jb->S * 32 * 3);
 }
 OR_EXPORT int or_pt_table_len(const or_job *jb) { return jb->M; }
 OR_EXPORT void or_get_pt_table(const or_job *jb, uint32_t *out) {

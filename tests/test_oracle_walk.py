@@ -1,0 +1,178 @@
+"""Pins of the oracle's replica-walk bookkeeping and round-trip times (Sec. 2.3).
+
+The round-trip (tunnelling) time is the expected number of Monte Carlo steps a
+configuration takes from the lowest temperature to the highest and back.  The
+oracle tracks it online with a per-slot label; these tests fix it against
+  * a closed form: with (numerically) equal temperatures every exchange is
+    accepted, the ascending pass then rotates the ladder by one place per pass,
+    and every round trip lasts exactly N_T passes;
+  * an offline rescan of each slot's recorded temperature history that finds
+    the round trips from the definition directly;
+  * the bound every trip obeys under the ascending pass (a configuration moves
+    down at most one temperature per pass, so a trip takes >= N_T passes);
+  * hand-worked values of the summary (mean, standard error, the
+    logarithmic-binning check).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_04621_amd import workloads
+
+
+def _job(S, NT, L, d, betas, seed=5):
+    J = workloads.couplings_pm_j(S, L, d, seed=123)
+    return oracle.OracleJob(S, NT, L, d, J, betas, seed)
+
+
+def _expected_rotation(NT, P):
+    """Closed form of the all-accepted ascending pass: slot j of a set sits at
+    temperature (j - m) mod NT after pass m.  Returns per-slot labels, trip
+    beginnings and the bins of one set."""
+    lab = np.zeros(NT, np.int32)
+    beg = np.zeros(NT, np.uint32)
+    bins = np.zeros((32, 3), np.uint64)
+    for j in range(NT):
+        first = j if j >= 1 else NT  # first pass at the lowest temperature
+        if P < first:
+            continue
+        m = first + NT
+        while m <= P:  # every later arrival at the lowest ends a trip of NT
+            b = m.bit_length() - 1
+            bins[b] += np.array([1, NT, NT * NT], np.uint64)
+            m += NT
+        last_cold = first + ((P - first) // NT) * NT
+        beg[j] = last_cold
+        lab[j] = 1 if (j - P) % NT == 0 else 2  # the pass after a cold visit is hot
+    return lab, beg, bins
+
+
+@pytest.mark.parametrize("NT,P", [(2, 37), (3, 64), (5, 100), (8, 257)])
+def test_walk_rotation_closed_form(NT, P):
+    S, L, d = 2, 4, 2
+    betas = 0.5 - 1e-13 * np.arange(NT)  # strictly decreasing, every swap accepted
+    job = _job(S, NT, L, d, betas)
+    job.mcs(P)
+    sot, tos = job.maps()
+    for s in range(S):
+        for c in range(2):
+            assert [int(x) for x in tos[s, c]] == [(j - P) % NT for j in range(NT)]
+    lab, beg, trips = job.walk()
+    elab, ebeg, ebins = _expected_rotation(NT, P)
+    for s in range(S):
+        for c in range(2):
+            np.testing.assert_array_equal(lab[s, c * NT:(c + 1) * NT], elab)
+            np.testing.assert_array_equal(beg[s, c * NT:(c + 1) * NT], ebeg)
+        np.testing.assert_array_equal(trips[s], 2 * ebins)  # two replica sets
+    tau_b, err_b, tau, eq = oracle.tunnel_summary(trips, P)
+    assert tau == NT
+    filled = ebins[:, 0] > 0
+    assert np.all(tau_b[filled] == NT)
+    assert np.all(np.isnan(tau_b[~filled]))
+
+
+def _rescan(history, NT):
+    """Round trips from one slot's temperatures after passes 1..P: a trip
+    starts at the first arrival at the lowest temperature and at every arrival
+    there that follows a visit to the highest since the previous start."""
+    starts = []
+    hot_since = False
+    for m, k in enumerate(history, start=1):
+        if k == NT - 1 and starts:
+            hot_since = True
+        if k == 0 and (not starts or hot_since):
+            starts.append(m)
+            hot_since = False
+    bins = np.zeros((32, 3), np.uint64)
+    for a, b in zip(starts[:-1], starts[1:]):
+        n = b - a
+        bins[b.bit_length() - 1] += np.array([1, n, n * n], np.uint64)
+    if not starts:
+        return 0, 0, bins
+    return (2 if hot_since else 1), starts[-1], bins
+
+
+@pytest.mark.parametrize("d,L,NT,P,hou", [(2, 4, 5, 300, False), (3, 4, 6, 200, True),
+                                         (2, 6, 4, 250, False)])
+def test_walk_matches_offline_rescan(d, L, NT, P, hou):
+    S = 3
+    betas = np.geomspace(1 / 0.3, 1 / 3.0, NT)
+    job = _job(S, NT, L, d, betas, seed=77)
+    hist = np.zeros((P, S, 2, NT), np.int32)
+    for m in range(P):
+        job.mcs(1, houdayer=hou)
+        hist[m] = job.maps()[1]
+    lab, beg, trips = job.walk()
+    total = 0
+    for s in range(S):
+        want = np.zeros((32, 3), np.uint64)
+        for c in range(2):
+            for j in range(NT):
+                l, b, bins = _rescan([int(x) for x in hist[:, s, c, j]], NT)
+                assert lab[s, c * NT + j] == l
+                if l:
+                    assert beg[s, c * NT + j] == b
+                want += bins
+        np.testing.assert_array_equal(trips[s], want)
+        total += int(want[:, 0].sum())
+    assert total > 20  # the ladder is narrow enough for many round trips
+
+
+def test_trip_lengths_bounded_by_ladder():
+    """Ascending pass: a configuration moves down at most one temperature per
+    pass, so every trip takes at least N_T passes."""
+    S, NT, L, d, P = 4, 8, 6, 2, 400
+    betas = np.geomspace(1 / 0.4, 1 / 2.5, NT)
+    job = _job(S, NT, L, d, betas, seed=9)
+    job.mcs(P)
+    _, _, trips = job.walk()
+    C = trips[..., 0].astype(np.int64)
+    D = trips[..., 1].astype(np.int64)
+    Q = trips[..., 2].astype(np.int64)
+    assert C.sum() > 0
+    assert np.all(D >= NT * C)
+    assert np.all(Q >= NT * D)
+    assert np.all(C * Q >= D * D)  # Cauchy-Schwarz within each bin
+    for b in range(32):  # no trip ends outside its bin's passes
+        if C[:, b].sum():
+            assert (1 << b) <= P
+
+
+def test_tunnel_summary_hand_values():
+    trips = np.zeros((2, 32, 3), np.uint64)
+    trips[0, 3] = [1, 4, 16]  # sample 0: one trip of 4 ending in passes 8..15
+    trips[1, 3] = [1, 6, 36]  # sample 1: one trip of 6
+    trips[1, 4] = [3, 18, 110]  # lengths 5, 6, 7 (25 + 36 + 49 = 110)
+    tau_b, err_b, tau, eq = oracle.tunnel_summary(trips, 20)
+    assert tau_b[3] == 5.0 and err_b[3] == 1.0  # {4, 6}: mean 5, s.e. 1
+    assert tau_b[4] == 6.0
+    assert math.isclose(err_b[4], 1 / math.sqrt(3), rel_tol=1e-15)  # {5,6,7}
+    assert tau == 28 / 5
+    assert np.isnan(tau_b[0]) and np.isnan(err_b[0])
+    assert eq == 0  # 20 passes: complete bins 0..3, bins 1 and 2 empty
+    one = oracle.tunnel_summary(trips[1], 20)
+    assert one[2] == 24 / 4 and one[0][3] == 6.0 and np.isnan(one[1][3])
+
+
+def test_tunnel_summary_equilibration_flag():
+    def bins(values):
+        t = np.zeros((32, 3), np.uint64)
+        for b, lens in values.items():
+            t[b] = [len(lens), sum(lens), sum(x * x for x in lens)]
+        return t
+    agree = bins({3: [4, 6], 4: [5, 7], 5: [4, 5, 6, 7]})
+    # bins 3..5 complete once passes >= 63
+    assert oracle.tunnel_summary(agree, 62)[3] == 0
+    assert oracle.tunnel_summary(agree, 63)[3] == 1
+    assert oracle.tunnel_summary(agree, 126)[3] == 1  # bin 6 not complete yet
+    assert oracle.tunnel_summary(agree, 127)[3] == 0  # bin 6 complete and empty
+    drift = bins({3: [4, 6], 4: [5, 7], 5: [20, 22, 21, 23]})
+    assert oracle.tunnel_summary(drift, 63)[3] == 0
+    thin = bins({3: [4, 6], 4: [5], 5: [4, 5, 6, 7]})  # one trip in bin 4
+    assert oracle.tunnel_summary(thin, 63)[3] == 0
+    exact = bins({0: [], 1: [3, 3], 2: [3, 3, 3]})  # zero errors, equal means
+    exact[0] = [0, 0, 0]
+    assert oracle.tunnel_summary(bins({0: [3, 3], 1: [3, 3], 2: [3, 3, 3]}), 7)[3] == 1
+    assert oracle.tunnel_summary(exact, 7)[3] == 0  # bin 0 empty
