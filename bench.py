@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=500, help="steps per fused launch")
     ap.add_argument("--plain-steps", type=int, default=300,
                     help="steps re-timed with one launch per kernel (0: skip)")
+    ap.add_argument("--walk-steps", type=int, default=1000,
+                    help="steps of the same workload with the replica walk kept (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-jobs", type=int, default=2000)
@@ -335,6 +337,29 @@ def main():
     _, dis, n_meas = pt.pt_observables(job)
     pt.pt_destroy(job)
 
+    # the same workload with the replica walk and its round trips kept
+    walk = None
+    if args.walk_steps > 0:
+        print("# replica walk kept", file=sys.stderr, flush=True)
+        wj = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed,
+                        layout=layout, walk=True)
+        pt.pt_mcs(wj, args.warmup, houdayer=wl.houdayer, measure=True)
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        for st in range(0, args.walk_steps, chunk):
+            pt.pt_mcs(wj, min(chunk, args.walk_steps - st), houdayer=wl.houdayer, measure=True)
+        torch.cuda.synchronize()
+        dtw = time.perf_counter() - tw
+        passes = pt.pt_get_counters(wj)["u"]
+        trips = pt.pt_get_walk(wj)[2]
+        _, _, tau, eq = pt.pt_tunnel_summary(trips, passes)
+        walk = {"value": round(flips_per_step * args.walk_steps / dtw / 1e9, 2), "unit": "flips/ns",
+                "steps": args.walk_steps, "passes": passes,
+                "round_trips": int(trips[..., 0].sum()),
+                "tau_tunnel": None if np.isnan(tau) else round(tau, 3),
+                "equilibrated": eq}
+        pt.pt_destroy(wj)
+
     batched = None
     if not args.no_batched:
         print("# batched form", file=sys.stderr, flush=True)
@@ -360,6 +385,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_form": plain,
+        "replica_walk": walk,
         "batched": batched,
         "served": serve,
         "e_coldest": round(float(dis[0, 0]), 6), "binder_coldest": round(float(dis[0, 5]), 6),

@@ -59,6 +59,11 @@ extern "C" {
 /* Device spin layouts (pt_init_ex flags). */
 #define PT_LAYOUT_INT8 0u   /* one int8 per spin, lattice-contiguous */
 #define PT_LAYOUT_PACKED 1u /* one bit per spin, split by checkerboard colour */
+/* Also a pt_init_ex flag (ORed with the layout; accepted by pt_plan_query,
+ * pt_job_bytes and in pt_request.layout): the job keeps the replica walk in
+ * temperature space and its round trips (pt_get_walk).  Off by default: the
+ * fused kernels then carry no walk code at all. */
+#define PT_TRACK_WALK 0x10u
 
 /* pt_mcs flags */
 #define PT_MCS_HOUDAYER 1u
@@ -108,7 +113,8 @@ int pt_init(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
             uint64_t seed);
 
 /* pt_init with a device spin layout: flags = PT_LAYOUT_INT8 or
- * PT_LAYOUT_PACKED.  Results are bit-identical for both layouts. */
+ * PT_LAYOUT_PACKED, optionally | PT_TRACK_WALK.  Results are bit-identical
+ * for both layouts, with or without the walk. */
 int pt_init_ex(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
                int32_t dim, const int8_t *couplings, const double *betas,
                uint64_t seed, uint32_t flags);
@@ -127,7 +133,9 @@ int pt_sweep(pt_job *job, int32_t n);
  * replica set separately, k = 0 .. N_T-2 ascending: with a, b the slots at
  * beta_k, beta_{k+1} and D = E_b - E_a, the temperatures are swapped iff
  * D <= 0 or r < floor(2^32 exp(-(beta_k - beta_{k+1}) D)), r being word 0 of
- * the Philox counter (k, u, set, 4<<28 | sample), u the exchange counter. */
+ * the Philox counter (k, u, set, 4<<28 | sample), u the exchange counter.
+ * In a job created with PT_TRACK_WALK every pass, fused or not, then updates
+ * the replica walk (pt_get_walk). */
 int pt_exchange(pt_job *job);
 
 /* One Houdayer cluster move (Sec. 2.4, Eq. (10)) per sample and temperature
@@ -163,12 +171,14 @@ int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
 int pt_get_plan(pt_job *job, uint32_t flags, int32_t *out4);
 
 /* The same report for a job of this shape before it exists (host only, no
- * device call): a plan depends on dim, L and replicas, not on samples. */
+ * device call): a plan depends on dim, L and replicas, not on samples, and on
+ * whether PT_TRACK_WALK (also accepted in flags here) keeps the walk. */
 int pt_plan_query(int32_t dim, int32_t L, int32_t replicas, uint32_t flags, int32_t *out4);
 
 /* Upper bound of the device bytes pt_init_ex allocates for this shape
- * (including the split-sample scratch when the plan needs it); the request
- * server admits by this figure.  Host only; PT_EINVAL as pt_init_ex. */
+ * (including the split-sample scratch when the plan needs it); layout as
+ * pt_init_ex's flags.  The request server admits by this figure.  Host
+ * only; PT_EINVAL as pt_init_ex. */
 int pt_job_bytes(int32_t samples, int32_t replicas, int32_t L, int32_t dim, uint32_t layout,
                  const double *betas, uint64_t *out);
 
@@ -199,8 +209,43 @@ int pt_get_counters(pt_job *job, uint64_t *out);
 /* int64 [samples][replicas][7]: sum E, sum E^2, sum Q, sum |Q|, sum Q^2,
  * sum Q^4 low 64 bits, sum Q^4 high 64 bits */
 int pt_get_moments(pt_job *job, int64_t *out);
+/* Replica walk in temperature space and round-trip times (Sec. 2.3: the
+ * round-trip or tunnelling time is the expected number of Monte Carlo steps a
+ * configuration needs from the lowest temperature to the highest and back).
+ * Each slot is looked at after every exchange pass m = u (the exchange
+ * counter after the pass, from 1).  Its label is 0 until it first sits at the
+ * lowest temperature, then 1 ("going up"), and 2 ("going down") once it
+ * reaches the highest temperature while labelled 1.  A slot labelled 2 back
+ * at the lowest temperature ends a round trip of m - begin passes and begins
+ * the next (label 1, begin = m).  Houdayer moves leave slots where they are.
+ *   label  int32  [samples][2*replicas]  (slot r of set c at index c*replicas+r)
+ *   begin  uint32 [samples][2*replicas]  pass at which the current trip began
+ *   trips  uint64 [samples][32][3]       trips ending in passes [2^b, 2^(b+1)),
+ *          both replica sets: count, sum of lengths, sum of squared lengths
+ * Any output may be NULL.  Synchronous.  The pass clock is the 32-bit
+ * exchange counter.  PT_EINVAL for a job created without PT_TRACK_WALK. */
+int pt_get_walk(pt_job *job, int32_t *label, uint32_t *begin, uint64_t *trips);
+
+/* Round-trip time estimates from `rows` rows of round-trip bins
+ * ([rows][32][3] as pt_get_walk writes them; every row is pooled), after
+ * `passes` exchange passes.  Host-only, no job needed.  Outputs (any may be
+ * NULL):
+ *   tau_b [32]  mean trip length of bin b (NaN if empty)
+ *   err_b [32]  its standard error sqrt((C Q - D^2) / (C^2 (C - 1))) from the
+ *               bin's count C, sum D and sum of squares Q (NaN if C < 2)
+ *   tau         mean length over every trip (NaN if none)
+ *   equilibrated  1 iff the last three complete bins (bin b is complete once
+ *               passes >= 2^(b+1) - 1) each hold two or more trips and every
+ *               two of them differ by at most 2 sqrt(err_i^2 + err_j^2): the
+ *               logarithmic-binning check of Sec. 2.3.
+ * PT_EINVAL if trips is NULL or rows < 1. */
+int pt_tunnel_summary(const uint64_t *trips, int32_t rows, uint64_t passes,
+                      double *tau_b, double *err_b, double *tau,
+                      int32_t *equilibrated);
+
 /* Checkpoint: the whole dynamic state (spins, energies, maps, counters,
- * moments).  With buf == NULL, *len receives the size.  Otherwise *len must
+ * moments, and the replica walk if kept).  With buf == NULL, *len receives
+ * the size.  Otherwise *len must
  * hold at least that size.  pt_set_state restores a state taken from a job of
  * identical shape and layout; continuing is bit-identical to never stopping. */
 int pt_get_state(pt_job *job, void *buf, size_t *len);

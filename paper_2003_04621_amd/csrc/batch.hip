@@ -120,9 +120,11 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     if (mcs > 0 && meas) feat |= kFeatMeas;
     if (mcs > 0 && hou) feat |= kFeatHou;
     if (mcs > 0 && mode == 3) feat |= kFeatSplit;
+    if (mcs > 0 && j->track_walk) feat |= kFeatWalk;
     if (mode == 3) {
       FusedArgs A = make_fused_args(j->g, j->split_lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
-                                    j->thrpt, j->M, j->mom, j->ctr, mcs, false, meas);
+                                    j->thrpt, j->M, j->mom, j->walk, j->trips, j->ctr, mcs, false,
+                                    meas);
       A.parts = j->split_parts;
       A.R = j->split_R;
       A.jlds = j->split_jlds;
@@ -142,7 +144,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     }
     const int nsets = mode == 2 ? 1 : 2;
     hj.push_back(make_fused_args(j->g, j->plan[mode], j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
-                                 j->thrpt, j->M, j->mom, j->ctr, mcs, hou, meas));
+                                 j->thrpt, j->M, j->mom, j->walk, j->trips, j->ctr, mcs, hou, meas));
     lds_words = std::max(lds_words, (size_t)j->plan[mode].words);
     if (mcs <= 0) continue;
     const double c = (double)nsets * j->g.NT * j->g.N * mcs;
@@ -320,17 +322,25 @@ int snapshot(pt_batch* b, Snap& sn, bool restore) {
   size_t k = 0;
   for (pt_job* j : b->jobs) {
     const size_t lat = (size_t)j->g.S * j->g.nslot, maps = sizeof(int32_t) * (size_t)j->g.S * 2 * j->g.NT;
-    void* src[6] = {j->spins, j->E, j->sot, j->tos, j->ctr, j->mom};
-    const size_t len[6] = {j->spin_bytes(), sizeof(int32_t) * lat, maps, maps, sizeof(DevCounters),
-                           sizeof(int64_t) * 8 * (size_t)j->g.S * j->g.NT};
-    for (int i = 0; i < 6; ++i, ++k) {
+    void* src[8] = {j->spins, j->E, j->sot, j->tos, j->ctr, j->mom, j->walk, j->trips};
+    const size_t len[8] = {j->spin_bytes(),
+                           sizeof(int32_t) * lat,
+                           maps,
+                           maps,
+                           sizeof(DevCounters),
+                           sizeof(int64_t) * 8 * (size_t)j->g.S * j->g.NT,
+                           sizeof(int32_t) * 2 * lat,
+                           sizeof(uint64_t) * 32 * 3 * (size_t)j->g.S};
+    for (int i = 0; i < 8; ++i) {
+      if (!src[i]) continue;  // no replica walk kept
+      const size_t at = k++;
       if (!restore) {
         void* p = nullptr;
         if (hipMalloc(&p, len[i]) != hipSuccess) return pt_fail(PT_ENOMEM, "pt_batch_tune: snapshot allocation failed");
         sn.bufs.push_back(p);
         if (hipMemcpyAsync(p, src[i], len[i], hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
           return pt_fail(PT_EDEVICE, "pt_batch_tune: snapshot copy failed");
-      } else if (hipMemcpyAsync(src[i], sn.bufs[k], len[i], hipMemcpyDeviceToDevice, b->stream) !=
+      } else if (hipMemcpyAsync(src[i], sn.bufs[at], len[i], hipMemcpyDeviceToDevice, b->stream) !=
                  hipSuccess) {
         return pt_fail(PT_EDEVICE, "pt_batch_tune: restore copy failed");
       }
@@ -345,7 +355,8 @@ std::string cache_key(const pt_batch* b, uint32_t flags) {
   std::vector<std::string> parts;
   for (const pt_job* j : b->jobs)
     parts.push_back(std::to_string(j->g.L) + "x" + std::to_string(j->g.NT) + "x" +
-                    std::to_string(j->g.S) + "x" + std::to_string(j->g.layout));
+                    std::to_string(j->g.S) + "x" + std::to_string(j->g.layout) +
+                    (j->track_walk ? "w" : ""));
   std::sort(parts.begin(), parts.end());
   std::string key = "gfx950/d" + std::to_string(b->d) + "/f" + std::to_string(flags) + "/";
   size_t i = 0;

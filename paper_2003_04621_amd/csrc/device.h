@@ -233,6 +233,39 @@ __device__ __forceinline__ uint32_t load_counter(const uint32_t* p) {
 }
 
 // ---------------------------------------------------------------------------
+// Replica walk in temperature space and its round-trip (tunnelling) time,
+// Sec. 2.3: the number of steps a configuration takes from the lowest
+// temperature to the highest and back.  Called by one thread per replica set
+// after exchange pass m (counted from 1; modulo 2^32) with the set's slots
+// `cold` and `hot` now at the lowest and highest temperature.  wk holds the
+// set's [NT][2] walk words: a label (0 = not yet at the lowest temperature,
+// 1 = going up, 2 = going down: reached the highest while going up) and the
+// pass at which the slot's current round trip began.  A slot labelled 2 that
+// is back at the lowest temperature ends a round trip of m - begin passes,
+// added to bin floor(log2 m) of the [32][3] sums `bins` (count, sum of
+// lengths, sum of squared lengths; atomically, as the two replica sets of a
+// sample may be walked at once), and begins the next one.
+// ---------------------------------------------------------------------------
+// wk is 8-byte aligned; cold != hot (N_T >= 2), so both slots' words are read
+// before either is written.
+__device__ __forceinline__ void walk_observe(int32_t* wk, uint64_t* bins, int cold, int hot,
+                                             uint32_t m) {
+  int2* wc = reinterpret_cast<int2*>(wk) + cold;
+  int32_t* wh = wk + 2 * hot;
+  const int2 c = *wc;
+  const int lab_hot = *wh;
+  if (c.x == 2) {
+    const uint64_t len = (uint32_t)(m - (uint32_t)c.y);
+    unsigned long long* b = reinterpret_cast<unsigned long long*>(bins) + 3 * (31 - __clz(m | 1u));
+    atomicAdd(b, 1ull);
+    atomicAdd(b + 1, (unsigned long long)len);
+    atomicAdd(b + 2, (unsigned long long)(len * len));
+  }
+  if (c.x != 1) *wc = make_int2(1, (int32_t)m);
+  if (lab_hot == 1) *wh = 2;
+}
+
+// ---------------------------------------------------------------------------
 // Word geometry.
 // ---------------------------------------------------------------------------
 struct WordNb {

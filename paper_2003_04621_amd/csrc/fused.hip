@@ -106,9 +106,13 @@ __device__ __forceinline__ void exchange_prepare(const FusedArgs& A, uint32_t* l
   }
 }
 
-// The pass itself, after exchange_prepare and a workgroup barrier.
+// The pass itself, after exchange_prepare and a workgroup barrier; with WALK
+// and `walk`, pass m (counted from 1) of the replica walk, with round trips
+// summed in LDS (`walk` is false where the job does not track the walk or
+// another workgroup of the sample keeps it).
+template <bool WALK>
 __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* lds, int c_lo,
-                                                  int nsets) {
+                                                  int nsets, uint32_t m, bool walk) {
   const Geo& g = A.g;
   const int NT = g.NT, tid = threadIdx.x, T = blockDim.x;
   const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
@@ -163,6 +167,9 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
     }
     so[NT - 1] = m0[cur];
     to[m0[cur]] = NT - 1;
+    if (WALK && walk)
+      walk_observe(reinterpret_cast<int32_t*>(lds + A.lay.walk) + 2 * c * NT,
+                   reinterpret_cast<uint64_t*>(lds + A.lay.trip), so[0], m0[cur], m);
   }
   __syncthreads();
 }
@@ -687,7 +694,17 @@ __device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_
 // state is written back, so the two sets of a sample may run in different
 // workgroups at the same time.
 // ---------------------------------------------------------------------------
-template <int D, bool HOU, bool MEAS>
+// Adds the round trips a workgroup summed in LDS during the launch to the
+// sample's totals (atomically: the sample's two replica sets may have run in
+// two workgroups).
+__device__ __forceinline__ void flush_trips(const FusedArgs& A, const uint32_t* lds, int s) {
+  const uint64_t* bl = reinterpret_cast<const uint64_t*>(lds + A.lay.trip);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(A.trips) + (size_t)s * 32 * 3;
+  for (int i = threadIdx.x; i < 32 * 3; i += blockDim.x)
+    if (bl[i]) atomicAdd(dst + i, (unsigned long long)bl[i]);
+}
+
+template <int D, bool HOU, bool MEAS, bool WALK>
 __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, int s, int c_lo, int nsets) {
   const Geo& g = A.g;
   const int T = blockDim.x, tid = threadIdx.x;
@@ -725,16 +742,22 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
   for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
   if (meas)
     for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
+  const bool walk = WALK && A.walk != nullptr;
+  int32_t* wkl = reinterpret_cast<int32_t*>(lds + A.lay.walk);
+  if (walk) {
+    for (int i = tid; i < 2 * nres; i += T) wkl[2 * slot0 + i] = A.walk[2 * lat0 + i];
+    for (int i = tid; i < 2 * 32 * 3; i += T) lds[A.lay.trip + i] = 0u;
+  }
   if (hou && tid == 0) lds[A.lay.hq] = 0u;
   const uint32_t t0 = A.ctr->t, u0 = A.ctr->u, v0 = A.ctr->v;
   __syncthreads();
 
   for (int step = 0; step < A.nmcs; ++step) {
-    const uint32_t t = t0 + (uint32_t)step;
-    exchange_prepare(A, lds, s, u0 + (uint32_t)step, c_lo, nsets);
+    const uint32_t t = t0 + (uint32_t)step, u = u0 + (uint32_t)step;
+    exchange_prepare(A, lds, s, u, c_lo, nsets);
     sweep_resident<D>(A, Jl, W, El, tosl, thrl, slot0, nres, s, t);
     if (hou) houdayer_resident<D>(A, lds, s, v0 + (uint32_t)step);
-    exchange_resident(A, lds, c_lo, nsets);
+    exchange_resident<WALK>(A, lds, c_lo, nsets, u + 1u, walk);
     if (meas) measure_resident(A, lds);
   }
 
@@ -753,6 +776,10 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
   for (int i = tid; i < nres; i += T) {
     A.sot[(size_t)s * 2 * NT + slot0 + i] = sotl[slot0 + i];
     A.tos[(size_t)s * 2 * NT + slot0 + i] = tosl[slot0 + i];
+  }
+  if (walk) {
+    for (int i = tid; i < 2 * nres; i += T) A.walk[2 * lat0 + i] = wkl[2 * slot0 + i];
+    flush_trips(A, lds, s);
   }
   if (meas)
     for (int i = tid; i < 8 * NT; i += T) A.mom[(size_t)s * NT * 8 + i] = mom[i];
@@ -839,7 +866,7 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
 
 // nmcs Monte Carlo steps (sweep, exchange, measurement) of part `part` of
 // split sample s.
-template <int D, bool MEAS>
+template <int D, bool MEAS, bool WALK>
 __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int s, int part,
                                           int* flag) {
   const Geo& g = A.g;
@@ -881,6 +908,13 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
   for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
   if (meas)
     for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
+  // part 0 keeps the sample's replica walk
+  const bool walk = WALK && A.walk != nullptr && part == 0;
+  int32_t* wkl = reinterpret_cast<int32_t*>(lds + A.lay.walk);
+  if (walk) {
+    for (int i = tid; i < 2 * nslot; i += T) wkl[i] = A.walk[(size_t)s * 2 * nslot + i];
+    for (int i = tid; i < 2 * 32 * 3; i += T) lds[A.lay.trip + i] = 0u;
+  }
   const uint32_t t0 = A.ctr->t, u0 = A.ctr->u;
   uint32_t* bar = A.bar + s;
   uint32_t* fault = A.bar + g.S;
@@ -889,8 +923,8 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
   __syncthreads();
 
   for (int step = 0; step < A.nmcs; ++step) {
-    const uint32_t t = t0 + (uint32_t)step;
-    exchange_prepare(A, lds, s, u0 + (uint32_t)step, 0, 2);
+    const uint32_t t = t0 + (uint32_t)step, u = u0 + (uint32_t)step;
+    exchange_prepare(A, lds, s, u, 0, 2);
     sweep_resident<D, true>(A, Jsrc, W, El, tosl, thrl, slot0, nres, s, t);
     // publish, meet, and take the sample-wide steps
     const int par = step & 1;
@@ -902,7 +936,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     if (!part_barrier(bar, (uint32_t)(A.parts * (step + 1)), fault, flag)) break;
     for (int i = tid; i < nslot; i += T) El[i] = Ex[par * nslot + i];
     __syncthreads();
-    exchange_resident(A, lds, 0, 2);
+    exchange_resident<WALK>(A, lds, 0, 2, u + 1u, walk);
     if (meas) measure_split(A, lds, part, snap + (size_t)par * nslot * W2);
   }
 
@@ -923,6 +957,10 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
       A.sot[(size_t)s * 2 * NT + i] = sotl[i];
       A.tos[(size_t)s * 2 * NT + i] = tosl[i];
     }
+  if (walk) {
+    for (int i = tid; i < 2 * nslot; i += T) A.walk[(size_t)s * 2 * nslot + i] = wkl[i];
+    flush_trips(A, lds, s);
+  }
   if (meas)
     for (int k = part; k < NT; k += A.parts)
       for (int i = tid; i < 8; i += T) A.mom[((size_t)s * NT + k) * 8 + i] = mom[k * 8 + i];
@@ -936,12 +974,20 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
 // keeps the register count, and so the number of resident wavefronts, of a
 // launch as low as its work allows.
 // ---------------------------------------------------------------------------
+// Wavefronts per SIMD the register allocation must allow.  The replica-walk
+// bookkeeping inside the step loop lifts the sweep + exchange (+ measurement)
+// kernels a few registers above the 80 that two 768-thread workgroups per CU
+// need, so those variants are held to 80 (about 1% slower than without the
+// walk); every other variant gets what a 1024-thread workgroup needs.
+template <int F>
+constexpr int kWavesPerSimd = ((F & kFeatWalk) && !(F & (kFeatHou | kFeatSplit))) ? 6 : 4;
+
 template <int D, int F>
-__global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jobs,
-                                                const BatchItem* __restrict__ items, int nitems,
-                                                uint32_t* queue) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<F>)))
+k_batch(const FusedArgs* __restrict__ jobs, const BatchItem* __restrict__ items, int nitems,
+        uint32_t* queue) {
   constexpr bool kHou = (F & kFeatHou) != 0, kMeas = (F & kFeatMeas) != 0;
-  constexpr bool kSplit = (F & kFeatSplit) != 0;
+  constexpr bool kSplit = (F & kFeatSplit) != 0, kWalk = (F & kFeatWalk) != 0;
   // 16-byte aligned: the moment words are updated with 64-bit LDS atomics,
   // which need naturally aligned addresses (the plan offsets are 8-byte
   // aligned relative to this base)
@@ -957,9 +1003,9 @@ __global__ void __launch_bounds__(1024) k_batch(const FusedArgs* __restrict__ jo
     const FusedArgs A = jobs[it.job];
     if (A.nmcs > 0) {
       if (kSplit && it.nsets == 0)
-        run_split<D, kMeas>(A, lds, it.sample, it.c_lo, &flag);
+        run_split<D, kMeas, kWalk>(A, lds, it.sample, it.c_lo, &flag);
       else
-        run_sample<D, kHou, kMeas>(A, lds, it.sample, it.c_lo, it.nsets);
+        run_sample<D, kHou, kMeas, kWalk>(A, lds, it.sample, it.c_lo, it.nsets);
     }
     __syncthreads();
   }
@@ -991,7 +1037,7 @@ __global__ void k_batch_advance(const FusedArgs* __restrict__ jobs, int njobs) {
 }
 
 // ---------------------------------------------------------------------------
-bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) {
+bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay, bool walk) {
   // LDS words per workgroup on gfx950 (160 KiB), less room for static LDS
   const size_t budget = (160 * 1024 - 512) / 4;
   size_t off = 0;
@@ -1013,6 +1059,8 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) 
   lay.qneg = take(g.NT, 1);
   lay.rpt = take(2 * g.NT, 1);
   lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
+  lay.walk = take(walk ? 2 * (size_t)g.nslot : 0, walk ? 2 : 1);
+  lay.trip = take(walk ? 2 * 32 * 3 : 0, walk ? 2 : 1);
   lay.PC = 0;
   lay.Qs = (int)off;
   lay.hq = (int)off;
@@ -1028,7 +1076,7 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay) 
   return off <= budget;
 }
 
-bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
+bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, bool walk) {
   const size_t budget = (160 * 1024 - 512) / 4;
   const size_t W2 = 2 * (size_t)g.NW, Jw = 2 * 2 * (size_t)g.d * g.NW;
   for (int jl = 1; jl >= 0; --jl) {
@@ -1037,6 +1085,7 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
     fixed += g.nslot + 3 * 2 * (size_t)g.NT + 4 * (size_t)g.NT;
     fixed = (fixed + 1) / 2 * 2 + 16 * (size_t)g.NT;
     fixed += g.NT + 2 * (size_t)g.NT + 2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32);
+    if (walk) fixed = (fixed + 1) / 2 * 2 + 2 * (size_t)g.nslot + 2 * 32 * 3;
     if (fixed >= budget) continue;
     const size_t rmax = std::min<size_t>((budget - fixed) / W2, (size_t)g.nslot);
     if (rmax < 1 || (jl && rmax < std::min(g.nslot, 8))) continue;
@@ -1063,6 +1112,8 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
     lay.qneg = take(g.NT, 1);
     lay.rpt = take(2 * g.NT, 1);
     lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
+    lay.walk = take(walk ? 2 * (size_t)g.nslot : 0, walk ? 2 : 1);
+    lay.trip = take(walk ? 2 * 32 * 3 : 0, walk ? 2 : 1);
     lay.PC = 0;
     lay.Qs = (int)off;
     lay.hq = (int)off;
@@ -1074,8 +1125,9 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds) {
 
 FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
                           int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
-                          const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
-                          int nmcs, bool hou, bool meas) {
+                          const uint32_t* thrpt, int M, int64_t* mom, int32_t* walk,
+                          uint64_t* trips, const DevCounters* ctr, int nmcs, bool hou,
+                          bool meas) {
   FusedArgs A;
   A.g = g;
   A.spins = spins;
@@ -1087,6 +1139,8 @@ FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, con
   A.thrpt = thrpt;
   A.M = M;
   A.mom = mom;
+  A.walk = walk;
+  A.trips = trips;
   A.ctr = ctr;
   A.nmcs = nmcs;
   A.hou = hou ? 1 : 0;
@@ -1117,8 +1171,8 @@ constexpr BatchKernel pick(int feat, std::integer_sequence<int, F...>) {
 }
 
 BatchKernel batch_kernel(int d, int feat) {
-  using All = std::make_integer_sequence<int, 8>;
-  return d == 3 ? pick<3>(feat & 7, All{}) : pick<2>(feat & 7, All{});
+  using All = std::make_integer_sequence<int, 16>;
+  return d == 3 ? pick<3>(feat & 15, All{}) : pick<2>(feat & 15, All{});
 }
 }  // namespace
 

@@ -28,6 +28,10 @@ struct pt_job {
   int M = 0;
   ptsg::DevCounters* ctr = nullptr;
   int64_t* mom = nullptr;    // [S][NT][8]
+  // replica walk, allocated only for jobs created with PT_TRACK_WALK
+  bool track_walk = false;
+  int32_t* walk = nullptr;   // [S][2NT][2]: replica-walk label, pass its round trip began
+  uint64_t* trips = nullptr; // [S][32][3]: round trips per log2 bin of the ending pass
   // fused-step LDS plans: both sets without / with Houdayer, one set
   ptsg::FusedLayout plan[3];
   bool fused_ok[3] = {false, false, false};
@@ -96,8 +100,9 @@ int batch_slots(const pt_batch* b);
 // replica sets do not fit one workgroup together, but a split plan exists),
 // and how many bytes that scratch takes.
 size_t split_scratch_bytes(const ptsg::Geo& g);
-// Device bytes a job of this shape allocates (an upper bound).
-size_t job_device_bytes(int S, int NT, int L, int d, int layout, const double* betas);
+// Device bytes a job of this shape allocates (an upper bound); `flags` as
+// pt_init_ex's (a layout, optionally with PT_TRACK_WALK).
+size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* betas);
 // Length of a row of the exchange threshold table.
 int pt_table_len(const double* betas, int NT, int d, long N);
 // pt_init_ex with explicit allocation hooks (NULL: hipMalloc / hipFree).

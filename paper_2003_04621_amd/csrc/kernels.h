@@ -26,9 +26,12 @@ hipError_t launch_sweep(const Geo& g, void* spins, const uint32_t* jw, int32_t* 
                         const int32_t* tos, const uint32_t* thr, DevCounters* ctr, int n,
                         hipStream_t st);
 
-// One replica-exchange pass numbered ctr->u.
+// One replica-exchange pass numbered ctr->u, followed by the replica-walk
+// bookkeeping of walk_observe (walk [S][2NT][2], trips [S][32][3]; both null
+// for a job that does not keep it).
 hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t* tos,
-                           const uint32_t* thrpt, int M, DevCounters* ctr, hipStream_t st);
+                           const uint32_t* thrpt, int M, int32_t* walk, uint64_t* trips,
+                           DevCounters* ctr, hipStream_t st);
 
 // One Houdayer pass numbered ctr->v.
 hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
@@ -45,9 +48,10 @@ hipError_t launch_advance(DevCounters* ctr, CounterStep step, hipStream_t st);
 // LDS word offsets of the fused Monte Carlo step kernel: configurations W,
 // couplings J, energies E, maps sot/tos (and the pre-pass copy sot0),
 // threshold rows, moments, overlap counts, exchange randoms and decision
-// matrix, and the Houdayer words Qs of PC wavefronts; `words` in all.
+// matrix, replica-walk words and the launch's round-trip sums (64-bit
+// aligned), and the Houdayer words Qs of PC wavefronts; `words` in all.
 struct FusedLayout {
-  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, Qs, PC, hq, words;
+  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, walk, trip, Qs, PC, hq, words;
 };
 
 // Everything one fused workgroup needs about a job, for nmcs steps.
@@ -62,6 +66,10 @@ struct FusedArgs {
   const uint32_t* thrpt;
   int M;
   int64_t* mom;
+  // replica walk (null unless the job tracks it): [S][2NT][2] label and pass
+  // the current round trip began; [S][32][3] round trips per log2 bin
+  int32_t* walk;
+  uint64_t* trips;
   const DevCounters* ctr;
   int nmcs, hou, meas;
   uint32_t magicNW;  // item / NW
@@ -89,21 +97,24 @@ constexpr int kMaxParts = 64;
 
 // Plans the LDS of a fused workgroup holding `nsets` replica sets of one
 // sample (`waves` wavefronts); false if it does not fit in 160 KiB.
-bool fused_plan(const Geo& g, bool houdayer, int nsets, int waves, FusedLayout& lay);
+bool fused_plan(const Geo& g, bool houdayer, int nsets, int waves, FusedLayout& lay,
+                bool walk = false);
 
 // Plans a split sample: the fewest parts (<= kMaxParts) whose R slots fit one
 // workgroup's LDS, with the couplings in LDS when that still leaves room for
 // min(2 N_T, 8) slots.  False if even one slot does not fit.
-bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds);
+bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, bool walk = false);
 
 FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
                           int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
-                          const uint32_t* thrpt, int M, int64_t* mom, const DevCounters* ctr,
-                          int nmcs, bool houdayer, bool measure);
+                          const uint32_t* thrpt, int M, int64_t* mom, int32_t* walk,
+                          uint64_t* trips, const DevCounters* ctr, int nmcs, bool houdayer,
+                          bool measure);
 
-// Kinds of work a batch launch holds; the launch runs the kernel compiled for
-// exactly that set.
-constexpr int kFeatHou = 1, kFeatMeas = 2, kFeatSplit = 4;
+// Kinds of work a batch launch holds (Houdayer moves, measurements, split
+// samples, jobs that track the replica walk); the launch runs the kernel
+// compiled for exactly that set.
+constexpr int kFeatHou = 1, kFeatMeas = 2, kFeatSplit = 4, kFeatWalk = 8;
 
 // Persistent batch: resets the queue, runs every item to its job's nmcs, then
 // advances each job's counters.  `jobs` and `items` are device arrays.

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -62,11 +63,12 @@ namespace {
 // The LDS plans of a job of geometry job->g (host only).
 void plan_job(pt_job* job) {
   const Geo& g = job->g;
-  job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0]);
-  job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1]);
-  job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2]);
+  const bool w = job->track_walk;
+  job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0], w);
+  job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1], w);
+  job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2], w);
   job->split_ok = !job->fused_ok[0] &&
-                  split_plan(g, job->split_lay, job->split_parts, job->split_R, job->split_jlds);
+                  split_plan(g, job->split_lay, job->split_parts, job->split_R, job->split_jlds, w);
 }
 
 // pt_get_plan's report for a planned job.
@@ -194,7 +196,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (samples < 1 || samples >= (1 << 28)) return pt_fail(PT_EINVAL, "samples must be in [1, 2^28)");
   if (replicas < 2 || replicas > 4096) return pt_fail(PT_EINVAL, "replicas must be in [2, 4096]");
-  if (flags != PT_LAYOUT_INT8 && flags != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown flags");
+  const uint32_t layout = flags & ~(uint32_t)PT_TRACK_WALK;
+  if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown flags");
   for (int k = 0; k < replicas; ++k) {
     if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
       return pt_fail(PT_EINVAL, "betas must be finite and > 0");
@@ -215,7 +218,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   job->free_fn = free_;
   job->alloc_ctx = ctx;
   job->stream = stream;
-  job->g = make_geo(samples, replicas, L, dim, (int)flags, seed);
+  job->track_walk = (flags & PT_TRACK_WALK) != 0;
+  job->g = make_geo(samples, replicas, L, dim, (int)layout, seed);
   const Geo& g = job->g;
 
   // Metropolis thresholds: x = 2m (m = 1..d), energy change 4m.
@@ -247,6 +251,10 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   job->thrpt = (uint32_t*)job->dalloc(sizeof(uint32_t) * thrpt.size());
   job->ctr = (DevCounters*)job->dalloc(sizeof(DevCounters));
   job->mom = (int64_t*)job->dalloc(sizeof(int64_t) * 8 * (size_t)samples * replicas);
+  if (job->track_walk) {
+    job->walk = (int32_t*)job->dalloc(sizeof(int32_t) * 2 * (size_t)nlat);
+    job->trips = (uint64_t*)job->dalloc(sizeof(uint64_t) * 32 * 3 * (size_t)samples);
+  }
   int8_t* J8 = (int8_t*)job->dalloc((size_t)ncoup);
   bool split_mem = true;
   if (job->split_ok) {
@@ -257,7 +265,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
     split_mem = job->Ex && job->snap && job->bar;
   }
   if (!job->spins || !job->jw || !job->E || !job->sot || !job->tos || !job->thr || !job->thrpt ||
-      !job->ctr || !job->mom || !J8 || !split_mem) {
+      !job->ctr || !job->mom || !J8 || !split_mem ||
+      (job->track_walk && (!job->walk || !job->trips))) {
     job->release();
     delete job;
     return pt_fail(PT_ENOMEM, "device allocation failed");
@@ -278,6 +287,10 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   step(hipMemcpyAsync(job->tos, ident.data(), maps, hipMemcpyHostToDevice, st));
   step(hipMemsetAsync(job->ctr, 0, sizeof(DevCounters), st));
   step(hipMemsetAsync(job->mom, 0, sizeof(int64_t) * 8 * (size_t)samples * replicas, st));
+  if (job->track_walk) {
+    step(hipMemsetAsync(job->walk, 0, sizeof(int32_t) * 2 * (size_t)nlat, st));
+    step(hipMemsetAsync(job->trips, 0, sizeof(uint64_t) * 32 * 3 * (size_t)samples, st));
+  }
   if (job->bar) step(hipMemsetAsync(job->bar, 0, sizeof(uint32_t) * ((size_t)samples + 1), st));
   step(launch_pack_couplings(g, J8, job->jw, st));
   step(launch_init_spins(g, job->spins, st));
@@ -324,13 +337,16 @@ size_t split_scratch_bytes(const Geo& g) {
   return sizeof(int32_t) * per + sizeof(uint32_t) * per * 2 * g.NW + sizeof(uint32_t) * (g.S + 1);
 }
 
-size_t job_device_bytes(int S, int NT, int L, int d, int layout, const double* betas) {
+size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* betas) {
+  const int layout = flags & ~(int)PT_TRACK_WALK;
+  const bool walk = (flags & PT_TRACK_WALK) != 0;
   const size_t N = (d == 3) ? (size_t)L * L * L : (size_t)L * L;
   const size_t NW = N / L / fields_per_word(L);
   const size_t lat = (size_t)S * 2 * NT;
   const size_t spins = layout == PT_LAYOUT_PACKED ? lat * 2 * NW * 4 : lat * N;
   const size_t jw = (size_t)S * 2 * 2 * d * NW * 4;
   const size_t small = sizeof(int32_t) * (lat + 4 * (size_t)S * NT) + sizeof(int64_t) * 8 * S * NT +
+                       (walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)S : 0) +
                        sizeof(uint32_t) * (size_t)NT * (4 + pt_table_len(betas, NT, d, (long)N)) + 4096;
   return spins + jw + (size_t)S * d * N + small + split_scratch_bytes(make_geo(S, NT, L, d, layout, 0));
 }
@@ -374,8 +390,8 @@ PT_API int pt_sweep(pt_job* job, int32_t n) {
 
 PT_API int pt_exchange(pt_job* job) {
   if (int rc = check_job(job)) return rc;
-  PT_HIP(job, launch_exchange(job->g, job->E, job->sot, job->tos, job->thrpt, job->M, job->ctr,
-                              job->stream));
+  PT_HIP(job, launch_exchange(job->g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
+                              job->trips, job->ctr, job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 1, 0, 0}, job->stream));
   return PT_OK;
 }
@@ -424,7 +440,8 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   for (int i = 0; i < n; ++i) {
     PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, st));
     if (hou) PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
-    PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->ctr, st));
+    PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
+                                job->trips, job->ctr, st));
     if (meas) PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->ctr, st));
     PT_HIP(job, launch_advance(job->ctr, CounterStep{1, 1, hou ? 1u : 0u, meas ? 1u : 0u}, st));
   }
@@ -445,12 +462,13 @@ PT_API int pt_plan_query(int32_t dim, int32_t L, int32_t replicas, uint32_t flag
   if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (replicas < 2) return pt_fail(PT_EINVAL, "replicas must be >= 2");
-  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | PT_TRACK_WALK))
     return pt_fail(PT_EINVAL, "unknown flags");
   pt_job job;
   job.g = make_geo(1, replicas, L, dim, PT_LAYOUT_INT8, 0);
+  job.track_walk = (flags & PT_TRACK_WALK) != 0;
   plan_job(&job);
-  plan_report(&job, flags, out4);
+  plan_report(&job, flags & ~(uint32_t)PT_TRACK_WALK, out4);
   return PT_OK;
 }
 
@@ -460,7 +478,8 @@ PT_API int pt_job_bytes(int32_t samples, int32_t replicas, int32_t L, int32_t di
   if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (samples < 1 || replicas < 2) return pt_fail(PT_EINVAL, "need samples >= 1 and replicas >= 2");
-  if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown layout");
+  const uint32_t lay = layout & ~(uint32_t)PT_TRACK_WALK;
+  if (lay != PT_LAYOUT_INT8 && lay != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown layout");
   for (int k = 0; k < replicas; ++k)
     if (!(betas[k] > 0.0) || (k > 0 && !(betas[k] < betas[k - 1])))
       return pt_fail(PT_EINVAL, "betas must be > 0 and strictly decreasing");
@@ -561,6 +580,74 @@ PT_API int pt_get_moments(pt_job* job, int64_t* out) {
   return PT_OK;
 }
 
+PT_API int pt_get_walk(pt_job* job, int32_t* label, uint32_t* begin, uint64_t* trips) {
+  if (int rc = check_job(job)) return rc;
+  if (!job->track_walk) return pt_fail(PT_EINVAL, "the job was created without PT_TRACK_WALK");
+  if (int rc = check_fault(job)) return rc;
+  const Geo& g = job->g;
+  const size_t lat = (size_t)g.S * g.nslot;
+  if (label || begin) {
+    std::vector<int32_t> w(2 * lat);
+    PT_HIP(job, hipMemcpyAsync(w.data(), job->walk, sizeof(int32_t) * w.size(), hipMemcpyDeviceToHost,
+                               job->stream));
+    PT_HIP(job, hipStreamSynchronize(job->stream));
+    for (size_t i = 0; i < lat; ++i) {
+      if (label) label[i] = w[2 * i];
+      if (begin) begin[i] = (uint32_t)w[2 * i + 1];
+    }
+  }
+  if (trips) {
+    PT_HIP(job, hipMemcpyAsync(trips, job->trips, sizeof(uint64_t) * 32 * 3 * (size_t)g.S,
+                               hipMemcpyDeviceToHost, job->stream));
+    PT_HIP(job, hipStreamSynchronize(job->stream));
+  }
+  return PT_OK;
+}
+
+PT_API int pt_tunnel_summary(const uint64_t* trips, int32_t rows, uint64_t passes, double* tau_b,
+                             double* err_b, double* tau, int32_t* equilibrated) {
+  if (!trips || rows < 1) return pt_fail(PT_EINVAL, "need one or more rows of round-trip bins");
+  // exact pooled sums per bin: count, sum of lengths, sum of squared lengths
+  unsigned __int128 C[32] = {}, D[32] = {}, Q[32] = {};
+  for (int32_t r = 0; r < rows; ++r)
+    for (int b = 0; b < 32; ++b) {
+      const uint64_t* t = trips + ((size_t)r * 32 + b) * 3;
+      C[b] += t[0];
+      D[b] += t[1];
+      Q[b] += t[2];
+    }
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  double mean[32], se[32];
+  unsigned __int128 Ct = 0, Dt = 0;
+  for (int b = 0; b < 32; ++b) {
+    Ct += C[b];
+    Dt += D[b];
+    mean[b] = C[b] ? (double)D[b] / (double)C[b] : nan;
+    se[b] = nan;
+    if (C[b] > 1) {
+      // C Q - D^2 >= 0 (Cauchy-Schwarz), exact in 128 bits while C Q < 2^128
+      const unsigned __int128 num = C[b] * Q[b] - D[b] * D[b];
+      const double c = (double)C[b];
+      se[b] = std::sqrt((double)num / (c * c * (double)(C[b] - 1)));
+    }
+    if (tau_b) tau_b[b] = mean[b];
+    if (err_b) err_b[b] = se[b];
+  }
+  if (tau) *tau = Ct ? (double)Dt / (double)Ct : nan;
+  if (equilibrated) {
+    // the last bin b complete after `passes` passes: 2^(b+1) - 1 <= passes
+    int top = -1;
+    while (top < 31 && ((uint64_t)2 << (top + 1)) - 1 <= passes) ++top;
+    int ok = top >= 2;
+    for (int b = top - 2; ok && b <= top; ++b) ok = C[b] > 1;
+    for (int i = top - 2; ok && i <= top; ++i)
+      for (int j = i + 1; ok && j <= top; ++j)
+        ok = std::fabs(mean[i] - mean[j]) <= 2.0 * std::sqrt(se[i] * se[i] + se[j] * se[j]);
+    *equilibrated = ok;
+  }
+  return PT_OK;
+}
+
 PT_API int pt_observables(pt_job* job, double* per_sample, double* disorder, int64_t* n_meas) {
   if (int rc = check_job(job)) return rc;
   if (int rc = check_fault(job)) return rc;
@@ -631,7 +718,8 @@ size_t state_size(const pt_job* job) {
   const size_t lat = (size_t)g.S * g.nslot;
   return sizeof(StateHeader) + job->spin_bytes() + sizeof(int32_t) * lat +
          2 * sizeof(int32_t) * (size_t)g.S * 2 * g.NT + sizeof(DevCounters) +
-         sizeof(int64_t) * 8 * (size_t)g.S * g.NT;
+         sizeof(int64_t) * 8 * (size_t)g.S * g.NT +
+         (job->track_walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)g.S : 0);
 }
 }  // namespace
 
@@ -647,7 +735,8 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   if (*len < need) return pt_fail(PT_EINVAL, "state buffer too small");
   const Geo& g = job->g;
   char* p = static_cast<char*>(buf);
-  StateHeader h{kStateMagic, g.S, g.NT, g.L, g.d, g.layout, 0, (uint64_t)job->spin_bytes()};
+  StateHeader h{kStateMagic, g.S, g.NT, g.L, g.d, g.layout, job->track_walk ? 1 : 0,
+                (uint64_t)job->spin_bytes()};
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
   const size_t lat = (size_t)g.S * g.nslot, maps = sizeof(int32_t) * (size_t)g.S * 2 * g.NT;
@@ -664,6 +753,13 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   p += sizeof(DevCounters);
   PT_HIP(job, hipMemcpyAsync(p, job->mom, sizeof(int64_t) * 8 * (size_t)g.S * g.NT,
                              hipMemcpyDeviceToHost, st));
+  p += sizeof(int64_t) * 8 * (size_t)g.S * g.NT;
+  if (job->track_walk) {
+    PT_HIP(job, hipMemcpyAsync(p, job->walk, sizeof(int32_t) * 2 * lat, hipMemcpyDeviceToHost, st));
+    p += sizeof(int32_t) * 2 * lat;
+    PT_HIP(job, hipMemcpyAsync(p, job->trips, sizeof(uint64_t) * 32 * 3 * (size_t)g.S,
+                               hipMemcpyDeviceToHost, st));
+  }
   PT_HIP(job, hipStreamSynchronize(st));
   *len = need;
   return PT_OK;
@@ -677,7 +773,8 @@ PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (h.magic != kStateMagic || h.S != g.S || h.NT != g.NT || h.L != g.L || h.d != g.d ||
-      h.layout != g.layout || h.spin_bytes != job->spin_bytes())
+      h.layout != g.layout || h.pad != (job->track_walk ? 1 : 0) ||
+      h.spin_bytes != job->spin_bytes())
     return pt_fail(PT_EINVAL, "state was taken from a job of another shape or layout");
   const char* p = static_cast<const char*>(buf) + sizeof(h);
   const size_t lat = (size_t)g.S * g.nslot, maps = sizeof(int32_t) * (size_t)g.S * 2 * g.NT;
@@ -694,6 +791,13 @@ PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
   p += sizeof(DevCounters);
   PT_HIP(job, hipMemcpyAsync(job->mom, p, sizeof(int64_t) * 8 * (size_t)g.S * g.NT,
                              hipMemcpyHostToDevice, st));
+  p += sizeof(int64_t) * 8 * (size_t)g.S * g.NT;
+  if (job->track_walk) {
+    PT_HIP(job, hipMemcpyAsync(job->walk, p, sizeof(int32_t) * 2 * lat, hipMemcpyHostToDevice, st));
+    p += sizeof(int32_t) * 2 * lat;
+    PT_HIP(job, hipMemcpyAsync(job->trips, p, sizeof(uint64_t) * 32 * 3 * (size_t)g.S,
+                               hipMemcpyHostToDevice, st));
+  }
   PT_HIP(job, hipStreamSynchronize(st));
   return PT_OK;
 }

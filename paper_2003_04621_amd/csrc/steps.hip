@@ -169,10 +169,12 @@ hipError_t launch_energy(const Geo& g, const void* spins, const uint32_t* jw, in
 }
 
 // ---------------------------------------------------------------------------
-// replica exchange, one lane per (sample, replica set); ascending k
+// replica exchange, one lane per (sample, replica set); ascending k; then
+// the set's replica-walk bookkeeping if the job keeps it (walk not null)
 // ---------------------------------------------------------------------------
 __global__ void k_exchange(Geo g, const int32_t* __restrict__ E, int32_t* __restrict__ sot,
                            int32_t* __restrict__ tos, const uint32_t* __restrict__ thrpt, int M,
+                           int32_t* __restrict__ walk, uint64_t* __restrict__ trips,
                            DevCounters* ctr) {
   const uint32_t u = load_counter(&ctr->u);
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -203,14 +205,18 @@ __global__ void k_exchange(Geo g, const int32_t* __restrict__ E, int32_t* __rest
         a = b;
       }
     }
+    if (walk)
+      walk_observe(walk + ((size_t)s * g.nslot + (size_t)c * g.NT) * 2, trips + (size_t)s * 32 * 3,
+                   so[0], a, u + 1u);
   }
 }
 
 hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t* tos,
-                           const uint32_t* thrpt, int M, DevCounters* ctr, hipStream_t st) {
+                           const uint32_t* thrpt, int M, int32_t* walk, uint64_t* trips,
+                           DevCounters* ctr, hipStream_t st) {
   const long lanes = (long)g.S * 2;
   hipLaunchKernelGGL(k_exchange, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, g, E, sot,
-                     tos, thrpt, M, ctr);
+                     tos, thrpt, M, walk, trips, ctr);
   return hipGetLastError();
 }
 

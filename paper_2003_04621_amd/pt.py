@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libptsg.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
 PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
+PT_TRACK_WALK = 0x10
 PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE"}
@@ -27,7 +28,8 @@ _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVIC
 EXPORTS = [
     "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_measure", "pt_mcs",
     "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
-    "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_state", "pt_set_state",
+    "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_walk", "pt_tunnel_summary",
+    "pt_get_state", "pt_set_state",
     "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
     "pt_batch_get_config", "pt_batch_set_config", "pt_batch_launch_shape", "pt_batch_destroy",
@@ -76,6 +78,7 @@ def lib():
             "pt_job_bytes": [I32, I32, I32, I32, U32, P, P], "pt_observables": [P, P, P, P], "pt_destroy": [P],
             "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
             "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
+            "pt_get_walk": [P, P, P, P], "pt_tunnel_summary": [P, I32, U64, P, P, P, P],
             "pt_get_state": [P, P, C.POINTER(C.c_size_t)], "pt_set_state": [P, P, C.c_size_t],
             "pt_set_stream": [P, P], "pt_set_allocator": [_ALLOC, _FREE, P],
             "pt_batch_create": [P, I32, C.POINTER(P)], "pt_batch_set_stream": [P, P],
@@ -167,9 +170,10 @@ def _destroy_live_jobs():
 class Job:
     """Owning handle of a pt_job plus its shape."""
 
-    def __init__(self, handle, samples, replicas, L, dim, layout):
+    def __init__(self, handle, samples, replicas, L, dim, layout, walk=False):
         self.h = handle
         self.S, self.NT, self.L, self.d, self.layout = samples, replicas, L, dim, layout
+        self.walk = bool(walk)
         self.N = L ** dim
         _live_jobs.add(self)
 
@@ -183,9 +187,10 @@ class Job:
 
 
 def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_INT8,
-            stream=None) -> Job:
+            stream=None, walk=False) -> Job:
     """Creates a job; `stream` is a torch.cuda.Stream, a raw hipStream_t int,
-    or None for torch's current stream (torch memory hooks are installed)."""
+    or None for torch's current stream (torch memory hooks are installed);
+    `walk` keeps the replica walk and its round trips (PT_TRACK_WALK)."""
     import torch
     if _hooks is None:
         use_torch_memory()
@@ -197,8 +202,9 @@ def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_
         raise PTError(PT_EINVAL, "couplings must have samples*dim*L^dim entries")
     h = C.c_void_p()
     _check(lib().pt_init_ex(C.byref(h), int(samples), int(replicas), int(L), int(dim), _p(J),
-                            _p(b), C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(layout)))
-    job = Job(h, int(samples), int(replicas), int(L), int(dim), int(layout))
+                            _p(b), C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
+                            int(layout) | (PT_TRACK_WALK if walk else 0)))
+    job = Job(h, int(samples), int(replicas), int(L), int(dim), int(layout), walk)
     if stream is None:
         stream = torch.cuda.current_stream()
     pt_set_stream(job, stream)
@@ -246,18 +252,20 @@ def pt_get_plan(job: Job, houdayer=False, measure=False, plain=False) -> dict:
 
 
 def pt_plan_query(dim: int, L: int, replicas: int, houdayer=False, measure=False,
-                  plain=False) -> dict:
+                  plain=False, walk=False) -> dict:
     """pt_get_plan's report for a job of this shape, without creating it
     (host only)."""
     flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
-             | (PT_MCS_PLAIN if plain else 0))
+             | (PT_MCS_PLAIN if plain else 0) | (PT_TRACK_WALK if walk else 0))
     out = np.zeros(4, np.int32)
     _check(lib().pt_plan_query(int(dim), int(L), int(replicas), flags, _p(out)))
     return dict(mode=int(out[0]), parts=int(out[1]), per_part=int(out[2]), lds_bytes=int(out[3]))
 
 
-def pt_job_bytes(samples: int, replicas: int, L: int, dim: int, betas, layout: int = PT_LAYOUT_INT8) -> int:
+def pt_job_bytes(samples: int, replicas: int, L: int, dim: int, betas, layout: int = PT_LAYOUT_INT8,
+                 walk: bool = False) -> int:
     """Upper bound of the device bytes of a job of this shape (host only)."""
+    layout = int(layout) | (PT_TRACK_WALK if walk else 0)
     b = np.ascontiguousarray(betas, dtype=np.float64)
     if b.size != replicas:
         raise PTError(PT_EINVAL, "betas must have `replicas` entries")
@@ -319,6 +327,28 @@ def pt_get_moments(job: Job) -> dict:
     d = {n: out[:, :, i].copy() for i, n in enumerate(names)}
     d["Q4"] = out[:, :, 5:7].view(np.uint64).copy()
     return d
+
+
+def pt_get_walk(job: Job):
+    """(label [S][2NT] int32, begin [S][2NT] uint32, trips [S][32][3] uint64)."""
+    lab = np.zeros((job.S, 2 * job.NT), np.int32)
+    beg = np.zeros((job.S, 2 * job.NT), np.uint32)
+    trips = np.zeros((job.S, 32, 3), np.uint64)
+    _check(lib().pt_get_walk(job.h, _p(lab), _p(beg), _p(trips)))
+    return lab, beg, trips
+
+
+def pt_tunnel_summary(trips, passes: int):
+    """(tau_b [32], err_b [32], tau, equilibrated) from round-trip bins
+    [..., 32, 3], every leading index pooled."""
+    t = np.ascontiguousarray(trips, dtype=np.uint64).reshape(-1, 32, 3)
+    tau_b = np.zeros(32, np.float64)
+    err_b = np.zeros(32, np.float64)
+    tau = np.zeros(1, np.float64)
+    eq = np.zeros(1, np.int32)
+    _check(lib().pt_tunnel_summary(_p(t), t.shape[0], int(passes), _p(tau_b), _p(err_b),
+                                   _p(tau), _p(eq)))
+    return tau_b, err_b, float(tau[0]), int(eq[0])
 
 
 def pt_get_state(job: Job) -> bytes:

@@ -28,7 +28,8 @@ def say(*a):
 def state(pt, job):
     return (pt.pt_get_spins(job), pt.pt_get_energies(job), *pt.pt_get_maps(job),
             tuple(sorted(pt.pt_get_counters(job).items())),
-            {k: np.asarray(v).copy() for k, v in pt.pt_get_moments(job).items()})
+            {k: np.asarray(v).copy() for k, v in pt.pt_get_moments(job).items()},
+            pt.pt_get_walk(job) if job.walk else ())
 
 
 def same_state(a, b):
@@ -36,6 +37,8 @@ def same_state(a, b):
         if not (np.asarray(x) == np.asarray(y)).all():
             return False
     if a[4] != b[4]:
+        return False
+    if not all((x == y).all() for x, y in zip(a[6], b[6])):
         return False
     return all((a[5][k] == b[5][k]).all() for k in a[5])
 
@@ -49,6 +52,9 @@ def matches_oracle(pt, job, ref):
     gm, rm = pt.pt_get_moments(job), ref.moments()
     for k in rm:
         assert (np.asarray(gm[k]) == np.asarray(rm[k]).astype(np.asarray(gm[k]).dtype)).all(), k
+    if job.walk:
+        for x, y in zip(pt.pt_get_walk(job), ref.walk()):
+            assert (x == y).all()
 
 
 SHAPES_3D = [  # (L, samples, replicas, layout)

@@ -35,6 +35,9 @@ def compare(pt, job, ref, what=""):
     gm, rm = pt.pt_get_moments(job), ref.moments()
     for k in rm:
         assert (np.asarray(gm[k]) == np.asarray(rm[k]).astype(np.asarray(gm[k]).dtype)).all(), (what, k)
+    if job.walk:
+        for x, y, name in zip(pt.pt_get_walk(job), ref.walk(), ("labels", "begins", "trips")):
+            assert (x == y).all(), f"{what}: replica walk {name} differ"
 
 
 def compare_observables(pt, job, ref):
@@ -55,11 +58,12 @@ CASES = [
 
 @pytest.mark.parametrize("d,L,S,NT,layout", CASES)
 def test_mcs_parity(pt, d, L, S, NT, layout):
-    say(f"case d={d} L={L} S={S} NT={NT} layout={layout}")
+    walk = CASES.index((d, L, S, NT, layout)) % 2 == 1  # every other case keeps the walk
+    say(f"case d={d} L={L} S={S} NT={NT} layout={layout} walk={walk}")
     J = W.couplings_pm_j(S, L, d, 100 + L)
     betas = W.geometric_betas(0.5, 2.5, NT)
     seed = 0x1234_5678_9ABC + L
-    job = pt.pt_init(S, NT, L, d, J, betas, seed, layout=layout)
+    job = pt.pt_init(S, NT, L, d, J, betas, seed, layout=layout, walk=walk)
     ref = oracle.OracleJob(S, NT, L, d, J, betas, seed)
     compare(pt, job, ref, "init")
     pt.pt_sweep(job, 1)
@@ -179,7 +183,7 @@ def test_full_size_3d_l16_sampled(pt):
     wl = W.workload("3d_l16")
     say(f"case {wl.name} S={wl.samples} NT={wl.replicas} L={wl.L}")
     J = wl.couplings()
-    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed)
+    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed, walk=True)
     pt.pt_mcs(job, 12, measure=True)
     picks = [0, 517, wl.samples - 1]
     ref = oracle.OracleJob(len(picks), wl.replicas, wl.L, wl.dim, J[picks], wl.betas, wl.seed,
@@ -192,6 +196,8 @@ def test_full_size_3d_l16_sampled(pt):
     gm, rm = pt.pt_get_moments(job), ref.moments()
     for k in rm:
         assert (np.asarray(gm[k])[picks] == np.asarray(rm[k]).astype(np.asarray(gm[k]).dtype)).all(), k
+    for x, y in zip(pt.pt_get_walk(job), ref.walk()):
+        assert (x[picks] == y).all()
     ps, _, n = pt.pt_observables(job)
     rps, _, rn = ref.observables()
     assert n == rn == 12
@@ -202,7 +208,7 @@ def test_full_size_2d_l64_houdayer_sampled(pt):
     wl = W.workload("2d_l64")
     say(f"case {wl.name} S={wl.samples} NT={wl.replicas} L={wl.L}")
     J = wl.couplings()
-    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed)
+    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed, walk=True)
     pt.pt_mcs(job, 6, houdayer=True, measure=True)
     picks = [3, wl.samples - 2]
     ref = oracle.OracleJob(len(picks), wl.replicas, wl.L, wl.dim, J[picks], wl.betas, wl.seed,
@@ -212,6 +218,8 @@ def test_full_size_2d_l64_houdayer_sampled(pt):
     assert (pt.pt_get_energies(job)[picks] == ref.energies()).all()
     for a, b in zip(pt.pt_get_maps(job), ref.maps()):
         assert (a[picks] == b).all()
+    for x, y in zip(pt.pt_get_walk(job), ref.walk()):
+        assert (x[picks] == y).all()
 
 
 @pytest.mark.parametrize("layout", [0, 1])

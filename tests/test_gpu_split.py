@@ -33,6 +33,9 @@ def matches_oracle(pt, job, ref, what):
     gm, rm = pt.pt_get_moments(job), ref.moments()
     for k in rm:
         assert (np.asarray(gm[k]) == np.asarray(rm[k]).astype(np.asarray(gm[k]).dtype)).all(), (what, k)
+    if job.walk:
+        for x, y in zip(pt.pt_get_walk(job), ref.walk()):
+            assert (x == y).all(), f"{what}: replica walk"
 
 
 SPLIT_CASES = [
@@ -46,18 +49,18 @@ SPLIT_CASES = [
 ]
 
 
-def _job(pt, d, L, S, NT, layout, seed0):
+def _job(pt, d, L, S, NT, layout, seed0, walk=False):
     J = W.couplings_pm_j(S, L, d, seed0 + L)
     b = W.geometric_betas(0.9, 2.0, NT) if d == 3 else W.geometric_betas(0.6, 5.0, NT)
     seed = 0xABCD_0000 + 31 * L + NT
-    return (pt.pt_init(S, NT, L, d, J, b, seed, layout=layout),
+    return (pt.pt_init(S, NT, L, d, J, b, seed, layout=layout, walk=walk),
             oracle.OracleJob(S, NT, L, d, J, b, seed))
 
 
 @pytest.mark.parametrize("d,L,S,NT,layout,parts", SPLIT_CASES)
 def test_split_matches_oracle(pt, d, L, S, NT, layout, parts):
     say(f"split case d={d} L={L} S={S} NT={NT} layout={layout}")
-    job, ref = _job(pt, d, L, S, NT, layout, 300)
+    job, ref = _job(pt, d, L, S, NT, layout, 300, walk=layout == 0)
     plan = pt.pt_get_plan(job, measure=True)
     assert plan["mode"] == 3 and plan["parts"] == parts, plan
     assert plan["lds_bytes"] <= 160 * 1024

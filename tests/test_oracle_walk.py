@@ -20,33 +20,12 @@ import pytest
 
 import oracle
 from paper_2003_04621_amd import workloads
+from walk_forms import expected_rotation, rescan
 
 
 def _job(S, NT, L, d, betas, seed=5):
     J = workloads.couplings_pm_j(S, L, d, seed=123)
     return oracle.OracleJob(S, NT, L, d, J, betas, seed)
-
-
-def _expected_rotation(NT, P):
-    """Closed form of the all-accepted ascending pass: slot j of a set sits at
-    temperature (j - m) mod NT after pass m.  Returns per-slot labels, trip
-    beginnings and the bins of one set."""
-    lab = np.zeros(NT, np.int32)
-    beg = np.zeros(NT, np.uint32)
-    bins = np.zeros((32, 3), np.uint64)
-    for j in range(NT):
-        first = j if j >= 1 else NT  # first pass at the lowest temperature
-        if P < first:
-            continue
-        m = first + NT
-        while m <= P:  # every later arrival at the lowest ends a trip of NT
-            b = m.bit_length() - 1
-            bins[b] += np.array([1, NT, NT * NT], np.uint64)
-            m += NT
-        last_cold = first + ((P - first) // NT) * NT
-        beg[j] = last_cold
-        lab[j] = 1 if (j - P) % NT == 0 else 2  # the pass after a cold visit is hot
-    return lab, beg, bins
 
 
 @pytest.mark.parametrize("NT,P", [(2, 37), (3, 64), (5, 100), (8, 257)])
@@ -60,7 +39,7 @@ def test_walk_rotation_closed_form(NT, P):
         for c in range(2):
             assert [int(x) for x in tos[s, c]] == [(j - P) % NT for j in range(NT)]
     lab, beg, trips = job.walk()
-    elab, ebeg, ebins = _expected_rotation(NT, P)
+    elab, ebeg, ebins = expected_rotation(NT, P)
     for s in range(S):
         for c in range(2):
             np.testing.assert_array_equal(lab[s, c * NT:(c + 1) * NT], elab)
@@ -71,27 +50,6 @@ def test_walk_rotation_closed_form(NT, P):
     filled = ebins[:, 0] > 0
     assert np.all(tau_b[filled] == NT)
     assert np.all(np.isnan(tau_b[~filled]))
-
-
-def _rescan(history, NT):
-    """Round trips from one slot's temperatures after passes 1..P: a trip
-    starts at the first arrival at the lowest temperature and at every arrival
-    there that follows a visit to the highest since the previous start."""
-    starts = []
-    hot_since = False
-    for m, k in enumerate(history, start=1):
-        if k == NT - 1 and starts:
-            hot_since = True
-        if k == 0 and (not starts or hot_since):
-            starts.append(m)
-            hot_since = False
-    bins = np.zeros((32, 3), np.uint64)
-    for a, b in zip(starts[:-1], starts[1:]):
-        n = b - a
-        bins[b.bit_length() - 1] += np.array([1, n, n * n], np.uint64)
-    if not starts:
-        return 0, 0, bins
-    return (2 if hot_since else 1), starts[-1], bins
 
 
 @pytest.mark.parametrize("d,L,NT,P,hou", [(2, 4, 5, 300, False), (3, 4, 6, 200, True),
@@ -110,7 +68,7 @@ def test_walk_matches_offline_rescan(d, L, NT, P, hou):
         want = np.zeros((32, 3), np.uint64)
         for c in range(2):
             for j in range(NT):
-                l, b, bins = _rescan([int(x) for x in hist[:, s, c, j]], NT)
+                l, b, bins = rescan([int(x) for x in hist[:, s, c, j]], NT)
                 assert lab[s, c * NT + j] == l
                 if l:
                     assert beg[s, c * NT + j] == b
@@ -172,7 +130,6 @@ def test_tunnel_summary_equilibration_flag():
     assert oracle.tunnel_summary(drift, 63)[3] == 0
     thin = bins({3: [4, 6], 4: [5], 5: [4, 5, 6, 7]})  # one trip in bin 4
     assert oracle.tunnel_summary(thin, 63)[3] == 0
-    exact = bins({0: [], 1: [3, 3], 2: [3, 3, 3]})  # zero errors, equal means
-    exact[0] = [0, 0, 0]
+    # zero errors and equal means agree; an empty bin among the last three does not
     assert oracle.tunnel_summary(bins({0: [3, 3], 1: [3, 3], 2: [3, 3, 3]}), 7)[3] == 1
-    assert oracle.tunnel_summary(exact, 7)[3] == 0  # bin 0 empty
+    assert oracle.tunnel_summary(bins({1: [3, 3], 2: [3, 3, 3]}), 7)[3] == 0

@@ -53,6 +53,11 @@ def test_plain_flag_and_known_shapes(lib):
     p = pt.pt_plan_query(3, 16, 32, measure=True)
     assert p == {"mode": 0, "parts": 1, "per_part": 64, "lds_bytes": 40056}
     assert 4 * p["lds_bytes"] <= 160 * 1024
+    # keeping the replica walk adds its words (2 per slot) and the launch's
+    # round-trip sums (32 x 3 64-bit)
+    w = pt.pt_plan_query(3, 16, 32, measure=True, walk=True)
+    assert w == {"mode": 0, "parts": 1, "per_part": 64,
+                 "lds_bytes": 40056 + 4 * 2 * 64 + 8 * 32 * 3}
     p = pt.pt_plan_query(3, 48, 48, measure=True)
     assert p["mode"] == 3 and p["parts"] == 12 and p["per_part"] == 8
     assert pt.pt_plan_query(2, 64, 24, houdayer=True, measure=True)["mode"] == 1
@@ -73,6 +78,8 @@ def test_job_bytes(lib):
     assert many >= 1000 * 64 * 4096 and many <= 1000 * one
     packed = pt.pt_job_bytes(1000, 32, 16, 3, b, layout=pt.PT_LAYOUT_PACKED)
     assert packed < many
+    # the replica walk: two words per slot and 32 x 3 64-bit sums per sample
+    assert pt.pt_job_bytes(1000, 32, 16, 3, b, walk=True) == many + 1000 * (64 * 8 + 768)
     # a split plan brings its scratch: published energies and configurations
     b48 = 1.0 / np.linspace(0.9, 2.0, 48)
     assert pt.pt_job_bytes(1, 48, 48, 3, b48) > 96 * 48 ** 3 + 2 * 96 * 2 * 2304 * 4
