@@ -42,19 +42,18 @@ struct Ctr4 {
 };
 
 // Three-input bitwise function with truth table TT (gfx950 v_bitop3_b32):
-// result bit = TT bit number (a_bit * 4 + b_bit * 2 + c_bit).
+// result bit = TT bit number (a_bit * 4 + b_bit * 2 + c_bit).  Through the
+// compiler builtin rather than inline assembly, so that the scheduler sees the
+// instruction: it can then fill the wait a 64-bit multiply needs after a VALU
+// write of its operand with independent work instead of an s_nop.
 template <unsigned TT>
 __device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:%4" : "=v"(r) : "v"(a), "v"(b), "v"(c), "i"(TT));
-  return r;
+  return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
 }
-// The same with a wave-uniform third operand.
+// The same, for a wave-uniform third operand.
 template <unsigned TT>
 __device__ __forceinline__ uint32_t bop3s(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:%4" : "=v"(r) : "v"(a), "v"(b), "s"(c), "i"(TT));
-  return r;
+  return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
 }
 constexpr unsigned kXor3 = 0x96;   // a ^ b ^ c
 constexpr unsigned kMaj3 = 0xE8;   // majority(a, b, c)

@@ -974,13 +974,14 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
 // keeps the register count, and so the number of resident wavefronts, of a
 // launch as low as its work allows.
 // ---------------------------------------------------------------------------
-// Wavefronts per SIMD the register allocation must allow.  The replica-walk
-// bookkeeping inside the step loop lifts the sweep + exchange (+ measurement)
-// kernels a few registers above the 80 that two 768-thread workgroups per CU
-// need, so those variants are held to 80 (about 1% slower than without the
-// walk); every other variant gets what a 1024-thread workgroup needs.
+// Wavefronts per SIMD the register allocation must allow.  The sweep +
+// exchange (+ measurement, + replica walk) kernels are held to the 80 VGPRs
+// that two 768-thread workgroups per CU need: left alone the scheduler takes
+// a few more (for values used once per item, which then go to scratch
+// instead, outside the step loop).  Every other variant gets what a
+// 1024-thread workgroup needs.
 template <int F>
-constexpr int kWavesPerSimd = ((F & kFeatWalk) && !(F & (kFeatHou | kFeatSplit))) ? 6 : 4;
+constexpr int kWavesPerSimd = !(F & (kFeatHou | kFeatSplit)) ? 6 : 4;
 
 template <int D, int F>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<F>)))
