@@ -54,6 +54,20 @@ def phi_star(L: int) -> float:
     return 0.406 + 0.014 * L
 
 
+def n_t_star(L: int) -> int:
+    """Linear fit of the optimal number of temperatures, Eq. (9):
+    a_NT + b_NT L with the constants printed for the 2D Gaussian model
+    (a_NT = 0.025, b_NT = 0.644), rounded to the nearest count and at least 2."""
+    return max(2, int(round(0.025 + 0.644 * L)))
+
+
+def optimized_betas(L: int, t_min: float, t_max: float) -> np.ndarray:
+    """The power-law ladder of Eqs. (6)-(7) with the fitted phi*(L) and
+    N_T*(L) of Eqs. (8)-(9): the paper's recipe for sizes not simulated
+    directly (fitted on the 2D Gaussian model)."""
+    return power_law_betas(t_min, t_max, n_t_star(L), phi_star(L))
+
+
 @dataclass
 class Workload:
     name: str

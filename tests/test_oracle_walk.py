@@ -133,3 +133,23 @@ def test_tunnel_summary_equilibration_flag():
     # zero errors and equal means agree; an empty bin among the last three does not
     assert oracle.tunnel_summary(bins({0: [3, 3], 1: [3, 3], 2: [3, 3, 3]}), 7)[3] == 1
     assert oracle.tunnel_summary(bins({1: [3, 3], 2: [3, 3, 3]}), 7)[3] == 0
+
+
+def test_ladder_fits_printed_constants():
+    """Eqs. (6)-(9): the fitted schedule parameters with the printed constants
+    (a_phi = 0.406, b_phi = 0.014, a_NT = 0.025, b_NT = 0.644) and the
+    power-law ladder they give."""
+    assert workloads.phi_star(15) == pytest.approx(0.406 + 0.014 * 15)
+    assert workloads.phi_star(64) == pytest.approx(1.302)
+    assert workloads.n_t_star(15) == 10  # 0.025 + 9.66 = 9.685
+    assert workloads.n_t_star(40) == 26  # 25.785
+    assert workloads.n_t_star(2) == 2
+    b = workloads.optimized_betas(40, 0.2, 1.5)
+    T = 1.0 / b
+    assert len(T) == 26 and T[0] == pytest.approx(0.2) and T[-1] == pytest.approx(1.5)
+    phi = workloads.phi_star(40)  # 0.966: spacing slightly denser at high T
+    i = np.arange(26)
+    np.testing.assert_allclose(T, 0.2 + (1.5 - 0.2) * (i / 25.0) ** phi, rtol=1e-13)
+    # phi = 1 is the linear schedule
+    np.testing.assert_allclose(1.0 / workloads.power_law_betas(0.2, 1.5, 5, 1.0),
+                               [0.2, 0.525, 0.85, 1.175, 1.5], rtol=1e-13)
