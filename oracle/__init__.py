@@ -83,6 +83,9 @@ def _declare(L):
     L.or_get_counters.argtypes = [P, P]
     L.or_get_moments.argtypes = [P, P, P, P, P, P, P]
     L.or_get_walk.argtypes = [P, P, P, P]
+    L.or_overlap_modes.argtypes = [C.c_int, C.c_int, P, P, P]
+    L.or_enable_modes.argtypes = [P]
+    L.or_get_modes.argtypes = [P, P]
     L.or_pt_table_len.argtypes = [P]
     L.or_pt_table_len.restype = C.c_int
     L.or_get_pt_table.argtypes = [P, P]
@@ -293,6 +296,16 @@ class OracleJob:
         lib().or_get_walk(self._h, _p(lab), _p(beg), _p(trips))
         return lab, beg, trips
 
+    def enable_modes(self):
+        """Accumulate the two-replica modes at every later measurement."""
+        lib().or_enable_modes(self._h)
+
+    def modes(self) -> np.ndarray:
+        """Accumulated plane-sum autocorrelations A(delta), [S][NT][L/2+1]."""
+        out = np.zeros((self.S, self.NT, self.L // 2 + 1), np.int64)
+        lib().or_get_modes(self._h, _p(out))
+        return out
+
     def observables(self):
         ps = np.zeros((self.S, self.NT, 5), np.float64)
         dis = np.zeros((self.NT, 6), np.float64)
@@ -360,3 +373,63 @@ def tunnel_summary(trips, passes):
                     if abs(tau_b[a] - tau_b[b]) > lim:
                         eq = 0
     return tau_b, err_b, tau, eq
+
+
+# --------------------------------------------------------------------------
+# Two-replica modes: spin-glass susceptibility and correlation length
+# --------------------------------------------------------------------------
+def overlap_modes(L: int, d: int, sa, sb) -> np.ndarray:
+    """A(delta), delta = 0 .. L/2, of one pair of configurations: the sum over
+    the d axes of the autocorrelation of the overlap's plane sums."""
+    a = np.ascontiguousarray(sa, dtype=np.int8)
+    b = np.ascontiguousarray(sb, dtype=np.int8)
+    out = np.zeros(L // 2 + 1, np.int64)
+    lib().or_overlap_modes(int(L), int(d), _p(a), _p(b), _p(out))
+    return out
+
+
+def _cos_frac(m: int, L: int) -> float:
+    """cos(2 pi m / L), exact where it is 0 or +-1."""
+    m %= L
+    if m == 0:
+        return 1.0
+    if 2 * m == L:
+        return -1.0
+    if 4 * m == L or 4 * m == 3 * L:
+        return 0.0
+    return math.cos(2.0 * math.pi * m / L)
+
+
+def mode_power(A, L: int, n: int) -> float:
+    """sum over the d axes of |sum_i q_i exp(2 pi i n x_mu / L)|^2 from A(0..L/2):
+    sum_{delta=0}^{L-1} cos(2 pi n delta / L) A(delta), with A(L - delta) = A(delta),
+    summed in increasing delta."""
+    tot = 0.0
+    for delta in range(L):
+        a = A[delta] if delta <= L // 2 else A[L - delta]
+        tot += _cos_frac(n * delta, L) * float(a)
+    return tot
+
+
+def correlation_length(modes, Q2, n_meas: int, L: int, d: int):
+    """Per temperature, disorder-averaged (integer sums over samples first):
+    chi_SG(0) = [sum Q^2] / (S n_meas N), chi_SG(k_min) = [sum_mu |q(k_mu)|^2 N^2]
+    / (d S n_meas N) with k_min = 2 pi / L along each axis, and the second-moment
+    correlation length xi = sqrt(chi(0)/chi(k_min) - 1) / (2 sin(pi / L))
+    (nan where the ratio is below 1 or chi(k_min) is 0).
+
+    modes: [S][NT][L/2+1] accumulated A(delta); Q2: [S][NT] accumulated Q^2."""
+    m = np.asarray(modes, dtype=np.int64)
+    S, NT = m.shape[0], m.shape[1]
+    N = L ** d
+    chi0 = np.zeros(NT)
+    chik = np.zeros(NT)
+    xi = np.full(NT, np.nan)
+    for k in range(NT):
+        A = [int(sum(int(m[s, k, j]) for s in range(S))) for j in range(L // 2 + 1)]
+        q2 = int(sum(int(Q2[s][k]) for s in range(S)))
+        chi0[k] = q2 / (S * n_meas * N)
+        chik[k] = mode_power(A, L, 1) / (d * S * n_meas * N)
+        if chik[k] > 0 and chi0[k] / chik[k] >= 1.0:
+            xi[k] = math.sqrt(chi0[k] / chik[k] - 1.0) / (2.0 * math.sin(math.pi / L))
+    return chi0, chik, xi

@@ -22,6 +22,8 @@
  *   - Counter-based Philox random numbers: Sec. 3 (Salmon et al. 2011).
  *   - Round-trip (tunnelling) time of the replica walk in temperature space
  *     and its logarithmically binned time series: Sec. 2.3.
+ *   - Two-replica modes for the spin-glass susceptibility and correlation
+ *     length (named in Sec. 3, not defined there; the usual definitions).
  *
  * Readings where the paper is silent (all documented in the design notes):
  *   checkerboard order (colour 0 then colour 1, increasing site index inside a
@@ -230,6 +232,8 @@ typedef struct {
   int32_t *wlab;          /* [S][2NT]: walk label of slot (0 none, 1 up, 2 down) */
   uint32_t *wbeg;         /* [S][2NT]: pass at which its current round trip began */
   uint64_t *trip;         /* [S][32][3]: per log2 bin: trips, sum len, sum len^2 */
+  int modes_on;
+  int64_t *modes;         /* [S][NT][L/2+1]: plane-sum autocorrelations A(delta) */
 } or_job;
 
 static int8_t *or_lat(or_job *jb, int s, int slot) {
@@ -310,7 +314,7 @@ OR_EXPORT void or_destroy(or_job *jb) {
   free(jb->sample_key); free(jb->J); free(jb->s); free(jb->E);
   free(jb->sot); free(jb->tos); free(jb->beta); free(jb->thr); free(jb->thrpt);
   free(jb->mE); free(jb->mE2); free(jb->mQ); free(jb->mAQ); free(jb->mQ2);
-  free(jb->mQ4); free(jb->wlab); free(jb->wbeg); free(jb->trip);
+  free(jb->mQ4); free(jb->wlab); free(jb->wbeg); free(jb->trip); free(jb->modes);
   free(jb);
 }
 
@@ -533,6 +537,44 @@ OR_EXPORT void or_houdayer(or_job *jb) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Two-replica modes (usual definitions; the paper names the quantities but   */
+/* does not define them).  With the overlap field q_i = s_i^a s_i^b and the    */
+/* plane sums P_mu(x) = sum of q_i over the sites with coordinate x_mu = x,     */
+/* the Fourier mode of q along axis mu at k = 2 pi n / L has                   */
+/*   |sum_i q_i e^{i k x_mu}|^2 = sum_{delta=0}^{L-1} cos(k delta) C_mu(delta), */
+/* C_mu(delta) = sum_x P_mu(x) P_mu((x + delta) mod L).  A(delta) is the sum    */
+/* of C_mu(delta) over the d axes, an exact integer; C_mu(L - delta) =          */
+/* C_mu(delta), so delta = 0 .. floor(L/2) carries everything.  Writes          */
+/* A(0 .. floor(L/2)) to out.                                                   */
+/* ------------------------------------------------------------------------ */
+OR_EXPORT void or_overlap_modes(int L, int d, const int8_t *sa, const int8_t *sb,
+                                int64_t *out) {
+  int N = (d == 3) ? L * L * L : L * L;
+  int64_t *P = (int64_t *)calloc((size_t)3 * L, sizeof(int64_t));
+  for (int i = 0; i < N; ++i) {
+    int x[3];
+    or_coords(L, d, i, x);
+    int q = sa[i] * sb[i];
+    for (int mu = 0; mu < d; ++mu) P[mu * L + x[mu]] += q;
+  }
+  for (int delta = 0; delta <= L / 2; ++delta) {
+    int64_t A = 0;
+    for (int mu = 0; mu < d; ++mu)
+      for (int x = 0; x < L; ++x)
+        A += P[mu * L + x] * P[mu * L + (x + delta) % L];
+    out[delta] = A;
+  }
+  free(P);
+}
+
+/* Accumulate the modes at every measurement from now on. */
+OR_EXPORT void or_enable_modes(or_job *jb) {
+  if (jb->modes_on) return;
+  jb->modes_on = 1;
+  jb->modes = (int64_t *)calloc((size_t)jb->S * jb->NT * (jb->L / 2 + 1), sizeof(int64_t));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Measurement (Sec. 2.1, Eqs. (3), (4); measurement step of Sec. 3).          */
 /* Per sample and temperature k: the two replicas at k (one per set) give      */
 /* E_a, E_b and the overlap Q = sum_i s_i^a s_i^b.  Exact integer sums of E,    */
@@ -557,6 +599,13 @@ OR_EXPORT void or_measure(or_job *jb) {
       jb->mQ2[o] += Q * Q;
       unsigned __int128 q2 = (unsigned __int128)(Q * Q);
       jb->mQ4[o] += q2 * q2;
+      if (jb->modes_on) {
+        const int nm = jb->L / 2 + 1;
+        int64_t *A = (int64_t *)malloc(sizeof(int64_t) * nm);
+        or_overlap_modes(jb->L, jb->d, la, lb, A);
+        for (int m = 0; m < nm; ++m) jb->modes[o * nm + m] += A[m];
+        free(A);
+      }
     }
   jb->n_meas += 1;
 }
@@ -658,6 +707,12 @@ OR_EXPORT void or_get_walk(const or_job *jb, int32_t *label, uint32_t *begin,
   if (label) memcpy(label, jb->wlab, sizeof(int32_t) * n);
   if (begin) memcpy(begin, jb->wbeg, sizeof(uint32_t) * n);
   if (trips) memcpy(trips, jb->trip, sizeof(uint64_t) * (size_t)jb->S * 32 * 3);
+}
+/* Accumulated modes [S][NT][L/2+1] (zeros if never enabled). */
+OR_EXPORT void or_get_modes(const or_job *jb, int64_t *out) {
+  size_t n = (size_t)jb->S * jb->NT * (jb->L / 2 + 1);
+  if (jb->modes_on) memcpy(out, jb->modes, sizeof(int64_t) * n);
+  else memset(out, 0, sizeof(int64_t) * n);
 }
 OR_EXPORT int or_pt_table_len(const or_job *jb) { return jb->M; }
 OR_EXPORT void or_get_pt_table(const or_job *jb, uint32_t *out) {
