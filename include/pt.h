@@ -64,6 +64,12 @@ extern "C" {
  * temperature space and its round trips (pt_get_walk).  Off by default: the
  * fused kernels then carry no walk code at all. */
 #define PT_TRACK_WALK 0x10u
+/* Also a pt_init_ex flag (same places as PT_TRACK_WALK): every measurement
+ * also accumulates the two-replica modes of each temperature (pt_get_modes,
+ * pt_correlation_length).  Off by default: the fused kernels then carry no
+ * mode code.  A job keeping the modes whose two replica sets do not fit one
+ * workgroup runs the per-step kernels (no split-sample plan). */
+#define PT_TRACK_MODES 0x20u
 
 /* pt_mcs flags */
 #define PT_MCS_HOUDAYER 1u
@@ -113,8 +119,8 @@ int pt_init(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
             uint64_t seed);
 
 /* pt_init with a device spin layout: flags = PT_LAYOUT_INT8 or
- * PT_LAYOUT_PACKED, optionally | PT_TRACK_WALK.  Results are bit-identical
- * for both layouts, with or without the walk. */
+ * PT_LAYOUT_PACKED, optionally | PT_TRACK_WALK and/or | PT_TRACK_MODES.
+ * Results are bit-identical for both layouts, with or without either. */
 int pt_init_ex(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
                int32_t dim, const int8_t *couplings, const double *betas,
                uint64_t seed, uint32_t flags);
@@ -243,9 +249,32 @@ int pt_tunnel_summary(const uint64_t *trips, int32_t rows, uint64_t passes,
                       double *tau_b, double *err_b, double *tau,
                       int32_t *equilibrated);
 
+/* Two-replica modes for the spin-glass susceptibility and correlation length
+ * (Sec. 3 names them as two-replica measurements; the usual definitions).
+ * Per measurement and temperature, with q_i = s_i^a s_i^b the overlap of the
+ * set-0 and set-1 replicas at that temperature and P_mu(x) the sum of q_i
+ * over the sites whose coordinate along axis mu is x, the job adds
+ *   A(delta) = sum over axes mu of sum_x P_mu(x) P_mu((x + delta) mod L),
+ * delta = 0 .. L/2 (A(L - delta) = A(delta)): exact integers, from which
+ * sum_mu |sum_i q_i exp(2 pi i n x_mu / L)|^2 = sum_{delta<L} cos(2 pi n
+ * delta / L) A(delta).
+ *   out int64 [samples][replicas][L/2 + 1]
+ * Synchronous.  PT_EINVAL for a job created without PT_TRACK_MODES. */
+int pt_get_modes(pt_job *job, int64_t *out);
+
+/* Per temperature k (int32 index 0 = coldest), disorder-averaged from integer
+ * sums over samples: chi0[k] = chi_SG(0) = [sum Q^2] / (S n_meas N) (the
+ * overlap moment, Q = sum_i q_i), chik[k] = chi_SG(k_min) = [sum_delta
+ * cos(2 pi delta / L) A(delta)] / (d S n_meas N) with k_min = 2 pi / L along
+ * each axis (averaged over the d axes), and xi[k] = sqrt(chi0/chik - 1) /
+ * (2 sin(pi / L)), the second-moment correlation length (NaN if chik <= 0 or
+ * chi0 < chik).  Outputs double [replicas]; any may be NULL.  The cosine is
+ * taken exactly where it is 0 or +-1.  PT_EINVAL as pt_get_modes. */
+int pt_correlation_length(pt_job *job, double *chi0, double *chik, double *xi);
+
 /* Checkpoint: the whole dynamic state (spins, energies, maps, counters,
- * moments, and the replica walk if kept).  With buf == NULL, *len receives
- * the size.  Otherwise *len must
+ * moments, and the replica walk and modes if kept).  With buf == NULL, *len
+ * receives the size.  Otherwise *len must
  * hold at least that size.  pt_set_state restores a state taken from a job of
  * identical shape and layout; continuing is bit-identical to never stopping. */
 int pt_get_state(pt_job *job, void *buf, size_t *len);

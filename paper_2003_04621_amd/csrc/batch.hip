@@ -121,10 +121,11 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     if (mcs > 0 && hou) feat |= kFeatHou;
     if (mcs > 0 && mode == 3) feat |= kFeatSplit;
     if (mcs > 0 && j->track_walk) feat |= kFeatWalk;
+    if (mcs > 0 && meas && j->track_modes) feat |= kFeatModes;
     if (mode == 3) {
       FusedArgs A = make_fused_args(j->g, j->split_lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
-                                    j->thrpt, j->M, j->mom, j->walk, j->trips, j->ctr, mcs, false,
-                                    meas);
+                                    j->thrpt, j->M, j->mom, j->walk, j->trips, nullptr, j->ctr, mcs,
+                                    false, meas);
       A.parts = j->split_parts;
       A.R = j->split_R;
       A.jlds = j->split_jlds;
@@ -144,7 +145,8 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     }
     const int nsets = mode == 2 ? 1 : 2;
     hj.push_back(make_fused_args(j->g, j->plan[mode], j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
-                                 j->thrpt, j->M, j->mom, j->walk, j->trips, j->ctr, mcs, hou, meas));
+                                 j->thrpt, j->M, j->mom, j->walk, j->trips, j->modes, j->ctr, mcs, hou,
+                                 meas));
     lds_words = std::max(lds_words, (size_t)j->plan[mode].words);
     if (mcs <= 0) continue;
     const double c = (double)nsets * j->g.NT * j->g.N * mcs;
@@ -322,17 +324,18 @@ int snapshot(pt_batch* b, Snap& sn, bool restore) {
   size_t k = 0;
   for (pt_job* j : b->jobs) {
     const size_t lat = (size_t)j->g.S * j->g.nslot, maps = sizeof(int32_t) * (size_t)j->g.S * 2 * j->g.NT;
-    void* src[8] = {j->spins, j->E, j->sot, j->tos, j->ctr, j->mom, j->walk, j->trips};
-    const size_t len[8] = {j->spin_bytes(),
+    void* src[9] = {j->spins, j->E, j->sot, j->tos, j->ctr, j->mom, j->walk, j->trips, j->modes};
+    const size_t len[9] = {j->spin_bytes(),
                            sizeof(int32_t) * lat,
                            maps,
                            maps,
                            sizeof(DevCounters),
                            sizeof(int64_t) * 8 * (size_t)j->g.S * j->g.NT,
                            sizeof(int32_t) * 2 * lat,
-                           sizeof(uint64_t) * 32 * 3 * (size_t)j->g.S};
-    for (int i = 0; i < 8; ++i) {
-      if (!src[i]) continue;  // no replica walk kept
+                           sizeof(uint64_t) * 32 * 3 * (size_t)j->g.S,
+                           sizeof(int64_t) * (size_t)j->g.S * j->g.NT * (j->g.L / 2 + 1)};
+    for (int i = 0; i < 9; ++i) {
+      if (!src[i]) continue;  // no replica walk or modes kept
       const size_t at = k++;
       if (!restore) {
         void* p = nullptr;
@@ -356,7 +359,7 @@ std::string cache_key(const pt_batch* b, uint32_t flags) {
   for (const pt_job* j : b->jobs)
     parts.push_back(std::to_string(j->g.L) + "x" + std::to_string(j->g.NT) + "x" +
                     std::to_string(j->g.S) + "x" + std::to_string(j->g.layout) +
-                    (j->track_walk ? "w" : ""));
+                    (j->track_walk ? "w" : "") + (j->track_modes ? "m" : ""));
   std::sort(parts.begin(), parts.end());
   std::string key = "gfx950/d" + std::to_string(b->d) + "/f" + std::to_string(flags) + "/";
   size_t i = 0;

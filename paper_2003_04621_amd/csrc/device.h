@@ -245,6 +245,28 @@ __device__ __forceinline__ uint32_t load_counter(const uint32_t* p) {
 // lengths, sum of squared lengths; atomically, as the two replica sets of a
 // sample may be walked at once), and begins the next one.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Two-replica modes (the spin-glass susceptibility and correlation-length modes
+// that Sec. 3 names; usual definitions).  From the plane counts cnt[mu][x]
+// (mu < d, x < L) of the sites where the two replicas differ, the overlap's
+// plane sums are P_mu(x) = L^(d-1) - 2 cnt[mu][x]; returns
+// A(delta) = sum_mu sum_x P_mu(x) P_mu((x + delta) mod L), an exact integer
+// from which |sum_i q_i exp(i k x_mu)|^2 = sum_delta cos(k delta) A(delta).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t mode_autocorr(const Geo& g, const int32_t* cnt, int delta) {
+  const int L = g.L, plane = g.N / L;
+  int64_t A = 0;
+  for (int mu = 0; mu < g.d; ++mu) {
+    const int32_t* c = cnt + mu * L;
+    int y = delta;
+    for (int x = 0; x < L; ++x) {
+      A += (int64_t)(plane - 2 * c[x]) * (int64_t)(plane - 2 * c[y]);
+      if (++y == L) y = 0;
+    }
+  }
+  return A;
+}
+
 // wk is 8-byte aligned; cold != hot (N_T >= 2), so both slots' words are read
 // before either is written.
 __device__ __forceinline__ void walk_observe(int32_t* wk, uint64_t* bins, int cold, int hot,

@@ -203,6 +203,60 @@ __device__ __forceinline__ void add_moments(const Geo& g, int64_t* m, int32_t ea
 // temperature counts the sites where its two replicas differ and adds the
 // moments.
 // ---------------------------------------------------------------------------
+// The two-replica modes of temperature k (mode_autocorr) by one wavefront,
+// from the resident words of its two replicas: plane counts of the differing
+// sites in the wavefront's LDS counters (slow axes by LDS atomics per word
+// field; the fast axis x0, whose sites interleave inside a field, by one
+// ballot per bit position: bit j of a colour-c word is the site
+// x0 = 2 (j mod H) + ((c + par) & 1) of its field's row), then A(delta) for
+// delta <= L/2 added to the item's LDS sums.
+__device__ __forceinline__ void modes_resident(const Geo& g, const FusedLayout& lay, uint32_t* lds,
+                                               const uint32_t* Wa, const uint32_t* Wb, int k,
+                                               int wave, int lane) {
+  const int L = g.L, NW = g.NW, MH = L / 2 + 1;
+  int32_t* cnt = reinterpret_cast<int32_t*>(lds + lay.mcnt) + wave * 3 * L;
+  int64_t* acc = reinterpret_cast<int64_t*>(lds + lay.modes) + (size_t)k * MH;
+  for (int i = lane; i < 3 * L; i += 64) cnt[i] = 0;
+  wave_lds_sync();
+  int col = 0;  // lane x < L: differing sites at x0 = x
+  for (int base = 0; base < NW; base += 64) {
+    const int w = base + lane;
+    uint32_t X0 = 0, X1 = 0;
+    int par = 0;
+    if (w < NW) {
+      X0 = (Wa[w] ^ Wb[w]) & g.maskW;
+      X1 = (Wa[NW + w] ^ Wb[NW + w]) & g.maskW;
+      const WordNb q = word_nb(g, w);
+      par = q.par;
+      if (g.d == 3) {
+        const int n = __popc(X0) + __popc(X1);
+        if (n) atomicAdd(&cnt[L + q.x1], n);
+      }
+      for (int f = 0; f < g.P; ++f) {
+        const uint32_t m = g.maskH << (f * g.H);
+        const int n = __popc(X0 & m) + __popc(X1 & m);
+        if (n) atomicAdd(&cnt[(g.d - 1) * L + f * g.B + q.xs], n);
+      }
+    }
+    const uint64_t podd = __ballot(par);
+    for (int f = 0; f < g.P; ++f)
+      for (int bb = 0; bb < g.H; ++bb) {
+        const int j = f * g.H + bb;
+        const uint64_t m0 = __ballot((X0 >> j) & 1u), m1 = __ballot((X1 >> j) & 1u);
+        // colour-0 words hold x0 of parity par, colour-1 words the other one
+        const int even = __popcll(m0 & ~podd) + __popcll(m1 & podd);
+        const int odd = __popcll(m0 & podd) + __popcll(m1 & ~podd);
+        if (lane == 2 * bb) col += even;
+        if (lane == 2 * bb + 1) col += odd;
+      }
+  }
+  if (lane < L) cnt[lane] = col;
+  wave_lds_sync();
+  if (lane < MH) acc[lane] += mode_autocorr(g, cnt, lane);
+  wave_lds_sync();
+}
+
+template <bool MODES>
 __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* lds) {
   const Geo& g = A.g;
   const int NT = g.NT, NW = g.NW, tid = threadIdx.x, T = blockDim.x;
@@ -219,6 +273,7 @@ __device__ __forceinline__ void measure_resident(const FusedArgs& A, uint32_t* l
     for (int w = lane; w < 2 * NW; w += 64) neg += __popc(Wa[w] ^ Wb[w]);
     neg = wave_total(neg);
     if (lane == 0) add_moments(g, mom + (size_t)k * 8, El[a], El[b], neg);
+    if (MODES && A.modes) modes_resident(g, A.lay, lds, Wa, Wb, k, wave, lane);
   }
   __syncthreads();
 }
@@ -704,7 +759,7 @@ __device__ __forceinline__ void flush_trips(const FusedArgs& A, const uint32_t* 
     if (bl[i]) atomicAdd(dst + i, (unsigned long long)bl[i]);
 }
 
-template <int D, bool HOU, bool MEAS, bool WALK>
+template <int D, bool HOU, bool MEAS, bool WALK, bool MODES>
 __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, int s, int c_lo, int nsets) {
   const Geo& g = A.g;
   const int T = blockDim.x, tid = threadIdx.x;
@@ -742,6 +797,11 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
   for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
   if (meas)
     for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
+  const bool modes = MODES && meas && A.modes != nullptr;
+  const int MH = g.L / 2 + 1;
+  int64_t* modl = reinterpret_cast<int64_t*>(lds + A.lay.modes);
+  if (modes)
+    for (int i = tid; i < NT * MH; i += T) modl[i] = A.modes[(size_t)s * NT * MH + i];
   const bool walk = WALK && A.walk != nullptr;
   int32_t* wkl = reinterpret_cast<int32_t*>(lds + A.lay.walk);
   if (walk) {
@@ -758,7 +818,7 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
     sweep_resident<D>(A, Jl, W, El, tosl, thrl, slot0, nres, s, t);
     if (hou) houdayer_resident<D>(A, lds, s, v0 + (uint32_t)step);
     exchange_resident<WALK>(A, lds, c_lo, nsets, u + 1u, walk);
-    if (meas) measure_resident(A, lds);
+    if (meas) measure_resident<MODES>(A, lds);
   }
 
   // ---- store the resident sets
@@ -781,6 +841,8 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
     for (int i = tid; i < 2 * nres; i += T) A.walk[2 * lat0 + i] = wkl[2 * slot0 + i];
     flush_trips(A, lds, s);
   }
+  if (modes)
+    for (int i = tid; i < NT * MH; i += T) A.modes[(size_t)s * NT * MH + i] = modl[i];
   if (meas)
     for (int i = tid; i < 8 * NT; i += T) A.mom[(size_t)s * NT * 8 + i] = mom[i];
 }
@@ -989,6 +1051,7 @@ k_batch(const FusedArgs* __restrict__ jobs, const BatchItem* __restrict__ items,
         uint32_t* queue) {
   constexpr bool kHou = (F & kFeatHou) != 0, kMeas = (F & kFeatMeas) != 0;
   constexpr bool kSplit = (F & kFeatSplit) != 0, kWalk = (F & kFeatWalk) != 0;
+  constexpr bool kModes = (F & kFeatModes) != 0;
   // 16-byte aligned: the moment words are updated with 64-bit LDS atomics,
   // which need naturally aligned addresses (the plan offsets are 8-byte
   // aligned relative to this base)
@@ -1006,7 +1069,7 @@ k_batch(const FusedArgs* __restrict__ jobs, const BatchItem* __restrict__ items,
       if (kSplit && it.nsets == 0)
         run_split<D, kMeas, kWalk>(A, lds, it.sample, it.c_lo, &flag);
       else
-        run_sample<D, kHou, kMeas, kWalk>(A, lds, it.sample, it.c_lo, it.nsets);
+        run_sample<D, kHou, kMeas, kWalk, kModes>(A, lds, it.sample, it.c_lo, it.nsets);
     }
     __syncthreads();
   }
@@ -1038,7 +1101,8 @@ __global__ void k_batch_advance(const FusedArgs* __restrict__ jobs, int njobs) {
 }
 
 // ---------------------------------------------------------------------------
-bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay, bool walk) {
+bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay, bool walk,
+                bool modes) {
   // LDS words per workgroup on gfx950 (160 KiB), less room for static LDS
   const size_t budget = (160 * 1024 - 512) / 4;
   size_t off = 0;
@@ -1062,6 +1126,9 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay, 
   lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
   lay.walk = take(walk ? 2 * (size_t)g.nslot : 0, walk ? 2 : 1);
   lay.trip = take(walk ? 2 * 32 * 3 : 0, walk ? 2 : 1);
+  const bool md = modes && nsets == 2;
+  lay.mcnt = take(md ? (size_t)waves * 3 * g.L : 0, 1);
+  lay.modes = take(md ? 2 * (size_t)g.NT * (g.L / 2 + 1) : 0, md ? 2 : 1);
   lay.PC = 0;
   lay.Qs = (int)off;
   lay.hq = (int)off;
@@ -1115,6 +1182,7 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, b
     lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
     lay.walk = take(walk ? 2 * (size_t)g.nslot : 0, walk ? 2 : 1);
     lay.trip = take(walk ? 2 * 32 * 3 : 0, walk ? 2 : 1);
+    lay.mcnt = lay.modes = (int)off;
     lay.PC = 0;
     lay.Qs = (int)off;
     lay.hq = (int)off;
@@ -1127,8 +1195,8 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, b
 FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
                           int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
                           const uint32_t* thrpt, int M, int64_t* mom, int32_t* walk,
-                          uint64_t* trips, const DevCounters* ctr, int nmcs, bool hou,
-                          bool meas) {
+                          uint64_t* trips, int64_t* modes, const DevCounters* ctr, int nmcs,
+                          bool hou, bool meas) {
   FusedArgs A;
   A.g = g;
   A.spins = spins;
@@ -1142,6 +1210,7 @@ FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, con
   A.mom = mom;
   A.walk = walk;
   A.trips = trips;
+  A.modes = modes;
   A.ctr = ctr;
   A.nmcs = nmcs;
   A.hou = hou ? 1 : 0;
@@ -1164,16 +1233,26 @@ static hipError_t lds_attr(K kernel, size_t bytes) {
 namespace {
 using BatchKernel = void (*)(const FusedArgs*, const BatchItem*, int, uint32_t*);
 
+// Split samples never carry the modes (such jobs run the per-step kernels),
+// so those combinations are not compiled.
+template <int D, int F>
+constexpr BatchKernel kernel_or_null() {
+  if constexpr ((F & kFeatSplit) && (F & kFeatModes))
+    return nullptr;
+  else
+    return &k_batch<D, F>;
+}
+
 template <int D, int... F>
 constexpr BatchKernel pick(int feat, std::integer_sequence<int, F...>) {
   BatchKernel k = nullptr;
-  ((k = (feat == F ? &k_batch<D, F> : k)), ...);
+  ((k = (feat == F ? kernel_or_null<D, F>() : k)), ...);
   return k;
 }
 
 BatchKernel batch_kernel(int d, int feat) {
-  using All = std::make_integer_sequence<int, 16>;
-  return d == 3 ? pick<3>(feat & 15, All{}) : pick<2>(feat & 15, All{});
+  using All = std::make_integer_sequence<int, 32>;
+  return d == 3 ? pick<3>(feat & 31, All{}) : pick<2>(feat & 31, All{});
 }
 }  // namespace
 

@@ -28,6 +28,9 @@ struct pt_job {
   int M = 0;
   ptsg::DevCounters* ctr = nullptr;
   int64_t* mom = nullptr;    // [S][NT][8]
+  // two-replica modes, allocated only for jobs created with PT_TRACK_MODES
+  bool track_modes = false;
+  int64_t* modes = nullptr;  // [S][NT][L/2+1]
   // replica walk, allocated only for jobs created with PT_TRACK_WALK
   bool track_walk = false;
   int32_t* walk = nullptr;   // [S][2NT][2]: replica-walk label, pass its round trip began
@@ -101,7 +104,7 @@ int batch_slots(const pt_batch* b);
 // and how many bytes that scratch takes.
 size_t split_scratch_bytes(const ptsg::Geo& g);
 // Device bytes a job of this shape allocates (an upper bound); `flags` as
-// pt_init_ex's (a layout, optionally with PT_TRACK_WALK).
+// pt_init_ex's (a layout, optionally with PT_TRACK_WALK / PT_TRACK_MODES).
 size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* betas);
 // Length of a row of the exchange threshold table.
 int pt_table_len(const double* betas, int NT, int d, long N);

@@ -37,9 +37,11 @@ hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t
 hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
                            const int32_t* sot, DevCounters* ctr, hipStream_t st);
 
-// One measurement; mom is int64 [S][NT][8].
+// One measurement; mom is int64 [S][NT][8]; modes (null: not kept) int64
+// [S][NT][L/2+1] receives each temperature's mode_autocorr sums.
 hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E,
-                          const int32_t* sot, int64_t* mom, DevCounters* ctr, hipStream_t st);
+                          const int32_t* sot, int64_t* mom, int64_t* modes, DevCounters* ctr,
+                          hipStream_t st);
 
 // Advances the device counters by `step` (one thread; enqueued after the
 // kernels that read them).
@@ -49,9 +51,10 @@ hipError_t launch_advance(DevCounters* ctr, CounterStep step, hipStream_t st);
 // couplings J, energies E, maps sot/tos (and the pre-pass copy sot0),
 // threshold rows, moments, overlap counts, exchange randoms and decision
 // matrix, replica-walk words and the launch's round-trip sums (64-bit
-// aligned), and the Houdayer words Qs of PC wavefronts; `words` in all.
+// aligned), per-wavefront plane counters and the item's two-replica mode sums
+// (64-bit), and the Houdayer words Qs of PC wavefronts; `words` in all.
 struct FusedLayout {
-  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, walk, trip, Qs, PC, hq, words;
+  int W, J, E, sot, tos, sot0, thr, mom, qneg, rpt, acc, walk, trip, mcnt, modes, Qs, PC, hq, words;
 };
 
 // Everything one fused workgroup needs about a job, for nmcs steps.
@@ -70,6 +73,8 @@ struct FusedArgs {
   // the current round trip began; [S][32][3] round trips per log2 bin
   int32_t* walk;
   uint64_t* trips;
+  // two-replica modes (null unless the job keeps them): [S][NT][L/2+1]
+  int64_t* modes;
   const DevCounters* ctr;
   int nmcs, hou, meas;
   uint32_t magicNW;  // item / NW
@@ -98,7 +103,7 @@ constexpr int kMaxParts = 64;
 // Plans the LDS of a fused workgroup holding `nsets` replica sets of one
 // sample (`waves` wavefronts); false if it does not fit in 160 KiB.
 bool fused_plan(const Geo& g, bool houdayer, int nsets, int waves, FusedLayout& lay,
-                bool walk = false);
+                bool walk = false, bool modes = false);
 
 // Plans a split sample: the fewest parts (<= kMaxParts) whose R slots fit one
 // workgroup's LDS, with the couplings in LDS when that still leaves room for
@@ -108,13 +113,14 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, b
 FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
                           int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
                           const uint32_t* thrpt, int M, int64_t* mom, int32_t* walk,
-                          uint64_t* trips, const DevCounters* ctr, int nmcs, bool houdayer,
-                          bool measure);
+                          uint64_t* trips, int64_t* modes, const DevCounters* ctr, int nmcs,
+                          bool houdayer, bool measure);
 
 // Kinds of work a batch launch holds (Houdayer moves, measurements, split
-// samples, jobs that track the replica walk); the launch runs the kernel
-// compiled for exactly that set.
-constexpr int kFeatHou = 1, kFeatMeas = 2, kFeatSplit = 4, kFeatWalk = 8;
+// samples, jobs that track the replica walk, jobs that measure the two-replica
+// modes; never split samples with modes); the launch runs the kernel compiled
+// for exactly that set.
+constexpr int kFeatHou = 1, kFeatMeas = 2, kFeatSplit = 4, kFeatWalk = 8, kFeatModes = 16;
 
 // Persistent batch: resets the queue, runs every item to its job's nmcs, then
 // advances each job's counters.  `jobs` and `items` are device arrays.

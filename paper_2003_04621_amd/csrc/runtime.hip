@@ -63,11 +63,13 @@ namespace {
 // The LDS plans of a job of geometry job->g (host only).
 void plan_job(pt_job* job) {
   const Geo& g = job->g;
-  const bool w = job->track_walk;
-  job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0], w);
-  job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1], w);
-  job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2], w);
-  job->split_ok = !job->fused_ok[0] &&
+  const bool w = job->track_walk, md = job->track_modes;
+  job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0], w, md);
+  job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1], w, md);
+  job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2], w, md);
+  // a job keeping the modes whose two sets do not fit one workgroup runs the
+  // per-step kernels
+  job->split_ok = !job->fused_ok[0] && !md &&
                   split_plan(g, job->split_lay, job->split_parts, job->split_R, job->split_jlds, w);
 }
 
@@ -196,7 +198,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (samples < 1 || samples >= (1 << 28)) return pt_fail(PT_EINVAL, "samples must be in [1, 2^28)");
   if (replicas < 2 || replicas > 4096) return pt_fail(PT_EINVAL, "replicas must be in [2, 4096]");
-  const uint32_t layout = flags & ~(uint32_t)PT_TRACK_WALK;
+  const uint32_t layout = flags & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
   if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown flags");
   for (int k = 0; k < replicas; ++k) {
     if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
@@ -219,6 +221,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   job->alloc_ctx = ctx;
   job->stream = stream;
   job->track_walk = (flags & PT_TRACK_WALK) != 0;
+  job->track_modes = (flags & PT_TRACK_MODES) != 0;
   job->g = make_geo(samples, replicas, L, dim, (int)layout, seed);
   const Geo& g = job->g;
 
@@ -255,6 +258,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
     job->walk = (int32_t*)job->dalloc(sizeof(int32_t) * 2 * (size_t)nlat);
     job->trips = (uint64_t*)job->dalloc(sizeof(uint64_t) * 32 * 3 * (size_t)samples);
   }
+  const size_t mode_words = (size_t)samples * replicas * (L / 2 + 1);
+  if (job->track_modes) job->modes = (int64_t*)job->dalloc(sizeof(int64_t) * mode_words);
   int8_t* J8 = (int8_t*)job->dalloc((size_t)ncoup);
   bool split_mem = true;
   if (job->split_ok) {
@@ -266,7 +271,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   }
   if (!job->spins || !job->jw || !job->E || !job->sot || !job->tos || !job->thr || !job->thrpt ||
       !job->ctr || !job->mom || !J8 || !split_mem ||
-      (job->track_walk && (!job->walk || !job->trips))) {
+      (job->track_walk && (!job->walk || !job->trips)) || (job->track_modes && !job->modes)) {
     job->release();
     delete job;
     return pt_fail(PT_ENOMEM, "device allocation failed");
@@ -287,6 +292,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   step(hipMemcpyAsync(job->tos, ident.data(), maps, hipMemcpyHostToDevice, st));
   step(hipMemsetAsync(job->ctr, 0, sizeof(DevCounters), st));
   step(hipMemsetAsync(job->mom, 0, sizeof(int64_t) * 8 * (size_t)samples * replicas, st));
+  if (job->track_modes) step(hipMemsetAsync(job->modes, 0, sizeof(int64_t) * mode_words, st));
   if (job->track_walk) {
     step(hipMemsetAsync(job->walk, 0, sizeof(int32_t) * 2 * (size_t)nlat, st));
     step(hipMemsetAsync(job->trips, 0, sizeof(uint64_t) * 32 * 3 * (size_t)samples, st));
@@ -312,10 +318,7 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
                     g_ctx, nullptr);
 }
 
-bool job_is_resident(const pt_job* j, uint32_t flags) {
-  if (flags & PT_MCS_HOUDAYER) return j->fused_ok[1];
-  return j->fused_ok[0] || j->fused_ok[2] || j->split_ok;
-}
+bool job_is_resident(const pt_job* j, uint32_t flags) { return job_plan_mode(j, flags) >= 0; }
 
 int pt_table_len(const double* betas, int NT, int d, long N) {
   int M = 1;
@@ -338,8 +341,8 @@ size_t split_scratch_bytes(const Geo& g) {
 }
 
 size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* betas) {
-  const int layout = flags & ~(int)PT_TRACK_WALK;
-  const bool walk = (flags & PT_TRACK_WALK) != 0;
+  const int layout = flags & ~(int)(PT_TRACK_WALK | PT_TRACK_MODES);
+  const bool walk = (flags & PT_TRACK_WALK) != 0, modes = (flags & PT_TRACK_MODES) != 0;
   const size_t N = (d == 3) ? (size_t)L * L * L : (size_t)L * L;
   const size_t NW = N / L / fields_per_word(L);
   const size_t lat = (size_t)S * 2 * NT;
@@ -347,6 +350,7 @@ size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* be
   const size_t jw = (size_t)S * 2 * 2 * d * NW * 4;
   const size_t small = sizeof(int32_t) * (lat + 4 * (size_t)S * NT) + sizeof(int64_t) * 8 * S * NT +
                        (walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)S : 0) +
+                       (modes ? sizeof(int64_t) * (size_t)S * NT * (L / 2 + 1) : 0) +
                        sizeof(uint32_t) * (size_t)NT * (4 + pt_table_len(betas, NT, d, (long)N)) + 4096;
   return spins + jw + (size_t)S * d * N + small + split_scratch_bytes(make_geo(S, NT, L, d, layout, 0));
 }
@@ -405,7 +409,8 @@ PT_API int pt_houdayer(pt_job* job) {
 
 PT_API int pt_measure(pt_job* job) {
   if (int rc = check_job(job)) return rc;
-  PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->ctr, job->stream));
+  PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr,
+                             job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 0, 1}, job->stream));
   return PT_OK;
 }
@@ -442,7 +447,8 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
     if (hou) PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
     PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
                                 job->trips, job->ctr, st));
-    if (meas) PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->ctr, st));
+    if (meas)
+      PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr, st));
     PT_HIP(job, launch_advance(job->ctr, CounterStep{1, 1, hou ? 1u : 0u, meas ? 1u : 0u}, st));
   }
   return PT_OK;
@@ -462,13 +468,15 @@ PT_API int pt_plan_query(int32_t dim, int32_t L, int32_t replicas, uint32_t flag
   if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (replicas < 2) return pt_fail(PT_EINVAL, "replicas must be >= 2");
-  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | PT_TRACK_WALK))
+  const uint32_t track = PT_TRACK_WALK | PT_TRACK_MODES;
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | track))
     return pt_fail(PT_EINVAL, "unknown flags");
   pt_job job;
   job.g = make_geo(1, replicas, L, dim, PT_LAYOUT_INT8, 0);
   job.track_walk = (flags & PT_TRACK_WALK) != 0;
+  job.track_modes = (flags & PT_TRACK_MODES) != 0;
   plan_job(&job);
-  plan_report(&job, flags & ~(uint32_t)PT_TRACK_WALK, out4);
+  plan_report(&job, flags & ~track, out4);
   return PT_OK;
 }
 
@@ -478,7 +486,7 @@ PT_API int pt_job_bytes(int32_t samples, int32_t replicas, int32_t L, int32_t di
   if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (samples < 1 || replicas < 2) return pt_fail(PT_EINVAL, "need samples >= 1 and replicas >= 2");
-  const uint32_t lay = layout & ~(uint32_t)PT_TRACK_WALK;
+  const uint32_t lay = layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
   if (lay != PT_LAYOUT_INT8 && lay != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown layout");
   for (int k = 0; k < replicas; ++k)
     if (!(betas[k] > 0.0) || (k > 0 && !(betas[k] < betas[k - 1])))
@@ -648,6 +656,68 @@ PT_API int pt_tunnel_summary(const uint64_t* trips, int32_t rows, uint64_t passe
   return PT_OK;
 }
 
+PT_API int pt_get_modes(pt_job* job, int64_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (!job->track_modes) return pt_fail(PT_EINVAL, "the job was created without PT_TRACK_MODES");
+  if (int rc = check_fault(job)) return rc;
+  if (!out) return pt_fail(PT_EINVAL, "null output");
+  const Geo& g = job->g;
+  PT_HIP(job, hipMemcpyAsync(out, job->modes, sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1),
+                             hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  return PT_OK;
+}
+
+namespace {
+// cos(2 pi m / L), exact where it is 0 or +-1.
+double cos_frac(long m, int L) {
+  m %= L;
+  if (m == 0) return 1.0;
+  if (2 * m == L) return -1.0;
+  if (4 * m == L || 4 * m == 3 * (long)L) return 0.0;
+  return std::cos(2.0 * M_PI * (double)m / (double)L);
+}
+}  // namespace
+
+PT_API int pt_correlation_length(pt_job* job, double* chi0, double* chik, double* xi) {
+  if (int rc = check_job(job)) return rc;
+  if (!job->track_modes) return pt_fail(PT_EINVAL, "the job was created without PT_TRACK_MODES");
+  if (int rc = check_fault(job)) return rc;
+  const Geo& g = job->g;
+  const int L = g.L, MH = L / 2 + 1;
+  const size_t n = (size_t)g.S * g.NT;
+  std::vector<int64_t> md(n * MH), m(8 * n);
+  DevCounters c;
+  PT_HIP(job, hipMemcpyAsync(md.data(), job->modes, sizeof(int64_t) * md.size(), hipMemcpyDeviceToHost,
+                             job->stream));
+  PT_HIP(job, hipMemcpyAsync(m.data(), job->mom, sizeof(int64_t) * m.size(), hipMemcpyDeviceToHost,
+                             job->stream));
+  PT_HIP(job, hipMemcpyAsync(&c, job->ctr, sizeof(c), hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  const double nm = (double)c.n_meas, N = (double)g.N, S = (double)g.S;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (int k = 0; k < g.NT; ++k) {
+    // integer sums over samples first
+    std::vector<int64_t> A(MH, 0);
+    int64_t q2 = 0;
+    for (int s = 0; s < g.S; ++s) {
+      const size_t i = (size_t)s * g.NT + k;
+      for (int j = 0; j < MH; ++j) A[j] += md[i * MH + j];
+      q2 += m[i * 8 + 4];
+    }
+    double p1 = 0.0;  // sum over delta in [0, L) of cos(2 pi delta / L) A(delta)
+    for (int delta = 0; delta < L; ++delta)
+      p1 += cos_frac(delta, L) * (double)A[delta <= L / 2 ? delta : L - delta];
+    const double c0 = (double)q2 / (S * nm * N), ck = p1 / ((double)g.d * S * nm * N);
+    double x = nan;
+    if (ck > 0.0 && c0 / ck >= 1.0) x = std::sqrt(c0 / ck - 1.0) / (2.0 * std::sin(M_PI / L));
+    if (chi0) chi0[k] = c0;
+    if (chik) chik[k] = ck;
+    if (xi) xi[k] = x;
+  }
+  return PT_OK;
+}
+
 PT_API int pt_observables(pt_job* job, double* per_sample, double* disorder, int64_t* n_meas) {
   if (int rc = check_job(job)) return rc;
   if (int rc = check_fault(job)) return rc;
@@ -719,7 +789,12 @@ size_t state_size(const pt_job* job) {
   return sizeof(StateHeader) + job->spin_bytes() + sizeof(int32_t) * lat +
          2 * sizeof(int32_t) * (size_t)g.S * 2 * g.NT + sizeof(DevCounters) +
          sizeof(int64_t) * 8 * (size_t)g.S * g.NT +
-         (job->track_walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)g.S : 0);
+         (job->track_walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)g.S : 0) +
+         (job->track_modes ? sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1) : 0);
+}
+
+int32_t state_flags(const pt_job* job) {
+  return (job->track_walk ? 1 : 0) | (job->track_modes ? 2 : 0);
 }
 }  // namespace
 
@@ -735,7 +810,7 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   if (*len < need) return pt_fail(PT_EINVAL, "state buffer too small");
   const Geo& g = job->g;
   char* p = static_cast<char*>(buf);
-  StateHeader h{kStateMagic, g.S, g.NT, g.L, g.d, g.layout, job->track_walk ? 1 : 0,
+  StateHeader h{kStateMagic, g.S, g.NT, g.L, g.d, g.layout, state_flags(job),
                 (uint64_t)job->spin_bytes()};
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -759,7 +834,11 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
     p += sizeof(int32_t) * 2 * lat;
     PT_HIP(job, hipMemcpyAsync(p, job->trips, sizeof(uint64_t) * 32 * 3 * (size_t)g.S,
                                hipMemcpyDeviceToHost, st));
+    p += sizeof(uint64_t) * 32 * 3 * (size_t)g.S;
   }
+  if (job->track_modes)
+    PT_HIP(job, hipMemcpyAsync(p, job->modes, sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1),
+                               hipMemcpyDeviceToHost, st));
   PT_HIP(job, hipStreamSynchronize(st));
   *len = need;
   return PT_OK;
@@ -773,7 +852,7 @@ PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (h.magic != kStateMagic || h.S != g.S || h.NT != g.NT || h.L != g.L || h.d != g.d ||
-      h.layout != g.layout || h.pad != (job->track_walk ? 1 : 0) ||
+      h.layout != g.layout || h.pad != state_flags(job) ||
       h.spin_bytes != job->spin_bytes())
     return pt_fail(PT_EINVAL, "state was taken from a job of another shape or layout");
   const char* p = static_cast<const char*>(buf) + sizeof(h);
@@ -797,7 +876,11 @@ PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
     p += sizeof(int32_t) * 2 * lat;
     PT_HIP(job, hipMemcpyAsync(job->trips, p, sizeof(uint64_t) * 32 * 3 * (size_t)g.S,
                                hipMemcpyHostToDevice, st));
+    p += sizeof(uint64_t) * 32 * 3 * (size_t)g.S;
   }
+  if (job->track_modes)
+    PT_HIP(job, hipMemcpyAsync(job->modes, p, sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1),
+                               hipMemcpyHostToDevice, st));
   PT_HIP(job, hipStreamSynchronize(st));
   return PT_OK;
 }

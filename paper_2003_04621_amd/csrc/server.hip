@@ -350,7 +350,7 @@ PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* tick
       req->burn_in > req->sweeps)
     return pt_fail(PT_EINVAL, "pt_server_submit: need samples >= 1, replicas >= 2, 0 <= burn_in <= sweeps");
   if (req->flags & ~(uint32_t)PT_MCS_HOUDAYER) return pt_fail(PT_EINVAL, "pt_server_submit: unknown flags");
-  const uint32_t layout = req->layout & ~(uint32_t)PT_TRACK_WALK;
+  const uint32_t layout = req->layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
   if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED)
     return pt_fail(PT_EINVAL, "pt_server_submit: unknown layout");
   for (int k = 0; k < req->replicas; ++k)

@@ -223,16 +223,69 @@ hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t
 // ---------------------------------------------------------------------------
 // measurement: one block per (sample, temperature)
 // ---------------------------------------------------------------------------
+// Plane counts cnt[mu][x] of the sites where the two replicas differ (the
+// per-site form of the two-replica modes), by LDS atomics.
+__device__ __forceinline__ void plane_counts_int8(const Geo& g, const int8_t* sa, const int8_t* sb,
+                                                  int32_t* cnt) {
+  const int L = g.L;
+  for (int i = threadIdx.x; i < g.N; i += blockDim.x) {
+    if (sa[i] == sb[i]) continue;
+    const int r = i / L, x0 = i - r * L, x2 = r / L, x1 = r - x2 * L;
+    atomicAdd(&cnt[x0], 1);
+    atomicAdd(&cnt[L + x1], 1);
+    if (g.d == 3) atomicAdd(&cnt[2 * L + x2], 1);
+  }
+}
+
+__device__ __forceinline__ void plane_counts_packed(const Geo& g, const uint32_t* sa,
+                                                    const uint32_t* sb, int32_t* cnt) {
+  const int L = g.L;
+  for (int w = threadIdx.x; w < g.NW; w += blockDim.x) {
+    const WordNb q = word_nb(g, w);
+    for (int c = 0; c < 2; ++c) {
+      uint32_t X = (sa[c * g.NW + w] ^ sb[c * g.NW + w]) & g.maskW;
+      while (X) {
+        const int j = __ffs(X) - 1;
+        X &= X - 1;
+        const int f = j / g.H, bb = j - f * g.H;
+        const int x0 = 2 * bb + ((c + q.par) & 1), xs = f * g.B + q.xs;
+        atomicAdd(&cnt[x0], 1);
+        if (g.d == 3) {
+          atomicAdd(&cnt[L + q.x1], 1);
+          atomicAdd(&cnt[2 * L + xs], 1);
+        } else {
+          atomicAdd(&cnt[L + xs], 1);
+        }
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_measure(Geo g, const void* spins, const int32_t* __restrict__ E,
                                                  const int32_t* __restrict__ sot, int64_t* mom,
-                                                 DevCounters* ctr) {
+                                                 int64_t* modes, DevCounters* ctr) {
   __shared__ int red;
+  __shared__ int32_t cnt[3 * 64];
   const int pair = blockIdx.x;  // s*NT + k
   const int s = pair / g.NT, k = pair - s * g.NT;
   const int a = sot[((size_t)s * 2 + 0) * g.NT + k];
   const int b = g.NT + sot[((size_t)s * 2 + 1) * g.NT + k];
   if (threadIdx.x == 0) red = 0;
+  if (modes)
+    for (int i = threadIdx.x; i < 3 * g.L; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
+  if (modes) {
+    if (g.layout == kLayoutPacked) {
+      const uint32_t* base = static_cast<const uint32_t*>(spins) + (size_t)s * g.nslot * 2 * g.NW;
+      plane_counts_packed(g, base + (size_t)a * 2 * g.NW, base + (size_t)b * 2 * g.NW, cnt);
+    } else {
+      const int8_t* base = static_cast<const int8_t*>(spins) + (size_t)s * g.nslot * g.N;
+      plane_counts_int8(g, base + (size_t)a * g.N, base + (size_t)b * g.N, cnt);
+    }
+    __syncthreads();
+    const int MH = g.L / 2 + 1;
+    if ((int)threadIdx.x < MH) modes[(size_t)pair * MH + threadIdx.x] += mode_autocorr(g, cnt, threadIdx.x);
+  }
   int neg = 0;
   if (g.layout == kLayoutPacked) {
     const uint32_t* sa = static_cast<const uint32_t*>(spins) + ((size_t)s * g.nslot + a) * 2 * g.NW;
@@ -267,9 +320,9 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* spins, const
 }
 
 hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E, const int32_t* sot,
-                          int64_t* mom, DevCounters* ctr, hipStream_t st) {
+                          int64_t* mom, int64_t* modes, DevCounters* ctr, hipStream_t st) {
   hipLaunchKernelGGL(k_measure, dim3((unsigned)(g.S * g.NT)), dim3(256), 0, st, g, spins, E, sot, mom,
-                     ctr);
+                     modes, ctr);
   return hipGetLastError();
 }
 

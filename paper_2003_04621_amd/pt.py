@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libptsg.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
 PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
 PT_TRACK_WALK = 0x10
+PT_TRACK_MODES = 0x20
 PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE"}
@@ -29,6 +30,7 @@ EXPORTS = [
     "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_measure", "pt_mcs",
     "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_walk", "pt_tunnel_summary",
+    "pt_get_modes", "pt_correlation_length",
     "pt_get_state", "pt_set_state",
     "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
@@ -79,6 +81,7 @@ def lib():
             "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
             "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
             "pt_get_walk": [P, P, P, P], "pt_tunnel_summary": [P, I32, U64, P, P, P, P],
+            "pt_get_modes": [P, P], "pt_correlation_length": [P, P, P, P],
             "pt_get_state": [P, P, C.POINTER(C.c_size_t)], "pt_set_state": [P, P, C.c_size_t],
             "pt_set_stream": [P, P], "pt_set_allocator": [_ALLOC, _FREE, P],
             "pt_batch_create": [P, I32, C.POINTER(P)], "pt_batch_set_stream": [P, P],
@@ -170,10 +173,10 @@ def _destroy_live_jobs():
 class Job:
     """Owning handle of a pt_job plus its shape."""
 
-    def __init__(self, handle, samples, replicas, L, dim, layout, walk=False):
+    def __init__(self, handle, samples, replicas, L, dim, layout, walk=False, modes=False):
         self.h = handle
         self.S, self.NT, self.L, self.d, self.layout = samples, replicas, L, dim, layout
-        self.walk = bool(walk)
+        self.walk, self.modes = bool(walk), bool(modes)
         self.N = L ** dim
         _live_jobs.add(self)
 
@@ -187,10 +190,11 @@ class Job:
 
 
 def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_INT8,
-            stream=None, walk=False) -> Job:
+            stream=None, walk=False, modes=False) -> Job:
     """Creates a job; `stream` is a torch.cuda.Stream, a raw hipStream_t int,
     or None for torch's current stream (torch memory hooks are installed);
-    `walk` keeps the replica walk and its round trips (PT_TRACK_WALK)."""
+    `walk` keeps the replica walk and its round trips (PT_TRACK_WALK), `modes`
+    the two-replica modes (PT_TRACK_MODES)."""
     import torch
     if _hooks is None:
         use_torch_memory()
@@ -203,8 +207,9 @@ def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_
     h = C.c_void_p()
     _check(lib().pt_init_ex(C.byref(h), int(samples), int(replicas), int(L), int(dim), _p(J),
                             _p(b), C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
-                            int(layout) | (PT_TRACK_WALK if walk else 0)))
-    job = Job(h, int(samples), int(replicas), int(L), int(dim), int(layout), walk)
+                            int(layout) | (PT_TRACK_WALK if walk else 0)
+                            | (PT_TRACK_MODES if modes else 0)))
+    job = Job(h, int(samples), int(replicas), int(L), int(dim), int(layout), walk, modes)
     if stream is None:
         stream = torch.cuda.current_stream()
     pt_set_stream(job, stream)
@@ -252,20 +257,21 @@ def pt_get_plan(job: Job, houdayer=False, measure=False, plain=False) -> dict:
 
 
 def pt_plan_query(dim: int, L: int, replicas: int, houdayer=False, measure=False,
-                  plain=False, walk=False) -> dict:
+                  plain=False, walk=False, modes=False) -> dict:
     """pt_get_plan's report for a job of this shape, without creating it
     (host only)."""
     flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
-             | (PT_MCS_PLAIN if plain else 0) | (PT_TRACK_WALK if walk else 0))
+             | (PT_MCS_PLAIN if plain else 0) | (PT_TRACK_WALK if walk else 0)
+             | (PT_TRACK_MODES if modes else 0))
     out = np.zeros(4, np.int32)
     _check(lib().pt_plan_query(int(dim), int(L), int(replicas), flags, _p(out)))
     return dict(mode=int(out[0]), parts=int(out[1]), per_part=int(out[2]), lds_bytes=int(out[3]))
 
 
 def pt_job_bytes(samples: int, replicas: int, L: int, dim: int, betas, layout: int = PT_LAYOUT_INT8,
-                 walk: bool = False) -> int:
+                 walk: bool = False, modes: bool = False) -> int:
     """Upper bound of the device bytes of a job of this shape (host only)."""
-    layout = int(layout) | (PT_TRACK_WALK if walk else 0)
+    layout = int(layout) | (PT_TRACK_WALK if walk else 0) | (PT_TRACK_MODES if modes else 0)
     b = np.ascontiguousarray(betas, dtype=np.float64)
     if b.size != replicas:
         raise PTError(PT_EINVAL, "betas must have `replicas` entries")
@@ -336,6 +342,22 @@ def pt_get_walk(job: Job):
     trips = np.zeros((job.S, 32, 3), np.uint64)
     _check(lib().pt_get_walk(job.h, _p(lab), _p(beg), _p(trips)))
     return lab, beg, trips
+
+
+def pt_get_modes(job: Job) -> np.ndarray:
+    """Accumulated two-replica modes A(delta), [S][NT][L/2+1] int64."""
+    out = np.zeros((job.S, job.NT, job.L // 2 + 1), np.int64)
+    _check(lib().pt_get_modes(job.h, _p(out)))
+    return out
+
+
+def pt_correlation_length(job: Job):
+    """(chi_SG(0), chi_SG(k_min), xi) per temperature, disorder-averaged."""
+    c0 = np.zeros(job.NT, np.float64)
+    ck = np.zeros(job.NT, np.float64)
+    xi = np.zeros(job.NT, np.float64)
+    _check(lib().pt_correlation_length(job.h, _p(c0), _p(ck), _p(xi)))
+    return c0, ck, xi
 
 
 def pt_tunnel_summary(trips, passes: int):

@@ -1,0 +1,134 @@
+"""GPU parity of the two-replica modes (spin-glass susceptibility and
+correlation length; Sec. 3 names them, the usual definitions are used).
+
+The accumulated A(delta) sums must equal the oracle's bit for bit on every
+measurement path (fused with compile-time and run-time geometry, with and
+without Houdayer moves, both spin layouts, the per-step kernels, batches, jobs
+too large for one workgroup), chi_SG and xi must agree to 1e-12, and at the
+full 3D L=16 size the sum rule sum_delta A(delta) = d Q^2 ties every sample's
+modes to its overlap moment."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_04621_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2003_04621_amd import pt as _pt
+    _pt.lib()
+    return _pt
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def same_modes(pt, job, ref, what):
+    gm = pt.pt_get_modes(job)
+    rm = ref.modes()
+    assert (gm == rm).all(), f"{what}: modes differ at {np.argwhere(gm != rm)[:5]}"
+    assert (pt.pt_get_moments(job)["Q2"] == ref.moments()["Q2"]).all(), what
+    c0, ck, xi = pt.pt_correlation_length(job)
+    n = pt.pt_get_counters(job)["n_meas"]
+    r0, rk, rxi = oracle.correlation_length(rm, ref.moments()["Q2"], n, job.L, job.d)
+    np.testing.assert_allclose(c0, r0, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(ck, rk, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(xi, rxi, rtol=1e-11, atol=0, equal_nan=True)
+
+
+CASES = [
+    # (name, dim, L, samples, replicas, layout, houdayer, how)
+    ("fused 3D L=8", 3, 8, 3, 4, 0, False, "mcs"),
+    ("fused 3D L=16 (compile-time shape)", 3, 16, 2, 5, 0, False, "mcs"),
+    ("fused 3D L=12 packed", 3, 12, 2, 3, 1, False, "mcs"),
+    ("fused 3D L=6", 3, 6, 2, 3, 0, True, "mcs"),
+    ("fused 2D L=10", 2, 10, 3, 4, 1, False, "mcs"),
+    ("fused 2D L=64 Houdayer", 2, 64, 2, 4, 0, True, "mcs"),
+    ("plain 3D L=8 int8", 3, 8, 2, 3, 0, False, "plain"),
+    ("plain 3D L=12 packed", 3, 12, 2, 3, 1, False, "plain"),
+    ("plain 2D L=14 packed", 2, 14, 2, 3, 1, True, "plain"),
+    ("batch 3D L=8", 3, 8, 2, 4, 0, False, "batch"),
+    ("per-step fallback 3D L=32", 3, 32, 1, 24, 0, False, "mcs"),
+]
+
+
+@pytest.mark.parametrize("name,d,L,S,NT,layout,hou,how", CASES)
+def test_modes_vs_oracle(pt, name, d, L, S, NT, layout, hou, how):
+    say(f"modes case {name}: S={S} NT={NT}")
+    J = W.couplings_pm_j(S, L, d, 40 + L)
+    betas = W.geometric_betas(0.7, 2.2, NT)
+    seed = 777 + L + NT
+    job = pt.pt_init(S, NT, L, d, J, betas, seed, layout=layout, modes=True)
+    ref = oracle.OracleJob(S, NT, L, d, J, betas, seed)
+    ref.enable_modes()
+    steps = (3, 2) if L >= 32 else (11, 9)
+    batch = None
+    if how == "batch":
+        other = pt.pt_init(1, 3, 6, d, W.couplings_pm_j(1, 6, d, 5), W.geometric_betas(1.0, 2.0, 3), 9)
+        batch = pt.pt_batch_create([job, other])
+    for n in steps:
+        if batch is not None:
+            pt.pt_batch_run(batch, n, houdayer=hou, measure=True)
+        else:
+            pt.pt_mcs(job, n, houdayer=hou, measure=True, plain=how == "plain")
+        ref.mcs(n, houdayer=hou, measure=True)
+        same_modes(pt, job, ref, f"{name} after {n}")
+    if batch is not None:
+        pt.pt_batch_destroy(batch)
+
+
+def test_modes_full_size_sum_rule_and_samples(pt):
+    """3D L=16, 1000 samples x 2 x 32 temperatures, in the benchmark's launch
+    configuration: the sum rule for every sample and temperature, and two
+    samples re-run by the oracle."""
+    wl = W.workload("3d_l16")
+    say(f"case {wl.name} with modes, S={wl.samples} NT={wl.replicas}")
+    J = wl.couplings()
+    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed, modes=True)
+    pt.pt_mcs(job, 10, measure=True)
+    A = pt.pt_get_modes(job)
+    Q2 = pt.pt_get_moments(job)["Q2"]
+    L = wl.L
+    ext = 2 * A.sum(axis=2) - A[:, :, 0] - A[:, :, L // 2]
+    assert (ext == wl.dim * Q2).all()
+    picks = [0, wl.samples - 1]
+    ref = oracle.OracleJob(len(picks), wl.replicas, wl.L, wl.dim, J[picks], wl.betas, wl.seed,
+                           sample_keys=picks)
+    ref.enable_modes()
+    ref.mcs(10, measure=True)
+    assert (A[picks] == ref.modes()).all()
+
+
+def test_modes_are_opt_in_and_checkpointed(pt):
+    d, L, S, NT = 3, 8, 2, 3
+    J = W.couplings_pm_j(S, L, d, 3)
+    b = W.geometric_betas(0.8, 2.0, NT)
+    plain_job = pt.pt_init(S, NT, L, d, J, b, 6)
+    with pytest.raises(pt.PTError):
+        pt.pt_get_modes(plain_job)
+    with pytest.raises(pt.PTError):
+        pt.pt_correlation_length(plain_job)
+    a = pt.pt_init(S, NT, L, d, J, b, 6, modes=True, walk=True)
+    pt.pt_mcs(a, 7, measure=True)
+    pt.pt_mcs(plain_job, 7, measure=True)
+    assert (pt.pt_get_spins(a) == pt.pt_get_spins(plain_job)).all()
+    st = pt.pt_get_state(a)
+    with pytest.raises(pt.PTError):
+        pt.pt_set_state(plain_job, st)
+    c = pt.pt_init(S, NT, L, d, J, b, 6, modes=True, walk=True)
+    pt.pt_set_state(c, st)
+    pt.pt_mcs(a, 5, measure=True)
+    pt.pt_mcs(c, 5, measure=True)
+    assert (pt.pt_get_modes(a) == pt.pt_get_modes(c)).all()
+    ref = oracle.OracleJob(S, NT, L, d, J, b, 6)
+    ref.enable_modes()
+    ref.mcs(12, measure=True)
+    same_modes(pt, c, ref, "restored")
+    assert pt.pt_plan_query(3, 32, 24, measure=True, modes=True)["mode"] == -1  # per-step kernels
+    assert pt.pt_plan_query(3, 32, 24, measure=True)["mode"] == 3

@@ -58,6 +58,13 @@ def test_plain_flag_and_known_shapes(lib):
     w = pt.pt_plan_query(3, 16, 32, measure=True, walk=True)
     assert w == {"mode": 0, "parts": 1, "per_part": 64,
                  "lds_bytes": 40056 + 4 * 2 * 64 + 8 * 32 * 3}
+    # keeping the two-replica modes adds 16 wavefronts' plane counters (3 L
+    # words each) and the item's mode sums (N_T x (L/2 + 1) 64-bit)
+    m = pt.pt_plan_query(3, 16, 32, measure=True, modes=True)
+    assert m == {"mode": 0, "parts": 1, "per_part": 64,
+                 "lds_bytes": 40056 + 4 * 16 * 3 * 16 + 8 * 32 * 9}
+    # a job keeping the modes never splits a sample: it runs the per-step kernels
+    assert pt.pt_plan_query(3, 48, 48, measure=True, modes=True)["mode"] == -1
     p = pt.pt_plan_query(3, 48, 48, measure=True)
     assert p["mode"] == 3 and p["parts"] == 12 and p["per_part"] == 8
     assert pt.pt_plan_query(2, 64, 24, houdayer=True, measure=True)["mode"] == 1
@@ -80,6 +87,7 @@ def test_job_bytes(lib):
     assert packed < many
     # the replica walk: two words per slot and 32 x 3 64-bit sums per sample
     assert pt.pt_job_bytes(1000, 32, 16, 3, b, walk=True) == many + 1000 * (64 * 8 + 768)
+    assert pt.pt_job_bytes(1000, 32, 16, 3, b, modes=True) == many + 1000 * 32 * 9 * 8
     # a split plan brings its scratch: published energies and configurations
     b48 = 1.0 / np.linspace(0.9, 2.0, 48)
     assert pt.pt_job_bytes(1, 48, 48, 3, b48) > 96 * 48 ** 3 + 2 * 96 * 2 * 2304 * 4
