@@ -242,6 +242,8 @@ def main():
                     help="steps re-timed with one launch per kernel (0: skip)")
     ap.add_argument("--walk-steps", type=int, default=1000,
                     help="steps of the same workload with the replica walk kept (0: skip)")
+    ap.add_argument("--modes-steps", type=int, default=1000,
+                    help="steps of the same workload measuring the two-replica modes (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-jobs", type=int, default=2000)
@@ -360,6 +362,27 @@ def main():
                 "equilibrated": eq}
         pt.pt_destroy(wj)
 
+    # the same workload measuring the two-replica modes at every step
+    modes = None
+    if args.modes_steps > 0:
+        print("# two-replica modes measured", file=sys.stderr, flush=True)
+        mj = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed,
+                        layout=layout, modes=True)
+        pt.pt_mcs(mj, args.warmup, houdayer=wl.houdayer)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        for st in range(0, args.modes_steps, chunk):
+            pt.pt_mcs(mj, min(chunk, args.modes_steps - st), houdayer=wl.houdayer, measure=True)
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - tm
+        c0, ck, xi = pt.pt_correlation_length(mj)
+        modes = {"value": round(flips_per_step * args.modes_steps / dtm / 1e9, 2), "unit": "flips/ns",
+                 "steps": args.modes_steps,
+                 "chi_sg_coldest": round(float(c0[0]), 4), "chi_sg_kmin_coldest": round(float(ck[0]), 4),
+                 "xi_coldest": None if np.isnan(xi[0]) else round(float(xi[0]), 4),
+                 "xi_hottest": None if np.isnan(xi[-1]) else round(float(xi[-1]), 4)}
+        pt.pt_destroy(mj)
+
     batched = None
     if not args.no_batched:
         print("# batched form", file=sys.stderr, flush=True)
@@ -386,6 +409,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_form": plain,
         "replica_walk": walk,
+        "modes": modes,
         "batched": batched,
         "served": serve,
         "e_coldest": round(float(dis[0, 0]), 6), "binder_coldest": round(float(dis[0, 5]), 6),

@@ -238,17 +238,18 @@ __device__ __forceinline__ void modes_resident(const Geo& g, const FusedLayout& 
         if (n) atomicAdd(&cnt[(g.d - 1) * L + f * g.B + q.xs], n);
       }
     }
-    const uint64_t podd = __ballot(par);
-    for (int f = 0; f < g.P; ++f)
-      for (int bb = 0; bb < g.H; ++bb) {
+    // colour-0 words hold the sites of x0 parity par, colour-1 words the other
+    const uint32_t XE = par ? X1 : X0, XO = par ? X0 : X1;
+    for (int bb = 0; bb < g.H; ++bb) {
+      int even = 0, odd = 0;
+      for (int f = 0; f < g.P; ++f) {
         const int j = f * g.H + bb;
-        const uint64_t m0 = __ballot((X0 >> j) & 1u), m1 = __ballot((X1 >> j) & 1u);
-        // colour-0 words hold x0 of parity par, colour-1 words the other one
-        const int even = __popcll(m0 & ~podd) + __popcll(m1 & podd);
-        const int odd = __popcll(m0 & podd) + __popcll(m1 & ~podd);
-        if (lane == 2 * bb) col += even;
-        if (lane == 2 * bb + 1) col += odd;
+        even += __popcll(__ballot((XE >> j) & 1u));
+        odd += __popcll(__ballot((XO >> j) & 1u));
       }
+      if (lane == 2 * bb) col += even;
+      if (lane == 2 * bb + 1) col += odd;
+    }
   }
   if (lane < L) cnt[lane] = col;
   wave_lds_sync();
