@@ -89,16 +89,22 @@ typedef struct {
   uint64_t seed;
   int32_t sweeps;                    /* Monte Carlo steps in total */
   int32_t burn_in;                   /* steps before the first measurement */
-  uint32_t flags;                    /* PT_MCS_HOUDAYER or 0 */
-  uint32_t layout;                   /* PT_LAYOUT_INT8 or PT_LAYOUT_PACKED */
+  uint32_t flags;                    /* PT_MCS_HOUDAYER and/or PT_SERVE_UNTIL_EQUILIBRATED, or 0 */
+  uint32_t layout;                   /* PT_LAYOUT_INT8 or PT_LAYOUT_PACKED, | PT_TRACK_WALK */
 } pt_request;
+
+/* pt_request flag: the job ends between rounds, once past its burn-in, as soon
+ * as its round trips pass the logarithmic-binning check of pt_tunnel_summary
+ * (Sec. 2.3); `sweeps` is then an upper bound.  Needs PT_TRACK_WALK. */
+#define PT_SERVE_UNTIL_EQUILIBRATED 0x100u
 
 /* The outcome of a request; times in seconds since pt_server_start. */
 typedef struct {
-  int32_t status; /* PT_OK, or the error that ended the request */
-  int32_t reserved;
-  int64_t n_meas;
+  int32_t status;       /* PT_OK, or the error that ended the request */
+  int32_t equilibrated; /* with PT_TRACK_WALK: the round-trip check, 1 or 0; else -1 */
+  int64_t n_meas;       /* measurements taken (steps after the burn-in) */
   double t_submit, t_admit, t_done;
+  double tau_tunnel;    /* with PT_TRACK_WALK: mean round trip in passes (NaN if none) */
 } pt_result;
 
 /* Creates a job: copies the couplings in, draws the initial spins (one
@@ -349,7 +355,9 @@ int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server **out)
 int pt_server_submit(pt_server *s, const pt_request *req, uint64_t *ticket);
 /* Returns 1 while the request is queued or running; PT_OK once it finished,
  * filling *out and (if not NULL) disorder [replicas][6] as pt_observables,
- * after which the ticket is forgotten; PT_EINVAL for an unknown ticket. */
+ * after which the ticket is forgotten; PT_EINVAL for an unknown ticket.  A
+ * request's layout may carry PT_TRACK_WALK (results then include the
+ * round-trip time), not PT_TRACK_MODES (PT_EINVAL at submission). */
 int pt_server_poll(pt_server *s, uint64_t ticket, pt_result *out, double *disorder);
 /* out[8] = {attempted flips completed, busy seconds, rounds, admitted,
  *           completed, peak admitted bytes, peak concurrent jobs, uptime s} */

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <limits>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -48,7 +49,22 @@ struct Finished {
   int64_t n_meas = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::vector<double> disorder;  // [NT][6]
+  double tau = 0;                // round-trip time (walk kept), else NaN
+  int equilibrated = -1;         // its logarithmic-binning check, else -1
 };
+
+// Round-trip summary of a job keeping the replica walk (Sec. 2.3): mean trip
+// length and the logarithmic-binning check after the job's exchange passes.
+int walk_summary(pt_job* job, double& tau, int& eq) {
+  std::vector<uint64_t> trips((size_t)job->g.S * 32 * 3);
+  uint64_t ctr[4];
+  if (int rc = pt_get_walk(job, nullptr, nullptr, trips.data())) return rc;
+  if (int rc = pt_get_counters(job, ctr)) return rc;
+  int32_t e = 0;
+  if (int rc = pt_tunnel_summary(trips.data(), job->g.S, ctr[1], nullptr, nullptr, &tau, &e)) return rc;
+  eq = e;
+  return PT_OK;
+}
 
 }  // namespace
 
@@ -105,9 +121,11 @@ void finish(pt_server* sv, Active& a, int status) {
   f.t_submit = a.req.t_submit;
   f.t_admit = a.t_admit;
   f.disorder.assign((size_t)a.req.NT * 6, 0.0);
+  f.tau = std::numeric_limits<double>::quiet_NaN();
   if (status == PT_OK && a.job) {
     int64_t n = 0;
-    const int rc = pt_observables(a.job, nullptr, f.disorder.data(), &n);
+    int rc = pt_observables(a.job, nullptr, f.disorder.data(), &n);
+    if (rc == PT_OK && a.job->track_walk) rc = walk_summary(a.job, f.tau, f.equilibrated);
     if (rc != PT_OK) f.status = rc;
     f.n_meas = n;
   }
@@ -127,6 +145,7 @@ void fail_request(pt_server* sv, const Request& r, int status) {
   f.t_submit = r.t_submit;
   f.t_admit = f.t_done = sv->now();
   f.disorder.assign((size_t)r.NT * 6, 0.0);
+  f.tau = std::numeric_limits<double>::quiet_NaN();
   sv->finished[r.ticket] = std::move(f);
   sv->cv_done.notify_all();
 }
@@ -286,7 +305,14 @@ void serve(pt_server* sv) {
         continue;
       }
       a.done += steps[i];
-      if (a.done >= a.req.sweeps)
+      bool end = a.done >= a.req.sweeps;
+      if (!end && (a.req.flags & PT_SERVE_UNTIL_EQUILIBRATED) && a.done > a.req.burn_in) {
+        // ends early once its round trips pass the logarithmic-binning check
+        double tau = 0;
+        int eq = 0;
+        if (walk_summary(a.job, tau, eq) == PT_OK && eq == 1) end = true;
+      }
+      if (end)
         done.push_back(std::move(a));
       else
         still.push_back(std::move(a));
@@ -349,10 +375,13 @@ PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* tick
   if (req->samples < 1 || req->replicas < 2 || req->sweeps < 0 || req->burn_in < 0 ||
       req->burn_in > req->sweeps)
     return pt_fail(PT_EINVAL, "pt_server_submit: need samples >= 1, replicas >= 2, 0 <= burn_in <= sweeps");
-  if (req->flags & ~(uint32_t)PT_MCS_HOUDAYER) return pt_fail(PT_EINVAL, "pt_server_submit: unknown flags");
-  const uint32_t layout = req->layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
+  if (req->flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_SERVE_UNTIL_EQUILIBRATED))
+    return pt_fail(PT_EINVAL, "pt_server_submit: unknown flags");
+  const uint32_t layout = req->layout & ~(uint32_t)PT_TRACK_WALK;
   if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED)
-    return pt_fail(PT_EINVAL, "pt_server_submit: unknown layout");
+    return pt_fail(PT_EINVAL, "pt_server_submit: unknown layout (the server reports no modes)");
+  if ((req->flags & PT_SERVE_UNTIL_EQUILIBRATED) && !(req->layout & PT_TRACK_WALK))
+    return pt_fail(PT_EINVAL, "pt_server_submit: stopping at equilibrium needs PT_TRACK_WALK");
   for (int k = 0; k < req->replicas; ++k)
     if (!(req->betas[k] > 0.0) || (k > 0 && !(req->betas[k] < req->betas[k - 1])))
       return pt_fail(PT_EINVAL, "pt_server_submit: betas must be > 0 and strictly decreasing");
@@ -397,6 +426,8 @@ PT_API int pt_server_poll(pt_server* sv, uint64_t ticket, pt_result* out, double
   out->t_submit = f.t_submit;
   out->t_admit = f.t_admit;
   out->t_done = f.t_done;
+  out->equilibrated = f.equilibrated;
+  out->tau_tunnel = f.tau;
   if (disorder) std::copy(f.disorder.begin(), f.disorder.end(), disorder);
   sv->finished.erase(it);
   return PT_OK;

@@ -23,6 +23,7 @@ PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
 PT_TRACK_WALK = 0x10
 PT_TRACK_MODES = 0x20
 PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
+PT_SERVE_UNTIL_EQUILIBRATED = 0x100
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE"}
 
@@ -47,8 +48,9 @@ class PTRequest(C.Structure):
 
 
 class PTResult(C.Structure):
-    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("n_meas", C.c_int64),
-                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+    _fields_ = [("status", C.c_int32), ("equilibrated", C.c_int32), ("n_meas", C.c_int64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("tau_tunnel", C.c_double)]
 
 
 class PTError(RuntimeError):
@@ -480,12 +482,15 @@ def pt_server_start(hbm_budget: int, steps_per_round: int = 100) -> Server:
 
 
 def pt_server_submit(server: Server, dim, L, replicas, samples, betas, couplings, seed, sweeps,
-                     burn_in, houdayer=False, layout=PT_LAYOUT_INT8) -> int:
+                     burn_in, houdayer=False, layout=PT_LAYOUT_INT8, walk=False,
+                     until_equilibrated=False) -> int:
     b = np.ascontiguousarray(betas, dtype=np.float64)
     J = np.ascontiguousarray(couplings, dtype=np.int8)
+    flags = (PT_MCS_HOUDAYER if houdayer else 0) | (PT_SERVE_UNTIL_EQUILIBRATED
+                                                    if until_equilibrated else 0)
     req = PTRequest(int(dim), int(L), int(replicas), int(samples), b.ctypes.data, J.ctypes.data,
-                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps), int(burn_in),
-                    PT_MCS_HOUDAYER if houdayer else 0, int(layout))
+                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps), int(burn_in), flags,
+                    int(layout) | (PT_TRACK_WALK if walk else 0))
     t = C.c_uint64(0)
     _check(lib().pt_server_submit(server.h, C.byref(req), C.byref(t)))
     server.replicas[t.value] = int(replicas)
@@ -493,7 +498,9 @@ def pt_server_submit(server: Server, dim, L, replicas, samples, betas, couplings
 
 
 def pt_server_poll(server: Server, ticket: int):
-    """None while pending; else (status, n_meas, t_submit, t_admit, t_done, disorder)."""
+    """None while pending; else a dict of status, n_meas, times, the
+    disorder averages and, for requests keeping the walk, tau_tunnel and
+    equilibrated (-1 otherwise)."""
     res = PTResult()
     nt = server.replicas[ticket]
     dis = np.zeros((nt, 6), np.float64)
@@ -503,7 +510,8 @@ def pt_server_poll(server: Server, ticket: int):
     _check(rc)
     del server.replicas[ticket]
     return dict(status=res.status, n_meas=res.n_meas, t_submit=res.t_submit,
-                t_admit=res.t_admit, t_done=res.t_done, disorder=dis)
+                t_admit=res.t_admit, t_done=res.t_done, disorder=dis,
+                tau_tunnel=res.tau_tunnel, equilibrated=res.equilibrated)
 
 
 def pt_server_stats(server: Server) -> dict:

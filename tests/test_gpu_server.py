@@ -128,3 +128,44 @@ def test_server_rejects_oversized_and_bad_requests(pt):
     with pytest.raises(pt.PTError):
         pt.pt_server_submit(srv, 3, 31, 16, 1, b, J, seed, 5, 0)      # odd L
     pt.pt_server_stop(srv)
+
+
+def test_server_reports_round_trips_and_stops_at_equilibrium(pt):
+    """A request keeping the replica walk returns its round-trip time and the
+    logarithmic-binning check (Sec. 2.3), equal to the same job run alone; one
+    asking to stop at equilibrium ends early, between rounds, with the check
+    passed, and equals the job run alone for the steps it took."""
+    dim, L, NT, S = 3, 4, 4, 2
+    J = W.couplings_pm_j(S, L, dim, 61)
+    b = W.geometric_betas(1.8, 2.6, NT)
+    srv = pt.pt_server_start(1 << 30, steps_per_round=37)
+    t_walk = pt.pt_server_submit(srv, dim, L, NT, S, b, J, 71, 300, 20, walk=True)
+    t_plain = pt.pt_server_submit(srv, dim, L, NT, S, b, J, 71, 300, 20)
+    t_eq = pt.pt_server_submit(srv, dim, L, NT, S, b, J, 72, 20000, 10, walk=True,
+                               until_equilibrated=True)
+    res = _wait(pt, srv, {"walk": t_walk, "plain": t_plain, "eq": t_eq})
+    pt.pt_server_stop(srv)
+    assert res["plain"]["equilibrated"] == -1 and np.isnan(res["plain"]["tau_tunnel"])
+    for key, seed, steps in (("walk", 71, 300), ("eq", 72, res["eq"]["n_meas"] + 10)):
+        r = res[key]
+        assert r["status"] == 0
+        job = pt.pt_init(S, NT, L, dim, J, b, seed, walk=True)
+        pt.pt_mcs(job, 10 if key == "eq" else 20)
+        pt.pt_mcs(job, steps - (10 if key == "eq" else 20), measure=True)
+        _, dis, nm = pt.pt_observables(job)
+        _, _, tau, eq = pt.pt_tunnel_summary(pt.pt_get_walk(job)[2], steps)
+        assert nm == r["n_meas"] and np.array_equal(r["disorder"], dis)
+        assert r["tau_tunnel"] == tau and r["equilibrated"] == eq
+        pt.pt_destroy(job)
+    assert res["eq"]["equilibrated"] == 1 and res["eq"]["n_meas"] < 20000 - 10
+
+
+def test_server_rejects_modes_and_unguarded_stop(pt):
+    srv = pt.pt_server_start(1 << 24, steps_per_round=3)
+    J = W.couplings_pm_j(1, 4, 3, 1)
+    b = W.geometric_betas(1.0, 2.0, 3)
+    with pytest.raises(pt.PTError):
+        pt.pt_server_submit(srv, 3, 4, 3, 1, b, J, 1, 10, 0, layout=pt.PT_TRACK_MODES)
+    with pytest.raises(pt.PTError):
+        pt.pt_server_submit(srv, 3, 4, 3, 1, b, J, 1, 10, 0, until_equilibrated=True)
+    pt.pt_server_stop(srv)
