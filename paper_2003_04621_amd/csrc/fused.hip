@@ -147,7 +147,55 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
     }
   }
   __syncthreads();
-  if (tid < nsets) {
+  const int wave = tid >> 6, lane = tid & 63, nwave = T >> 6;
+  if (NT <= 64) {
+    // One wavefront per set; lane k holds decision row k.  From the carried
+    // position cur the next rejection is the first step k >= cur whose
+    // decision for cur is a rejection, found by one ballot; the configuration
+    // carried up from cur stops there and the one at k + 1 is carried on.
+    for (int cs = wave; cs < nsets; cs += nwave) {
+      const int c = c_lo + cs;
+      const int32_t* m0 = sot0 + c * NT;
+      int32_t* so = sotl + c * NT;
+      int32_t* to = tosl + c * NT;
+      const uint32_t* arow = acc + (size_t)c * (NT - 1) * (NB >> 5);
+      uint64_t row = 0;
+      if (lane < NT - 1) {
+        row = arow[lane * (NB >> 5)];
+        if (NB > 32) row |= (uint64_t)arow[lane * (NB >> 5) + 1] << 32;
+      }
+      uint64_t rej = 0;  // steps that rejected
+      int cur = 0;
+      for (;;) {
+        const uint64_t r = __ballot(lane >= cur && lane < NT - 1 && !((row >> cur) & 1u));
+        if (r == 0) break;
+        const int k = __ffsll((unsigned long long)r) - 1;
+        rej |= 1ull << k;
+        cur = k + 1;
+      }
+      // a rejecting step keeps the configuration carried from just after the
+      // previous rejection (or from 0); an accepting one takes the one above
+      if (lane < NT - 1) {
+        int fin;
+        if ((rej >> lane) & 1u) {
+          const uint64_t below = rej & ((1ull << lane) - 1u);
+          fin = m0[below ? 64 - __clzll((long long)below) : 0];
+        } else {
+          fin = m0[lane + 1];
+        }
+        so[lane] = fin;
+        to[fin] = lane;
+      }
+      if (lane == 0) {
+        const int hot = m0[cur];
+        so[NT - 1] = hot;
+        to[hot] = NT - 1;
+        if (WALK && walk)
+          walk_observe(reinterpret_cast<int32_t*>(lds + A.lay.walk) + 2 * c * NT,
+                       reinterpret_cast<uint64_t*>(lds + A.lay.trip), so[0], hot, m);
+      }
+    }
+  } else if (tid < nsets) {
     const int c = c_lo + tid;
     const int32_t* m0 = sot0 + c * NT;
     int32_t* so = sotl + c * NT;
