@@ -297,3 +297,26 @@ def test_full_run_small3d(pt):
     compare(pt, job, ref, "small3d full run")
     compare_observables(pt, job, ref)
     pt.pt_destroy(job)
+
+
+@pytest.mark.parametrize("NT", [2, 31, 32, 33, 63, 64, 65])
+def test_exchange_ladder_sizes(pt, NT):
+    """The exchange walk at the ladder sizes where its form changes: decision
+    rows of one or two words (N_T = 32 / 33), the last ladder one wavefront
+    walks by ballots (64) and the first one walked serially (65); every bit
+    of the state and the walk against the oracle after fused and per-step
+    steps, with narrow spacing so that most exchanges are accepted and long
+    chains form."""
+    d, L, S = 2, 4, 2
+    J = W.couplings_pm_j(S, L, d, 900 + NT)
+    betas = W.geometric_betas(1.0, 1.6, NT)
+    say(f"ladder case NT={NT}")
+    job = pt.pt_init(S, NT, L, d, J, betas, 31 + NT, walk=True)
+    ref = oracle.OracleJob(S, NT, L, d, J, betas, 31 + NT)
+    pt.pt_mcs(job, 25, measure=True)
+    ref.mcs(25, measure=True)
+    compare(pt, job, ref, "fused")
+    pt.pt_mcs(job, 5, measure=True, plain=True)
+    ref.mcs(5, measure=True)
+    compare(pt, job, ref, "per-step")
+    pt.pt_destroy(job)
