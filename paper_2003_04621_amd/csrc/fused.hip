@@ -251,6 +251,8 @@ __device__ __forceinline__ void add_moments(const Geo& g, int64_t* m, int32_t ea
 // temperature counts the sites where its two replicas differ and adds the
 // moments.
 // ---------------------------------------------------------------------------
+typedef short __attribute__((ext_vector_type(2))) Short2;
+
 // The two-replica modes of temperature k (mode_autocorr) by one wavefront,
 // from the resident words of its two replicas: plane counts of the differing
 // sites in the wavefront's LDS counters (slow axes by LDS atomics per word
@@ -301,7 +303,43 @@ __device__ __forceinline__ void modes_resident(const Geo& g, const FusedLayout& 
   }
   if (lane < L) cnt[lane] = col;
   wave_lds_sync();
-  if (lane < MH) acc[lane] += mode_autocorr(g, cnt, lane);
+  // Plane sums P = L^(d-1) - 2 cnt (|P| <= 2^12) packed in 16-bit pairs, in
+  // place: per axis the L/2 even-aligned pairs (P(2i), P(2i+1)), then the L/2
+  // odd-aligned ones (P(2i+1), P(2i+2 mod L)).  sum_x P(x) P(x + delta) is then
+  // L/2 two-way dot products of pair i with the pair starting at 2i + delta,
+  // an even- or odd-aligned one as delta is even or odd.
+  const int half = L / 2, plane = g.N / L;
+  uint32_t pe[3] = {0, 0, 0}, po[3] = {0, 0, 0};
+  if (lane < half)
+    for (int mu = 0; mu < g.d; ++mu) {
+      const int32_t* c = cnt + mu * L;
+      const int a = plane - 2 * c[2 * lane], b = plane - 2 * c[2 * lane + 1];
+      const int e = plane - 2 * c[(2 * lane + 2) % L];
+      pe[mu] = ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
+      po[mu] = ((uint32_t)b & 0xFFFFu) | ((uint32_t)e << 16);
+    }
+  wave_lds_sync();
+  if (lane < half)
+    for (int mu = 0; mu < g.d; ++mu) {
+      cnt[mu * L + lane] = (int32_t)pe[mu];
+      cnt[mu * L + half + lane] = (int32_t)po[mu];
+    }
+  wave_lds_sync();
+  if (lane < MH) {
+    int64_t A = 0;
+    for (int mu = 0; mu < g.d; ++mu) {
+      const Short2* E = reinterpret_cast<const Short2*>(cnt + mu * L);
+      const Short2* Y = E + ((lane & 1) ? half : 0);
+      int32_t sum = 0;  // <= L 2^24 <= 2^30
+      int j = lane >> 1;
+      for (int i = 0; i < half; ++i) {
+        sum = __builtin_amdgcn_sdot2(E[i], Y[j], sum, false);
+        if (++j == half) j = 0;
+      }
+      A += sum;
+    }
+    acc[lane] += A;
+  }
   wave_lds_sync();
 }
 

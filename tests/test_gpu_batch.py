@@ -225,3 +225,36 @@ def test_full_size_batched_mix_sampled(pt):
     pt.pt_batch_destroy(batch)
     for j in jobs:
         pt.pt_destroy(j)
+
+
+def test_tuner_restores_walk_and_modes(pt):
+    """Tuning trials run on a snapshot: the replica walk, its round-trip sums
+    and the two-replica modes are restored with everything else, so a tuned
+    batch of jobs keeping them continues bit-exactly (graph-replayed too)."""
+    shapes = [(4, 2, 5, 0), (8, 1, 4, 1), (6, 2, 3, 0)]
+    jobs, refs = [], []
+    for n, (L, S, NT, layout) in enumerate(shapes):
+        J = W.couplings_pm_j(S, L, 3, 300 + n)
+        b = W.geometric_betas(1.6, 2.4, NT)
+        jobs.append(pt.pt_init(S, NT, L, 3, J, b, 3000 + n, layout=layout, walk=True, modes=True))
+        r = oracle.OracleJob(S, NT, L, 3, J, b, 3000 + n)
+        r.enable_modes()
+        refs.append(r)
+    batch = pt.pt_batch_create(jobs)
+    pt.pt_batch_run(batch, 30, measure=True)
+    for r in refs:
+        r.mcs(30, measure=True)
+    before = [state(pt, j) for j in jobs]
+    modes_before = [pt.pt_get_modes(j) for j in jobs]
+    with tempfile.TemporaryDirectory() as d:
+        pt.pt_batch_tune(batch, 7, measure=True, cache_path=os.path.join(d, "tune.jsonl"))
+    for j, s0, m0 in zip(jobs, before, modes_before):
+        assert same_state(state(pt, j), s0)
+        assert (pt.pt_get_modes(j) == m0).all()
+    pt.pt_batch_run(batch, 40, measure=True, graph=True)
+    for r in refs:
+        r.mcs(40, measure=True)
+    for j, r in zip(jobs, refs):
+        matches_oracle(pt, j, r)
+        assert (pt.pt_get_modes(j) == r.modes()).all()
+    assert sum(int(pt.pt_get_walk(j)[2][..., 0].sum()) for j in jobs) > 0
