@@ -67,8 +67,7 @@ extern "C" {
 /* Also a pt_init_ex flag (same places as PT_TRACK_WALK): every measurement
  * also accumulates the two-replica modes of each temperature (pt_get_modes,
  * pt_correlation_length).  Off by default: the fused kernels then carry no
- * mode code.  A job keeping the modes whose two replica sets do not fit one
- * workgroup runs the per-step kernels (no split-sample plan). */
+ * mode code. */
 #define PT_TRACK_MODES 0x20u
 
 /* pt_mcs flags */

@@ -124,7 +124,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     if (mcs > 0 && meas && j->track_modes) feat |= kFeatModes;
     if (mode == 3) {
       FusedArgs A = make_fused_args(j->g, j->split_lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
-                                    j->thrpt, j->M, j->mom, j->walk, j->trips, nullptr, j->ctr, mcs,
+                                    j->thrpt, j->M, j->mom, j->walk, j->trips, j->modes, j->ctr, mcs,
                                     false, meas);
       A.parts = j->split_parts;
       A.R = j->split_R;

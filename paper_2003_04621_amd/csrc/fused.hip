@@ -986,6 +986,7 @@ __device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uin
 
 // Overlap and moments of the temperatures this part owns (k = part mod
 // parts), from the configurations published this step (`pub`: [nslot][2NW]).
+template <bool MODES>
 __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds, int part,
                                               const uint32_t* pub) {
   const Geo& g = A.g;
@@ -1010,12 +1011,21 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
   __syncthreads();
   for (int k = part + tid * A.parts; k < NT; k += T * A.parts)
     add_moments(g, mom + (size_t)k * 8, El[sotl[k]], El[NT + sotl[NT + k]], qneg[k]);
+  if (MODES && A.modes) {
+    // the owned temperatures' modes, one wavefront each, from the published words
+    const int wave = tid >> 6, lane = tid & 63, nwave = T >> 6;
+    for (int kl = wave; kl < nk; kl += nwave) {
+      const int k = part + kl * A.parts;
+      modes_resident(g, A.lay, lds, pub + (size_t)sotl[k] * W2, pub + (size_t)(NT + sotl[NT + k]) * W2,
+                     k, wave, lane);
+    }
+  }
   __syncthreads();
 }
 
 // nmcs Monte Carlo steps (sweep, exchange, measurement) of part `part` of
 // split sample s.
-template <int D, bool MEAS, bool WALK>
+template <int D, bool MEAS, bool WALK, bool MODES>
 __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int s, int part,
                                           int* flag) {
   const Geo& g = A.g;
@@ -1057,6 +1067,13 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
   for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
   if (meas)
     for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
+  // mode sums of the temperatures this part measures (k = part mod parts)
+  const bool modes = MODES && meas && A.modes != nullptr;
+  const int MH = g.L / 2 + 1;
+  int64_t* modl = reinterpret_cast<int64_t*>(lds + A.lay.modes);
+  if (modes)
+    for (int k = part; k < NT; k += A.parts)
+      for (int i = tid; i < MH; i += T) modl[k * MH + i] = A.modes[((size_t)s * NT + k) * MH + i];
   // part 0 keeps the sample's replica walk
   const bool walk = WALK && A.walk != nullptr && part == 0;
   int32_t* wkl = reinterpret_cast<int32_t*>(lds + A.lay.walk);
@@ -1086,7 +1103,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     for (int i = tid; i < nslot; i += T) El[i] = Ex[par * nslot + i];
     __syncthreads();
     exchange_resident<WALK>(A, lds, 0, 2, u + 1u, walk);
-    if (meas) measure_split(A, lds, part, snap + (size_t)par * nslot * W2);
+    if (meas) measure_split<MODES>(A, lds, part, snap + (size_t)par * nslot * W2);
   }
 
   // ---- store this part's slots; part 0 stores the maps, owners the moments
@@ -1113,6 +1130,9 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
   if (meas)
     for (int k = part; k < NT; k += A.parts)
       for (int i = tid; i < 8; i += T) A.mom[((size_t)s * NT + k) * 8 + i] = mom[k * 8 + i];
+  if (modes)
+    for (int k = part; k < NT; k += A.parts)
+      for (int i = tid; i < MH; i += T) A.modes[((size_t)s * NT + k) * MH + i] = modl[k * MH + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1154,7 +1174,7 @@ k_batch(const FusedArgs* __restrict__ jobs, const BatchItem* __restrict__ items,
     const FusedArgs A = jobs[it.job];
     if (A.nmcs > 0) {
       if (kSplit && it.nsets == 0)
-        run_split<D, kMeas, kWalk>(A, lds, it.sample, it.c_lo, &flag);
+        run_split<D, kMeas, kWalk, kModes>(A, lds, it.sample, it.c_lo, &flag);
       else
         run_sample<D, kHou, kMeas, kWalk, kModes>(A, lds, it.sample, it.c_lo, it.nsets);
     }
@@ -1231,7 +1251,11 @@ bool fused_plan(const Geo& g, bool hou, int nsets, int waves, FusedLayout& lay, 
   return off <= budget;
 }
 
-bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, bool walk) {
+bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, bool walk,
+                bool modes) {
+  const int waves = 16;  // plane counters for up to 16 wavefronts
+  const size_t mcnt = modes ? (size_t)waves * 3 * g.L : 0;
+  const size_t mwords = modes ? 2 * (size_t)g.NT * (g.L / 2 + 1) : 0;
   const size_t budget = (160 * 1024 - 512) / 4;
   const size_t W2 = 2 * (size_t)g.NW, Jw = 2 * 2 * (size_t)g.d * g.NW;
   for (int jl = 1; jl >= 0; --jl) {
@@ -1241,6 +1265,7 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, b
     fixed = (fixed + 1) / 2 * 2 + 16 * (size_t)g.NT;
     fixed += g.NT + 2 * (size_t)g.NT + 2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32);
     if (walk) fixed = (fixed + 1) / 2 * 2 + 2 * (size_t)g.nslot + 2 * 32 * 3;
+    if (modes) fixed = (fixed + mcnt + 1) / 2 * 2 + mwords;
     if (fixed >= budget) continue;
     const size_t rmax = std::min<size_t>((budget - fixed) / W2, (size_t)g.nslot);
     if (rmax < 1 || (jl && rmax < std::min(g.nslot, 8))) continue;
@@ -1269,7 +1294,8 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, b
     lay.acc = take(2 * (size_t)(g.NT - 1) * ((g.NT + 31) / 32), 1);
     lay.walk = take(walk ? 2 * (size_t)g.nslot : 0, walk ? 2 : 1);
     lay.trip = take(walk ? 2 * 32 * 3 : 0, walk ? 2 : 1);
-    lay.mcnt = lay.modes = (int)off;
+    lay.mcnt = take(mcnt, 1);
+    lay.modes = take(mwords, modes ? 2 : 1);
     lay.PC = 0;
     lay.Qs = (int)off;
     lay.hq = (int)off;
@@ -1320,14 +1346,9 @@ static hipError_t lds_attr(K kernel, size_t bytes) {
 namespace {
 using BatchKernel = void (*)(const FusedArgs*, const BatchItem*, int, uint32_t*);
 
-// Split samples never carry the modes (such jobs run the per-step kernels),
-// so those combinations are not compiled.
 template <int D, int F>
 constexpr BatchKernel kernel_or_null() {
-  if constexpr ((F & kFeatSplit) && (F & kFeatModes))
-    return nullptr;
-  else
-    return &k_batch<D, F>;
+  return &k_batch<D, F>;
 }
 
 template <int D, int... F>

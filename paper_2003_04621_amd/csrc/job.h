@@ -102,7 +102,7 @@ int batch_slots(const pt_batch* b);
 // Whether a job of this shape needs the split-sample scratch (its two
 // replica sets do not fit one workgroup together, but a split plan exists),
 // and how many bytes that scratch takes.
-size_t split_scratch_bytes(const ptsg::Geo& g);
+size_t split_scratch_bytes(const ptsg::Geo& g, bool walk = false, bool modes = false);
 // Device bytes a job of this shape allocates (an upper bound); `flags` as
 // pt_init_ex's (a layout, optionally with PT_TRACK_WALK / PT_TRACK_MODES).
 size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* betas);

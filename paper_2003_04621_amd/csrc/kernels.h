@@ -108,7 +108,8 @@ bool fused_plan(const Geo& g, bool houdayer, int nsets, int waves, FusedLayout& 
 // Plans a split sample: the fewest parts (<= kMaxParts) whose R slots fit one
 // workgroup's LDS, with the couplings in LDS when that still leaves room for
 // min(2 N_T, 8) slots.  False if even one slot does not fit.
-bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, bool walk = false);
+bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, bool walk = false,
+                bool modes = false);
 
 FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, const uint32_t* jw,
                           int32_t* E, int32_t* sot, int32_t* tos, const uint32_t* thr,
@@ -118,8 +119,7 @@ FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, con
 
 // Kinds of work a batch launch holds (Houdayer moves, measurements, split
 // samples, jobs that track the replica walk, jobs that measure the two-replica
-// modes; never split samples with modes); the launch runs the kernel compiled
-// for exactly that set.
+// modes); the launch runs the kernel compiled for exactly that set.
 constexpr int kFeatHou = 1, kFeatMeas = 2, kFeatSplit = 4, kFeatWalk = 8, kFeatModes = 16;
 
 // Persistent batch: resets the queue, runs every item to its job's nmcs, then

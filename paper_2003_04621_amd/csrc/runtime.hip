@@ -67,10 +67,8 @@ void plan_job(pt_job* job) {
   job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0], w, md);
   job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1], w, md);
   job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2], w, md);
-  // a job keeping the modes whose two sets do not fit one workgroup runs the
-  // per-step kernels
-  job->split_ok = !job->fused_ok[0] && !md &&
-                  split_plan(g, job->split_lay, job->split_parts, job->split_R, job->split_jlds, w);
+  job->split_ok = !job->fused_ok[0] && split_plan(g, job->split_lay, job->split_parts,
+                                                   job->split_R, job->split_jlds, w, md);
 }
 
 // pt_get_plan's report for a planned job.
@@ -332,10 +330,11 @@ int pt_table_len(const double* betas, int NT, int d, long N) {
   return M;
 }
 
-size_t split_scratch_bytes(const Geo& g) {
+size_t split_scratch_bytes(const Geo& g, bool walk, bool modes) {
   FusedLayout lay;
   int parts, R, jlds;
-  if (fused_plan(g, false, 2, 16, lay) || !split_plan(g, lay, parts, R, jlds)) return 0;
+  if (fused_plan(g, false, 2, 16, lay, walk, modes) || !split_plan(g, lay, parts, R, jlds, walk, modes))
+    return 0;
   const size_t per = (size_t)g.S * 2 * g.nslot;
   return sizeof(int32_t) * per + sizeof(uint32_t) * per * 2 * g.NW + sizeof(uint32_t) * (g.S + 1);
 }
@@ -352,7 +351,7 @@ size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* be
                        (walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)S : 0) +
                        (modes ? sizeof(int64_t) * (size_t)S * NT * (L / 2 + 1) : 0) +
                        sizeof(uint32_t) * (size_t)NT * (4 + pt_table_len(betas, NT, d, (long)N)) + 4096;
-  return spins + jw + (size_t)S * d * N + small + split_scratch_bytes(make_geo(S, NT, L, d, layout, 0));
+  return spins + jw + (size_t)S * d * N + small + split_scratch_bytes(make_geo(S, NT, L, d, layout, 0), walk, modes);
 }
 
 PT_API int pt_init(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,

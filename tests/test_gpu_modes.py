@@ -3,8 +3,9 @@ correlation length; Sec. 3 names them, the usual definitions are used).
 
 The accumulated A(delta) sums must equal the oracle's bit for bit on every
 measurement path (fused with compile-time and run-time geometry, with and
-without Houdayer moves, both spin layouts, the per-step kernels, batches, jobs
-too large for one workgroup), chi_SG and xi must agree to 1e-12, and at the
+without Houdayer moves, both spin layouts, the per-step kernels, batches,
+samples split over several workgroups), chi_SG and xi must agree to 1e-12,
+and at the
 full 3D L=16 size the sum rule sum_delta A(delta) = d Q^2 ties every sample's
 modes to its overlap moment."""
 import numpy as np
@@ -54,7 +55,9 @@ CASES = [
     ("plain 3D L=12 packed", 3, 12, 2, 3, 1, False, "plain"),
     ("plain 2D L=14 packed", 2, 14, 2, 3, 1, True, "plain"),
     ("batch 3D L=8", 3, 8, 2, 4, 0, False, "batch"),
-    ("per-step fallback 3D L=32", 3, 32, 1, 24, 0, False, "mcs"),
+    ("split 3D L=32 (2 parts)", 3, 32, 1, 24, 0, False, "mcs"),
+    ("split 3D L=48 (parts straddling the sets)", 3, 48, 1, 8, 1, False, "mcs"),
+    ("split 3D L=32 per-step", 3, 32, 1, 24, 1, False, "plain"),
 ]
 
 
@@ -130,5 +133,5 @@ def test_modes_are_opt_in_and_checkpointed(pt):
     ref.enable_modes()
     ref.mcs(12, measure=True)
     same_modes(pt, c, ref, "restored")
-    assert pt.pt_plan_query(3, 32, 24, measure=True, modes=True)["mode"] == -1  # per-step kernels
+    assert pt.pt_plan_query(3, 32, 24, measure=True, modes=True)["mode"] == 3  # split samples
     assert pt.pt_plan_query(3, 32, 24, measure=True)["mode"] == 3
