@@ -175,6 +175,15 @@ int pt_measure(pt_job *job);
  * bit-identical results. */
 int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
 
+/* Measurement interval (Sec. 3: measurements are taken at intervals): from
+ * now on a step of pt_mcs or pt_batch_run with PT_MCS_MEASURE measures only if
+ * its 1-based sweep number (the sweep counter after the step) is a multiple
+ * of `every` (>= 1; 1, the default, measures every step).  The rule follows
+ * the job's own counter, so results do not depend on how the steps are split
+ * into calls.  pt_measure still measures when called.  A job setting, not
+ * part of the checkpoint.  PT_EINVAL if every < 1. */
+int pt_set_measure_interval(pt_job *job, int32_t every);
+
 /* The plan pt_mcs takes for these flags, int32 [4]: mode (0 both sets per
  * workgroup, 1 the same with Houdayer, 2 one set per workgroup, 3 split
  * sample, -1 per-step kernels), workgroups per sample, configurations per

@@ -86,6 +86,7 @@ def _declare(L):
     L.or_overlap_modes.argtypes = [C.c_int, C.c_int, P, P, P]
     L.or_enable_modes.argtypes = [P]
     L.or_get_modes.argtypes = [P, P]
+    L.or_set_measure_every.argtypes = [P, C.c_int]
     L.or_pt_table_len.argtypes = [P]
     L.or_pt_table_len.restype = C.c_int
     L.or_get_pt_table.argtypes = [P, P]
@@ -295,6 +296,10 @@ class OracleJob:
         trips = np.zeros((self.S, 32, 3), np.uint64)
         lib().or_get_walk(self._h, _p(lab), _p(beg), _p(trips))
         return lab, beg, trips
+
+    def set_measure_every(self, every):
+        """mcs() measures only after sweeps whose count is a multiple of every."""
+        lib().or_set_measure_every(self._h, int(every))
 
     def enable_modes(self):
         """Accumulate the two-replica modes at every later measurement."""

@@ -234,6 +234,7 @@ typedef struct {
   uint64_t *trip;         /* [S][32][3]: per log2 bin: trips, sum len, sum len^2 */
   int modes_on;
   int64_t *modes;         /* [S][NT][L/2+1]: plane-sum autocorrelations A(delta) */
+  int every;              /* or_mcs measures when the sweep count is a multiple */
 } or_job;
 
 static int8_t *or_lat(or_job *jb, int s, int slot) {
@@ -288,6 +289,7 @@ OR_EXPORT or_job *or_create(int S, int NT, int L, int d, const int8_t *J,
   jb->wlab = (int32_t *)calloc((size_t)S * jb->nslot, sizeof(int32_t));
   jb->wbeg = (uint32_t *)calloc((size_t)S * jb->nslot, sizeof(uint32_t));
   jb->trip = (uint64_t *)calloc((size_t)S * 32 * 3, sizeof(uint64_t));
+  jb->every = 1;
   /* initial spins: one Philox word per site, s = -1 iff its top bit is set */
   for (int s = 0; s < S; ++s)
     for (int r = 0; r < jb->nslot; ++r) {
@@ -610,6 +612,12 @@ OR_EXPORT void or_measure(or_job *jb) {
   jb->n_meas += 1;
 }
 
+/* Measurements at intervals (Sec. 3): or_mcs then measures only after the
+   sweeps whose count (from 1) is a multiple of every. */
+OR_EXPORT void or_set_measure_every(or_job *jb, int every) {
+  jb->every = every < 1 ? 1 : every;
+}
+
 /* One Monte Carlo step in the order of Sec. 2.4: one Metropolis sweep, then
    (optionally) one Houdayer move per same-temperature pair, then one
    replica-exchange pass, then (optionally) one measurement. */
@@ -618,7 +626,7 @@ OR_EXPORT void or_mcs(or_job *jb, int n, int houdayer, int measure) {
     or_sweep(jb, 1);
     if (houdayer) or_houdayer(jb);
     or_exchange(jb);
-    if (measure) or_measure(jb);
+    if (measure && jb->t % (uint64_t)jb->every == 0) or_measure(jb);
   }
 }
 

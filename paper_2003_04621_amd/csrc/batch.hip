@@ -41,6 +41,7 @@ struct pt_batch {
   int built_mcs = -1;
   uint32_t built_flags = 0;
   BatchConfig built_cfg;
+  std::vector<int> built_every;
   // captured launch (captured on a private stream, replayed on `stream`)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -126,6 +127,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
       FusedArgs A = make_fused_args(j->g, j->split_lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
                                     j->thrpt, j->M, j->mom, j->walk, j->trips, j->modes, j->ctr, mcs,
                                     false, meas);
+      A.every = j->meas_every;
       A.parts = j->split_parts;
       A.R = j->split_R;
       A.jlds = j->split_jlds;
@@ -147,6 +149,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     hj.push_back(make_fused_args(j->g, j->plan[mode], j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
                                  j->thrpt, j->M, j->mom, j->walk, j->trips, j->modes, j->ctr, mcs, hou,
                                  meas));
+    hj.back().every = j->meas_every;
     lds_words = std::max(lds_words, (size_t)j->plan[mode].words);
     if (mcs <= 0) continue;
     const double c = (double)nsets * j->g.NT * j->g.N * mcs;
@@ -262,8 +265,12 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
 }
 
 int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
-  if (b->built && b->built_mcs == mcs && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg))
+  std::vector<int> every(b->jobs.size());  // the work list carries each job's interval
+  for (size_t i = 0; i < b->jobs.size(); ++i) every[i] = b->jobs[i]->meas_every;
+  if (b->built && b->built_mcs == mcs && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg) &&
+      b->built_every == every)
     return PT_OK;
+  b->built_every = every;
   const std::vector<int> steps(b->jobs.size(), mcs);
   const std::vector<uint32_t> fl(b->jobs.size(), flags);
   if (int rc = build_worklist_ex(b, steps, fl)) return rc;

@@ -164,7 +164,15 @@ struct DevCounters {
 // per-block atomic on one address serialises tens of thousands of blocks).
 struct CounterStep {
   uint32_t dt, du, dv, dm;
+  // measurement interval (0 or 1: dm as given); with every > 1 the dt sweeps
+  // from t count dm * (number of their 1-based sweep numbers divisible by it)
+  uint32_t every;
 };
+
+// Whether the step with 1-based sweep number t1 measures at interval `every`.
+__host__ __device__ constexpr bool measures_at(uint32_t t1, uint32_t every) {
+  return every <= 1u || t1 % every == 0u;
+}
 
 // The geometry fields of Geo, a function of L and d alone.  Fields per word:
 // the most row fields of H = L/2 bits that fit 32 bits with a block length

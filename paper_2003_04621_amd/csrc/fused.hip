@@ -905,7 +905,7 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
     sweep_resident<D>(A, Jl, W, El, tosl, thrl, slot0, nres, s, t);
     if (hou) houdayer_resident<D>(A, lds, s, v0 + (uint32_t)step);
     exchange_resident<WALK>(A, lds, c_lo, nsets, u + 1u, walk);
-    if (meas) measure_resident<MODES>(A, lds);
+    if (meas && measures_at(t + 1u, (uint32_t)A.every)) measure_resident<MODES>(A, lds);
   }
 
   // ---- store the resident sets
@@ -1094,8 +1094,9 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     sweep_resident<D, true>(A, Jsrc, W, El, tosl, thrl, slot0, nres, s, t);
     // publish, meet, and take the sample-wide steps
     const int par = step & 1;
+    const bool mstep = meas && measures_at(t + 1u, (uint32_t)A.every);
     for (int i = tid; i < nres; i += T) Ex[par * nslot + slot0 + i] = El[slot0 + i];
-    if (meas) {
+    if (mstep) {
       uint32_t* dst = snap + ((size_t)par * nslot + slot0) * W2;
       for (int i = tid; i < nres * W2; i += T) dst[i] = W[i];
     }
@@ -1103,7 +1104,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     for (int i = tid; i < nslot; i += T) El[i] = Ex[par * nslot + i];
     __syncthreads();
     exchange_resident<WALK>(A, lds, 0, 2, u + 1u, walk);
-    if (meas) measure_split<MODES>(A, lds, part, snap + (size_t)par * nslot * W2);
+    if (mstep) measure_split<MODES>(A, lds, part, snap + (size_t)par * nslot * W2);
   }
 
   // ---- store this part's slots; part 0 stores the maps, owners the moments
@@ -1200,11 +1201,11 @@ __global__ void k_batch_advance(const FusedArgs* __restrict__ jobs, int njobs) {
   if (j >= njobs) return;
   const FusedArgs& A = jobs[j];
   DevCounters* c = const_cast<DevCounters*>(A.ctr);
-  const uint32_t n = (uint32_t)A.nmcs;
+  const uint32_t n = (uint32_t)A.nmcs, t0 = c->t, e = (uint32_t)A.every;
   c->t += n;
   c->u += n;
   if (A.hou) c->v += n;
-  if (A.meas) c->n_meas += n;
+  if (A.meas) c->n_meas += e > 1u ? (t0 + n) / e - t0 / e : n;
 }
 
 // ---------------------------------------------------------------------------
@@ -1328,6 +1329,7 @@ FusedArgs make_fused_args(const Geo& g, const FusedLayout& lay, void* spins, con
   A.nmcs = nmcs;
   A.hou = hou ? 1 : 0;
   A.meas = meas ? 1 : 0;
+  A.every = 1;
   A.magicNW = (uint32_t)((0x100000000ull + (uint64_t)g.NW - 1) / (uint64_t)g.NW);
   A.lay = lay;
   A.parts = A.R = A.jlds = 0;

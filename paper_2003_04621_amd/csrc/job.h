@@ -28,6 +28,8 @@ struct pt_job {
   int M = 0;
   ptsg::DevCounters* ctr = nullptr;
   int64_t* mom = nullptr;    // [S][NT][8]
+  // measured steps of pt_mcs / batches: 1-based sweep number a multiple of this
+  int meas_every = 1;
   // two-replica modes, allocated only for jobs created with PT_TRACK_MODES
   bool track_modes = false;
   int64_t* modes = nullptr;  // [S][NT][L/2+1]

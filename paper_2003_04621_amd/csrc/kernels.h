@@ -38,10 +38,11 @@ hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_
                            const int32_t* sot, DevCounters* ctr, hipStream_t st);
 
 // One measurement; mom is int64 [S][NT][8]; modes (null: not kept) int64
-// [S][NT][L/2+1] receives each temperature's mode_autocorr sums.
+// [S][NT][L/2+1] receives each temperature's mode_autocorr sums.  With
+// every > 1 nothing happens unless measures_at(ctr->t + 1, every).
 hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E,
                           const int32_t* sot, int64_t* mom, int64_t* modes, DevCounters* ctr,
-                          hipStream_t st);
+                          int every, hipStream_t st);
 
 // Advances the device counters by `step` (one thread; enqueued after the
 // kernels that read them).
@@ -77,6 +78,7 @@ struct FusedArgs {
   int64_t* modes;
   const DevCounters* ctr;
   int nmcs, hou, meas;
+  int every;  // a measured step is one whose 1-based sweep number is a multiple
   uint32_t magicNW;  // item / NW
   FusedLayout lay;
   // Split samples (parts > 0): part p of a sample holds slots [p R, p R + R),

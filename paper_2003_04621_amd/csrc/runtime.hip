@@ -369,6 +369,13 @@ PT_API int pt_destroy(pt_job* job) {
   return PT_OK;
 }
 
+PT_API int pt_set_measure_interval(pt_job* job, int32_t every) {
+  if (int rc = check_job(job)) return rc;
+  if (every < 1) return pt_fail(PT_EINVAL, "the measurement interval must be >= 1");
+  job->meas_every = every;  // batches rebuild their work lists when it changes
+  return PT_OK;
+}
+
 PT_API int pt_set_stream(pt_job* job, void* hip_stream) {
   if (int rc = check_job(job)) return rc;
   job->stream = (hipStream_t)hip_stream;
@@ -408,7 +415,7 @@ PT_API int pt_houdayer(pt_job* job) {
 
 PT_API int pt_measure(pt_job* job) {
   if (int rc = check_job(job)) return rc;
-  PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr,
+  PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr, 1,
                              job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 0, 1}, job->stream));
   return PT_OK;
@@ -447,8 +454,11 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
     PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
                                 job->trips, job->ctr, st));
     if (meas)
-      PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr, st));
-    PT_HIP(job, launch_advance(job->ctr, CounterStep{1, 1, hou ? 1u : 0u, meas ? 1u : 0u}, st));
+      PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr,
+                                 job->meas_every, st));
+    PT_HIP(job, launch_advance(job->ctr,
+                               CounterStep{1, 1, hou ? 1u : 0u, meas ? 1u : 0u, (uint32_t)job->meas_every},
+                               st));
   }
   return PT_OK;
 }

@@ -263,7 +263,8 @@ __device__ __forceinline__ void plane_counts_packed(const Geo& g, const uint32_t
 
 __global__ void __launch_bounds__(256) k_measure(Geo g, const void* spins, const int32_t* __restrict__ E,
                                                  const int32_t* __restrict__ sot, int64_t* mom,
-                                                 int64_t* modes, DevCounters* ctr) {
+                                                 int64_t* modes, DevCounters* ctr, int every) {
+  if (!measures_at(load_counter(&ctr->t) + 1u, (uint32_t)every)) return;  // uniform
   __shared__ int red;
   __shared__ int32_t cnt[3 * 64];
   const int pair = blockIdx.x;  // s*NT + k
@@ -320,9 +321,10 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* spins, const
 }
 
 hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E, const int32_t* sot,
-                          int64_t* mom, int64_t* modes, DevCounters* ctr, hipStream_t st) {
+                          int64_t* mom, int64_t* modes, DevCounters* ctr, int every,
+                          hipStream_t st) {
   hipLaunchKernelGGL(k_measure, dim3((unsigned)(g.S * g.NT)), dim3(256), 0, st, g, spins, E, sot, mom,
-                     modes, ctr);
+                     modes, ctr, every);
   return hipGetLastError();
 }
 
@@ -331,10 +333,13 @@ hipError_t launch_measure(const Geo& g, const void* spins, const int32_t* E, con
 // ---------------------------------------------------------------------------
 __global__ void k_advance(DevCounters* ctr, CounterStep step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const uint32_t t0 = ctr->t;
     ctr->t += step.dt;
     ctr->u += step.du;
     ctr->v += step.dv;
-    ctr->n_meas += step.dm;
+    ctr->n_meas += step.every > 1u
+                       ? step.dm * ((t0 + step.dt) / step.every - t0 / step.every)
+                       : step.dm;
   }
 }
 

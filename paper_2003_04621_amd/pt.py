@@ -33,7 +33,7 @@ EXPORTS = [
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_walk", "pt_tunnel_summary",
     "pt_get_modes", "pt_correlation_length",
     "pt_get_state", "pt_set_state",
-    "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
+    "pt_set_measure_interval", "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
     "pt_batch_get_config", "pt_batch_set_config", "pt_batch_launch_shape", "pt_batch_destroy",
     "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_stats", "pt_server_stop",
@@ -86,6 +86,7 @@ def lib():
             "pt_get_modes": [P, P], "pt_correlation_length": [P, P, P, P],
             "pt_get_state": [P, P, C.POINTER(C.c_size_t)], "pt_set_state": [P, P, C.c_size_t],
             "pt_set_stream": [P, P], "pt_set_allocator": [_ALLOC, _FREE, P],
+            "pt_set_measure_interval": [P, I32],
             "pt_batch_create": [P, I32, C.POINTER(P)], "pt_batch_set_stream": [P, P],
             "pt_batch_run": [P, I32, U32], "pt_batch_tune": [P, I32, U32, C.c_char_p],
             "pt_batch_get_config": [P, P], "pt_batch_set_config": [P, I32, I32, I32],
@@ -216,6 +217,11 @@ def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_
         stream = torch.cuda.current_stream()
     pt_set_stream(job, stream)
     return job
+
+
+def pt_set_measure_interval(job: Job, every: int) -> None:
+    """Measured steps of pt_mcs / batches: 1-based sweep number a multiple of `every`."""
+    _check(lib().pt_set_measure_interval(job.h, int(every)))
 
 
 def pt_set_stream(job: Job, stream) -> None:

@@ -51,3 +51,25 @@ def test_readout_is_exact_ratio_of_integer_moments(orc):
         g = 0.5 * (3 - float(q4k / q2 ** 2))
         assert abs(dis[k, 5] - g) < 1e-13
         assert abs(dis[k, 0] - float(Fraction(int(m["E"][:, k].sum()), S * 2 * n * N))) < 1e-15
+
+
+def test_measurement_interval_equals_explicit_measurements():
+    """Sec. 3 takes measurements at intervals: with an interval of 3, ten steps
+    measure after sweeps 3, 6 and 9, exactly as stepping and measuring by hand."""
+    import oracle as _or
+    from paper_2003_04621_amd import workloads as _W
+    S, NT, L, d = 2, 3, 4, 3
+    J = _W.couplings_pm_j(S, L, d, seed=17)
+    b = _W.geometric_betas(0.8, 2.0, NT)
+    a = _or.OracleJob(S, NT, L, d, J, b, 5)
+    a.set_measure_every(3)
+    a.mcs(4, measure=True)
+    a.mcs(6, measure=True)
+    h = _or.OracleJob(S, NT, L, d, J, b, 5)
+    for i in range(1, 11):
+        h.mcs(1)
+        if i % 3 == 0:
+            h.measure()
+    assert a.counters() == h.counters() and a.counters()["n_meas"] == 3
+    for k, v in a.moments().items():
+        assert (v == h.moments()[k]).all(), k
