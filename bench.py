@@ -376,7 +376,16 @@ def main():
         torch.cuda.synchronize()
         dtm = time.perf_counter() - tm
         c0, ck, xi = pt.pt_correlation_length(mj)
+        # the same job measuring every 10th step, as measurements usually are
+        pt.pt_set_measure_interval(mj, 10)
+        torch.cuda.synchronize()
+        tm10 = time.perf_counter()
+        for st in range(0, args.modes_steps, chunk):
+            pt.pt_mcs(mj, min(chunk, args.modes_steps - st), houdayer=wl.houdayer, measure=True)
+        torch.cuda.synchronize()
+        dtm10 = time.perf_counter() - tm10
         modes = {"value": round(flips_per_step * args.modes_steps / dtm / 1e9, 2), "unit": "flips/ns",
+                 "value_every_10": round(flips_per_step * args.modes_steps / dtm10 / 1e9, 2),
                  "steps": args.modes_steps,
                  "chi_sg_coldest": round(float(c0[0]), 4), "chi_sg_kmin_coldest": round(float(ck[0]), 4),
                  "xi_coldest": None if np.isnan(xi[0]) else round(float(xi[0]), 4),
