@@ -49,7 +49,7 @@ OPS_PER_FLIP = 16
 # HBM bytes per 500-step launch of the fused kernel on the 3d_l16 workload
 # (int8 layout), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
 # copy's readings (profiles/k_batch_3d_l16_hbm_traffic.md).
-TRAFFIC_3D_L16_INT8_500 = 5.68e8
+TRAFFIC_3D_L16_INT8_500 = 5.71e8
 
 
 def cpu_baseline(wl, budget_s: float):
