@@ -69,6 +69,27 @@ def test_null_handles_are_rejected():
     assert L.pt_destroy(None) == pt.PT_EINVAL
     h = C.c_void_p()
     assert L.pt_init(C.byref(h), 1, 2, 4, 2, None, None, 0) == pt.PT_EINVAL
+    assert L.pt_set_measure_interval(None, 3) == pt.PT_EINVAL
+    assert L.pt_get_walk(None, None, None, None) == pt.PT_EINVAL
+    assert L.pt_get_modes(None, None) == pt.PT_EINVAL
+    assert L.pt_correlation_length(None, None, None, None) == pt.PT_EINVAL
+    assert L.pt_tunnel_summary(None, 1, 10, None, None, None, None) == pt.PT_EINVAL
+
+
+def test_init_flags_and_queries_validated_on_host():
+    """Unknown pt_init_ex flags are refused before any device call; the walk
+    and mode flags are accepted by the host-only plan and byte queries."""
+    from paper_2003_04621_amd import pt
+    L = pt.lib()
+    J = np.ones(2 * 16, np.int8)
+    b = np.array([1.0, 0.5])
+    h = C.c_void_p()
+    for bad in (2, 0x40, 0x100):
+        assert L.pt_init_ex(C.byref(h), 1, 2, 4, 2, pt._p(J), pt._p(b), 0, bad) == pt.PT_EINVAL
+    out = np.zeros(4, np.int32)
+    for flags in (pt.PT_TRACK_WALK, pt.PT_TRACK_MODES, pt.PT_TRACK_WALK | pt.PT_TRACK_MODES):
+        assert L.pt_plan_query(3, 16, 8, flags | pt.PT_MCS_MEASURE, pt._p(out)) == pt.PT_OK
+    assert L.pt_plan_query(3, 16, 8, 0x40, pt._p(out)) == pt.PT_EINVAL
 
 
 def test_allocator_hooks_must_be_paired():
