@@ -89,7 +89,7 @@ typedef struct {
   int32_t sweeps;                    /* Monte Carlo steps in total */
   int32_t burn_in;                   /* steps before the first measurement */
   uint32_t flags;                    /* PT_MCS_HOUDAYER and/or PT_SERVE_UNTIL_EQUILIBRATED, or 0 */
-  uint32_t layout;                   /* PT_LAYOUT_INT8 or PT_LAYOUT_PACKED, | PT_TRACK_WALK */
+  uint32_t layout;                   /* PT_LAYOUT_INT8 or PT_LAYOUT_PACKED, | PT_TRACK_WALK/_MODES */
 } pt_request;
 
 /* pt_request flag: the job ends between rounds, once past its burn-in, as soon
@@ -365,8 +365,13 @@ int pt_server_submit(pt_server *s, const pt_request *req, uint64_t *ticket);
  * filling *out and (if not NULL) disorder [replicas][6] as pt_observables,
  * after which the ticket is forgotten; PT_EINVAL for an unknown ticket.  A
  * request's layout may carry PT_TRACK_WALK (results then include the
- * round-trip time), not PT_TRACK_MODES (PT_EINVAL at submission). */
+ * round-trip time) and PT_TRACK_MODES (see pt_server_poll_ex). */
 int pt_server_poll(pt_server *s, uint64_t ticket, pt_result *out, double *disorder);
+/* pt_server_poll that also fills (if not NULL) correlation [replicas][3]:
+ * chi_SG(0), chi_SG(k_min) and xi as pt_correlation_length, for a request
+ * whose layout carries PT_TRACK_MODES (NaN otherwise). */
+int pt_server_poll_ex(pt_server *s, uint64_t ticket, pt_result *out, double *disorder,
+                      double *correlation);
 /* out[8] = {attempted flips completed, busy seconds, rounds, admitted,
  *           completed, peak admitted bytes, peak concurrent jobs, uptime s} */
 int pt_server_stats(pt_server *s, double *out);

@@ -51,6 +51,7 @@ struct Finished {
   std::vector<double> disorder;  // [NT][6]
   double tau = 0;                // round-trip time (walk kept), else NaN
   int equilibrated = -1;         // its logarithmic-binning check, else -1
+  std::vector<double> corr;      // [NT][3] chi_SG(0), chi_SG(k_min), xi (modes kept), else NaN
 };
 
 // Round-trip summary of a job keeping the replica walk (Sec. 2.3): mean trip
@@ -122,10 +123,20 @@ void finish(pt_server* sv, Active& a, int status) {
   f.t_admit = a.t_admit;
   f.disorder.assign((size_t)a.req.NT * 6, 0.0);
   f.tau = std::numeric_limits<double>::quiet_NaN();
+  f.corr.assign((size_t)a.req.NT * 3, std::numeric_limits<double>::quiet_NaN());
   if (status == PT_OK && a.job) {
     int64_t n = 0;
     int rc = pt_observables(a.job, nullptr, f.disorder.data(), &n);
     if (rc == PT_OK && a.job->track_walk) rc = walk_summary(a.job, f.tau, f.equilibrated);
+    if (rc == PT_OK && a.job->track_modes) {
+      std::vector<double> c0(a.req.NT), ck(a.req.NT), xi(a.req.NT);
+      rc = pt_correlation_length(a.job, c0.data(), ck.data(), xi.data());
+      for (int k = 0; k < a.req.NT; ++k) {
+        f.corr[(size_t)k * 3 + 0] = c0[k];
+        f.corr[(size_t)k * 3 + 1] = ck[k];
+        f.corr[(size_t)k * 3 + 2] = xi[k];
+      }
+    }
     if (rc != PT_OK) f.status = rc;
     f.n_meas = n;
   }
@@ -146,6 +157,7 @@ void fail_request(pt_server* sv, const Request& r, int status) {
   f.t_admit = f.t_done = sv->now();
   f.disorder.assign((size_t)r.NT * 6, 0.0);
   f.tau = std::numeric_limits<double>::quiet_NaN();
+  f.corr.assign((size_t)r.NT * 3, std::numeric_limits<double>::quiet_NaN());
   sv->finished[r.ticket] = std::move(f);
   sv->cv_done.notify_all();
 }
@@ -377,9 +389,9 @@ PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* tick
     return pt_fail(PT_EINVAL, "pt_server_submit: need samples >= 1, replicas >= 2, 0 <= burn_in <= sweeps");
   if (req->flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_SERVE_UNTIL_EQUILIBRATED))
     return pt_fail(PT_EINVAL, "pt_server_submit: unknown flags");
-  const uint32_t layout = req->layout & ~(uint32_t)PT_TRACK_WALK;
+  const uint32_t layout = req->layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
   if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED)
-    return pt_fail(PT_EINVAL, "pt_server_submit: unknown layout (the server reports no modes)");
+    return pt_fail(PT_EINVAL, "pt_server_submit: unknown layout");
   if ((req->flags & PT_SERVE_UNTIL_EQUILIBRATED) && !(req->layout & PT_TRACK_WALK))
     return pt_fail(PT_EINVAL, "pt_server_submit: stopping at equilibrium needs PT_TRACK_WALK");
   for (int k = 0; k < req->replicas; ++k)
@@ -413,6 +425,11 @@ PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* tick
 }
 
 PT_API int pt_server_poll(pt_server* sv, uint64_t ticket, pt_result* out, double* disorder) {
+  return pt_server_poll_ex(sv, ticket, out, disorder, nullptr);
+}
+
+PT_API int pt_server_poll_ex(pt_server* sv, uint64_t ticket, pt_result* out, double* disorder,
+                             double* correlation) {
   if (!sv || !out) return pt_fail(PT_EINVAL, "pt_server_poll: null argument");
   std::lock_guard<std::mutex> lk(sv->mu);
   auto it = sv->finished.find(ticket);
@@ -429,6 +446,7 @@ PT_API int pt_server_poll(pt_server* sv, uint64_t ticket, pt_result* out, double
   out->equilibrated = f.equilibrated;
   out->tau_tunnel = f.tau;
   if (disorder) std::copy(f.disorder.begin(), f.disorder.end(), disorder);
+  if (correlation) std::copy(f.corr.begin(), f.corr.end(), correlation);
   sv->finished.erase(it);
   return PT_OK;
 }

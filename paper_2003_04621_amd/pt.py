@@ -36,7 +36,8 @@ EXPORTS = [
     "pt_set_measure_interval", "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
     "pt_batch_get_config", "pt_batch_set_config", "pt_batch_launch_shape", "pt_batch_destroy",
-    "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_stats", "pt_server_stop",
+    "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_poll_ex", "pt_server_stats",
+    "pt_server_stop",
 ]
 
 
@@ -95,6 +96,7 @@ def lib():
             "pt_server_start": [C.c_size_t, I32, C.POINTER(P)],
             "pt_server_submit": [P, C.POINTER(PTRequest), C.POINTER(C.c_uint64)],
             "pt_server_poll": [P, C.c_uint64, C.POINTER(PTResult), P],
+            "pt_server_poll_ex": [P, C.c_uint64, C.POINTER(PTResult), P, P],
             "pt_server_stats": [P, P], "pt_server_stop": [P],
         }
         for name, args in sig.items():
@@ -489,14 +491,14 @@ def pt_server_start(hbm_budget: int, steps_per_round: int = 100) -> Server:
 
 def pt_server_submit(server: Server, dim, L, replicas, samples, betas, couplings, seed, sweeps,
                      burn_in, houdayer=False, layout=PT_LAYOUT_INT8, walk=False,
-                     until_equilibrated=False) -> int:
+                     until_equilibrated=False, modes=False) -> int:
     b = np.ascontiguousarray(betas, dtype=np.float64)
     J = np.ascontiguousarray(couplings, dtype=np.int8)
     flags = (PT_MCS_HOUDAYER if houdayer else 0) | (PT_SERVE_UNTIL_EQUILIBRATED
                                                     if until_equilibrated else 0)
     req = PTRequest(int(dim), int(L), int(replicas), int(samples), b.ctypes.data, J.ctypes.data,
                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps), int(burn_in), flags,
-                    int(layout) | (PT_TRACK_WALK if walk else 0))
+                    int(layout) | (PT_TRACK_WALK if walk else 0) | (PT_TRACK_MODES if modes else 0))
     t = C.c_uint64(0)
     _check(lib().pt_server_submit(server.h, C.byref(req), C.byref(t)))
     server.replicas[t.value] = int(replicas)
@@ -510,14 +512,15 @@ def pt_server_poll(server: Server, ticket: int):
     res = PTResult()
     nt = server.replicas[ticket]
     dis = np.zeros((nt, 6), np.float64)
-    rc = lib().pt_server_poll(server.h, C.c_uint64(ticket), C.byref(res), _p(dis))
+    corr = np.zeros((nt, 3), np.float64)
+    rc = lib().pt_server_poll_ex(server.h, C.c_uint64(ticket), C.byref(res), _p(dis), _p(corr))
     if rc == 1:
         return None
     _check(rc)
     del server.replicas[ticket]
     return dict(status=res.status, n_meas=res.n_meas, t_submit=res.t_submit,
                 t_admit=res.t_admit, t_done=res.t_done, disorder=dis,
-                tau_tunnel=res.tau_tunnel, equilibrated=res.equilibrated)
+                tau_tunnel=res.tau_tunnel, equilibrated=res.equilibrated, correlation=corr)
 
 
 def pt_server_stats(server: Server) -> dict:

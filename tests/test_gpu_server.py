@@ -160,12 +160,34 @@ def test_server_reports_round_trips_and_stops_at_equilibrium(pt):
     assert res["eq"]["equilibrated"] == 1 and res["eq"]["n_meas"] < 20000 - 10
 
 
-def test_server_rejects_modes_and_unguarded_stop(pt):
+def test_server_rejects_unguarded_stop(pt):
     srv = pt.pt_server_start(1 << 24, steps_per_round=3)
     J = W.couplings_pm_j(1, 4, 3, 1)
     b = W.geometric_betas(1.0, 2.0, 3)
     with pytest.raises(pt.PTError):
-        pt.pt_server_submit(srv, 3, 4, 3, 1, b, J, 1, 10, 0, layout=pt.PT_TRACK_MODES)
-    with pytest.raises(pt.PTError):
         pt.pt_server_submit(srv, 3, 4, 3, 1, b, J, 1, 10, 0, until_equilibrated=True)
+    with pytest.raises(pt.PTError):
+        pt.pt_server_submit(srv, 3, 4, 3, 1, b, J, 1, 10, 0, layout=0x40)
     pt.pt_server_stop(srv)
+
+
+def test_server_reports_correlation_length(pt):
+    """A request keeping the two-replica modes returns chi_SG(0), chi_SG(k_min)
+    and xi per temperature, equal to the same job run alone; others NaN."""
+    dim, L, NT, S = 3, 8, 4, 2
+    J = W.couplings_pm_j(S, L, dim, 81)
+    b = W.geometric_betas(0.8, 2.0, NT)
+    srv = pt.pt_server_start(1 << 30, steps_per_round=9)
+    t_m = pt.pt_server_submit(srv, dim, L, NT, S, b, J, 5, 40, 10, modes=True)
+    t_p = pt.pt_server_submit(srv, dim, L, NT, S, b, J, 5, 40, 10)
+    res = _wait(pt, srv, {"m": t_m, "p": t_p})
+    pt.pt_server_stop(srv)
+    assert np.isnan(res["p"]["correlation"]).all()
+    job = pt.pt_init(S, NT, L, dim, J, b, 5, modes=True)
+    pt.pt_mcs(job, 10)
+    pt.pt_mcs(job, 30, measure=True)
+    c0, ck, xi = pt.pt_correlation_length(job)
+    got = res["m"]["correlation"]
+    assert np.array_equal(got[:, 0], c0) and np.array_equal(got[:, 1], ck)
+    assert np.array_equal(got[:, 2], xi, equal_nan=True)
+    assert np.array_equal(res["m"]["disorder"], res["p"]["disorder"])
