@@ -90,6 +90,9 @@ typedef struct {
   int32_t burn_in;                   /* steps before the first measurement */
   uint32_t flags;                    /* PT_MCS_HOUDAYER and/or PT_SERVE_UNTIL_EQUILIBRATED, or 0 */
   uint32_t layout;                   /* PT_LAYOUT_INT8 or PT_LAYOUT_PACKED, | PT_TRACK_WALK/_MODES */
+  int32_t measure_every;             /* measurement interval after the burn-in (0 or 1: every
+                                        step), as pt_set_measure_interval */
+  int32_t reserved;
 } pt_request;
 
 /* pt_request flag: the job ends between rounds, once past its burn-in, as soon

@@ -28,7 +28,7 @@ namespace {
 
 struct Request {
   uint64_t ticket = 0;
-  int dim = 3, L = 0, NT = 0, S = 0, sweeps = 0, burn_in = 0;
+  int dim = 3, L = 0, NT = 0, S = 0, sweeps = 0, burn_in = 0, every = 1;
   uint32_t flags = 0, layout = 0;
   uint64_t seed = 0;
   std::vector<double> betas;
@@ -202,6 +202,7 @@ void create_jobs(pt_server* sv, std::vector<Request>& admit, std::vector<Active>
       continue;
     }
     a.job->stream = sv->st_main;
+    a.job->meas_every = a.req.every;
     ready.push_back(std::move(a));
     sv->admitted += 1;
   }
@@ -387,6 +388,7 @@ PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* tick
   if (req->samples < 1 || req->replicas < 2 || req->sweeps < 0 || req->burn_in < 0 ||
       req->burn_in > req->sweeps)
     return pt_fail(PT_EINVAL, "pt_server_submit: need samples >= 1, replicas >= 2, 0 <= burn_in <= sweeps");
+  if (req->measure_every < 0) return pt_fail(PT_EINVAL, "pt_server_submit: measure_every must be >= 0");
   if (req->flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_SERVE_UNTIL_EQUILIBRATED))
     return pt_fail(PT_EINVAL, "pt_server_submit: unknown flags");
   const uint32_t layout = req->layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
@@ -409,6 +411,7 @@ PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* tick
   r.S = req->samples;
   r.sweeps = req->sweeps;
   r.burn_in = req->burn_in;
+  r.every = req->measure_every < 1 ? 1 : req->measure_every;
   r.flags = req->flags;
   r.layout = req->layout;
   r.seed = req->seed;

@@ -45,7 +45,8 @@ class PTRequest(C.Structure):
     _fields_ = [("dim", C.c_int32), ("L", C.c_int32), ("replicas", C.c_int32),
                 ("samples", C.c_int32), ("betas", C.c_void_p), ("couplings", C.c_void_p),
                 ("seed", C.c_uint64), ("sweeps", C.c_int32), ("burn_in", C.c_int32),
-                ("flags", C.c_uint32), ("layout", C.c_uint32)]
+                ("flags", C.c_uint32), ("layout", C.c_uint32), ("measure_every", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class PTResult(C.Structure):
@@ -491,14 +492,15 @@ def pt_server_start(hbm_budget: int, steps_per_round: int = 100) -> Server:
 
 def pt_server_submit(server: Server, dim, L, replicas, samples, betas, couplings, seed, sweeps,
                      burn_in, houdayer=False, layout=PT_LAYOUT_INT8, walk=False,
-                     until_equilibrated=False, modes=False) -> int:
+                     until_equilibrated=False, modes=False, measure_every=1) -> int:
     b = np.ascontiguousarray(betas, dtype=np.float64)
     J = np.ascontiguousarray(couplings, dtype=np.int8)
     flags = (PT_MCS_HOUDAYER if houdayer else 0) | (PT_SERVE_UNTIL_EQUILIBRATED
                                                     if until_equilibrated else 0)
     req = PTRequest(int(dim), int(L), int(replicas), int(samples), b.ctypes.data, J.ctypes.data,
                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps), int(burn_in), flags,
-                    int(layout) | (PT_TRACK_WALK if walk else 0) | (PT_TRACK_MODES if modes else 0))
+                    int(layout) | (PT_TRACK_WALK if walk else 0) | (PT_TRACK_MODES if modes else 0),
+                    int(measure_every), 0)
     t = C.c_uint64(0)
     _check(lib().pt_server_submit(server.h, C.byref(req), C.byref(t)))
     server.replicas[t.value] = int(replicas)

@@ -191,3 +191,24 @@ def test_server_reports_correlation_length(pt):
     assert np.array_equal(got[:, 0], c0) and np.array_equal(got[:, 1], ck)
     assert np.array_equal(got[:, 2], xi, equal_nan=True)
     assert np.array_equal(res["m"]["disorder"], res["p"]["disorder"])
+
+
+def test_server_measurement_interval(pt):
+    """A request's measurement interval: the served result equals the job run
+    alone with the same interval (Sec. 3 measures at intervals)."""
+    dim, L, NT, S, sweeps, burn = 3, 8, 4, 2, 47, 9
+    J = W.couplings_pm_j(S, L, dim, 82)
+    b = W.geometric_betas(0.8, 2.0, NT)
+    srv = pt.pt_server_start(1 << 30, steps_per_round=8)
+    t = pt.pt_server_submit(srv, dim, L, NT, S, b, J, 6, sweeps, burn, measure_every=5, modes=True)
+    r = _wait(pt, srv, {0: t})[0]
+    pt.pt_server_stop(srv)
+    job = pt.pt_init(S, NT, L, dim, J, b, 6, modes=True)
+    pt.pt_set_measure_interval(job, 5)
+    pt.pt_mcs(job, burn)
+    pt.pt_mcs(job, sweeps - burn, measure=True)
+    _, dis, nm = pt.pt_observables(job)
+    assert r["n_meas"] == nm == len([t1 for t1 in range(burn + 1, sweeps + 1) if t1 % 5 == 0])
+    assert np.array_equal(r["disorder"], dis)
+    c0, ck, xi = pt.pt_correlation_length(job)
+    assert np.array_equal(r["correlation"][:, 0], c0)
