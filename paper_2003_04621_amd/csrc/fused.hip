@@ -153,6 +153,9 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
     // position cur the next rejection is the first step k >= cur whose
     // decision for cur is a rejection, found by one ballot; the configuration
     // carried up from cur stops there and the one at k + 1 is carried on.
+    // The walking wavefronts hold up the rest of the workgroup at the next
+    // barrier, so they issue ahead of the CU's other wavefronts meanwhile.
+    if (wave < nsets) __builtin_amdgcn_s_setprio(2);
     for (int cs = wave; cs < nsets; cs += nwave) {
       const int c = c_lo + cs;
       const int32_t* m0 = sot0 + c * NT;
@@ -195,6 +198,7 @@ __device__ __forceinline__ void exchange_resident(const FusedArgs& A, uint32_t* 
                        reinterpret_cast<uint64_t*>(lds + A.lay.trip), so[0], hot, m);
       }
     }
+    if (wave < nsets) __builtin_amdgcn_s_setprio(0);
   } else if (tid < nsets) {
     const int c = c_lo + tid;
     const int32_t* m0 = sot0 + c * NT;
