@@ -65,7 +65,8 @@ def _declare(L):
     L.or_create.restype = P
     L.or_destroy.argtypes = [P]
     L.or_destroy.restype = None
-    for name in ("or_exchange", "or_houdayer", "or_measure", "or_recompute_energies"):
+    for name in ("or_exchange", "or_houdayer", "or_houdayer_multi", "or_measure",
+                 "or_recompute_energies"):
         getattr(L, name).argtypes = [P]
         getattr(L, name).restype = None
     L.or_sweep.argtypes = [P, C.c_int]
@@ -74,6 +75,10 @@ def _declare(L):
     L.or_mcs.restype = None
     L.or_houdayer_move.argtypes = [C.c_int, C.c_int, P, P, P, C.c_uint64, P, P]
     L.or_houdayer_move.restype = C.c_int64
+    L.or_houdayer_multi_move.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P]
+    L.or_houdayer_multi_move.restype = C.c_int64
+    L.or_multi_coins.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, P]
+    L.or_multi_coins.restype = None
     L.or_observables.argtypes = [P, P, P, P]
     L.or_observables.restype = None
     L.or_get_spins.argtypes = [P, P]
@@ -178,6 +183,30 @@ def houdayer_move(L, d, J, sa, sb, r64):
     return int(delta), cl.astype(bool), int(size[0])
 
 
+def houdayer_multi_move(L, d, J, sa, sb, coin):
+    """Applies one multi-cluster Houdayer move in place on int8 arrays sa, sb:
+    the cluster whose lowest site is m is exchanged iff coin[m].
+
+    Returns (delta, exchanged-site mask, number of clusters)."""
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    assert sa.dtype == np.int8 and sb.dtype == np.int8
+    assert sa.flags.c_contiguous and sb.flags.c_contiguous
+    N = nsites(L, d)
+    c = np.ascontiguousarray(coin, dtype=np.uint8)
+    assert c.size == N
+    fl = np.zeros(N, np.int8)
+    n = np.zeros(1, np.int32)
+    delta = lib().or_houdayer_multi_move(L, d, _p(J), _p(sa), _p(sb), _p(c), _p(fl), _p(n))
+    return int(delta), fl.astype(bool), int(n[0])
+
+
+def multi_coins(seed: int, sample: int, k: int, v: int, N: int) -> np.ndarray:
+    """The coins of one multi-cluster move (pass v, temperature k, sample)."""
+    out = np.zeros(N, np.uint8)
+    lib().or_multi_coins(C.c_uint64(seed), sample, k, v, N, _p(out))
+    return out
+
+
 def density_of_states(L: int, d: int, J: np.ndarray) -> np.ndarray:
     N = nsites(L, d)
     J = np.ascontiguousarray(J, dtype=np.int8)
@@ -235,14 +264,21 @@ class OracleJob:
     def exchange(self):
         lib().or_exchange(self._h)
 
-    def houdayer(self):
-        lib().or_houdayer(self._h)
+    def houdayer(self, multi=False):
+        """One Houdayer pass; multi=True: the multi-cluster variant."""
+        if multi:
+            lib().or_houdayer_multi(self._h)
+        else:
+            lib().or_houdayer(self._h)
 
     def measure(self):
         lib().or_measure(self._h)
 
-    def mcs(self, n, houdayer=False, measure=False):
-        lib().or_mcs(self._h, int(n), int(bool(houdayer)), int(bool(measure)))
+    def mcs(self, n, houdayer=False, measure=False, multi=False):
+        """n Monte Carlo steps; multi=True makes the Houdayer moves the
+        multi-cluster variant."""
+        h = (2 if multi else 1) if houdayer else 0
+        lib().or_mcs(self._h, int(n), h, int(bool(measure)))
 
     def spins(self) -> np.ndarray:
         out = np.zeros((self.S, 2 * self.NT, self.N), np.int8)

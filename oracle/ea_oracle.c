@@ -16,7 +16,8 @@
  *   - Single-spin-flip Metropolis: Sec. 2.2 (Metropolis transition rates).
  *   - Replica exchange acceptance: Sec. 2.2, Eq. (5); exchange of temperatures
  *     rather than configurations with two index arrays: Sec. 2.2 and Sec. 3.
- *   - Houdayer cluster move in overlap space: Sec. 2.4, Eq. (10).
+ *   - Houdayer cluster move in overlap space: Sec. 2.4, Eq. (10); its
+ *     multi-cluster variant, which Sec. 3 and Sec. 5 propose.
  *   - One Monte Carlo step = Metropolis sweep, Houdayer move per same-T pair,
  *     PT update over neighbouring-T pairs: Sec. 2.4 (enumerated update scheme).
  *   - Counter-based Philox random numbers: Sec. 3 (Salmon et al. 2011).
@@ -82,7 +83,7 @@ OR_EXPORT void or_philox_stream(uint32_t c0, uint32_t c1, uint32_t c2,
 }
 
 /* Counter tags: the top four bits of the fourth counter word. */
-enum { OR_TAG_INIT = 2, OR_TAG_METRO = 3, OR_TAG_PT = 4, OR_TAG_HOU = 5 };
+enum { OR_TAG_INIT = 2, OR_TAG_METRO = 3, OR_TAG_PT = 4, OR_TAG_HOU = 5, OR_TAG_HOU_MULTI = 6 };
 
 static uint32_t or_rand_word(uint64_t seed, uint32_t c0, uint32_t c1,
                              uint32_t c2, uint32_t tag, uint32_t sample,
@@ -539,6 +540,109 @@ OR_EXPORT void or_houdayer(or_job *jb) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Multi-cluster variant of the Houdayer move.  Sec. 3 proposes turning the    */
+/* single-cluster update into a multi-cluster one, and Sec. 5 names this as    */
+/* the way to remove the idling that clusters of uneven size cause.  On the    */
+/* pair (a, b), every nearest-neighbour cluster of q = -1 sites is exchanged,  */
+/* independently of the others, with probability 1/2.  A cluster is named by   */
+/* its lowest site m and is exchanged iff coin[m] != 0 (coin has N entries;    */
+/* only those of the clusters' lowest sites are read).  Clusters are found in  */
+/* increasing order of m: a breadth-first search from each q = -1 site not     */
+/* yet in a cluster, taken in increasing i, starts at the cluster's lowest     */
+/* site.  Two clusters are never adjacent (adjacent q = -1 sites belong to one */
+/* cluster), so the neighbours outside a cluster have q = +1 and no exchange   */
+/* moves them: each cluster's energy change is computed from the state before */
+/* the move, and the order of the exchanges does not matter.  Returns delta    */
+/* with E_a += delta, E_b -= delta.  flip_out (may be NULL) receives 1 on      */
+/* exchanged sites, *nclusters (may be NULL) the number of clusters.           */
+/* ------------------------------------------------------------------------ */
+OR_EXPORT int64_t or_houdayer_multi_move(int L, int d, const int8_t *Jsample,
+                                         int8_t *sa, int8_t *sb, const uint8_t *coin,
+                                         int8_t *flip_out, int32_t *nclusters) {
+  int N = (d == 3) ? L * L * L : L * L;
+  int8_t *seen = (int8_t *)calloc((size_t)N, 1);
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * N);
+  int64_t delta = 0;
+  int32_t count = 0;
+  if (flip_out) memset(flip_out, 0, (size_t)N);
+  for (int m = 0; m < N; ++m) {
+    if (seen[m] || sa[m] == sb[m]) continue;
+    /* the cluster whose lowest site is m */
+    int head = 0, tail = 0;
+    seen[m] = 1;
+    queue[tail++] = m;
+    while (head < tail) {
+      int i = queue[head++];
+      for (int mu = 0; mu < d; ++mu)
+        for (int dir = -1; dir <= 1; dir += 2) {
+          int j = or_neighbour(L, d, i, mu, dir);
+          if (!seen[j] && sa[j] != sb[j]) {
+            seen[j] = 1;
+            queue[tail++] = j;
+          }
+        }
+    }
+    count += 1;
+    if (!coin[m]) continue;
+    /* every bond leaving the cluster changes sign in replica a */
+    for (int q = 0; q < tail; ++q) {
+      int i = queue[q];
+      for (int mu = 0; mu < d; ++mu)
+        for (int dir = -1; dir <= 1; dir += 2) {
+          int j = or_neighbour(L, d, i, mu, dir);
+          if (sa[j] == sb[j])
+            delta += 2 * (int64_t)or_bond(Jsample, L, d, N, i, mu, dir) * sa[i] * sa[j];
+        }
+    }
+    for (int q = 0; q < tail; ++q) {
+      int i = queue[q];
+      sa[i] = (int8_t)-sa[i];
+      sb[i] = (int8_t)-sb[i];
+      if (flip_out) flip_out[i] = 1;
+    }
+  }
+  if (nclusters) *nclusters = count;
+  free(seen);
+  free(queue);
+  return delta;
+}
+
+/* Coins of one multi-cluster move: coin[m] = bit (m mod 128) of the 128-bit
+   output of the Philox counter (m / 128, v, k, TAG_HOU_MULTI<<28 | sample),
+   bit j of the output being bit j mod 32 of word j / 32. */
+OR_EXPORT void or_multi_coins(uint64_t seed, uint32_t sample, uint32_t k, uint32_t v, int N,
+                              uint8_t *coin) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int m = 0; m < N; m += 128) {
+    uint32_t ctr[4] = {(uint32_t)(m / 128), v, k, ((uint32_t)OR_TAG_HOU_MULTI << 28) | sample};
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    for (int j = 0; j < 128 && m + j < N; ++j) coin[m + j] = (uint8_t)((w[j / 32] >> (j % 32)) & 1u);
+  }
+}
+
+/* One multi-cluster Houdayer pass: every sample, every temperature k, pair
+   (set 0, set 1) at k after the temperature relabelling, coins from
+   or_multi_coins with the Houdayer pass counter v (shared with the
+   single-cluster move). */
+OR_EXPORT void or_houdayer_multi(or_job *jb) {
+  const int NT = jb->NT;
+  uint8_t *coin = (uint8_t *)malloc((size_t)jb->N);
+  for (int s = 0; s < jb->S; ++s)
+    for (int k = 0; k < NT; ++k) {
+      int a = 0 * NT + jb->sot[((size_t)s * 2 + 0) * NT + k];
+      int b = 1 * NT + jb->sot[((size_t)s * 2 + 1) * NT + k];
+      or_multi_coins(jb->seed, jb->sample_key[s], (uint32_t)k, (uint32_t)jb->v, jb->N, coin);
+      int64_t delta = or_houdayer_multi_move(jb->L, jb->d, or_cpl(jb, s), or_lat(jb, s, a),
+                                             or_lat(jb, s, b), coin, NULL, NULL);
+      jb->E[(size_t)s * jb->nslot + a] += delta;
+      jb->E[(size_t)s * jb->nslot + b] -= delta;
+    }
+  free(coin);
+  jb->v += 1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Two-replica modes (usual definitions; the paper names the quantities but   */
 /* does not define them).  With the overlap field q_i = s_i^a s_i^b and the    */
 /* plane sums P_mu(x) = sum of q_i over the sites with coordinate x_mu = x,     */
@@ -619,12 +723,14 @@ OR_EXPORT void or_set_measure_every(or_job *jb, int every) {
 }
 
 /* One Monte Carlo step in the order of Sec. 2.4: one Metropolis sweep, then
-   (optionally) one Houdayer move per same-temperature pair, then one
+   (optionally) one Houdayer move per same-temperature pair -- houdayer = 1
+   the single-cluster move, 2 the multi-cluster one -- then one
    replica-exchange pass, then (optionally) one measurement. */
 OR_EXPORT void or_mcs(or_job *jb, int n, int houdayer, int measure) {
   for (int i = 0; i < n; ++i) {
     or_sweep(jb, 1);
-    if (houdayer) or_houdayer(jb);
+    if (houdayer == 2) or_houdayer_multi(jb);
+    else if (houdayer) or_houdayer(jb);
     or_exchange(jb);
     if (measure && jb->t % (uint64_t)jb->every == 0) or_measure(jb);
   }
