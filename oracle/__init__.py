@@ -1,7 +1,8 @@
 """CPU oracle for the parallel-tempering EA spin-glass path -- TEST INFRASTRUCTURE.
 
-A plain, slow, single-threaded C implementation (``ea_oracle.c``) of what the
-GPU path computes, plus an independent exact-enumeration helper (``enum.c``).
+A plain, slow, single-threaded C implementation (``ea_oracle.c`` for bimodal
+couplings, ``gauss_oracle.c`` for Gaussian ones) of what the GPU path
+computes, plus an independent exact-enumeration helper (``enum.c``).
 Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package; the product library never does.
 
@@ -19,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["ea_oracle.c", "enum.c"]
+_SOURCES = ["ea_oracle.c", "enum.c", "gauss_oracle.c"]
 _lib = None
 
 
@@ -28,7 +29,7 @@ def build() -> str:
     srcs = [os.path.join(_HERE, s) for s in _SOURCES]
     tmp = _LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fvisibility=hidden",
-           "-o", tmp] + srcs + ["-lm"]
+           "-o", tmp] + srcs + ["-lquadmath", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -98,6 +99,30 @@ def _declare(L):
     L.or_sweep_order.argtypes = [C.c_int, C.c_int, P]
     L.or_metro_rule.argtypes = [C.c_int, C.c_uint32, P]
     L.or_metro_rule.restype = C.c_int
+    L.org_energy.argtypes = [C.c_int, C.c_int, P, P]
+    L.org_energy.restype = C.c_int64
+    L.org_local_x.argtypes = [C.c_int, C.c_int, P, P, C.c_int]
+    L.org_local_x.restype = C.c_int64
+    L.org_accept.argtypes = [C.c_uint32, C.c_double, C.c_int64]
+    L.org_accept.restype = C.c_int
+    L.org_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_uint64, P]
+    L.org_create.restype = P
+    L.org_destroy.argtypes = [P]
+    L.org_destroy.restype = None
+    for name in ("org_exchange", "org_measure", "org_recompute_energies"):
+        getattr(L, name).argtypes = [P]
+        getattr(L, name).restype = None
+    L.org_sweep.argtypes = [P, C.c_int]
+    L.org_houdayer.argtypes = [P, C.c_int]
+    L.org_mcs.argtypes = [P, C.c_int, C.c_int, C.c_int]
+    L.org_set_measure_every.argtypes = [P, C.c_int]
+    L.org_observables.argtypes = [P, P, P, P]
+    L.org_get_spins.argtypes = [P, P]
+    L.org_set_spins.argtypes = [P, P]
+    L.org_get_energies.argtypes = [P, P]
+    L.org_get_maps.argtypes = [P, P, P]
+    L.org_get_counters.argtypes = [P, P]
+    L.org_get_moments.argtypes = [P, P, P, P, P, P, P]
     L.en_density_of_states.argtypes = [C.c_int, C.c_int, P, P]
     L.en_density_of_states.restype = C.c_int
     L.en_state_energies.argtypes = [C.c_int, C.c_int, P, P]
@@ -474,3 +499,116 @@ def correlation_length(modes, Q2, n_meas: int, L: int, d: int):
         if chik[k] > 0 and chi0[k] / chik[k] >= 1.0:
             xi[k] = math.sqrt(chi0[k] / chik[k] - 1.0) / (2.0 * math.sin(math.pi / L))
     return chi0, chik, xi
+
+
+# --------------------------------------------------------------------------
+# Gaussian couplings (gauss_oracle.c)
+# --------------------------------------------------------------------------
+GAUSS_UNIT = 2.0 ** -16
+
+
+def gauss_energy(L: int, d: int, Jn: np.ndarray, spins: np.ndarray) -> int:
+    """Eq. (1) in 2^-16 units for coupling units Jn [d][N]."""
+    J = np.ascontiguousarray(Jn, dtype=np.int32)
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    return int(lib().org_energy(L, d, _p(J), _p(s)))
+
+
+def gauss_local_x(L: int, d: int, Jn: np.ndarray, spins: np.ndarray, i: int) -> int:
+    J = np.ascontiguousarray(Jn, dtype=np.int32)
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    return int(lib().org_local_x(L, d, _p(J), _p(s), i))
+
+
+def gauss_accept(r: int, b: float, u: int) -> int:
+    """1 iff r < 2^32 exp(-b u 2^-16) (b > 0, u > 0 units of 2^-16)."""
+    return int(lib().org_accept(int(r), float(b), int(u)))
+
+
+class OracleGaussJob:
+    """S samples x 2 replica sets x NT temperatures with Gaussian couplings
+    given as integer units Jn [S][d][N] of 2^-16; energies in the same units."""
+
+    def __init__(self, samples, replicas, L, dim, couplings_units, betas, seed, sample_keys=None):
+        self.S, self.NT, self.L, self.d = int(samples), int(replicas), int(L), int(dim)
+        self.N = nsites(self.L, self.d)
+        self._J = np.ascontiguousarray(couplings_units, dtype=np.int32).reshape(self.S, self.d, self.N)
+        self._b = np.ascontiguousarray(betas, dtype=np.float64)
+        keys = None
+        if sample_keys is not None:
+            self._keys = np.ascontiguousarray(sample_keys, dtype=np.uint32)
+            keys = _p(self._keys)
+        self._h = lib().org_create(self.S, self.NT, self.L, self.d, _p(self._J), _p(self._b),
+                                   C.c_uint64(seed), keys)
+        if not self._h:
+            raise ValueError("oracle rejected the job arguments")
+
+    def close(self):
+        if self._h:
+            lib().org_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n=1):
+        lib().org_sweep(self._h, int(n))
+
+    def exchange(self):
+        lib().org_exchange(self._h)
+
+    def houdayer(self, multi=False):
+        lib().org_houdayer(self._h, int(bool(multi)))
+
+    def measure(self):
+        lib().org_measure(self._h)
+
+    def mcs(self, n, houdayer=False, measure=False, multi=False):
+        h = (2 if multi else 1) if houdayer else 0
+        lib().org_mcs(self._h, int(n), h, int(bool(measure)))
+
+    def set_measure_every(self, every):
+        lib().org_set_measure_every(self._h, int(every))
+
+    def spins(self):
+        out = np.zeros((self.S, 2 * self.NT, self.N), np.int8)
+        lib().org_get_spins(self._h, _p(out))
+        return out
+
+    def set_spins(self, spins):
+        s = np.ascontiguousarray(spins, dtype=np.int8).reshape(self.S, 2 * self.NT, self.N)
+        lib().org_set_spins(self._h, _p(s))
+
+    def energies(self):
+        out = np.zeros((self.S, 2 * self.NT), np.int64)
+        lib().org_get_energies(self._h, _p(out))
+        return out
+
+    def maps(self):
+        sot = np.zeros((self.S, 2, self.NT), np.int32)
+        tos = np.zeros((self.S, 2, self.NT), np.int32)
+        lib().org_get_maps(self._h, _p(sot), _p(tos))
+        return sot, tos
+
+    def counters(self):
+        out = np.zeros(4, np.uint64)
+        lib().org_get_counters(self._h, _p(out))
+        return dict(t=int(out[0]), u=int(out[1]), v=int(out[2]), n_meas=int(out[3]))
+
+    def moments(self):
+        ST = (self.S, self.NT)
+        E, Q, AQ, Q2 = (np.zeros(ST, np.int64) for _ in range(4))
+        E2 = np.zeros(ST + (2,), np.uint64)
+        Q4 = np.zeros(ST + (2,), np.uint64)
+        lib().org_get_moments(self._h, _p(E), _p(E2), _p(Q), _p(AQ), _p(Q2), _p(Q4))
+        return dict(E=E, E2=E2, Q=Q, AQ=AQ, Q2=Q2, Q4=Q4)
+
+    def observables(self):
+        ps = np.zeros((self.S, self.NT, 5), np.float64)
+        dis = np.zeros((self.NT, 6), np.float64)
+        n = np.zeros(1, np.int64)
+        lib().org_observables(self._h, _p(ps), _p(dis), _p(n))
+        return ps, dis, int(n[0])

@@ -25,6 +25,26 @@ def couplings_pm_j(samples: int, L: int, dim: int, seed: int, p: float = 0.5) ->
     return np.where(u < p, 1, -1).astype(np.int8)
 
 
+# Gaussian couplings live on a fixed-point grid: J = n * GAUSS_UNIT, |J| <= GAUSS_MAX.
+GAUSS_UNIT = 2.0 ** -16
+GAUSS_MAX = 8.0
+
+
+def couplings_gauss(samples: int, L: int, dim: int, seed: int) -> np.ndarray:
+    """Gaussian couplings (Sec. 2.1: standard normal) as float32 [samples][dim][L^dim]:
+    normal draws rounded to the nearest multiple of 2^-16 and clipped to [-8, 8]
+    (the grid every value of which a float32 holds exactly)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((samples, dim, L ** dim))
+    n = np.clip(np.rint(z / GAUSS_UNIT), -GAUSS_MAX / GAUSS_UNIT, GAUSS_MAX / GAUSS_UNIT)
+    return (n * GAUSS_UNIT).astype(np.float32)
+
+
+def gauss_units(J: np.ndarray) -> np.ndarray:
+    """The integer grid units n = J / 2^-16 of float32 Gaussian couplings."""
+    return np.rint(np.asarray(J, np.float64) / GAUSS_UNIT).astype(np.int32)
+
+
 def ferromagnet(samples: int, L: int, dim: int) -> np.ndarray:
     """J = +1 everywhere (p = 1 in Eq. (2)): the pure Ising ferromagnet."""
     return np.ones((samples, dim, L ** dim), np.int8)
