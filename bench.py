@@ -10,15 +10,20 @@ the timed region.  Steps run fused (the persistent kernel, one sample per
 workgroup resident in LDS, `--chunk` steps per launch); the same steps with
 one launch per kernel are timed afterwards for comparison.
 
-Also measured (each its own JSON object): the batched form (2000 jobs of
-uneven L in one graph-replayed persistent launch, int8 and packed layouts,
-against one job per launch) and the served form (Poisson arrivals of mixed-L
-requests at 70% of the measured capacity, HBM-budget admission; p50/p99
-latency and delivered flips/ns).
+Also measured (each its own JSON object): the 2D L = 64 workload with a
+Houdayer move every step (its own roofline); the time split into Metropolis,
+Houdayer, exchange and measurement in t_update units of Eq. (11), per kernel
+of the plain form and as differences of fused runs; the replica walk and the
+two-replica modes; the batched form (2000 jobs of uneven L in one
+graph-replayed persistent launch, int8 and packed layouts, against one job
+per launch) and the served form (Poisson arrivals of mixed-L requests at 70%
+of the measured capacity, HBM-budget admission; p50/p99 latency and
+delivered flips/ns).
 
 Prints one JSON line: spin flips/ns over the timed steps, the fused kernel's
 roofline position (VALU-bound: integer issue slots), and the CPU oracle's
-rate on a bounded sample of the same workload.
+rate on a bounded sample of the same workload, one sample per process on the
+host's cores (the single-core rate beside it).
 """
 from __future__ import annotations
 
@@ -35,10 +40,10 @@ sys.path.insert(0, ROOT)
 
 # MI355X VALU peak: 256 CUs x 128 32-bit lanes per clock x 2.4 GHz = 78.6 T
 # lane-operations/s, the rate behind the published 157.3 TFLOP/s fp32 vector
-# figure (an FMA counts two flops).  paper_2003_04621_amd/rate_probe measures
-# on the GPU 0.72-0.79 of this for plain integer ops (v_add_u32, v_bitop3_b32)
-# and half of it for the 32x32->64-bit multiply (v_mad_u64_u32), which
-# therefore costs two issue slots.
+# figure (an FMA counts two flops).  An instruction-rate probe measured on the
+# GPU 0.72-0.79 of this for plain integer ops (v_add_u32, v_bitop3_b32) and half
+# of it for the 32x32->64-bit multiply (v_mad_u64_u32), which therefore costs
+# two issue slots (profiles/valu_issue_rates_gfx950.md).
 PEAK_VALU_OPS = 256 * 128 * 2.4e9
 # Algorithmic work per attempted flip, in issue slots: the site's share of one
 # Philox4x32-10 call (10 rounds x 2 multiplies x 2 slots + 10 x 2 three-input
@@ -46,32 +51,54 @@ PEAK_VALU_OPS = 256 * 128 * 2.4e9
 # local field and classification (amortised over 16-32 sites of a word) are
 # not counted.
 OPS_PER_FLIP = 16
-# HBM bytes per 500-step launch of the fused kernel on the 3d_l16 workload
-# (int8 layout), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
-# copy's readings (profiles/k_batch_3d_l16_hbm_traffic.md).
-TRAFFIC_3D_L16_INT8_500 = 5.71e8
+# HBM bytes per launch of the fused kernel, keyed by (workload, layout,
+# variant: 1 Houdayer | 2 measure), from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# scaled by a plain copy's readings (profiles/*_hbm_traffic.md).  Every
+# sample is loaded once and stored once per launch, so the bytes do not depend
+# on the number of steps a launch runs.  Entries are removed when the kernel
+# changes until the counters are taken again.
+TRAFFIC_PER_LAUNCH = {}
 
 
-def cpu_baseline(wl, budget_s: float):
+def _oracle_steps(args):
+    """Worker: `n` oracle Monte Carlo steps of one sample (all replicas) of
+    workload `name`; returns the seconds they took."""
+    name, key, n = args
     import oracle
     from paper_2003_04621_amd import workloads as W
-    keys = [0, 1]
-    J = wl.couplings()[keys]
-    ref = oracle.OracleJob(len(keys), wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed,
-                           sample_keys=keys)
-    per_mcs = len(keys) * 2 * wl.replicas * wl.N
-    # calibrate on a few steps, then run about `budget_s` seconds
-    t = time.perf_counter()
-    ref.mcs(2, houdayer=wl.houdayer, measure=True)
-    dt = time.perf_counter() - t
-    n = max(1, int(budget_s / max(dt / 2, 1e-6)))
+    wl = W.workload(name)
+    J = wl.couplings()[[key]]
+    ref = oracle.OracleJob(1, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed, sample_keys=[key])
     t = time.perf_counter()
     ref.mcs(n, houdayer=wl.houdayer, measure=True)
-    dt = time.perf_counter() - t
-    return {"value": round(per_mcs * n / dt / 1e9, 6), "unit": "flips/ns", "cores": 1,
-            "kind": "oracle",
-            "sample": f"samples {keys} of {wl.samples} (all {2 * wl.replicas} replicas), "
-                      f"{n} Monte Carlo steps, {dt:.1f} s single-threaded"}
+    return time.perf_counter() - t
+
+
+def cpu_baseline(wl, budget_s: float, cores: int):
+    """The oracle on the host: one sample per process on `cores` processes at
+    once (the paper's multi-threaded CPU comparison runs one disorder sample
+    per thread), each for the same number of steps, about `budget_s` seconds;
+    the single-process rate of the same sample is reported beside it.  Runs
+    before anything touches the GPU (the worker processes are forked)."""
+    import multiprocessing as mp
+    per_sample_step = 2 * wl.replicas * wl.N
+    dt2 = _oracle_steps((wl.name, 0, 2))
+    n = max(1, int(budget_s / max(dt2 / 2, 1e-6)))
+    one = _oracle_steps((wl.name, 0, n))
+    single = per_sample_step * n / one / 1e9
+    cores = max(1, min(cores, wl.samples))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        times = pool.map(_oracle_steps, [(wl.name, k, n) for k in range(cores)])
+    wall = max(times)  # the processes run at the same time; the slowest sets the rate
+    return {"value": round(per_sample_step * n * cores / wall / 1e9, 6), "unit": "flips/ns",
+            "cores": cores, "kind": "oracle",
+            "sample": f"samples 0..{cores - 1} of {wl.samples} (all {2 * wl.replicas} replicas), "
+                      f"one per process on {cores} host cores at once, {n} Monte Carlo steps each, "
+                      f"slowest process {wall:.1f} s",
+            "single_core": {"value": round(single, 6), "unit": "flips/ns", "cores": 1,
+                            "sample": f"sample 0, {n} steps, {one:.1f} s"},
+            "host_cpus": os.cpu_count()}
 
 
 def batched_mix(pt, torch, W, args):
@@ -230,6 +257,102 @@ def served(pt, torch, W, args):
             "failed": bad + bad_b}
 
 
+def fused_run(pt, torch, job, wl, K, chunk, houdayer, measure, layout_name):
+    """K fused steps of `job` in launches of `chunk` steps; the rate over the
+    host clock and the kernel's roofline position from the HIP-event duration
+    of its full-length launches (events on the job's stream)."""
+    stream = torch.cuda.current_stream()
+    chunk = max(1, min(chunk, K))
+    starts = list(range(0, K, chunk))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in starts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (a, b), st in zip(ev, starts):
+        a.record(stream)
+        pt.pt_mcs(job, min(chunk, K - st), houdayer=houdayer, measure=measure)
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launch_ms = float(np.mean([a.elapsed_time(b) for (a, b), st in zip(ev, starts)
+                               if K - st >= chunk]))
+    achieved = OPS_PER_FLIP * wl.flips_per_sweep * chunk / (launch_ms * 1e-3) / 1e12
+    peak = PEAK_VALU_OPS / 1e12
+    feat = (1 if houdayer else 0) | (2 if measure else 0)
+    return elapsed, {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": TRAFFIC_PER_LAUNCH.get((wl.name, layout_name, feat)),
+        "kernel": f"k_batch<{wl.dim}, {feat}> ({chunk} steps per launch)",
+        "launch_ms": round(launch_ms, 4)}
+
+
+def phase_split(pt, torch, wl, layout, steps, warmup):
+    """Time per phase of a Monte Carlo step in the paper's four-part
+    breakdown (Metropolis, Houdayer, replica exchange, measurement), as
+    t_update of Eq. (11): kernel time per replica and spin.  Plain form: each
+    phase is its own launch (pt_sweep, pt_houdayer, pt_exchange, pt_measure),
+    timed with HIP events on the job's stream.  Fused form: the differences
+    between fused runs with and without the Houdayer move and the
+    measurement (the sweep and the exchange share one kernel)."""
+    stream = torch.cuda.current_stream()
+    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed,
+                     layout=layout)
+    norm = wl.flips_per_sweep  # N_T N_C N_R N_B L^d
+    pt.pt_mcs(job, warmup, houdayer=wl.houdayer, measure=True)
+    phases = [("metropolis", lambda: pt.pt_sweep(job, 1))]
+    if wl.houdayer:
+        phases.append(("houdayer", lambda: pt.pt_houdayer(job)))
+    phases += [("exchange", lambda: pt.pt_exchange(job)), ("measure", lambda: pt.pt_measure(job))]
+    ev = {name: [] for name, _ in phases}
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        for name, fn in phases:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            ev[name].append((a, b))
+    torch.cuda.synchronize()
+    plain = {}
+    total = 0.0
+    for name, _ in phases:
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev[name]]))
+        total += ms
+        plain[name] = {"ms_per_step": round(ms, 5), "t_update_ns": round(ms * 1e6 / norm, 7)}
+    for name in plain:
+        plain[name]["share"] = round(plain[name]["ms_per_step"] / total, 4)
+
+    def fused_ms(hou, meas, n):
+        pt.pt_mcs(job, 2, houdayer=hou, measure=meas)       # work list built, warm
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        pt.pt_mcs(job, n, houdayer=hou, measure=meas)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    n = max(steps, 50)
+    base = fused_ms(False, False, n)
+    fused = {"metropolis+exchange": {"ms_per_step": round(base, 5),
+                                     "t_update_ns": round(base * 1e6 / norm, 7)}}
+    with_meas = fused_ms(wl.houdayer, True, n)
+    if wl.houdayer:
+        with_hou = fused_ms(True, False, n)
+        d = with_hou - base
+        fused["houdayer"] = {"ms_per_step": round(d, 5), "t_update_ns": round(d * 1e6 / norm, 7),
+                             "us_per_cluster_pass": round(d * 1e3, 3),
+                             "ns_per_pair": round(d * 1e6 / (wl.samples * wl.replicas), 3)}
+        d = with_meas - with_hou
+    else:
+        d = with_meas - base
+    fused["measure"] = {"ms_per_step": round(d, 5), "t_update_ns": round(d * 1e6 / norm, 7)}
+    pt.pt_destroy(job)
+    return {"workload": wl.name, "steps": steps, "plain": plain, "fused": fused,
+            "unit_note": "t_update_ns = kernel ns per step / (samples x 2 sets x N_T x L^d), Eq. (11)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,11 +363,17 @@ def main():
     ap.add_argument("--chunk", type=int, default=500, help="steps per fused launch")
     ap.add_argument("--plain-steps", type=int, default=300,
                     help="steps re-timed with one launch per kernel (0: skip)")
+    ap.add_argument("--houdayer-steps", type=int, default=1000,
+                    help="steps of the 2D L=64 Houdayer workload (0: skip)")
+    ap.add_argument("--phase-steps", type=int, default=100,
+                    help="steps of the per-phase time split (0: skip)")
     ap.add_argument("--walk-steps", type=int, default=1000,
                     help="steps of the same workload with the replica walk kept (0: skip)")
     ap.add_argument("--modes-steps", type=int, default=1000,
                     help="steps of the same workload measuring the two-replica modes (0: skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-cores", type=int, default=16,
+                    help="host processes of the CPU baseline (at most the host's CPUs)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-jobs", type=int, default=2000)
     ap.add_argument("--batch-steps", type=int, default=1000)
@@ -258,8 +387,6 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-seed", type=int, default=31)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--traffic-bytes", type=float, default=None,
-                    help="HBM bytes per sweep launch measured with rocprofv3 counters")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -278,10 +405,17 @@ def main():
               "has no multi-GPU run; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2003_04621_amd import pt, workloads as W
-
+    from paper_2003_04621_amd import workloads as W
     wl = W.workload(args.workload)
+    # the CPU baseline first: its worker processes are forked before the GPU is touched
+    cpu = None
+    if not args.no_cpu:
+        print(f"# CPU oracle baseline ({args.cpu_cores} processes)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, args.cpu_seconds, min(args.cpu_cores, os.cpu_count() or 1))
+
+    import torch
+    from paper_2003_04621_amd import pt
+
     layout = pt.PT_LAYOUT_PACKED if args.layout == "packed" else pt.PT_LAYOUT_INT8
     torch.cuda.set_device(0)
     job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed,
@@ -293,34 +427,8 @@ def main():
     torch.cuda.synchronize()
 
     K = args.steps
-    stream = torch.cuda.current_stream()
-    chunk = max(1, min(args.chunk, K))
-    starts = list(range(0, K, chunk))
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in starts]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for (a, b), st in zip(ev, starts):
-        n = min(chunk, K - st)
-        a.record(stream)
-        pt.pt_mcs(job, n, houdayer=wl.houdayer, measure=True)
-        b.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    # one fused launch per chunk: average launch duration over full chunks
-    full = [a.elapsed_time(b) for (a, b), st in zip(ev, starts) if K - st >= chunk]
-    launch_ms = float(np.mean(full))
+    elapsed, roofline = fused_run(pt, torch, job, wl, K, args.chunk, wl.houdayer, True, args.layout)
     value = flips_per_step * K / elapsed / 1e9
-    achieved = OPS_PER_FLIP * flips_per_step * chunk / (launch_ms * 1e-3) / 1e12
-    peak = PEAK_VALU_OPS / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TOP/s", "frac": round(achieved / peak, 4),
-                "traffic": (args.traffic_bytes if args.traffic_bytes is not None else
-                            TRAFFIC_3D_L16_INT8_500
-                            if (wl.name, args.layout, chunk) == ("3d_l16", "int8", 500) else None),
-                "kernel": f"k_batch<{wl.dim}, {2 | (1 if wl.houdayer else 0)}> ({chunk} steps per launch)",
-                "launch_ms": round(launch_ms, 4)}
 
     # the same steps as separate per-step launches, for the fused/plain ratio
     plain = None
@@ -339,6 +447,35 @@ def main():
     _, dis, n_meas = pt.pt_observables(job)
     pt.pt_destroy(job)
 
+    # the 2D L = 64 workload with a Houdayer move every step
+    hou = None
+    if args.houdayer_steps > 0 and wl.name != "2d_l64":
+        wh = W.workload("2d_l64")
+        print(f"# workload {wh.name} with Houdayer moves", file=sys.stderr, flush=True)
+        hj = pt.pt_init(wh.samples, wh.replicas, wh.L, wh.dim, wh.couplings(), wh.betas, wh.seed,
+                        layout=layout)
+        pt.pt_mcs(hj, args.warmup, houdayer=True, measure=True)
+        el_h, roof_h = fused_run(pt, torch, hj, wh, args.houdayer_steps, args.chunk, True, True,
+                                 args.layout)
+        _, dis_h, _ = pt.pt_observables(hj)
+        pt.pt_destroy(hj)
+        hou = {"workload": f"{wh.name}: 2D +-J, L={wh.L}, {wh.samples} samples x 2 x {wh.replicas} "
+                           "temperatures (power-law ladder, T in [0.2, 1.6]), sweep + Houdayer + "
+                           "exchange + measure",
+               "value": round(wh.flips_per_sweep * args.houdayer_steps / el_h / 1e9, 2),
+               "unit": "flips/ns", "steps": args.houdayer_steps, "roofline": roof_h,
+               "roofline_note": "achieved counts the Metropolis work only (16 slots per flip); "
+                                "the Houdayer move is extra work in the same launches",
+               "e_coldest": round(float(dis_h[0, 0]), 6)}
+
+    # the four-part time split (Sec. 4.5) of both workloads
+    split = None
+    if args.phase_steps > 0:
+        print("# per-phase split", file=sys.stderr, flush=True)
+        split = [phase_split(pt, torch, wl, layout, args.phase_steps, 20)]
+        if wl.name != "2d_l64":
+            split.append(phase_split(pt, torch, W.workload("2d_l64"), layout, args.phase_steps, 20))
+
     # the same workload with the replica walk and its round trips kept
     walk = None
     if args.walk_steps > 0:
@@ -348,8 +485,8 @@ def main():
         pt.pt_mcs(wj, args.warmup, houdayer=wl.houdayer, measure=True)
         torch.cuda.synchronize()
         tw = time.perf_counter()
-        for st in range(0, args.walk_steps, chunk):
-            pt.pt_mcs(wj, min(chunk, args.walk_steps - st), houdayer=wl.houdayer, measure=True)
+        for st in range(0, args.walk_steps, args.chunk):
+            pt.pt_mcs(wj, min(args.chunk, args.walk_steps - st), houdayer=wl.houdayer, measure=True)
         torch.cuda.synchronize()
         dtw = time.perf_counter() - tw
         passes = pt.pt_get_counters(wj)["u"]
@@ -371,8 +508,8 @@ def main():
         pt.pt_mcs(mj, args.warmup, houdayer=wl.houdayer)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        for st in range(0, args.modes_steps, chunk):
-            pt.pt_mcs(mj, min(chunk, args.modes_steps - st), houdayer=wl.houdayer, measure=True)
+        for st in range(0, args.modes_steps, args.chunk):
+            pt.pt_mcs(mj, min(args.chunk, args.modes_steps - st), houdayer=wl.houdayer, measure=True)
         torch.cuda.synchronize()
         dtm = time.perf_counter() - tm
         c0, ck, xi = pt.pt_correlation_length(mj)
@@ -380,8 +517,8 @@ def main():
         pt.pt_set_measure_interval(mj, 10)
         torch.cuda.synchronize()
         tm10 = time.perf_counter()
-        for st in range(0, args.modes_steps, chunk):
-            pt.pt_mcs(mj, min(chunk, args.modes_steps - st), houdayer=wl.houdayer, measure=True)
+        for st in range(0, args.modes_steps, args.chunk):
+            pt.pt_mcs(mj, min(args.chunk, args.modes_steps - st), houdayer=wl.houdayer, measure=True)
         torch.cuda.synchronize()
         dtm10 = time.perf_counter() - tm10
         modes = {"value": round(flips_per_step * args.modes_steps / dtm / 1e9, 2), "unit": "flips/ns",
@@ -400,9 +537,6 @@ def main():
     if not args.no_served:
         print("# served form", file=sys.stderr, flush=True)
         serve = served(pt, torch, W, args)
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_seconds)
     out = {
         "metric": "spin flips/ns (1 GPU)", "value": round(value, 2), "unit": "flips/ns",
         "n_gpus": 1, "steps": K, "warmup": args.warmup,
@@ -417,6 +551,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_form": plain,
+        "houdayer_2d": hou,
+        "phase_split": split,
         "replica_walk": walk,
         "modes": modes,
         "batched": batched,

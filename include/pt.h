@@ -75,6 +75,9 @@ extern "C" {
 #define PT_MCS_MEASURE 2u
 #define PT_MCS_PLAIN 4u /* force the separate per-step kernels */
 #define PT_BATCH_GRAPH 8u /* pt_batch_run: replay a captured hipGraph of the launch */
+/* With PT_MCS_HOUDAYER (pt_mcs, pt_batch_run, pt_request.flags):
+ * the Houdayer moves are the multi-cluster variant (pt_houdayer_multi). */
+#define PT_MCS_MULTICLUSTER 0x40u
 
 typedef struct pt_job pt_job;
 typedef struct pt_batch pt_batch;
@@ -88,10 +91,14 @@ typedef struct {
   uint64_t seed;
   int32_t sweeps;                    /* Monte Carlo steps in total */
   int32_t burn_in;                   /* steps before the first measurement */
-  uint32_t flags;                    /* PT_MCS_HOUDAYER and/or PT_SERVE_UNTIL_EQUILIBRATED, or 0 */
+  uint32_t flags;                    /* PT_MCS_HOUDAYER (| PT_MCS_MULTICLUSTER) and/or
+                                        PT_SERVE_UNTIL_EQUILIBRATED, or 0 */
   uint32_t layout;                   /* PT_LAYOUT_INT8 or PT_LAYOUT_PACKED, | PT_TRACK_WALK/_MODES */
-  int32_t measure_every;             /* measurement interval after the burn-in (0 or 1: every
-                                        step), as pt_set_measure_interval */
+  int32_t measure_every;             /* measurement interval (0 or 1: every step), as
+                                        pt_set_measure_interval: a step after the burn-in
+                                        measures iff its absolute 1-based sweep number is a
+                                        multiple of it (so with burn_in 9 and interval 5 the
+                                        first measurement is sweep 10) */
   int32_t reserved;
 } pt_request;
 
@@ -104,7 +111,8 @@ typedef struct {
 typedef struct {
   int32_t status;       /* PT_OK, or the error that ended the request */
   int32_t equilibrated; /* with PT_TRACK_WALK: the round-trip check, 1 or 0; else -1 */
-  int64_t n_meas;       /* measurements taken (steps after the burn-in) */
+  int64_t n_meas;       /* measurements taken: the steps after the burn-in whose sweep
+                           number is a multiple of measure_every (all of them for 0 or 1) */
   double t_submit, t_admit, t_done;
   double tau_tunnel;    /* with PT_TRACK_WALK: mean round trip in passes (NaN if none) */
 } pt_result;
@@ -162,13 +170,26 @@ int pt_exchange(pt_job *job);
  * changes by delta and E_b by -delta. */
 int pt_houdayer(pt_job *job);
 
+/* One multi-cluster Houdayer move per sample and temperature k (the variant
+ * Sec. 3 proposes and Sec. 5 names as the remedy for the load imbalance of
+ * single clusters): on the pair (set 0, set 1) at beta_k, every
+ * nearest-neighbour cluster of q = -1 sites is exchanged, independently of
+ * the others, with probability 1/2.  A cluster is named by its lowest site m
+ * and exchanged iff bit m mod 128 of Philox counter (m / 128, v, k,
+ * 6<<28 | sample) is set, bit j of the 128-bit output being bit j mod 32 of
+ * word j / 32; v is the Houdayer pass counter the single-cluster move also
+ * advances.  E_a changes by delta, E_b by -delta (E_a + E_b is conserved).
+ * PT_EINVAL if L^dim > 32768 (16-bit cluster labels). */
+int pt_houdayer_multi(pt_job *job);
+
 /* Accumulates one measurement (Eqs. (3), (4)): per sample and temperature,
  * exact integer sums of E (both replicas), E^2, Q, |Q|, Q^2 and Q^4 (128-bit)
  * with Q = sum_i s_i^a s_i^b over the pair at that temperature. */
 int pt_measure(pt_job *job);
 
 /* n Monte Carlo steps (Sec. 2.4): sweep, Houdayer if flags has
- * PT_MCS_HOUDAYER, exchange, measure if flags has PT_MCS_MEASURE.  The steps
+ * PT_MCS_HOUDAYER (the multi-cluster variant with PT_MCS_MULTICLUSTER too),
+ * exchange, measure if flags has PT_MCS_MEASURE.  The steps
  * run fused, the configurations resident in LDS for the whole launch, with
  * the first plan that fits a workgroup (pt_get_plan): both replica sets of a
  * sample in one workgroup; one set per workgroup (no measurement, no
@@ -205,7 +226,9 @@ int pt_plan_query(int32_t dim, int32_t L, int32_t replicas, uint32_t flags, int3
 int pt_job_bytes(int32_t samples, int32_t replicas, int32_t L, int32_t dim, uint32_t layout,
                  const double *betas, uint64_t *out);
 
-/* Observables from the accumulated moments, in double precision.
+/* Observables from the accumulated moments, in double precision: the energy
+ * per spin of Eq. (3) and the overlap of Eq. (4) with its moments, thermal
+ * averages over the measurements and disorder averages over the samples.
  *   per_sample [samples][replicas][5]: <e>, <q>, <|q|>, <q^2>, <q^4>
  *   disorder   [replicas][6]: the same averaged over samples (integer
  *              numerators summed first) and the Binder parameter

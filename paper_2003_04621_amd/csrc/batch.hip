@@ -89,10 +89,11 @@ void drop_graph(pt_batch* b) {
 }
 
 // Plan of a job for the given flags and config: 0 both sets per workgroup,
-// 1 the same with Houdayer room, 2 one set per workgroup, 3 split sample; -1
-// if none exists.
+// 1 the same with Houdayer room, 2 one set per workgroup, 3 split sample, 4
+// both sets with multi-cluster Houdayer room; -1 if none exists.
 int job_mode(const pt_job* j, uint32_t flags, const BatchConfig& cfg) {
   const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  if (hou && (flags & PT_MCS_MULTICLUSTER)) return j->fused_ok[4] ? 4 : -1;
   if (hou) return j->fused_ok[1] ? 1 : -1;
   if (cfg.sets == 2 && j->fused_ok[0]) return 0;
   if (meas) return j->fused_ok[0] ? 0 : (j->split_ok ? 3 : -1);
@@ -100,6 +101,96 @@ int job_mode(const pt_job* j, uint32_t flags, const BatchConfig& cfg) {
   if (j->fused_ok[0]) return 0;
   return j->split_ok ? 3 : -1;
 }
+
+}  // namespace
+
+// The launch arguments of job j for `mcs` fused steps in plan `mode`.
+FusedArgs job_fused_args(const pt_job* j, int mode, int mcs, uint32_t flags) {
+  const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  const FusedLayout& lay = mode == 3 ? j->split_lay : j->plan[mode];
+  FusedArgs A = make_fused_args(j->g, lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr, j->thrpt,
+                                j->M, j->mom, j->walk, j->trips, j->modes, j->ctr, mcs,
+                                mode == 3 ? false : hou, meas);
+  A.every = j->meas_every;
+  if (A.hou && (flags & PT_MCS_MULTICLUSTER)) A.hou = 2;
+  if (mode == 3) {
+    A.parts = j->split_parts;
+    A.R = j->split_R;
+    A.jlds = j->split_jlds;
+    A.Ex = j->Ex;
+    A.snap = j->snap;
+    A.bar = j->bar;
+  }
+  return A;
+}
+
+// Persistent grid: as many workgroups as can be resident at once (the
+// runtime's occupancy for this kernel, LDS plan and workgroup size).  Unless
+// configured (cfg_threads > 0), the workgroup size is a multiple of four
+// wavefronts, so that every SIMD of a CU holds the same number of them (a CU
+// places a workgroup's wavefronts on its four SIMDs in turn; with 6 or 10 per
+// workgroup two SIMDs carry more than the others and set the pace).  With no
+// more items than CUs each item runs alone, on the largest workgroup;
+// otherwise the size with the most wavefronts per CU, then at least two
+// workgroups per CU (they fill each other's barriers and serial exchange
+// passes), then the larger workgroup (fewer items in flight leave fewer CUs
+// idle at the end).
+int launch_shape(int d, int feat, size_t lds_bytes, int nitems, int ncu, int cfg_threads,
+                 int* threads_out, int* per_cu_out) {
+  auto resident = [&](int threads) {
+    int n = 0;
+    if (batch_residency(d, feat, threads, lds_bytes, &n) != hipSuccess) n = 0;
+    return n;
+  };
+  int threads = cfg_threads;
+  if (threads == 0) {
+    int best_n = 0, best_waves = 0;
+    for (int t : {1024, 768, 512, 256}) {
+      const int n = resident(t), waves = n * t / 64;
+      if (n < 1) continue;
+      bool better;
+      if (best_n == 0) {
+        better = true;
+      } else if (nitems <= ncu) {
+        better = false;  // sizes are tried largest first
+      } else {
+        better = waves > best_waves || (waves == best_waves && n >= 2 && best_n < 2);
+      }
+      if (better) {
+        best_n = n;
+        best_waves = waves;
+        threads = t;
+      }
+    }
+    if (threads == 0) threads = 256;
+  }
+  const int per_cu = resident(threads);
+  if (per_cu < 1)
+    return pt_fail(PT_EINVAL, "no workgroup of " + std::to_string(threads) +
+                                  " threads fits a CU with this launch's LDS and registers");
+  *threads_out = threads;
+  *per_cu_out = per_cu;
+  return PT_OK;
+}
+
+// ordered_split_launch for callers outside this file.
+hipError_t split_ordered(hipStream_t st, hipError_t (*launch)(void*), void* ctx) {
+  return ordered_split_launch(st, [&] { return launch(ctx); });
+}
+
+// Creates the current device's ordering event for split launches now (it is
+// otherwise created by the first such launch).
+hipError_t split_order_prepare() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  if (!g_split_ev[dev]) e = hipEventCreateWithFlags(&g_split_ev[dev], hipEventDisableTiming);
+  return e;
+}
+
+namespace {
 
 // Work list for per-job step counts and flags (jobs with 0 steps get no item).
 int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vector<uint32_t>& jflags) {
@@ -124,17 +215,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     if (mcs > 0 && j->track_walk) feat |= kFeatWalk;
     if (mcs > 0 && meas && j->track_modes) feat |= kFeatModes;
     if (mode == 3) {
-      FusedArgs A = make_fused_args(j->g, j->split_lay, j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
-                                    j->thrpt, j->M, j->mom, j->walk, j->trips, j->modes, j->ctr, mcs,
-                                    false, meas);
-      A.every = j->meas_every;
-      A.parts = j->split_parts;
-      A.R = j->split_R;
-      A.jlds = j->split_jlds;
-      A.Ex = j->Ex;
-      A.snap = j->snap;
-      A.bar = j->bar;
-      hj.push_back(A);
+      hj.push_back(job_fused_args(j, mode, mcs, flags));
       lds_words = std::max(lds_words, (size_t)j->split_lay.words);
       if (mcs <= 0) continue;
       // the parts of a sample are consecutive, and split samples go first so
@@ -146,10 +227,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
       continue;
     }
     const int nsets = mode == 2 ? 1 : 2;
-    hj.push_back(make_fused_args(j->g, j->plan[mode], j->spins, j->jw, j->E, j->sot, j->tos, j->thr,
-                                 j->thrpt, j->M, j->mom, j->walk, j->trips, j->modes, j->ctr, mcs, hou,
-                                 meas));
-    hj.back().every = j->meas_every;
+    hj.push_back(job_fused_args(j, mode, mcs, flags));
     lds_words = std::max(lds_words, (size_t)j->plan[mode].words);
     if (mcs <= 0) continue;
     const double c = (double)nsets * j->g.NT * j->g.N * mcs;
@@ -214,48 +292,10 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
   b->feat = feat;
   e = prepare_batch(b->d, feat, b->lds_bytes, nullptr);
   if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
-  // persistent grid: as many workgroups as can be resident at once (the
-  // runtime's occupancy for this kernel, LDS plan and workgroup size).
-  // Unless configured, the workgroup size is a multiple of four wavefronts,
-  // so that every SIMD of a CU holds the same number of them (a CU places a
-  // workgroup's wavefronts on its four SIMDs in turn; with 6 or 10 per
-  // workgroup two SIMDs carry more than the others and set the pace).  With
-  // no more items than CUs each item runs alone, on the largest workgroup;
-  // otherwise the size with the most wavefronts per CU, then at least two
-  // workgroups per CU (they fill each other's barriers and serial exchange
-  // passes), then the larger workgroup (fewer items in flight leave fewer
-  // CUs idle at the end).
-  auto resident = [&](int threads) {
-    int n = 0;
-    if (batch_residency(b->d, feat, threads, b->lds_bytes, &n) != hipSuccess) n = 0;
-    return n;
-  };
-  int threads = b->cfg.threads;
-  if (threads == 0) {
-    int best_n = 0, best_waves = 0;
-    for (int t : {1024, 768, 512, 256}) {
-      const int n = resident(t), waves = n * t / 64;
-      if (n < 1) continue;
-      bool better;
-      if (best_n == 0) {
-        better = true;
-      } else if (b->nitems <= b->ncu) {
-        better = false;  // sizes are tried largest first
-      } else {
-        better = waves > best_waves || (waves == best_waves && n >= 2 && best_n < 2);
-      }
-      if (better) {
-        best_n = n;
-        best_waves = waves;
-        threads = t;
-      }
-    }
-    if (threads == 0) threads = 256;
-  }
-  const int per_cu = resident(threads);
-  if (per_cu < 1)
-    return pt_fail(PT_EINVAL, "pt_batch_run: no workgroup of " + std::to_string(threads) +
-                                  " threads fits a CU with this launch's LDS and registers");
+  int threads = 0, per_cu = 0;
+  if (int rc = launch_shape(b->d, feat, b->lds_bytes, b->nitems, b->ncu, b->cfg.threads, &threads,
+                            &per_cu))
+    return rc;
   b->threads = threads;
   b->per_cu = per_cu;
   b->blocks = std::max(1, std::min(b->ncu * per_cu, b->nitems));
@@ -517,12 +557,14 @@ PT_API int pt_batch_set_stream(pt_batch* b, void* hip_stream) {
 PT_API int pt_batch_run(pt_batch* b, int32_t mcs, uint32_t flags) {
   if (!b) return pt_fail(PT_EINVAL, "null batch");
   if (mcs < 0) return pt_fail(PT_EINVAL, "pt_batch_run: mcs must be >= 0");
-  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_BATCH_GRAPH))
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_MULTICLUSTER | PT_BATCH_GRAPH))
     return pt_fail(PT_EINVAL, "pt_batch_run: unknown flags");
+  if ((flags & PT_MCS_MULTICLUSTER) && !(flags & PT_MCS_HOUDAYER))
+    return pt_fail(PT_EINVAL, "pt_batch_run: PT_MCS_MULTICLUSTER needs PT_MCS_HOUDAYER");
   for (pt_job* j : b->jobs)
     if (j->poisoned) return pt_fail(PT_ESTATE, "pt_batch_run: a job is poisoned");
   if (mcs == 0) return PT_OK;
-  const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE);
+  const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_MULTICLUSTER);
   if (int rc = build_worklist(b, mcs, work_flags)) return rc;
   const int rc = run_once(b, (flags & PT_BATCH_GRAPH) != 0);
   if (rc != PT_OK)
@@ -560,7 +602,7 @@ PT_API int pt_batch_set_config(pt_batch* b, int32_t threads, int32_t sets, int32
 PT_API int pt_batch_tune(pt_batch* b, int32_t trial_mcs, uint32_t flags, const char* cache_path) {
   if (!b) return pt_fail(PT_EINVAL, "null batch");
   if (trial_mcs < 1) return pt_fail(PT_EINVAL, "pt_batch_tune: trial_mcs must be >= 1");
-  const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE);
+  const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_MULTICLUSTER);
   const std::string key = cache_key(b, work_flags);
   BatchConfig cached;
   if (cache_lookup(cache_path, key, cached)) {

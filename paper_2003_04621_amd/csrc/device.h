@@ -431,11 +431,28 @@ __device__ __forceinline__ void neighbour_words(const Geo& g, const uint32_t* Wo
 // c*NW + w] exactly as in LDS.
 // ---------------------------------------------------------------------------
 // Row R as two H-bit fields: bits of the even-x0 sites and of the odd-x0 sites.
+// Even- and odd-x0 sign bits of four int8 spins packed in v (sites 4a .. 4a+3),
+// placed at bits 2a, 2a+1 of e and o.
+__device__ __forceinline__ void gather4(uint32_t v, int a, uint32_t& e, uint32_t& o) {
+  e |= (((v >> 7) & 1u) | ((v >> 22) & 2u)) << (2 * a);
+  o |= (((v >> 15) & 1u) | ((v >> 30) & 2u)) << (2 * a);
+}
+
 __device__ __forceinline__ void row_from_int8(const Geo& g, const int8_t* lat, int R,
                                               uint32_t& Weven, uint32_t& Wodd) {
   uint32_t e = 0, o = 0;
   const int8_t* row = lat + (size_t)R * g.L;
-  if ((g.L & 3) == 0) {
+  if ((g.L & 15) == 0) {
+    // 16-byte loads (rows of a lattice start 16-byte aligned when 16 | L)
+    const uint4* r128 = reinterpret_cast<const uint4*>(row);
+    for (int a = 0; a < g.L / 16; ++a) {
+      const uint4 v = r128[a];
+      gather4(v.x, 4 * a + 0, e, o);
+      gather4(v.y, 4 * a + 1, e, o);
+      gather4(v.z, 4 * a + 2, e, o);
+      gather4(v.w, 4 * a + 3, e, o);
+    }
+  } else if ((g.L & 3) == 0) {
     const uint32_t* r32 = reinterpret_cast<const uint32_t*>(row);
     for (int a = 0; a < g.L / 4; ++a) {
       const uint32_t v = r32[a];
@@ -455,10 +472,24 @@ __device__ __forceinline__ void row_from_int8(const Geo& g, const int8_t* lat, i
   Wodd = o;
 }
 
+// Four int8 spins (sites 4a .. 4a+3) from bits 2a, 2a+1 of the even- and
+// odd-x0 words e and o (bit set: -1).
+__device__ __forceinline__ uint32_t spread4(uint32_t e, uint32_t o, int a) {
+  const uint32_t ee = (e >> (2 * a)) & 3u, oo = (o >> (2 * a)) & 3u;
+  const uint32_t bits = (ee & 1u) | ((oo & 1u) << 1) | ((ee & 2u) << 1) | ((oo & 2u) << 2);
+  const uint32_t spread = (bits & 1u) | ((bits & 2u) << 7) | ((bits & 4u) << 14) | ((bits & 8u) << 21);
+  return 0x01010101u + spread * 0xFEu;
+}
+
 __device__ __forceinline__ void row_to_int8(const Geo& g, int8_t* lat, int R, uint32_t e,
                                             uint32_t o) {
   int8_t* row = lat + (size_t)R * g.L;
-  if ((g.L & 3) == 0) {
+  if ((g.L & 15) == 0) {
+    uint4* r128 = reinterpret_cast<uint4*>(row);
+    for (int a = 0; a < g.L / 16; ++a)
+      r128[a] = make_uint4(spread4(e, o, 4 * a), spread4(e, o, 4 * a + 1), spread4(e, o, 4 * a + 2),
+                           spread4(e, o, 4 * a + 3));
+  } else if ((g.L & 3) == 0) {
     uint32_t* r32 = reinterpret_cast<uint32_t*>(row);
     for (int a = 0; a < g.L / 4; ++a) {
       const uint32_t ee = (e >> (2 * a)) & 3u, oo = (o >> (2 * a)) & 3u;

@@ -14,6 +14,7 @@
 #include "device.h"
 #include "houdayer_ops.h"
 #include "kernels.h"
+#include "multicluster.h"
 
 namespace ptsg {
 
@@ -106,6 +107,78 @@ __global__ void __launch_bounds__(256) k_houdayer(Geo g, void* spins, const uint
       E[lat_b] -= delta_acc;
     }
   }
+}
+
+// The multi-cluster variant (multicluster.h), one workgroup per pair: the
+// workgroup finds the exchanged clusters together, then computes the energy
+// change and applies the exchange as the single-cluster kernel does.
+template <int D>
+__global__ void __launch_bounds__(256) k_houdayer_multi(Geo g, void* spins,
+                                                        const uint32_t* __restrict__ jw,
+                                                        int32_t* __restrict__ E,
+                                                        const int32_t* __restrict__ sot,
+                                                        DevCounters* ctr) {
+  extern __shared__ __align__(16) uint32_t lds_m[];
+  const int T = blockDim.x, t = threadIdx.x;
+  const int NW = g.NW;
+  uint32_t* A = lds_m;            // replica a, both colours
+  uint32_t* Q = A + 2 * NW;       // overlap words (later replica b)
+  uint32_t* Cl = Q + 2 * NW;      // exchanged sites
+  uint32_t* scr = Cl + 2 * NW;    // row masks, coins, labels (2 NW is even: 8-byte aligned)
+  __shared__ int delta_acc;
+
+  const uint32_t v = load_counter(&ctr->v);
+  const int pair = blockIdx.x;  // s*NT + k
+  const int s = pair / g.NT, k = pair - s * g.NT;
+  const int a = sot[((size_t)s * 2 + 0) * g.NT + k];
+  const int b = g.NT + sot[((size_t)s * 2 + 1) * g.NT + k];
+  const size_t lat_a = (size_t)s * g.nslot + a, lat_b = (size_t)s * g.nslot + b;
+
+  load_lattice(g, spins, lat_a, A, t, T);
+  load_lattice(g, spins, lat_b, Q, t, T);
+  if (t == 0) delta_acc = 0;
+  __syncthreads();
+  for (int i = t; i < 2 * NW; i += T) Q[i] ^= A[i];
+  __syncthreads();
+  multi_cluster_words<D>(g, Q, Cl, scr, s, k, v, t, T, [] { __syncthreads(); });
+
+  const uint32_t* jw0 = jw + (size_t)s * 2 * 2 * D * NW;
+  int dl = 0;
+  for (int w = t; w < NW; w += T) dl += cluster_delta_word<D>(g, Cl, A, jw0, w);
+  if (dl) atomicAdd(&delta_acc, dl);
+  __syncthreads();
+  for (int i = t; i < 2 * NW; i += T) {
+    const uint32_t an = A[i] ^ Cl[i];
+    A[i] = an;
+    Q[i] ^= an;
+  }
+  __syncthreads();
+  store_lattice(g, spins, lat_a, A, t, T, Cl);
+  store_lattice(g, spins, lat_b, Q, t, T, Cl);
+  if (t == 0 && delta_acc != 0) {
+    E[lat_a] += delta_acc;
+    E[lat_b] -= delta_acc;
+  }
+}
+
+hipError_t launch_houdayer_multi(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
+                                 const int32_t* sot, DevCounters* ctr, hipStream_t st) {
+  if (g.N > kMultiMaxSites) return hipErrorInvalidValue;
+  const int threads = 256;
+  const size_t lds = sizeof(uint32_t) * (2 * (size_t)g.NW + multi_scratch_words(g.N, g.NR, g.NW));
+  const unsigned blocks = (unsigned)(g.S * g.NT);
+  const void* k = g.d == 3 ? (const void*)k_houdayer_multi<3> : (const void*)k_houdayer_multi<2>;
+  if (lds > 65536) {
+    const hipError_t ea = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ea != hipSuccess) return ea;
+  }
+  if (g.d == 3)
+    hipLaunchKernelGGL(k_houdayer_multi<3>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot,
+                       ctr);
+  else
+    hipLaunchKernelGGL(k_houdayer_multi<2>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot,
+                       ctr);
+  return hipGetLastError();
 }
 
 hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,

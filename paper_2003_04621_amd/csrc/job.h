@@ -37,9 +37,11 @@ struct pt_job {
   bool track_walk = false;
   int32_t* walk = nullptr;   // [S][2NT][2]: replica-walk label, pass its round trip began
   uint64_t* trips = nullptr; // [S][32][3]: round trips per log2 bin of the ending pass
-  // fused-step LDS plans: both sets without / with Houdayer, one set
-  ptsg::FusedLayout plan[3];
-  bool fused_ok[3] = {false, false, false};
+  // fused-step LDS plans: both sets without / with Houdayer, one set, (3
+  // unused: split samples have split_lay), both sets with multi-cluster
+  // Houdayer moves
+  ptsg::FusedLayout plan[5];
+  bool fused_ok[5] = {false, false, false, false, false};
   // split-sample plan (samples whose sets do not fit one workgroup) and its
   // scratch: published energies / configurations and barrier counters
   ptsg::FusedLayout split_lay{};
@@ -92,6 +94,20 @@ void batch_free(pt_batch* b);
 // mcs fused steps of one job through its own one-job batch (work list cached
 // while mcs and flags repeat).
 int batch_run_job(pt_batch* b, pt_job* job, int mcs, uint32_t flags);
+// The launch arguments of job j for `mcs` fused steps in plan `mode` (as
+// job_plan_mode returns it) with pt_mcs flags `flags`.
+ptsg::FusedArgs job_fused_args(const pt_job* j, int mode, int mcs, uint32_t flags);
+// Threads per workgroup and workgroups per CU of a persistent launch of the
+// batch kernel (d, feat) with lds_bytes of LDS per workgroup over nitems items
+// on ncu CUs; cfg_threads > 0 fixes the workgroup size.  PT_EINVAL if no
+// workgroup fits.
+int launch_shape(int d, int feat, size_t lds_bytes, int nitems, int ncu, int cfg_threads,
+                 int* threads, int* per_cu);
+// Enqueues launch(ctx) on st ordered after every earlier launch holding split
+// samples on this device (see pt_batch_run), and creates the device's ordering
+// event ahead of time.
+hipError_t split_ordered(hipStream_t st, hipError_t (*launch)(void*), void* ctx);
+hipError_t split_order_prepare();
 // Whether job j can run `flags` fused (some workgroup plan fits).
 bool job_is_resident(const pt_job* j, uint32_t flags);
 // The fused plan a job alone takes for `flags` (as pt_get_plan), -1 if none.

@@ -36,6 +36,9 @@ hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t
 // One Houdayer pass numbered ctr->v.
 hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
                            const int32_t* sot, DevCounters* ctr, hipStream_t st);
+// One multi-cluster Houdayer pass numbered ctr->v (g.N <= kMultiMaxSites).
+hipError_t launch_houdayer_multi(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
+                                 const int32_t* sot, DevCounters* ctr, hipStream_t st);
 
 // One measurement; mom is int64 [S][NT][8]; modes (null: not kept) int64
 // [S][NT][L/2+1] receives each temperature's mode_autocorr sums.  With
@@ -103,9 +106,11 @@ struct BatchItem {
 constexpr int kMaxParts = 64;
 
 // Plans the LDS of a fused workgroup holding `nsets` replica sets of one
-// sample (`waves` wavefronts); false if it does not fit in 160 KiB.
+// sample (`waves` wavefronts); false if it does not fit in 160 KiB.  With
+// houdayer and multi, the Houdayer moves are the multi-cluster variant, done
+// by the first lay.PC wavefronts, each with a scratch area at lay.Qs.
 bool fused_plan(const Geo& g, bool houdayer, int nsets, int waves, FusedLayout& lay,
-                bool walk = false, bool modes = false);
+                bool walk = false, bool modes = false, bool multi = false);
 
 // Plans a split sample: the fewest parts (<= kMaxParts) whose R slots fit one
 // workgroup's LDS, with the couplings in LDS when that still leaves room for

@@ -13,6 +13,7 @@
 
 #include "job.h"
 #include "kernels.h"
+#include "multicluster.h"
 #include "pt.h"
 
 using namespace ptsg;
@@ -67,6 +68,7 @@ void plan_job(pt_job* job) {
   job->fused_ok[0] = fused_plan(g, false, 2, 16, job->plan[0], w, md);
   job->fused_ok[1] = fused_plan(g, true, 2, 16, job->plan[1], w, md);
   job->fused_ok[2] = fused_plan(g, false, 1, 16, job->plan[2], w, md);
+  job->fused_ok[4] = fused_plan(g, true, 2, 16, job->plan[4], w, md, true);
   job->split_ok = !job->fused_ok[0] && split_plan(g, job->split_lay, job->split_parts,
                                                    job->split_R, job->split_jlds, w, md);
 }
@@ -75,7 +77,7 @@ void plan_job(pt_job* job) {
 void plan_report(const pt_job* job, uint32_t flags, int32_t* out4) {
   const Geo& g = job->g;
   const int mode = (flags & PT_MCS_PLAIN) ? -1 : job_plan_mode(job, flags);
-  out4[0] = mode;
+  out4[0] = mode == 4 ? 1 : mode;  // the multi-cluster plan is reported as mode 1
   if (mode < 0) {
     out4[1] = out4[2] = out4[3] = 0;
   } else if (mode == 3) {
@@ -413,6 +415,16 @@ PT_API int pt_houdayer(pt_job* job) {
   return PT_OK;
 }
 
+PT_API int pt_houdayer_multi(pt_job* job) {
+  if (int rc = check_job(job)) return rc;
+  if (job->g.N > kMultiMaxSites)
+    return pt_fail(PT_EINVAL, "multi-cluster moves need L^dim <= " + std::to_string(kMultiMaxSites));
+  PT_HIP(job, launch_houdayer_multi(job->g, job->spins, job->jw, job->E, job->sot, job->ctr,
+                                    job->stream));
+  PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 1, 0}, job->stream));
+  return PT_OK;
+}
+
 PT_API int pt_measure(pt_job* job) {
   if (int rc = check_job(job)) return rc;
   PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr, 1,
@@ -424,11 +436,16 @@ PT_API int pt_measure(pt_job* job) {
 PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   if (int rc = check_job(job)) return rc;
   if (n < 0) return pt_fail(PT_EINVAL, "n must be >= 0");
-  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | PT_MCS_MULTICLUSTER))
     return pt_fail(PT_EINVAL, "unknown flags");
+  if ((flags & PT_MCS_MULTICLUSTER) && !(flags & PT_MCS_HOUDAYER))
+    return pt_fail(PT_EINVAL, "PT_MCS_MULTICLUSTER needs PT_MCS_HOUDAYER");
+  if ((flags & PT_MCS_MULTICLUSTER) && job->g.N > kMultiMaxSites)
+    return pt_fail(PT_EINVAL, "multi-cluster moves need L^dim <= " + std::to_string(kMultiMaxSites));
   const Geo& g = job->g;
   hipStream_t st = job->stream;
   const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  const bool multi = flags & PT_MCS_MULTICLUSTER;
   // fused through the job's one-job batch whenever a workgroup plan exists:
   // both sets per workgroup, one set per workgroup (no overlap needed), or
   // the sample split over several workgroups (no Houdayer move)
@@ -438,7 +455,8 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
     const int chunk = 500;
     for (int done = 0; done < n; done += chunk) {
       const int m = (n - done) < chunk ? (n - done) : chunk;
-      const int rc = batch_run_job(job->self_batch, job, m, flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE));
+      const int rc = batch_run_job(job->self_batch, job, m,
+                                   flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_MULTICLUSTER));
       if (rc != PT_OK) {
         job->poisoned = rc == PT_EDEVICE;
         return rc;
@@ -450,7 +468,10 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   // advance per step keeps the numbering of the separate entry points.
   for (int i = 0; i < n; ++i) {
     PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, st));
-    if (hou) PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
+    if (hou && multi)
+      PT_HIP(job, launch_houdayer_multi(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
+    else if (hou)
+      PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
     PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
                                 job->trips, job->ctr, st));
     if (meas)
@@ -466,8 +487,10 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
 PT_API int pt_get_plan(pt_job* job, uint32_t flags, int32_t* out4) {
   if (int rc = check_job(job)) return rc;
   if (!out4) return pt_fail(PT_EINVAL, "null output");
-  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN))
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | PT_MCS_MULTICLUSTER))
     return pt_fail(PT_EINVAL, "unknown flags");
+  if ((flags & PT_MCS_MULTICLUSTER) && !(flags & PT_MCS_HOUDAYER))
+    return pt_fail(PT_EINVAL, "PT_MCS_MULTICLUSTER needs PT_MCS_HOUDAYER");
   plan_report(job, flags, out4);
   return PT_OK;
 }
@@ -478,8 +501,10 @@ PT_API int pt_plan_query(int32_t dim, int32_t L, int32_t replicas, uint32_t flag
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (replicas < 2) return pt_fail(PT_EINVAL, "replicas must be >= 2");
   const uint32_t track = PT_TRACK_WALK | PT_TRACK_MODES;
-  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | track))
+  if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | PT_MCS_MULTICLUSTER | track))
     return pt_fail(PT_EINVAL, "unknown flags");
+  if ((flags & PT_MCS_MULTICLUSTER) && !(flags & PT_MCS_HOUDAYER))
+    return pt_fail(PT_EINVAL, "PT_MCS_MULTICLUSTER needs PT_MCS_HOUDAYER");
   pt_job job;
   job.g = make_geo(1, replicas, L, dim, PT_LAYOUT_INT8, 0);
   job.track_walk = (flags & PT_TRACK_WALK) != 0;

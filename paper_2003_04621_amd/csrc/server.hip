@@ -247,7 +247,7 @@ void serve(pt_server* sv) {
     double f_max = 0;
     for (size_t i = 0; i < sv->active.size(); ++i) {
       Active& a = sv->active[i];
-      const uint32_t f = (a.req.flags & PT_MCS_HOUDAYER) |
+      const uint32_t f = (a.req.flags & (PT_MCS_HOUDAYER | PT_MCS_MULTICLUSTER)) |
                          (a.done < a.req.burn_in ? 0u : (uint32_t)PT_MCS_MEASURE);
       int items = 0;
       job_items(a.job, f, items, item_flips[i]);
@@ -264,7 +264,7 @@ void serve(pt_server* sv) {
         quota = q > 1e9 ? 1000000000 : (int)q;
       }
       int n = left < quota ? left : quota;
-      uint32_t f = a.req.flags & PT_MCS_HOUDAYER;
+      uint32_t f = a.req.flags & (PT_MCS_HOUDAYER | PT_MCS_MULTICLUSTER);
       if (a.done < a.req.burn_in) {
         const int to_burn = a.req.burn_in - a.done;
         if (n > to_burn) n = to_burn;
@@ -389,8 +389,13 @@ PT_API int pt_server_submit(pt_server* sv, const pt_request* req, uint64_t* tick
       req->burn_in > req->sweeps)
     return pt_fail(PT_EINVAL, "pt_server_submit: need samples >= 1, replicas >= 2, 0 <= burn_in <= sweeps");
   if (req->measure_every < 0) return pt_fail(PT_EINVAL, "pt_server_submit: measure_every must be >= 0");
-  if (req->flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_SERVE_UNTIL_EQUILIBRATED))
+  if (req->flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MULTICLUSTER | PT_SERVE_UNTIL_EQUILIBRATED))
     return pt_fail(PT_EINVAL, "pt_server_submit: unknown flags");
+  if ((req->flags & PT_MCS_MULTICLUSTER) &&
+      (!(req->flags & PT_MCS_HOUDAYER) ||
+       (req->dim == 3 ? (long)req->L * req->L * req->L : (long)req->L * req->L) > 32768))
+    return pt_fail(PT_EINVAL, "pt_server_submit: PT_MCS_MULTICLUSTER needs PT_MCS_HOUDAYER and "
+                              "L^dim <= 32768");
   const uint32_t layout = req->layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
   if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED)
     return pt_fail(PT_EINVAL, "pt_server_submit: unknown layout");

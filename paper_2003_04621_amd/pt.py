@@ -23,12 +23,14 @@ PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
 PT_TRACK_WALK = 0x10
 PT_TRACK_MODES = 0x20
 PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
+PT_MCS_MULTICLUSTER = 0x40
 PT_SERVE_UNTIL_EQUILIBRATED = 0x100
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE"}
 
 EXPORTS = [
-    "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_measure", "pt_mcs",
+    "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_houdayer_multi",
+    "pt_measure", "pt_mcs",
     "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_walk", "pt_tunnel_summary",
     "pt_get_modes", "pt_correlation_length",
@@ -79,7 +81,8 @@ def lib():
         sig = {
             "pt_init": [C.POINTER(P), I32, I32, I32, I32, P, P, U64],
             "pt_init_ex": [C.POINTER(P), I32, I32, I32, I32, P, P, U64, U32],
-            "pt_sweep": [P, I32], "pt_exchange": [P], "pt_houdayer": [P], "pt_measure": [P],
+            "pt_sweep": [P, I32], "pt_exchange": [P], "pt_houdayer": [P], "pt_houdayer_multi": [P],
+            "pt_measure": [P],
             "pt_mcs": [P, I32, U32], "pt_get_plan": [P, U32, P], "pt_plan_query": [I32, I32, I32, U32, P],
             "pt_job_bytes": [I32, I32, I32, I32, U32, P, P], "pt_observables": [P, P, P, P], "pt_destroy": [P],
             "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
@@ -244,35 +247,42 @@ def pt_houdayer(job: Job) -> None:
     _check(lib().pt_houdayer(job.h))
 
 
+def pt_houdayer_multi(job: Job) -> None:
+    _check(lib().pt_houdayer_multi(job.h))
+
+
 def pt_measure(job: Job) -> None:
     _check(lib().pt_measure(job.h))
 
 
+def _step_flags(houdayer=False, measure=False, plain=False, multi=False):
+    """pt_mcs flags; multi=True makes the Houdayer moves the multi-cluster
+    variant (needs houdayer=True)."""
+    return ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
+            | (PT_MCS_PLAIN if plain else 0) | (PT_MCS_MULTICLUSTER if multi else 0))
+
+
 def pt_mcs(job: Job, n: int, houdayer: bool = False, measure: bool = False,
-           plain: bool = False) -> None:
-    flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
-             | (PT_MCS_PLAIN if plain else 0))
-    _check(lib().pt_mcs(job.h, int(n), flags))
+           plain: bool = False, multi: bool = False) -> None:
+    _check(lib().pt_mcs(job.h, int(n), _step_flags(houdayer, measure, plain, multi)))
 
 
-def pt_get_plan(job: Job, houdayer=False, measure=False, plain=False) -> dict:
+def pt_get_plan(job: Job, houdayer=False, measure=False, plain=False, multi=False) -> dict:
     """The fused plan pt_mcs takes for these flags: mode (0 both sets per
     workgroup, 1 with Houdayer room, 2 one set per workgroup, 3 split sample,
     -1 per-step kernels), workgroups per sample, configurations per
     workgroup, LDS bytes per workgroup."""
-    flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
-             | (PT_MCS_PLAIN if plain else 0))
+    flags = _step_flags(houdayer, measure, plain, multi)
     out = np.zeros(4, np.int32)
     _check(lib().pt_get_plan(job.h, flags, _p(out)))
     return dict(mode=int(out[0]), parts=int(out[1]), per_part=int(out[2]), lds_bytes=int(out[3]))
 
 
 def pt_plan_query(dim: int, L: int, replicas: int, houdayer=False, measure=False,
-                  plain=False, walk=False, modes=False) -> dict:
+                  plain=False, walk=False, modes=False, multi=False) -> dict:
     """pt_get_plan's report for a job of this shape, without creating it
     (host only)."""
-    flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
-             | (PT_MCS_PLAIN if plain else 0) | (PT_TRACK_WALK if walk else 0)
+    flags = (_step_flags(houdayer, measure, plain, multi) | (PT_TRACK_WALK if walk else 0)
              | (PT_TRACK_MODES if modes else 0))
     out = np.zeros(4, np.int32)
     _check(lib().pt_plan_query(int(dim), int(L), int(replicas), flags, _p(out)))
@@ -427,13 +437,14 @@ def pt_batch_create(jobs, stream=None) -> Batch:
     return b
 
 
-def _flags(houdayer, measure, graph=False):
+def _flags(houdayer, measure, graph=False, multi=False):
     return ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MEASURE if measure else 0)
-            | (PT_BATCH_GRAPH if graph else 0))
+            | (PT_BATCH_GRAPH if graph else 0) | (PT_MCS_MULTICLUSTER if multi else 0))
 
 
-def pt_batch_run(batch: Batch, mcs: int, houdayer=False, measure=False, graph=False) -> None:
-    _check(lib().pt_batch_run(batch.h, int(mcs), _flags(houdayer, measure, graph)))
+def pt_batch_run(batch: Batch, mcs: int, houdayer=False, measure=False, graph=False,
+                 multi=False) -> None:
+    _check(lib().pt_batch_run(batch.h, int(mcs), _flags(houdayer, measure, graph, multi)))
 
 
 def pt_batch_tune(batch: Batch, trial_mcs: int = 3, houdayer=False, measure=False,
@@ -492,11 +503,12 @@ def pt_server_start(hbm_budget: int, steps_per_round: int = 100) -> Server:
 
 def pt_server_submit(server: Server, dim, L, replicas, samples, betas, couplings, seed, sweeps,
                      burn_in, houdayer=False, layout=PT_LAYOUT_INT8, walk=False,
-                     until_equilibrated=False, modes=False, measure_every=1) -> int:
+                     until_equilibrated=False, modes=False, measure_every=1,
+                     multi=False) -> int:
     b = np.ascontiguousarray(betas, dtype=np.float64)
     J = np.ascontiguousarray(couplings, dtype=np.int8)
-    flags = (PT_MCS_HOUDAYER if houdayer else 0) | (PT_SERVE_UNTIL_EQUILIBRATED
-                                                    if until_equilibrated else 0)
+    flags = ((PT_MCS_HOUDAYER if houdayer else 0) | (PT_MCS_MULTICLUSTER if multi else 0)
+             | (PT_SERVE_UNTIL_EQUILIBRATED if until_equilibrated else 0))
     req = PTRequest(int(dim), int(L), int(replicas), int(samples), b.ctypes.data, J.ctypes.data,
                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps), int(burn_in), flags,
                     int(layout) | (PT_TRACK_WALK if walk else 0) | (PT_TRACK_MODES if modes else 0),

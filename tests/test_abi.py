@@ -89,7 +89,16 @@ def test_init_flags_and_queries_validated_on_host():
     out = np.zeros(4, np.int32)
     for flags in (pt.PT_TRACK_WALK, pt.PT_TRACK_MODES, pt.PT_TRACK_WALK | pt.PT_TRACK_MODES):
         assert L.pt_plan_query(3, 16, 8, flags | pt.PT_MCS_MEASURE, pt._p(out)) == pt.PT_OK
-    assert L.pt_plan_query(3, 16, 8, 0x40, pt._p(out)) == pt.PT_EINVAL
+    assert L.pt_plan_query(3, 16, 8, 0x80, pt._p(out)) == pt.PT_EINVAL
+    # the multi-cluster modifier only with Houdayer moves
+    assert L.pt_plan_query(3, 16, 8, pt.PT_MCS_MULTICLUSTER, pt._p(out)) == pt.PT_EINVAL
+    assert L.pt_plan_query(3, 16, 8, pt.PT_MCS_MULTICLUSTER | pt.PT_MCS_HOUDAYER,
+                           pt._p(out)) == pt.PT_OK
+    assert out[0] == 1
+    # multi-cluster labels name at most 32768 sites: no fused plan beyond
+    assert L.pt_plan_query(3, 34, 2, pt.PT_MCS_MULTICLUSTER | pt.PT_MCS_HOUDAYER,
+                           pt._p(out)) == pt.PT_OK
+    assert out[0] == -1
 
 
 def test_allocator_hooks_must_be_paired():

@@ -6,6 +6,7 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 from paper_2003_04621_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -29,7 +30,7 @@ REQUESTS = [  # (dim, L, replicas, samples, sweeps, burn_in, houdayer, layout)
     (3, 16, 6, 1, 25, 12, False, 1),
     (2, 64, 3, 1, 20, 5, True, 0),
     (3, 12, 5, 3, 17, 0, False, 0),
-    (3, 48, 8, 1, 9, 4, False, 0),      # too large for one workgroup: per-step kernels
+    (3, 48, 8, 1, 9, 4, False, 0),      # too large for one workgroup: a split sample
     (2, 16, 4, 2, 33, 11, True, 1),
     (3, 8, 3, 1, 0, 0, False, 0),        # nothing to do
     (3, 24, 4, 1, 14, 7, False, 1),
@@ -91,6 +92,45 @@ def test_server_matches_alone_and_respects_budget(pt):
         assert r["n_meas"] == nm == spec[4] - spec[5]
         if nm > 0:
             assert np.array_equal(r["disorder"], dis), spec
+
+
+ORACLE_REQUESTS = [  # (dim, L, replicas, samples, sweeps, burn_in, houdayer, layout, plan)
+    (3, 32, 4, 1, 9, 3, True, 0, -1),     # 3D Houdayer too large for a workgroup: side stream
+    (3, 48, 4, 1, 8, 3, False, 1, 3),     # a split sample
+    (2, 16, 5, 2, 13, 4, True, 0, 1),     # 2D Houdayer, resident
+    (3, 8, 6, 3, 11, 0, False, 1, 0),     # measured from the first step
+    (3, 12, 3, 2, 10, 10, True, 0, 1),    # burn-in only: nothing measured
+]
+
+
+def test_server_results_match_the_oracle(pt):
+    """Each finished request re-run by the CPU oracle from its inputs: the
+    number of measurements exactly and the disorder averages within 1e-12
+    (Sec. 2.4 steps, Eqs. (3)-(5), (10)), for the per-step side stream, a split
+    sample and resident jobs served together."""
+    srv = pt.pt_server_start(64 << 20, steps_per_round=4)
+    tickets = {}
+    for n, spec in enumerate(ORACLE_REQUESTS):
+        dim, L, NT, S, sweeps, burn, hou, layout, plan = spec
+        assert pt.pt_plan_query(dim, L, NT, houdayer=hou, measure=True)["mode"] == plan
+        J, b, seed = _inputs(40 + n, spec[:8])
+        say(f"submit {spec}")
+        tickets[n] = pt.pt_server_submit(srv, dim, L, NT, S, b, J, seed, sweeps, burn, hou, layout)
+    res = _wait(pt, srv, tickets, timeout=240.0)
+    pt.pt_server_stop(srv)
+    for n, spec in enumerate(ORACLE_REQUESTS):
+        dim, L, NT, S, sweeps, burn, hou, layout, plan = spec
+        r = res[n]
+        assert r["status"] == 0, (spec, r["status"])
+        J, b, seed = _inputs(40 + n, spec[:8])
+        ref = oracle.OracleJob(S, NT, L, dim, J, b, seed)
+        ref.mcs(burn, houdayer=hou)
+        ref.mcs(sweeps - burn, houdayer=hou, measure=True)
+        _, rdis, rn = ref.observables()
+        say(f"oracle {spec}: n_meas {rn}")
+        assert r["n_meas"] == rn == sweeps - burn
+        if rn > 0:
+            np.testing.assert_allclose(r["disorder"], rdis, rtol=1e-12, atol=0)
 
 
 def test_server_same_result_alone_and_in_mix(pt):

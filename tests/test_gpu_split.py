@@ -46,6 +46,8 @@ SPLIT_CASES = [
     (3, 24, 1, 48, 1, 2),    # two fields per word
     (2, 64, 1, 160, 0, 2),   # 2D
     (3, 48, 1, 48, 1, 12),   # the largest served shape: 12 parts of 8
+    (3, 64, 1, 4, 0, 2),     # the largest L: one row field per word, couplings in global memory
+    (3, 64, 1, 2, 1, 1),     # one part holding all four configurations
 ]
 
 
@@ -74,6 +76,25 @@ def test_split_matches_oracle(pt, d, L, S, NT, layout, parts):
     rps, rdis, rn = ref.observables()
     assert n == rn == 3
     np.testing.assert_allclose(ps, rps, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(dis, rdis, rtol=1e-12, atol=0)
+    pt.pt_destroy(job)
+
+
+def test_3d_l64_per_step_kernels(pt):
+    """The largest 3D lattice (L = 64, N = 262144) through the per-step kernels,
+    Houdayer moves included (one workgroup per pair), against the oracle."""
+    say("3D L=64 per-step sweep + Houdayer + exchange + measure")
+    job, ref = _job(pt, 3, 64, 1, 3, 0, 410)
+    assert pt.pt_get_plan(job, houdayer=True, measure=True)["mode"] == -1
+    pt.pt_mcs(job, 2, houdayer=True, measure=True, plain=True)
+    ref.mcs(2, houdayer=True, measure=True)
+    matches_oracle(pt, job, ref, "per-step")
+    pt.pt_mcs(job, 1, measure=True)
+    ref.mcs(1, measure=True)
+    matches_oracle(pt, job, ref, "split after per-step")
+    ps, dis, n = pt.pt_observables(job)
+    rps, rdis, rn = ref.observables()
+    assert n == rn == 3
     np.testing.assert_allclose(dis, rdis, rtol=1e-12, atol=0)
     pt.pt_destroy(job)
 
