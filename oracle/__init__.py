@@ -93,6 +93,7 @@ def _declare(L):
     L.or_enable_modes.argtypes = [P]
     L.or_get_modes.argtypes = [P, P]
     L.or_set_measure_every.argtypes = [P, C.c_int]
+    L.or_get_stats.argtypes = [P, P]
     L.or_pt_table_len.argtypes = [P]
     L.or_pt_table_len.restype = C.c_int
     L.or_get_pt_table.argtypes = [P, P]
@@ -357,6 +358,15 @@ class OracleJob:
         trips = np.zeros((self.S, 32, 3), np.uint64)
         lib().or_get_walk(self._h, _p(lab), _p(beg), _p(trips))
         return lab, beg, trips
+
+    def stats(self):
+        """Run diagnostics [S][NT][24] (int64): accepted Metropolis flips at
+        temperature k, accepted exchanges of (k, k+1), Houdayer passes at k
+        that exchanged sites, the sites they exchanged, and a histogram of the
+        exchanged sites per pass by floor(log2) (20 bins)."""
+        out = np.zeros((self.S, self.NT, 24), np.int64)
+        lib().or_get_stats(self._h, _p(out))
+        return out
 
     def set_measure_every(self, every):
         """mcs() measures only after sweeps whose count is a multiple of every."""

@@ -236,7 +236,16 @@ typedef struct {
   int modes_on;
   int64_t *modes;         /* [S][NT][L/2+1]: plane-sum autocorrelations A(delta) */
   int every;              /* or_mcs measures when the sweep count is a multiple */
+  int64_t *stats;         /* [S][NT][OR_NSTAT] run diagnostics (always kept here) */
 } or_job;
+
+/* Run diagnostics per sample and temperature k (Sec. 2.3 discusses acceptance
+   rates, Sec. 3 the spread of cluster sizes): [0] accepted Metropolis flips of
+   the configurations at k during a sweep (both sets), [1] accepted exchanges
+   of the pair (k, k+1) (both sets), [2] Houdayer passes at k that exchanged at
+   least one site, [3] sites they exchanged, [4 + b] passes that exchanged
+   between 2^b and 2^(b+1) - 1 sites. */
+#define OR_NSTAT 24
 
 static int8_t *or_lat(or_job *jb, int s, int slot) {
   return jb->s + ((size_t)s * jb->nslot + slot) * jb->N;
@@ -291,6 +300,7 @@ OR_EXPORT or_job *or_create(int S, int NT, int L, int d, const int8_t *J,
   jb->wbeg = (uint32_t *)calloc((size_t)S * jb->nslot, sizeof(uint32_t));
   jb->trip = (uint64_t *)calloc((size_t)S * 32 * 3, sizeof(uint64_t));
   jb->every = 1;
+  jb->stats = (int64_t *)calloc((size_t)S * NT * OR_NSTAT, sizeof(int64_t));
   /* initial spins: one Philox word per site, s = -1 iff its top bit is set */
   for (int s = 0; s < S; ++s)
     for (int r = 0; r < jb->nslot; ++r) {
@@ -318,6 +328,7 @@ OR_EXPORT void or_destroy(or_job *jb) {
   free(jb->sot); free(jb->tos); free(jb->beta); free(jb->thr); free(jb->thrpt);
   free(jb->mE); free(jb->mE2); free(jb->mQ); free(jb->mAQ); free(jb->mQ2);
   free(jb->mQ4); free(jb->wlab); free(jb->wbeg); free(jb->trip); free(jb->modes);
+  free(jb->stats);
   free(jb);
 }
 
@@ -359,6 +370,7 @@ OR_EXPORT void or_sweep(or_job *jb, int n) {
             if (flip) {
               lat[i] = (int8_t)-lat[i];
               *Eslot += 2 * x;
+              jb->stats[((size_t)s * NT + k) * OR_NSTAT + 0] += 1;
             }
           }
         }
@@ -440,6 +452,7 @@ OR_EXPORT void or_exchange(or_job *jb) {
         if (acc) {
           sot[k] = b; sot[k + 1] = a;
           tos[b] = k; tos[a] = k + 1;
+          jb->stats[((size_t)s * NT + k) * OR_NSTAT + 1] += 1;
         }
       }
       or_walk_observe(jb, s, c, jb->u + 1);
@@ -515,6 +528,18 @@ OR_EXPORT int64_t or_houdayer_move(int L, int d, const int8_t *Jsample,
   return delta;
 }
 
+/* Diagnostics of one Houdayer move at temperature k that exchanged `size`
+   sites. */
+static void or_count_exchanged(or_job *jb, int s, int k, int32_t size) {
+  if (size <= 0) return;
+  int64_t *st = &jb->stats[((size_t)s * jb->NT + k) * OR_NSTAT];
+  int b = 0;
+  while ((size >> (b + 1)) != 0) ++b;
+  st[2] += 1;
+  st[3] += size;
+  st[4 + b] += 1;
+}
+
 /* One Houdayer pass: every sample, every temperature k, pair (set 0, set 1)
    at k after the temperature relabelling.  Random word: Philox counter
    (k, v, 0, TAG_HOU<<28 | sample), r64 = w0 | w1 << 32. */
@@ -530,11 +555,13 @@ OR_EXPORT void or_houdayer(or_job *jb) {
       uint32_t w[4];
       or_philox4x32_10(ctr, key, w);
       uint64_t r64 = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+      int32_t size = 0;
       int64_t delta = or_houdayer_move(jb->L, jb->d, or_cpl(jb, s),
                                        or_lat(jb, s, a), or_lat(jb, s, b), r64,
-                                       NULL, NULL);
+                                       NULL, &size);
       jb->E[(size_t)s * jb->nslot + a] += delta;
       jb->E[(size_t)s * jb->nslot + b] -= delta;
+      or_count_exchanged(jb, s, k, size);
     }
   jb->v += 1;
 }
@@ -633,10 +660,15 @@ OR_EXPORT void or_houdayer_multi(or_job *jb) {
       int a = 0 * NT + jb->sot[((size_t)s * 2 + 0) * NT + k];
       int b = 1 * NT + jb->sot[((size_t)s * 2 + 1) * NT + k];
       or_multi_coins(jb->seed, jb->sample_key[s], (uint32_t)k, (uint32_t)jb->v, jb->N, coin);
+      int8_t *fl = (int8_t *)malloc((size_t)jb->N);
       int64_t delta = or_houdayer_multi_move(jb->L, jb->d, or_cpl(jb, s), or_lat(jb, s, a),
-                                             or_lat(jb, s, b), coin, NULL, NULL);
+                                             or_lat(jb, s, b), coin, fl, NULL);
       jb->E[(size_t)s * jb->nslot + a] += delta;
       jb->E[(size_t)s * jb->nslot + b] -= delta;
+      int32_t size = 0;
+      for (int i = 0; i < jb->N; ++i) size += fl[i];
+      free(fl);
+      or_count_exchanged(jb, s, k, size);
     }
   free(coin);
   jb->v += 1;
@@ -822,6 +854,11 @@ OR_EXPORT void or_get_walk(const or_job *jb, int32_t *label, uint32_t *begin,
   if (begin) memcpy(begin, jb->wbeg, sizeof(uint32_t) * n);
   if (trips) memcpy(trips, jb->trip, sizeof(uint64_t) * (size_t)jb->S * 32 * 3);
 }
+/* Run diagnostics [S][NT][OR_NSTAT]. */
+OR_EXPORT void or_get_stats(const or_job *jb, int64_t *out) {
+  memcpy(out, jb->stats, sizeof(int64_t) * (size_t)jb->S * jb->NT * OR_NSTAT);
+}
+
 /* Accumulated modes [S][NT][L/2+1] (zeros if never enabled). */
 OR_EXPORT void or_get_modes(const or_job *jb, int64_t *out) {
   size_t n = (size_t)jb->S * jb->NT * (jb->L / 2 + 1);
