@@ -141,6 +141,45 @@ int pt_init_ex(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
                int32_t dim, const int8_t *couplings, const double *betas,
                uint64_t seed, uint32_t flags);
 
+/* A job with Gaussian couplings (Sec. 2.1: couplings drawn from a standard
+ * normal distribution; the 2D Gaussian workload of Sec. 4.2).  Couplings are
+ * host float32 [samples][dim][L^dim], each a multiple of 2^-16 with |J| <= 8
+ * (workloads.couplings_gauss draws them so), held internally as the integers
+ * n = J 2^16, so every local field and energy is an exact integer number of
+ * 2^-16 units.  Other arguments, the initial spins, maps, counters and
+ * random-number counters are pt_init_ex's; flags is a layout
+ * (PT_LAYOUT_INT8 or PT_LAYOUT_PACKED) with no tracking flags.
+ * The steps of such a job differ from the +-J rule only in the acceptance: a
+ * Metropolis flip with x = s_i h_i > 0 (energy change 2x units) is accepted
+ * iff its Philox word r < 2^32 exp(-beta_k 2x 2^-16), and an exchange with
+ * D > 0 units iff r < 2^32 exp(-(beta_k - beta_{k+1}) D 2^-16), both decided
+ * exactly (real-number comparisons of the integer r; see pt_gauss_accept_test).
+ * pt_sweep, pt_exchange, pt_houdayer, pt_houdayer_multi, pt_measure, pt_mcs
+ * (always the per-step kernels), pt_observables (energies per spin in
+ * coupling units), pt_get/set_spins, pt_get_maps, pt_get_counters,
+ * pt_set_measure_interval and pt_destroy take such jobs; energies and
+ * moments are read with pt_get_energies64 and pt_get_moments8; pt_get_energies,
+ * pt_get_moments, checkpoints, batches and the server refuse them
+ * (PT_EINVAL).  PT_EINVAL also for a coupling off the grid or out of range. */
+int pt_init_gauss(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
+                  int32_t dim, const float *couplings, const double *betas,
+                  uint64_t seed, uint32_t flags);
+
+/* The acceptance decisions of Gaussian jobs for test inputs (host arrays of
+ * n words r, inverse-temperature factors b > 0 and energy changes u > 0 in
+ * 2^-16 units, u <= 2^52): out[i] = 1 iff r[i] < 2^32 exp(-b[i] u[i] 2^-16),
+ * computed on the device by mode 0 the Metropolis path (u < 2^24: float32,
+ * then double, then double-double where a tier's error bound leaves the
+ * answer open), 1 the exchange path (double, then double-double), 2 the
+ * double-double evaluation alone.  Synchronous; allocates its own device
+ * buffers.  PT_EINVAL for out-of-range inputs or mode. */
+int pt_gauss_accept_test(const uint32_t *r, const double *b, const int64_t *u, int32_t *out,
+                         int32_t n, int32_t mode);
+
+/* The double-double decision of pt_gauss_accept_test's mode 2 run on the
+ * host: 1 accept, 0 reject, PT_EINVAL for b <= 0 or u out of (0, 2^52]. */
+int pt_gauss_accept_host(uint32_t r, double b, int64_t u);
+
 /* n >= 0 Metropolis sweeps (Sec. 2.2) of every configuration: colour 0 of
  * the checkerboard, then colour 1.  A site with x = s_i * sum_j J_ij s_j <= 0
  * always flips; otherwise it flips iff its 32-bit Philox word r satisfies
@@ -255,6 +294,14 @@ int pt_get_counters(pt_job *job, uint64_t *out);
 /* int64 [samples][replicas][7]: sum E, sum E^2, sum Q, sum |Q|, sum Q^2,
  * sum Q^4 low 64 bits, sum Q^4 high 64 bits */
 int pt_get_moments(pt_job *job, int64_t *out);
+/* Energies as int64 [samples][2*replicas]: in 2^-16 units for a Gaussian
+ * job, the +-J energies widened otherwise (Eq. (1)). */
+int pt_get_energies64(pt_job *job, int64_t *out);
+/* int64 [samples][replicas][8]: sum E, sum E^2 (low 64 bits), sum Q, sum |Q|,
+ * sum Q^2, sum Q^4 (low, high 64 bits), sum E^2 (high 64 bits; 0 for +-J
+ * jobs, whose E^2 sums fit 64 bits).  E in 2^-16 units for Gaussian jobs.
+ * Eqs. (3)-(4). */
+int pt_get_moments8(pt_job *job, int64_t *out);
 /* Replica walk in temperature space and round-trip times (Sec. 2.3: the
  * round-trip or tunnelling time is the expected number of Monte Carlo steps a
  * configuration needs from the lowest temperature to the highest and back).

@@ -50,6 +50,15 @@ struct pt_job {
   int32_t* Ex = nullptr;     // [S][2][2NT]
   uint32_t* snap = nullptr;  // [S][2][2NT][2NW]
   uint32_t* bar = nullptr;   // [S] barrier counters + fault word
+  // Gaussian couplings (pt_init_gauss): integer units, 64-bit energies, the
+  // per-group coupling data of gauss.h and the inverse temperatures; thr,
+  // thrpt, jw and E stay null for such a job
+  bool gauss = false;
+  int32_t* gJn = nullptr;    // [S][d][N] coupling units
+  int4* gJ = nullptr;        // [S][2][2d+1][NGc]
+  int64_t* E64 = nullptr;    // [S][2NT]
+  double* gbeta = nullptr;   // [NT]
+  float* gcz = nullptr;      // [NT]
   bool poisoned = false;
   struct pt_batch* self_batch = nullptr;  // one-job batch behind pt_mcs
   std::vector<void*> allocs;

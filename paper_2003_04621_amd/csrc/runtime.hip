@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include "gauss.h"
+#include "gauss_kernels.h"
 #include "job.h"
 #include "kernels.h"
 #include "multicluster.h"
@@ -318,6 +320,96 @@ PT_API int pt_init_ex(pt_job** out, int32_t samples, int32_t replicas, int32_t L
                     g_ctx, nullptr);
 }
 
+// A job with Gaussian couplings: float32 couplings on the 2^-16 grid (|J| <= 8)
+// held as integer units; spins as pt_init_ex's layouts; no replica walk or
+// modes.  The steps run as separate kernels on the job's stream.
+PT_API int pt_init_gauss(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
+                         const float* couplings, const double* betas, uint64_t seed, uint32_t flags) {
+  g_err.clear();
+  if (!out || !couplings || !betas) return pt_fail(PT_EINVAL, "null pointer argument");
+  if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
+  if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
+  if (samples < 1 || samples >= (1 << 28)) return pt_fail(PT_EINVAL, "samples must be in [1, 2^28)");
+  if (replicas < 2 || replicas > 4096) return pt_fail(PT_EINVAL, "replicas must be in [2, 4096]");
+  if (flags != PT_LAYOUT_INT8 && flags != PT_LAYOUT_PACKED)
+    return pt_fail(PT_EINVAL, "flags: a layout only (Gaussian jobs keep no replica walk or modes)");
+  for (int k = 0; k < replicas; ++k) {
+    if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
+      return pt_fail(PT_EINVAL, "betas must be finite and > 0");
+    if (k > 0 && !(betas[k] < betas[k - 1]))
+      return pt_fail(PT_EINVAL, "betas must be strictly decreasing (index 0 = coldest)");
+  }
+  const long N = (dim == 3) ? (long)L * L * L : (long)L * L;
+  const long ncoup = (long)samples * dim * N;
+  const long nlat = (long)samples * 2 * replicas;
+  if (nlat > 0x7FFFFFFFL || (long)samples * replicas > 0x7FFFFFFFL)
+    return pt_fail(PT_EINVAL, "too many lattices for one job");
+  std::vector<int32_t> units((size_t)ncoup);
+  for (long i = 0; i < ncoup; ++i) {
+    const float J = couplings[i];
+    const double n = (double)J * 65536.0;  // exact: a power-of-two scale of a float
+    if (!std::isfinite(J) || n != std::floor(n) || n > (double)kGaussMaxUnits ||
+        n < -(double)kGaussMaxUnits)
+      return pt_fail(PT_EINVAL, "Gaussian couplings must be multiples of 2^-16 in [-8, 8]");
+    units[(size_t)i] = (int32_t)n;
+  }
+
+  pt_job* job = new (std::nothrow) pt_job();
+  if (!job) return pt_fail(PT_ENOMEM, "host allocation failed");
+  job->alloc_fn = g_alloc;
+  job->free_fn = g_free;
+  job->alloc_ctx = g_ctx;
+  job->gauss = true;
+  job->g = make_geo(samples, replicas, L, dim, (int)flags, seed);
+  const Geo& g = job->g;
+  const size_t maps = sizeof(int32_t) * (size_t)samples * 2 * replicas;
+  const size_t ngrp = (size_t)samples * 2 * (2 * dim + 1) * gauss_groups(g);
+  job->spins = job->dalloc(job->spin_bytes());
+  job->gJn = (int32_t*)job->dalloc(sizeof(int32_t) * (size_t)ncoup);
+  job->gJ = (int4*)job->dalloc(sizeof(int4) * ngrp);
+  job->E64 = (int64_t*)job->dalloc(sizeof(int64_t) * (size_t)nlat);
+  job->sot = (int32_t*)job->dalloc(maps);
+  job->tos = (int32_t*)job->dalloc(maps);
+  job->gbeta = (double*)job->dalloc(sizeof(double) * replicas);
+  job->gcz = (float*)job->dalloc(sizeof(float) * replicas);
+  job->ctr = (DevCounters*)job->dalloc(sizeof(DevCounters));
+  job->mom = (int64_t*)job->dalloc(sizeof(int64_t) * 8 * (size_t)samples * replicas);
+  if (!job->spins || !job->gJn || !job->gJ || !job->E64 || !job->sot || !job->tos || !job->gbeta ||
+      !job->gcz || !job->ctr || !job->mom) {
+    job->release();
+    delete job;
+    return pt_fail(PT_ENOMEM, "device allocation failed");
+  }
+  std::vector<int32_t> ident((size_t)samples * 2 * replicas);
+  for (size_t i = 0; i < ident.size(); ++i) ident[i] = (int32_t)(i % replicas);
+  std::vector<float> cz((size_t)replicas);
+  for (int k = 0; k < replicas; ++k) cz[(size_t)k] = gauss_cz(betas[k]);
+  hipStream_t st = job->stream;
+  hipError_t e = hipSuccess;
+  auto step = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+  step(hipMemcpyAsync(job->gJn, units.data(), sizeof(int32_t) * units.size(), hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->gbeta, betas, sizeof(double) * replicas, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->gcz, cz.data(), sizeof(float) * replicas, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->sot, ident.data(), maps, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->tos, ident.data(), maps, hipMemcpyHostToDevice, st));
+  step(hipMemsetAsync(job->ctr, 0, sizeof(DevCounters), st));
+  step(hipMemsetAsync(job->mom, 0, sizeof(int64_t) * 8 * (size_t)samples * replicas, st));
+  step(launch_gauss_prepare(g, job->gJn, job->gJ, st));
+  step(launch_init_spins(g, job->spins, st));
+  step(launch_gauss_energy(g, job->spins, job->gJ, job->E64, st));
+  step(hipStreamSynchronize(st));
+  if (e != hipSuccess) {
+    std::string msg = std::string("pt_init_gauss: ") + hipGetErrorString(e);
+    job->release();
+    delete job;
+    return pt_fail(PT_EDEVICE, msg);
+  }
+  *out = job;
+  return PT_OK;
+}
+
 bool job_is_resident(const pt_job* j, uint32_t flags) { return job_plan_mode(j, flags) >= 0; }
 
 int pt_table_len(const double* betas, int NT, int d, long N) {
@@ -393,8 +485,12 @@ PT_API int pt_sweep(pt_job* job, int32_t n) {
   const int chunk = 1000;
   for (int done = 0; done < n; done += chunk) {
     const int m = (n - done) < chunk ? (n - done) : chunk;
-    PT_HIP(job, launch_sweep(job->g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, m,
-                             job->stream));
+    if (job->gauss)
+      PT_HIP(job, launch_gauss_sweep(job->g, job->spins, job->gJ, job->E64, job->tos, job->gbeta,
+                                     job->gcz, job->ctr, m, job->stream));
+    else
+      PT_HIP(job, launch_sweep(job->g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, m,
+                               job->stream));
     PT_HIP(job, launch_advance(job->ctr, CounterStep{(uint32_t)m, 0, 0, 0}, job->stream));
   }
   return PT_OK;
@@ -402,7 +498,11 @@ PT_API int pt_sweep(pt_job* job, int32_t n) {
 
 PT_API int pt_exchange(pt_job* job) {
   if (int rc = check_job(job)) return rc;
-  PT_HIP(job, launch_exchange(job->g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
+  if (job->gauss)
+    PT_HIP(job, launch_gauss_exchange(job->g, job->E64, job->sot, job->tos, job->gbeta, job->ctr,
+                                      job->stream));
+  else
+    PT_HIP(job, launch_exchange(job->g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
                               job->trips, job->ctr, job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 1, 0, 0}, job->stream));
   return PT_OK;
@@ -410,7 +510,11 @@ PT_API int pt_exchange(pt_job* job) {
 
 PT_API int pt_houdayer(pt_job* job) {
   if (int rc = check_job(job)) return rc;
-  PT_HIP(job, launch_houdayer(job->g, job->spins, job->jw, job->E, job->sot, job->ctr, job->stream));
+  if (job->gauss)
+    PT_HIP(job, launch_gauss_houdayer(job->g, job->spins, job->gJ, job->E64, job->sot, job->ctr, false,
+                                      job->stream));
+  else
+    PT_HIP(job, launch_houdayer(job->g, job->spins, job->jw, job->E, job->sot, job->ctr, job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 1, 0}, job->stream));
   return PT_OK;
 }
@@ -419,7 +523,11 @@ PT_API int pt_houdayer_multi(pt_job* job) {
   if (int rc = check_job(job)) return rc;
   if (job->g.N > kMultiMaxSites)
     return pt_fail(PT_EINVAL, "multi-cluster moves need L^dim <= " + std::to_string(kMultiMaxSites));
-  PT_HIP(job, launch_houdayer_multi(job->g, job->spins, job->jw, job->E, job->sot, job->ctr,
+  if (job->gauss)
+    PT_HIP(job, launch_gauss_houdayer(job->g, job->spins, job->gJ, job->E64, job->sot, job->ctr, true,
+                                      job->stream));
+  else
+    PT_HIP(job, launch_houdayer_multi(job->g, job->spins, job->jw, job->E, job->sot, job->ctr,
                                     job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 1, 0}, job->stream));
   return PT_OK;
@@ -427,13 +535,19 @@ PT_API int pt_houdayer_multi(pt_job* job) {
 
 PT_API int pt_measure(pt_job* job) {
   if (int rc = check_job(job)) return rc;
-  PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr, 1,
+  if (job->gauss)
+    PT_HIP(job, launch_gauss_measure(job->g, job->spins, job->E64, job->sot, job->mom, job->ctr, 1,
+                                     job->stream));
+  else
+    PT_HIP(job, launch_measure(job->g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr, 1,
                              job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 0, 1}, job->stream));
   return PT_OK;
 }
 
-PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
+namespace {
+// Argument checks of pt_mcs.
+int check_mcs(pt_job* job, int32_t n, uint32_t flags) {
   if (int rc = check_job(job)) return rc;
   if (n < 0) return pt_fail(PT_EINVAL, "n must be >= 0");
   if (flags & ~(uint32_t)(PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_PLAIN | PT_MCS_MULTICLUSTER))
@@ -442,15 +556,54 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
     return pt_fail(PT_EINVAL, "PT_MCS_MULTICLUSTER needs PT_MCS_HOUDAYER");
   if ((flags & PT_MCS_MULTICLUSTER) && job->g.N > kMultiMaxSites)
     return pt_fail(PT_EINVAL, "multi-cluster moves need L^dim <= " + std::to_string(kMultiMaxSites));
+  return PT_OK;
+}
+
+// n Monte Carlo steps as separate kernels, one launch per step and kernel
+// (no scratch, no allocation).  Within one step every counter is read by
+// exactly one kernel, so a single advance per step keeps the numbering of
+// the separate entry points.
+int mcs_per_step(pt_job* job, int32_t n, uint32_t flags) {
   const Geo& g = job->g;
   hipStream_t st = job->stream;
   const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
   const bool multi = flags & PT_MCS_MULTICLUSTER;
+  const CounterStep adv{1, 1, hou ? 1u : 0u, meas ? 1u : 0u, (uint32_t)job->meas_every};
+  for (int i = 0; i < n; ++i) {
+    if (job->gauss) {
+      PT_HIP(job, launch_gauss_sweep(g, job->spins, job->gJ, job->E64, job->tos, job->gbeta, job->gcz,
+                                     job->ctr, 1, st));
+      if (hou)
+        PT_HIP(job, launch_gauss_houdayer(g, job->spins, job->gJ, job->E64, job->sot, job->ctr, multi, st));
+      PT_HIP(job, launch_gauss_exchange(g, job->E64, job->sot, job->tos, job->gbeta, job->ctr, st));
+      if (meas)
+        PT_HIP(job, launch_gauss_measure(g, job->spins, job->E64, job->sot, job->mom, job->ctr,
+                                         job->meas_every, st));
+    } else {
+      PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, st));
+      if (hou && multi)
+        PT_HIP(job, launch_houdayer_multi(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
+      else if (hou)
+        PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
+      PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
+                                  job->trips, job->ctr, st));
+      if (meas)
+        PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr,
+                                   job->meas_every, st));
+    }
+    PT_HIP(job, launch_advance(job->ctr, adv, st));
+  }
+  return PT_OK;
+}
+}  // namespace
+
+PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
+  if (int rc = check_mcs(job, n, flags)) return rc;
   // fused through the job's one-job batch whenever a workgroup plan exists:
   // both sets per workgroup, one set per workgroup (no overlap needed), or
   // the sample split over several workgroups (no Houdayer move)
-  if (!(flags & PT_MCS_PLAIN) && job_is_resident(job, flags)) {
-    if (!job->self_batch) job->self_batch = batch_new(st);
+  if (!job->gauss && !(flags & PT_MCS_PLAIN) && job_is_resident(job, flags)) {
+    if (!job->self_batch) job->self_batch = batch_new(job->stream);
     if (!job->self_batch) return pt_fail(PT_ENOMEM, "pt_mcs: host allocation failed");
     const int chunk = 500;
     for (int done = 0; done < n; done += chunk) {
@@ -464,24 +617,7 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
     }
     return PT_OK;
   }
-  // Within one step every counter is read by exactly one kernel, so a single
-  // advance per step keeps the numbering of the separate entry points.
-  for (int i = 0; i < n; ++i) {
-    PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, st));
-    if (hou && multi)
-      PT_HIP(job, launch_houdayer_multi(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
-    else if (hou)
-      PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
-    PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
-                                job->trips, job->ctr, st));
-    if (meas)
-      PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr,
-                                 job->meas_every, st));
-    PT_HIP(job, launch_advance(job->ctr,
-                               CounterStep{1, 1, hou ? 1u : 0u, meas ? 1u : 0u, (uint32_t)job->meas_every},
-                               st));
-  }
-  return PT_OK;
+  return mcs_per_step(job, n, flags);
 }
 
 PT_API int pt_get_plan(pt_job* job, uint32_t flags, int32_t* out4) {
@@ -576,11 +712,17 @@ PT_API int pt_set_spins(pt_job* job, const int8_t* in) {
     pack_host(g, in, tmp.data());
     PT_HIP(job, hipMemcpyAsync(job->spins, tmp.data(), job->spin_bytes(), hipMemcpyHostToDevice,
                                job->stream));
-    PT_HIP(job, launch_energy(g, job->spins, job->jw, job->E, job->stream));
+    if (job->gauss)
+      PT_HIP(job, launch_gauss_energy(g, job->spins, job->gJ, job->E64, job->stream));
+    else
+      PT_HIP(job, launch_energy(g, job->spins, job->jw, job->E, job->stream));
     PT_HIP(job, hipStreamSynchronize(job->stream));
   } else {
     PT_HIP(job, hipMemcpyAsync(job->spins, in, n, hipMemcpyHostToDevice, job->stream));
-    PT_HIP(job, launch_energy(g, job->spins, job->jw, job->E, job->stream));
+    if (job->gauss)
+      PT_HIP(job, launch_gauss_energy(g, job->spins, job->gJ, job->E64, job->stream));
+    else
+      PT_HIP(job, launch_energy(g, job->spins, job->jw, job->E, job->stream));
     PT_HIP(job, hipStreamSynchronize(job->stream));
   }
   return PT_OK;
@@ -588,6 +730,7 @@ PT_API int pt_set_spins(pt_job* job, const int8_t* in) {
 
 PT_API int pt_get_energies(pt_job* job, int32_t* out) {
   if (int rc = check_job(job)) return rc;
+  if (job->gauss) return pt_fail(PT_EINVAL, "Gaussian energies are 64-bit: use pt_get_energies64");
   if (int rc = check_fault(job)) return rc;
   if (!out) return pt_fail(PT_EINVAL, "null output");
   const size_t n = (size_t)job->g.S * job->g.nslot;
@@ -610,6 +753,7 @@ PT_API int pt_get_maps(pt_job* job, int32_t* slot_of_temp, int32_t* temp_of_slot
 
 PT_API int pt_get_moments(pt_job* job, int64_t* out) {
   if (int rc = check_job(job)) return rc;
+  if (job->gauss) return pt_fail(PT_EINVAL, "Gaussian jobs keep 128-bit E^2 sums: use pt_get_moments8");
   if (int rc = check_fault(job)) return rc;
   if (!out) return pt_fail(PT_EINVAL, "null output");
   const size_t n = (size_t)job->g.S * job->g.NT;
@@ -620,6 +764,72 @@ PT_API int pt_get_moments(pt_job* job, int64_t* out) {
   for (size_t i = 0; i < n; ++i)
     for (int c = 0; c < 7; ++c) out[i * 7 + c] = m[i * 8 + c];
   return PT_OK;
+}
+
+PT_API int pt_get_energies64(pt_job* job, int64_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
+  if (!out) return pt_fail(PT_EINVAL, "null output");
+  const size_t n = (size_t)job->g.S * job->g.nslot;
+  if (job->gauss) {
+    PT_HIP(job, hipMemcpyAsync(out, job->E64, sizeof(int64_t) * n, hipMemcpyDeviceToHost, job->stream));
+    PT_HIP(job, hipStreamSynchronize(job->stream));
+    return PT_OK;
+  }
+  std::vector<int32_t> e32(n);
+  PT_HIP(job, hipMemcpyAsync(e32.data(), job->E, sizeof(int32_t) * n, hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  for (size_t i = 0; i < n; ++i) out[i] = e32[i];
+  return PT_OK;
+}
+
+PT_API int pt_get_moments8(pt_job* job, int64_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
+  if (!out) return pt_fail(PT_EINVAL, "null output");
+  const size_t n = (size_t)job->g.S * job->g.NT;
+  PT_HIP(job, hipMemcpyAsync(out, job->mom, sizeof(int64_t) * 8 * n, hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  if (!job->gauss)
+    for (size_t i = 0; i < n; ++i) out[i * 8 + 7] = 0;  // +-J: E^2 sums fit 64 bits
+  return PT_OK;
+}
+
+PT_API int pt_gauss_accept_test(const uint32_t* r, const double* b, const int64_t* u, int32_t* out,
+                                int32_t n, int32_t mode) {
+  if (!r || !b || !u || !out || n < 0) return pt_fail(PT_EINVAL, "null pointer or n < 0");
+  if (mode < 0 || mode > 2) return pt_fail(PT_EINVAL, "mode must be 0, 1 or 2");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!(b[i] > 0.0) || !std::isfinite(b[i]) || u[i] <= 0 || u[i] > (int64_t)1 << 52)
+      return pt_fail(PT_EINVAL, "need b > 0 finite and 0 < u <= 2^52");
+    if (mode == 0 && u[i] >= ((int64_t)1 << 24)) return pt_fail(PT_EINVAL, "mode 0 needs u < 2^24");
+  }
+  if (n == 0) return PT_OK;
+  uint32_t* dr = nullptr;
+  double* db = nullptr;
+  int64_t* du = nullptr;
+  int32_t* dout = nullptr;
+  hipError_t e = hipMalloc((void**)&dr, sizeof(uint32_t) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&db, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&du, sizeof(int64_t) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&dout, sizeof(int32_t) * n);
+  if (e == hipSuccess) e = hipMemcpy(dr, r, sizeof(uint32_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db, b, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(du, u, sizeof(int64_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_gauss_accept(dr, db, du, dout, n, mode, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+  (void)hipFree(dr);
+  (void)hipFree(db);
+  (void)hipFree(du);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_gauss_accept_test: ") + hipGetErrorString(e));
+  return PT_OK;
+}
+
+PT_API int pt_gauss_accept_host(uint32_t r, double b, int64_t u) {
+  if (!(b > 0.0) || !std::isfinite(b) || u <= 0 || u > (int64_t)1 << 52)
+    return pt_fail(PT_EINVAL, "need b > 0 finite and 0 < u <= 2^52");
+  return gauss_accept_dd(r, b, u) ? 1 : 0;
 }
 
 PT_API int pt_get_walk(pt_job* job, int32_t* label, uint32_t* begin, uint64_t* trips) {
@@ -766,6 +976,8 @@ PT_API int pt_observables(pt_job* job, double* per_sample, double* disorder, int
   if (n_meas) *n_meas = (int64_t)c.n_meas;
   const double nm = (double)c.n_meas, Nd = (double)g.N;
   const double N2 = Nd * Nd, N4 = N2 * N2;
+  // energies per spin in coupling units: Gaussian sums are in 2^-16 units
+  const double unit = job->gauss ? 1.0 / 65536.0 : 1.0;
   auto q4_of = [&](size_t i) {
     const unsigned __int128 v =
         ((unsigned __int128)(uint64_t)m[i * 8 + 6] << 64) | (unsigned __int128)(uint64_t)m[i * 8 + 5];
@@ -774,7 +986,7 @@ PT_API int pt_observables(pt_job* job, double* per_sample, double* disorder, int
   if (per_sample) {
     for (size_t i = 0; i < n; ++i) {
       double* o = per_sample + i * 5;
-      o[0] = (double)m[i * 8 + 0] / (2.0 * nm * Nd);
+      o[0] = (double)m[i * 8 + 0] * unit / (2.0 * nm * Nd);
       o[1] = (double)m[i * 8 + 2] / (nm * Nd);
       o[2] = (double)m[i * 8 + 3] / (nm * Nd);
       o[3] = (double)m[i * 8 + 4] / (nm * N2);
@@ -795,7 +1007,7 @@ PT_API int pt_observables(pt_job* job, double* per_sample, double* disorder, int
         sQ4 += q4_of(i);
       }
       double* o = disorder + (size_t)k * 6;
-      o[0] = (double)sE / (S * 2.0 * nm * Nd);
+      o[0] = (double)sE * unit / (S * 2.0 * nm * Nd);
       o[1] = (double)sQ / (S * nm * Nd);
       o[2] = (double)sAQ / (S * nm * Nd);
       o[3] = (double)sQ2 / (S * nm * N2);
@@ -834,6 +1046,7 @@ int32_t state_flags(const pt_job* job) {
 
 PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   if (int rc = check_job(job)) return rc;
+  if (job->gauss) return pt_fail(PT_EINVAL, "checkpoints of Gaussian jobs are not supported");
   if (int rc = check_fault(job)) return rc;
   if (!len) return pt_fail(PT_EINVAL, "null length");
   const size_t need = state_size(job);
@@ -880,6 +1093,7 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
 
 PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
   if (int rc = check_job(job)) return rc;
+  if (job->gauss) return pt_fail(PT_EINVAL, "checkpoints of Gaussian jobs are not supported");
   if (!buf) return pt_fail(PT_EINVAL, "null state buffer");
   if (len != state_size(job)) return pt_fail(PT_EINVAL, "state size does not match this job");
   const Geo& g = job->g;

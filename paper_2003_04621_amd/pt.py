@@ -40,6 +40,8 @@ EXPORTS = [
     "pt_batch_get_config", "pt_batch_set_config", "pt_batch_launch_shape", "pt_batch_destroy",
     "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_poll_ex", "pt_server_stats",
     "pt_server_stop",
+    "pt_init_gauss", "pt_get_energies64", "pt_get_moments8", "pt_gauss_accept_test",
+    "pt_gauss_accept_host",
 ]
 
 
@@ -102,6 +104,10 @@ def lib():
             "pt_server_poll": [P, C.c_uint64, C.POINTER(PTResult), P],
             "pt_server_poll_ex": [P, C.c_uint64, C.POINTER(PTResult), P, P],
             "pt_server_stats": [P, P], "pt_server_stop": [P],
+            "pt_init_gauss": [C.POINTER(P), I32, I32, I32, I32, P, P, U64, U32],
+            "pt_get_energies64": [P, P], "pt_get_moments8": [P, P],
+            "pt_gauss_accept_test": [P, P, P, P, I32, I32],
+            "pt_gauss_accept_host": [U32, C.c_double, C.c_int64],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -186,6 +192,7 @@ class Job:
         self.h = handle
         self.S, self.NT, self.L, self.d, self.layout = samples, replicas, L, dim, layout
         self.walk, self.modes = bool(walk), bool(modes)
+        self.gauss = False
         self.N = L ** dim
         _live_jobs.add(self)
 
@@ -223,6 +230,66 @@ def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_
         stream = torch.cuda.current_stream()
     pt_set_stream(job, stream)
     return job
+
+
+def pt_init_gauss(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_INT8,
+                  stream=None) -> Job:
+    """Creates a job with Gaussian couplings: float32 [samples][dim][L^dim] on
+    the 2^-16 grid, |J| <= 8 (workloads.couplings_gauss); `stream` as
+    pt_init's."""
+    import torch
+    if _hooks is None:
+        use_torch_memory()
+    J = np.ascontiguousarray(couplings, dtype=np.float32)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    if b.shape != (int(replicas),):
+        raise PTError(PT_EINVAL, "betas must have shape (replicas,)")
+    if J.size != int(samples) * int(dim) * int(L) ** int(dim):
+        raise PTError(PT_EINVAL, "couplings must have samples*dim*L^dim entries")
+    h = C.c_void_p()
+    _check(lib().pt_init_gauss(C.byref(h), int(samples), int(replicas), int(L), int(dim), _p(J),
+                               _p(b), C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(layout)))
+    job = Job(h, int(samples), int(replicas), int(L), int(dim), int(layout))
+    job.gauss = True
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    pt_set_stream(job, stream)
+    return job
+
+
+def pt_get_energies64(job: Job) -> np.ndarray:
+    """int64 [S][2NT]: 2^-16 units for Gaussian jobs."""
+    out = np.zeros((job.S, 2 * job.NT), np.int64)
+    _check(lib().pt_get_energies64(job.h, _p(out)))
+    return out
+
+
+def pt_get_moments8(job: Job) -> np.ndarray:
+    """int64 [S][NT][8]: E, E^2 lo, Q, |Q|, Q^2, Q^4 lo, Q^4 hi, E^2 hi."""
+    out = np.zeros((job.S, job.NT, 8), np.int64)
+    _check(lib().pt_get_moments8(job.h, _p(out)))
+    return out
+
+
+def pt_gauss_accept_test(r, b, u, mode: int) -> np.ndarray:
+    """Device acceptance decisions r < 2^32 exp(-b u 2^-16) (mode 0 Metropolis
+    tiers, 1 exchange tiers, 2 double-double alone)."""
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    if not (r.shape == b.shape == u.shape) or r.ndim != 1:
+        raise PTError(PT_EINVAL, "r, b, u must be 1-D arrays of one length")
+    out = np.zeros(r.shape, np.int32)
+    _check(lib().pt_gauss_accept_test(_p(r), _p(b), _p(u), _p(out), int(r.size), int(mode)))
+    return out
+
+
+def pt_gauss_accept_host(r: int, b: float, u: int) -> int:
+    """The double-double decision on the host (1 accept, 0 reject)."""
+    rc = lib().pt_gauss_accept_host(int(r) & 0xFFFFFFFF, float(b), int(u))
+    if rc < 0:
+        _check(rc)
+    return rc
 
 
 def pt_set_measure_interval(job: Job, every: int) -> None:

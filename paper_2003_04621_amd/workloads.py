@@ -102,6 +102,7 @@ class Workload:
     seed: int = 2000
     notes: str = ""
     extra: dict = field(default_factory=dict)
+    gauss: bool = False    # Gaussian couplings (float32 on the 2^-16 grid) instead of +-J
 
     @property
     def N(self) -> int:
@@ -114,6 +115,8 @@ class Workload:
         return self.samples * 2 * self.replicas * self.N
 
     def couplings(self) -> np.ndarray:
+        if self.gauss:
+            return couplings_gauss(self.samples, self.L, self.dim, self.couplings_seed)
         return couplings_pm_j(self.samples, self.L, self.dim, self.couplings_seed)
 
 
@@ -133,6 +136,9 @@ def workload(name: str) -> Workload:
               configurations span several workgroups).
     3d_l32  : 3D +-J, L=32, 128 samples x 32 temperatures, T in [0.9, 2.0]
               geometric (served size, split over two workgroups).
+    2d_l64_gauss : 2D with Gaussian couplings (Sec. 4.2's model), otherwise
+              the 2d_l64 workload: L=64, 500 samples x 24 temperatures on the
+              same power-law ladder, Metropolis + Houdayer + exchange.
     """
     if name == "small3d":
         return Workload(name, 3, 8, 8, 16, geometric_betas(0.9, 2.0, 16), 1000, False)
@@ -141,6 +147,9 @@ def workload(name: str) -> Workload:
     if name == "2d_l64":
         return Workload(name, 2, 64, 500, 24, power_law_betas(0.2, 1.6, 24, phi_star(64)),
                         5000, True)
+    if name == "2d_l64_gauss":
+        return Workload(name, 2, 64, 500, 24, power_law_betas(0.2, 1.6, 24, phi_star(64)),
+                        5000, True, gauss=True)
     if name == "3d_l48":
         return Workload(name, 3, 48, 64, 32, geometric_betas(0.9, 2.0, 32), 10000, False)
     if name == "3d_l32":
