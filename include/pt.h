@@ -238,6 +238,24 @@ int pt_measure(pt_job *job);
  * bit-identical results. */
 int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
 
+/* Most work items (samples, or parts of split samples, of one launch) that
+ * pt_mcs_noalloc takes. */
+#define PT_NOALLOC_MAX_ITEMS 65536
+
+/* pt_mcs that allocates no device memory, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, steps and results as pt_mcs, bit for bit.
+ * pt_mcs keeps each job's work list, queue counter and launch state in device
+ * memory it allocates on first use; this entry point instead writes them to
+ * a static scratch array of the library (about 1 MiB per GPU, held from the
+ * first call on that GPU until the process ends) and needs nothing else (the
+ * per-step kernels it takes when no fused plan fits use no scratch).  Every
+ * call on one GPU shares that GPU's scratch: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.
+ * PT_EINVAL if one launch would need more than PT_NOALLOC_MAX_ITEMS work
+ * items (nothing runs); otherwise errors as pt_mcs. */
+int pt_mcs_noalloc(pt_job *job, int32_t n, uint32_t flags);
+
 /* Measurement interval (Sec. 3: measurements are taken at intervals): from
  * now on a step of pt_mcs or pt_batch_run with PT_MCS_MEASURE measures only if
  * its 1-based sweep number (the sweep counter after the step) is a multiple

@@ -192,20 +192,35 @@ hipError_t split_order_prepare() {
 
 namespace {
 
+// A launch's work list as built on the host: the jobs' launch arguments,
+// the items (split samples first), the LDS words of the largest plan and the
+// kinds of work present.
+struct HostWorklist {
+  std::vector<FusedArgs> jobs;
+  std::vector<BatchItem> items;
+  size_t lds_words = 0;
+  int feat = 0;
+  bool has_split = false;
+};
+
 // Work list for per-job step counts and flags (jobs with 0 steps get no item).
-int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vector<uint32_t>& jflags) {
-  std::vector<FusedArgs> hj;
-  std::vector<BatchItem> hi, split;
+int plan_worklist(const std::vector<pt_job*>& jobs, const BatchConfig& cfg, const std::vector<int>& steps,
+                  const std::vector<uint32_t>& jflags, HostWorklist& out) {
+  std::vector<FusedArgs>& hj = out.jobs;
+  std::vector<BatchItem>& hi = out.items;
+  std::vector<BatchItem> split;
   std::vector<std::pair<double, size_t>> split_groups;  // (cost of a part, first item)
   std::vector<double> cost;
   size_t lds_words = 0;
   int feat = 0;
-  for (size_t jx = 0; jx < b->jobs.size(); ++jx) {
-    pt_job* j = b->jobs[jx];
+  hj.clear();
+  hi.clear();
+  for (size_t jx = 0; jx < jobs.size(); ++jx) {
+    pt_job* j = jobs[jx];
     const uint32_t flags = jflags[jx];
     const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
     const int mcs = steps[jx];
-    const int mode = job_mode(j, flags, b->cfg);
+    const int mode = job_mode(j, flags, cfg);
     if (mode < 0)
       return pt_fail(PT_EINVAL, "pt_batch_run: job " + std::to_string(jx) +
                                     " does not fit one workgroup's LDS for these flags (use pt_mcs)");
@@ -237,7 +252,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
         cost.push_back(c);
       }
   }
-  if (b->cfg.order == 0) {
+  if (cfg.order == 0) {
     std::vector<size_t> idx(hi.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
     std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
@@ -245,7 +260,7 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     for (size_t i = 0; i < idx.size(); ++i) sorted[i] = hi[idx[i]];
     hi.swap(sorted);
   }
-  if (b->cfg.order == 0 && split_groups.size() > 1) {
+  if (cfg.order == 0 && split_groups.size() > 1) {
     // split samples longest parts first, each sample's parts kept together
     std::stable_sort(split_groups.begin(), split_groups.end(),
                      [](const std::pair<double, size_t>& x, const std::pair<double, size_t>& y) {
@@ -254,13 +269,28 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     std::vector<BatchItem> sorted;
     sorted.reserve(split.size());
     for (const auto& gr : split_groups) {
-      const size_t end = gr.second + (size_t)b->jobs[split[gr.second].job]->split_parts;
+      const size_t end = gr.second + (size_t)jobs[split[gr.second].job]->split_parts;
       for (size_t i = gr.second; i < end; ++i) sorted.push_back(split[i]);
     }
     split.swap(sorted);
   }
   hi.insert(hi.begin(), split.begin(), split.end());
-  b->has_split = !split.empty();
+  out.has_split = !split.empty();
+  out.lds_words = lds_words;
+  out.feat = feat;
+  return PT_OK;
+}
+
+// Work list for per-job step counts and flags, uploaded to the batch's own
+// device buffers (grown as needed).
+int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vector<uint32_t>& jflags) {
+  HostWorklist wl;
+  if (int rc = plan_worklist(b->jobs, b->cfg, steps, jflags, wl)) return rc;
+  const std::vector<FusedArgs>& hj = wl.jobs;
+  const std::vector<BatchItem>& hi = wl.items;
+  const size_t lds_words = wl.lds_words;
+  const int feat = wl.feat;
+  b->has_split = wl.has_split;
   hipError_t e = hipSuccess;
   if ((int)hj.size() > b->cap_jobs) {
     if (b->d_jobs) (void)hipFree(b->d_jobs);
@@ -490,6 +520,88 @@ int batch_run_job(pt_batch* b, pt_job* job, int mcs, uint32_t flags) {
   b->stream = job->stream;
   if (int rc = build_worklist(b, mcs, flags)) return rc;
   return run_once(b, false);
+}
+
+// ---- the work list in library-held device memory (pt_mcs_noalloc) ---------
+namespace {
+// Library-held scratch of pt_mcs_noalloc, one copy per GPU for the life of
+// the process: the work-queue counter (first 256 bytes), then the job's
+// launch arguments, then the work items.  In host code `scratch` only names
+// the symbol; the device address comes from hipGetSymbolAddress.
+constexpr size_t kScratchArgsAt = 256;
+constexpr size_t kScratchItemsAt = (kScratchArgsAt + sizeof(FusedArgs) + 255) / 256 * 256;
+constexpr size_t kScratchMaxItems = PT_NOALLOC_MAX_ITEMS;
+constexpr size_t kScratchBytes = kScratchItemsAt + kScratchMaxItems * sizeof(BatchItem);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[64] = {};
+int g_scratch_ncu[64] = {};
+
+// The current device's address of `scratch` (and its CU count), looked up
+// once per device with that device current; the split-launch ordering event
+// is created at the same time, so later calls create nothing.
+int scratch_for_device(unsigned char** ptr, int* ncu) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return pt_fail(PT_EDEVICE, "pt_mcs_noalloc: no current device");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return pt_fail(PT_EDEVICE, std::string("pt_mcs_noalloc: scratch address: ") + hipGetErrorString(e));
+    int n = 0;
+    e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = split_order_prepare();
+    if (e != hipSuccess)
+      return pt_fail(PT_EDEVICE, std::string("pt_mcs_noalloc: set-up: ") + hipGetErrorString(e));
+    g_scratch_ncu[dev] = n > 0 ? n : 256;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *ptr = g_scratch_ptr[dev];
+  *ncu = g_scratch_ncu[dev];
+  return PT_OK;
+}
+}  // namespace
+
+int batch_run_job_noalloc(pt_job* job, int mcs, uint32_t flags, int* nitems_out) {
+  HostWorklist wl;
+  if (int rc = plan_worklist({job}, BatchConfig{}, {mcs}, {flags}, wl)) return rc;
+  if (nitems_out) *nitems_out = (int)wl.items.size();
+  if (wl.items.size() > kScratchMaxItems)
+    return pt_fail(PT_EINVAL, "pt_mcs_noalloc: " + std::to_string(wl.items.size()) +
+                                  " work items exceed the library scratch (at most " +
+                                  std::to_string(kScratchMaxItems) + ")");
+  if (wl.items.empty()) return PT_OK;
+  unsigned char* base = nullptr;
+  int ncu = 0;
+  if (int rc = scratch_for_device(&base, &ncu)) return rc;
+  FusedArgs* d_jobs = reinterpret_cast<FusedArgs*>(base + kScratchArgsAt);
+  BatchItem* d_items = reinterpret_cast<BatchItem*>(base + kScratchItemsAt);
+  uint32_t* d_queue = reinterpret_cast<uint32_t*>(base);
+  const int d = job->g.d;
+  const size_t lds_bytes = wl.lds_words * 4;
+  hipError_t e = prepare_batch(d, wl.feat, lds_bytes, nullptr);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_mcs_noalloc: ") + hipGetErrorString(e));
+  const int nitems = (int)wl.items.size();
+  int threads = 0, per_cu = 0;
+  if (int rc = launch_shape(d, wl.feat, lds_bytes, nitems, ncu, 0, &threads, &per_cu)) return rc;
+  const int blocks = std::max(1, std::min(ncu * per_cu, nitems));
+  // pageable host sources: each copy has read its source when it returns,
+  // and it is ordered on the stream before the launch that reads it
+  e = hipMemcpyAsync(d_jobs, wl.jobs.data(), sizeof(FusedArgs), hipMemcpyHostToDevice, job->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_items, wl.items.data(), sizeof(BatchItem) * wl.items.size(),
+                       hipMemcpyHostToDevice, job->stream);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_mcs_noalloc: ") + hipGetErrorString(e));
+  auto launch = [&] {
+    return launch_batch(d, wl.feat, d_jobs, 1, d_items, nitems, d_queue, blocks, threads, lds_bytes,
+                        job->stream);
+  };
+  e = wl.has_split ? ordered_split_launch(job->stream, launch) : launch();
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_mcs_noalloc: ") + hipGetErrorString(e));
+  return PT_OK;
 }
 
 int job_plan_mode(const pt_job* j, uint32_t flags) { return job_mode(j, flags, BatchConfig{}); }

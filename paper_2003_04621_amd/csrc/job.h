@@ -103,6 +103,11 @@ void batch_free(pt_batch* b);
 // mcs fused steps of one job through its own one-job batch (work list cached
 // while mcs and flags repeat).
 int batch_run_job(pt_batch* b, pt_job* job, int mcs, uint32_t flags);
+// The same launch with its work list and queue counter in the library's
+// static per-device scratch instead of batch-owned device memory (no device
+// allocation); *nitems receives the work items of the launch.  PT_EINVAL when
+// they exceed PT_NOALLOC_MAX_ITEMS.
+int batch_run_job_noalloc(pt_job* job, int mcs, uint32_t flags, int* nitems);
 // The launch arguments of job j for `mcs` fused steps in plan `mode` (as
 // job_plan_mode returns it) with pt_mcs flags `flags`.
 ptsg::FusedArgs job_fused_args(const pt_job* j, int mode, int mcs, uint32_t flags);

@@ -620,6 +620,23 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   return mcs_per_step(job, n, flags);
 }
 
+PT_API int pt_mcs_noalloc(pt_job* job, int32_t n, uint32_t flags) {
+  if (int rc = check_mcs(job, n, flags)) return rc;
+  if (job->gauss || (flags & PT_MCS_PLAIN) || !job_is_resident(job, flags))
+    return mcs_per_step(job, n, flags);  // per-step kernels use no scratch
+  const int chunk = 500;
+  for (int done = 0; done < n; done += chunk) {
+    const int m = (n - done) < chunk ? (n - done) : chunk;
+    const int rc = batch_run_job_noalloc(job, m, flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_MULTICLUSTER),
+                                         nullptr);
+    if (rc != PT_OK) {
+      job->poisoned = rc == PT_EDEVICE;
+      return rc;
+    }
+  }
+  return PT_OK;
+}
+
 PT_API int pt_get_plan(pt_job* job, uint32_t flags, int32_t* out4) {
   if (int rc = check_job(job)) return rc;
   if (!out4) return pt_fail(PT_EINVAL, "null output");

@@ -25,12 +25,13 @@ PT_TRACK_MODES = 0x20
 PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
 PT_MCS_MULTICLUSTER = 0x40
 PT_SERVE_UNTIL_EQUILIBRATED = 0x100
+PT_NOALLOC_MAX_ITEMS = 65536
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE"}
 
 EXPORTS = [
     "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_houdayer_multi",
-    "pt_measure", "pt_mcs",
+    "pt_measure", "pt_mcs", "pt_mcs_noalloc",
     "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_walk", "pt_tunnel_summary",
     "pt_get_modes", "pt_correlation_length",
@@ -85,7 +86,7 @@ def lib():
             "pt_init_ex": [C.POINTER(P), I32, I32, I32, I32, P, P, U64, U32],
             "pt_sweep": [P, I32], "pt_exchange": [P], "pt_houdayer": [P], "pt_houdayer_multi": [P],
             "pt_measure": [P],
-            "pt_mcs": [P, I32, U32], "pt_get_plan": [P, U32, P], "pt_plan_query": [I32, I32, I32, U32, P],
+            "pt_mcs": [P, I32, U32], "pt_mcs_noalloc": [P, I32, U32], "pt_get_plan": [P, U32, P], "pt_plan_query": [I32, I32, I32, U32, P],
             "pt_job_bytes": [I32, I32, I32, I32, U32, P, P], "pt_observables": [P, P, P, P], "pt_destroy": [P],
             "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
             "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
@@ -332,6 +333,11 @@ def _step_flags(houdayer=False, measure=False, plain=False, multi=False):
 def pt_mcs(job: Job, n: int, houdayer: bool = False, measure: bool = False,
            plain: bool = False, multi: bool = False) -> None:
     _check(lib().pt_mcs(job.h, int(n), _step_flags(houdayer, measure, plain, multi)))
+
+
+def pt_mcs_noalloc(job: Job, n: int, houdayer: bool = False, measure: bool = False,
+                   plain: bool = False, multi: bool = False) -> None:
+    _check(lib().pt_mcs_noalloc(job.h, int(n), _step_flags(houdayer, measure, plain, multi)))
 
 
 def pt_get_plan(job: Job, houdayer=False, measure=False, plain=False, multi=False) -> dict:
