@@ -55,6 +55,7 @@ extern "C" {
 #define PT_ENOMEM (-2)
 #define PT_EDEVICE (-3)
 #define PT_ESTATE (-4)
+#define PT_ECANCELED (-5) /* a served request ended by pt_server_cancel */
 
 /* Device spin layouts (pt_init_ex flags). */
 #define PT_LAYOUT_INT8 0u   /* one int8 per spin, lattice-contiguous */
@@ -463,9 +464,22 @@ int pt_server_poll(pt_server *s, uint64_t ticket, pt_result *out, double *disord
  * whose layout carries PT_TRACK_MODES (NaN otherwise). */
 int pt_server_poll_ex(pt_server *s, uint64_t ticket, pt_result *out, double *disorder,
                       double *correlation);
-/* out[8] = {attempted flips completed, busy seconds, rounds, admitted,
- *           completed, peak admitted bytes, peak concurrent jobs, uptime s} */
+/* out[11] = {attempted flips completed, busy seconds, rounds, admitted,
+ *            completed, peak admitted bytes, peak concurrent jobs, uptime s,
+ *            queue depth (requests waiting for admission), jobs in the
+ *            current round, cancelled requests} */
 int pt_server_stats(pt_server *s, double *out);
+/* Cancels a request, leaving every other request's work and result as if it
+ * had never been submitted (each job's result depends only on its own
+ * request).  A queued request is dropped at once; a running one ends at the
+ * next round boundary (unless it completes its steps first, in which case its
+ * normal result stands) and its device memory returns to the budget.  The
+ * cancelled request's pt_server_poll result has status PT_ECANCELED and no
+ * observables.  Returns PT_OK when the cancellation is recorded, 1 if the
+ * request has already finished (its result waits to be polled), PT_EINVAL
+ * for an unknown ticket or one whose result was already collected.
+ * Operational control of the served form: not a step of the method. */
+int pt_server_cancel(pt_server *s, uint64_t ticket);
 /* Finishes every queued and running request, then stops the server. */
 int pt_server_stop(pt_server *s);
 

@@ -19,6 +19,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "job.h"
@@ -81,13 +82,16 @@ struct pt_server {
   std::deque<Request> pending;
   std::vector<Active> active;
   std::unordered_map<uint64_t, Finished> finished;
+  std::unordered_set<uint64_t> live;    // admitted requests not finished yet
+  std::unordered_set<uint64_t> cancel;  // live requests to end between rounds
+  size_t n_active = 0;                  // jobs of the current round
   uint64_t next_ticket = 1;
   bool stopping = false;
   std::thread worker;
   std::chrono::steady_clock::time_point t0;
   // statistics
   double flips = 0, busy = 0;
-  uint64_t rounds = 0, admitted = 0, completed = 0;
+  uint64_t rounds = 0, admitted = 0, completed = 0, cancelled = 0;
   size_t peak_used = 0;
   int max_active = 0;
 
@@ -145,7 +149,12 @@ void finish(pt_server* sv, Active& a, int status) {
   f.t_done = sv->now();
   std::lock_guard<std::mutex> lk(sv->mu);
   sv->used -= a.bytes;
-  sv->completed += 1;
+  if (status == PT_ECANCELED)
+    sv->cancelled += 1;
+  else
+    sv->completed += 1;
+  sv->cancel.erase(a.req.ticket);
+  sv->live.erase(a.req.ticket);
   sv->finished[a.req.ticket] = std::move(f);
   sv->cv_done.notify_all();
 }
@@ -177,6 +186,7 @@ std::vector<Request> take_admissions(pt_server* sv) {
     }
     if (used + need > sv->budget) break;
     used += need;
+    sv->live.insert(r.ticket);
     admit.push_back(std::move(r));
     sv->pending.pop_front();
   }
@@ -204,6 +214,7 @@ void create_jobs(pt_server* sv, std::vector<Request>& admit, std::vector<Active>
     a.job->stream = sv->st_main;
     a.job->meas_every = a.req.every;
     ready.push_back(std::move(a));
+    std::lock_guard<std::mutex> lk(sv->mu);
     sv->admitted += 1;
   }
 }
@@ -219,6 +230,22 @@ void serve(pt_server* sv) {
       });
       if (sv->stopping && sv->pending.empty() && sv->active.empty() && done.empty()) break;
     }
+    {
+      // cancelled running jobs end here, between rounds (nothing of theirs is
+      // on the GPU); the other jobs are not touched
+      std::vector<Active> keep, gone;
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (Active& a : sv->active) {
+          if (sv->cancel.erase(a.req.ticket))
+            gone.push_back(std::move(a));
+          else
+            keep.push_back(std::move(a));
+        }
+      }
+      sv->active.swap(keep);
+      for (Active& a : gone) finish(sv, a, PT_ECANCELED);
+    }
     if (sv->active.empty()) {
       // nothing on the GPU: read out, then admit, before the first round
       for (Active& a : done) finish(sv, a, PT_OK);
@@ -227,7 +254,11 @@ void serve(pt_server* sv) {
       create_jobs(sv, admit, sv->active);
       if (sv->active.empty()) continue;
     }
-    if ((int)sv->active.size() > sv->max_active) sv->max_active = (int)sv->active.size();
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->n_active = sv->active.size();
+      if ((int)sv->n_active > sv->max_active) sv->max_active = (int)sv->n_active;
+    }
 
     // one round: every active job advances, measuring after its burn-in
     const double t_round = sv->now();
@@ -306,9 +337,12 @@ void serve(pt_server* sv) {
 
     if (rc == PT_OK && hipStreamSynchronize(sv->st_main) != hipSuccess) rc = PT_EDEVICE;
     if (rc == PT_OK && hipStreamSynchronize(sv->st_side) != hipSuccess) rc = PT_EDEVICE;
-    sv->busy += sv->now() - t_round;
-    sv->rounds += 1;
-    if (rc == PT_OK) sv->flips += round_flips;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->busy += sv->now() - t_round;
+      sv->rounds += 1;
+      if (rc == PT_OK) sv->flips += round_flips;
+    }
     // completions
     std::vector<Active> still;
     for (size_t i = 0; i < sv->active.size(); ++i) {
@@ -332,6 +366,8 @@ void serve(pt_server* sv) {
     }
     for (Active& a : ready) still.push_back(std::move(a));
     sv->active.swap(still);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->n_active = sv->active.size();
   }
 }
 
@@ -459,6 +495,34 @@ PT_API int pt_server_poll_ex(pt_server* sv, uint64_t ticket, pt_result* out, dou
   return PT_OK;
 }
 
+PT_API int pt_server_cancel(pt_server* sv, uint64_t ticket) {
+  if (!sv) return pt_fail(PT_EINVAL, "pt_server_cancel: null server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (ticket == 0 || ticket >= sv->next_ticket) return pt_fail(PT_EINVAL, "pt_server_cancel: unknown ticket");
+  if (sv->finished.count(ticket)) return 1;  // its result is waiting to be polled
+  for (auto it = sv->pending.begin(); it != sv->pending.end(); ++it) {
+    if (it->ticket != ticket) continue;
+    Finished f;
+    f.status = PT_ECANCELED;
+    f.t_submit = it->t_submit;
+    f.t_admit = f.t_done = sv->now();
+    f.disorder.assign((size_t)it->NT * 6, 0.0);
+    f.tau = std::numeric_limits<double>::quiet_NaN();
+    f.corr.assign((size_t)it->NT * 3, std::numeric_limits<double>::quiet_NaN());
+    sv->finished[ticket] = std::move(f);
+    sv->pending.erase(it);
+    sv->cancelled += 1;
+    sv->cv_done.notify_all();
+    return PT_OK;
+  }
+  if (!sv->live.count(ticket)) return pt_fail(PT_EINVAL, "pt_server_cancel: result already collected");
+  // admitted: the worker ends it at the next round boundary unless it has
+  // completed its steps by then
+  sv->cancel.insert(ticket);
+  sv->cv.notify_all();
+  return PT_OK;
+}
+
 PT_API int pt_server_stats(pt_server* sv, double* out) {
   if (!sv || !out) return pt_fail(PT_EINVAL, "pt_server_stats: null argument");
   std::lock_guard<std::mutex> lk(sv->mu);
@@ -470,6 +534,9 @@ PT_API int pt_server_stats(pt_server* sv, double* out) {
   out[5] = (double)sv->peak_used;
   out[6] = (double)sv->max_active;
   out[7] = sv->now();
+  out[8] = (double)sv->pending.size();
+  out[9] = (double)sv->n_active;
+  out[10] = (double)sv->cancelled;
   return PT_OK;
 }
 

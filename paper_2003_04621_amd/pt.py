@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libptsg.so")
 
-PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE, PT_ECANCELED = 0, -1, -2, -3, -4, -5
 PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
 PT_TRACK_WALK = 0x10
 PT_TRACK_MODES = 0x20
@@ -27,7 +27,7 @@ PT_MCS_MULTICLUSTER = 0x40
 PT_SERVE_UNTIL_EQUILIBRATED = 0x100
 PT_NOALLOC_MAX_ITEMS = 65536
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
-          PT_ESTATE: "PT_ESTATE"}
+          PT_ESTATE: "PT_ESTATE", PT_ECANCELED: "PT_ECANCELED"}
 
 EXPORTS = [
     "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_houdayer_multi",
@@ -40,7 +40,7 @@ EXPORTS = [
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
     "pt_batch_get_config", "pt_batch_set_config", "pt_batch_launch_shape", "pt_batch_destroy",
     "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_poll_ex", "pt_server_stats",
-    "pt_server_stop",
+    "pt_server_stop", "pt_server_cancel",
     "pt_init_gauss", "pt_get_energies64", "pt_get_moments8", "pt_gauss_accept_test",
     "pt_gauss_accept_host",
 ]
@@ -104,7 +104,7 @@ def lib():
             "pt_server_submit": [P, C.POINTER(PTRequest), C.POINTER(C.c_uint64)],
             "pt_server_poll": [P, C.c_uint64, C.POINTER(PTResult), P],
             "pt_server_poll_ex": [P, C.c_uint64, C.POINTER(PTResult), P, P],
-            "pt_server_stats": [P, P], "pt_server_stop": [P],
+            "pt_server_stats": [P, P], "pt_server_stop": [P], "pt_server_cancel": [P, C.c_uint64],
             "pt_init_gauss": [C.POINTER(P), I32, I32, I32, I32, P, P, U64, U32],
             "pt_get_energies64": [P, P], "pt_get_moments8": [P, P],
             "pt_gauss_accept_test": [P, P, P, P, I32, I32],
@@ -611,11 +611,21 @@ def pt_server_poll(server: Server, ticket: int):
 
 
 def pt_server_stats(server: Server) -> dict:
-    out = np.zeros(8, np.float64)
+    out = np.zeros(11, np.float64)
     _check(lib().pt_server_stats(server.h, _p(out)))
     keys = ["flips", "busy_s", "rounds", "admitted", "completed", "peak_bytes", "peak_jobs",
-            "uptime_s"]
+            "uptime_s", "queued", "running", "cancelled"]
     return dict(zip(keys, out.tolist()))
+
+
+def pt_server_cancel(server: Server, ticket: int) -> bool:
+    """Cancels a queued or running request (its poll result then has status
+    PT_ECANCELED); False if it had already finished (its result stands)."""
+    rc = lib().pt_server_cancel(server.h, C.c_uint64(ticket))
+    if rc == 1:
+        return False
+    _check(rc)
+    return True
 
 
 def pt_server_stop(server: Server) -> None:

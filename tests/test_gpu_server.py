@@ -252,3 +252,55 @@ def test_server_measurement_interval(pt):
     assert np.array_equal(r["disorder"], dis)
     c0, ck, xi = pt.pt_correlation_length(job)
     assert np.array_equal(r["correlation"][:, 0], c0)
+
+
+def test_server_cancel_leaves_other_results_unchanged(pt):
+    """A queued and a running request are cancelled; every other request's
+    result equals the same job run alone, bit for bit, and the cancelled ones
+    report PT_ECANCELED (the failure-handling side of the served form)."""
+    keep = {0: (3, 8, 4, 2, 40, 10, False, 0), 2: (3, 12, 5, 1, 30, 6, False, 1),
+            4: (2, 16, 4, 2, 26, 8, True, 0)}
+    long_run = (3, 16, 6, 1, 20000, 100, False, 0)   # cancelled while running
+    queued = (3, 16, 4, 1, 50, 10, False, 0)         # cancelled while queued
+    def nbytes(spec):
+        dim, L, NT, S = spec[:4]
+        return pt.pt_job_bytes(S, NT, L, dim, W.geometric_betas(0.6, 2.0, NT), layout=spec[7])
+    # room for requests 0, 1 (the long one) and 2 together; 3 and 4 wait
+    budget = nbytes(keep[0]) + nbytes(long_run) + nbytes(keep[2]) + 4096
+    srv = pt.pt_server_start(budget, steps_per_round=2)
+    specs = {0: keep[0], 1: long_run, 2: keep[2], 3: queued, 4: keep[4]}
+    tickets = {}
+    for n in range(5):
+        dim, L, NT, S, sweeps, burn, hou, layout = specs[n]
+        J, b, seed = _inputs(60 + n, specs[n])
+        say(f"submit {specs[n]}")
+        tickets[n] = pt.pt_server_submit(srv, dim, L, NT, S, b, J, seed, sweeps, burn, hou, layout)
+    assert pt.pt_server_cancel(srv, tickets[3]) is True     # still queued
+    t0 = time.time()
+    while pt.pt_server_stats(srv)["rounds"] < 3:
+        assert time.time() - t0 < 60, "no rounds"
+        time.sleep(0.005)
+    assert pt.pt_server_cancel(srv, tickets[1]) is True     # running
+    res = _wait(pt, srv, tickets, timeout=180.0)
+    stats = pt.pt_server_stats(srv)
+    # a request that finished but was not polled yet cannot be cancelled
+    J, b, seed = _inputs(70, keep[0])
+    t_done = pt.pt_server_submit(srv, 3, 8, 4, 2, b, J, seed, 0, 0)
+    t0 = time.time()
+    while pt.pt_server_stats(srv)["completed"] < stats["completed"] + 1:
+        assert time.time() - t0 < 60, "empty request did not finish"
+        time.sleep(0.005)
+    assert pt.pt_server_cancel(srv, t_done) is False
+    assert pt.pt_server_poll(srv, t_done)["status"] == 0
+    with pytest.raises(pt.PTError):
+        pt.pt_server_cancel(srv, tickets[1])       # result already collected
+    with pytest.raises(pt.PTError):
+        pt.pt_server_cancel(srv, 10 ** 9)          # never issued
+    pt.pt_server_stop(srv)
+    assert res[1]["status"] == pt.PT_ECANCELED and res[3]["status"] == pt.PT_ECANCELED
+    assert stats["cancelled"] == 2 and stats["queued"] == 0
+    for n, spec in keep.items():
+        dis, nm = _alone(pt, 60 + n, spec)
+        assert res[n]["status"] == 0, (spec, res[n]["status"])
+        assert res[n]["n_meas"] == nm == spec[4] - spec[5]
+        assert np.array_equal(res[n]["disorder"], dis), spec
