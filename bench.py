@@ -57,7 +57,7 @@ OPS_PER_FLIP = 16
 # sample is loaded once and stored once per launch, so the bytes do not depend
 # on the number of steps a launch runs.  Entries are removed when the kernel
 # changes until the counters are taken again.
-TRAFFIC_PER_LAUNCH = {}
+TRAFFIC_PER_LAUNCH = {("3d_l16", "int8", 2): 573461248}
 
 
 def _oracle_steps(args):
@@ -257,7 +257,7 @@ def served(pt, torch, W, args):
             "failed": bad + bad_b}
 
 
-def fused_run(pt, torch, job, wl, K, chunk, houdayer, measure, layout_name):
+def fused_run(pt, torch, job, wl, K, chunk, houdayer, measure, layout_name, multi=False):
     """K fused steps of `job` in launches of `chunk` steps; the rate over the
     host clock and the kernel's roofline position from the HIP-event duration
     of its full-length launches (events on the job's stream)."""
@@ -270,7 +270,7 @@ def fused_run(pt, torch, job, wl, K, chunk, houdayer, measure, layout_name):
     t0 = time.perf_counter()
     for (a, b), st in zip(ev, starts):
         a.record(stream)
-        pt.pt_mcs(job, min(chunk, K - st), houdayer=houdayer, measure=measure)
+        pt.pt_mcs(job, min(chunk, K - st), houdayer=houdayer, measure=measure, multi=multi)
         b.record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -365,6 +365,10 @@ def main():
                     help="steps re-timed with one launch per kernel (0: skip)")
     ap.add_argument("--houdayer-steps", type=int, default=1000,
                     help="steps of the 2D L=64 Houdayer workload (0: skip)")
+    ap.add_argument("--multi-steps", type=int, default=1000,
+                    help="steps of the 2D L=64 workload with multi-cluster moves (0: skip)")
+    ap.add_argument("--gauss-steps", type=int, default=100,
+                    help="steps of the 2D L=64 Gaussian-coupling workload (0: skip)")
     ap.add_argument("--phase-steps", type=int, default=100,
                     help="steps of the per-phase time split (0: skip)")
     ap.add_argument("--walk-steps", type=int, default=1000,
@@ -468,6 +472,47 @@ def main():
                                 "the Houdayer move is extra work in the same launches",
                "e_coldest": round(float(dis_h[0, 0]), 6)}
 
+    # the same 2D workload with the multi-cluster variant of the Houdayer move
+    multi = None
+    if args.multi_steps > 0:
+        wh = W.workload("2d_l64")
+        print(f"# workload {wh.name} with multi-cluster Houdayer moves", file=sys.stderr, flush=True)
+        mj = pt.pt_init(wh.samples, wh.replicas, wh.L, wh.dim, wh.couplings(), wh.betas, wh.seed,
+                        layout=layout)
+        pt.pt_mcs(mj, args.warmup, houdayer=True, measure=True, multi=True)
+        el_m, roof_m = fused_run(pt, torch, mj, wh, args.multi_steps, args.chunk, True, True,
+                                 args.layout, multi=True)
+        _, dis_m, _ = pt.pt_observables(mj)
+        pt.pt_destroy(mj)
+        multi = {"workload": f"{wh.name} with every q = -1 cluster of a pair exchanged "
+                             "independently (multi-cluster variant)",
+                 "value": round(wh.flips_per_sweep * args.multi_steps / el_m / 1e9, 2),
+                 "unit": "flips/ns", "steps": args.multi_steps, "roofline": roof_m,
+                 "e_coldest": round(float(dis_m[0, 0]), 6)}
+
+    # the 2D Gaussian-coupling workload (Sec. 4.2's second model; per-step kernels)
+    gauss = None
+    if args.gauss_steps > 0:
+        wg = W.workload("2d_l64_gauss")
+        print(f"# workload {wg.name}", file=sys.stderr, flush=True)
+        gj = pt.pt_init_gauss(wg.samples, wg.replicas, wg.L, wg.dim, wg.couplings(), wg.betas,
+                              wg.seed)
+        pt.pt_mcs(gj, min(args.warmup, 20), houdayer=True, measure=True)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        pt.pt_mcs(gj, args.gauss_steps, houdayer=True, measure=True)
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - tg
+        _, dis_g, _ = pt.pt_observables(gj)
+        pt.pt_destroy(gj)
+        gauss = {"workload": f"{wg.name}: 2D Gaussian couplings (standard normal on the 2^-16 "
+                             f"grid), L={wg.L}, {wg.samples} samples x 2 x {wg.replicas} "
+                             "temperatures, sweep + Houdayer + exchange + measure",
+                 "value": round(wg.flips_per_sweep * args.gauss_steps / dtg / 1e9, 2),
+                 "unit": "flips/ns", "steps": args.gauss_steps,
+                 "form": "one launch per kernel per step",
+                 "e_coldest": round(float(dis_g[0, 0]), 6)}
+
     # the four-part time split (Sec. 4.5) of both workloads
     split = None
     if args.phase_steps > 0:
@@ -552,6 +597,8 @@ def main():
         "cpu_baseline": cpu,
         "plain_form": plain,
         "houdayer_2d": hou,
+        "multicluster_2d": multi,
+        "gauss_2d": gauss,
         "phase_split": split,
         "replica_walk": walk,
         "modes": modes,

@@ -7,7 +7,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -51,6 +53,13 @@ struct pt_batch {
   int feat = 0;            // kinds of work in the work list (kFeat*)
   int threads = 0;         // threads per workgroup of the built launch
   int per_cu = 0;          // workgroups of that size resident per CU
+  // pinned staging of the work list (the upload is then truly asynchronous)
+  // and the events ordering its reuse: stage_ev after the last upload from
+  // it, last_ev after the last launch reading the device work list
+  void* h_stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_ev = nullptr, last_ev = nullptr;
+  std::vector<FusedArgs> args;  // host copy of the uploaded launch arguments
 };
 
 namespace {
@@ -137,9 +146,26 @@ FusedArgs job_fused_args(const pt_job* j, int mode, int mcs, uint32_t flags) {
 // idle at the end).
 int launch_shape(int d, int feat, size_t lds_bytes, int nitems, int ncu, int cfg_threads,
                  int* threads_out, int* per_cu_out) {
+  // the runtime's answer for a (device, kernel variant, workgroup size, LDS)
+  // never changes, so each is asked once
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int, size_t>, int> known;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
   auto resident = [&](int threads) {
+    const auto key = std::make_tuple(dev, d, feat, threads, lds_bytes);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      const auto it = known.find(key);
+      if (it != known.end()) return it->second;
+    }
     int n = 0;
-    if (batch_residency(d, feat, threads, lds_bytes, &n) != hipSuccess) n = 0;
+    if (batch_residency(d, feat, threads, lds_bytes, &n) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    known[key] = n;
     return n;
   };
   int threads = cfg_threads;
@@ -281,6 +307,40 @@ int plan_worklist(const std::vector<pt_job*>& jobs, const BatchConfig& cfg, cons
   return PT_OK;
 }
 
+// Uploads launch arguments (and, if ni > 0, work items) to the batch's
+// device buffers.  The upload goes through pinned staging memory, so it is
+// asynchronous and ordered on the stream before the launch that reads it: the
+// host does not wait for the GPU.  The staging area is rewritten only after
+// the previous upload from it has been done (stage_ev), and the device list
+// only after the last launch that read it, whatever stream that ran on
+// (last_ev).
+int upload_worklist(pt_batch* b, const FusedArgs* args, size_t nj, const BatchItem* items, size_t ni) {
+  hipError_t e = hipSuccess;
+  const size_t jbytes = sizeof(FusedArgs) * nj, ibytes = sizeof(BatchItem) * ni;
+  if (!b->stage_ev) e = hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming);
+  if (e == hipSuccess && !b->last_ev) e = hipEventCreateWithFlags(&b->last_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventSynchronize(b->stage_ev);
+  if (e == hipSuccess && jbytes + ibytes > b->stage_cap) {
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    b->h_stage = nullptr;
+    b->stage_cap = 0;
+    e = hipHostMalloc(&b->h_stage, jbytes + ibytes, hipHostMallocDefault);
+    if (e != hipSuccess) return pt_fail(PT_ENOMEM, "pt_batch_run: pinned staging allocation failed");
+    b->stage_cap = jbytes + ibytes;
+  }
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  unsigned char* stage = static_cast<unsigned char*>(b->h_stage);
+  std::memcpy(stage, args, jbytes);
+  if (ibytes) std::memcpy(stage + jbytes, items, ibytes);
+  e = hipStreamWaitEvent(b->stream, b->last_ev, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_jobs, stage, jbytes, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && ibytes)
+    e = hipMemcpyAsync(b->d_items, stage + jbytes, ibytes, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->stage_ev, b->stream);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  return PT_OK;
+}
+
 // Work list for per-job step counts and flags, uploaded to the batch's own
 // device buffers (grown as needed).
 int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vector<uint32_t>& jflags) {
@@ -310,13 +370,8 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
     e = hipMalloc((void**)&b->d_queue, 256);
     if (e != hipSuccess) return pt_fail(PT_ENOMEM, "pt_batch_run: device allocation failed");
   }
-  e = hipMemcpyAsync(b->d_jobs, hj.data(), sizeof(FusedArgs) * hj.size(), hipMemcpyHostToDevice,
-                     b->stream);
-  if (e == hipSuccess && !hi.empty())
-    e = hipMemcpyAsync(b->d_items, hi.data(), sizeof(BatchItem) * hi.size(), hipMemcpyHostToDevice,
-                       b->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  if (int rc = upload_worklist(b, hj.data(), hj.size(), hi.data(), hi.size())) return rc;
+  b->args = hj;
   b->nitems = (int)hi.size();
   b->lds_bytes = lds_words * 4;
   b->feat = feat;
@@ -337,9 +392,18 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
 int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
   std::vector<int> every(b->jobs.size());  // the work list carries each job's interval
   for (size_t i = 0; i < b->jobs.size(); ++i) every[i] = b->jobs[i]->meas_every;
-  if (b->built && b->built_mcs == mcs && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg) &&
-      b->built_every == every)
+  const bool same = b->built && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg) &&
+                    b->built_every == every;
+  if (same && b->built_mcs == mcs) return PT_OK;
+  if (same && b->built_mcs > 0 && mcs > 0) {
+    // only the step count differs: the items, their order and the launch
+    // shape stay, and the kernels read the count from the launch arguments
+    // in device memory (a captured graph stays valid too)
+    for (FusedArgs& a : b->args) a.nmcs = mcs;
+    if (int rc = upload_worklist(b, b->args.data(), b->args.size(), nullptr, 0)) return rc;
+    b->built_mcs = mcs;
     return PT_OK;
+  }
   b->built_every = every;
   const std::vector<int> steps(b->jobs.size(), mcs);
   const std::vector<uint32_t> fl(b->jobs.size(), flags);
@@ -358,7 +422,8 @@ int run_once(pt_batch* b, bool use_graph) {
       return launch_batch(b->d, b->feat, b->d_jobs, (int)b->jobs.size(), b->d_items, b->nitems,
                           b->d_queue, b->blocks, b->threads, b->lds_bytes, b->stream);
     };
-    const hipError_t e = b->has_split ? ordered_split_launch(b->stream, launch) : launch();
+    hipError_t e = b->has_split ? ordered_split_launch(b->stream, launch) : launch();
+    if (e == hipSuccess && b->last_ev) e = hipEventRecord(b->last_ev, b->stream);
     if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
     return PT_OK;
   }
@@ -387,7 +452,8 @@ int run_once(pt_batch* b, bool use_graph) {
     b->graph_ok = true;
   }
   auto replay = [&] { return hipGraphLaunch(b->exec, b->stream); };
-  const hipError_t e = b->has_split ? ordered_split_launch(b->stream, replay) : replay();
+  hipError_t e = b->has_split ? ordered_split_launch(b->stream, replay) : replay();
+  if (e == hipSuccess && b->last_ev) e = hipEventRecord(b->last_ev, b->stream);
   if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
   return PT_OK;
 }
@@ -630,6 +696,10 @@ void batch_free(pt_batch* b) {
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->stage_ev) (void)hipEventSynchronize(b->stage_ev);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
+  if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
+  if (b->last_ev) (void)hipEventDestroy(b->last_ev);
   (void)hipGetLastError();
   delete b;
 }
@@ -767,6 +837,10 @@ PT_API int pt_batch_destroy(pt_batch* b) {
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->stage_ev) (void)hipEventSynchronize(b->stage_ev);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
+  if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
+  if (b->last_ev) (void)hipEventDestroy(b->last_ev);
   (void)hipGetLastError();
   delete b;
   return PT_OK;

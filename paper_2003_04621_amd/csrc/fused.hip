@@ -2,6 +2,8 @@
 // reset and counter advance kernels, LDS plans of resident and split samples,
 // launch arguments, and the launch of the persistent batch kernel whose
 // device code is in fused_device.h.
+#include <map>
+#include <mutex>
 #include <utility>
 
 #include "fused_device.h"
@@ -193,7 +195,27 @@ BatchKernel batch_kernel(int d, int feat) {
 
 hipError_t prepare_batch(int d, int feat, size_t lds_bytes, int* vgprs) {
   const BatchKernel k = batch_kernel(d, feat);
-  hipError_t e = lds_attr(k, lds_bytes);
+  // the dynamic-LDS limit of each variant is raised only when a launch needs
+  // more than any before it on this device (kernel attributes are per device)
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> set_to;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  bool raise = false;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    size_t& cur = set_to[{dev, (const void*)k}];
+    raise = lds_bytes > cur;
+  }
+  if (raise) {
+    e = lds_attr(k, lds_bytes);
+    if (e == hipSuccess) {
+      std::lock_guard<std::mutex> lk(mu);
+      size_t& cur = set_to[{dev, (const void*)k}];
+      if (lds_bytes > cur) cur = lds_bytes;
+    }
+  }
   if (e == hipSuccess && vgprs) {
     hipFuncAttributes at{};
     e = hipFuncGetAttributes(&at, (const void*)k);

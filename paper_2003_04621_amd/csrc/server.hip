@@ -74,7 +74,10 @@ struct pt_server {
   size_t budget = 0, used = 0;
   int steps_per_round = 100;
   int device = 0;
-  hipStream_t st_main = nullptr, st_side = nullptr, st_admit = nullptr;
+  // st_main: the 3D batch launch of a round; st_two: the 2D one (the two
+  // run side by side); st_side: per-step jobs; st_admit: job set-up and
+  // tear-down
+  hipStream_t st_main = nullptr, st_two = nullptr, st_side = nullptr, st_admit = nullptr;
   hipMemPool_t pool = nullptr;  // device memory of the jobs
   pt_batch* batch[2] = {nullptr, nullptr};  // 2D and 3D jobs
   std::mutex mu;
@@ -336,6 +339,7 @@ void serve(pt_server* sv) {
     }
 
     if (rc == PT_OK && hipStreamSynchronize(sv->st_main) != hipSuccess) rc = PT_EDEVICE;
+    if (rc == PT_OK && hipStreamSynchronize(sv->st_two) != hipSuccess) rc = PT_EDEVICE;
     if (rc == PT_OK && hipStreamSynchronize(sv->st_side) != hipSuccess) rc = PT_EDEVICE;
     {
       std::lock_guard<std::mutex> lk(sv->mu);
@@ -390,19 +394,21 @@ PT_API int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server
   props.location.id = sv->device;
   uint64_t keep = UINT64_MAX;  // freed blocks stay in the pool for reuse
   if (hipStreamCreateWithFlags(&sv->st_main, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&sv->st_two, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&sv->st_side, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&sv->st_admit, hipStreamNonBlocking) != hipSuccess ||
       hipMemPoolCreate(&sv->pool, &props) != hipSuccess ||
       hipMemPoolSetAttribute(sv->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
     (void)hipGetLastError();
     if (sv->st_main) (void)hipStreamDestroy(sv->st_main);
+    if (sv->st_two) (void)hipStreamDestroy(sv->st_two);
     if (sv->st_side) (void)hipStreamDestroy(sv->st_side);
     if (sv->st_admit) (void)hipStreamDestroy(sv->st_admit);
     if (sv->pool) (void)hipMemPoolDestroy(sv->pool);
     delete sv;
     return pt_fail(PT_EDEVICE, "pt_server_start: stream or memory pool creation failed");
   }
-  sv->batch[0] = batch_new(sv->st_main);
+  sv->batch[0] = batch_new(sv->st_two);
   sv->batch[1] = batch_new(sv->st_main);
   if (!sv->batch[0] || !sv->batch[1]) {
     batch_free(sv->batch[0]);
@@ -552,6 +558,7 @@ PT_API int pt_server_stop(pt_server* sv) {
   batch_free(sv->batch[1]);
   (void)hipStreamSynchronize(sv->st_admit);
   (void)hipStreamDestroy(sv->st_main);
+  (void)hipStreamDestroy(sv->st_two);
   (void)hipStreamDestroy(sv->st_side);
   (void)hipStreamDestroy(sv->st_admit);
   (void)hipMemPoolDestroy(sv->pool);
