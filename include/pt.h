@@ -70,6 +70,11 @@ extern "C" {
  * pt_correlation_length).  Off by default: the fused kernels then carry no
  * mode code. */
 #define PT_TRACK_MODES 0x20u
+/* Also a pt_init_ex flag (and accepted by pt_job_bytes): the job keeps run
+ * diagnostics per sample and temperature (pt_get_stats).  Such a job always
+ * runs the per-step kernels (pt_mcs and pt_mcs_noalloc take them; batches
+ * and the server refuse it); results are bit-identical either way. */
+#define PT_TRACK_STATS 0x80u
 
 /* pt_mcs flags */
 #define PT_MCS_HOUDAYER 1u
@@ -367,6 +372,19 @@ int pt_tunnel_summary(const uint64_t *trips, int32_t rows, uint64_t passes,
  *   out int64 [samples][replicas][L/2 + 1]
  * Synchronous.  PT_EINVAL for a job created without PT_TRACK_MODES. */
 int pt_get_modes(pt_job *job, int64_t *out);
+
+/* Run diagnostics of a job created with PT_TRACK_STATS (Sec. 2.3 discusses
+ * the exchange acceptance rates, Sec. 3 the spread of cluster sizes that
+ * unbalances the cluster kernel): int64 out [samples][replicas][24], counted
+ * since creation (kept by pt_get_state / pt_set_state) --
+ *   [0]      accepted Metropolis flips of the configurations at temperature
+ *            k, both replica sets (divide by 2 N and the sweeps for a rate)
+ *   [1]      accepted exchanges of the pair (k, k+1), both replica sets
+ *   [2]      Houdayer passes at k that exchanged at least one site
+ *   [3]      the sites those passes exchanged
+ *   [4 + b]  passes that exchanged between 2^b and 2^(b+1) - 1 sites
+ * Synchronises the stream.  PT_EINVAL for a job without diagnostics. */
+int pt_get_stats(pt_job *job, int64_t *out);
 
 /* Per temperature k (int32 index 0 = coldest), disorder-averaged from integer
  * sums over samples: chi0[k] = chi_SG(0) = [sum Q^2] / (S n_meas N) (the

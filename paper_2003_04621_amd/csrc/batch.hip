@@ -714,6 +714,8 @@ PT_API int pt_batch_create(pt_job* const* jobs, int32_t n, pt_batch** out) {
     if (jobs[i]->g.d != d) return pt_fail(PT_EINVAL, "pt_batch_create: all jobs must have the same dim");
     if (jobs[i]->gauss)
       return pt_fail(PT_EINVAL, "pt_batch_create: jobs with Gaussian couplings run alone (pt_mcs)");
+    if (jobs[i]->track_stats)
+      return pt_fail(PT_EINVAL, "pt_batch_create: jobs keeping run diagnostics run alone (pt_mcs)");
     for (int k = 0; k < i; ++k)
       if (jobs[k] == jobs[i]) return pt_fail(PT_EINVAL, "pt_batch_create: a job appears twice");
   }

@@ -18,10 +18,21 @@
 
 namespace ptsg {
 
+// Diagnostics of one pass at temperature k of sample s that exchanged
+// `size` > 0 sites (one thread per pair: no atomics needed).
+__device__ __forceinline__ void count_exchanged(const Geo& g, int64_t* stats, int s, int k,
+                                                uint32_t size) {
+  int64_t* st = stats + ((size_t)s * g.NT + k) * kNStat;
+  st[2] += 1;
+  st[3] += size;
+  st[4 + (31 - __clz(size))] += 1;
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) k_houdayer(Geo g, void* spins, const uint32_t* __restrict__ jw,
                                                   int32_t* __restrict__ E,
-                                                  const int32_t* __restrict__ sot, DevCounters* ctr) {
+                                                  const int32_t* __restrict__ sot, DevCounters* ctr,
+                                                  int64_t* __restrict__ stats) {
   extern __shared__ uint32_t lds[];
   const int T = blockDim.x, t = threadIdx.x;
   const int NW = g.NW;
@@ -29,7 +40,7 @@ __global__ void __launch_bounds__(256) k_houdayer(Geo g, void* spins, const uint
   uint32_t* Q = A + 2 * NW;        // overlap words (later replica b)
   uint32_t* Cl = Q + 2 * NW;       // cluster words
   uint32_t* pre = Cl + 2 * NW;     // [T] chunk counts -> prefix sums
-  __shared__ uint32_t n_minus;
+  __shared__ uint32_t n_minus, size_acc;
   __shared__ int delta_acc;
 
   const uint32_t v = load_counter(&ctr->v);
@@ -41,7 +52,10 @@ __global__ void __launch_bounds__(256) k_houdayer(Geo g, void* spins, const uint
 
   load_lattice(g, spins, lat_a, A, t, T);
   load_lattice(g, spins, lat_b, Q, t, T);
-  if (t == 0) delta_acc = 0;
+  if (t == 0) {
+    delta_acc = 0;
+    size_acc = 0;
+  }
   __syncthreads();
   for (int i = t; i < 2 * NW; i += T) {
     Q[i] ^= A[i];
@@ -91,6 +105,11 @@ __global__ void __launch_bounds__(256) k_houdayer(Geo g, void* spins, const uint
     int dl = 0;
     for (int w = t; w < NW; w += T) dl += cluster_delta_word<D>(g, Cl, A, jw0, w);
     if (dl) atomicAdd(&delta_acc, dl);
+    if (stats) {
+      uint32_t sz = 0;
+      for (int i = t; i < 2 * NW; i += T) sz += __popc(Cl[i]);
+      if (sz) atomicAdd(&size_acc, sz);
+    }
     __syncthreads();
 
     // exchange the replicas on the cluster: a' = a ^ C, b' = Q ^ a'
@@ -105,6 +124,7 @@ __global__ void __launch_bounds__(256) k_houdayer(Geo g, void* spins, const uint
     if (t == 0) {
       E[lat_a] += delta_acc;
       E[lat_b] -= delta_acc;
+      if (stats) count_exchanged(g, stats, s, k, size_acc);
     }
   }
 }
@@ -117,7 +137,7 @@ __global__ void __launch_bounds__(256) k_houdayer_multi(Geo g, void* spins,
                                                         const uint32_t* __restrict__ jw,
                                                         int32_t* __restrict__ E,
                                                         const int32_t* __restrict__ sot,
-                                                        DevCounters* ctr) {
+                                                        DevCounters* ctr, int64_t* __restrict__ stats) {
   extern __shared__ __align__(16) uint32_t lds_m[];
   const int T = blockDim.x, t = threadIdx.x;
   const int NW = g.NW;
@@ -126,6 +146,7 @@ __global__ void __launch_bounds__(256) k_houdayer_multi(Geo g, void* spins,
   uint32_t* Cl = Q + 2 * NW;      // exchanged sites
   uint32_t* scr = Cl + 2 * NW;    // row masks, coins, labels (2 NW is even: 8-byte aligned)
   __shared__ int delta_acc;
+  __shared__ uint32_t size_acc;
 
   const uint32_t v = load_counter(&ctr->v);
   const int pair = blockIdx.x;  // s*NT + k
@@ -136,7 +157,10 @@ __global__ void __launch_bounds__(256) k_houdayer_multi(Geo g, void* spins,
 
   load_lattice(g, spins, lat_a, A, t, T);
   load_lattice(g, spins, lat_b, Q, t, T);
-  if (t == 0) delta_acc = 0;
+  if (t == 0) {
+    delta_acc = 0;
+    size_acc = 0;
+  }
   __syncthreads();
   for (int i = t; i < 2 * NW; i += T) Q[i] ^= A[i];
   __syncthreads();
@@ -146,6 +170,11 @@ __global__ void __launch_bounds__(256) k_houdayer_multi(Geo g, void* spins,
   int dl = 0;
   for (int w = t; w < NW; w += T) dl += cluster_delta_word<D>(g, Cl, A, jw0, w);
   if (dl) atomicAdd(&delta_acc, dl);
+  if (stats) {
+    uint32_t sz = 0;
+    for (int i = t; i < 2 * NW; i += T) sz += __popc(Cl[i]);
+    if (sz) atomicAdd(&size_acc, sz);
+  }
   __syncthreads();
   for (int i = t; i < 2 * NW; i += T) {
     const uint32_t an = A[i] ^ Cl[i];
@@ -159,10 +188,12 @@ __global__ void __launch_bounds__(256) k_houdayer_multi(Geo g, void* spins,
     E[lat_a] += delta_acc;
     E[lat_b] -= delta_acc;
   }
+  if (t == 0 && stats && size_acc) count_exchanged(g, stats, s, k, size_acc);
 }
 
 hipError_t launch_houdayer_multi(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
-                                 const int32_t* sot, DevCounters* ctr, hipStream_t st) {
+                                 const int32_t* sot, DevCounters* ctr, int64_t* stats,
+                                 hipStream_t st) {
   if (g.N > kMultiMaxSites) return hipErrorInvalidValue;
   const int threads = 256;
   const size_t lds = sizeof(uint32_t) * (2 * (size_t)g.NW + multi_scratch_words(g.N, g.NR, g.NW));
@@ -174,15 +205,15 @@ hipError_t launch_houdayer_multi(const Geo& g, void* spins, const uint32_t* jw, 
   }
   if (g.d == 3)
     hipLaunchKernelGGL(k_houdayer_multi<3>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot,
-                       ctr);
+                       ctr, stats);
   else
     hipLaunchKernelGGL(k_houdayer_multi<2>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot,
-                       ctr);
+                       ctr, stats);
   return hipGetLastError();
 }
 
 hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
-                           const int32_t* sot, DevCounters* ctr, hipStream_t st) {
+                           const int32_t* sot, DevCounters* ctr, int64_t* stats, hipStream_t st) {
   int threads = ((g.NW + 63) / 64) * 64;
   if (threads > 256) threads = 256;
   const size_t lds = sizeof(uint32_t) * (6 * (size_t)g.NW + threads);
@@ -193,14 +224,16 @@ hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (ea != hipSuccess) return ea;
     }
-    hipLaunchKernelGGL(k_houdayer<3>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot, ctr);
+    hipLaunchKernelGGL(k_houdayer<3>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot, ctr,
+                       stats);
   } else {
     if (lds > 65536) {
       const hipError_t ea = hipFuncSetAttribute((const void*)k_houdayer<2>,
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (ea != hipSuccess) return ea;
     }
-    hipLaunchKernelGGL(k_houdayer<2>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot, ctr);
+    hipLaunchKernelGGL(k_houdayer<2>, dim3(blocks), dim3(threads), lds, st, g, spins, jw, E, sot, ctr,
+                       stats);
   }
   return hipGetLastError();
 }

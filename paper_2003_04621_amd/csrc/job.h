@@ -37,6 +37,10 @@ struct pt_job {
   bool track_walk = false;
   int32_t* walk = nullptr;   // [S][2NT][2]: replica-walk label, pass its round trip began
   uint64_t* trips = nullptr; // [S][32][3]: round trips per log2 bin of the ending pass
+  // run diagnostics, allocated only for jobs created with PT_TRACK_STATS
+  // (such jobs always run the per-step kernels)
+  bool track_stats = false;
+  int64_t* stats = nullptr;  // [S][NT][kNStat]
   // fused-step LDS plans: both sets without / with Houdayer, one set, (3
   // unused: split samples have split_lay), both sets with multi-cluster
   // Houdayer moves

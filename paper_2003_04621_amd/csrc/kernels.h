@@ -21,24 +21,33 @@ hipError_t launch_pack_couplings(const Geo& g, const int8_t* J8, uint32_t* jw, h
 hipError_t launch_energy(const Geo& g, const void* spins, const uint32_t* jw, int32_t* E,
                          hipStream_t st);
 
-// n checkerboard Metropolis sweeps starting at sweep number ctr->t.
+// Run diagnostics per sample and temperature (jobs created with
+// PT_TRACK_STATS): int64 [S][NT][kNStat] -- [0] accepted Metropolis flips of
+// the configurations at that temperature, [1] accepted exchanges of the pair
+// (k, k+1), [2] Houdayer passes that exchanged sites, [3] the sites they
+// exchanged, [4 + b] passes that exchanged between 2^b and 2^(b+1) - 1 sites.
+constexpr int kNStat = 24;
+
+// n checkerboard Metropolis sweeps starting at sweep number ctr->t (stats:
+// null, or the diagnostics above).
 hipError_t launch_sweep(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
                         const int32_t* tos, const uint32_t* thr, DevCounters* ctr, int n,
-                        hipStream_t st);
+                        int64_t* stats, hipStream_t st);
 
 // One replica-exchange pass numbered ctr->u, followed by the replica-walk
 // bookkeeping of walk_observe (walk [S][2NT][2], trips [S][32][3]; both null
 // for a job that does not keep it).
 hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t* tos,
                            const uint32_t* thrpt, int M, int32_t* walk, uint64_t* trips,
-                           DevCounters* ctr, hipStream_t st);
+                           DevCounters* ctr, int64_t* stats, hipStream_t st);
 
 // One Houdayer pass numbered ctr->v.
 hipError_t launch_houdayer(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
-                           const int32_t* sot, DevCounters* ctr, hipStream_t st);
+                           const int32_t* sot, DevCounters* ctr, int64_t* stats, hipStream_t st);
 // One multi-cluster Houdayer pass numbered ctr->v (g.N <= kMultiMaxSites).
 hipError_t launch_houdayer_multi(const Geo& g, void* spins, const uint32_t* jw, int32_t* E,
-                                 const int32_t* sot, DevCounters* ctr, hipStream_t st);
+                                 const int32_t* sot, DevCounters* ctr, int64_t* stats,
+                                 hipStream_t st);
 
 // One measurement; mom is int64 [S][NT][8]; modes (null: not kept) int64
 // [S][NT][L/2+1] receives each temperature's mode_autocorr sums.  With

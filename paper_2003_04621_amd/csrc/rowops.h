@@ -19,7 +19,8 @@ namespace ptsg {
 template <int D>
 __device__ __forceinline__ void sweep_word_j(const Geo& g, uint32_t* W, const uint32_t (&jv)[2 * D],
                                              int c, int w, int slot, int s, uint32_t tcount,
-                                             uint32_t th2, uint32_t th4, uint32_t th6, int& dE) {
+                                             uint32_t th2, uint32_t th4, uint32_t th6, int& dE,
+                                             int* nflip = nullptr) {
   const WordNb q = word_nb(g, w);
   const int p = (c + q.par) & 1;
   const uint32_t* Wo = W + (1 - c) * g.NW;
@@ -138,6 +139,7 @@ __device__ __forceinline__ void sweep_word_j(const Geo& g, uint32_t* W, const ui
     F = bop3<kAndOr>(G1, C1, A | C2) & g.maskW;
   }
   dE += 4 * (D * __popc(F) - (__popc(F & u0) + 2 * __popc(F & u1) + 4 * __popc(F & u2)));
+  if (nflip) *nflip += __popc(F);
   W[c * g.NW + w] = Wc ^ F;
 }
 
@@ -146,12 +148,13 @@ __device__ __forceinline__ void sweep_word_j(const Geo& g, uint32_t* W, const ui
 template <int D>
 __device__ __forceinline__ void sweep_word(const Geo& g, uint32_t* W, const uint32_t* __restrict__ jw,
                                            int c, int w, int slot, int s, uint32_t tcount,
-                                           uint32_t th2, uint32_t th4, uint32_t th6, int& dE) {
+                                           uint32_t th2, uint32_t th4, uint32_t th6, int& dE,
+                                           int* nflip = nullptr) {
   const size_t js = (size_t)g.NW;
   uint32_t jv[2 * D];
 #pragma unroll
   for (int dir = 0; dir < 2 * D; ++dir) jv[dir] = jw[dir * js + w];
-  sweep_word_j<D>(g, W, jv, c, w, slot, s, tcount, th2, th4, th6, dE);
+  sweep_word_j<D>(g, W, jv, c, w, slot, s, tcount, th2, th4, th6, dE, nflip);
 }
 
 // Number of unsatisfied bonds of the colour-0 word w (every bond has exactly

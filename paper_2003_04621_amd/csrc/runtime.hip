@@ -200,7 +200,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (samples < 1 || samples >= (1 << 28)) return pt_fail(PT_EINVAL, "samples must be in [1, 2^28)");
   if (replicas < 2 || replicas > 4096) return pt_fail(PT_EINVAL, "replicas must be in [2, 4096]");
-  const uint32_t layout = flags & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
+  const uint32_t layout = flags & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES | PT_TRACK_STATS);
   if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown flags");
   for (int k = 0; k < replicas; ++k) {
     if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
@@ -224,6 +224,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   job->stream = stream;
   job->track_walk = (flags & PT_TRACK_WALK) != 0;
   job->track_modes = (flags & PT_TRACK_MODES) != 0;
+  job->track_stats = (flags & PT_TRACK_STATS) != 0;
   job->g = make_geo(samples, replicas, L, dim, (int)layout, seed);
   const Geo& g = job->g;
 
@@ -262,6 +263,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   }
   const size_t mode_words = (size_t)samples * replicas * (L / 2 + 1);
   if (job->track_modes) job->modes = (int64_t*)job->dalloc(sizeof(int64_t) * mode_words);
+  const size_t stat_words = (size_t)samples * replicas * kNStat;
+  if (job->track_stats) job->stats = (int64_t*)job->dalloc(sizeof(int64_t) * stat_words);
   int8_t* J8 = (int8_t*)job->dalloc((size_t)ncoup);
   bool split_mem = true;
   if (job->split_ok) {
@@ -273,7 +276,8 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   }
   if (!job->spins || !job->jw || !job->E || !job->sot || !job->tos || !job->thr || !job->thrpt ||
       !job->ctr || !job->mom || !J8 || !split_mem ||
-      (job->track_walk && (!job->walk || !job->trips)) || (job->track_modes && !job->modes)) {
+      (job->track_walk && (!job->walk || !job->trips)) || (job->track_modes && !job->modes) ||
+      (job->track_stats && !job->stats)) {
     job->release();
     delete job;
     return pt_fail(PT_ENOMEM, "device allocation failed");
@@ -295,6 +299,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   step(hipMemsetAsync(job->ctr, 0, sizeof(DevCounters), st));
   step(hipMemsetAsync(job->mom, 0, sizeof(int64_t) * 8 * (size_t)samples * replicas, st));
   if (job->track_modes) step(hipMemsetAsync(job->modes, 0, sizeof(int64_t) * mode_words, st));
+  if (job->track_stats) step(hipMemsetAsync(job->stats, 0, sizeof(int64_t) * stat_words, st));
   if (job->track_walk) {
     step(hipMemsetAsync(job->walk, 0, sizeof(int32_t) * 2 * (size_t)nlat, st));
     step(hipMemsetAsync(job->trips, 0, sizeof(uint64_t) * 32 * 3 * (size_t)samples, st));
@@ -410,7 +415,9 @@ PT_API int pt_init_gauss(pt_job** out, int32_t samples, int32_t replicas, int32_
   return PT_OK;
 }
 
-bool job_is_resident(const pt_job* j, uint32_t flags) { return job_plan_mode(j, flags) >= 0; }
+bool job_is_resident(const pt_job* j, uint32_t flags) {
+  return !j->track_stats && job_plan_mode(j, flags) >= 0;
+}
 
 int pt_table_len(const double* betas, int NT, int d, long N) {
   int M = 1;
@@ -434,8 +441,9 @@ size_t split_scratch_bytes(const Geo& g, bool walk, bool modes) {
 }
 
 size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* betas) {
-  const int layout = flags & ~(int)(PT_TRACK_WALK | PT_TRACK_MODES);
+  const int layout = flags & ~(int)(PT_TRACK_WALK | PT_TRACK_MODES | PT_TRACK_STATS);
   const bool walk = (flags & PT_TRACK_WALK) != 0, modes = (flags & PT_TRACK_MODES) != 0;
+  const bool stats = (flags & PT_TRACK_STATS) != 0;
   const size_t N = (d == 3) ? (size_t)L * L * L : (size_t)L * L;
   const size_t NW = N / L / fields_per_word(L);
   const size_t lat = (size_t)S * 2 * NT;
@@ -444,6 +452,7 @@ size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* be
   const size_t small = sizeof(int32_t) * (lat + 4 * (size_t)S * NT) + sizeof(int64_t) * 8 * S * NT +
                        (walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)S : 0) +
                        (modes ? sizeof(int64_t) * (size_t)S * NT * (L / 2 + 1) : 0) +
+                       (stats ? sizeof(int64_t) * (size_t)S * NT * kNStat : 0) +
                        sizeof(uint32_t) * (size_t)NT * (4 + pt_table_len(betas, NT, d, (long)N)) + 4096;
   return spins + jw + (size_t)S * d * N + small + split_scratch_bytes(make_geo(S, NT, L, d, layout, 0), walk, modes);
 }
@@ -490,7 +499,7 @@ PT_API int pt_sweep(pt_job* job, int32_t n) {
                                      job->gcz, job->ctr, m, job->stream));
     else
       PT_HIP(job, launch_sweep(job->g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, m,
-                               job->stream));
+                               job->stats, job->stream));
     PT_HIP(job, launch_advance(job->ctr, CounterStep{(uint32_t)m, 0, 0, 0}, job->stream));
   }
   return PT_OK;
@@ -503,7 +512,7 @@ PT_API int pt_exchange(pt_job* job) {
                                       job->stream));
   else
     PT_HIP(job, launch_exchange(job->g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
-                              job->trips, job->ctr, job->stream));
+                                job->trips, job->ctr, job->stats, job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 1, 0, 0}, job->stream));
   return PT_OK;
 }
@@ -514,7 +523,8 @@ PT_API int pt_houdayer(pt_job* job) {
     PT_HIP(job, launch_gauss_houdayer(job->g, job->spins, job->gJ, job->E64, job->sot, job->ctr, false,
                                       job->stream));
   else
-    PT_HIP(job, launch_houdayer(job->g, job->spins, job->jw, job->E, job->sot, job->ctr, job->stream));
+    PT_HIP(job, launch_houdayer(job->g, job->spins, job->jw, job->E, job->sot, job->ctr, job->stats,
+                                job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 1, 0}, job->stream));
   return PT_OK;
 }
@@ -528,7 +538,7 @@ PT_API int pt_houdayer_multi(pt_job* job) {
                                       job->stream));
   else
     PT_HIP(job, launch_houdayer_multi(job->g, job->spins, job->jw, job->E, job->sot, job->ctr,
-                                    job->stream));
+                                      job->stats, job->stream));
   PT_HIP(job, launch_advance(job->ctr, CounterStep{0, 0, 1, 0}, job->stream));
   return PT_OK;
 }
@@ -580,13 +590,13 @@ int mcs_per_step(pt_job* job, int32_t n, uint32_t flags) {
         PT_HIP(job, launch_gauss_measure(g, job->spins, job->E64, job->sot, job->mom, job->ctr,
                                          job->meas_every, st));
     } else {
-      PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, st));
+      PT_HIP(job, launch_sweep(g, job->spins, job->jw, job->E, job->tos, job->thr, job->ctr, 1, job->stats, st));
       if (hou && multi)
-        PT_HIP(job, launch_houdayer_multi(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
+        PT_HIP(job, launch_houdayer_multi(g, job->spins, job->jw, job->E, job->sot, job->ctr, job->stats, st));
       else if (hou)
-        PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, st));
+        PT_HIP(job, launch_houdayer(g, job->spins, job->jw, job->E, job->sot, job->ctr, job->stats, st));
       PT_HIP(job, launch_exchange(g, job->E, job->sot, job->tos, job->thrpt, job->M, job->walk,
-                                  job->trips, job->ctr, st));
+                                  job->trips, job->ctr, job->stats, st));
       if (meas)
         PT_HIP(job, launch_measure(g, job->spins, job->E, job->sot, job->mom, job->modes, job->ctr,
                                    job->meas_every, st));
@@ -673,7 +683,7 @@ PT_API int pt_job_bytes(int32_t samples, int32_t replicas, int32_t L, int32_t di
   if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
   if (L < 4 || L > 64 || (L & 1)) return pt_fail(PT_EINVAL, "L must be even and in [4, 64]");
   if (samples < 1 || replicas < 2) return pt_fail(PT_EINVAL, "need samples >= 1 and replicas >= 2");
-  const uint32_t lay = layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES);
+  const uint32_t lay = layout & ~(uint32_t)(PT_TRACK_WALK | PT_TRACK_MODES | PT_TRACK_STATS);
   if (lay != PT_LAYOUT_INT8 && lay != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown layout");
   for (int k = 0; k < replicas; ++k)
     if (!(betas[k] > 0.0) || (k > 0 && !(betas[k] < betas[k - 1])))
@@ -917,6 +927,17 @@ PT_API int pt_tunnel_summary(const uint64_t* trips, int32_t rows, uint64_t passe
   return PT_OK;
 }
 
+PT_API int pt_get_stats(pt_job* job, int64_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (int rc = check_fault(job)) return rc;
+  if (!out) return pt_fail(PT_EINVAL, "null output");
+  if (!job->track_stats) return pt_fail(PT_EINVAL, "the job was not created with PT_TRACK_STATS");
+  PT_HIP(job, hipMemcpyAsync(out, job->stats, sizeof(int64_t) * (size_t)job->g.S * job->g.NT * kNStat,
+                             hipMemcpyDeviceToHost, job->stream));
+  PT_HIP(job, hipStreamSynchronize(job->stream));
+  return PT_OK;
+}
+
 PT_API int pt_get_modes(pt_job* job, int64_t* out) {
   if (int rc = check_job(job)) return rc;
   if (!job->track_modes) return pt_fail(PT_EINVAL, "the job was created without PT_TRACK_MODES");
@@ -1053,11 +1074,12 @@ size_t state_size(const pt_job* job) {
          2 * sizeof(int32_t) * (size_t)g.S * 2 * g.NT + sizeof(DevCounters) +
          sizeof(int64_t) * 8 * (size_t)g.S * g.NT +
          (job->track_walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)g.S : 0) +
-         (job->track_modes ? sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1) : 0);
+         (job->track_modes ? sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1) : 0) +
+         (job->track_stats ? sizeof(int64_t) * (size_t)g.S * g.NT * kNStat : 0);
 }
 
 int32_t state_flags(const pt_job* job) {
-  return (job->track_walk ? 1 : 0) | (job->track_modes ? 2 : 0);
+  return (job->track_walk ? 1 : 0) | (job->track_modes ? 2 : 0) | (job->track_stats ? 4 : 0);
 }
 }  // namespace
 
@@ -1100,8 +1122,13 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
                                hipMemcpyDeviceToHost, st));
     p += sizeof(uint64_t) * 32 * 3 * (size_t)g.S;
   }
-  if (job->track_modes)
+  if (job->track_modes) {
     PT_HIP(job, hipMemcpyAsync(p, job->modes, sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1),
+                               hipMemcpyDeviceToHost, st));
+    p += sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1);
+  }
+  if (job->track_stats)
+    PT_HIP(job, hipMemcpyAsync(p, job->stats, sizeof(int64_t) * (size_t)g.S * g.NT * kNStat,
                                hipMemcpyDeviceToHost, st));
   PT_HIP(job, hipStreamSynchronize(st));
   *len = need;
@@ -1143,8 +1170,13 @@ PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
                                hipMemcpyHostToDevice, st));
     p += sizeof(uint64_t) * 32 * 3 * (size_t)g.S;
   }
-  if (job->track_modes)
+  if (job->track_modes) {
     PT_HIP(job, hipMemcpyAsync(job->modes, p, sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1),
+                               hipMemcpyHostToDevice, st));
+    p += sizeof(int64_t) * (size_t)g.S * g.NT * (g.L / 2 + 1);
+  }
+  if (job->track_stats)
+    PT_HIP(job, hipMemcpyAsync(job->stats, p, sizeof(int64_t) * (size_t)g.S * g.NT * kNStat,
                                hipMemcpyHostToDevice, st));
   PT_HIP(job, hipStreamSynchronize(st));
   return PT_OK;

@@ -175,7 +175,7 @@ hipError_t launch_energy(const Geo& g, const void* spins, const uint32_t* jw, in
 __global__ void k_exchange(Geo g, const int32_t* __restrict__ E, int32_t* __restrict__ sot,
                            int32_t* __restrict__ tos, const uint32_t* __restrict__ thrpt, int M,
                            int32_t* __restrict__ walk, uint64_t* __restrict__ trips,
-                           DevCounters* ctr) {
+                           DevCounters* ctr, int64_t* __restrict__ stats) {
   const uint32_t u = load_counter(&ctr->u);
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (long)g.S * 2) {
@@ -200,6 +200,9 @@ __global__ void k_exchange(Geo g, const int32_t* __restrict__ E, int32_t* __rest
         so[k + 1] = a;
         to[b] = k;
         to[a] = k + 1;
+        if (stats)  // both replica sets of the sample count here
+          atomicAdd(reinterpret_cast<unsigned long long*>(stats + ((size_t)s * g.NT + k) * kNStat + 1),
+                    1ull);
         // the configuration now at k+1 is a; keep carrying it upward
       } else {
         a = b;
@@ -213,10 +216,10 @@ __global__ void k_exchange(Geo g, const int32_t* __restrict__ E, int32_t* __rest
 
 hipError_t launch_exchange(const Geo& g, const int32_t* E, int32_t* sot, int32_t* tos,
                            const uint32_t* thrpt, int M, int32_t* walk, uint64_t* trips,
-                           DevCounters* ctr, hipStream_t st) {
+                           DevCounters* ctr, int64_t* stats, hipStream_t st) {
   const long lanes = (long)g.S * 2;
   hipLaunchKernelGGL(k_exchange, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, g, E, sot,
-                     tos, thrpt, M, walk, trips, ctr);
+                     tos, thrpt, M, walk, trips, ctr, stats);
   return hipGetLastError();
 }
 

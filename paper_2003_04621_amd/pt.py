@@ -22,6 +22,7 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE, PT_ECANCELED = 0, -1, -2, -3
 PT_LAYOUT_INT8, PT_LAYOUT_PACKED = 0, 1
 PT_TRACK_WALK = 0x10
 PT_TRACK_MODES = 0x20
+PT_TRACK_STATS = 0x80
 PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
 PT_MCS_MULTICLUSTER = 0x40
 PT_SERVE_UNTIL_EQUILIBRATED = 0x100
@@ -34,7 +35,7 @@ EXPORTS = [
     "pt_measure", "pt_mcs", "pt_mcs_noalloc",
     "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_walk", "pt_tunnel_summary",
-    "pt_get_modes", "pt_correlation_length",
+    "pt_get_modes", "pt_correlation_length", "pt_get_stats",
     "pt_get_state", "pt_set_state",
     "pt_set_measure_interval", "pt_set_stream", "pt_set_allocator", "pt_last_error", "pt_version",
     "pt_batch_create", "pt_batch_set_stream", "pt_batch_run", "pt_batch_tune",
@@ -91,7 +92,7 @@ def lib():
             "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
             "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
             "pt_get_walk": [P, P, P, P], "pt_tunnel_summary": [P, I32, U64, P, P, P, P],
-            "pt_get_modes": [P, P], "pt_correlation_length": [P, P, P, P],
+            "pt_get_modes": [P, P], "pt_correlation_length": [P, P, P, P], "pt_get_stats": [P, P],
             "pt_get_state": [P, P, C.POINTER(C.c_size_t)], "pt_set_state": [P, P, C.c_size_t],
             "pt_set_stream": [P, P], "pt_set_allocator": [_ALLOC, _FREE, P],
             "pt_set_measure_interval": [P, I32],
@@ -207,11 +208,12 @@ class Job:
 
 
 def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_INT8,
-            stream=None, walk=False, modes=False) -> Job:
+            stream=None, walk=False, modes=False, stats=False) -> Job:
     """Creates a job; `stream` is a torch.cuda.Stream, a raw hipStream_t int,
     or None for torch's current stream (torch memory hooks are installed);
     `walk` keeps the replica walk and its round trips (PT_TRACK_WALK), `modes`
-    the two-replica modes (PT_TRACK_MODES)."""
+    the two-replica modes (PT_TRACK_MODES), `stats` the run diagnostics
+    (PT_TRACK_STATS)."""
     import torch
     if _hooks is None:
         use_torch_memory()
@@ -225,7 +227,7 @@ def pt_init(samples, replicas, L, dim, couplings, betas, seed, layout=PT_LAYOUT_
     _check(lib().pt_init_ex(C.byref(h), int(samples), int(replicas), int(L), int(dim), _p(J),
                             _p(b), C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
                             int(layout) | (PT_TRACK_WALK if walk else 0)
-                            | (PT_TRACK_MODES if modes else 0)))
+                            | (PT_TRACK_MODES if modes else 0) | (PT_TRACK_STATS if stats else 0)))
     job = Job(h, int(samples), int(replicas), int(L), int(dim), int(layout), walk, modes)
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -436,6 +438,16 @@ def pt_get_walk(job: Job):
     trips = np.zeros((job.S, 32, 3), np.uint64)
     _check(lib().pt_get_walk(job.h, _p(lab), _p(beg), _p(trips)))
     return lab, beg, trips
+
+
+def pt_get_stats(job: Job) -> np.ndarray:
+    """Run diagnostics [S][NT][24] (int64) of a job created with stats=True:
+    accepted Metropolis flips at temperature k, accepted exchanges of
+    (k, k+1), Houdayer passes that exchanged sites, the sites exchanged, and
+    their histogram by floor(log2) (20 bins)."""
+    out = np.zeros((job.S, job.NT, 24), np.int64)
+    _check(lib().pt_get_stats(job.h, _p(out)))
+    return out
 
 
 def pt_get_modes(job: Job) -> np.ndarray:
