@@ -76,6 +76,38 @@ __device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
+// The same function with round 1's key words folded into the counter words
+// c1 and c3 first: for the Metropolis counters those are the same for every
+// lane of a wavefront in the fused kernels (sweep number, colour, tag and
+// sample), so c3 ^ k1 is one scalar operand and round 1 takes a two-input
+// XOR where the three-input one would first copy one of its two scalar
+// operands to a vector register (an instruction reads at most one scalar
+// register).  Elsewhere the folded words are loop-invariant per lattice.  XOR
+// is associative: the output words are identical.
+__device__ __forceinline__ Ctr4 philox10_u(Ctr4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t y0 = c.y ^ k0;
+  const uint32_t w1 = c.w ^ k1;
+  const uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
+  c = Ctr4{(uint32_t)(p1 >> 32) ^ y0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ w1, (uint32_t)p0};
+  k0 += kWeyl0;
+  k1 += kWeyl1;
+#pragma unroll
+  for (int r = 1; r < 10; ++r) {
+    const uint64_t q0 = (uint64_t)kPhiloxM0 * c.x;
+    const uint64_t q1 = (uint64_t)kPhiloxM1 * c.z;
+    Ctr4 n;
+    n.x = bop3s<kXor3>((uint32_t)(q1 >> 32), c.y, k0);
+    n.y = (uint32_t)q1;
+    n.z = bop3s<kXor3>((uint32_t)(q0 >> 32), c.w, k1);
+    n.w = (uint32_t)q0;
+    c = n;
+    k0 += kWeyl0;
+    k1 += kWeyl1;
+  }
+  return c;
+}
+
 // (mask << 1) | (r < t): the borrow of r - t shifted into the mask, two VALU
 // instructions.  t is a per-lane value (lanes of one wavefront may serve
 // lattices at different temperatures).

@@ -1019,7 +1019,7 @@ constexpr uint64_t kBarrierTicks = 6000000000ull;
 // every later wait of the job gives up at once.  Only thread 0 synchronises
 // with the other parts: every wavefront first waits until its own stores have
 // completed (they are then in this XCD's L2, whose dirty lines thread 0's
-// release writes back), and the workgroup barrier after thread 0's acquire
+// release writes back), and the workgroup barrier after thread 0's acquire fence
 // (which invalidates the caches) orders every later load after it.
 __device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uint32_t* fault,
                                              int* flag) {
@@ -1029,7 +1029,10 @@ __device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uin
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int good = 1;
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    // poll with relaxed loads and acquire once, after the count is reached:
+    // an acquire load invalidates caches on every poll, which would also
+    // evict the data other workgroups on the same L2 are computing with
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
           wall_clock64() - t0 > kBarrierTicks) {
         __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1038,6 +1041,9 @@ __device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uin
       }
       __builtin_amdgcn_s_sleep(2);
     }
+    // the relaxed load read the value of the other parts' release increments:
+    // this fence makes their published energies and words visible
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *flag = good;
   }
   __syncthreads();

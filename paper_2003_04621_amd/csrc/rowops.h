@@ -62,7 +62,7 @@ __device__ __forceinline__ void sweep_word_j(const Geo& g, uint32_t* W, const ui
     for (int f = g.P - 1; f >= 0; --f) {
       const uint32_t R = (uint32_t)word_row(g, q, f);
       for (int grp = g.G - 1; grp >= 0; --grp) {
-        const Ctr4 r = philox10(Ctr4{R * (uint32_t)g.G + (uint32_t)grp, c1w, (uint32_t)slot, c3w},
+        const Ctr4 r = philox10_u(Ctr4{R * (uint32_t)g.G + (uint32_t)grp, c1w, (uint32_t)slot, c3w},
                                 g.key0, g.key1);
         if (D == 3) {
           shift_in_k_pair(C1, C2, r.w, r.z, th2, th4, th6);
@@ -83,7 +83,7 @@ __device__ __forceinline__ void sweep_word_j(const Geo& g, uint32_t* W, const ui
   for (int f = g.P - 1; f >= 0; --f) {
     const uint32_t R = (uint32_t)word_row(g, q, f);
     for (int grp = g.G - 1; grp >= 0; --grp) {
-      const Ctr4 r = philox10(Ctr4{R * (uint32_t)g.G + (uint32_t)grp, c1w, (uint32_t)slot, c3w},
+      const Ctr4 r = philox10_u(Ctr4{R * (uint32_t)g.G + (uint32_t)grp, c1w, (uint32_t)slot, c3w},
                               g.key0, g.key1);
       const int nv = g.H - 4 * grp;  // sites of this row field served by the call
       if (D == 3) {
