@@ -428,10 +428,11 @@ int pt_batch_set_stream(pt_batch *b, void *hip_stream);
  * workgroup). */
 int pt_batch_run(pt_batch *b, int32_t mcs, uint32_t flags);
 
-/* Autotuner: times trial_mcs steps of each launch configuration (threads per
- * workgroup 1024/768/512/256, one or two replica sets per item, largest-first or
- * job order) on the batch itself, restores every job's state after each trial,
- * and keeps the fastest.  cache_path (may be NULL) is a JSON-lines file keyed
+/* Autotuner: after one untimed trial, times trial_mcs steps of each launch
+ * configuration (threads per workgroup 1024/768/512/256, one or two replica
+ * sets per item, largest-first or job order) twice on the batch itself,
+ * restoring every job's state after each trial, and keeps the configuration
+ * whose faster run was fastest.  cache_path (may be NULL) is a JSON-lines file keyed
  * by the batch shape; a hit skips the trials. */
 int pt_batch_tune(pt_batch *b, int32_t trial_mcs, uint32_t flags, const char *cache_path);
 /* cfg3 = {threads per workgroup, replica sets per item, order}.  threads 0

@@ -806,23 +806,37 @@ PT_API int pt_batch_tune(pt_batch* b, int32_t trial_mcs, uint32_t flags, const c
   BatchConfig best = b->cfg;
   double best_ms = 1e300;
   int rc = PT_OK;
-  for (int threads : {1024, 768, 512, 256})
-    for (int sets : {2, 1})
+  // one untimed trial first (the GPU clock and the caches settle), then each
+  // configuration timed twice from the same state, keeping its faster run
+  const BatchConfig start = b->cfg;
+  rc = build_worklist(b, trial_mcs, work_flags);
+  if (rc == PT_OK) rc = run_once(b, false);
+  if (rc == PT_OK) rc = snapshot(b, sn, true);
+  for (int threads : {1024, 768, 512, 256}) {
+    for (int sets : {2, 1}) {
       for (int order : {0, 1}) {
+        if (rc != PT_OK) break;
         b->cfg = BatchConfig{threads, sets, order};
         if ((rc = build_worklist(b, trial_mcs, work_flags))) break;
-        (void)hipEventRecord(e0, b->stream);
-        if ((rc = run_once(b, false))) break;
-        (void)hipEventRecord(e1, b->stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-          best_ms = ms;
+        double cfg_ms = 1e300;
+        for (int rep = 0; rep < 2 && rc == PT_OK; ++rep) {
+          (void)hipEventRecord(e0, b->stream);
+          if ((rc = run_once(b, false))) break;
+          (void)hipEventRecord(e1, b->stream);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (ms < cfg_ms) cfg_ms = ms;
+          rc = snapshot(b, sn, true);
+        }
+        if (rc == PT_OK && cfg_ms < best_ms) {
+          best_ms = cfg_ms;
           best = b->cfg;
         }
-        if ((rc = snapshot(b, sn, true))) break;
       }
+    }
+  }
+  if (rc != PT_OK) best = start;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (void* p : sn.bufs) (void)hipFree(p);
@@ -834,16 +848,6 @@ PT_API int pt_batch_tune(pt_batch* b, int32_t trial_mcs, uint32_t flags, const c
 PT_API int pt_batch_destroy(pt_batch* b) {
   if (!b) return pt_fail(PT_EINVAL, "null batch");
   (void)hipStreamSynchronize(b->stream);
-  drop_graph(b);
-  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  if (b->d_jobs) (void)hipFree(b->d_jobs);
-  if (b->d_items) (void)hipFree(b->d_items);
-  if (b->d_queue) (void)hipFree(b->d_queue);
-  if (b->stage_ev) (void)hipEventSynchronize(b->stage_ev);
-  if (b->h_stage) (void)hipHostFree(b->h_stage);
-  if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
-  if (b->last_ev) (void)hipEventDestroy(b->last_ev);
-  (void)hipGetLastError();
-  delete b;
+  batch_free(b);
   return PT_OK;
 }
