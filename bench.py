@@ -183,10 +183,13 @@ def _requests(W, rng, n, seed0):
     return reqs
 
 
-def _serve(pt, args, reqs, arrivals):
+def _serve(pt, args, reqs, arrivals, until_eq=False):
     """Submits reqs[i] at arrivals[i] seconds and waits for every result.
     Also returns (seconds, flips) on the server's clock at the moment the
-    last request was admitted: until then the queue was never empty."""
+    last request was admitted: until then the queue was never empty.  With
+    until_eq the requests keep the replica walk and end as soon as their
+    round trips pass the logarithmic-binning check (their sweeps an upper
+    bound)."""
     srv = pt.pt_server_start(args.serve_budget << 20, steps_per_round=args.serve_round)
     n = len(reqs)
     tickets, results = {}, {}
@@ -203,7 +206,8 @@ def _serve(pt, args, reqs, arrivals):
         while i < n and arrivals[i] <= now:
             r = reqs[i]
             tickets[i] = pt.pt_server_submit(srv, 3, r["L"], r["NT"], 1, r["betas"], r["J"],
-                                             r["seed"], r["sweeps"], r["sweeps"] // 2)
+                                             r["seed"], r["sweeps"], r["sweeps"] // 2,
+                                             walk=until_eq, until_equilibrated=until_eq)
             i += 1
         if saturated is None and i == n:
             st = pt.pt_server_stats(srv)
@@ -220,6 +224,8 @@ def _serve(pt, args, reqs, arrivals):
     span = max(r["t_done"] for r in results.values()) - min(r["t_submit"] for r in results.values())
     lat = np.array([results[k]["t_done"] - results[k]["t_submit"] for k in range(n)])
     bad = sum(1 for r in results.values() if r["status"] != 0)
+    if until_eq:
+        return stats, span, lat, bad, saturated, results
     return stats, span, lat, bad, saturated
 
 
@@ -239,6 +245,25 @@ def served(pt, torch, W, args):
     lam = args.serve_load * capacity * 1e9 / mean_flips       # jobs per second
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
     stats, span, lat, bad, _ = _serve(pt, args, reqs, arrivals)
+    # time to an equilibrated result: the same kind of requests keeping the
+    # replica walk, each ending once its round trips pass the binning check
+    # (Sec. 2.3), at the same arrival rate
+    eq = None
+    if args.serve_eq_requests > 0:
+        reqs_e = _requests(W, rng, args.serve_eq_requests, 7000)
+        arr_e = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs_e)))
+        st_e, span_e, lat_e, bad_e, _, res_e = _serve(pt, args, reqs_e, arr_e, until_eq=True)
+        done_eq = [k for k, r in res_e.items() if r["equilibrated"] == 1]
+        used = [(reqs_e[k]["sweeps"] // 2 + res_e[k]["n_meas"]) / reqs_e[k]["sweeps"] for k in res_e]
+        eq = {"requests": len(reqs_e), "equilibrated": len(done_eq),
+              "p50_latency_s": round(float(np.percentile(lat_e, 50)), 4),
+              "p99_latency_s": round(float(np.percentile(lat_e, 99)), 4),
+              "p50_latency_equilibrated_s": (round(float(np.percentile(
+                  [res_e[k]["t_done"] - res_e[k]["t_submit"] for k in done_eq], 50)), 4)
+                  if done_eq else None),
+              "mean_fraction_of_sweeps_run": round(float(np.mean(used)), 4),
+              "value": round(st_e["flips"] / span_e / 1e9, 2), "unit": "flips/ns",
+              "failed": bad_e}
     return {"workload": f"{len(reqs)} requests, Poisson arrivals at {lam:.2f}/s "
                         f"({args.serve_load:.0%} of the measured capacity), 3D +-J, one sample, "
                         "L in {16,24,32,48}, 16-48 temperatures, 1e3-1e4 steps (half burn-in)",
@@ -254,7 +279,8 @@ def served(pt, torch, W, args):
             "busy_fraction": round(stats["busy_s"] / span, 3),
             "peak_concurrent_jobs": int(stats["peak_jobs"]),
             "peak_admitted_mib": round(stats["peak_bytes"] / 2 ** 20, 1),
-            "failed": bad + bad_b}
+            "failed": bad + bad_b,
+            "until_equilibrated": eq}
 
 
 def fused_run(pt, torch, job, wl, K, chunk, houdayer, measure, layout_name, multi=False):
@@ -412,6 +438,8 @@ def main():
     ap.add_argument("--serve-round", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-seed", type=int, default=31)
+    ap.add_argument("--serve-eq-requests", type=int, default=500,
+                    help="requests of the run that stops each job at equilibrium (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (calibrates "
