@@ -57,7 +57,7 @@ OPS_PER_FLIP = 16
 # sample is loaded once and stored once per launch, so the bytes do not depend
 # on the number of steps a launch runs.  Entries are removed when the kernel
 # changes until the counters are taken again.
-TRAFFIC_PER_LAUNCH = {("3d_l16", "int8", 2): 573461248}
+TRAFFIC_PER_LAUNCH = {("3d_l16", "int8", 2): 572715904}
 
 
 def _oracle_steps(args):
@@ -313,24 +313,23 @@ def fused_run(pt, torch, job, wl, K, chunk, houdayer, measure, layout_name, mult
         "launch_ms": round(launch_ms, 4)}
 
 
-def settle_gpu(pt, torch, wl, layout, seconds):
-    """An untimed busy period before anything is timed.  The GPU raises its
-    clock over the first tens of milliseconds of sustained load (on one box,
-    back-to-back 20-step launches of the 3D L=16 workload took 2.87 ms right
-    after an idle period, falling to 2.58 ms after about 20 ms of work, and
-    2.58 ms from the first one after a busy second), so a scratch job of the
-    same workload runs fused steps for `seconds` first.  The timed job is not
-    touched: it still gets exactly the requested warm-up steps."""
-    if seconds <= 0:
-        return 0.0
-    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed + 1,
-                     layout=layout)
+def settle_gpu(pt, torch, scratch, wl, seconds):
+    """An untimed busy period right before the timed region.  The GPU raises
+    its clock over the first tens of milliseconds of sustained load and lowers
+    it again within a tenth of a second of idling (on one box, 20-step
+    launches of the 3D L=16 workload took 2.86 ms after an idle period,
+    falling to 2.55 ms after about 20 ms of back-to-back work, and 2.83 ms
+    again after 0.1 s of host-side set-up), so a scratch job of the same
+    workload runs fused steps for `seconds`.  The timed job is not touched:
+    it gets exactly the requested warm-up steps.  The scratch job is freed
+    here."""
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        pt.pt_mcs(job, 20, houdayer=wl.houdayer, measure=True)
+        pt.pt_mcs(scratch, 20, houdayer=wl.houdayer, measure=True)
         torch.cuda.synchronize()
-    pt.pt_destroy(job)
-    return time.perf_counter() - t0
+    dt = time.perf_counter() - t0
+    pt.pt_destroy(scratch)
+    return dt
 
 
 def phase_split(pt, torch, wl, layout, steps, warmup):
@@ -472,14 +471,20 @@ def main():
 
     layout = pt.PT_LAYOUT_PACKED if args.layout == "packed" else pt.PT_LAYOUT_INT8
     torch.cuda.set_device(0)
-    settled = settle_gpu(pt, torch, wl, layout, args.settle)
     job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed,
                      layout=layout)
+    scratch = None
+    if args.settle > 0:
+        scratch = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas,
+                             wl.seed + 1, layout=layout)
     flips_per_step = wl.flips_per_sweep
     print(f"# workload {wl.name}: S={wl.samples} NT={wl.replicas} L={wl.L} d={wl.dim} "
           f"layout={args.layout}; warmup {args.warmup}", file=sys.stderr, flush=True)
     pt.pt_mcs(job, args.warmup, houdayer=wl.houdayer, measure=True)
     torch.cuda.synchronize()
+    # the clock-settling work runs right before the timed region: an idle
+    # tenth of a second is enough for the clock to drop again
+    settled = settle_gpu(pt, torch, scratch, wl, args.settle) if scratch is not None else 0.0
 
     K = args.steps
     elapsed, roofline = fused_run(pt, torch, job, wl, K, args.chunk, wl.houdayer, True, args.layout)
