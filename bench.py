@@ -167,13 +167,13 @@ def batched_mix(pt, torch, W, args):
     return out
 
 
-def _requests(W, rng, n, seed0):
+def _requests(W, rng, n, seed0, Ls=(16, 24, 32, 48), nt=(16, 48), sweeps=(1e3, 1e4)):
     """n requests of the served mix: 3D +-J, one sample, L uniform in
     {16, 24, 32, 48}, 16..48 temperatures, 10^3..10^4 steps (log-uniform),
-    half of them burn-in."""
-    Ls = rng.choice([16, 24, 32, 48], size=n)
-    NTs = rng.integers(16, 49, size=n)
-    sweeps = np.exp(rng.uniform(np.log(1e3), np.log(1e4), size=n)).astype(int)
+    half of them burn-in (other ranges as given)."""
+    Ls = rng.choice(list(Ls), size=n)
+    NTs = rng.integers(nt[0], nt[1] + 1, size=n)
+    sweeps = np.exp(rng.uniform(np.log(sweeps[0]), np.log(sweeps[1]), size=n)).astype(int)
     reqs = []
     for i in range(n):
         L, NT = int(Ls[i]), int(NTs[i])
@@ -250,12 +250,21 @@ def served(pt, torch, W, args):
     # (Sec. 2.3), at the same arrival rate
     eq = None
     if args.serve_eq_requests > 0:
-        reqs_e = _requests(W, rng, args.serve_eq_requests, 7000)
-        arr_e = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs_e)))
+        # smaller lattices than the mix above: at T_min = 0.9 the L >= 16
+        # requests of that mix do not pass the check within 1e4 sweeps
+        reqs_e = _requests(W, rng, args.serve_eq_requests, 7000, Ls=(8, 12, 16), nt=(12, 24),
+                           sweeps=(2e3, 2e4))
+        mean_e = float(np.mean([r["flips"] for r in reqs_e]))
+        lam_e = args.serve_load * capacity * 1e9 / mean_e
+        arr_e = np.cumsum(rng.exponential(1.0 / lam_e, size=len(reqs_e)))
         st_e, span_e, lat_e, bad_e, _, res_e = _serve(pt, args, reqs_e, arr_e, until_eq=True)
         done_eq = [k for k, r in res_e.items() if r["equilibrated"] == 1]
         used = [(reqs_e[k]["sweeps"] // 2 + res_e[k]["n_meas"]) / reqs_e[k]["sweeps"] for k in res_e]
-        eq = {"requests": len(reqs_e), "equilibrated": len(done_eq),
+        eq = {"workload": f"{len(reqs_e)} requests, Poisson arrivals at {lam_e:.2f}/s, 3D +-J, "
+                          "one sample, L in {8,12,16}, 12-24 temperatures in [0.9, 2.0], replica "
+                          "walk kept, each ending once its round trips pass the logarithmic-"
+                          "binning check (Sec. 2.3), at most 2e3-2e4 steps (half burn-in)",
+              "requests": len(reqs_e), "equilibrated": len(done_eq),
               "p50_latency_s": round(float(np.percentile(lat_e, 50)), 4),
               "p99_latency_s": round(float(np.percentile(lat_e, 99)), 4),
               "p50_latency_equilibrated_s": (round(float(np.percentile(
