@@ -6,23 +6,28 @@
 // the Philox output for counter (m / 128, v, k, 6 << 28 | sample) is set (bit
 // j = bit j mod 32 of word j / 32).
 //
-// Connected components by union-find over a team of threads (one wavefront
-// in the fused step, one workgroup in the per-pair kernel), with a 32-bit
-// parent label per site in LDS, natural site order:
-//   1. each row's q = -1 sites form runs along x0 (periodically); every site
-//      starts pointing at its run's lowest site, the run's root;
+// Connected components by union-find over the runs of q = -1 sites along x0,
+// by a team of threads (one wavefront in the fused step, one workgroup in the
+// per-pair kernel), with a 32-bit parent label per run in LDS, kept at the
+// run's lowest site (natural site order):
+//   1. each row's q = -1 sites form runs along x0 (periodically), found with
+//      bit operations on the row's 64-bit mask; a run is named by its lowest
+//      site (its start, or x0 = 0 for the run that wraps through x0 = L - 1)
+//      and starts as its own root;
 //   2. every pair of runs overlapping along x1 (or x2) is united once, at the
 //      first site of each overlap segment: the two roots are found (following
-//      parents, each step also pointing the site passed at its grandparent)
+//      parents, each step also pointing the run passed at its grandparent)
 //      and the larger is hooked under the smaller with an LDS atomic minimum;
 //      if it had been hooked meanwhile, its new parent's root is united next;
-//   3. every site takes its root, which is then its component's lowest site
-//      (parents only ever point to lower sites of the same component, and
-//      nothing hooks a component's lowest site);
+//   3. every run takes its root, which is then its component's lowest site
+//      (parents only ever point to lower runs of the same component, and
+//      nothing hooks a component's lowest run);
 //   4. the coins of all sites (one Philox call per 128 sites) and, for each
-//      q = -1 site, the coin of its root give the exchanged sites.
+//      run, the coin of its root give the exchanged runs, whose bit masks
+//      make the exchanged colour words.
 // Concurrent finds and hooks only ever replace a parent by a lower ancestor
 // in the same component, so every value read is valid and every find ends.
+// All work is per run, not per site: a row of L sites holds at most L/2 runs.
 #pragma once
 #include "device.h"
 
@@ -49,6 +54,57 @@ __device__ __forceinline__ uint64_t spread_bits(uint32_t x) {
   v = (v | (v << 2)) & 0x3333333333333333ull;
   v = (v | (v << 1)) & 0x5555555555555555ull;
   return v;
+}
+
+// Bits 2b of x (b < 32) moved to bit b (the inverse of spread_bits).
+__device__ __forceinline__ uint32_t compress_even_bits(uint64_t x) {
+  x &= 0x5555555555555555ull;
+  x = (x | (x >> 1)) & 0x3333333333333333ull;
+  x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+  return (uint32_t)x;
+}
+
+// The runs of q = -1 sites of one row (L-bit mask m in x0 order, taken
+// periodically).  starts: bit x0 set iff x0 is q = -1 and x0 - 1 is not;
+// wrap: the start of the run through x0 = L - 1 when that run continues at
+// x0 = 0 (-1 if none).  A row that is q = -1 everywhere has no start and is
+// one run.
+struct RowRuns {
+  uint64_t m, starts;
+  int wrap;
+};
+
+__device__ __forceinline__ RowRuns row_runs(uint64_t m, int L, uint64_t full) {
+  RowRuns r;
+  r.m = m;
+  r.starts = m & ~(((m << 1) | (m >> (L - 1))) & full);
+  r.wrap = (m != full && (m & 1ull) && ((m >> (L - 1)) & 1ull)) ? 63 - __clzll((long long)r.starts)
+                                                                 : -1;
+  return r;
+}
+
+// Name (lowest x0) of the run holding q = -1 site x0.
+__device__ __forceinline__ int run_name(const RowRuns& r, int x0) {
+  const uint64_t le = r.starts & ((2ull << x0) - 1ull);  // x0 = 63: every bit
+  if (!le) return 0;  // no start at or below x0: the wrapping (or whole-row) run
+  const int st = 63 - __clzll((long long)le);
+  return st == r.wrap ? 0 : st;
+}
+
+// Sites of the run starting at `st` (st = r.wrap: the wrapping run).
+__device__ __forceinline__ uint64_t run_mask(const RowRuns& r, int st, int L, uint64_t full) {
+  const uint64_t above = full & ~((1ull << st) - 1ull);  // x0 >= st
+  const uint64_t zeros = ~r.m & above;
+  if (zeros) return above & ((1ull << (__ffsll((long long)zeros) - 1)) - 1ull);
+  uint64_t mask = above;  // runs to x0 = L - 1
+  if (st == r.wrap) {
+    const uint64_t z = ~r.m & full;  // not empty: the row is not all q = -1
+    mask |= (1ull << (__ffsll((long long)z) - 1)) - 1ull;
+  }
+  return mask;
 }
 
 // The q = -1 sites of row R as an L-bit mask in x0 order.
@@ -118,26 +174,21 @@ __device__ __forceinline__ void multi_cluster_words(const Geo& g, const uint32_t
   uint32_t* lab = coin + 4 * nblk;
   const uint64_t full = L == 64 ? ~0ull : ((1ull << L) - 1ull);
 
-  // 1. row masks and run roots; coins
+  // 1. row masks; every run its own root, kept at its lowest site; coins
   for (int R = t; R < NR; R += T) {
     const uint64_t m = row_q_mask(g, Q, R);
     qr[R] = m;
     if (!m) continue;
-    uint32_t* row = lab + R * L;
+    const RowRuns rr = row_runs(m, L, full);
     const uint32_t base = (uint32_t)(R * L);
-    if (m == full) {
-      for (int x0 = 0; x0 < L; ++x0) row[x0] = base;
+    if (!rr.starts) {
+      lab[base] = base;  // the whole row is one run
       continue;
     }
-    // the run through x0 = L - 1 continues at x0 = 0 when both are q = -1;
-    // its lowest site is then x0 = 0
-    const bool wrap = (m & 1ull) && ((m >> (L - 1)) & 1ull);
-    const int last = L - (int)__clzll((long long)~(m << (64 - L)));  // start of the run ending at L-1
-    int start = 0;
-    for (int x0 = 0; x0 < L; ++x0) {
-      if (!((m >> x0) & 1ull)) continue;
-      if (x0 == 0 || !((m >> (x0 - 1)) & 1ull)) start = x0;
-      row[x0] = base + (uint32_t)((wrap && x0 >= last) ? 0 : start);
+    for (uint64_t rest = rr.starts; rest; rest &= rest - 1ull) {
+      const int st = __ffsll((long long)rest) - 1;
+      const uint32_t name = base + (uint32_t)(st == rr.wrap ? 0 : st);
+      lab[name] = name;
     }
   }
   for (int blk = t; blk < nblk; blk += T) {
@@ -154,61 +205,72 @@ __device__ __forceinline__ void multi_cluster_words(const Geo& g, const uint32_t
   for (int R = t; R < NR; R += T) {
     const uint64_t m = qr[R];
     if (!m) continue;
+    const RowRuns rr = row_runs(m, L, full);
     int up[D - 1];
     rows_up(g, R, up);
 #pragma unroll
     for (int j = 0; j < D - 1; ++j) {
-      const uint64_t e = m & qr[up[j]];
+      const uint64_t mu = qr[up[j]];
+      const uint64_t e = m & mu;
       if (!e) continue;
+      const RowRuns ru = row_runs(mu, L, full);
       // first site of each segment (cyclically); a full overlap is one segment
       uint64_t first = e & ~(((e << 1) | (e >> (L - 1))) & full);
       if (e == full) first = 1ull;
       for (; first; first &= first - 1ull) {
         const int x0 = (int)__ffsll((long long)first) - 1;
-        uf_unite(lab, (uint32_t)(R * L + x0), (uint32_t)(up[j] * L + x0));
+        uf_unite(lab, (uint32_t)(R * L + run_name(rr, x0)), (uint32_t)(up[j] * L + run_name(ru, x0)));
       }
     }
   }
   sync();
 
-  // 3. every q = -1 site takes its root (once per run, written to its sites)
+  // 3. every run takes its root
   for (int R = t; R < NR; R += T) {
     const uint64_t m = qr[R];
     if (!m) continue;
-    uint32_t* row = lab + R * L;
-    uint32_t last_root = 0, root = 0;
-    for (int x0 = 0; x0 < L; ++x0) {
-      if (!((m >> x0) & 1ull)) continue;
-      const uint32_t r0 = row[x0];
-      if (x0 == 0 || r0 != last_root) {
-        last_root = r0;
-        root = uf_root(lab, (uint32_t)(R * L + x0));
-      }
-      row[x0] = root;
+    const RowRuns rr = row_runs(m, L, full);
+    const uint32_t base = (uint32_t)(R * L);
+    if (!rr.starts) {
+      lab[base] = uf_root(lab, base);
+      continue;
+    }
+    for (uint64_t rest = rr.starts; rest; rest &= rest - 1ull) {
+      const int st = __ffsll((long long)rest) - 1;
+      const uint32_t name = base + (uint32_t)(st == rr.wrap ? 0 : st);
+      lab[name] = uf_root(lab, name);
     }
   }
   sync();
 
-  // 4. exchanged sites: the q = -1 sites whose root's coin is set
-  for (int i = t; i < 2 * NW; i += T) {
-    const int c = i >= NW ? 1 : 0, w = i - c * NW;
-    const uint32_t qw = Q[i];
-    uint32_t out = 0;
-    if (qw) {
-      const WordNb q = word_nb(g, w);
-      const int p = (c + q.par) & 1;  // x0 parity of colour c in this word's rows
-      for (int f = 0; f < g.P; ++f) {
-        const uint32_t bits = (qw >> (f * g.H)) & g.maskH;
-        if (!bits) continue;
-        const int R = word_row(g, q, f);
-        for (uint32_t rest = bits; rest; rest &= rest - 1u) {
-          const int b = __ffs(rest) - 1;
-          const uint32_t m = lab[R * L + 2 * b + p];
-          if ((coin[m >> 5] >> (m & 31)) & 1u) out |= 1u << (f * g.H + b);
+  // 4. exchanged sites: the runs whose root's coin is set, as colour words
+  for (int w = t; w < NW; w += T) {
+    const WordNb q = word_nb(g, w);
+    uint32_t out[2] = {0u, 0u};
+    for (int f = 0; f < g.P; ++f) {
+      const int R = word_row(g, q, f);
+      const uint64_t m = qr[R];
+      if (!m) continue;
+      const RowRuns rr = row_runs(m, L, full);
+      const uint32_t base = (uint32_t)(R * L);
+      uint64_t X = 0;
+      if (!rr.starts) {
+        const uint32_t root = lab[base];
+        if ((coin[root >> 5] >> (root & 31)) & 1u) X = full;
+      } else {
+        for (uint64_t rest = rr.starts; rest; rest &= rest - 1ull) {
+          const int st = __ffsll((long long)rest) - 1;
+          const uint32_t root = lab[base + (uint32_t)(st == rr.wrap ? 0 : st)];
+          if ((coin[root >> 5] >> (root & 31)) & 1u) X |= run_mask(rr, st, L, full);
         }
       }
+      if (!X) continue;
+      const int p0 = row_parity(g, R);  // colour of the even-x0 sites
+      out[p0] |= compress_even_bits(X) << (f * g.H);
+      out[1 - p0] |= compress_even_bits(X >> 1) << (f * g.H);
     }
-    C[i] = out;
+    C[w] = out[0];
+    C[NW + w] = out[1];
   }
   sync();
 }
