@@ -163,10 +163,10 @@ int pt_init_ex(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
  * pt_sweep, pt_exchange, pt_houdayer, pt_houdayer_multi, pt_measure, pt_mcs
  * (always the per-step kernels), pt_observables (energies per spin in
  * coupling units), pt_get/set_spins, pt_get_maps, pt_get_counters,
- * pt_set_measure_interval and pt_destroy take such jobs; energies and
- * moments are read with pt_get_energies64 and pt_get_moments8; pt_get_energies,
- * pt_get_moments, checkpoints, batches and the server refuse them
- * (PT_EINVAL).  PT_EINVAL also for a coupling off the grid or out of range. */
+ * pt_set_measure_interval, pt_get_state / pt_set_state and pt_destroy take
+ * such jobs; energies and moments are read with pt_get_energies64 and
+ * pt_get_moments8; pt_get_energies, pt_get_moments, batches and the server
+ * refuse them (PT_EINVAL).  PT_EINVAL also for a coupling off the grid or out of range. */
 int pt_init_gauss(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
                   int32_t dim, const float *couplings, const double *betas,
                   uint64_t seed, uint32_t flags);
@@ -396,11 +396,12 @@ int pt_get_stats(pt_job *job, int64_t *out);
  * taken exactly where it is 0 or +-1.  PT_EINVAL as pt_get_modes. */
 int pt_correlation_length(pt_job *job, double *chi0, double *chik, double *xi);
 
-/* Checkpoint: the whole dynamic state (spins, energies, maps, counters,
- * moments, and the replica walk and modes if kept).  With buf == NULL, *len
- * receives the size.  Otherwise *len must
- * hold at least that size.  pt_set_state restores a state taken from a job of
- * identical shape and layout; continuing is bit-identical to never stopping. */
+/* Checkpoint: the whole dynamic state (spins, energies -- 64-bit for
+ * Gaussian jobs --, maps, counters, moments, and the replica walk, modes and
+ * run diagnostics if kept).  With buf == NULL, *len receives the size.
+ * Otherwise *len must hold at least that size.  pt_set_state restores a
+ * state taken from a job of identical shape, layout, coupling kind and kept
+ * extras; continuing is bit-identical to never stopping. */
 int pt_get_state(pt_job *job, void *buf, size_t *len);
 int pt_set_state(pt_job *job, const void *buf, size_t len);
 

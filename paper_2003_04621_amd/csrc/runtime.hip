@@ -1070,7 +1070,9 @@ constexpr uint64_t kStateMagic = 0x50545347'53544154ull;  // "PTSGSTAT"
 size_t state_size(const pt_job* job) {
   const Geo& g = job->g;
   const size_t lat = (size_t)g.S * g.nslot;
-  return sizeof(StateHeader) + job->spin_bytes() + sizeof(int32_t) * lat +
+  // energies: int32 for +-J jobs, int64 (2^-16 units) for Gaussian ones
+  const size_t ebytes = (job->gauss ? sizeof(int64_t) : sizeof(int32_t)) * lat;
+  return sizeof(StateHeader) + job->spin_bytes() + ebytes +
          2 * sizeof(int32_t) * (size_t)g.S * 2 * g.NT + sizeof(DevCounters) +
          sizeof(int64_t) * 8 * (size_t)g.S * g.NT +
          (job->track_walk ? sizeof(int32_t) * 2 * lat + sizeof(uint64_t) * 32 * 3 * (size_t)g.S : 0) +
@@ -1079,13 +1081,13 @@ size_t state_size(const pt_job* job) {
 }
 
 int32_t state_flags(const pt_job* job) {
-  return (job->track_walk ? 1 : 0) | (job->track_modes ? 2 : 0) | (job->track_stats ? 4 : 0);
+  return (job->track_walk ? 1 : 0) | (job->track_modes ? 2 : 0) | (job->track_stats ? 4 : 0) |
+         (job->gauss ? 8 : 0);
 }
 }  // namespace
 
 PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   if (int rc = check_job(job)) return rc;
-  if (job->gauss) return pt_fail(PT_EINVAL, "checkpoints of Gaussian jobs are not supported");
   if (int rc = check_fault(job)) return rc;
   if (!len) return pt_fail(PT_EINVAL, "null length");
   const size_t need = state_size(job);
@@ -1104,8 +1106,10 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
   hipStream_t st = job->stream;
   PT_HIP(job, hipMemcpyAsync(p, job->spins, job->spin_bytes(), hipMemcpyDeviceToHost, st));
   p += job->spin_bytes();
-  PT_HIP(job, hipMemcpyAsync(p, job->E, sizeof(int32_t) * lat, hipMemcpyDeviceToHost, st));
-  p += sizeof(int32_t) * lat;
+  const size_t ebytes = (job->gauss ? sizeof(int64_t) : sizeof(int32_t)) * lat;
+  const void* Esrc = job->gauss ? (const void*)job->E64 : (const void*)job->E;
+  PT_HIP(job, hipMemcpyAsync(p, Esrc, ebytes, hipMemcpyDeviceToHost, st));
+  p += ebytes;
   PT_HIP(job, hipMemcpyAsync(p, job->sot, maps, hipMemcpyDeviceToHost, st));
   p += maps;
   PT_HIP(job, hipMemcpyAsync(p, job->tos, maps, hipMemcpyDeviceToHost, st));
@@ -1137,7 +1141,6 @@ PT_API int pt_get_state(pt_job* job, void* buf, size_t* len) {
 
 PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
   if (int rc = check_job(job)) return rc;
-  if (job->gauss) return pt_fail(PT_EINVAL, "checkpoints of Gaussian jobs are not supported");
   if (!buf) return pt_fail(PT_EINVAL, "null state buffer");
   if (len != state_size(job)) return pt_fail(PT_EINVAL, "state size does not match this job");
   const Geo& g = job->g;
@@ -1152,8 +1155,10 @@ PT_API int pt_set_state(pt_job* job, const void* buf, size_t len) {
   hipStream_t st = job->stream;
   PT_HIP(job, hipMemcpyAsync(job->spins, p, job->spin_bytes(), hipMemcpyHostToDevice, st));
   p += job->spin_bytes();
-  PT_HIP(job, hipMemcpyAsync(job->E, p, sizeof(int32_t) * lat, hipMemcpyHostToDevice, st));
-  p += sizeof(int32_t) * lat;
+  const size_t ebytes = (job->gauss ? sizeof(int64_t) : sizeof(int32_t)) * lat;
+  void* Edst = job->gauss ? (void*)job->E64 : (void*)job->E;
+  PT_HIP(job, hipMemcpyAsync(Edst, p, ebytes, hipMemcpyHostToDevice, st));
+  p += ebytes;
   PT_HIP(job, hipMemcpyAsync(job->sot, p, maps, hipMemcpyHostToDevice, st));
   p += maps;
   PT_HIP(job, hipMemcpyAsync(job->tos, p, maps, hipMemcpyHostToDevice, st));

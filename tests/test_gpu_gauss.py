@@ -177,11 +177,39 @@ def test_gauss_set_spins_and_symmetry(pt):
     matches(pt, job, ref, "after set_spins")
 
 
+def test_gauss_checkpoint_resume(pt):
+    """Checkpoint after n steps, keep going, restore and redo: the continuation
+    is bit-identical (spins, 64-bit energies, maps, counters, moments), and the
+    oracle run for 2n steps agrees; a +-J job's state is refused."""
+    d, L, S, NT = 2, 16, 2, 4
+    job, ref = make(pt, d, L, S, NT, 0, 9)
+    pt.pt_mcs(job, 6, houdayer=True, measure=True)
+    state = pt.pt_get_state(job)
+    pt.pt_mcs(job, 5, houdayer=True, measure=True, multi=True)
+    after = (pt.pt_get_spins(job), pt.pt_get_energies64(job), pt.pt_get_moments8(job),
+             pt.pt_get_counters(job))
+    pt.pt_set_state(job, state)
+    pt.pt_mcs(job, 5, houdayer=True, measure=True, multi=True)
+    again = (pt.pt_get_spins(job), pt.pt_get_energies64(job), pt.pt_get_moments8(job),
+             pt.pt_get_counters(job))
+    for x, y in zip(after[:3], again[:3]):
+        assert (x == y).all()
+    assert after[3] == again[3]
+    ref.mcs(6, houdayer=True, measure=True)
+    ref.mcs(5, houdayer=True, measure=True, multi=True)
+    matches(pt, job, ref, "restored and continued")
+    other = pt.pt_init(S, NT, L, d, W.couplings_pm_j(S, L, d, 3), W.geometric_betas(0.5, 1.0, NT), 1)
+    with pytest.raises(pt.PTError):
+        pt.pt_set_state(other, state)
+    pt.pt_destroy(other)
+    pt.pt_destroy(job)
+
+
 def test_gauss_refusals(pt):
     d, L, S, NT = 2, 8, 1, 3
     job, _ = make(pt, d, L, S, NT, 0, 1)
     for fn in (lambda: pt.pt_get_energies(job), lambda: pt.pt_get_moments(job),
-               lambda: pt.pt_get_state(job), lambda: pt.pt_batch_create([job])):
+               lambda: pt.pt_batch_create([job])):
         with pytest.raises(pt.PTError):
             fn()
     Jf = W.couplings_gauss(S, L, d, 1)
