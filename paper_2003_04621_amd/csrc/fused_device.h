@@ -854,8 +854,8 @@ __device__ __forceinline__ void sweep_resident_shape(const Geo& g, const FusedAr
 
 // The sweep with the geometry of the shapes the workloads run most folded to
 // compile-time constants (3D L = 16, 2D L = 64; for split samples, which run
-// one workgroup per CU whatever their registers, also 3D L = 32 and 48), else
-// from g.
+// one workgroup per CU whatever their registers, also 3D L = 24, 32 and 48),
+// else from g.
 template <int D, bool kSplitShapes = false>
 __device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_t* J, uint32_t* W,
                                                int32_t* El, const int32_t* tosl,
@@ -875,6 +875,11 @@ __device__ __forceinline__ void sweep_resident(const FusedArgs& A, const uint32_
     }
     if (A.g.L == 48) {
       sweep_resident_shape<3, 48>(fixed_shape<3, 48>(A.g), A, J, W, El, tosl, thrl, slot0, nres,
+                                  s, t);
+      return;
+    }
+    if (A.g.L == 24) {
+      sweep_resident_shape<3, 24>(fixed_shape<3, 24>(A.g), A, J, W, El, tosl, thrl, slot0, nres,
                                   s, t);
       return;
     }
@@ -1063,16 +1068,19 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
   for (int k = part + tid * A.parts; k < NT; k += T * A.parts) qneg[k] = 0;
   __syncthreads();
-  // all owned temperatures' words in one flat loop, so that many loads are in
-  // flight at once
-  const int nk = (NT - part + A.parts - 1) / A.parts, total = nk * W2;
-#pragma unroll 4
-  for (int idx = tid; idx < total; idx += T) {
-    const int kl = idx / W2, i = idx - kl * W2;
+  // each thread sums the differing sites of its words of one owned
+  // temperature, the wavefront adds the lanes' sums (one LDS atomic per
+  // wavefront and temperature instead of one per word)
+  const int nk = (NT - part + A.parts - 1) / A.parts;
+  for (int kl = 0; kl < nk; ++kl) {
     const int k = part + kl * A.parts;
-    const uint32_t a = pub[(size_t)sotl[k] * W2 + i], b = pub[(size_t)(NT + sotl[NT + k]) * W2 + i];
-    const int neg = __popc(a ^ b);
-    if (neg) atomicAdd(&qneg[k], neg);
+    const uint32_t* pa = pub + (size_t)sotl[k] * W2;
+    const uint32_t* pb = pub + (size_t)(NT + sotl[NT + k]) * W2;
+    int neg = 0;
+#pragma unroll 4
+    for (int i = tid; i < W2; i += T) neg += __popc(pa[i] ^ pb[i]);
+    neg = wave_total(neg);
+    if ((tid & 63) == 0 && neg) atomicAdd(&qneg[k], neg);
   }
   __syncthreads();
   for (int k = part + tid * A.parts; k < NT; k += T * A.parts)
