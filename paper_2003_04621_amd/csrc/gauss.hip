@@ -199,38 +199,55 @@ __global__ void __launch_bounds__(512) k_gsweep(Geo g, void* spins, const int4* 
     for (int c = 0; c < 2; ++c) {
       const int4* Jc = Js + (size_t)c * (2 * D + 1) * NGc;
       const uint32_t c1 = 2u * (t0 + (uint32_t)rep) + (uint32_t)c;
-      for (int gi = t; gi < NGc; gi += T) {
+      // every lane runs every round of the group loop (lanes past the last
+      // group idle), so that the wavefront can add its lanes' energy changes
+      // before one 64-bit LDS atomic (|sum| < 64 x 4 x 2 x 6 x 2^19 < 2^31)
+      for (int gi0 = 0; gi0 < NGc; gi0 += T) {
+        const int gi = gi0 + t;
+        const bool valid = gi < NGc;
         int4 m[2 * D];
+        int4 hs = make_int4(0, 0, 0, 0);
+        GroupPos gp{};
+        WordNb nb{};
+        int p = 0;
+        uint32_t c0 = 0;
+        if (valid) {
 #pragma unroll
-        for (int k = 0; k < 2 * D; ++k) m[k] = Jc[(size_t)k * NGc + gi];
-        const int4 hs = Jc[(size_t)2 * D * NGc + gi];
-        const GroupPos gp = group_pos(g, gi);
-        const WordNb nb = word_nb(g, gp.w);
-        const int p = (c + nb.par) & 1;
-        const uint32_t c0 = (uint32_t)word_row(g, nb, gp.f) * (uint32_t)g.G + (uint32_t)gp.q;
+          for (int k = 0; k < 2 * D; ++k) m[k] = Jc[(size_t)k * NGc + gi];
+          hs = Jc[(size_t)2 * D * NGc + gi];
+          gp = group_pos(g, gi);
+          nb = word_nb(g, gp.w);
+          p = (c + nb.par) & 1;
+          c0 = (uint32_t)word_row(g, nb, gp.f) * (uint32_t)g.G + (uint32_t)gp.q;
+        }
         for (int l = 0; l < nl; ++l) {
-          uint32_t* Wl = W + (size_t)l * 2 * NW;
-          const uint32_t Wc = Wl[c * NW + gp.w];
-          uint32_t n[2 * D], a[2 * D];
-          neighbour_words<D>(g, Wl + (1 - c) * NW, gp.w, nb, p, n);
-#pragma unroll
-          for (int k = 0; k < 2 * D; ++k) a[k] = (Wc ^ n[k]) >> gp.shift;
-          int x[4];
-          group_fields<D>(a, m, hs, x);
-          const uint32_t slot = (uint32_t)(set * g.NT + j0 + l);
-          const Ctr4 r = philox10(Ctr4{c0, c1, slot, c3}, g.key0, g.key1);
-          uint32_t F = 0;
           int dE = 0;
-          for (int j = 0; j < gp.nv; ++j) {
-            const int xj = x[j];
-            const bool flip = xj <= 0 || gauss_accept_metro(word_of(r, j), czl[l], bl[l], 2u * (uint32_t)xj);
-            if (flip) {
-              F |= 1u << j;
-              dE += 2 * xj;
+          if (valid) {
+            uint32_t* Wl = W + (size_t)l * 2 * NW;
+            const uint32_t Wc = Wl[c * NW + gp.w];
+            uint32_t n[2 * D], a[2 * D];
+            neighbour_words<D>(g, Wl + (1 - c) * NW, gp.w, nb, p, n);
+#pragma unroll
+            for (int k = 0; k < 2 * D; ++k) a[k] = (Wc ^ n[k]) >> gp.shift;
+            int x[4];
+            group_fields<D>(a, m, hs, x);
+            const uint32_t slot = (uint32_t)(set * g.NT + j0 + l);
+            const Ctr4 r = philox10(Ctr4{c0, c1, slot, c3}, g.key0, g.key1);
+            uint32_t F = 0;
+            for (int j = 0; j < gp.nv; ++j) {
+              const int xj = x[j];
+              const bool flip =
+                  xj <= 0 || gauss_accept_metro(word_of(r, j), czl[l], bl[l], 2u * (uint32_t)xj);
+              if (flip) {
+                F |= 1u << j;
+                dE += 2 * xj;
+              }
             }
+            if (F) atomicXor(&Wl[c * NW + gp.w], F << gp.shift);
           }
-          if (F) atomicXor(&Wl[c * NW + gp.w], F << gp.shift);
-          if (dE) atomicAdd(&El[l], (unsigned long long)(int64_t)dE);
+#pragma unroll
+          for (int o = 32; o >= 1; o >>= 1) dE += __shfl_xor(dE, o, 64);
+          if ((t & 63) == 0 && dE) atomicAdd(&El[l], (unsigned long long)(int64_t)dE);
         }
       }
       __syncthreads();
