@@ -174,3 +174,36 @@ def test_multicluster_served_matches_oracle(pt):
         _, rdis, rn = ref.observables()
         assert out[n]["status"] == 0 and out[n]["n_meas"] == rn
         np.testing.assert_allclose(out[n]["disorder"], rdis, rtol=1e-12, atol=0)
+
+
+def test_full_size_2d_l64_multicluster_sampled(pt):
+    """The benchmark's multi-cluster workload at full size (2D L = 64, 500
+    samples x 2 x 24 temperatures, fused launch), a few Monte Carlo steps with
+    multi-cluster moves and measurements; sampled samples re-run by the
+    oracle under their own sample keys, and the run diagnostics of a sampled
+    job with PT_TRACK_STATS (per-step kernels) against the oracle's."""
+    wl = W.workload("2d_l64")
+    say(f"case {wl.name} multi-cluster S={wl.samples} NT={wl.replicas} L={wl.L}")
+    J = wl.couplings()
+    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, J, wl.betas, wl.seed)
+    assert pt.pt_get_plan(job, houdayer=True, measure=True, multi=True)["mode"] == 1
+    pt.pt_mcs(job, 5, houdayer=True, measure=True, multi=True)
+    picks = [0, 211, wl.samples - 1]
+    ref = oracle.OracleJob(len(picks), wl.replicas, wl.L, wl.dim, J[picks], wl.betas, wl.seed,
+                           sample_keys=picks)
+    ref.mcs(5, houdayer=True, measure=True, multi=True)
+    assert (pt.pt_get_spins(job)[picks] == ref.spins()).all()
+    assert (pt.pt_get_energies(job)[picks] == ref.energies()).all()
+    for a, b in zip(pt.pt_get_maps(job), ref.maps()):
+        assert (a[picks] == b).all()
+    mom, rmom = pt.pt_get_moments(job), ref.moments()
+    for key in rmom:
+        assert (np.asarray(mom[key])[picks] == np.asarray(rmom[key])).all(), key
+    pt.pt_destroy(job)
+    # the same first steps of the sampled samples with the diagnostics kept
+    sj = pt.pt_init(len(picks), wl.replicas, wl.L, wl.dim, J[picks], wl.betas, wl.seed, stats=True)
+    ref2 = oracle.OracleJob(len(picks), wl.replicas, wl.L, wl.dim, J[picks], wl.betas, wl.seed)
+    pt.pt_mcs(sj, 3, houdayer=True, measure=True, multi=True)
+    ref2.mcs(3, houdayer=True, measure=True, multi=True)
+    assert (pt.pt_get_stats(sj) == ref2.stats()).all()
+    pt.pt_destroy(sj)
