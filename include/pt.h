@@ -465,7 +465,11 @@ int pt_batch_destroy(pt_batch *b);
  * disorder-averaged observables are kept for pt_server_poll and its memory is
  * released.  Job set-up and read-out overlap the running round on a stream of
  * their own; device memory comes from a stream-ordered pool owned by the
- * server (not the allocator hooks) and returns to it when a job finishes. */
+ * server (not the allocator hooks) and returns to it when a job finishes.
+ * Admitted requests (their bytes counted against the budget from then on)
+ * get their jobs created oldest first while the round in flight still runs,
+ * at least one per round (an idle server starts its first round after 5 ms of
+ * set-up); the others join later rounds. */
 int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server **out);
 /* A round gives each job up to steps_per_round steps; when every work item of
  * the round has a workgroup of its own, jobs whose items are smaller than the
@@ -486,13 +490,14 @@ int pt_server_poll_ex(pt_server *s, uint64_t ticket, pt_result *out, double *dis
                       double *correlation);
 /* out[11] = {attempted flips completed, busy seconds, rounds, admitted,
  *            completed, peak admitted bytes, peak concurrent jobs, uptime s,
- *            queue depth (requests waiting for admission), jobs in the
- *            current round, cancelled requests} */
+ *            queue depth (requests waiting for admission or for their
+ *            job to be created), jobs in the current round, cancelled
+ *            requests} */
 int pt_server_stats(pt_server *s, double *out);
 /* Cancels a request, leaving every other request's work and result as if it
  * had never been submitted (each job's result depends only on its own
- * request).  A queued request is dropped at once; a running one ends at the
- * next round boundary (unless it completes its steps first, in which case its
+ * request).  A queued request is dropped at once; an admitted one ends at
+ * the next round boundary (unless it completes its steps first, in which case its
  * normal result stands) and its device memory returns to the budget.  The
  * cancelled request's pt_server_poll result has status PT_ECANCELED and no
  * observables.  Returns PT_OK when the cancellation is recorded, 1 if the

@@ -8,8 +8,11 @@
 // its burn-in.  While a round runs on the GPU, the worker thread reads out
 // and releases the jobs that finished in the previous round and creates the
 // newly admitted ones on a third stream, from a stream-ordered memory pool,
-// so that job set-up and tear-down overlap the rounds.  Results depend only
-// on the request, never on what else ran beside it.
+// so that job set-up and tear-down overlap the rounds.  Admitted requests get
+// their jobs created only while the round in flight still runs (the rest
+// wait, their memory reserved, for the next round), so that a large admission
+// never holds the GPU idle between rounds.  Results depend only on
+// the request, never on what else ran beside it.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -88,6 +91,7 @@ struct pt_server {
   std::unordered_set<uint64_t> live;    // admitted requests not finished yet
   std::unordered_set<uint64_t> cancel;  // live requests to end between rounds
   size_t n_active = 0;                  // jobs of the current round
+  size_t n_staged = 0;                  // admitted, memory reserved, job not created yet
   uint64_t next_ticket = 1;
   bool stopping = false;
   std::thread worker;
@@ -174,9 +178,9 @@ void fail_request(pt_server* sv, const Request& r, int status) {
   sv->cv_done.notify_all();
 }
 
-// Takes queued requests in arrival order while the budget holds.
-std::vector<Request> take_admissions(pt_server* sv) {
-  std::vector<Request> admit;
+// Moves queued requests to `staged` in arrival order while the budget holds
+// (their memory is reserved from then on).
+void take_admissions(pt_server* sv, std::deque<Request>& staged) {
   std::lock_guard<std::mutex> lk(sv->mu);
   size_t used = sv->used;
   while (!sv->pending.empty()) {
@@ -190,20 +194,39 @@ std::vector<Request> take_admissions(pt_server* sv) {
     if (used + need > sv->budget) break;
     used += need;
     sv->live.insert(r.ticket);
-    admit.push_back(std::move(r));
+    staged.push_back(std::move(r));
     sv->pending.pop_front();
   }
   sv->used = used;
+  sv->n_staged = staged.size();
   if (used > sv->peak_used) sv->peak_used = used;
-  return admit;
 }
 
-// Creates the admitted jobs on st_admit (they join the next round).
-void create_jobs(pt_server* sv, std::vector<Request>& admit, std::vector<Active>& ready) {
-  for (Request& r : admit) {
+// Creates admitted jobs on st_admit (they join the next round), oldest
+// first, while `staged` is not empty and more() holds; at least one job is
+// created per call.  A staged request cancelled meanwhile ends here without a
+// job.
+template <class More>
+void create_jobs(pt_server* sv, std::deque<Request>& staged, std::vector<Active>& ready, More more) {
+  bool first = true;
+  while (!staged.empty() && (first || more())) {
+    first = false;
+    Request r = std::move(staged.front());
+    staged.pop_front();
     Active a;
     a.bytes = job_device_bytes(r.S, r.NT, r.L, r.dim, (int)r.layout, r.betas.data());
     a.t_admit = sv->now();
+    bool gone;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->n_staged = staged.size();
+      gone = sv->cancel.erase(r.ticket) > 0;
+    }
+    if (gone) {
+      a.req = std::move(r);
+      finish(sv, a, PT_ECANCELED);
+      continue;
+    }
     const int rc = job_create(&a.job, r.S, r.NT, r.L, r.dim, r.J.data(), r.betas.data(), r.seed,
                               r.layout, pool_alloc, pool_free, sv, sv->st_admit);
     a.req = std::move(r);
@@ -222,16 +245,29 @@ void create_jobs(pt_server* sv, std::vector<Request>& admit, std::vector<Active>
   }
 }
 
+// Job creation time allowed before the first round of an idle server.
+constexpr double kFirstFill = 0.005;
+
+// Whether work of the round in flight is still queued or running.
+bool round_running(const pt_server* sv) {
+  for (hipStream_t st : {sv->st_main, sv->st_two, sv->st_side})
+    if (hipStreamQuery(st) == hipErrorNotReady) return true;
+  return false;
+}
+
 void serve(pt_server* sv) {
   (void)hipSetDevice(sv->device);
-  std::vector<Active> done;  // finished in the last round, not yet read out
+  std::vector<Active> done;    // finished in the last round, not yet read out
+  std::deque<Request> staged;  // admitted, memory reserved, job not created yet
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       sv->cv.wait(lk, [&] {
-        return sv->stopping || !sv->pending.empty() || !sv->active.empty() || !done.empty();
+        return sv->stopping || !sv->pending.empty() || !sv->active.empty() || !done.empty() ||
+               !staged.empty();
       });
-      if (sv->stopping && sv->pending.empty() && sv->active.empty() && done.empty()) break;
+      if (sv->stopping && sv->pending.empty() && sv->active.empty() && done.empty() && staged.empty())
+        break;
     }
     {
       // cancelled running jobs end here, between rounds (nothing of theirs is
@@ -245,16 +281,33 @@ void serve(pt_server* sv) {
           else
             keep.push_back(std::move(a));
         }
+        // admitted requests whose jobs were not created yet end without one
+        for (auto it = staged.begin(); it != staged.end();) {
+          if (sv->cancel.erase(it->ticket)) {
+            Active a;
+            a.bytes = job_device_bytes(it->S, it->NT, it->L, it->dim, (int)it->layout, it->betas.data());
+            a.t_admit = sv->now();
+            a.req = std::move(*it);
+            gone.push_back(std::move(a));
+            it = staged.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        sv->n_staged = staged.size();
       }
       sv->active.swap(keep);
       for (Active& a : gone) finish(sv, a, PT_ECANCELED);
     }
     if (sv->active.empty()) {
-      // nothing on the GPU: read out, then admit, before the first round
+      // nothing on the GPU: read out, then admit, and start a round with the
+      // jobs created within a few milliseconds; the other admitted requests
+      // are created while it runs
       for (Active& a : done) finish(sv, a, PT_OK);
       done.clear();
-      std::vector<Request> admit = take_admissions(sv);
-      create_jobs(sv, admit, sv->active);
+      take_admissions(sv, staged);
+      const double until = sv->now() + kFirstFill;
+      create_jobs(sv, staged, sv->active, [&] { return sv->now() < until; });
       if (sv->active.empty()) continue;
     }
     {
@@ -334,8 +387,8 @@ void serve(pt_server* sv) {
     done.clear();
     std::vector<Active> ready;
     if (rc == PT_OK) {
-      std::vector<Request> admit = take_admissions(sv);
-      create_jobs(sv, admit, ready);
+      take_admissions(sv, staged);
+      create_jobs(sv, staged, ready, [&] { return round_running(sv); });
     }
 
     if (rc == PT_OK && hipStreamSynchronize(sv->st_main) != hipSuccess) rc = PT_EDEVICE;
@@ -540,7 +593,7 @@ PT_API int pt_server_stats(pt_server* sv, double* out) {
   out[5] = (double)sv->peak_used;
   out[6] = (double)sv->max_active;
   out[7] = sv->now();
-  out[8] = (double)sv->pending.size();
+  out[8] = (double)(sv->pending.size() + sv->n_staged);
   out[9] = (double)sv->n_active;
   out[10] = (double)sv->cancelled;
   return PT_OK;
