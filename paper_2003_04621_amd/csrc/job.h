@@ -145,7 +145,13 @@ size_t job_device_bytes(int S, int NT, int L, int d, int flags, const double* be
 // Length of a row of the exchange threshold table.
 int pt_table_len(const double* betas, int NT, int d, long N);
 // pt_init_ex with explicit allocation hooks (NULL: hipMalloc / hipFree).
+// With `stage` set, the host data of the set-up (couplings, tables, maps) is
+// first copied to host memory from stage(bytes, ctx), which must be pinned and
+// stay unchanged until the work queued on `stream` is done, and the function
+// returns once that work is queued: the caller orders every later use of the
+// job after it (an event on `stream`).  Without it, it returns after the
+// set-up has completed.
 int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
                const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags,
                void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx,
-               hipStream_t stream);
+               hipStream_t stream, void* (*stage)(size_t, void*) = nullptr);

@@ -193,7 +193,7 @@ PT_API int pt_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, 
 int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32_t dim,
                const int8_t* couplings, const double* betas, uint64_t seed, uint32_t flags,
                void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx,
-               hipStream_t stream) {
+               hipStream_t stream, void* (*stage)(size_t, void*)) {
   g_err.clear();
   if (!out || !couplings || !betas) return pt_fail(PT_EINVAL, "null pointer argument");
   if (dim != 2 && dim != 3) return pt_fail(PT_EINVAL, "dim must be 2 or 3");
@@ -290,12 +290,34 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   auto step = [&](hipError_t r) {
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
-  step(hipMemcpyAsync(J8, couplings, (size_t)ncoup, hipMemcpyHostToDevice, st));
-  step(hipMemcpyAsync(job->thr, thr.data(), sizeof(uint32_t) * thr.size(), hipMemcpyHostToDevice, st));
-  step(hipMemcpyAsync(job->thrpt, thrpt.data(), sizeof(uint32_t) * thrpt.size(), hipMemcpyHostToDevice,
+  // the copies' sources: the caller's and these vectors (the call then waits
+  // for the set-up below), or pinned staging copies of them
+  const void* src_J = couplings;
+  const void* src_thr = thr.data();
+  const void* src_thrpt = thrpt.data();
+  const void* src_ident = ident.data();
+  if (stage) {
+    auto put = [&](const void* from, size_t bytes) -> const void* {
+      void* to = stage(bytes, ctx);
+      if (to) std::memcpy(to, from, bytes);
+      return to;
+    };
+    src_J = put(couplings, (size_t)ncoup);
+    src_thr = put(thr.data(), sizeof(uint32_t) * thr.size());
+    src_thrpt = put(thrpt.data(), sizeof(uint32_t) * thrpt.size());
+    src_ident = put(ident.data(), maps);
+    if (!src_J || !src_thr || !src_thrpt || !src_ident) {
+      job->release();
+      delete job;
+      return pt_fail(PT_ENOMEM, "pinned staging allocation failed");
+    }
+  }
+  step(hipMemcpyAsync(J8, src_J, (size_t)ncoup, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->thr, src_thr, sizeof(uint32_t) * thr.size(), hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->thrpt, src_thrpt, sizeof(uint32_t) * thrpt.size(), hipMemcpyHostToDevice,
                       st));
-  step(hipMemcpyAsync(job->sot, ident.data(), maps, hipMemcpyHostToDevice, st));
-  step(hipMemcpyAsync(job->tos, ident.data(), maps, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->sot, src_ident, maps, hipMemcpyHostToDevice, st));
+  step(hipMemcpyAsync(job->tos, src_ident, maps, hipMemcpyHostToDevice, st));
   step(hipMemsetAsync(job->ctr, 0, sizeof(DevCounters), st));
   step(hipMemsetAsync(job->mom, 0, sizeof(int64_t) * 8 * (size_t)samples * replicas, st));
   if (job->track_modes) step(hipMemsetAsync(job->modes, 0, sizeof(int64_t) * mode_words, st));
@@ -308,7 +330,7 @@ int job_create(pt_job** out, int32_t samples, int32_t replicas, int32_t L, int32
   step(launch_pack_couplings(g, J8, job->jw, st));
   step(launch_init_spins(g, job->spins, st));
   step(launch_energy(g, job->spins, job->jw, job->E, st));
-  step(hipStreamSynchronize(st));
+  if (!stage) step(hipStreamSynchronize(st));
   if (e != hipSuccess) {
     std::string msg = std::string("pt_init: ") + hipGetErrorString(e);
     job->release();

@@ -82,6 +82,12 @@ struct pt_server {
   // tear-down
   hipStream_t st_main = nullptr, st_two = nullptr, st_side = nullptr, st_admit = nullptr;
   hipMemPool_t pool = nullptr;  // device memory of the jobs
+  // Pinned host blocks the set-up copies of the jobs created during one round
+  // read from (bump-allocated; reused once that set-up has completed, which
+  // admit_ev marks), and the event every stream of the next round waits for.
+  std::vector<std::pair<char*, size_t>> stage_blocks;
+  size_t stage_block = 0, stage_used = 0;
+  hipEvent_t admit_ev = nullptr;
   pt_batch* batch[2] = {nullptr, nullptr};  // 2D and 3D jobs
   std::mutex mu;
   std::condition_variable cv, cv_done;
@@ -124,6 +130,30 @@ void* pool_alloc(size_t bytes, void* ctx) {
 void pool_free(void* p, void* ctx) {
   pt_server* sv = static_cast<pt_server*>(ctx);
   (void)hipFreeAsync(p, sv->st_admit);
+}
+
+// Pinned host memory for one job's set-up copies (see stage_blocks).
+void* stage_take(size_t bytes, void* ctx) {
+  pt_server* sv = static_cast<pt_server*>(ctx);
+  bytes = (bytes + 255) & ~(size_t)255;
+  while (sv->stage_block < sv->stage_blocks.size() &&
+         sv->stage_used + bytes > sv->stage_blocks[sv->stage_block].second) {
+    ++sv->stage_block;
+    sv->stage_used = 0;
+  }
+  if (sv->stage_block == sv->stage_blocks.size()) {
+    const size_t cap = bytes > ((size_t)8 << 20) ? bytes : ((size_t)8 << 20);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    sv->stage_blocks.push_back({static_cast<char*>(p), cap});
+    sv->stage_used = 0;
+  }
+  char* p = sv->stage_blocks[sv->stage_block].first + sv->stage_used;
+  sv->stage_used += bytes;
+  return p;
 }
 
 void finish(pt_server* sv, Active& a, int status) {
@@ -208,6 +238,12 @@ void take_admissions(pt_server* sv, std::deque<Request>& staged) {
 // job.
 template <class More>
 void create_jobs(pt_server* sv, std::deque<Request>& staged, std::vector<Active>& ready, More more) {
+  if (staged.empty()) return;
+  // the set-up queued by the last call has completed before the round that
+  // is now running started (it waited for admit_ev): its staging is free
+  (void)hipEventSynchronize(sv->admit_ev);
+  sv->stage_block = 0;
+  sv->stage_used = 0;
   bool first = true;
   while (!staged.empty() && (first || more())) {
     first = false;
@@ -228,7 +264,7 @@ void create_jobs(pt_server* sv, std::deque<Request>& staged, std::vector<Active>
       continue;
     }
     const int rc = job_create(&a.job, r.S, r.NT, r.L, r.dim, r.J.data(), r.betas.data(), r.seed,
-                              r.layout, pool_alloc, pool_free, sv, sv->st_admit);
+                              r.layout, pool_alloc, pool_free, sv, sv->st_admit, stage_take);
     a.req = std::move(r);
     a.req.J.clear();
     a.req.J.shrink_to_fit();
@@ -243,6 +279,15 @@ void create_jobs(pt_server* sv, std::deque<Request>& staged, std::vector<Active>
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->admitted += 1;
   }
+  (void)hipEventRecord(sv->admit_ev, sv->st_admit);
+}
+
+// Orders the next round's streams after the set-up of the jobs created so far.
+hipError_t wait_admitted(pt_server* sv) {
+  hipError_t e = hipSuccess;
+  for (hipStream_t st : {sv->st_main, sv->st_two, sv->st_side})
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, sv->admit_ev, 0);
+  return e;
 }
 
 // Job creation time allowed before the first round of an idle server.
@@ -370,7 +415,7 @@ void serve(pt_server* sv) {
         side.push_back(i);
       }
     }
-    int rc = PT_OK;
+    int rc = wait_admitted(sv) == hipSuccess ? PT_OK : PT_EDEVICE;
     for (int b = 0; b < 2 && rc == PT_OK; ++b)
       rc = batch_round(sv->batch[b], res_jobs[b], res_steps[b], res_flags[b]);
     for (size_t i : side) {
@@ -394,6 +439,10 @@ void serve(pt_server* sv) {
     if (rc == PT_OK && hipStreamSynchronize(sv->st_main) != hipSuccess) rc = PT_EDEVICE;
     if (rc == PT_OK && hipStreamSynchronize(sv->st_two) != hipSuccess) rc = PT_EDEVICE;
     if (rc == PT_OK && hipStreamSynchronize(sv->st_side) != hipSuccess) rc = PT_EDEVICE;
+    // the set-up queued during this round runs once the round has freed the
+    // CUs; a failure of it shows here or at the next round's sync
+    const hipError_t qa = hipStreamQuery(sv->st_admit);
+    if (rc == PT_OK && qa != hipSuccess && qa != hipErrorNotReady) rc = PT_EDEVICE;
     {
       std::lock_guard<std::mutex> lk(sv->mu);
       sv->busy += sv->now() - t_round;
@@ -450,6 +499,7 @@ PT_API int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server
       hipStreamCreateWithFlags(&sv->st_two, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&sv->st_side, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&sv->st_admit, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&sv->admit_ev, hipEventDisableTiming) != hipSuccess ||
       hipMemPoolCreate(&sv->pool, &props) != hipSuccess ||
       hipMemPoolSetAttribute(sv->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
     (void)hipGetLastError();
@@ -457,6 +507,7 @@ PT_API int pt_server_start(size_t hbm_budget, int32_t steps_per_round, pt_server
     if (sv->st_two) (void)hipStreamDestroy(sv->st_two);
     if (sv->st_side) (void)hipStreamDestroy(sv->st_side);
     if (sv->st_admit) (void)hipStreamDestroy(sv->st_admit);
+    if (sv->admit_ev) (void)hipEventDestroy(sv->admit_ev);
     if (sv->pool) (void)hipMemPoolDestroy(sv->pool);
     delete sv;
     return pt_fail(PT_EDEVICE, "pt_server_start: stream or memory pool creation failed");
@@ -610,6 +661,8 @@ PT_API int pt_server_stop(pt_server* sv) {
   batch_free(sv->batch[0]);
   batch_free(sv->batch[1]);
   (void)hipStreamSynchronize(sv->st_admit);
+  for (auto& blk : sv->stage_blocks) (void)hipHostFree(blk.first);
+  (void)hipEventDestroy(sv->admit_ev);
   (void)hipStreamDestroy(sv->st_main);
   (void)hipStreamDestroy(sv->st_two);
   (void)hipStreamDestroy(sv->st_side);
