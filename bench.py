@@ -441,8 +441,8 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-burst", type=int, default=300, help="requests of the capacity burst")
-    ap.add_argument("--serve-budget", type=int, default=512, help="MiB")
+    ap.add_argument("--serve-burst", type=int, default=900, help="requests of the capacity burst")
+    ap.add_argument("--serve-budget", type=int, default=2048, help="MiB")
     ap.add_argument("--serve-round", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-seed", type=int, default=31)
