@@ -592,4 +592,33 @@ __device__ __forceinline__ void store_lattice(const Geo& g, void* spins, size_t 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cross-lane moves within a wavefront (DPP).
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_ones(uint32_t x) {  // lanes without a source: ~0
+  return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_zero(uint32_t x) {  // lanes without a source: 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, ROWS == 0xF);
+}
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
+constexpr int kBcast15 = 0x142, kBcast31 = 0x143;  // to rows 1, 3 / rows 2, 3
+constexpr int kWaveRol1 = 0x134, kWaveRor1 = 0x13C;  // lane i takes lane i + 1 / i - 1 (mod 64)
+
+// Sum over the wavefront as a wavefront constant, by DPP: row prefix sums,
+// then the broadcasts of lanes 15 and 31 carry them on, so that lane 63 ends
+// with the total (no LDS round trips).
+__device__ __forceinline__ int wave_total(int v) {
+  v += (int)dpp_zero<kRowShr1>((uint32_t)v);
+  v += (int)dpp_zero<kRowShr2>((uint32_t)v);
+  v += (int)dpp_zero<kRowShr4>((uint32_t)v);
+  v += (int)dpp_zero<kRowShr8>((uint32_t)v);
+  v += (int)dpp_zero<kBcast15, 0xA>((uint32_t)v);
+  v += (int)dpp_zero<kBcast31, 0xC>((uint32_t)v);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 }  // namespace ptsg

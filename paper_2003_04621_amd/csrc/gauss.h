@@ -135,14 +135,19 @@ __device__ inline bool gauss_accept_d(uint32_t r, double b, int64_t u) {
 // (v_exp_f32) is within 2^-18 of the true one; a word outside a 2^-15 band
 // around it is decided here, the rest by the double tier.  For z >= 33 the
 // threshold is below 1 and only r = 0 accepts.
-__device__ inline bool gauss_accept_metro(uint32_t r, float cz, double b, uint32_t u) {
+// The float32 tier alone: 1 accept, 0 reject, -1 undecided (inside the band).
+__device__ __forceinline__ int gauss_metro_f32(uint32_t r, float cz, uint32_t u) {
   const float z = (float)u * cz;
-  if (z >= 33.0f) return r == 0u;
+  if (z >= 33.0f) return r == 0u ? 1 : 0;
   const float t = __builtin_amdgcn_exp2f(-z) * 4294967296.0f;
   const float rf = (float)r;
-  if (rf < t * (1.0f - 0x1p-15f)) return true;
-  if (rf > t * (1.0f + 0x1p-15f)) return false;
-  return gauss_accept_d(r, b, (int64_t)u);
+  if (rf < t * (1.0f - 0x1p-15f)) return 1;
+  if (rf > t * (1.0f + 0x1p-15f)) return 0;
+  return -1;
+}
+__device__ inline bool gauss_accept_metro(uint32_t r, float cz, double b, uint32_t u) {
+  const int f = gauss_metro_f32(r, cz, u);
+  return f >= 0 ? f != 0 : gauss_accept_d(r, b, (int64_t)u);
 }
 
 }  // namespace ptsg

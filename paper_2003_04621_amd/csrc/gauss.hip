@@ -7,6 +7,8 @@
 // (gauss.h), the energies 64-bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "gauss.h"
 #include "gauss_kernels.h"
@@ -233,20 +235,31 @@ __global__ void __launch_bounds__(512) k_gsweep(Geo g, void* spins, const int4* 
             group_fields<D>(a, m, hs, x);
             const uint32_t slot = (uint32_t)(set * g.NT + j0 + l);
             const Ctr4 r = philox10(Ctr4{c0, c1, slot, c3}, g.key0, g.key1);
-            uint32_t F = 0;
-            for (int j = 0; j < gp.nv; ++j) {
-              const int xj = x[j];
-              const bool flip =
-                  xj <= 0 || gauss_accept_metro(word_of(r, j), czl[l], bl[l], 2u * (uint32_t)xj);
-              if (flip) {
-                F |= 1u << j;
-                dE += 2 * xj;
+            // the float32 tier for the group's sites, then the rare sites
+            // inside its band one by one through the exact tiers
+            const float cz = czl[l];
+            uint32_t F = 0, und = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j < gp.nv) {
+                const int xj = x[j];
+                const int f = xj <= 0 ? 1 : gauss_metro_f32(word_of(r, j), cz, 2u * (uint32_t)xj);
+                if (f > 0) F |= 1u << j;
+                if (f < 0) und |= 1u << j;
               }
             }
+            while (und) {
+              const int j = __builtin_ctz(und);
+              und &= und - 1u;
+              if (gauss_accept_d(word_of(r, j), bl[l], (int64_t)(2 * x[j]))) F |= 1u << j;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if ((F >> j) & 1u) dE += 2 * x[j];
             if (F) atomicXor(&Wl[c * NW + gp.w], F << gp.shift);
           }
-#pragma unroll
-          for (int o = 32; o >= 1; o >>= 1) dE += __shfl_xor(dE, o, 64);
+          // every lane of the wavefront is here (see above): a DPP sum
+          dE = wave_total(dE);
           if ((t & 63) == 0 && dE) atomicAdd(&El[l], (unsigned long long)(int64_t)dE);
         }
       }
@@ -564,7 +577,10 @@ hipError_t launch_gauss_exchange(const Geo& g, const int64_t* E64, int32_t* sot,
 hipError_t launch_gauss_houdayer(const Geo& g, void* spins, const int4* Jg, int64_t* E64,
                                  const int32_t* sot, const DevCounters* ctr, bool multi,
                                  hipStream_t st) {
-  const int threads = 256;
+  // single cluster: one thread per colour word of the flood fill (at most
+  // 256), so that a lattice with few words grows its cluster in one
+  // wavefront; the multi-cluster teams take 256 threads
+  const int threads = multi ? 256 : std::min(256, (g.NW + 63) / 64 * 64);
   if (multi && g.N > kMultiMaxSites) return hipErrorInvalidValue;
   // A, Q and the cluster words (6 NW), then the chunk sums [threads], or for
   // the multi-cluster move A and the team scratch (which begins with Q and C)
