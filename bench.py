@@ -51,6 +51,9 @@ PEAK_VALU_OPS = 256 * 128 * 2.4e9
 # local field and classification (amortised over 16-32 sites of a word) are
 # not counted.
 OPS_PER_FLIP = 16
+# The same for a Gaussian-coupling site in 2D: the Philox share (15), the four
+# bond terms of its integer local field (4) and the threshold compare (1).
+GAUSS_OPS_PER_FLIP = 20
 # HBM bytes per launch of the fused kernel, keyed by (workload, layout,
 # variant: 1 Houdayer | 2 measure), from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # scaled by a plain copy's readings (profiles/*_hbm_traffic.md).  Every
@@ -564,18 +567,38 @@ def main():
                               wg.seed)
         pt.pt_mcs(gj, min(args.warmup, 20), houdayer=True, measure=True)
         torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ga, gb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         tg = time.perf_counter()
+        ga.record(stream)
         pt.pt_mcs(gj, args.gauss_steps, houdayer=True, measure=True)
+        gb.record(stream)
         torch.cuda.synchronize()
         dtg = time.perf_counter() - tg
+        g_ms = ga.elapsed_time(gb)
+        # the same steps as one launch per kernel per step
+        gplain = 20
+        tp = time.perf_counter()
+        pt.pt_mcs(gj, gplain, houdayer=True, measure=True, plain=True)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - tp
         _, dis_g, _ = pt.pt_observables(gj)
         pt.pt_destroy(gj)
+        g_achieved = GAUSS_OPS_PER_FLIP * wg.flips_per_sweep * args.gauss_steps / (g_ms * 1e-3) / 1e12
         gauss = {"workload": f"{wg.name}: 2D Gaussian couplings (standard normal on the 2^-16 "
                              f"grid), L={wg.L}, {wg.samples} samples x 2 x {wg.replicas} "
                              "temperatures, sweep + Houdayer + exchange + measure",
                  "value": round(wg.flips_per_sweep * args.gauss_steps / dtg / 1e9, 2),
                  "unit": "flips/ns", "steps": args.gauss_steps,
-                 "form": "one launch per kernel per step",
+                 "form": f"fused, {args.gauss_steps} steps in one launch of k_gfused<2, true, true>",
+                 "roofline": {"bound": "alu", "achieved": round(g_achieved, 3),
+                              "peak": round(PEAK_VALU_OPS / 1e12, 3), "unit": "TOP/s",
+                              "frac": round(g_achieved / (PEAK_VALU_OPS / 1e12), 4), "traffic": None,
+                              "kernel": "k_gfused<2, true, true>", "launch_ms": round(g_ms, 4),
+                              "ops_per_flip": GAUSS_OPS_PER_FLIP},
+                 "plain_form": {"value": round(wg.flips_per_sweep * gplain / dtp / 1e9, 2),
+                                "unit": "flips/ns", "steps": gplain,
+                                "form": "one launch per kernel per step"},
                  "e_coldest": round(float(dis_g[0, 0]), 6)}
 
     # the four-part time split (Sec. 4.5) of both workloads

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libptsg.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = ["runtime.hip", "batch.hip", "server.hip", "sweep.hip", "steps.hip", "houdayer.hip",
            "fused.hip", "fused_k2a.hip", "fused_k2b.hip", "fused_k3a.hip", "fused_k3b.hip",
-           "gauss.hip"]
+           "gauss.hip", "gauss_fused.hip"]
 
 # Packed FP32 instructions are disabled on purpose (no float code needs them).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

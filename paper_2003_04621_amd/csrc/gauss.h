@@ -150,4 +150,94 @@ __device__ inline bool gauss_accept_metro(uint32_t r, float cz, double b, uint32
   return f >= 0 ? f != 0 : gauss_accept_d(r, b, (int64_t)u);
 }
 
+// ---------------------------------------------------------------------------
+// Site groups of the Gaussian kernels.
+// ---------------------------------------------------------------------------
+// Decodes group gi of a colour: word w, field f, group q.
+struct GroupPos {
+  int w, f, q, shift, nv;
+};
+__device__ __forceinline__ GroupPos group_pos(const Geo& g, int gi) {
+  const int Gp = (g.H + 3) / 4;
+  GroupPos p;
+  p.w = gi % g.NW;
+  const int fg = gi / g.NW;
+  p.f = fg / Gp;
+  p.q = fg - p.f * Gp;
+  p.shift = p.f * g.H + 4 * p.q;
+  p.nv = min(4, g.H - 4 * p.q);
+  return p;
+}
+
+__device__ __forceinline__ int lane_of(const int4& v, int j) {
+  return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ uint32_t word_of(const Ctr4& v, int j) {
+  return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w;
+}
+
+// x = s_i h_i of the four sites of a group from the antiparallel words a[k]
+// (already shifted to the group) and the group's coupling data.
+template <int D>
+__device__ __forceinline__ void group_fields(const uint32_t (&a)[2 * D], const int4 (&m)[2 * D],
+                                             const int4& hs, int (&x)[4]) {
+  x[0] = hs.x;
+  x[1] = hs.y;
+  x[2] = hs.z;
+  x[3] = hs.w;
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) {
+    x[0] += m[k].x & -(int)(a[k] & 1u);
+    x[1] += m[k].y & -(int)((a[k] >> 1) & 1u);
+    x[2] += m[k].z & -(int)((a[k] >> 2) & 1u);
+    x[3] += m[k].w & -(int)((a[k] >> 3) & 1u);
+  }
+}
+
+// Energy change of replica a when the cluster C (both colours' words) is
+// exchanged with replica b: the sum over bonds leaving C of 2 n s_i^a s_j^a,
+// taken from the colour-0 end of every bond (with m = -2n, m (2 a - 1) where a
+// = 1 if the bond's two spins of replica a are antiparallel).  Threads t of T
+// share the groups; each returns its part.
+template <int D>
+__device__ inline int64_t gauss_cluster_delta(const Geo& g, const uint32_t* C, const uint32_t* A,
+                                              const int4* __restrict__ J0, int t, int T) {
+  const int NW = g.NW, NGc = gauss_groups(g);
+  int64_t dl = 0;
+  for (int gi = t; gi < NGc; gi += T) {
+    const GroupPos gp = group_pos(g, gi);
+    const WordNb nb = word_nb(g, gp.w);
+    const uint32_t vmask = (1u << gp.nv) - 1u;
+    uint32_t nc[2 * D], X[2 * D];
+    neighbour_words<D>(g, C + NW, gp.w, nb, nb.par, nc);
+    const uint32_t C0 = C[gp.w];
+    uint32_t any = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+      X[k] = ((C0 ^ nc[k]) >> gp.shift) & vmask;
+      any |= X[k];
+    }
+    if (!any) continue;
+    uint32_t na[2 * D];
+    neighbour_words<D>(g, A + NW, gp.w, nb, nb.par, na);
+    const uint32_t A0 = A[gp.w];
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+      if (!X[k]) continue;
+      const uint32_t a = (A0 ^ na[k]) >> gp.shift;
+      const int4 m = J0[(size_t)k * NGc + gi];
+      for (int j = 0; j < 4; ++j)
+        if ((X[k] >> j) & 1u) dl += ((a >> j) & 1u) ? lane_of(m, j) : -lane_of(m, j);
+    }
+  }
+  return dl;
+}
+
+// (hi, lo) += (vhi, vlo) as one 128-bit integer held in two int64 words.
+__device__ __forceinline__ void add128(int64_t* lo, int64_t* hi, uint64_t vlo, uint64_t vhi) {
+  const uint64_t l = (uint64_t)*lo + vlo;
+  *lo = (int64_t)l;
+  *hi = (int64_t)((uint64_t)*hi + vhi + (l < vlo ? 1u : 0u));
+}
+
 }  // namespace ptsg

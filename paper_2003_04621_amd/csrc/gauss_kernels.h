@@ -33,6 +33,17 @@ hipError_t launch_gauss_houdayer(const Geo& g, void* spins, const int4* Jg, int6
 // nothing happens unless measures_at(ctr->t + 1, every).
 hipError_t launch_gauss_measure(const Geo& g, const void* spins, const int64_t* E64, const int32_t* sot,
                                 int64_t* mom, const DevCounters* ctr, int every, hipStream_t st);
+// Fused steps (gauss_fused.hip): n steps of sweep (+ single-cluster Houdayer)
+// + exchange (+ measurement at interval `every`), one workgroup per sample
+// holding all its configurations in LDS; the counters are read, not advanced.
+// hipErrorInvalidValue if the sample does not fit (gauss_fused_lds above
+// kGaussFusedMaxLds).
+constexpr size_t kGaussFusedMaxLds = 160 * 1024;
+size_t gauss_fused_lds(const Geo& g);
+hipError_t launch_gauss_fused(const Geo& g, void* spins, const int4* Jg, int64_t* E64, int32_t* sot,
+                              int32_t* tos, const double* beta, const float* cz, int64_t* mom,
+                              const DevCounters* ctr, int n, bool hou, bool meas, int every,
+                              hipStream_t st);
 // Acceptance decisions of device arrays (tests): mode 0 Metropolis tiers,
 // 1 exchange tiers, 2 double-double alone.
 hipError_t launch_gauss_accept(const uint32_t* r, const double* b, const int64_t* u, int32_t* out, int n,

@@ -78,6 +78,16 @@ void plan_job(pt_job* job) {
 // pt_get_plan's report for a planned job.
 void plan_report(const pt_job* job, uint32_t flags, int32_t* out4) {
   const Geo& g = job->g;
+  if (job->gauss) {
+    // fused: one workgroup per sample (gauss_fused.hip); else per-step kernels
+    const bool fused = !(flags & (PT_MCS_PLAIN | PT_MCS_MULTICLUSTER)) &&
+                       gauss_fused_lds(g) <= kGaussFusedMaxLds;
+    out4[0] = fused ? 0 : -1;
+    out4[1] = fused ? 1 : 0;
+    out4[2] = fused ? g.nslot : 0;
+    out4[3] = fused ? (int32_t)gauss_fused_lds(g) : 0;
+    return;
+  }
   const int mode = (flags & PT_MCS_PLAIN) ? -1 : job_plan_mode(job, flags);
   out4[0] = mode == 4 ? 1 : mode;  // the multi-cluster plan is reported as mode 1
   if (mode < 0) {
@@ -627,10 +637,34 @@ int mcs_per_step(pt_job* job, int32_t n, uint32_t flags) {
   }
   return PT_OK;
 }
+// Whether a Gaussian job's steps with these flags run fused (gauss_fused.hip):
+// single-cluster Houdayer moves or none, and the sample's configurations fit
+// one workgroup's LDS.
+bool gauss_fused_ok(const pt_job* job, uint32_t flags) {
+  return job->gauss && !(flags & (PT_MCS_PLAIN | PT_MCS_MULTICLUSTER)) &&
+         gauss_fused_lds(job->g) <= kGaussFusedMaxLds;
+}
+
+// n fused steps of a Gaussian job, in launches of at most 500 steps, each
+// followed by the counters' advance (allocates nothing).
+int mcs_gauss_fused(pt_job* job, int32_t n, uint32_t flags) {
+  const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
+  const int chunk = 500;
+  for (int done = 0; done < n; done += chunk) {
+    const uint32_t m = (uint32_t)((n - done) < chunk ? (n - done) : chunk);
+    PT_HIP(job, launch_gauss_fused(job->g, job->spins, job->gJ, job->E64, job->sot, job->tos,
+                                   job->gbeta, job->gcz, job->mom, job->ctr, (int)m, hou, meas,
+                                   job->meas_every, job->stream));
+    const CounterStep adv{m, m, hou ? m : 0u, meas ? m : 0u, (uint32_t)job->meas_every};
+    PT_HIP(job, launch_advance(job->ctr, adv, job->stream));
+  }
+  return PT_OK;
+}
 }  // namespace
 
 PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
   if (int rc = check_mcs(job, n, flags)) return rc;
+  if (gauss_fused_ok(job, flags)) return mcs_gauss_fused(job, n, flags);
   // fused through the job's one-job batch whenever a workgroup plan exists:
   // both sets per workgroup, one set per workgroup (no overlap needed), or
   // the sample split over several workgroups (no Houdayer move)
@@ -654,6 +688,7 @@ PT_API int pt_mcs(pt_job* job, int32_t n, uint32_t flags) {
 
 PT_API int pt_mcs_noalloc(pt_job* job, int32_t n, uint32_t flags) {
   if (int rc = check_mcs(job, n, flags)) return rc;
+  if (gauss_fused_ok(job, flags)) return mcs_gauss_fused(job, n, flags);
   if (job->gauss || (flags & PT_MCS_PLAIN) || !job_is_resident(job, flags))
     return mcs_per_step(job, n, flags);  // per-step kernels use no scratch
   const int chunk = 500;

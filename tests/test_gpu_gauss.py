@@ -148,6 +148,62 @@ def test_gauss_steps_match_oracle(pt, d, L, S, NT, layout):
     pt.pt_destroy(job)
 
 
+FUSED_SHAPES = [  # (dim, L, samples, replicas, layout)
+    (2, 8, 3, 4, 0),
+    (2, 12, 2, 5, 1),
+    (2, 64, 2, 24, 1),
+    (3, 6, 2, 3, 0),
+    (3, 8, 2, 6, 1),
+    (3, 16, 2, 8, 0),
+]
+
+
+def same_state(pt, x, y, what):
+    assert (pt.pt_get_spins(x) == pt.pt_get_spins(y)).all(), f"{what}: spins"
+    assert (pt.pt_get_energies64(x) == pt.pt_get_energies64(y)).all(), f"{what}: energies"
+    for a, b in zip(pt.pt_get_maps(x), pt.pt_get_maps(y)):
+        assert (a == b).all(), f"{what}: maps"
+    assert pt.pt_get_counters(x) == pt.pt_get_counters(y), what
+    assert (pt.pt_get_moments8(x) == pt.pt_get_moments8(y)).all(), f"{what}: moments"
+
+
+@pytest.mark.parametrize("d,L,S,NT,layout", FUSED_SHAPES)
+def test_gauss_fused_matches_per_step_and_oracle(pt, d, L, S, NT, layout):
+    """Fused Gaussian steps (one workgroup per sample with all its
+    configurations in LDS, n steps per launch) against the per-step kernels
+    (PT_MCS_PLAIN) and the oracle: spins, 64-bit energies, maps, counters and
+    moments bit for bit, with and without Houdayer moves and measurements, at
+    a measurement interval, and across launches of more than 500 steps."""
+    say(f"gauss fused d={d} L={L} S={S} NT={NT} layout={layout}")
+    job, ref = make(pt, d, L, S, NT, layout, 300 + L)
+    plain, _ = make(pt, d, L, S, NT, layout, 300 + L)
+    plan = pt.pt_get_plan(job, houdayer=True, measure=True)
+    assert plan["mode"] == 0 and plan["parts"] == 1 and plan["per_part"] == 2 * NT
+    assert pt.pt_get_plan(job, houdayer=True, measure=True, plain=True)["mode"] == -1
+    assert pt.pt_get_plan(job, houdayer=True, measure=True, multi=True)["mode"] == -1
+    for n, hou, meas in ((7, True, True), (5, False, True), (4, True, False), (3, False, False)):
+        pt.pt_mcs(job, n, houdayer=hou, measure=meas)
+        pt.pt_mcs(plain, n, houdayer=hou, measure=meas, plain=True)
+        ref.mcs(n, houdayer=hou, measure=meas)
+        same_state(pt, job, plain, f"{n} steps houdayer={hou} measure={meas}")
+    matches(pt, job, ref, "fused steps", obs=True)
+    pt.pt_set_measure_interval(job, 3)
+    pt.pt_set_measure_interval(plain, 3)
+    ref.set_measure_every(3)
+    pt.pt_mcs(job, 8, houdayer=True, measure=True)
+    pt.pt_mcs(plain, 8, houdayer=True, measure=True, plain=True)
+    ref.mcs(8, houdayer=True, measure=True)
+    same_state(pt, job, plain, "interval 3")
+    matches(pt, job, ref, "interval 3", obs=True)
+    if L ** d <= 512:
+        # a call longer than one launch (500 steps)
+        pt.pt_mcs(job, 520, houdayer=True, measure=True)
+        pt.pt_mcs(plain, 520, houdayer=True, measure=True, plain=True)
+        same_state(pt, job, plain, "520 steps")
+    pt.pt_destroy(job)
+    pt.pt_destroy(plain)
+
+
 def test_gauss_long_cold_2d(pt):
     """A long run at low temperatures (most moves decided by the threshold
     comparison), 2D L = 16 with both Houdayer variants alternating."""
