@@ -655,7 +655,10 @@ int mcs_gauss_fused(pt_job* job, int32_t n, uint32_t flags) {
     PT_HIP(job, launch_gauss_fused(job->g, job->spins, job->gJ, job->E64, job->sot, job->tos,
                                    job->gbeta, job->gcz, job->mom, job->ctr, (int)m, hou, meas,
                                    job->meas_every, job->stream));
-    const CounterStep adv{m, m, hou ? m : 0u, meas ? m : 0u, (uint32_t)job->meas_every};
+    // n_meas: m measurements at interval 1, else one per multiple of the
+    // interval among the m sweep numbers (CounterStep's rule)
+    const uint32_t every = (uint32_t)job->meas_every;
+    const CounterStep adv{m, m, hou ? m : 0u, meas ? (every > 1u ? 1u : m) : 0u, every};
     PT_HIP(job, launch_advance(job->ctr, adv, job->stream));
   }
   return PT_OK;
