@@ -161,7 +161,11 @@ int pt_init_ex(pt_job **out, int32_t samples, int32_t replicas, int32_t L,
  * D > 0 units iff r < 2^32 exp(-(beta_k - beta_{k+1}) D 2^-16), both decided
  * exactly (real-number comparisons of the integer r; see pt_gauss_accept_test).
  * pt_sweep, pt_exchange, pt_houdayer, pt_houdayer_multi, pt_measure, pt_mcs
- * (always the per-step kernels), pt_observables (energies per spin in
+ * (fused, n steps per launch with one workgroup per sample holding all its
+ * configurations, when pt_get_plan reports mode 0: single-cluster or no
+ * Houdayer moves and a sample that fits one workgroup's LDS; otherwise, and
+ * with PT_MCS_PLAIN, the per-step kernels; both bit-identical),
+ * pt_mcs_noalloc (the same), pt_get_plan, pt_observables (energies per spin in
  * coupling units), pt_get/set_spins, pt_get_maps, pt_get_counters,
  * pt_set_measure_interval, pt_get_state / pt_set_state and pt_destroy take
  * such jobs; energies and moments are read with pt_get_energies64 and
@@ -274,7 +278,9 @@ int pt_set_measure_interval(pt_job *job, int32_t every);
 /* The plan pt_mcs takes for these flags, int32 [4]: mode (0 both sets per
  * workgroup, 1 the same with Houdayer, 2 one set per workgroup, 3 split
  * sample, -1 per-step kernels), workgroups per sample, configurations per
- * workgroup, and LDS bytes per workgroup (0 for mode -1).  Host only. */
+ * workgroup, and LDS bytes per workgroup (0 for mode -1).  A Gaussian job
+ * reports mode 0 for its fused steps (with or without Houdayer moves) and -1
+ * for the per-step kernels.  Host only. */
 int pt_get_plan(pt_job *job, uint32_t flags, int32_t *out4);
 
 /* The same report for a job of this shape before it exists (host only, no
