@@ -535,63 +535,81 @@ __device__ __forceinline__ void rank_in_row64(uint32_t E, uint32_t O, uint32_t m
   SO = even ? 0u : 1u << b;
 }
 
+// The Houdayer cluster of pair k of a 2D sample with 64 rows (L = 64), one
+// row per lane, everything in registers: overlap, seed (the m-th q = -1 site
+// in site order, by a scan over lanes), flood fill alternating column fills
+// and row closures until one of them adds nothing.  False (for the whole
+// wavefront) if the pair has no q = -1 site; else c0, c1 are the cluster's
+// colour-0 and colour-1 words of this lane's row.
+__device__ __forceinline__ bool rows64_cluster(const Geo& g, const uint32_t* Wa, const uint32_t* Wb,
+                                               int s, int k, uint32_t v, int lane, uint32_t& c0,
+                                               uint32_t& c1) {
+  const bool odd = lane & 1;  // parity of the row = colour of its even sites
+  const uint32_t q0 = Wa[lane] ^ Wb[lane], q1 = Wa[64 + lane] ^ Wb[64 + lane];
+  const uint32_t qx = odd ? q1 : q0, qy = odd ? q0 : q1;
+  // q = -1 sites up to and including this row (a DPP scan over the rows)
+  const uint32_t lc = __popc(q0) + __popc(q1);
+  uint32_t incl = lc;
+  incl += dpp_zero<kRowShr1>(incl);
+  incl += dpp_zero<kRowShr2>(incl);
+  incl += dpp_zero<kRowShr4>(incl);
+  incl += dpp_zero<kRowShr8>(incl);
+  incl += dpp_zero<kBcast15, 0xA>(incl);
+  incl += dpp_zero<kBcast31, 0xC>(incl);
+  const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  if (n == 0) return false;
+  // seed: the m-th q = -1 site in increasing site order (row by row)
+  const Ctr4 r = philox10(Ctr4{(uint32_t)k, v, 0u, (kTagHou << 28) | (uint32_t)s}, g.key0, g.key1);
+  const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
+  const uint32_t m = (uint32_t)__umul64hi(r64, (uint64_t)n);
+  uint32_t X = 0, Y = 0;  // cluster: even-site and odd-site words of the row
+  if (m >= incl - lc && m < incl) rank_in_row64(qx, qy, m - (incl - lc), X, Y);
+  const uint32_t rqx = __builtin_bitreverse32(qx), rqy = __builtin_bitreverse32(qy);
+  row_closure(g, X, Y, qx, qy, rqx, rqy);
+  const ColumnChain hx = column_chain(qx, lane), hy = column_chain(qy, lane);
+  for (;;) {
+    uint32_t nx = column_fill(hx, X), ny = column_fill(hy, Y);
+    if (!__any(nx != X || ny != Y)) break;
+    X = nx;
+    Y = ny;
+    row_closure(g, nx, ny, qx, qy, rqx, rqy);
+    if (!__any(nx != X || ny != Y)) break;
+    X = nx;
+    Y = ny;
+  }
+  c0 = odd ? Y : X;
+  c1 = odd ? X : Y;
+  return true;
+}
+
+// The next pair of the Houdayer phase for this wavefront, from the hottest
+// down (clusters grow larger and take more passes at high temperature), each
+// to the next free wavefront; -1 when none is left.  Every lane adds 1 (one
+// 64-count LDS atomic per take) and all read lane 0's result: a take under a
+// lane-0 branch would let the compiler run the other lanes on into the next
+// pair without it.  The counter is cleared after each Houdayer phase.
+__device__ __forceinline__ int take_pair_hottest(uint32_t* hctr, int NT) {
+  const uint32_t i = (uint32_t)__builtin_amdgcn_readfirstlane((int)atomicAdd(hctr, 1u)) >> 6;
+  return i >= (uint32_t)NT ? -1 : NT - 1 - (int)i;
+}
+
 // Houdayer moves of a 2D sample with 64 rows (L = 64), one wavefront per
-// pair at a time and one row per lane, everything in registers: overlap,
-// seed (a scan over lanes in site order), flood fill alternating column
-// fills and row closures until one of them adds nothing, energy change from
-// the bonds leaving the cluster (vertical neighbours taken from the adjacent
-// lanes), exchange on the cluster.
+// pair at a time and one row per lane (rows64_cluster), then the energy
+// change from the bonds leaving the cluster (vertical neighbours taken from
+// the adjacent lanes) and the exchange on the cluster.
 __device__ __forceinline__ void houdayer_rows64(const Geo& g, uint32_t* W, const uint32_t* Jl,
                                                 int32_t* El, const int32_t* sotl, int s, uint32_t v,
                                                 uint32_t* hctr, int lane) {
   const int NT = g.NT;
-  const bool odd = lane & 1;  // parity of the row = colour of its even sites
+  const bool odd = lane & 1;
   for (;;) {
-    // pairs from the hottest down (clusters grow larger and take more
-    // passes at high temperature), each to the next free wavefront.  Every
-    // lane adds 1 (one 64-count LDS atomic per take) and all read lane 0's
-    // result: a take under a lane-0 branch would let the compiler run the
-    // other lanes on into the next pair without it.  The counter is cleared
-    // after each Houdayer phase.
-    const uint32_t i = (uint32_t)__builtin_amdgcn_readfirstlane((int)atomicAdd(hctr, 1u)) >> 6;
-    if (i >= (uint32_t)NT) break;
-    const int k = NT - 1 - (int)i;
+    const int k = take_pair_hottest(hctr, NT);
+    if (k < 0) break;
     const int a = sotl[k], b = NT + sotl[NT + k];
     uint32_t* Wa = W + (size_t)a * 128;
     uint32_t* Wb = W + (size_t)b * 128;
-    const uint32_t q0 = Wa[lane] ^ Wb[lane], q1 = Wa[64 + lane] ^ Wb[64 + lane];
-    const uint32_t qx = odd ? q1 : q0, qy = odd ? q0 : q1;
-    // q = -1 sites up to and including this row (a DPP scan over the rows)
-    const uint32_t lc = __popc(q0) + __popc(q1);
-    uint32_t incl = lc;
-    incl += dpp_zero<kRowShr1>(incl);
-    incl += dpp_zero<kRowShr2>(incl);
-    incl += dpp_zero<kRowShr4>(incl);
-    incl += dpp_zero<kRowShr8>(incl);
-    incl += dpp_zero<kBcast15, 0xA>(incl);
-    incl += dpp_zero<kBcast31, 0xC>(incl);
-    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    if (n == 0) continue;
-    // seed: the m-th q = -1 site in increasing site order (row by row)
-    const Ctr4 r = philox10(Ctr4{(uint32_t)k, v, 0u, (kTagHou << 28) | (uint32_t)s}, g.key0, g.key1);
-    const uint64_t r64 = (uint64_t)r.x | ((uint64_t)r.y << 32);
-    const uint32_t m = (uint32_t)__umul64hi(r64, (uint64_t)n);
-    uint32_t X = 0, Y = 0;  // cluster: even-site and odd-site words of the row
-    if (m >= incl - lc && m < incl) rank_in_row64(qx, qy, m - (incl - lc), X, Y);
-    const uint32_t rqx = __builtin_bitreverse32(qx), rqy = __builtin_bitreverse32(qy);
-    row_closure(g, X, Y, qx, qy, rqx, rqy);
-    const ColumnChain hx = column_chain(qx, lane), hy = column_chain(qy, lane);
-    for (;;) {
-      uint32_t nx = column_fill(hx, X), ny = column_fill(hy, Y);
-      if (!__any(nx != X || ny != Y)) break;
-      X = nx;
-      Y = ny;
-      row_closure(g, nx, ny, qx, qy, rqx, rqy);
-      if (!__any(nx != X || ny != Y)) break;
-      X = nx;
-      Y = ny;
-    }
-    const uint32_t c0 = odd ? Y : X, c1 = odd ? X : Y;
+    uint32_t c0, c1;
+    if (!rows64_cluster(g, Wa, Wb, s, k, v, lane, c0, c1)) continue;
     const uint32_t a0 = Wa[lane], a1 = Wa[64 + lane], b0 = Wb[lane], b1 = Wb[64 + lane];
     // energy change of replica a over the bonds of the colour-0 sites (each
     // bond has one): +x0, -x0 in the row, +x1, -x1 in the next/previous row

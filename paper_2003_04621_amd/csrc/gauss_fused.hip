@@ -34,7 +34,7 @@ int gauss_fused_threads(const Geo& g) {
 
 // LDS word offsets (64-bit arrays first, so that they stay 8-byte aligned).
 struct GaussLayout {
-  int E, beta, mom, cz, sot, tos, W, Qs, words;
+  int E, beta, mom, cz, sot, tos, hq, W, Qs, words;
 };
 
 GaussLayout gauss_layout(const Geo& g, int nwave) {
@@ -46,8 +46,10 @@ GaussLayout gauss_layout(const Geo& g, int nwave) {
   l.cz = o;    o += g.NT;                   // float [N_T] the float32 tier's constants
   l.sot = o;   o += 2 * g.NT;               // int32 [2][N_T]
   l.tos = o;   o += 2 * g.NT;               // int32 [2][N_T]
+  l.hq = o;    o += 1;                      // the in-register Houdayer move's pair counter
   l.W = o;     o += 2 * g.NT * 2 * g.NW;    // [2 N_T][2 NW] configuration words
-  l.Qs = o;    o += nwave * 4 * g.NW;       // per wavefront: overlap and cluster words
+  // per wavefront: overlap and cluster words of the word-hop flood fill
+  l.Qs = o;    o += rows64_houdayer(g) ? 0 : nwave * 4 * g.NW;
   l.words = o;
   return l;
 }
@@ -120,6 +122,63 @@ __device__ void gauss_houdayer_resident(const Geo& g, uint32_t* W, int64_t* El, 
   __syncthreads();
 }
 
+// The same for a 2D sample with 64 rows (L = 64, one row per word): the
+// cluster is found in registers, one row per lane (rows64_cluster), pairs from
+// the hottest down; the energy change sums, over the cluster's boundary bonds
+// from this row's colour-0 sites (a few per row), the bond's -2n from its
+// coupling group with the sign of replica a across it.  Ends with a workgroup
+// barrier, after which the pair counter is cleared.
+__device__ void gauss_houdayer_rows64(const Geo& g, uint32_t* W, int64_t* El, const int32_t* sotl,
+                                      const int4* __restrict__ J0, int s, uint32_t v, uint32_t* hctr) {
+  const int NT = g.NT, NGc = gauss_groups(g), lane = threadIdx.x & 63;
+  const bool odd = lane & 1;
+  for (;;) {
+    const int k = take_pair_hottest(hctr, NT);
+    if (k < 0) break;
+    const int a = sotl[k], b = NT + sotl[NT + k];
+    uint32_t* Wa = W + (size_t)a * 128;
+    uint32_t* Wb = W + (size_t)b * 128;
+    uint32_t c0, c1;
+    if (!rows64_cluster(g, Wa, Wb, s, k, v, lane, c0, c1)) continue;
+    const uint32_t a0 = Wa[lane], a1 = Wa[64 + lane], b0 = Wb[lane], b1 = Wb[64 + lane];
+    // the colour-0 sites' bonds: +x0, -x0 in the row, +x1, -x1 to the
+    // next/previous row, the order of the coupling groups' directions
+    uint32_t nc[4], na[4];
+    x0_neighbours(g, c1, odd, nc[0], nc[1]);
+    x0_neighbours(g, a1, odd, na[0], na[1]);
+    nc[2] = dpp_ones<kWaveRol1>(c1);
+    nc[3] = dpp_ones<kWaveRor1>(c1);
+    na[2] = dpp_ones<kWaveRol1>(a1);
+    na[3] = dpp_ones<kWaveRor1>(a1);
+    int64_t dl = 0;
+#pragma unroll
+    for (int dir = 0; dir < 4; ++dir) {
+      const uint32_t X = c0 ^ nc[dir];  // bonds leaving the cluster
+      const uint32_t U = a0 ^ na[dir];  // replica a antiparallel across them
+      for (uint32_t grp = X; grp;) {
+        const int q = __builtin_ctz(grp) >> 2;  // group of four sites of the row
+        const uint32_t xb = (X >> (4 * q)) & 0xFu, ub = (U >> (4 * q)) & 0xFu;
+        grp &= ~(0xFu << (4 * q));
+        const int4 m = J0[(size_t)dir * NGc + lane + 64 * q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if ((xb >> j) & 1u) dl += ((ub >> j) & 1u) ? lane_of(m, j) : -lane_of(m, j);
+      }
+    }
+    const int64_t delta = wave_sum64(dl);
+    Wa[lane] = a0 ^ c0;
+    Wa[64 + lane] = a1 ^ c1;
+    Wb[lane] = b0 ^ c0;
+    Wb[64 + lane] = b1 ^ c1;
+    if (lane == 0) {
+      El[a] += delta;
+      El[b] -= delta;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *hctr = 0u;  // the next use is behind the step's barriers
+}
+
 // One workgroup per sample, `n` steps of sweep (+ Houdayer) + exchange
 // (+ measurement at the job's interval).  The counters are read at the start;
 // the caller advances them by n steps afterwards.
@@ -157,6 +216,7 @@ __global__ void __launch_bounds__(512) k_gfused(Geo g, void* spins, const int4* 
   }
   if (MEAS)
     for (int i = tid; i < 8 * NT; i += T) ml[i] = mom[(size_t)s * NT * 8 + i];
+  if (tid == 0) lds[lay.hq] = 0u;
   const uint32_t t0 = load_counter(&ctr->t), u0 = load_counter(&ctr->u), v0 = load_counter(&ctr->v);
   __syncthreads();
 
@@ -232,7 +292,13 @@ __global__ void __launch_bounds__(512) k_gfused(Geo g, void* spins, const int4* 
       __syncthreads();
     }
     // ---- Houdayer move per pair
-    if (HOU) gauss_houdayer_resident<D>(g, W, El, sotl, lds + lay.Qs, Js, s, v0 + (uint32_t)step);
+    if (HOU) {
+      if (D == 2 && rows64_houdayer(g))
+        gauss_houdayer_rows64(fixed_shape<2, 64>(g), W, El, sotl, Js, s, v0 + (uint32_t)step,
+                              lds + lay.hq);
+      else
+        gauss_houdayer_resident<D>(g, W, El, sotl, lds + lay.Qs, Js, s, v0 + (uint32_t)step);
+    }
     // ---- replica exchange, one thread per set, k ascending with the updated map
     if (lane == 0 && wave < 2) {
       const int c = wave;
