@@ -135,15 +135,15 @@ __device__ inline bool gauss_accept_d(uint32_t r, double b, int64_t u) {
 // (v_exp_f32) is within 2^-18 of the true one; a word outside a 2^-15 band
 // around it is decided here, the rest by the double tier.  For z >= 33 the
 // threshold is below 1 and only r = 0 accepts.
-// The float32 tier alone: 1 accept, 0 reject, -1 undecided (inside the band).
+// The float32 tier alone, without branches: 1 accept, 0 reject, -1
+// undecided (inside the band).  For z >= 33 the threshold is below 1/2 (or
+// flushed to 0): every r >= 1 is rejected and r = 0 is accepted or, if the
+// threshold underflowed, left to the double tier, which accepts it.
 __device__ __forceinline__ int gauss_metro_f32(uint32_t r, float cz, uint32_t u) {
   const float z = (float)u * cz;
-  if (z >= 33.0f) return r == 0u ? 1 : 0;
   const float t = __builtin_amdgcn_exp2f(-z) * 4294967296.0f;
   const float rf = (float)r;
-  if (rf < t * (1.0f - 0x1p-15f)) return 1;
-  if (rf > t * (1.0f + 0x1p-15f)) return 0;
-  return -1;
+  return rf < t * (1.0f - 0x1p-15f) ? 1 : (rf > t * (1.0f + 0x1p-15f) ? 0 : -1);
 }
 __device__ inline bool gauss_accept_metro(uint32_t r, float cz, double b, uint32_t u) {
   const int f = gauss_metro_f32(r, cz, u);
@@ -176,8 +176,19 @@ __device__ __forceinline__ uint32_t word_of(const Ctr4& v, int j) {
   return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w;
 }
 
+// Bit j of a sign-extended to a mask (0 or -1), one v_bfe_i32.  Written as
+// an instruction so that the compiler keeps the mask-and-add form (its own
+// canonical form, a compare and a select per term, costs one more).
+template <int J>
+__device__ __forceinline__ int bit_mask(uint32_t a) {
+  int r;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(a), "i"(J));
+  return r;
+}
+
 // x = s_i h_i of the four sites of a group from the antiparallel words a[k]
-// (already shifted to the group) and the group's coupling data.
+// (already shifted to the group) and the group's coupling data: bit j of a[k]
+// as a mask selects the term.
 template <int D>
 __device__ __forceinline__ void group_fields(const uint32_t (&a)[2 * D], const int4 (&m)[2 * D],
                                              const int4& hs, int (&x)[4]) {
@@ -187,11 +198,42 @@ __device__ __forceinline__ void group_fields(const uint32_t (&a)[2 * D], const i
   x[3] = hs.w;
 #pragma unroll
   for (int k = 0; k < 2 * D; ++k) {
-    x[0] += m[k].x & -(int)(a[k] & 1u);
-    x[1] += m[k].y & -(int)((a[k] >> 1) & 1u);
-    x[2] += m[k].z & -(int)((a[k] >> 2) & 1u);
-    x[3] += m[k].w & -(int)((a[k] >> 3) & 1u);
+    x[0] += m[k].x & bit_mask<0>(a[k]);
+    x[1] += m[k].y & bit_mask<1>(a[k]);
+    x[2] += m[k].z & bit_mask<2>(a[k]);
+    x[3] += m[k].w & bit_mask<3>(a[k]);
   }
+}
+
+// The Metropolis decisions of one group of four same-colour sites (the first
+// nv valid) whose Philox words are r: local fields, the float32 tier for the
+// four sites without branches (x <= 0 flips at once), then the exact tiers
+// for the rare sites inside its band.  Returns the flip bits (bit j = site j)
+// and adds the flips' energy change 2x to dE.
+template <int D>
+__device__ __forceinline__ uint32_t gauss_group_flips(const uint32_t (&a)[2 * D], const int4 (&m)[2 * D],
+                                                      const int4& hs, int nv, const Ctr4& r, float cz,
+                                                      double beta, int& dE) {
+  int x[4];
+  group_fields<D>(a, m, hs, x);
+  uint32_t F = 0, und = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int xj = x[j];
+    int f = gauss_metro_f32(word_of(r, j), cz, 2u * (uint32_t)(xj > 0 ? xj : 0));
+    f = xj <= 0 ? 1 : f;
+    f = j < nv ? f : 0;
+    F |= (uint32_t)(f > 0) << j;
+    und |= (uint32_t)(f < 0) << j;
+  }
+  while (und) {
+    const int j = __builtin_ctz(und);
+    und &= und - 1u;
+    if (gauss_accept_d(word_of(r, j), beta, (int64_t)(2 * x[j]))) F |= 1u << j;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) dE += ((F >> j) & 1u) ? 2 * x[j] : 0;
+  return F;
 }
 
 // Energy change of replica a when the cluster C (both colours' words) is

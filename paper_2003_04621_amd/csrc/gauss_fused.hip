@@ -257,29 +257,10 @@ __global__ void __launch_bounds__(512) k_gfused(Geo g, void* spins, const int4* 
             neighbour_words<D>(g, Wl + (1 - c) * NW, gp.w, nb, p, nw);
 #pragma unroll
             for (int k = 0; k < 2 * D; ++k) a[k] = (Wc ^ nw[k]) >> gp.shift;
-            int x[4];
-            group_fields<D>(a, m, hs, x);
             const Ctr4 r = philox10(Ctr4{c0, c1, (uint32_t)l, c3}, g.key0, g.key1);
             const int kt = tosl[l];
             const float czk = czl[kt];
-            uint32_t F = 0, und = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              if (j < gp.nv) {
-                const int xj = x[j];
-                const int f = xj <= 0 ? 1 : gauss_metro_f32(word_of(r, j), czk, 2u * (uint32_t)xj);
-                if (f > 0) F |= 1u << j;
-                if (f < 0) und |= 1u << j;
-              }
-            }
-            while (und) {
-              const int j = __builtin_ctz(und);
-              und &= und - 1u;
-              if (gauss_accept_d(word_of(r, j), bl[kt], (int64_t)(2 * x[j]))) F |= 1u << j;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if ((F >> j) & 1u) dE += 2 * x[j];
+            const uint32_t F = gauss_group_flips<D>(a, m, hs, gp.nv, r, czk, bl[kt], dE);
             if (F) atomicXor(&Wl[c * NW + gp.w], F << gp.shift);
           }
           // every lane of the workgroup runs every round: a DPP wavefront sum
