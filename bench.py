@@ -353,8 +353,8 @@ def phase_split(pt, torch, wl, layout, steps, warmup):
     between fused runs with and without the Houdayer move and the
     measurement (the sweep and the exchange share one kernel)."""
     stream = torch.cuda.current_stream()
-    job = pt.pt_init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed,
-                     layout=layout)
+    init = pt.pt_init_gauss if getattr(wl, "gauss", False) else pt.pt_init
+    job = init(wl.samples, wl.replicas, wl.L, wl.dim, wl.couplings(), wl.betas, wl.seed, layout=layout)
     norm = wl.flips_per_sweep  # N_T N_C N_R N_B L^d
     pt.pt_mcs(job, warmup, houdayer=wl.houdayer, measure=True)
     phases = [("metropolis", lambda: pt.pt_sweep(job, 1))]
@@ -601,13 +601,14 @@ def main():
                                 "form": "one launch per kernel per step"},
                  "e_coldest": round(float(dis_g[0, 0]), 6)}
 
-    # the four-part time split (Sec. 4.5) of both workloads
+    # the four-part time split (Sec. 4.5) of the workloads
     split = None
     if args.phase_steps > 0:
         print("# per-phase split", file=sys.stderr, flush=True)
         split = [phase_split(pt, torch, wl, layout, args.phase_steps, 20)]
-        if wl.name != "2d_l64":
-            split.append(phase_split(pt, torch, W.workload("2d_l64"), layout, args.phase_steps, 20))
+        for other in ("2d_l64", "2d_l64_gauss"):
+            if wl.name != other:
+                split.append(phase_split(pt, torch, W.workload(other), layout, args.phase_steps, 20))
 
     # the same workload with the replica walk and its round trips kept
     walk = None

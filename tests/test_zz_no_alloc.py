@@ -1,9 +1,10 @@
 """pt_mcs_noalloc (the work list in the library's static scratch, no device
 allocation) against pt_mcs on twin jobs: spins, energies, maps, counters and
 integer moments bit for bit, for two calls in a row (the second with a smaller
-job), a split sample, a Houdayer job, a call longer than one launch and the
-per-step fallback; a launch beyond the scratch's item limit is refused before
-anything runs."""
+job), a split sample, a Houdayer job, a call longer than one launch, the
+per-step fallback and a Gaussian-coupling job (fused steps that use no
+scratch); a launch beyond the scratch's item limit is refused before anything
+runs."""
 import numpy as np
 import pytest
 
@@ -93,3 +94,26 @@ def test_noalloc_per_step_fallback_and_limit(pt):
     pt.pt_mcs(job, 1)  # the job still works
     assert pt.pt_get_counters(job)["t"] == 1
     pt.pt_destroy(job)
+
+
+def test_noalloc_gauss(pt):
+    """Gaussian jobs: pt_mcs_noalloc takes the same fused steps as pt_mcs (one
+    workgroup per sample, no scratch), twice in a row."""
+    d, L, S, NT = 2, 16, 3, 6
+    say(f"pt_mcs_noalloc gauss d={d} L={L} S={S} NT={NT}")
+    Jf = W.couplings_gauss(S, L, d, 41)
+    b = W.geometric_betas(0.2, 1.6, NT)
+    a = pt.pt_init_gauss(S, NT, L, d, Jf, b, 17)
+    c = pt.pt_init_gauss(S, NT, L, d, Jf, b, 17)
+    assert pt.pt_get_plan(a, houdayer=True, measure=True)["mode"] == 0
+    for n in (9, 4):
+        pt.pt_mcs_noalloc(a, n, houdayer=True, measure=True)
+        pt.pt_mcs(c, n, houdayer=True, measure=True)
+        assert (pt.pt_get_spins(a) == pt.pt_get_spins(c)).all()
+        assert (pt.pt_get_energies64(a) == pt.pt_get_energies64(c)).all()
+        for x, y in zip(pt.pt_get_maps(a), pt.pt_get_maps(c)):
+            assert (x == y).all()
+        assert pt.pt_get_counters(a) == pt.pt_get_counters(c)
+        assert (pt.pt_get_moments8(a) == pt.pt_get_moments8(c)).all()
+    pt.pt_destroy(a)
+    pt.pt_destroy(c)
