@@ -255,8 +255,9 @@ def served(pt, torch, W, args):
     if args.serve_eq_requests > 0:
         # smaller lattices than the mix above: at T_min = 0.9 the L >= 16
         # requests of that mix do not pass the check within 1e4 sweeps
+        lo, hi = (float(x) for x in args.serve_eq_sweeps.split(","))
         reqs_e = _requests(W, rng, args.serve_eq_requests, 7000, Ls=(8, 12, 16), nt=(12, 24),
-                           sweeps=(2e3, 2e4))
+                           sweeps=(lo, hi))
         mean_e = float(np.mean([r["flips"] for r in reqs_e]))
         lam_e = args.serve_load * capacity * 1e9 / mean_e
         arr_e = np.cumsum(rng.exponential(1.0 / lam_e, size=len(reqs_e)))
@@ -266,7 +267,7 @@ def served(pt, torch, W, args):
         eq = {"workload": f"{len(reqs_e)} requests, Poisson arrivals at {lam_e:.2f}/s, 3D +-J, "
                           "one sample, L in {8,12,16}, 12-24 temperatures in [0.9, 2.0], replica "
                           "walk kept, each ending once its round trips pass the logarithmic-"
-                          "binning check (Sec. 2.3), at most 2e3-2e4 steps (half burn-in)",
+                          f"binning check (Sec. 2.3), at most {lo:.0e}-{hi:.0e} steps (half burn-in)",
               "requests": len(reqs_e), "equilibrated": len(done_eq),
               "p50_latency_s": round(float(np.percentile(lat_e, 50)), 4),
               "p99_latency_s": round(float(np.percentile(lat_e, 99)), 4),
@@ -449,6 +450,8 @@ def main():
     ap.add_argument("--serve-round", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-seed", type=int, default=31)
+    ap.add_argument("--serve-eq-sweeps", default="2e3,2e4",
+                    help="bounds of the equilibrium-stopped requests' steps (log-uniform)")
     ap.add_argument("--serve-eq-requests", type=int, default=500,
                     help="requests of the run that stops each job at equilibrium (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
