@@ -450,7 +450,7 @@ def main():
     ap.add_argument("--serve-round", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-seed", type=int, default=31)
-    ap.add_argument("--serve-eq-sweeps", default="2e3,2e4",
+    ap.add_argument("--serve-eq-sweeps", default="1e4,5e4",
                     help="bounds of the equilibrium-stopped requests' steps (log-uniform)")
     ap.add_argument("--serve-eq-requests", type=int, default=500,
                     help="requests of the run that stops each job at equilibrium (0: skip)")
