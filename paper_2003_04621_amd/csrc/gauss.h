@@ -206,17 +206,19 @@ __device__ __forceinline__ void group_fields(const uint32_t (&a)[2 * D], const i
 }
 
 // The Metropolis decisions of one group of four same-colour sites (the first
-// nv valid) whose Philox words are r: local fields, the float32 tier for the
-// four sites without branches (x <= 0 flips at once), then the exact tiers
-// for the rare sites inside its band.  Returns the flip bits (bit j = site j)
-// and adds the flips' energy change 2x to dE.
+// nv valid) whose Philox words are r, in two parts so that a caller can
+// interleave two groups: gauss_group_fast computes the local fields and the
+// float32 tier for the four sites without branches (x <= 0 flips at once):
+// the flip bits F and the undecided bits und; gauss_group_finish decides the
+// rare undecided sites by the exact tiers and adds the flips' energy change
+// 2x to dE.
 template <int D>
-__device__ __forceinline__ uint32_t gauss_group_flips(const uint32_t (&a)[2 * D], const int4 (&m)[2 * D],
-                                                      const int4& hs, int nv, const Ctr4& r, float cz,
-                                                      double beta, int& dE) {
-  int x[4];
+__device__ __forceinline__ void gauss_group_fast(const uint32_t (&a)[2 * D], const int4 (&m)[2 * D],
+                                                 const int4& hs, int nv, const Ctr4& r, float cz,
+                                                 int (&x)[4], uint32_t& F, uint32_t& und) {
   group_fields<D>(a, m, hs, x);
-  uint32_t F = 0, und = 0;
+  F = 0;
+  und = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int xj = x[j];
@@ -226,6 +228,9 @@ __device__ __forceinline__ uint32_t gauss_group_flips(const uint32_t (&a)[2 * D]
     F |= (uint32_t)(f > 0) << j;
     und |= (uint32_t)(f < 0) << j;
   }
+}
+__device__ __forceinline__ uint32_t gauss_group_finish(const int (&x)[4], const Ctr4& r, double beta,
+                                                       uint32_t F, uint32_t und, int& dE) {
   while (und) {
     const int j = __builtin_ctz(und);
     und &= und - 1u;
@@ -234,6 +239,15 @@ __device__ __forceinline__ uint32_t gauss_group_flips(const uint32_t (&a)[2 * D]
 #pragma unroll
   for (int j = 0; j < 4; ++j) dE += ((F >> j) & 1u) ? 2 * x[j] : 0;
   return F;
+}
+template <int D>
+__device__ __forceinline__ uint32_t gauss_group_flips(const uint32_t (&a)[2 * D], const int4 (&m)[2 * D],
+                                                      const int4& hs, int nv, const Ctr4& r, float cz,
+                                                      double beta, int& dE) {
+  int x[4];
+  uint32_t F, und;
+  gauss_group_fast<D>(a, m, hs, nv, r, cz, x, F, und);
+  return gauss_group_finish(x, r, beta, F, und, dE);
 }
 
 // Energy change of replica a when the cluster C (both colours' words) is
