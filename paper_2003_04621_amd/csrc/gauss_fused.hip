@@ -70,7 +70,9 @@ template <int D>
 __device__ void gauss_houdayer_resident(const Geo& g, uint32_t* W, int64_t* El, const int32_t* sotl,
                                         uint32_t* Qs, const int4* __restrict__ J0, int s,
                                         uint32_t v) {
-  const int NT = g.NT, NW = g.NW, W2 = 2 * NW, tid = threadIdx.x;
+  const int NT = g.NT, NW = g.NW, W2 = 2 * NW;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));  // as in gauss_houdayer_rows64
   const int wave = tid >> 6, lane = tid & 63, nwave = blockDim.x >> 6;
   uint32_t* Qw = Qs + (size_t)wave * 2 * W2;
   uint32_t* Cw = Qw + W2;
@@ -130,7 +132,12 @@ __device__ void gauss_houdayer_resident(const Geo& g, uint32_t* W, int64_t* El, 
 // barrier, after which the pair counter is cleared.
 __device__ void gauss_houdayer_rows64(const Geo& g, uint32_t* W, int64_t* El, const int32_t* sotl,
                                       const int4* __restrict__ J0, int s, uint32_t v, uint32_t* hctr) {
-  const int NT = g.NT, NGc = gauss_groups(g), lane = threadIdx.x & 63;
+  const int NT = g.NT, NGc = gauss_groups(g);
+  // recomputed at every call: what derives from the lane index (masks,
+  // addresses) would otherwise be hoisted out of the step loop and stay live
+  // through the sweep
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
   const bool odd = lane & 1;
   for (;;) {
     const int k = take_pair_hottest(hctr, NT);
@@ -231,7 +238,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
       const int4* Jc = Js + (size_t)c * (2 * D + 1) * NGc;
       const uint32_t c1 = 2u * t + (uint32_t)c;
       for (int gi0 = 0; gi0 < NGc; gi0 += T) {
-        const int gi = gi0 + tid;
+        // the group's position is recomputed every step: hoisted out of the
+        // step loop it would stay live through the Houdayer move, whose
+        // in-register cluster then no longer fits the register budget
+        int gi = gi0 + tid;
+        asm volatile("" : "+v"(gi));
         const bool valid = gi < NGc;
         int4 m[2 * D];
         int4 hs = make_int4(0, 0, 0, 0);
@@ -248,41 +259,66 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
           p = (c + nb.par) & 1;
           c0 = (uint32_t)word_row(g, nb, gp.f) * (uint32_t)g.G + (uint32_t)gp.q;
         }
-        // two configurations per round (2 N_T is even): two independent
-        // chains of loads, Philox rounds and compares for the scheduler
-        for (int l = 0; l < NS; l += 2) {
-          int dE0 = 0, dE1 = 0;
-          if (valid) {
-            uint32_t* W0 = W + (size_t)l * W2;
-            uint32_t* W1 = W0 + W2;
-            const uint32_t Wc0 = W0[c * NW + gp.w], Wc1 = W1[c * NW + gp.w];
-            uint32_t n0[2 * D], n1[2 * D], a0[2 * D], a1[2 * D];
-            neighbour_words<D>(g, W0 + (1 - c) * NW, gp.w, nb, p, n0);
-            neighbour_words<D>(g, W1 + (1 - c) * NW, gp.w, nb, p, n1);
+        if constexpr (D == 2) {
+          // two configurations per round (2 N_T is even): two independent
+          // chains of loads, Philox rounds and compares for the scheduler
+          for (int l = 0; l < NS; l += 2) {
+            int dE0 = 0, dE1 = 0;
+            if (valid) {
+              uint32_t* W0 = W + (size_t)l * W2;
+              uint32_t* W1 = W0 + W2;
+              const uint32_t Wc0 = W0[c * NW + gp.w], Wc1 = W1[c * NW + gp.w];
+              uint32_t n0[2 * D], n1[2 * D], a0[2 * D], a1[2 * D];
+              neighbour_words<D>(g, W0 + (1 - c) * NW, gp.w, nb, p, n0);
+              neighbour_words<D>(g, W1 + (1 - c) * NW, gp.w, nb, p, n1);
 #pragma unroll
-            for (int k = 0; k < 2 * D; ++k) {
-              a0[k] = (Wc0 ^ n0[k]) >> gp.shift;
-              a1[k] = (Wc1 ^ n1[k]) >> gp.shift;
+              for (int k = 0; k < 2 * D; ++k) {
+                a0[k] = (Wc0 ^ n0[k]) >> gp.shift;
+                a1[k] = (Wc1 ^ n1[k]) >> gp.shift;
+              }
+              const Ctr4 r0 = philox10(Ctr4{c0, c1, (uint32_t)l, c3}, g.key0, g.key1);
+              const Ctr4 r1 = philox10(Ctr4{c0, c1, (uint32_t)l + 1u, c3}, g.key0, g.key1);
+              const int k0 = tosl[l], k1 = tosl[l + 1];
+              int x0[4], x1[4];
+              uint32_t F0, F1, u0, u1;
+              gauss_group_fast<D>(a0, m, hs, gp.nv, r0, czl[k0], x0, F0, u0);
+              gauss_group_fast<D>(a1, m, hs, gp.nv, r1, czl[k1], x1, F1, u1);
+              F0 = gauss_group_finish(x0, r0, bl[k0], F0, u0, dE0);
+              F1 = gauss_group_finish(x1, r1, bl[k1], F1, u1, dE1);
+              if (F0) atomicXor(&W0[c * NW + gp.w], F0 << gp.shift);
+              if (F1) atomicXor(&W1[c * NW + gp.w], F1 << gp.shift);
             }
-            const Ctr4 r0 = philox10(Ctr4{c0, c1, (uint32_t)l, c3}, g.key0, g.key1);
-            const Ctr4 r1 = philox10(Ctr4{c0, c1, (uint32_t)l + 1u, c3}, g.key0, g.key1);
-            const int k0 = tosl[l], k1 = tosl[l + 1];
-            int x0[4], x1[4];
-            uint32_t F0, F1, u0, u1;
-            gauss_group_fast<D>(a0, m, hs, gp.nv, r0, czl[k0], x0, F0, u0);
-            gauss_group_fast<D>(a1, m, hs, gp.nv, r1, czl[k1], x1, F1, u1);
-            F0 = gauss_group_finish(x0, r0, bl[k0], F0, u0, dE0);
-            F1 = gauss_group_finish(x1, r1, bl[k1], F1, u1, dE1);
-            if (F0) atomicXor(&W0[c * NW + gp.w], F0 << gp.shift);
-            if (F1) atomicXor(&W1[c * NW + gp.w], F1 << gp.shift);
+            // every lane of the workgroup runs every round: DPP wavefront sums
+            // (|sum| < 64 x 4 x 2 x 6 x 2^19 < 2^31), one LDS atomic each
+            dE0 = wave_total(dE0);
+            dE1 = wave_total(dE1);
+            if (lane == 0) {
+              if (dE0)
+                atomicAdd(reinterpret_cast<unsigned long long*>(&El[l]), (unsigned long long)(int64_t)dE0);
+              if (dE1)
+                atomicAdd(reinterpret_cast<unsigned long long*>(&El[l + 1]), (unsigned long long)(int64_t)dE1);
+            }
           }
-          // every lane of the workgroup runs every round: DPP wavefront sums
-          // (|sum| < 64 x 4 x 2 x 6 x 2^19 < 2^31), one LDS atomic each
-          dE0 = wave_total(dE0);
-          dE1 = wave_total(dE1);
-          if (lane == 0) {
-            if (dE0) atomicAdd(reinterpret_cast<unsigned long long*>(&El[l]), (unsigned long long)(int64_t)dE0);
-            if (dE1) atomicAdd(reinterpret_cast<unsigned long long*>(&El[l + 1]), (unsigned long long)(int64_t)dE1);
+        } else {
+          // 3D: one configuration per round (two would not fit the register
+          // budget of four wavefronts per SIMD)
+          for (int l = 0; l < NS; ++l) {
+            int dE = 0;
+            if (valid) {
+              uint32_t* Wl = W + (size_t)l * W2;
+              const uint32_t Wc = Wl[c * NW + gp.w];
+              uint32_t nw[2 * D], a[2 * D];
+              neighbour_words<D>(g, Wl + (1 - c) * NW, gp.w, nb, p, nw);
+#pragma unroll
+              for (int k = 0; k < 2 * D; ++k) a[k] = (Wc ^ nw[k]) >> gp.shift;
+              const Ctr4 r = philox10(Ctr4{c0, c1, (uint32_t)l, c3}, g.key0, g.key1);
+              const int kt = tosl[l];
+              const uint32_t F = gauss_group_flips<D>(a, m, hs, gp.nv, r, czl[kt], bl[kt], dE);
+              if (F) atomicXor(&Wl[c * NW + gp.w], F << gp.shift);
+            }
+            dE = wave_total(dE);
+            if (lane == 0 && dE)
+              atomicAdd(reinterpret_cast<unsigned long long*>(&El[l]), (unsigned long long)(int64_t)dE);
           }
         }
       }
