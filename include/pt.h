@@ -259,7 +259,8 @@ int pt_mcs(pt_job *job, int32_t n, uint32_t flags);
  * memory it allocates on first use; this entry point instead writes them to
  * a static scratch array of the library (about 1 MiB per GPU, held from the
  * first call on that GPU until the process ends) and needs nothing else (the
- * per-step kernels it takes when no fused plan fits use no scratch).  Every
+ * per-step kernels it takes when no fused plan fits, and the fused steps of
+ * Gaussian-coupling jobs, use no scratch).  Every
  * call on one GPU shares that GPU's scratch: calls that overlap on one GPU
  * (other streams, other threads) race and must be ordered by the caller.
  * PT_EINVAL if one launch would need more than PT_NOALLOC_MAX_ITEMS work
