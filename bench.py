@@ -61,6 +61,11 @@ GAUSS_OPS_PER_FLIP = 20
 # on the number of steps a launch runs.  Entries are removed when the kernel
 # changes until the counters are taken again.
 TRAFFIC_PER_LAUNCH = {("3d_l16", "int8", 2): 572715904}
+# The fused Gaussian kernel on the 2d_l64_gauss workload, keyed by steps per
+# launch: it also re-reads the samples' coupling groups every step (those
+# that miss the L2), so its bytes grow with the step count
+# (profiles/k_gfused_2d_l64_gauss_hbm_traffic.md).
+GAUSS_TRAFFIC_PER_LAUNCH = {100: 1582418816}
 
 
 def _oracle_steps(args):
@@ -596,7 +601,8 @@ def main():
                  "form": f"fused, {args.gauss_steps} steps in one launch of k_gfused<2, true, true>",
                  "roofline": {"bound": "alu", "achieved": round(g_achieved, 3),
                               "peak": round(PEAK_VALU_OPS / 1e12, 3), "unit": "TOP/s",
-                              "frac": round(g_achieved / (PEAK_VALU_OPS / 1e12), 4), "traffic": None,
+                              "frac": round(g_achieved / (PEAK_VALU_OPS / 1e12), 4),
+                              "traffic": GAUSS_TRAFFIC_PER_LAUNCH.get(args.gauss_steps),
                               "kernel": "k_gfused<2, true, true>", "launch_ms": round(g_ms, 4),
                               "ops_per_flip": GAUSS_OPS_PER_FLIP},
                  "plain_form": {"value": round(wg.flips_per_sweep * gplain / dtp / 1e9, 2),
