@@ -113,6 +113,9 @@ typedef struct {
  * (Sec. 2.3); `sweeps` is then an upper bound.  Needs PT_TRACK_WALK. */
 #define PT_SERVE_UNTIL_EQUILIBRATED 0x100u
 
+/* pt_batch_tune flag: try both spin layouts as well as the launch shapes. */
+#define PT_TUNE_LAYOUT 0x200u
+
 /* The outcome of a request; times in seconds since pt_server_start. */
 typedef struct {
   int32_t status;       /* PT_OK, or the error that ended the request */
@@ -316,6 +319,20 @@ int pt_destroy(pt_job *job);
 int pt_get_spins(pt_job *job, int8_t *out);
 /* Replaces every spin (entries must be +1/-1) and recomputes every energy. */
 int pt_set_spins(pt_job *job, const int8_t *in);
+/* Moves the job's spins to another layout (PT_LAYOUT_INT8 or
+ * PT_LAYOUT_PACKED, Sec. 2.2): a new spin buffer is allocated through the
+ * job's allocator, filled by a conversion kernel and the old one freed, so the
+ * configuration, energies, counters and random-number streams are unchanged and
+ * later steps give the same results as without the move.  Waits for all work
+ * queued on the device first (a batch launch on another stream may still read
+ * the spins); batches holding the job rebuild their work list and graph on
+ * their next run.  A checkpoint from pt_get_state restores only into the
+ * layout it was taken from.  PT_OK at once if the job already has the layout;
+ * PT_EINVAL for another value, PT_ENOMEM if the allocation fails (the job
+ * keeps its layout). */
+int pt_set_layout(pt_job *job, uint32_t layout);
+/* The job's spin layout now (PT_LAYOUT_INT8 or PT_LAYOUT_PACKED). */
+int pt_get_layout(pt_job *job, uint32_t *out);
 /* int32 [samples][2*replicas] */
 int pt_get_energies(pt_job *job, int32_t *out);
 /* int32 [samples][2][replicas] each; either may be NULL */
@@ -440,8 +457,12 @@ int pt_batch_run(pt_batch *b, int32_t mcs, uint32_t flags);
  * configuration (threads per workgroup 1024/768/512/256, one or two replica
  * sets per item, largest-first or job order) twice on the batch itself,
  * restoring every job's state after each trial, and keeps the configuration
- * whose faster run was fastest.  cache_path (may be NULL) is a JSON-lines file keyed
- * by the batch shape; a hit skips the trials. */
+ * whose faster run was fastest.  With PT_TUNE_LAYOUT in flags the spin
+ * layout is a further axis: every configuration is timed with all jobs in the
+ * int8 layout and again in the packed one (pt_set_layout), and the jobs are
+ * left in the winning layout.  cache_path (may be NULL) is a JSON-lines file
+ * keyed by the batch shape, the flags and the jobs' layouts at the call; a hit
+ * skips the trials (and applies the cached layout). */
 int pt_batch_tune(pt_batch *b, int32_t trial_mcs, uint32_t flags, const char *cache_path);
 /* cfg3 = {threads per workgroup, replica sets per item, order}.  threads 0
  * (the default) picks per launch one of 1024/768/512/256 threads (a multiple

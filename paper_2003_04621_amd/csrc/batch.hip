@@ -44,6 +44,7 @@ struct pt_batch {
   uint32_t built_flags = 0;
   BatchConfig built_cfg;
   std::vector<int> built_every;
+  std::vector<uint32_t> built_epoch;  // the jobs' epochs when the list was built
   // captured launch (captured on a private stream, replayed on `stream`)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -391,9 +392,13 @@ int build_worklist_ex(pt_batch* b, const std::vector<int>& steps, const std::vec
 
 int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
   std::vector<int> every(b->jobs.size());  // the work list carries each job's interval
-  for (size_t i = 0; i < b->jobs.size(); ++i) every[i] = b->jobs[i]->meas_every;
+  std::vector<uint32_t> epoch(b->jobs.size());  // and its buffers and layout
+  for (size_t i = 0; i < b->jobs.size(); ++i) {
+    every[i] = b->jobs[i]->meas_every;
+    epoch[i] = b->jobs[i]->epoch;
+  }
   const bool same = b->built && b->built_flags == flags && same_cfg(b->built_cfg, b->cfg) &&
-                    b->built_every == every;
+                    b->built_every == every && b->built_epoch == epoch;
   if (same && b->built_mcs == mcs) return PT_OK;
   if (same && b->built_mcs > 0 && mcs > 0) {
     // only the step count differs: the items, their order and the launch
@@ -405,6 +410,7 @@ int build_worklist(pt_batch* b, int mcs, uint32_t flags) {
     return PT_OK;
   }
   b->built_every = every;
+  b->built_epoch = epoch;
   const std::vector<int> steps(b->jobs.size(), mcs);
   const std::vector<uint32_t> fl(b->jobs.size(), flags);
   if (int rc = build_worklist_ex(b, steps, fl)) return rc;
@@ -515,7 +521,7 @@ std::string cache_key(const pt_batch* b, uint32_t flags) {
   return key;
 }
 
-bool cache_lookup(const char* path, const std::string& key, BatchConfig& cfg) {
+bool cache_lookup(const char* path, const std::string& key, BatchConfig& cfg, int* layout) {
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
@@ -526,15 +532,20 @@ bool cache_lookup(const char* path, const std::string& key, BatchConfig& cfg) {
     const std::string l(line);
     const std::string want = "\"key\": \"" + key + "\"";
     if (l.find(want) == std::string::npos) continue;
-    int t = 0, s = 0, o = 0;
+    int t = 0, s = 0, o = 0, ly = -1;
     const char* p = std::strstr(line, "\"threads\":");
     const char* q = std::strstr(line, "\"sets\":");
     const char* r = std::strstr(line, "\"order\":");
+    const char* y = std::strstr(line, "\"layout\":");
     if (p && q && r && std::sscanf(p, "\"threads\": %d", &t) == 1 && std::sscanf(q, "\"sets\": %d", &s) == 1 &&
         std::sscanf(r, "\"order\": %d", &o) == 1) {
+      if (!y || std::sscanf(y, "\"layout\": %d", &ly) != 1 ||
+          (ly != (int)PT_LAYOUT_INT8 && ly != (int)PT_LAYOUT_PACKED))
+        ly = -1;
       cfg.threads = t;
       cfg.sets = s;
       cfg.order = o;
+      *layout = ly;
       found = true;
     }
   }
@@ -542,13 +553,27 @@ bool cache_lookup(const char* path, const std::string& key, BatchConfig& cfg) {
   return found;
 }
 
-void cache_store(const char* path, const std::string& key, const BatchConfig& cfg, double ms) {
+// layout < 0: the trials kept every job's layout
+void cache_store(const char* path, const std::string& key, const BatchConfig& cfg, int layout, double ms) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"sets\": %d, \"order\": %d, \"trial_ms\": %.4f}\n",
-               key.c_str(), cfg.threads, cfg.sets, cfg.order, ms);
+  if (layout < 0)
+    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"sets\": %d, \"order\": %d, \"trial_ms\": %.4f}\n",
+                 key.c_str(), cfg.threads, cfg.sets, cfg.order, ms);
+  else
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"threads\": %d, \"sets\": %d, \"order\": %d, \"layout\": %d, "
+                 "\"trial_ms\": %.4f}\n",
+                 key.c_str(), cfg.threads, cfg.sets, cfg.order, layout, ms);
   std::fclose(f);
+}
+
+// Every job of the batch to one spin layout.
+int set_layout_all(pt_batch* b, int layout) {
+  for (pt_job* j : b->jobs)
+    if (int rc = pt_set_layout(j, (uint32_t)layout)) return rc;
+  return PT_OK;
 }
 
 }  // namespace
@@ -789,60 +814,83 @@ PT_API int pt_batch_tune(pt_batch* b, int32_t trial_mcs, uint32_t flags, const c
   if (!b) return pt_fail(PT_EINVAL, "null batch");
   if (trial_mcs < 1) return pt_fail(PT_EINVAL, "pt_batch_tune: trial_mcs must be >= 1");
   const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_MULTICLUSTER);
-  const std::string key = cache_key(b, work_flags);
+  const bool try_layouts = (flags & PT_TUNE_LAYOUT) != 0;
+  const std::string key = cache_key(b, work_flags | (try_layouts ? PT_TUNE_LAYOUT : 0u));
   BatchConfig cached;
-  if (cache_lookup(cache_path, key, cached)) {
+  int cached_layout = -1;
+  if (cache_lookup(cache_path, key, cached, &cached_layout)) {
+    if (try_layouts && cached_layout >= 0)
+      if (int rc = set_layout_all(b, cached_layout)) return rc;
     b->cfg = cached;
     return PT_OK;
-  }
-  Snap sn;
-  if (int rc = snapshot(b, sn, false)) {
-    for (void* p : sn.bufs) (void)hipFree(p);
-    return rc;
   }
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  BatchConfig best = b->cfg;
+  const BatchConfig start = b->cfg;
+  BatchConfig best = start;
+  int best_layout = -1;
   double best_ms = 1e300;
   int rc = PT_OK;
-  // one untimed trial first (the GPU clock and the caches settle), then each
-  // configuration timed twice from the same state, keeping its faster run
-  const BatchConfig start = b->cfg;
-  rc = build_worklist(b, trial_mcs, work_flags);
-  if (rc == PT_OK) rc = run_once(b, false);
-  if (rc == PT_OK) rc = snapshot(b, sn, true);
-  for (int threads : {1024, 768, 512, 256}) {
-    for (int sets : {2, 1}) {
-      for (int order : {0, 1}) {
-        if (rc != PT_OK) break;
-        b->cfg = BatchConfig{threads, sets, order};
-        if ((rc = build_worklist(b, trial_mcs, work_flags))) break;
-        double cfg_ms = 1e300;
-        for (int rep = 0; rep < 2 && rc == PT_OK; ++rep) {
-          (void)hipEventRecord(e0, b->stream);
-          if ((rc = run_once(b, false))) break;
-          (void)hipEventRecord(e1, b->stream);
-          (void)hipEventSynchronize(e1);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (ms < cfg_ms) cfg_ms = ms;
-          rc = snapshot(b, sn, true);
-        }
-        if (rc == PT_OK && cfg_ms < best_ms) {
-          best_ms = cfg_ms;
-          best = b->cfg;
+  // with PT_TUNE_LAYOUT every configuration is timed with all jobs in the
+  // int8 layout, then in the packed one (the conversion is exact, so both
+  // start from the same state); otherwise in the jobs' own layouts
+  const std::vector<int> layouts = try_layouts ? std::vector<int>{(int)PT_LAYOUT_INT8, (int)PT_LAYOUT_PACKED}
+                                               : std::vector<int>{-1};
+  bool warmed = false;
+  for (int layout : layouts) {
+    if (rc != PT_OK) break;
+    if (layout >= 0 && (rc = set_layout_all(b, layout))) break;
+    Snap sn;
+    rc = snapshot(b, sn, false);
+    if (rc == PT_OK && !warmed) {
+      // one untimed trial first (the GPU clock and the caches settle), then
+      // each configuration timed twice from the same state, keeping its
+      // faster run
+      b->cfg = start;
+      rc = build_worklist(b, trial_mcs, work_flags);
+      if (rc == PT_OK) rc = run_once(b, false);
+      if (rc == PT_OK) rc = snapshot(b, sn, true);
+      warmed = true;
+    }
+    for (int threads : {1024, 768, 512, 256}) {
+      for (int sets : {2, 1}) {
+        for (int order : {0, 1}) {
+          if (rc != PT_OK) break;
+          b->cfg = BatchConfig{threads, sets, order};
+          if ((rc = build_worklist(b, trial_mcs, work_flags))) break;
+          double cfg_ms = 1e300;
+          for (int rep = 0; rep < 2 && rc == PT_OK; ++rep) {
+            (void)hipEventRecord(e0, b->stream);
+            if ((rc = run_once(b, false))) break;
+            (void)hipEventRecord(e1, b->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < cfg_ms) cfg_ms = ms;
+            rc = snapshot(b, sn, true);
+          }
+          if (rc == PT_OK && cfg_ms < best_ms) {
+            best_ms = cfg_ms;
+            best = b->cfg;
+            best_layout = layout;
+          }
         }
       }
     }
+    for (void* p : sn.bufs) (void)hipFree(p);
   }
-  if (rc != PT_OK) best = start;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  for (void* p : sn.bufs) (void)hipFree(p);
+  if (rc != PT_OK) {
+    b->cfg = start;
+    return rc;
+  }
+  // the jobs hold their starting state, in the last layout tried
+  if (best_layout >= 0 && (rc = set_layout_all(b, best_layout))) return rc;
   b->cfg = best;
-  if (rc == PT_OK) cache_store(cache_path, key, best, best_ms);
-  return rc;
+  cache_store(cache_path, key, best, best_layout, best_ms);
+  return PT_OK;
 }
 
 PT_API int pt_batch_destroy(pt_batch* b) {

@@ -64,6 +64,8 @@ struct pt_job {
   double* gbeta = nullptr;   // [NT]
   float* gcz = nullptr;      // [NT]
   bool poisoned = false;
+  // bumped when device buffers held by launch arguments change (pt_set_layout)
+  uint32_t epoch = 0;
   struct pt_batch* self_batch = nullptr;  // one-job batch behind pt_mcs
   std::vector<void*> allocs;
   void* (*alloc_fn)(size_t, void*) = nullptr;
@@ -86,6 +88,18 @@ struct pt_job {
     }
     if (p) allocs.push_back(p);
     return p;
+  }
+  // Frees one buffer from dalloc (after the work using it has completed).
+  void dfree(void* p) {
+    for (size_t i = 0; i < allocs.size(); ++i) {
+      if (allocs[i] != p) continue;
+      if (free_fn)
+        free_fn(p, alloc_ctx);
+      else
+        (void)hipFree(p);
+      allocs.erase(allocs.begin() + (long)i);
+      return;
+    }
   }
   void release() {
     for (void* p : allocs) {

@@ -12,6 +12,11 @@ namespace ptsg {
 // (i>>2, 0, r, 2<<28 | s); s_i = -1 iff the word's top bit is set.
 hipError_t launch_init_spins(const Geo& g, void* spins, hipStream_t st);
 
+// The spins of every lattice from the int8 layout to the packed colour words
+// (to_packed) or back; src and dst are distinct buffers.
+hipError_t launch_convert_layout(const Geo& g, const void* src, void* dst, bool to_packed,
+                                 hipStream_t st);
+
 // int8 couplings [S][d][N] -> direction words jw [S][2][2d][NR]: bit b of
 // jw[s][c][dir][R] is set iff the bond between the colour-c site b of row R and
 // its neighbour in direction dir (+x0, -x0, +x1, -x1, +x2, -x2) is -1.

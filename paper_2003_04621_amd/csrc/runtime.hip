@@ -815,6 +815,40 @@ PT_API int pt_set_spins(pt_job* job, const int8_t* in) {
   return PT_OK;
 }
 
+PT_API int pt_get_layout(pt_job* job, uint32_t* out) {
+  if (int rc = check_job(job)) return rc;
+  if (!out) return pt_fail(PT_EINVAL, "null output");
+  *out = (uint32_t)job->g.layout;
+  return PT_OK;
+}
+
+PT_API int pt_set_layout(pt_job* job, uint32_t layout) {
+  if (int rc = check_job(job)) return rc;
+  if (layout != PT_LAYOUT_INT8 && layout != PT_LAYOUT_PACKED) return pt_fail(PT_EINVAL, "unknown layout");
+  if (int rc = check_fault(job)) return rc;
+  if ((int)layout == job->g.layout) return PT_OK;
+  // work on any stream may still read the spins (a batch launch runs on the
+  // batch's stream): wait for the device before converting and freeing
+  PT_HIP(job, hipDeviceSynchronize());
+  Geo to = job->g;
+  to.layout = (int)layout;
+  const size_t lat = (size_t)to.S * to.nslot;
+  void* dst = job->dalloc(to.layout == kLayoutPacked ? lat * 2 * to.NW * sizeof(uint32_t) : lat * to.N);
+  if (!dst) return pt_fail(PT_ENOMEM, "pt_set_layout: device allocation failed");
+  const hipError_t e = launch_convert_layout(job->g, job->spins, dst, to.layout == kLayoutPacked,
+                                             job->stream);
+  const hipError_t es = e == hipSuccess ? hipStreamSynchronize(job->stream) : e;
+  if (es != hipSuccess) {
+    job->dfree(dst);
+    return pt_fail(PT_EDEVICE, std::string("pt_set_layout: ") + hipGetErrorString(es));
+  }
+  job->dfree(job->spins);
+  job->spins = dst;
+  job->g.layout = to.layout;
+  ++job->epoch;
+  return PT_OK;
+}
+
 PT_API int pt_get_energies(pt_job* job, int32_t* out) {
   if (int rc = check_job(job)) return rc;
   if (job->gauss) return pt_fail(PT_EINVAL, "Gaussian energies are 64-bit: use pt_get_energies64");

@@ -71,6 +71,37 @@ hipError_t launch_init_spins(const Geo& g, void* spins, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// spin layout conversion (int8 <-> packed colour words), one thread per
+// colour-word index of a lattice
+// ---------------------------------------------------------------------------
+__global__ void k_convert_layout(Geo g, const void* __restrict__ src, void* __restrict__ dst,
+                                 int to_packed) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)g.S * g.nslot * g.NW;
+  if (idx >= total) return;
+  const long lat = idx / g.NW;
+  const int w = (int)(idx - lat * g.NW);
+  if (to_packed) {
+    uint32_t w0, w1;
+    word_from_int8(g, static_cast<const int8_t*>(src) + lat * g.N, w, w0, w1);
+    uint32_t* out = static_cast<uint32_t*>(dst) + lat * 2 * (size_t)g.NW;
+    out[w] = w0;
+    out[g.NW + w] = w1;
+  } else {
+    const uint32_t* in = static_cast<const uint32_t*>(src) + lat * 2 * (size_t)g.NW;
+    word_to_int8(g, static_cast<int8_t*>(dst) + lat * g.N, w, in[w], in[g.NW + w]);
+  }
+}
+
+hipError_t launch_convert_layout(const Geo& g, const void* src, void* dst, bool to_packed,
+                                 hipStream_t st) {
+  const long total = (long)g.S * g.nslot * g.NW;
+  hipLaunchKernelGGL(k_convert_layout, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g,
+                     src, dst, to_packed ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // couplings -> direction words
 // ---------------------------------------------------------------------------
 __global__ void k_pack_couplings(Geo g, const int8_t* __restrict__ J8, uint32_t* __restrict__ jw) {

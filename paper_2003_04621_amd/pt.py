@@ -26,6 +26,7 @@ PT_TRACK_STATS = 0x80
 PT_MCS_HOUDAYER, PT_MCS_MEASURE, PT_MCS_PLAIN, PT_BATCH_GRAPH = 1, 2, 4, 8
 PT_MCS_MULTICLUSTER = 0x40
 PT_SERVE_UNTIL_EQUILIBRATED = 0x100
+PT_TUNE_LAYOUT = 0x200
 PT_NOALLOC_MAX_ITEMS = 65536
 _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVICE",
           PT_ESTATE: "PT_ESTATE", PT_ECANCELED: "PT_ECANCELED"}
@@ -33,7 +34,8 @@ _CODES = {PT_EINVAL: "PT_EINVAL", PT_ENOMEM: "PT_ENOMEM", PT_EDEVICE: "PT_EDEVIC
 EXPORTS = [
     "pt_init", "pt_init_ex", "pt_sweep", "pt_exchange", "pt_houdayer", "pt_houdayer_multi",
     "pt_measure", "pt_mcs", "pt_mcs_noalloc",
-    "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins", "pt_get_energies",
+    "pt_get_plan", "pt_plan_query", "pt_job_bytes", "pt_observables", "pt_destroy", "pt_get_spins", "pt_set_spins",
+    "pt_set_layout", "pt_get_layout", "pt_get_energies",
     "pt_get_maps", "pt_get_counters", "pt_get_moments", "pt_get_walk", "pt_tunnel_summary",
     "pt_get_modes", "pt_correlation_length", "pt_get_stats",
     "pt_get_state", "pt_set_state",
@@ -90,6 +92,7 @@ def lib():
             "pt_mcs": [P, I32, U32], "pt_mcs_noalloc": [P, I32, U32], "pt_get_plan": [P, U32, P], "pt_plan_query": [I32, I32, I32, U32, P],
             "pt_job_bytes": [I32, I32, I32, I32, U32, P, P], "pt_observables": [P, P, P, P], "pt_destroy": [P],
             "pt_get_spins": [P, P], "pt_set_spins": [P, P], "pt_get_energies": [P, P],
+            "pt_set_layout": [P, U32], "pt_get_layout": [P, P],
             "pt_get_maps": [P, P, P], "pt_get_counters": [P, P], "pt_get_moments": [P, P],
             "pt_get_walk": [P, P, P, P], "pt_tunnel_summary": [P, I32, U64, P, P, P, P],
             "pt_get_modes": [P, P], "pt_correlation_length": [P, P, P, P], "pt_get_stats": [P, P],
@@ -403,6 +406,18 @@ def pt_set_spins(job: Job, spins) -> None:
     _check(lib().pt_set_spins(job.h, _p(s)))
 
 
+def pt_set_layout(job: Job, layout: int) -> None:
+    _check(lib().pt_set_layout(job.h, int(layout)))
+    job.layout = int(layout)
+
+
+def pt_get_layout(job: Job) -> int:
+    out = np.zeros(1, np.uint32)
+    _check(lib().pt_get_layout(job.h, _p(out)))
+    job.layout = int(out[0])
+    return job.layout
+
+
 def pt_get_energies(job: Job) -> np.ndarray:
     out = np.zeros((job.S, 2 * job.NT), np.int32)
     _check(lib().pt_get_energies(job.h, _p(out)))
@@ -533,9 +548,17 @@ def pt_batch_run(batch: Batch, mcs: int, houdayer=False, measure=False, graph=Fa
 
 
 def pt_batch_tune(batch: Batch, trial_mcs: int = 3, houdayer=False, measure=False,
-                  cache_path: str | None = None) -> tuple:
+                  cache_path: str | None = None, layouts=False) -> tuple:
     path = cache_path.encode() if cache_path else None
-    _check(lib().pt_batch_tune(batch.h, int(trial_mcs), _flags(houdayer, measure), path))
+    flags = _flags(houdayer, measure) | (PT_TUNE_LAYOUT if layouts else 0)
+    rc = lib().pt_batch_tune(batch.h, int(trial_mcs), flags, path)
+    msg = lib().pt_last_error().decode() if rc != PT_OK else ""
+    for j in batch.jobs:  # the layout axis may have moved the jobs
+        out = np.zeros(1, np.uint32)
+        if lib().pt_get_layout(j.h, _p(out)) == PT_OK:
+            j.layout = int(out[0])
+    if rc != PT_OK:
+        raise PTError(rc, msg)
     return pt_batch_get_config(batch)
 
 
