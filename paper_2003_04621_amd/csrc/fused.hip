@@ -108,7 +108,9 @@ bool split_plan(const Geo& g, FusedLayout& lay, int& parts, int& R, int& jlds, b
     const size_t rmax = std::min<size_t>((budget - fixed) / W2, (size_t)g.nslot);
     if (rmax < 1 || (jl && rmax < std::min(g.nslot, 8))) continue;
     const int p = (int)((g.nslot + rmax - 1) / rmax);
-    if (p > kMaxParts) continue;
+    // the parts' moment increments ([p][N_T][8] 64-bit words) are combined
+    // through one parity half of the published-configuration scratch
+    if (p > kMaxParts || (size_t)p * 8 > W2) continue;
     R = (g.nslot + p - 1) / p;
     parts = (g.nslot + R - 1) / R;
     jlds = jl;

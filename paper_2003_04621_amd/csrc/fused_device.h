@@ -1000,10 +1000,11 @@ __device__ __forceinline__ void run_sample(const FusedArgs& A, uint32_t* lds, in
 // parity-double-buffered global scratch and meets the other parts at a
 // per-sample counter barrier; then every part takes the same exchange
 // decisions from the same energies and Philox words, so the maps agree
-// without further communication, and temperature k is measured by part
-// k mod parts from the published configurations.  A part overwrites a
-// parity buffer two steps later, after a barrier that every reader of it has
-// passed.
+// without further communication, and temperature k is measured by the part
+// holding its replica-set-0 configuration, which reads the set-1 partner from
+// LDS or from the published configurations (only set-1 slots are published).
+// A part overwrites a parity buffer two steps later, after a barrier that
+// every reader of it has passed.
 // ---------------------------------------------------------------------------
 
 // About 60 s of the 100 MHz constant clock: far beyond any legitimate wait
@@ -1047,38 +1048,47 @@ __device__ __forceinline__ bool part_barrier(uint32_t* bar, uint32_t target, uin
   return *flag != 0;
 }
 
-// Overlap and moments of the temperatures this part owns (k = part mod
-// parts), from the configurations published this step (`pub`: [nslot][2NW]).
+// Overlaps and moment increments of the temperatures whose replica-set-0
+// configuration this part holds (its slots below N_T, at temperature tos[r]),
+// each against its set-1 partner: from LDS when this part holds the partner
+// too, else from the words published this step (`pub`: [nslot][2NW], set-1
+// slots).  The increments go to this part's LDS sums, which start each launch
+// at zero and are combined across parts at its end (combine_split_moments).
+// With the modes kept, the parts publish every slot and temperature k's modes
+// are taken by part k mod parts from the published words.
 template <bool MODES>
-__device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds, int part,
-                                              const uint32_t* pub) {
+__device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds, int part, int slot0,
+                                              int nres, const uint32_t* W, const uint32_t* pub) {
   const Geo& g = A.g;
   const int NT = g.NT, W2 = 2 * g.NW, tid = threadIdx.x, T = blockDim.x;
   const int32_t* El = reinterpret_cast<const int32_t*>(lds + A.lay.E);
   const int32_t* sotl = reinterpret_cast<const int32_t*>(lds + A.lay.sot);
+  const int32_t* tosl = reinterpret_cast<const int32_t*>(lds + A.lay.tos);
   int32_t* qneg = reinterpret_cast<int32_t*>(lds + A.lay.qneg);
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
-  for (int k = part + tid * A.parts; k < NT; k += T * A.parts) qneg[k] = 0;
+  const int n0 = max(0, min(slot0 + nres, NT) - slot0);  // this part's set-0 slots
+  for (int i = tid; i < n0; i += T) qneg[i] = 0;
   __syncthreads();
-  // each thread sums the differing sites of its words of one owned
-  // temperature, the wavefront adds the lanes' sums (one LDS atomic per
-  // wavefront and temperature instead of one per word)
-  const int nk = (NT - part + A.parts - 1) / A.parts;
-  for (int kl = 0; kl < nk; ++kl) {
-    const int k = part + kl * A.parts;
-    const uint32_t* pa = pub + (size_t)sotl[k] * W2;
-    const uint32_t* pb = pub + (size_t)(NT + sotl[NT + k]) * W2;
+  // each thread sums the differing sites of its words of one pair, the
+  // wavefront adds the lanes' sums (one LDS atomic per wavefront and pair)
+  for (int i = 0; i < n0; ++i) {
+    const int r = slot0 + i, b = NT + sotl[NT + tosl[r]];
+    const uint32_t* pa = W + (size_t)i * W2;
+    const uint32_t* pb = (b < slot0 + nres) ? W + (size_t)(b - slot0) * W2 : pub + (size_t)b * W2;
     int neg = 0;
 #pragma unroll 4
-    for (int i = tid; i < W2; i += T) neg += __popc(pa[i] ^ pb[i]);
+    for (int w = tid; w < W2; w += T) neg += __popc(pa[w] ^ pb[w]);
     neg = wave_total(neg);
-    if ((tid & 63) == 0 && neg) atomicAdd(&qneg[k], neg);
+    if ((tid & 63) == 0 && neg) atomicAdd(&qneg[i], neg);
   }
   __syncthreads();
-  for (int k = part + tid * A.parts; k < NT; k += T * A.parts)
-    add_moments(g, mom + (size_t)k * 8, El[sotl[k]], El[NT + sotl[NT + k]], qneg[k]);
+  for (int i = tid; i < n0; i += T) {
+    const int r = slot0 + i, k = tosl[r];
+    add_moments(g, mom + (size_t)k * 8, El[r], El[NT + sotl[NT + k]], qneg[i]);
+  }
   if (MODES && A.modes) {
     // the owned temperatures' modes, one wavefront each, from the published words
+    const int nk = (NT - part + A.parts - 1) / A.parts;
     const int wave = tid >> 6, lane = tid & 63, nwave = T >> 6;
     for (int kl = wave; kl < nk; kl += nwave) {
       const int k = part + kl * A.parts;
@@ -1087,6 +1097,34 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
     }
   }
   __syncthreads();
+}
+
+// The end of a measuring launch of a split sample: every part writes its
+// moment increments to `scr` ([parts][N_T][8] 64-bit words; free once every
+// part has passed the last step's barrier), meets the other parts once more,
+// and part k mod parts adds the increments of temperature k (the Q^4 sum as a
+// 128-bit pair) to the sums in global memory.  False if the wait gave up.
+__device__ __forceinline__ bool combine_split_moments(const FusedArgs& A, const int64_t* mom, int s,
+                                                      int part, uint64_t* scr, uint32_t* bar,
+                                                      uint32_t target, uint32_t* fault, int* flag) {
+  const int NT = A.g.NT, tid = threadIdx.x, T = blockDim.x;
+  for (int i = tid; i < 8 * NT; i += T) scr[(size_t)part * 8 * NT + i] = (uint64_t)mom[i];
+  if (!part_barrier(bar, target, fault, flag)) return false;
+  for (int k = part + tid * A.parts; k < NT; k += T * A.parts) {
+    uint64_t* dst = reinterpret_cast<uint64_t*>(A.mom) + ((size_t)s * NT + k) * 8;
+    uint64_t m[8];
+    for (int j = 0; j < 8; ++j) m[j] = dst[j];
+    for (int p = 0; p < A.parts; ++p) {
+      const uint64_t* q = scr + ((size_t)p * NT + k) * 8;
+      for (int j = 0; j < 5; ++j) m[j] += q[j];
+      const uint64_t lo = m[5] + q[5];
+      m[6] += q[6] + (lo < m[5] ? 1u : 0u);
+      m[5] = lo;
+      m[7] += q[7];
+    }
+    for (int j = 0; j < 8; ++j) dst[j] = m[j];
+  }
+  return true;
 }
 
 // nmcs Monte Carlo steps (sweep, exchange, measurement) of part `part` of
@@ -1132,8 +1170,9 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     tosl[i] = A.tos[(size_t)s * 2 * NT + i];
   }
   for (int i = tid; i < 4 * NT; i += T) thrl[i] = A.thr[i];
+  // this launch's moment increments (combined across parts at its end)
   if (meas)
-    for (int i = tid; i < 8 * NT; i += T) mom[i] = A.mom[(size_t)s * NT * 8 + i];
+    for (int i = tid; i < 8 * NT; i += T) mom[i] = 0;
   // mode sums of the temperatures this part measures (k = part mod parts)
   const bool modes = MODES && meas && A.modes != nullptr;
   const int MH = g.L / 2 + 1;
@@ -1153,6 +1192,7 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
   uint32_t* fault = A.bar + g.S;
   int32_t* Ex = A.Ex + (size_t)s * 2 * nslot;
   uint32_t* snap = A.snap + (size_t)s * 2 * nslot * W2;
+  bool good = true;
   __syncthreads();
 
   for (int step = 0; step < A.nmcs; ++step) {
@@ -1164,17 +1204,26 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     const bool mstep = meas && measures_at(t + 1u, (uint32_t)A.every);
     for (int i = tid; i < nres; i += T) Ex[par * nslot + slot0 + i] = El[slot0 + i];
     if (mstep) {
+      // the set-1 slots (every slot when the modes are kept)
+      const int first = modes ? 0 : min(nres, max(0, NT - slot0));
       uint32_t* dst = snap + ((size_t)par * nslot + slot0) * W2;
-      for (int i = tid; i < nres * W2; i += T) dst[i] = W[i];
+      for (int i = first * W2 + tid; i < nres * W2; i += T) dst[i] = W[i];
     }
-    if (!part_barrier(bar, (uint32_t)(A.parts * (step + 1)), fault, flag)) break;
+    if (!part_barrier(bar, (uint32_t)(A.parts * (step + 1)), fault, flag)) {
+      good = false;
+      break;
+    }
     for (int i = tid; i < nslot; i += T) El[i] = Ex[par * nslot + i];
     __syncthreads();
     exchange_resident<WALK>(A, lds, 0, 2, u + 1u, walk);
-    if (mstep) measure_split<MODES>(A, lds, part, snap + (size_t)par * nslot * W2);
+    if (mstep) measure_split<MODES>(A, lds, part, slot0, nres, W, snap + (size_t)par * nslot * W2);
   }
+  if (meas && good)
+    combine_split_moments(A, mom, s, part,
+                          reinterpret_cast<uint64_t*>(snap + (size_t)(A.nmcs & 1) * nslot * W2), bar,
+                          (uint32_t)(A.parts * (A.nmcs + 1)), fault, flag);
 
-  // ---- store this part's slots; part 0 stores the maps, owners the moments
+  // ---- store this part's slots; part 0 stores the maps, owners the modes
   if (g.layout == kLayoutPacked) {
     uint32_t* dst = static_cast<uint32_t*>(A.spins) + lat0 * W2;
     for (int i = tid; i < nres * W2; i += T) dst[i] = W[i];
@@ -1196,9 +1245,6 @@ __device__ __forceinline__ void run_split(const FusedArgs& A, uint32_t* lds, int
     for (int i = tid; i < 2 * nslot; i += T) A.walk[(size_t)s * 2 * nslot + i] = wkl[i];
     flush_trips(A, lds, s);
   }
-  if (meas)
-    for (int k = part; k < NT; k += A.parts)
-      for (int i = tid; i < 8; i += T) A.mom[((size_t)s * NT + k) * 8 + i] = mom[k * 8 + i];
   if (modes)
     for (int k = part; k < NT; k += A.parts)
       for (int i = tid; i < MH; i += T) A.modes[((size_t)s * NT + k) * MH + i] = modl[k * MH + i];

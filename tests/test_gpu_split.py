@@ -72,9 +72,13 @@ def test_split_matches_oracle(pt, d, L, S, NT, layout, parts):
     pt.pt_mcs(job, 3, measure=True)
     ref.mcs(3, measure=True)
     matches_oracle(pt, job, ref, "measured")
+    # a second measuring launch (an even step count) adds to the sums
+    pt.pt_mcs(job, 2, measure=True)
+    ref.mcs(2, measure=True)
+    matches_oracle(pt, job, ref, "measured again")
     ps, dis, n = pt.pt_observables(job)
     rps, rdis, rn = ref.observables()
-    assert n == rn == 3
+    assert n == rn == 5
     np.testing.assert_allclose(ps, rps, rtol=1e-12, atol=0)
     np.testing.assert_allclose(dis, rdis, rtol=1e-12, atol=0)
     pt.pt_destroy(job)
