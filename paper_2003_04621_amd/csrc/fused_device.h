@@ -1067,19 +1067,29 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
   int32_t* qneg = reinterpret_cast<int32_t*>(lds + A.lay.qneg);
   int64_t* mom = reinterpret_cast<int64_t*>(lds + A.lay.mom);
   const int n0 = max(0, min(slot0 + nres, NT) - slot0);  // this part's set-0 slots
+  const int wave = tid >> 6, lane = tid & 63, nwave = T >> 6;
   for (int i = tid; i < n0; i += T) qneg[i] = 0;
   __syncthreads();
-  // each thread sums the differing sites of its words of one pair, the
-  // wavefront adds the lanes' sums (one LDS atomic per wavefront and pair)
-  for (int i = 0; i < n0; ++i) {
+  // the (pair, 64-word chunk) space is cut into one contiguous range per
+  // wavefront, so that every wavefront has many independent loads in flight
+  // whatever the number of pairs; a wavefront adds its lanes' counts of the
+  // differing sites once per pair in its range
+  const int C64 = (W2 + 63) >> 6, items = n0 * C64, per = (items + nwave - 1) / nwave;
+  const int hi = min(items, (wave + 1) * per);
+  for (int it = wave * per; it < hi;) {
+    const int i = it / C64, c1 = min(hi - i * C64, C64);
     const int r = slot0 + i, b = NT + sotl[NT + tosl[r]];
     const uint32_t* pa = W + (size_t)i * W2;
     const uint32_t* pb = (b < slot0 + nres) ? W + (size_t)(b - slot0) * W2 : pub + (size_t)b * W2;
     int neg = 0;
-#pragma unroll 4
-    for (int w = tid; w < W2; w += T) neg += __popc(pa[w] ^ pb[w]);
+#pragma unroll 8
+    for (int c = it - i * C64; c < c1; ++c) {
+      const int w = c * 64 + lane;
+      if (w < W2) neg += __popc(pa[w] ^ pb[w]);
+    }
     neg = wave_total(neg);
-    if ((tid & 63) == 0 && neg) atomicAdd(&qneg[i], neg);
+    if (lane == 0 && neg) atomicAdd(&qneg[i], neg);
+    it = i * C64 + c1;
   }
   __syncthreads();
   for (int i = tid; i < n0; i += T) {
@@ -1089,7 +1099,6 @@ __device__ __forceinline__ void measure_split(const FusedArgs& A, uint32_t* lds,
   if (MODES && A.modes) {
     // the owned temperatures' modes, one wavefront each, from the published words
     const int nk = (NT - part + A.parts - 1) / A.parts;
-    const int wave = tid >> 6, lane = tid & 63, nwave = T >> 6;
     for (int kl = wave; kl < nk; kl += nwave) {
       const int k = part + kl * A.parts;
       modes_resident(g, A.lay, lds, pub + (size_t)sotl[k] * W2, pub + (size_t)(NT + sotl[NT + k]) * W2,
