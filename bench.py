@@ -338,16 +338,16 @@ def settle_gpu(pt, torch, scratch, wl, seconds):
     launches of the 3D L=16 workload took 2.86 ms after an idle period,
     falling to 2.55 ms after about 20 ms of back-to-back work, and 2.83 ms
     again after 0.1 s of host-side set-up), so a scratch job of the same
-    workload runs fused steps for `seconds`.  The timed job is not touched:
-    it gets exactly the requested warm-up steps.  The scratch job is freed
-    here."""
+    workload runs fused steps for `seconds`, a few launches queued ahead so
+    that the GPU never idles between them.  The timed job is not touched: it
+    gets exactly the requested warm-up steps.  The caller frees the scratch
+    job after the timed region (freeing it here would idle the GPU)."""
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        pt.pt_mcs(scratch, 20, houdayer=wl.houdayer, measure=True)
+        for _ in range(4):
+            pt.pt_mcs(scratch, 20, houdayer=wl.houdayer, measure=True)
         torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    pt.pt_destroy(scratch)
-    return dt
+    return time.perf_counter() - t0
 
 
 def phase_split(pt, torch, wl, layout, steps, warmup):
@@ -509,6 +509,8 @@ def main():
     K = args.steps
     elapsed, roofline = fused_run(pt, torch, job, wl, K, args.chunk, wl.houdayer, True, args.layout)
     value = flips_per_step * K / elapsed / 1e9
+    if scratch is not None:
+        pt.pt_destroy(scratch)
 
     # the same steps as separate per-step launches, for the fused/plain ratio
     plain = None
