@@ -75,6 +75,20 @@ def test_set_layout_keeps_state_and_steps(pt, shape, start):
     same_as_oracle(pt, job, ref, "per-step kernels after the move back")
 
 
+@pytest.mark.parametrize("start", [0, 1])
+def test_set_layout_split_sample(pt, start):
+    """A sample split over two workgroups (3D L = 32, 24 temperatures): fused
+    measuring steps before and after the move."""
+    job, ref = pm_job(pt, 32, 1, 24, 3, start, 91 + start)
+    assert pt.pt_get_plan(job, measure=True)["mode"] == 3
+    pt.pt_mcs(job, 3, measure=True)
+    ref.mcs(3, measure=True)
+    pt.pt_set_layout(job, 1 - start)
+    pt.pt_mcs(job, 4, measure=True)
+    ref.mcs(4, measure=True)
+    same_as_oracle(pt, job, ref, "split sample after the move")
+
+
 def test_set_layout_gauss(pt):
     d, L, S, NT = 2, 12, 2, 3
     Jf = W.couplings_gauss(S, L, d, 41)
