@@ -448,9 +448,11 @@ int pt_batch_set_stream(pt_batch *b, void *hip_stream);
  * default; each job runs the plan pt_get_plan reports for these flags.  The
  * parts of a split sample are queued first and consecutively, and launches
  * holding split samples are ordered across the process's streams (their
- * workgroups wait for one another once per step).  PT_EINVAL if a job has no
- * plan for these flags (Houdayer on a sample whose two sets do not fit one
- * workgroup). */
+ * workgroups wait for one another once per step).  A job with no plan for
+ * these flags (Houdayer moves on a sample whose two sets do not fit one
+ * workgroup) runs its steps through the per-step kernels on its own stream
+ * (pt_set_stream), ordered by events after the batch stream's earlier work and
+ * before its later work, and outside any captured graph. */
 int pt_batch_run(pt_batch *b, int32_t mcs, uint32_t flags);
 
 /* Autotuner: after one untimed trial, times trial_mcs steps of each launch

@@ -47,6 +47,7 @@ struct pt_batch {
   std::vector<uint32_t> built_epoch;  // the jobs' epochs when the list was built
   // captured launch (captured on a private stream, replayed on `stream`)
   hipStream_t cap_stream = nullptr;
+  hipEvent_t side_ev = nullptr;  // orders per-step jobs against the batch stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool graph_ok = false;
@@ -248,9 +249,13 @@ int plan_worklist(const std::vector<pt_job*>& jobs, const BatchConfig& cfg, cons
     const bool hou = flags & PT_MCS_HOUDAYER, meas = flags & PT_MCS_MEASURE;
     const int mcs = steps[jx];
     const int mode = job_mode(j, flags, cfg);
-    if (mode < 0)
-      return pt_fail(PT_EINVAL, "pt_batch_run: job " + std::to_string(jx) +
-                                    " does not fit one workgroup's LDS for these flags (use pt_mcs)");
+    if (mode < 0) {
+      // no fused plan for these flags: the job's steps run through the
+      // per-step kernels beside the launch (pt_batch_run); here it only keeps
+      // its index, with no steps and no items
+      hj.push_back(job_fused_args(j, 0, 0, 0u));
+      continue;
+    }
     if (mcs > 0 && meas) feat |= kFeatMeas;
     if (mcs > 0 && hou) feat |= kFeatHou;
     if (mcs > 0 && mode == 3) feat |= kFeatSplit;
@@ -725,6 +730,7 @@ void batch_free(pt_batch* b) {
   if (b->h_stage) (void)hipHostFree(b->h_stage);
   if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
   if (b->last_ev) (void)hipEventDestroy(b->last_ev);
+  if (b->side_ev) (void)hipEventDestroy(b->side_ev);
   (void)hipGetLastError();
   delete b;
 }
@@ -765,6 +771,31 @@ PT_API int pt_batch_set_stream(pt_batch* b, void* hip_stream) {
   return PT_OK;
 }
 
+namespace {
+// The steps of the jobs that have no fused plan for these flags, through the
+// per-step kernels on each job's own stream: after the batch stream's earlier
+// work (the job's earlier fused steps), and before its later work.
+int run_unplanned(pt_batch* b, int mcs, uint32_t work_flags) {
+  std::vector<pt_job*> side;
+  for (pt_job* j : b->jobs)
+    if (job_mode(j, work_flags, b->cfg) < 0) side.push_back(j);
+  if (side.empty()) return PT_OK;
+  hipError_t e = hipSuccess;
+  if (!b->side_ev) e = hipEventCreateWithFlags(&b->side_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(b->side_ev, b->stream);
+  for (pt_job* j : side)
+    if (e == hipSuccess) e = hipStreamWaitEvent(j->stream, b->side_ev, 0);
+  if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  for (pt_job* j : side) {
+    if (int rc = pt_mcs(j, mcs, work_flags | PT_MCS_PLAIN)) return rc;
+    e = hipEventRecord(b->side_ev, j->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->side_ev, 0);
+    if (e != hipSuccess) return pt_fail(PT_EDEVICE, std::string("pt_batch_run: ") + hipGetErrorString(e));
+  }
+  return PT_OK;
+}
+}  // namespace
+
 PT_API int pt_batch_run(pt_batch* b, int32_t mcs, uint32_t flags) {
   if (!b) return pt_fail(PT_EINVAL, "null batch");
   if (mcs < 0) return pt_fail(PT_EINVAL, "pt_batch_run: mcs must be >= 0");
@@ -778,9 +809,11 @@ PT_API int pt_batch_run(pt_batch* b, int32_t mcs, uint32_t flags) {
   const uint32_t work_flags = flags & (PT_MCS_HOUDAYER | PT_MCS_MEASURE | PT_MCS_MULTICLUSTER);
   if (int rc = build_worklist(b, mcs, work_flags)) return rc;
   const int rc = run_once(b, (flags & PT_BATCH_GRAPH) != 0);
-  if (rc != PT_OK)
+  if (rc != PT_OK) {
     for (pt_job* j : b->jobs) j->poisoned = true;
-  return rc;
+    return rc;
+  }
+  return run_unplanned(b, mcs, work_flags);
 }
 
 PT_API int pt_batch_get_config(pt_batch* b, int32_t* cfg3) {

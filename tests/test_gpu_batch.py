@@ -184,12 +184,31 @@ def test_tuner_restores_state_and_caches(pt):
         matches_oracle(pt, j, r)
 
 
-def test_batch_rejects_oversized_and_mixed_dims(pt):
-    # a Houdayer move needs both replica sets of a sample in one workgroup
-    big = pt.pt_init(1, 48, 64, 3, W.couplings_pm_j(1, 64, 3, 1), W.geometric_betas(0.9, 2, 48), 1)
-    batch = pt.pt_batch_create([big])
-    with pytest.raises(pt.PTError):
-        pt.pt_batch_run(batch, 1, houdayer=True)
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_runs_unplanned_jobs_per_step(pt, graph):
+    """Houdayer moves on a 3D sample whose two sets do not fit one workgroup
+    (L = 32, 4 temperatures: no fused plan) run through the per-step kernels
+    beside the launch; every job matches the oracle, before and after steps
+    without Houdayer moves (where that job is fused, a split sample)."""
+    shapes = [(32, 1, 4, 0), (8, 2, 4, 1), (12, 1, 3, 0)]
+    jobs, refs = make_jobs(pt, shapes, 3, seed0=130)
+    assert pt.pt_get_plan(jobs[0], houdayer=True, measure=True)["mode"] == -1
+    batch = pt.pt_batch_create(jobs)
+    say(f"unplanned job in a batch, graph={graph}")
+    pt.pt_batch_run(batch, 2, measure=True, graph=graph)
+    for r in refs:
+        r.mcs(2, measure=True)
+    pt.pt_batch_run(batch, 3, houdayer=True, measure=True, graph=graph)
+    for r in refs:
+        r.mcs(3, houdayer=True, measure=True)
+    pt.pt_batch_run(batch, 2, measure=True, graph=graph)
+    for r in refs:
+        r.mcs(2, measure=True)
+    for j, r in zip(jobs, refs):
+        matches_oracle(pt, j, r)
+
+
+def test_batch_rejects_mixed_dims(pt):
     j2 = pt.pt_init(1, 2, 8, 2, W.couplings_pm_j(1, 8, 2, 1), np.array([1.0, 0.5]), 1)
     j3 = pt.pt_init(1, 2, 8, 3, W.couplings_pm_j(1, 8, 3, 1), np.array([1.0, 0.5]), 1)
     with pytest.raises(pt.PTError):
