@@ -160,3 +160,22 @@ def test_tuner_layout_axis(pt):
         r.mcs(3, measure=True)
     for n, (j, r) in enumerate(zip(jobs, refs)):
         same_as_oracle(pt, j, r, f"job {n} after tuning")
+
+
+def test_checkpoint_restores_only_into_its_layout(pt):
+    """A checkpoint names its layout: refused after a move, accepted after the
+    move back, and the restored job continues as the oracle does."""
+    job, ref = pm_job(pt, 8, 2, 3, 3, 0, 5)
+    pt.pt_mcs(job, 3, measure=True)
+    ref.mcs(3, measure=True)
+    ck = pt.pt_get_state(job)
+    pt.pt_mcs(job, 2, measure=True)
+    pt.pt_set_layout(job, 1)
+    with pytest.raises(pt.PTError):
+        pt.pt_set_state(job, ck)
+    pt.pt_set_layout(job, 0)
+    pt.pt_set_state(job, ck)
+    same_as_oracle(pt, job, ref, "restored")
+    pt.pt_mcs(job, 2, measure=True)
+    ref.mcs(2, measure=True)
+    same_as_oracle(pt, job, ref, "after the restore")
