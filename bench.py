@@ -323,6 +323,8 @@ def fused_run(pt, torch, job, wl, K, chunk, houdayer, measure, layout_name, mult
     achieved = OPS_PER_FLIP * wl.flips_per_sweep * chunk / (launch_ms * 1e-3) / 1e12
     peak = PEAK_VALU_OPS / 1e12
     feat = (1 if houdayer else 0) | (2 if measure else 0)
+    if pt.pt_get_plan(job, houdayer=houdayer, measure=measure, multi=multi)["mode"] == 3:
+        feat |= 4  # split samples: the launch runs the split variant
     return elapsed, {
         "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
         "frac": round(achieved / peak, 4),
